@@ -1,0 +1,240 @@
+"""Discrete operators of the dual staggered grid (oracle; test infrastructure only).
+
+Array layout ``[z][y][x]``: axis 0 is the wall-normal z, axes 1 and 2 are the periodic y
+and x. Coarse grid (Sec. 3.1): pressure and polymer stress at cell centres, velocity
+components at the right faces of their own direction (u[k][j][i] at x = (i+1) hx,
+v at y = (j+1) hy, w[k] at z = (k+1) hz with w[nz-1] the top wall, always 0; the bottom
+wall w is implicit and 0). Fine grid: every coarse cell halved in x and z (and in y when
+ny > 1), phase field at fine cell centres.
+
+Wall ghost rules (second-order central differences, Sec. 3.2):
+* homogeneous Neumann (phase field, chemical potential, pressure increment, polymer stress,
+  eqs. NS14, NS37 and the closing paragraph of Sec. 3.2.3): ghost = adjacent cell;
+* no-slip (eq. NS13, wall at rest) for cell-centred-in-z velocity: ghost = -adjacent;
+* w lives on z faces: its wall values are 0.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.fft as sfft
+
+# ---------------------------------------------------------------------------------------
+# neighbour access
+# ---------------------------------------------------------------------------------------
+
+
+def xp(a):
+    return np.roll(a, -1, axis=2)
+
+
+def xm(a):
+    return np.roll(a, 1, axis=2)
+
+
+def yp(a):
+    return np.roll(a, -1, axis=1)
+
+
+def ym(a):
+    return np.roll(a, 1, axis=1)
+
+
+def zp_neu(a):
+    return np.concatenate([a[1:], a[-1:]], axis=0)
+
+
+def zm_neu(a):
+    return np.concatenate([a[:1], a[:-1]], axis=0)
+
+
+def zp_dir(a):
+    return np.concatenate([a[1:], -a[-1:]], axis=0)
+
+
+def zm_dir(a):
+    return np.concatenate([-a[:1], a[:-1]], axis=0)
+
+
+def zm_face(w):
+    """w[k-1] on z faces with the bottom-wall value w[-1] = 0."""
+    return np.concatenate([np.zeros_like(w[:1]), w[:-1]], axis=0)
+
+
+def zp_face(w):
+    """w[k+1] on z faces; the layer above the top wall is never used, set to 0."""
+    return np.concatenate([w[1:], np.zeros_like(w[:1])], axis=0)
+
+
+# ---------------------------------------------------------------------------------------
+# Laplacians (7-point; 5-point when ny == 1 since the single periodic y cell adds 0)
+# ---------------------------------------------------------------------------------------
+
+
+def _lap_xy(a, h):
+    hx, hy, _ = h
+    return (xp(a) - 2 * a + xm(a)) / hx ** 2 + (yp(a) - 2 * a + ym(a)) / hy ** 2
+
+
+def lap_neumann(a, h):
+    return _lap_xy(a, h) + (zp_neu(a) - 2 * a + zm_neu(a)) / h[2] ** 2
+
+
+def lap_dirichlet(a, h):
+    return _lap_xy(a, h) + (zp_dir(a) - 2 * a + zm_dir(a)) / h[2] ** 2
+
+
+def lap_wface(w, h):
+    r = _lap_xy(w, h) + (zp_face(w) - 2 * w + zm_face(w)) / h[2] ** 2
+    r[-1] = 0.0
+    return r
+
+
+# ---------------------------------------------------------------------------------------
+# constant-coefficient Helmholtz / Poisson solves (the "FFT solver", Sec. 3.2.1-3.2.2)
+# ---------------------------------------------------------------------------------------
+
+
+def _eig_periodic(n, h):
+    return -4.0 / h ** 2 * np.sin(np.pi * np.arange(n) / n) ** 2
+
+
+def helmholtz(rhs, coeff, shift, kind, h):
+    """Solve ``coeff * L x - shift * x = rhs`` exactly.
+
+    ``kind``: 'neumann' (cell-centred in z, homogeneous Neumann walls), 'dirichlet'
+    (cell-centred in z, zero-value walls, ghost = -adjacent) or 'wface' (z-face located,
+    unknowns k = 0..nz-2, wall values 0; layer nz-1 of the result is 0).
+    FFT in x and y; in z the transform whose basis vectors are the exact eigenvectors of
+    the wall-normal second difference: DCT-II (Neumann), DST-II (Dirichlet, centred),
+    DST-I of length nz-1 (Dirichlet, faces). A singular Neumann Poisson problem
+    (shift == 0) returns the zero-mean solution.
+    """
+    nz, ny, nx = rhs.shape
+    hx, hy, hz = h
+    X = np.fft.fft2(rhs, axes=(1, 2))
+    lam_xy = _eig_periodic(ny, hy)[:, None] + _eig_periodic(nx, hx)[None, :]
+    if kind == "neumann":
+        Z = sfft.dct(X, type=2, axis=0, norm="ortho")
+        m = np.arange(nz)
+    elif kind == "dirichlet":
+        Z = sfft.dst(X, type=2, axis=0, norm="ortho")
+        m = np.arange(1, nz + 1)
+    elif kind == "wface":
+        Z = sfft.dst(X[: nz - 1], type=1, axis=0, norm="ortho")
+        m = np.arange(1, nz)
+    else:
+        raise ValueError(kind)
+    lam_z = -4.0 / hz ** 2 * np.sin(np.pi * m / (2 * nz)) ** 2
+    denom = coeff * (lam_z[:, None, None] + lam_xy[None, :, :]) - shift
+    singular = denom == 0.0
+    denom = np.where(singular, 1.0, denom)
+    Z = np.where(singular, 0.0, Z / denom)
+    if kind == "neumann":
+        Y = sfft.idct(Z, type=2, axis=0, norm="ortho")
+    elif kind == "dirichlet":
+        Y = sfft.idst(Z, type=2, axis=0, norm="ortho")
+    else:
+        Y = np.zeros((nz,) + Z.shape[1:], dtype=complex)
+        Y[: nz - 1] = sfft.idst(Z, type=1, axis=0, norm="ortho")
+    return np.ascontiguousarray(np.fft.ifft2(Y, axes=(1, 2)).real)
+
+
+# ---------------------------------------------------------------------------------------
+# dual-grid transfer (Sec. 3.1)
+# ---------------------------------------------------------------------------------------
+
+
+def prolong(u, v, w, ry):
+    """Coarse face velocities -> fine face velocities (eq. dual1, Rudman's interpolation).
+
+    Along the component's own axis, a fine face that coincides with a coarse face takes
+    its value and the fine face through a coarse cell centre takes the mean of the two
+    coarse faces; across the other axes the value is constant over the two fine cells.
+    The bottom-wall w is 0. The result keeps the discrete divergence of every fine cell
+    equal to that of its coarse parent cell.
+    """
+    nz, ny, nx = u.shape
+
+    def rep(a, axes):
+        for ax, r in axes:
+            if r > 1:
+                a = np.repeat(a, r, axis=ax)
+        return a
+
+    uf = np.empty((nz, ny, 2 * nx))
+    uf[:, :, 1::2] = u
+    uf[:, :, 0::2] = 0.5 * (xm(u) + u)
+    uf = rep(uf, [(1, ry), (0, 2)])
+
+    if ry == 2:
+        vf = np.empty((nz, 2 * ny, nx))
+        vf[:, 1::2, :] = v
+        vf[:, 0::2, :] = 0.5 * (ym(v) + v)
+    else:
+        vf = v.copy()
+    vf = rep(vf, [(2, 2), (0, 2)])
+
+    wf = np.empty((2 * nz, ny, nx))
+    wf[1::2] = w
+    wf[0::2] = 0.5 * (zm_face(w) + w)
+    wf = rep(wf, [(2, 2), (1, ry)])
+    return uf, vf, wf
+
+
+def _restrict_axis(f, axis, loc, r, wall):
+    """1D rule of eq. dual2 along one axis. 'c': coarse centre i averages fine (r i .. r i +
+    r - 1); 'f': coarse face i (at (i+1) h) averages the two fine cells on either side of
+    it. Periodic axes wrap; on the wall axis the faces run from the bottom wall (index -1)
+    to the top wall (nz - 1), and a fine neighbour beyond a wall is replaced by the
+    wall-adjacent fine cell (Neumann ghost), giving nz + 1 face layers."""
+    n = f.shape[axis]
+    take = lambda idx: np.take(f, idx, axis=axis)
+    if loc == "c":
+        if r == 1:
+            return f.copy()
+        return 0.5 * (take(np.arange(0, n, 2)) + take(np.arange(1, n, 2)))
+    if wall:
+        kf = np.arange(-1, n // 2)
+        a = np.clip(2 * kf + 1, 0, n - 1)
+        b = np.clip(2 * kf + 2, 0, n - 1)
+        return 0.5 * (take(a) + take(b))
+    if r == 1:
+        return 0.5 * (f + np.roll(f, -1, axis=axis))
+    nc = n // 2
+    a = (2 * np.arange(nc) + 1) % n
+    b = (2 * np.arange(nc) + 2) % n
+    return 0.5 * (take(a) + take(b))
+
+
+def restrict(f, loc, ry):
+    """Fine cell-centred field -> coarse location ``loc`` = (z, y, x) letters in {'c','f'}
+    (eq. dual2, extended to 3D as a tensor product of the 1D rules). A z face location
+    returns nz + 1 layers (bottom wall .. top wall)."""
+    lz, ly, lx = loc
+    g = _restrict_axis(f, 2, lx, 2, False)
+    g = _restrict_axis(g, 1, ly, ry, False)
+    g = _restrict_axis(g, 0, lz, 2, True)
+    return g
+
+
+def mixture(phi, a1, a2):
+    """Property linear in phi (eqs. NS8, NS9, dual3): phase 1 at phi = +1."""
+    return 0.5 * (1.0 + phi) * a1 + 0.5 * (1.0 - phi) * a2
+
+
+# ---------------------------------------------------------------------------------------
+# divergence / gradient on the staggered coarse grid
+# ---------------------------------------------------------------------------------------
+
+
+def divergence(u, v, w, h):
+    hx, hy, hz = h
+    return (u - xm(u)) / hx + (v - ym(v)) / hy + (w - zm_face(w)) / hz
+
+
+def gradient(p, h):
+    """Face gradient of a centred field with zero normal gradient at the walls."""
+    hx, hy, hz = h
+    gz = (zp_neu(p) - p) / hz
+    gz[-1] = 0.0
+    return (xp(p) - p) / hx, (yp(p) - p) / hy, gz

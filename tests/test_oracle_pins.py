@@ -1,0 +1,498 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by the mathematics.
+
+Each test checks the oracle against something other than itself: a loop-built dense
+operator, an exact discrete invariant, a closed form, or the temporal order of the scheme.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import discrete as D
+from oracle import model
+from oracle import step as S
+from tests import bruteforce as BF
+
+
+def _params(**kw):
+    base = dict(nx=8, ny=4, nz=6, lx=1.0, ly=0.5, lz=0.75, re=10.0, ca=0.5, cn=0.05, pe=50.0,
+                dt=1e-3)
+    base.update(kw)
+    return model.Params(**base)
+
+
+# --------------------------------------------------------------------------------------
+# Dong splitting constants (eqs. NS29-NS30)
+# --------------------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("sf", [1.0, 1.5, 3.0])
+@pytest.mark.parametrize("first", [True, False])
+def test_dong_factorisation(sf, first):
+    P = _params(s_factor=sf, cn=0.01, pe=1000.0, dt=1e-4)
+    C = model.constants(P, first)
+    g0 = 1.0 if first else 1.5
+    cn2 = P.cn ** 2
+    # (L - c)(L + alpha) must equal L^2 - (S/Cn^2) L + gamma0 / (M lambda dt)
+    assert math.isclose(C.alpha - C.c_psi, -C.S / cn2, rel_tol=1e-14)
+    assert math.isclose(-C.alpha * C.c_psi, g0 * P.pe / (P.dt * cn2), rel_tol=1e-12)
+    # NS30 bound on S
+    assert C.S / cn2 >= math.sqrt(4 * g0 * P.pe / (cn2 * P.dt)) * (1 - 1e-15)
+    if sf == 1.0:
+        assert C.c_psi == pytest.approx(-C.alpha, rel=1e-15)
+    assert C.alpha < 0 < C.c_psi
+    # C1 example: S ~ 77.5 on the BDF2 steps
+    if not first and sf == 1.0:
+        assert C.S == pytest.approx(0.01 * math.sqrt(4 * 1.5 * 1000 / 1e-4), rel=1e-15)
+
+
+# --------------------------------------------------------------------------------------
+# constant-coefficient solvers vs loop-built dense operators
+# --------------------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("kind", ["neumann", "dirichlet", "wface"])
+@pytest.mark.parametrize("shape", [(6, 4, 8), (5, 1, 8)])
+def test_helmholtz_matches_dense_solve(kind, shape):
+    rng = np.random.default_rng(7)
+    h = (0.13, 0.21, 0.17)
+    coeff, shift = 0.7, 3.3
+    A = BF.dense_operator(shape, h, coeff, shift, kind)
+    rhs = rng.standard_normal(shape)
+    if kind == "wface":
+        rhs[-1] = 0.0
+        ref = np.zeros(shape)
+        ref[:-1] = np.linalg.solve(A, rhs[:-1].ravel()).reshape((shape[0] - 1,) + shape[1:])
+    else:
+        ref = np.linalg.solve(A, rhs.ravel()).reshape(shape)
+    x = D.helmholtz(rhs, coeff, shift, kind, h)
+    assert np.max(np.abs(x - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_neumann_poisson_zero_mean():
+    rng = np.random.default_rng(3)
+    shape, h = (6, 4, 8), (0.1, 0.2, 0.15)
+    rhs = rng.standard_normal(shape)
+    rhs -= rhs.mean()
+    A = BF.dense_operator(shape, h, 1.0, 0.0, "neumann")
+    x = D.helmholtz(rhs, 1.0, 0.0, "neumann", h)
+    assert abs(x.mean()) < 1e-13
+    r = A @ x.ravel() - rhs.ravel()
+    assert np.max(np.abs(r)) < 1e-11 * np.max(np.abs(rhs))
+
+
+@pytest.mark.parametrize("kind,basis", [
+    ("neumann", lambda m, k, n: np.cos(np.pi * m * (k + 0.5) / n)),
+    ("dirichlet", lambda m, k, n: np.sin(np.pi * (m + 1) * (k + 0.5) / n)),
+])
+def test_exact_eigenmodes(kind, basis):
+    """A separable product of discrete eigenvectors is reproduced with the factor
+    1 / (coeff lambda - shift), lambda taken from the loop Laplacian of the mode."""
+    nz, ny, nx = 8, 4, 16
+    h = (0.1, 0.3, 0.125)
+    k = np.arange(nz)[:, None, None]
+    j = np.arange(ny)[None, :, None]
+    i = np.arange(nx)[None, None, :]
+    mode = basis(3, k, nz) * np.cos(2 * np.pi * 1 * (j + 0.5) / ny) * np.cos(2 * np.pi * 5 * (i + 0.5) / nx)
+    ghost = BF.neumann_ghost if kind == "neumann" else (lambda kg, a, jj, ii: -a[0, jj, ii] if kg < 0 else -a[-1, jj, ii])
+    Lm = BF.lap(mode, h, ghost)
+    sel = np.abs(mode) > 0.1
+    lam = np.mean(Lm[sel] / mode[sel])
+    assert np.allclose(Lm, lam * mode, atol=1e-10 * abs(lam))
+    coeff, shift = 1.3, -0.4
+    x = D.helmholtz(mode, coeff, shift, kind, h)
+    assert np.max(np.abs(x - mode / (coeff * lam - shift))) < 1e-13 * np.max(np.abs(x))
+
+
+# --------------------------------------------------------------------------------------
+# dual-grid transfers (eqs. dual1-dual3)
+# --------------------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("ny", [1, 4])
+def test_prolongation_preserves_divergence(ny):
+    rng = np.random.default_rng(11)
+    nz, nx = 6, 8
+    h = (0.2, 0.25, 0.15)
+    u, v, w = (rng.standard_normal((nz, ny, nx)) for _ in range(3))
+    w[-1] = 0.0
+    if ny == 1:
+        v[:] = 0.0
+    ry = 1 if ny == 1 else 2
+    uf, vf, wf = D.prolong(u, v, w, ry)
+    hf = (h[0] / 2, h[1] / ry, h[2] / 2)
+    # fine divergence by loops
+    nzf, nyf, nxf = uf.shape
+    divf = np.zeros((nzf, nyf, nxf))
+    for K in range(nzf):
+        for J in range(nyf):
+            for I in range(nxf):
+                wd = wf[K - 1, J, I] if K > 0 else 0.0
+                divf[K, J, I] = ((uf[K, J, I] - uf[K, J, I - 1]) / hf[0]
+                                 + (vf[K, J, I] - vf[K, J - 1, I]) / hf[1]
+                                 + (wf[K, J, I] - wd) / hf[2])
+    divc = D.divergence(u, v, w, h)
+    rep = np.repeat(np.repeat(np.repeat(divc, 2, axis=0), ry, axis=1), 2, axis=2)
+    assert np.max(np.abs(divf - rep)) < 1e-12 * np.max(np.abs(divc))
+    # top fine wall face and constants
+    assert np.all(wf[-1] == 0.0)
+    c = np.full((nz, ny, nx), 0.37)
+    ufc, _, _ = D.prolong(c, c, np.where(np.arange(nz)[:, None, None] < nz - 1, c, 0.0), ry)
+    assert np.all(ufc == 0.37)
+
+
+@pytest.mark.parametrize("ny", [1, 4])
+def test_restriction_invariants(ny):
+    rng = np.random.default_rng(5)
+    ry = 1 if ny == 1 else 2
+    f = rng.standard_normal((12, ry * ny, 16))
+    for loc in ("ccc", "ccf", "cfc", "fcc", "cff", "fcf", "ffc"):
+        c = D.restrict(np.full_like(f, -0.61), loc, ry)
+        assert np.all(c == -0.61)
+    rc = D.restrict(f, "ccc", ry)
+    assert rc.mean() == pytest.approx(f.mean(), abs=1e-15)
+    # x-face value is the mean of the 2 x 2 x 2 (ry=2) fine cells straddling the face
+    rx = D.restrict(f, "ccf", ry)
+    k, j, i = 2, 0, 7
+    ys = [ry * j + a for a in range(ry)]
+    cells = [f[2 * k + a, yy, (2 * i + 1 + b) % 16] for a in range(2) for yy in ys for b in range(2)]
+    assert rx[k, j, i] == pytest.approx(np.mean(cells), rel=1e-15)
+    # wall z-face: Neumann ghost = wall-adjacent fine layer
+    rz = D.restrict(f, "fcc", ry)
+    assert rz.shape[0] == 7
+    cells = [f[0, yy, 2 * i + b] for yy in ys for b in range(2)]
+    assert rz[0, j, i] == pytest.approx(np.mean(cells), rel=1e-15)
+
+
+# --------------------------------------------------------------------------------------
+# Cahn-Hilliard step (eqs. NS25-NS34)
+# --------------------------------------------------------------------------------------
+
+
+def _random_state(P, rng, amp_u=0.3):
+    nzf, nyf, nxf = P.fine_shape
+    cs = P.coarse_shape
+    phi0 = np.tanh(rng.standard_normal((nzf, nyf, nxf)))
+    phi1 = phi0 + 0.01 * rng.standard_normal(phi0.shape)
+    vel = lambda: amp_u * rng.standard_normal(cs)
+    u = [vel(), vel()]
+    v = [vel(), vel()] if P.ny > 1 else [np.zeros(cs), np.zeros(cs)]
+    w = [vel(), vel()]
+    for a in w:
+        a[-1] = 0.0
+    z = lambda: np.zeros(cs)
+    return {"phi": [phi0, phi1], "u": u, "v": v, "w": w, "p": [z(), z()],
+            "tau": [[z() for _ in range(6)], [z() for _ in range(6)]], "step": 3}
+
+
+@pytest.mark.parametrize("ny,first", [(1, False), (2, False), (2, True)])
+def test_ch_solves_unsplit_equation(ny, first):
+    """phi^{n+1} satisfies the unsplit eq. NS25 with the wetting ghost of eq. NS34 and the
+    zero-flux outer Laplacian, evaluated cell by cell."""
+    rng = np.random.default_rng(21)
+    P = _params(nx=4, ny=ny, nz=4, ly=0.25 * ny, theta_bottom_deg=60.0, theta_top_deg=110.0,
+                s_factor=1.3)
+    st = _random_state(P, rng)
+    if first:
+        st["step"] = 0
+    C = model.constants(P, first)
+    phi, G, phis, _ = S.cahn_hilliard(P, st, C)
+    hf = P.hf
+    nzf, nyf, nxf = phi.shape
+    p0, p1 = st["phi"]
+    if first:
+        ps, ph = p0, p0
+        us, vs, ws = st["u"][0], st["v"][0], st["w"][0]
+    else:
+        ps, ph = 2 * p0 - p1, 2 * p0 - 0.5 * p1
+        us = 2 * st["u"][0] - st["u"][1]
+        vs = 2 * st["v"][0] - st["v"][1]
+        ws = 2 * st["w"][0] - st["w"][1]
+    cn2 = P.cn ** 2
+    gw = {}
+    for K, th in ((0, P.theta_bottom_deg), (nzf - 1, P.theta_top_deg)):
+        gw[K] = math.cos(math.radians(th)) * (1 - ps[K] ** 2) / (math.sqrt(2) * P.cn)
+    # fine face velocities by loops (dual1)
+    ry = P.ry
+
+    def ufine(K, J, I):
+        k, j = K // 2, J // ry
+        i = I // 2
+        return us[k, j, i] if I % 2 == 1 else 0.5 * (us[k, j, i - 1] + us[k, j, i])
+
+    def vfine(K, J, I):
+        k, i = K // 2, I // 2
+        if ry == 1:
+            return vs[k, 0, i]
+        j = J // 2
+        return vs[k, j, i] if J % 2 == 1 else 0.5 * (vs[k, j - 1, i] + vs[k, j, i])
+
+    def wfine(K, J, I):
+        j, i = J // ry, I // 2
+        k = K // 2
+        if K % 2 == 1:
+            return ws[k, j, i]
+        lo = ws[k - 1, j, i] if k > 0 else 0.0
+        return 0.5 * (lo + ws[k, j, i])
+
+    def at(a, K, J, I):
+        return a[K, J % nyf, I % nxf]
+
+    def lap_w(a, K, J, I):
+        c = a[K, J, I]
+        s = (at(a, K, J, I + 1) - 2 * c + at(a, K, J, I - 1)) / hf[0] ** 2
+        s += (at(a, K, J + 1, I) - 2 * c + at(a, K, J - 1, I)) / hf[1] ** 2
+        up = a[K + 1, J, I] if K + 1 < nzf else c + hf[2] * gw[nzf - 1][J, I]
+        dn = a[K - 1, J, I] if K > 0 else c + hf[2] * gw[0][J, I]
+        return s + (up - 2 * c + dn) / hf[2] ** 2
+
+    inner = np.zeros_like(phi)
+    for K in range(nzf):
+        for J in range(nyf):
+            for I in range(nxf):
+                f = (ps[K, J, I] ** 3 - ps[K, J, I]) / cn2
+                inner[K, J, I] = lap_w(phi, K, J, I) - (C.S / cn2) * (phi[K, J, I] - ps[K, J, I]) - f
+    outer = BF.lap(inner, hf, BF.neumann_ghost)
+    res = np.zeros_like(phi)
+    scale = 0.0
+    for K in range(nzf):
+        for J in range(nyf):
+            for I in range(nxf):
+                def flux(u_face, a, b):
+                    return u_face * 0.5 * (a + b)
+                fxp = flux(ufine(K, J, I), ps[K, J, I], at(ps, K, J, I + 1))
+                fxm = flux(ufine(K, J, (I - 1) % nxf), at(ps, K, J, I - 1), ps[K, J, I])
+                fyp = flux(vfine(K, J, I), ps[K, J, I], at(ps, K, J + 1, I))
+                fym = flux(vfine(K, (J - 1) % nyf, I), at(ps, K, J - 1, I), ps[K, J, I])
+                fzp = flux(wfine(K, J, I), ps[K, J, I], ps[K + 1, J, I]) if K + 1 < nzf else 0.0
+                fzm = flux(wfine(K - 1, J, I), ps[K - 1, J, I], ps[K, J, I]) if K > 0 else 0.0
+                A = (fxp - fxm) / hf[0] + (fyp - fym) / hf[1] + (fzp - fzm) / hf[2]
+                term_t = (C.gamma0 * phi[K, J, I] - ph[K, J, I]) / P.dt
+                res[K, J, I] = term_t + A + (cn2 / P.pe) * outer[K, J, I]
+                scale = max(scale, abs(ph[K, J, I]) / P.dt, abs(A))
+    assert np.max(np.abs(res)) < 1e-9 * scale
+    # chemical potential: lambda times the bracket of NS25 (lambda = Cn^2 here)
+    Gref = -cn2 * inner  # -Cn^2 [L_w phi - (S/Cn^2)(phi - phi*) - f(phi*)]
+    assert np.max(np.abs(G - Gref)) < 1e-9 * np.max(np.abs(Gref))
+
+
+@pytest.mark.parametrize("theta", [60.0, 90.0, 135.0])
+def test_ch_mass_conservation(theta):
+    rng = np.random.default_rng(2)
+    P = _params(nx=8, ny=4, nz=6, ly=0.5, theta_bottom_deg=theta, theta_top_deg=180 - theta)
+    st = _random_state(P, rng)
+    C = model.constants(P, False)
+    phi, _, _, _ = S.cahn_hilliard(P, st, C)
+    # sum(gamma0 phi^{n+1} - phi_hat) = 0: advection and the zero-flux Laplacian telescope
+    before = np.sum(2.0 * st["phi"][0] - 0.5 * st["phi"][1]) / 1.5
+    assert abs(np.sum(phi) - before) < 1e-13 * np.sum(np.abs(phi))
+
+
+def test_ch_temporal_order_linear_mode():
+    """A small-amplitude discrete eigenmode of the linearised CH equation grows as
+    exp(sigma t), sigma = -(lam + Cn^2 lam^2) / Pe; the scheme converges to it at second
+    order in dt when S is held fixed."""
+    nxf, nzf = 16, 8
+    lx, lz = 1.0, 0.5
+    cfgbase = dict(nx=nxf // 2, ny=1, nz=nzf // 2, lx=lx, ly=lx / (nxf // 2), lz=lz, re=1.0,
+                   ca=1.0, cn=0.05, pe=0.5, theta_bottom_deg=90.0, theta_top_deg=90.0)
+    I = np.arange(nxf)[None, None, :]
+    K = np.arange(nzf)[:, None, None]
+    mode = np.cos(2 * np.pi * (I + 0.5) / nxf) * np.cos(np.pi * (K + 0.5) / nzf)
+    hf = (lx / nxf, lx / (nxf // 2), lz / nzf)
+    Lm = BF.lap(mode, hf, BF.neumann_ghost)
+    lam = Lm[0, 0, 0] / mode[0, 0, 0]
+    cn = cfgbase["cn"]
+    sigma = -(lam + cn ** 2 * lam ** 2) / cfgbase["pe"]
+    T = 0.4 / abs(sigma)
+    eps = 1e-7
+    errs = []
+    S_fixed = None
+    for n in (20, 40, 80):
+        dt = T / n
+        g = cn * math.sqrt(4 * 1.0 * cfgbase["pe"] / dt)
+        if S_fixed is None:
+            S_fixed = 4.0 * g * math.sqrt(1.5)
+        P = model.Params(dt=dt, s_factor=S_fixed / (cn * math.sqrt(4 * 1.5 * cfgbase["pe"] / dt)), **cfgbase)
+        assert P.s_factor >= 1.0
+        cs = P.coarse_shape
+        z = lambda: np.zeros(cs)
+        st = {"phi": [eps * mode, eps * mode], "u": [z(), z()], "v": [z(), z()], "w": [z(), z()],
+              "p": [z(), z()], "tau": [[z()] * 6, [z()] * 6], "step": 0}
+        for _ in range(n):
+            C = model.constants(P, st["step"] == 0)
+            phi, _, _, _ = S.cahn_hilliard(P, st, C)
+            st = dict(st, phi=[phi, st["phi"][0]], step=st["step"] + 1)
+        exact = eps * math.exp(sigma * T) * mode
+        errs.append(np.max(np.abs(st["phi"][0] - exact)) / np.max(np.abs(exact)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.3 < r1 < 4.8 and 3.3 < r2 < 4.8, errs
+
+
+# --------------------------------------------------------------------------------------
+# Navier-Stokes (eqs. NS35-NS39)
+# --------------------------------------------------------------------------------------
+
+
+def _uniform_phase_state(P, phase, u=None):
+    cs = P.coarse_shape
+    z = lambda: np.zeros(cs)
+    phi = np.full(P.fine_shape, float(phase))
+    u = z() if u is None else u
+    return {"phi": [phi, phi.copy()], "u": [u.copy(), u.copy()], "v": [z(), z()],
+            "w": [z(), z()], "p": [z(), z()], "tau": [[z()] * 6, [z()] * 6], "step": 5}
+
+
+@pytest.mark.parametrize("phase", [-1.0, 1.0])
+def test_poiseuille_steady_state(phase):
+    """Body-force channel flow: the discrete steady profile (tridiagonal solve of
+    mu/(Re rho) D2 u = -a with no-slip ghosts, built here by loops) is a fixed point."""
+    P = _params(nx=8, ny=2, nz=12, ly=0.25, lz=1.0, rho_ratio=4.0, mu_ratio=2.0,
+                a_ext=(0.8, 0.0, 0.0))
+    C = model.constants(P, False)
+    nz = P.nz
+    hz = P.h[2]
+    mu = C.mu1 if phase > 0 else C.mu2
+    rho = C.rho1 if phase > 0 else C.rho2
+    A = np.zeros((nz, nz))
+    for k in range(nz):
+        A[k, k] = -2.0
+        if k > 0:
+            A[k, k - 1] = 1.0
+        else:
+            A[k, k] -= 1.0
+        if k < nz - 1:
+            A[k, k + 1] = 1.0
+        else:
+            A[k, k] -= 1.0
+    A *= mu / (P.re * rho * hz ** 2)
+    prof = np.linalg.solve(A, -P.a_ext[0] * np.ones(nz))
+    u = np.broadcast_to(prof[:, None, None], P.coarse_shape).copy()
+    st = _uniform_phase_state(P, phase, u)
+    for _ in range(4):
+        st = S.step(P, st)
+    assert np.max(np.abs(st["u"][0] - u)) < 1e-11 * np.max(np.abs(u))
+    assert np.max(np.abs(st["w"][0])) < 1e-12 * np.max(np.abs(u))
+    assert np.max(np.abs(st["phi"][0] - phase)) < 1e-12
+
+
+def test_shear_mode_temporal_order():
+    """Decay of the lowest no-slip shear mode u(z) of uniform fluid: the projection scheme
+    reduces to BDF2 with implicit viscosity; error vs exp(lam t / Re) falls as dt^2."""
+    nz = 8
+    P0 = dict(nx=4, ny=1, nz=nz, lx=1.0, ly=0.25, lz=1.0, re=2.0, ca=1.0, cn=0.05, pe=10.0)
+    kk = np.arange(nz)
+    prof = np.sin(np.pi * (kk + 0.5) / nz)
+    hz = 1.0 / nz
+    up = np.append(prof[1:], -prof[-1])
+    dn = np.insert(prof[:-1], 0, -prof[0])
+    lam = ((up - 2 * prof + dn) / hz ** 2)[2] / prof[2]
+    T = 0.5 * P0["re"] / abs(lam)
+    errs = []
+    for n in (10, 20, 40):
+        P = model.Params(dt=T / n, **P0)
+        u0 = np.broadcast_to(prof[:, None, None], P.coarse_shape).copy()
+        st = _uniform_phase_state(P, 1.0, u0)
+        st["step"] = 0
+        st = S.run(P, st, n)
+        exact = u0 * math.exp(lam * T / P.re)
+        errs.append(np.max(np.abs(st["u"][0] - exact)) / np.max(np.abs(exact)))
+    assert 3.5 < errs[0] / errs[1] < 4.6 and 3.5 < errs[1] / errs[2] < 4.6, errs
+
+
+def test_projection_divergence_free():
+    rng = np.random.default_rng(4)
+    P = _params(nx=8, ny=4, nz=6, ly=0.5, rho_ratio=10.0, mu_ratio=3.0, theta_bottom_deg=70.0)
+    st = _random_state(P, rng, amp_u=0.05)
+    new = S.step(P, st)
+    u, v, w = new["u"][0], new["v"][0], new["w"][0]
+    div = D.divergence(u, v, w, P.h)
+    assert np.max(np.abs(div)) < 1e-11 * np.max(np.abs(u)) / min(P.h)
+    assert np.all(w[-1] == 0.0)
+
+
+# --------------------------------------------------------------------------------------
+# Oldroyd-B polymer stress (eqs. NS4, NS40-NS44)
+# --------------------------------------------------------------------------------------
+
+
+def test_oldroyd_b_shear_closed_form():
+    """For a steady shear u_x(z), RH vanishes at tau_xz = (1-beta) g, tau_xx = 2 Wi (1-beta)
+    g^2 and all other components 0, g the discrete shear rate (2h difference of the
+    cell-centred velocity, no-slip ghost)."""
+    P = _params(nx=4, ny=2, nz=10, ly=0.5, lz=1.0, wi=0.7, beta=0.4, viscoelastic=1)
+    nz = P.nz
+    hz = P.h[2]
+    zc = (np.arange(nz) + 0.5) * hz
+    prof = 3.0 * zc * (1 - zc) + 0.4 * zc ** 3
+    u = np.broadcast_to(prof[:, None, None], P.coarse_shape).copy()
+    v = np.zeros_like(u)
+    w = np.zeros_like(u)
+    g = np.zeros(nz)
+    for k in range(nz):
+        up = prof[k + 1] if k + 1 < nz else -prof[-1]
+        dn = prof[k - 1] if k > 0 else -prof[0]
+        g[k] = (up - dn) / (2 * hz)
+    G = np.broadcast_to(g[:, None, None], u.shape)
+    tau = [np.zeros_like(u) for _ in range(6)]
+    tau[S.XZ] = (1 - P.beta) * G
+    tau[S.XX] = 2 * P.wi * (1 - P.beta) * G ** 2
+    L = S.velocity_gradient(P, u, v, w)
+    rh = S.polymer_rhs(P, tau, u, v, w, L)
+    scale = np.max(np.abs(tau[S.XX])) / P.wi
+    for c in range(6):
+        assert np.max(np.abs(rh[c])) < 1e-12 * scale
+    # the wrong sign of the upper-convected terms would leave a residual: check it matters
+    tau_bad = [t.copy() for t in tau]
+    tau_bad[S.XX] = -tau_bad[S.XX]
+    rh_bad = S.polymer_rhs(P, tau_bad, u, v, w, L)
+    assert np.max(np.abs(rh_bad[S.XX])) > 1e-3 * scale
+
+
+def test_polymer_relaxation_rk2_factor():
+    P = _params(nx=4, ny=2, nz=4, ly=0.5, wi=0.3, beta=0.5, dt=0.05, viscoelastic=1)
+    rng = np.random.default_rng(8)
+    vals = rng.standard_normal(6)
+    tau = [np.full(P.coarse_shape, a) for a in vals]
+    z = np.zeros(P.coarse_shape)
+    out = S.polymer(P, tau, z, z, z)
+    r = P.dt / P.wi
+    fac = 1 - r + 0.5 * r * r
+    for c in range(6):
+        assert np.allclose(out[c], vals[c] * fac, rtol=1e-14, atol=0)
+
+
+# --------------------------------------------------------------------------------------
+# full step invariants and observables
+# --------------------------------------------------------------------------------------
+
+
+def test_full_step_mass_and_determinism():
+    cfg = W.config("C1", nx=16, nz=8, ly=2 / 16, steps=5)
+    P = model.Params.from_config(cfg)
+    st0 = W.droplet_state(cfg)
+    m0 = np.sum(st0["phi"][0])
+    st = S.run(P, st0, 6)
+    assert abs(np.sum(st["phi"][0]) - m0) < 1e-13 * np.sum(np.abs(st["phi"][0]))
+    st2 = S.run(P, W.droplet_state(cfg), 6)
+    assert np.array_equal(st["phi"][0], st2["phi"][0])
+    assert np.array_equal(st["u"][0], st2["u"][0])
+
+
+def test_observables_of_initial_drop():
+    """Semicircle of radius R on the wall: wetted half-length ~ R, centroid 4R/(3 pi)."""
+    cfg = W.config("C1", noise=0.0)
+    P = model.Params.from_config(cfg)
+    o = S.observables(P, W.droplet_state(cfg))
+    R = cfg.radius
+    assert o["wetted_radius"] == pytest.approx(R, abs=0.02 * R)
+    # diffuse interface shifts the centroid slightly; the sharp value is 4R/(3 pi)
+    assert o["centroid_height"] == pytest.approx(4 * R / (3 * math.pi), rel=0.05)
+    cfg3 = W.config("C2", nx=32, ny=32, nz=16)
+    P3 = model.Params.from_config(cfg3)
+    o3 = S.observables(P3, W.droplet_state(cfg3))
+    assert o3["wetted_radius"] == pytest.approx(cfg3.radius, rel=0.06)
+    assert o3["centroid_height"] == pytest.approx(3 * cfg3.radius / 8, rel=0.08)
