@@ -1,0 +1,186 @@
+/*
+ * drpf -- dual-resolution phase-field step for AMD MI355X (gfx950).
+ *
+ * One coupled time step of the dual-resolution phase-field solver of Bazesefidpar, Brandt
+ * and Tammisola: Cahn-Hilliard (Dong's stabilised splitting into two constant-coefficient
+ * Helmholtz equations, eqs. NS25-NS34 of the paper) on a phase-field grid twice as fine as
+ * the flow grid, Navier-Stokes with variable density and viscosity by the
+ * constant-coefficient projection (eqs. NS35-NS39), and an Oldroyd-B polymer stress
+ * (eq. NS4 with alpha = 0, advanced by the second-order TVD Runge-Kutta of eqs. NS40-NS44
+ * in stress form). The grids exchange data through the divergence-preserving prolongation
+ * (eq. dual1) and averaging restriction (eqs. dual2, dual3) of Sec. 3.1.
+ *
+ * Conventions
+ *   - Array layout [z][y][x], x contiguous. x and y periodic, z wall-normal with walls at
+ *     z = 0 and z = lz.
+ *   - Coarse grid nx * ny * nz cells (spacings lx/nx, ly/ny, lz/nz). The phase-field grid
+ *     has 2nx * ry*ny * 2nz cells with ry = 2, or ry = 1 when ny == 1 (the 2D form).
+ *   - Staggering: p and tau at cell centres; u[k][j][i] at x = (i+1) hx, v[k][j][i] at
+ *     y = (j+1) hy, w[k][j][i] at z = (k+1) hz (w[nz-1][.][.] is the top wall and stays 0;
+ *     the bottom-wall w is implicit and 0). phi at fine cell centres.
+ *   - Nondimensional groups follow the paper's problem statement (Sec. 4): Re, Ca, Cn, Pe,
+ *     Wi, beta, static contact angles (eq. NS16, measured through the drop, phase
+ *     phi = +1), rho_ratio = drop/ambient density, mu_ratio = drop/ambient viscosity.
+ *   - Scalars are double on the host. Device arrays hold double when precision == 64 and
+ *     float when precision == 32.
+ *
+ * Memory ownership: the caller allocates every device buffer (state arrays, the workspace)
+ * and keeps it valid until the work queued on the stream has completed. The library never
+ * allocates or frees device memory. A drpf_grid is a host object owned by the library,
+ * released by drpf_destroy.
+ *
+ * Streams: every call that takes a stream queues its work asynchronously on it (a
+ * hipStream_t passed as void*; NULL is the default stream), except drpf_observables, which
+ * synchronises that stream before returning. Calls on one grid must not overlap.
+ *
+ * Errors: every call returns one of the DRPF_* codes below; drpf_last_error() gives a
+ * thread-local message for the last failure on the calling thread.
+ */
+#ifndef DRPF_H
+#define DRPF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DRPF_OK 0
+#define DRPF_EINVAL 1        /* invalid argument or parameter set                      */
+#define DRPF_EWORKSPACE 2    /* workspace missing, too small or misaligned             */
+#define DRPF_EHIP 3          /* a HIP runtime call or kernel launch failed             */
+#define DRPF_ENONFINITE 4    /* a non-finite value was found (drpf_observables)         */
+#define DRPF_EUNSUPPORTED 5  /* valid but not supported by this build                  */
+
+/* Locations for drpf_restrict (eq. dual2 generalised to 3D as a tensor product of the
+ * 1D rules: along a centre-located axis coarse index i averages fine 2i and 2i+1; along a
+ * face-located axis it averages the two fine cells either side of the face at (i+1)h).
+ * Outputs for FACE_Z, EDGE_XZ and EDGE_YZ have nz+1 z layers, the bottom wall first; a
+ * fine neighbour beyond a wall is replaced by the wall-adjacent fine cell. */
+enum drpf_location {
+  DRPF_CENTER = 0,
+  DRPF_FACE_X = 1,
+  DRPF_FACE_Y = 2,
+  DRPF_FACE_Z = 3,
+  DRPF_EDGE_XY = 4,
+  DRPF_EDGE_XZ = 5,
+  DRPF_EDGE_YZ = 6
+};
+
+/* Grids and boundary kinds for drpf_helmholtz_solve. */
+enum drpf_which_grid { DRPF_GRID_FINE = 0, DRPF_GRID_COARSE = 1 };
+enum drpf_bc {
+  DRPF_BC_NEUMANN = 0,          /* cell-centred in z, zero normal gradient at the walls */
+  DRPF_BC_DIRICHLET = 1,        /* cell-centred in z, zero value (ghost = -adjacent)    */
+  DRPF_BC_FACE_DIRICHLET = 2    /* z-face located, unknowns k = 0..nz-2, walls 0        */
+};
+
+typedef struct drpf_params {
+  int nx, ny, nz;              /* coarse cells; powers of two; nx, nz >= 4; ny == 1 or >= 4 */
+  double lx, ly, lz;           /* box lengths (> 0)                                         */
+  double re, ca, cn, pe;       /* Reynolds, capillary, Cahn, Peclet numbers (> 0)           */
+  double wi, beta;             /* Weissenberg number and solvent-viscosity ratio of drop    */
+  double theta_bottom_deg;     /* static contact angle at z = 0, degrees in [0, 180]        */
+  double theta_top_deg;        /* static contact angle at z = lz                            */
+  double rho_ratio, mu_ratio;  /* drop / ambient density and total viscosity (> 0)          */
+  double dt;                   /* time step (> 0)                                           */
+  double s_factor;             /* stabilisation S as a multiple of the bound of eq. NS30, >= 1 */
+  double a_ext[3];             /* body acceleration (x, y, z)                               */
+  int viscoelastic;            /* 1: drop phase carries an Oldroyd-B polymer stress         */
+  int precision;               /* 64 or 32: element type of every device array              */
+} drpf_params;
+
+/* Device pointers of one solution state. Level n is index 0, level n-1 index 1.
+ * phi[2] is a third fine buffer the step writes the new phase field into.
+ * drpf_step rotates the pointers in this host struct after every step (no copies):
+ * afterwards phi[0] is level n+1, phi[1] level n, phi[2] the free buffer, and for the
+ * coarse fields [0] points to level n+1 (stored in the former n-1 buffer) and [1] to level
+ * n. tau[level][c], c = xx, yy, zz, xy, xz, yz, is read and written only when
+ * viscoelastic != 0. step counts completed steps; step == 0 takes the one-level start
+ * (gamma0 = 1, extrapolations replaced by level n). */
+typedef struct drpf_state {
+  void* phi[3];
+  void* u[2];
+  void* v[2];
+  void* w[2];
+  void* p[2];
+  void* tau[2][6];
+  long long step;
+} drpf_state;
+
+typedef struct drpf_grid drpf_grid;
+
+/* Observables returned by drpf_observables, in this order. */
+enum drpf_observable {
+  DRPF_OBS_MASS = 0,            /* h_f^3 * sum(phi), FP64 tree sum                        */
+  DRPF_OBS_WETTED_RADIUS = 1,   /* 2D: half the wetted length; 3D: sqrt(wetted area / pi),
+                                   from (1+phi)/2 on the wall-adjacent fine layer           */
+  DRPF_OBS_CENTROID_HEIGHT = 2, /* sum(z (1+phi)/2) / sum((1+phi)/2)                        */
+  DRPF_OBS_KINETIC_ENERGY = 3,  /* 0.5 h^3 sum(u^2 + v^2 + w^2) over the face arrays        */
+  DRPF_OBS_MAX_DIV = 4,         /* max |div u| over coarse cells                            */
+  DRPF_OBS_COUNT = 5
+};
+
+/* Fills every field with the defaults: C1-like 2D box, Newtonian, s_factor 1, FP64. */
+int drpf_params_default(drpf_params* p);
+
+/* Checks a parameter set (the rules in the struct comments). DRPF_EINVAL on failure. */
+int drpf_validate(const drpf_params* p);
+
+/* Element counts of the fine (phase-field) and coarse arrays. */
+int drpf_field_elems(const drpf_params* p, size_t* fine, size_t* coarse);
+
+/* Bytes of device workspace that drpf_init_grid needs (spectral buffers, tables, the
+ * restricted coarse set, stage buffers). */
+int drpf_workspace_bytes(const drpf_params* p, size_t* bytes);
+
+/* Validates p, carves the caller's workspace (device memory, 256-byte aligned, at least
+ * drpf_workspace_bytes) and uploads the transform and eigenvalue tables on `stream`.
+ * *out receives a host handle. DRPF_EINVAL / DRPF_EWORKSPACE / DRPF_EHIP on failure. */
+int drpf_init_grid(const drpf_params* p, void* d_workspace, size_t bytes, void* stream,
+                   drpf_grid** out);
+
+/* Releases the host handle (the workspace stays the caller's). */
+int drpf_destroy(drpf_grid* g);
+
+/* Advances `s` by `nsteps` coupled steps (Sec. 3.2: CH, restriction, NS projection,
+ * polymer), rotating the state pointers after each step as described above. */
+int drpf_step(drpf_grid* g, drpf_state* s, int nsteps, void* stream);
+
+/* Coarse face velocities (u, v, w) -> fine face velocities (uf, vf, wf) by eq. dual1
+ * (Rudman's divergence-preserving interpolation). Fine arrays have the fine grid's
+ * element count; wf's layer 2nz-1 is the top wall (0). */
+int drpf_prolong(drpf_grid* g, const void* u, const void* v, const void* w, void* uf,
+                 void* vf, void* wf, void* stream);
+
+/* Fine cell-centred field -> coarse location (eq. dual2). `location` is a drpf_location;
+ * `coarse` must hold nx*ny*nz elements, or nx*ny*(nz+1) for FACE_Z, EDGE_XZ, EDGE_YZ. */
+int drpf_restrict(drpf_grid* g, const void* fine, void* coarse, int location, void* stream);
+
+/* Solves coeff * L x - shift * x = rhs on the fine or coarse grid with the 7-point
+ * second-order Laplacian L (periodic x, y; boundary kind `bc` in z) by FFT in x and y and
+ * a batched tridiagonal solve per Fourier mode across the walls (the "FFT solver" of
+ * Sec. 3.2.1-3.2.2). coeff > 0, shift >= 0; shift == 0 is allowed only with
+ * DRPF_BC_NEUMANN and returns the zero-mean solution. For DRPF_BC_FACE_DIRICHLET layer
+ * nz-1 of rhs is ignored and that layer of x is set to 0. rhs and x may alias. */
+int drpf_helmholtz_solve(drpf_grid* g, int which_grid, int bc, double coeff, double shift,
+                         const void* rhs, void* x, void* stream);
+
+/* Computes the first min(n, DRPF_OBS_COUNT) observables of level n of `s` in FP64 into
+ * the host array out. Synchronises `stream`. DRPF_ENONFINITE if the phase field holds a
+ * NaN or Inf (the values are still written). */
+int drpf_observables(drpf_grid* g, const drpf_state* s, double* out, int n, void* stream);
+
+/* Device pointer and element count of an internal coarse array left by the last step,
+ * for inspection in tests: 0 phi_c, 1 G_c, 2..4 G at x/y/z faces, 5..7 1/rho at x/y/z
+ * faces, 8 mu_c, 9 mu at xy edges, 10..11 mu at xz/yz edges (nz+1 layers),
+ * 12..14 momentum right-hand sides r_u, r_v, r_w. */
+int drpf_debug_field(drpf_grid* g, int id, void** ptr, size_t* count);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* drpf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DRPF_H */

@@ -1,0 +1,277 @@
+"""ctypes binding of include/drpf.h with torch-owned device memory.
+
+Names follow the C API: ``Grid`` wraps a drpf_grid handle plus its workspace tensor;
+``DeviceState`` owns the state tensors and the drpf_state struct that points at them.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(HERE, "libdrpf.so")
+
+DRPF_OK, DRPF_EINVAL, DRPF_EWORKSPACE, DRPF_EHIP, DRPF_ENONFINITE, DRPF_EUNSUPPORTED = range(6)
+LOCATIONS = {"center": 0, "face_x": 1, "face_y": 2, "face_z": 3, "edge_xy": 4, "edge_xz": 5,
+             "edge_yz": 6}
+BCS = {"neumann": 0, "dirichlet": 1, "face_dirichlet": 2}
+OBSERVABLES = ("mass", "wetted_radius", "centroid_height", "kinetic_energy", "max_div")
+
+
+class DrpfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"drpf error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
+        ("re", ctypes.c_double), ("ca", ctypes.c_double), ("cn", ctypes.c_double),
+        ("pe", ctypes.c_double), ("wi", ctypes.c_double), ("beta", ctypes.c_double),
+        ("theta_bottom_deg", ctypes.c_double), ("theta_top_deg", ctypes.c_double),
+        ("rho_ratio", ctypes.c_double), ("mu_ratio", ctypes.c_double),
+        ("dt", ctypes.c_double), ("s_factor", ctypes.c_double),
+        ("a_ext", ctypes.c_double * 3),
+        ("viscoelastic", ctypes.c_int), ("precision", ctypes.c_int),
+    ]
+
+
+class State(ctypes.Structure):
+    _fields_ = [
+        ("phi", ctypes.c_void_p * 3),
+        ("u", ctypes.c_void_p * 2), ("v", ctypes.c_void_p * 2), ("w", ctypes.c_void_p * 2),
+        ("p", ctypes.c_void_p * 2),
+        ("tau", (ctypes.c_void_p * 6) * 2),
+        ("step", ctypes.c_longlong),
+    ]
+
+
+_LIB = None
+
+
+def lib():
+    """Loads libdrpf.so once. Raises if it has not been built: there is no fallback."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(lib_path):
+            raise RuntimeError(f"{lib_path} not found: build it with "
+                               "`python -m paper_2111_04577_amd.build_lib`")
+        L = ctypes.CDLL(lib_path)
+        vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+        P = ctypes.POINTER
+        sig = {
+            "drpf_params_default": [P(Params)],
+            "drpf_validate": [P(Params)],
+            "drpf_field_elems": [P(Params), P(sz), P(sz)],
+            "drpf_workspace_bytes": [P(Params), P(sz)],
+            "drpf_init_grid": [P(Params), vp, sz, vp, P(vp)],
+            "drpf_destroy": [vp],
+            "drpf_step": [vp, P(State), i, vp],
+            "drpf_prolong": [vp, vp, vp, vp, vp, vp, vp, vp],
+            "drpf_restrict": [vp, vp, vp, i, vp],
+            "drpf_helmholtz_solve": [vp, i, i, d, d, vp, vp, vp],
+            "drpf_observables": [vp, P(State), P(d), i, vp],
+            "drpf_debug_field": [vp, i, P(vp), P(sz)],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.drpf_last_error.argtypes = []
+        L.drpf_last_error.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def _check(rc):
+    if rc != DRPF_OK:
+        raise DrpfError(rc, lib().drpf_last_error().decode())
+
+
+def make_params(cfg, precision=64) -> Params:
+    """Params from any object with the drpf_params field names as attributes."""
+    p = Params()
+    lib().drpf_params_default(ctypes.byref(p))
+    for name, _ in Params._fields_:
+        if name in ("precision",):
+            continue
+        if hasattr(cfg, name):
+            val = getattr(cfg, name)
+            if name == "a_ext":
+                p.a_ext[:] = [float(x) for x in val]
+            else:
+                setattr(p, name, val)
+    p.precision = int(precision)
+    return p
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class DeviceState:
+    """State tensors on the device plus the drpf_state struct pointing at them."""
+
+    def __init__(self, grid: "Grid", host: dict):
+        import torch
+        self.grid = grid
+        dt = grid.torch_dtype
+        dev = grid.device
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev).contiguous()
+        fs, cs = grid.fine_shape, grid.coarse_shape
+        self.tensors = []
+
+        def keep(x):
+            self.tensors.append(x)
+            return x
+
+        self.phi = [keep(t(host["phi"][0])), keep(t(host["phi"][1])), keep(torch.zeros(fs, dtype=dt, device=dev))]
+        self.u = [keep(t(a)) for a in host["u"]]
+        self.v = [keep(t(a)) for a in host["v"]]
+        self.w = [keep(t(a)) for a in host["w"]]
+        self.p = [keep(t(a)) for a in host["p"]]
+        if grid.params.viscoelastic:
+            self.tau = [[keep(t(a)) for a in host["tau"][lvl]] for lvl in range(2)]
+        else:
+            self.tau = None
+        self.c = State()
+        self.c.step = int(host.get("step", 0))
+        self._push()
+
+    def _push(self):
+        c = self.c
+        for a in range(3):
+            c.phi[a] = self.phi[a].data_ptr()
+        for name in ("u", "v", "w", "p"):
+            arr = getattr(c, name)
+            for a in range(2):
+                arr[a] = getattr(self, name)[a].data_ptr()
+        if self.tau is not None:
+            for lvl in range(2):
+                for m in range(6):
+                    c.tau[lvl][m] = self.tau[lvl][m].data_ptr()
+
+    def _pull(self):
+        """Re-associate tensors with the pointers the library rotated."""
+        by_ptr = {x.data_ptr(): x for x in self.tensors}
+        c = self.c
+        self.phi = [by_ptr[c.phi[a]] for a in range(3)]
+        for name in ("u", "v", "w", "p"):
+            arr = getattr(c, name)
+            setattr(self, name, [by_ptr[arr[a]] for a in range(2)])
+        if self.tau is not None:
+            self.tau = [[by_ptr[c.tau[lvl][m]] for m in range(6)] for lvl in range(2)]
+
+    @property
+    def step(self) -> int:
+        return int(self.c.step)
+
+    def to_host(self) -> dict:
+        """Copy to FP64 numpy arrays: {phi, u, v, w, p: [level n, level n-1], tau, step}."""
+        h = lambda x: x.detach().double().cpu().numpy()
+        out = {"phi": [h(self.phi[0]), h(self.phi[1])],
+               "u": [h(a) for a in self.u], "v": [h(a) for a in self.v],
+               "w": [h(a) for a in self.w], "p": [h(a) for a in self.p], "step": self.step}
+        if self.tau is not None:
+            out["tau"] = [[h(a) for a in self.tau[lvl]] for lvl in range(2)]
+        else:
+            z = np.zeros(self.grid.coarse_shape)
+            out["tau"] = [[z.copy() for _ in range(6)] for _ in range(2)]
+        return out
+
+
+class Grid:
+    """One problem set-up on one device: the drpf_grid handle and its workspace tensor."""
+
+    def __init__(self, cfg, precision=64, device="cuda:0", stream=None):
+        import torch
+        self.params = make_params(cfg, precision)
+        L = lib()
+        _check(L.drpf_validate(ctypes.byref(self.params)))
+        nb = ctypes.c_size_t()
+        _check(L.drpf_workspace_bytes(ctypes.byref(self.params), ctypes.byref(nb)))
+        self.device = torch.device(device)
+        self.torch_dtype = torch.float64 if precision == 64 else torch.float32
+        # 256-byte alignment: torch's device allocator returns 512-byte aligned blocks
+        self.workspace = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self._ws_ptr = base + off
+        self.handle = ctypes.c_void_p()
+        _check(L.drpf_init_grid(ctypes.byref(self.params), ctypes.c_void_p(self._ws_ptr),
+                                ctypes.c_size_t(int(nb.value)), _stream_ptr(stream),
+                                ctypes.byref(self.handle)))
+        p = self.params
+        ry = 1 if p.ny == 1 else 2
+        self.fine_shape = (2 * p.nz, ry * p.ny, 2 * p.nx)
+        self.coarse_shape = (p.nz, p.ny, p.nx)
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and self.handle.value:
+                lib().drpf_destroy(self.handle)
+                self.handle = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    def state(self, host: dict) -> DeviceState:
+        return DeviceState(self, host)
+
+    def step(self, st: DeviceState, nsteps: int = 1, stream=None):
+        _check(lib().drpf_step(self.handle, ctypes.byref(st.c), int(nsteps), _stream_ptr(stream)))
+        st._pull()
+        return st
+
+    def observables(self, st: DeviceState, stream=None) -> dict:
+        out = (ctypes.c_double * 5)()
+        rc = lib().drpf_observables(self.handle, ctypes.byref(st.c), out, 5, _stream_ptr(stream))
+        if rc not in (DRPF_OK, DRPF_ENONFINITE):
+            _check(rc)
+        d = dict(zip(OBSERVABLES, list(out)))
+        d["finite"] = rc == DRPF_OK
+        return d
+
+    def helmholtz_solve(self, rhs, which="fine", bc="neumann", coeff=1.0, shift=0.0, out=None,
+                        stream=None):
+        import torch
+        x = torch.empty_like(rhs) if out is None else out
+        _check(lib().drpf_helmholtz_solve(self.handle, 0 if which == "fine" else 1, BCS[bc],
+                                          float(coeff), float(shift), ctypes.c_void_p(rhs.data_ptr()),
+                                          ctypes.c_void_p(x.data_ptr()), _stream_ptr(stream)))
+        return x
+
+    def prolong(self, u, v, w, stream=None):
+        import torch
+        uf = torch.empty(self.fine_shape, dtype=self.torch_dtype, device=self.device)
+        vf = torch.empty_like(uf)
+        wf = torch.empty_like(uf)
+        _check(lib().drpf_prolong(self.handle, *(ctypes.c_void_p(a.data_ptr()) for a in (u, v, w, uf, vf, wf)),
+                                  _stream_ptr(stream)))
+        return uf, vf, wf
+
+    def restrict(self, fine, location="center", stream=None):
+        import torch
+        loc = LOCATIONS[location]
+        nz = self.coarse_shape[0] + (1 if loc in (3, 5, 6) else 0)
+        out = torch.empty((nz,) + self.coarse_shape[1:], dtype=self.torch_dtype, device=self.device)
+        _check(lib().drpf_restrict(self.handle, ctypes.c_void_p(fine.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr()), loc, _stream_ptr(stream)))
+        return out
+
+    def debug_field(self, idx: int):
+        """Copy of an internal coarse array (see drpf_debug_field) as a numpy array."""
+        import torch
+        ptr = ctypes.c_void_p()
+        n = ctypes.c_size_t()
+        _check(lib().drpf_debug_field(self.handle, int(idx), ctypes.byref(ptr), ctypes.byref(n)))
+        esz = 8 if self.params.precision == 64 else 4
+        b0 = ptr.value - self.workspace.data_ptr()
+        raw = self.workspace[b0:b0 + int(n.value) * esz].clone().view(self.torch_dtype)
+        nz = int(n.value) // (self.coarse_shape[1] * self.coarse_shape[2])
+        return raw.reshape((nz,) + self.coarse_shape[1:]).double().cpu().numpy()

@@ -1,0 +1,577 @@
+// C-ABI of the drpf library: parameter validation, scheme constants, workspace layout,
+// host-built transform tables, and the per-step launch sequence (Sec. 3.2 of the paper:
+// Cahn-Hilliard on the fine grid, restriction, Navier-Stokes projection, polymer stress).
+#include <math.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/drpf.h"
+#include "kernels.hpp"
+
+using namespace drpf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+int hip_fail(hipError_t e, const char* where) {
+  return fail(DRPF_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(expr, where)                     \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+Dims make_dims(int nx, int ny, int nz, double lx, double ly, double lz) {
+  Dims d;
+  d.nx = nx;
+  d.ny = ny;
+  d.nz = nz;
+  d.logx = ilog2(nx);
+  d.logy = ilog2(ny);
+  d.pitch = nx / 2 + 1;
+  d.hx = lx / nx;
+  d.hy = ly / ny;
+  d.hz = lz / nz;
+  return d;
+}
+
+// Scheme constants (own derivation of the paper's formulas; see the header of this file).
+StepConsts make_consts(const drpf_params& p, bool first) {
+  StepConsts c;
+  memset(&c, 0, sizeof(c));
+  c.first = first ? 1 : 0;
+  c.gamma0 = first ? 1.0 : 1.5;
+  c.dt = p.dt;
+  c.cn = p.cn;
+  c.cn2 = p.cn * p.cn;
+  c.pe = p.pe;
+  // stabilisation: s_factor times the lower bound of eq. NS30 with M lambda = Cn^2 / Pe
+  c.S = p.s_factor * p.cn * sqrt(4.0 * c.gamma0 * p.pe / p.dt);
+  // eq. NS29: its discriminant equals 1 - 1/s_factor^2 for this S
+  const double disc = 1.0 - 1.0 / (p.s_factor * p.s_factor);
+  c.alpha = -(c.S / (2.0 * c.cn2)) * (1.0 + sqrt(disc));
+  c.c_psi = c.alpha + c.S / c.cn2;
+  const double d2r = M_PI / 180.0;
+  c.cos_bot = cos(p.theta_bottom_deg * d2r);
+  c.cos_top = cos(p.theta_top_deg * d2r);
+  c.rho1 = 1.0;
+  c.rho2 = 1.0 / p.rho_ratio;
+  c.mu1 = p.viscoelastic ? p.beta : 1.0;
+  c.mu2 = 1.0 / p.mu_ratio;
+  c.rho0 = c.rho1 < c.rho2 ? c.rho1 : c.rho2;
+  const double mumax = c.mu1 > c.mu2 ? c.mu1 : c.mu2;
+  c.nu_m = mumax / (p.re * c.rho0);
+  c.re = p.re;
+  c.k_sigma = 3.0 / (2.0 * sqrt(2.0) * p.re * p.ca * p.cn);
+  c.c_j = 0.5 * (c.rho1 - c.rho2) / p.pe;
+  c.wi = p.wi;
+  c.beta = p.beta;
+  c.ax = p.a_ext[0];
+  c.ay = p.a_ext[1];
+  c.az = p.a_ext[2];
+  return c;
+}
+
+struct Carver {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  }
+};
+
+struct TabOff {
+  size_t tw_xm, tw_xn, tw_y, lam_x, lam_y, ph_x, ph_y;
+};
+
+struct Offsets {
+  TabOff tf, tc;
+  size_t rf, sf, piv, rc, sc, rset[12], tau1[6], part, obs, total;
+};
+
+Offsets layout(const drpf_params& p, const Dims& F, const Dims& C) {
+  const size_t es = p.precision == 32 ? 4 : 8;
+  Carver cv;
+  Offsets o;
+  auto tabs = [&](const Dims& d, TabOff& t) {
+    t.tw_xm = cv.take((size_t)(d.nx / 2) * 2 * es);
+    t.tw_xn = cv.take((size_t)(d.nx / 2 + 1) * 2 * es);
+    t.tw_y = cv.take((size_t)d.ny * 2 * es);
+    t.lam_x = cv.take((size_t)d.pitch * 8);
+    t.lam_y = cv.take((size_t)d.ny * 8);
+    t.ph_x = cv.take((size_t)d.pitch * 16);
+    t.ph_y = cv.take((size_t)d.ny * 16);
+  };
+  tabs(F, o.tf);
+  tabs(C, o.tc);
+  o.rf = cv.take(F.cells() * es);
+  o.sf = cv.take(F.spec() * 2 * es);
+  const size_t pf = (size_t)F.lines() * F.nz, pc = (size_t)3 * C.lines() * C.nz;
+  o.piv = cv.take((pf > pc ? pf : pc) * 8);
+  o.rc = cv.take(3 * C.cells() * es);
+  o.sc = cv.take(4 * C.spec() * 2 * es);
+  const size_t nc = C.cells(), ne = (size_t)C.nx * C.ny * (C.nz + 1);
+  for (int a = 0; a < 12; ++a) o.rset[a] = cv.take((a >= 10 ? ne : nc) * es);
+  for (int m = 0; m < 6; ++m) o.tau1[m] = p.viscoelastic ? cv.take(nc * es) : 0;
+  o.part = cv.take(reduce_partials() * 8);
+  o.obs = cv.take(8 * 8);
+  o.total = cv.off;
+  return o;
+}
+
+}  // namespace
+
+struct drpf_grid {
+  drpf_params p;
+  Dims F, C;
+  StepConsts k1, k2;
+  char* ws;
+  Offsets o;
+};
+
+namespace {
+
+template <typename T>
+Tables<T> tables(drpf_grid* g, const TabOff& t) {
+  Tables<T> tb;
+  tb.tw_xm = reinterpret_cast<const cx<T>*>(g->ws + t.tw_xm);
+  tb.tw_xn = reinterpret_cast<const cx<T>*>(g->ws + t.tw_xn);
+  tb.tw_y = reinterpret_cast<const cx<T>*>(g->ws + t.tw_y);
+  tb.lam_x = reinterpret_cast<const double*>(g->ws + t.lam_x);
+  tb.lam_y = reinterpret_cast<const double*>(g->ws + t.lam_y);
+  tb.ph_x = reinterpret_cast<const double*>(g->ws + t.ph_x);
+  tb.ph_y = reinterpret_cast<const double*>(g->ws + t.ph_y);
+  return tb;
+}
+
+template <typename T>
+Restricted<T> rset(drpf_grid* g) {
+  T* a[12];
+  for (int m = 0; m < 12; ++m) a[m] = reinterpret_cast<T*>(g->ws + g->o.rset[m]);
+  Restricted<T> r;
+  r.phi_c = a[0];
+  r.G_c = a[1];
+  r.G_x = a[2];
+  r.G_y = a[3];
+  r.G_z = a[4];
+  r.ri_x = a[5];
+  r.ri_y = a[6];
+  r.ri_z = a[7];
+  r.mu_c = a[8];
+  r.mu_xy = a[9];
+  r.mu_xz = a[10];
+  r.mu_yz = a[11];
+  return r;
+}
+
+// Host tables in long double, rounded to the storage type.
+template <typename T>
+int upload_tables(drpf_grid* g, const Dims& d, const TabOff& t, hipStream_t st,
+                  std::vector<std::vector<unsigned char>>& keep) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  auto put = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    keep.emplace_back((const unsigned char*)src, (const unsigned char*)src + bytes);
+    return hipMemcpyAsync(g->ws + off, keep.back().data(), bytes, hipMemcpyHostToDevice, st);
+  };
+  std::vector<T> tw;
+  const int M = d.nx / 2;
+  tw.resize(2 * M);
+  for (int i = 0; i < M; ++i) {
+    tw[2 * i] = (T)cosl(2 * pi * i / M);
+    tw[2 * i + 1] = (T)-sinl(2 * pi * i / M);
+  }
+  HIPCHK(put(t.tw_xm, tw.data(), tw.size() * sizeof(T)), "upload twiddles");
+  tw.assign(2 * (M + 1), 0);
+  for (int k = 0; k <= M; ++k) {
+    tw[2 * k] = (T)cosl(2 * pi * k / d.nx);
+    tw[2 * k + 1] = (T)-sinl(2 * pi * k / d.nx);
+  }
+  HIPCHK(put(t.tw_xn, tw.data(), tw.size() * sizeof(T)), "upload twiddles");
+  tw.assign(2 * d.ny, 0);
+  for (int i = 0; i < d.ny; ++i) {
+    tw[2 * i] = (T)cosl(2 * pi * i / d.ny);
+    tw[2 * i + 1] = (T)-sinl(2 * pi * i / d.ny);
+  }
+  HIPCHK(put(t.tw_y, tw.data(), tw.size() * sizeof(T)), "upload twiddles");
+  std::vector<double> lx(d.pitch), ly(d.ny), px(2 * d.pitch), py(2 * d.ny);
+  for (int k = 0; k < d.pitch; ++k) {
+    const double s = sin(M_PI * k / d.nx);
+    lx[k] = -4.0 / (d.hx * d.hx) * s * s;
+    px[2 * k] = (double)cosl(2 * pi * k / d.nx);
+    px[2 * k + 1] = (double)sinl(2 * pi * k / d.nx);
+  }
+  for (int k = 0; k < d.ny; ++k) {
+    const double s = sin(M_PI * k / d.ny);
+    ly[k] = -4.0 / (d.hy * d.hy) * s * s;
+    py[2 * k] = (double)cosl(2 * pi * k / d.ny);
+    py[2 * k + 1] = (double)sinl(2 * pi * k / d.ny);
+  }
+  HIPCHK(put(t.lam_x, lx.data(), lx.size() * 8), "upload eigenvalues");
+  HIPCHK(put(t.lam_y, ly.data(), ly.size() * 8), "upload eigenvalues");
+  HIPCHK(put(t.ph_x, px.data(), px.size() * 8), "upload phases");
+  HIPCHK(put(t.ph_y, py.data(), py.size() * 8), "upload phases");
+  return DRPF_OK;
+}
+
+template <typename T>
+int step_impl(drpf_grid* g, drpf_state* s, int nsteps, hipStream_t st) {
+  const Dims& F = g->F;
+  const Dims& C = g->C;
+  const Tables<T> tf = tables<T>(g, g->o.tf), tc = tables<T>(g, g->o.tc);
+  T* Rf = reinterpret_cast<T*>(g->ws + g->o.rf);
+  cx<T>* Sf = reinterpret_cast<cx<T>*>(g->ws + g->o.sf);
+  double* piv = reinterpret_cast<double*>(g->ws + g->o.piv);
+  T* Rc = reinterpret_cast<T*>(g->ws + g->o.rc);
+  cx<T>* Sc = reinterpret_cast<cx<T>*>(g->ws + g->o.sc);
+  const Restricted<T> R = rset<T>(g);
+  const size_t nc = C.cells();
+  const bool ve = g->p.viscoelastic != 0;
+  for (int n = 0; n < nsteps; ++n) {
+    const StepConsts& K = s->step == 0 ? g->k1 : g->k2;
+    T* phin = (T*)s->phi[0];
+    T* phinm1 = (T*)s->phi[1];
+    T* phinew = (T*)s->phi[2];
+    // ---- Cahn-Hilliard on the fine grid
+    ChIn<T> ci{phin, phinm1, (const T*)s->u[0], (const T*)s->u[1], (const T*)s->v[0],
+               (const T*)s->v[1], (const T*)s->w[0], (const T*)s->w[1]};
+    HIPCHK(launch_ch_rhs<T>(F, C, K, ci, Rf, st), "ch_rhs");
+    const T* inf[4] = {Rf, nullptr, nullptr, nullptr};
+    HIPCHK(launch_fft_x_fwd<T>(F, tf, inf, 1, Sf, st), "fft_x fine");
+    HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, false, st), "fft_y fine");
+    HIPCHK(launch_zpass_ch<T>(F, tf, Sf, piv, K.c_psi, K.alpha, 1.0 / ((double)F.nx * F.ny), st),
+           "zpass_ch");
+    HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, true, st), "ifft_y fine");
+    RealSet<T> of;
+    memset(&of, 0, sizeof(of));
+    of.p[0] = phinew;
+    of.nfields = 1;
+    HIPCHK(launch_fft_x_inv<T>(F, tf, Sf, of, st), "ifft_x fine");
+    // ---- restriction, chemical potential, properties
+    HIPCHK(launch_restrict_g<T>(F, C, K, phinew, phin, phinm1, R, st), "restrict_g");
+    // ---- Navier-Stokes on the coarse grid
+    NsIn<T> ni;
+    ni.un = (const T*)s->u[0];
+    ni.unm1 = (const T*)s->u[1];
+    ni.vn = (const T*)s->v[0];
+    ni.vnm1 = (const T*)s->v[1];
+    ni.wn = (const T*)s->w[0];
+    ni.wnm1 = (const T*)s->w[1];
+    ni.pn = (const T*)s->p[0];
+    ni.pnm1 = (const T*)s->p[1];
+    for (int m = 0; m < 6; ++m) {
+      ni.taun[m] = ve ? (const T*)s->tau[0][m] : nullptr;
+      ni.taunm1[m] = ve ? (const T*)s->tau[1][m] : nullptr;
+    }
+    ni.viscoelastic = ve ? 1 : 0;
+    HIPCHK(launch_momentum_rhs<T>(C, K, ni, R, Rc, Rc + nc, Rc + 2 * nc, st), "momentum_rhs");
+    const T* inc[4] = {Rc, Rc + nc, Rc + 2 * nc, nullptr};
+    HIPCHK(launch_fft_x_fwd<T>(C, tc, inc, 3, Sc, st), "fft_x coarse");
+    HIPCHK(launch_fft_y<T>(C, tc, Sc, 3, false, st), "fft_y coarse");
+    HIPCHK(launch_zpass_ns<T>(C, tc, Sc, piv, K, 1.0 / ((double)C.nx * C.ny), st), "zpass_ns");
+    HIPCHK(launch_fft_y<T>(C, tc, Sc, 4, true, st), "ifft_y coarse");
+    RealSet<T> oc;
+    memset(&oc, 0, sizeof(oc));
+    oc.p[0] = (T*)s->u[1];
+    oc.p[1] = (T*)s->v[1];
+    oc.p[2] = (T*)s->w[1];
+    oc.p[3] = (T*)s->p[1];
+    oc.add[3] = (const T*)s->p[0];
+    oc.nfields = 4;
+    HIPCHK(launch_fft_x_inv<T>(C, tc, Sc, oc, st), "ifft_x coarse");
+    // ---- polymer stress, RK2-TVD with u^{n+1}
+    if (ve) {
+      const T* tn[6];
+      T* t1[6];
+      T* tout[6];
+      for (int m = 0; m < 6; ++m) {
+        tn[m] = (const T*)s->tau[0][m];
+        t1[m] = reinterpret_cast<T*>(g->ws + g->o.tau1[m]);
+        tout[m] = (T*)s->tau[1][m];
+      }
+      const T* t1c[6];
+      for (int m = 0; m < 6; ++m) t1c[m] = t1[m];
+      HIPCHK(launch_polymer_stage<T>(C, K, (const T*)s->u[1], (const T*)s->v[1], (const T*)s->w[1],
+                                     tn, tn, t1, 0.0, 1.0, st),
+             "polymer stage 1");
+      HIPCHK(launch_polymer_stage<T>(C, K, (const T*)s->u[1], (const T*)s->v[1], (const T*)s->w[1],
+                                     tn, t1c, tout, 0.5, 0.5, st),
+             "polymer stage 2");
+    }
+    // ---- rotate time levels (pointer swaps only)
+    void* ph0 = s->phi[0];
+    void* ph1 = s->phi[1];
+    s->phi[0] = s->phi[2];
+    s->phi[1] = ph0;
+    s->phi[2] = ph1;
+    void* tmp;
+    tmp = s->u[0]; s->u[0] = s->u[1]; s->u[1] = tmp;
+    tmp = s->v[0]; s->v[0] = s->v[1]; s->v[1] = tmp;
+    tmp = s->w[0]; s->w[0] = s->w[1]; s->w[1] = tmp;
+    tmp = s->p[0]; s->p[0] = s->p[1]; s->p[1] = tmp;
+    if (ve)
+      for (int m = 0; m < 6; ++m) {
+        tmp = s->tau[0][m];
+        s->tau[0][m] = s->tau[1][m];
+        s->tau[1][m] = tmp;
+      }
+    s->step += 1;
+  }
+  return DRPF_OK;
+}
+
+template <typename T>
+int helmholtz_impl(drpf_grid* g, int which, int bc, double coeff, double shift, const void* rhs,
+                   void* x, hipStream_t st) {
+  const Dims& d = which == DRPF_GRID_FINE ? g->F : g->C;
+  const Tables<T> tb = tables<T>(g, which == DRPF_GRID_FINE ? g->o.tf : g->o.tc);
+  cx<T>* S = reinterpret_cast<cx<T>*>(g->ws + (which == DRPF_GRID_FINE ? g->o.sf : g->o.sc));
+  double* piv = reinterpret_cast<double*>(g->ws + g->o.piv);
+  const T* in[4] = {(const T*)rhs, nullptr, nullptr, nullptr};
+  HIPCHK(launch_fft_x_fwd<T>(d, tb, in, 1, S, st), "fft_x");
+  HIPCHK(launch_fft_y<T>(d, tb, S, 1, false, st), "fft_y");
+  HIPCHK(launch_zpass_helmholtz<T>(d, tb, S, piv, bc, coeff, shift, 1.0 / ((double)d.nx * d.ny), st),
+         "zpass");
+  HIPCHK(launch_fft_y<T>(d, tb, S, 1, true, st), "ifft_y");
+  RealSet<T> o;
+  memset(&o, 0, sizeof(o));
+  o.p[0] = (T*)x;
+  o.nfields = 1;
+  HIPCHK(launch_fft_x_inv<T>(d, tb, S, o, st), "ifft_x");
+  return DRPF_OK;
+}
+
+template <typename T>
+int observables_impl(drpf_grid* g, const drpf_state* s, double* out, int n, hipStream_t st) {
+  double* part = reinterpret_cast<double*>(g->ws + g->o.part);
+  double* obs = reinterpret_cast<double*>(g->ws + g->o.obs);
+  HIPCHK(launch_observables<T>(g->F, g->C, (const T*)s->phi[0], (const T*)s->u[0],
+                               (const T*)s->v[0], (const T*)s->w[0], part, obs, st),
+         "observables");
+  double host[8];
+  HIPCHK(hipMemcpyAsync(host, obs, 6 * sizeof(double), hipMemcpyDeviceToHost, st), "copy observables");
+  HIPCHK(hipStreamSynchronize(st), "synchronise");
+  const int m = n < DRPF_OBS_COUNT ? n : DRPF_OBS_COUNT;
+  for (int i = 0; i < m; ++i) out[i] = host[i];
+  if (host[5] != 0.0) return fail(DRPF_ENONFINITE, "phase field holds non-finite values");
+  return DRPF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* drpf_last_error(void) { return g_err.c_str(); }
+
+int drpf_params_default(drpf_params* p) {
+  if (!p) return fail(DRPF_EINVAL, "null params");
+  memset(p, 0, sizeof(*p));
+  p->nx = 64;
+  p->ny = 1;
+  p->nz = 32;
+  p->lx = 2.0;
+  p->ly = 2.0 / 64;
+  p->lz = 1.0;
+  p->re = 10.0;
+  p->ca = 0.1;
+  p->cn = 0.01;
+  p->pe = 1000.0;
+  p->wi = 1.0;
+  p->beta = 1.0;
+  p->theta_bottom_deg = 60.0;
+  p->theta_top_deg = 90.0;
+  p->rho_ratio = 1.0;
+  p->mu_ratio = 1.0;
+  p->dt = 1e-4;
+  p->s_factor = 1.0;
+  p->viscoelastic = 0;
+  p->precision = 64;
+  return DRPF_OK;
+}
+
+int drpf_validate(const drpf_params* p) {
+  if (!p) return fail(DRPF_EINVAL, "null params");
+  if (!pow2(p->nx) || p->nx < 4 || p->nx > 1024) return fail(DRPF_EINVAL, "nx must be a power of two in [4, 1024]");
+  if (!pow2(p->nz) || p->nz < 4 || p->nz > 4096) return fail(DRPF_EINVAL, "nz must be a power of two in [4, 4096]");
+  if (!(p->ny == 1 || (pow2(p->ny) && p->ny >= 4 && p->ny <= 1024)))
+    return fail(DRPF_EINVAL, "ny must be 1 or a power of two in [4, 1024]");
+  if (!(p->lx > 0 && p->ly > 0 && p->lz > 0)) return fail(DRPF_EINVAL, "box lengths must be > 0");
+  if (!(p->re > 0 && p->ca > 0 && p->cn > 0 && p->pe > 0 && p->dt > 0))
+    return fail(DRPF_EINVAL, "Re, Ca, Cn, Pe and dt must be > 0");
+  if (!(p->s_factor >= 1.0)) return fail(DRPF_EINVAL, "s_factor must be >= 1 (eq. NS30)");
+  if (!(p->theta_bottom_deg >= 0 && p->theta_bottom_deg <= 180 && p->theta_top_deg >= 0 &&
+        p->theta_top_deg <= 180))
+    return fail(DRPF_EINVAL, "contact angles must lie in [0, 180] degrees");
+  if (!(p->rho_ratio > 0 && p->mu_ratio > 0)) return fail(DRPF_EINVAL, "density and viscosity ratios must be > 0");
+  if (p->viscoelastic && !(p->wi > 0 && p->beta > 0 && p->beta <= 1))
+    return fail(DRPF_EINVAL, "viscoelastic drop needs Wi > 0 and beta in (0, 1]");
+  if (!(p->precision == 64 || p->precision == 32)) return fail(DRPF_EINVAL, "precision must be 64 or 32");
+  for (int a = 0; a < 3; ++a)
+    if (!isfinite(p->a_ext[a])) return fail(DRPF_EINVAL, "a_ext must be finite");
+  return DRPF_OK;
+}
+
+int drpf_field_elems(const drpf_params* p, size_t* fine, size_t* coarse) {
+  const int rc = drpf_validate(p);
+  if (rc) return rc;
+  if (!fine || !coarse) return fail(DRPF_EINVAL, "null output");
+  const size_t ry = p->ny == 1 ? 1 : 2;
+  *fine = (size_t)(2 * p->nx) * (ry * p->ny) * (2 * p->nz);
+  *coarse = (size_t)p->nx * p->ny * p->nz;
+  return DRPF_OK;
+}
+
+int drpf_workspace_bytes(const drpf_params* p, size_t* bytes) {
+  const int rc = drpf_validate(p);
+  if (rc) return rc;
+  if (!bytes) return fail(DRPF_EINVAL, "null output");
+  const int ry = p->ny == 1 ? 1 : 2;
+  const Dims F = make_dims(2 * p->nx, ry * p->ny, 2 * p->nz, p->lx, p->ly, p->lz);
+  const Dims C = make_dims(p->nx, p->ny, p->nz, p->lx, p->ly, p->lz);
+  *bytes = layout(*p, F, C).total;
+  return DRPF_OK;
+}
+
+int drpf_init_grid(const drpf_params* p, void* d_workspace, size_t bytes, void* stream,
+                   drpf_grid** out) {
+  int rc = drpf_validate(p);
+  if (rc) return rc;
+  if (!out) return fail(DRPF_EINVAL, "null output handle");
+  size_t need = 0;
+  drpf_workspace_bytes(p, &need);
+  if (!d_workspace) return fail(DRPF_EWORKSPACE, "null workspace");
+  if (((uintptr_t)d_workspace & 255) != 0) return fail(DRPF_EWORKSPACE, "workspace must be 256-byte aligned");
+  if (bytes < need)
+    return fail(DRPF_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  drpf_grid* g = new drpf_grid;
+  g->p = *p;
+  const int ry = p->ny == 1 ? 1 : 2;
+  g->F = make_dims(2 * p->nx, ry * p->ny, 2 * p->nz, p->lx, p->ly, p->lz);
+  g->C = make_dims(p->nx, p->ny, p->nz, p->lx, p->ly, p->lz);
+  g->k1 = make_consts(*p, true);
+  g->k2 = make_consts(*p, false);
+  g->ws = (char*)d_workspace;
+  g->o = layout(*p, g->F, g->C);
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<std::vector<unsigned char>> keep;
+  if (p->precision == 64) {
+    rc = upload_tables<double>(g, g->F, g->o.tf, st, keep);
+    if (!rc) rc = upload_tables<double>(g, g->C, g->o.tc, st, keep);
+  } else {
+    rc = upload_tables<float>(g, g->F, g->o.tf, st, keep);
+    if (!rc) rc = upload_tables<float>(g, g->C, g->o.tc, st, keep);
+  }
+  if (!rc) {
+    const hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = hip_fail(e, "init synchronise");
+  }
+  if (rc) {
+    delete g;
+    return rc;
+  }
+  *out = g;
+  return DRPF_OK;
+}
+
+int drpf_destroy(drpf_grid* g) {
+  delete g;
+  return DRPF_OK;
+}
+
+int drpf_step(drpf_grid* g, drpf_state* s, int nsteps, void* stream) {
+  if (!g || !s) return fail(DRPF_EINVAL, "null grid or state");
+  if (nsteps < 0) return fail(DRPF_EINVAL, "nsteps must be >= 0");
+  if (!s->phi[0] || !s->phi[1] || !s->phi[2] || !s->u[0] || !s->u[1] || !s->v[0] || !s->v[1] ||
+      !s->w[0] || !s->w[1] || !s->p[0] || !s->p[1])
+    return fail(DRPF_EINVAL, "null state pointer");
+  if (g->p.viscoelastic)
+    for (int l = 0; l < 2; ++l)
+      for (int m = 0; m < 6; ++m)
+        if (!s->tau[l][m]) return fail(DRPF_EINVAL, "null polymer stress pointer");
+  if (s->step < 0) return fail(DRPF_EINVAL, "negative step counter");
+  hipStream_t st = (hipStream_t)stream;
+  return g->p.precision == 64 ? step_impl<double>(g, s, nsteps, st) : step_impl<float>(g, s, nsteps, st);
+}
+
+int drpf_prolong(drpf_grid* g, const void* u, const void* v, const void* w, void* uf, void* vf,
+                 void* wf, void* stream) {
+  if (!g || !u || !v || !w || !uf || !vf || !wf) return fail(DRPF_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  if (g->p.precision == 64)
+    HIPCHK(launch_prolong<double>(g->F, g->C, (const double*)u, (const double*)v, (const double*)w,
+                                  (double*)uf, (double*)vf, (double*)wf, st),
+           "prolong");
+  else
+    HIPCHK(launch_prolong<float>(g->F, g->C, (const float*)u, (const float*)v, (const float*)w,
+                                 (float*)uf, (float*)vf, (float*)wf, st),
+           "prolong");
+  return DRPF_OK;
+}
+
+int drpf_restrict(drpf_grid* g, const void* fine, void* coarse, int location, void* stream) {
+  if (!g || !fine || !coarse) return fail(DRPF_EINVAL, "null argument");
+  if (location < DRPF_CENTER || location > DRPF_EDGE_YZ) return fail(DRPF_EINVAL, "bad location");
+  hipStream_t st = (hipStream_t)stream;
+  if (g->p.precision == 64)
+    HIPCHK(launch_restrict<double>(g->F, g->C, (const double*)fine, (double*)coarse, location, st),
+           "restrict");
+  else
+    HIPCHK(launch_restrict<float>(g->F, g->C, (const float*)fine, (float*)coarse, location, st),
+           "restrict");
+  return DRPF_OK;
+}
+
+int drpf_helmholtz_solve(drpf_grid* g, int which_grid, int bc, double coeff, double shift,
+                         const void* rhs, void* x, void* stream) {
+  if (!g || !rhs || !x) return fail(DRPF_EINVAL, "null argument");
+  if (which_grid != DRPF_GRID_FINE && which_grid != DRPF_GRID_COARSE) return fail(DRPF_EINVAL, "bad grid");
+  if (bc < DRPF_BC_NEUMANN || bc > DRPF_BC_FACE_DIRICHLET) return fail(DRPF_EINVAL, "bad boundary kind");
+  if (!(coeff > 0) || !(shift >= 0) || !isfinite(coeff) || !isfinite(shift))
+    return fail(DRPF_EINVAL, "need coeff > 0 and shift >= 0");
+  if (shift == 0 && bc != DRPF_BC_NEUMANN) return fail(DRPF_EINVAL, "shift 0 only with Neumann walls");
+  hipStream_t st = (hipStream_t)stream;
+  return g->p.precision == 64 ? helmholtz_impl<double>(g, which_grid, bc, coeff, shift, rhs, x, st)
+                              : helmholtz_impl<float>(g, which_grid, bc, coeff, shift, rhs, x, st);
+}
+
+int drpf_observables(drpf_grid* g, const drpf_state* s, double* out, int n, void* stream) {
+  if (!g || !s || !out || n < 0) return fail(DRPF_EINVAL, "null argument");
+  if (!s->phi[0] || !s->u[0] || !s->v[0] || !s->w[0]) return fail(DRPF_EINVAL, "null state pointer");
+  hipStream_t st = (hipStream_t)stream;
+  return g->p.precision == 64 ? observables_impl<double>(g, s, out, n, st)
+                              : observables_impl<float>(g, s, out, n, st);
+}
+
+int drpf_debug_field(drpf_grid* g, int id, void** ptr, size_t* count) {
+  if (!g || !ptr || !count) return fail(DRPF_EINVAL, "null argument");
+  const size_t nc = g->C.cells(), ne = (size_t)g->C.nx * g->C.ny * (g->C.nz + 1);
+  const size_t es = g->p.precision == 32 ? 4 : 8;
+  if (id >= 0 && id < 12) {
+    *ptr = g->ws + g->o.rset[id];
+    *count = id >= 10 ? ne : nc;
+    return DRPF_OK;
+  }
+  if (id >= 12 && id < 15) {
+    *ptr = g->ws + g->o.rc + (size_t)(id - 12) * nc * es;
+    *count = nc;
+    return DRPF_OK;
+  }
+  return fail(DRPF_EINVAL, "unknown debug field id");
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Shared device/host definitions of the drpf HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace drpf {
+
+// ----------------------------------------------------------------------------------------
+// complex arithmetic (interleaved re/im, the layout of every spectral buffer)
+// ----------------------------------------------------------------------------------------
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T re, im;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> mk(T r, T i) {
+  cx<T> z;
+  z.re = r;
+  z.im = i;
+  return z;
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
+  return mk<T>(a.re + b.re, a.im + b.im);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) {
+  return mk<T>(a.re - b.re, a.im - b.im);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return mk<T>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) {
+  return mk<T>(s * a.re, s * a.im);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> conj(cx<T> a) {
+  return mk<T>(a.re, -a.im);
+}
+// multiply by +i or -i
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> mul_i(cx<T> a) {
+  return mk<T>(-a.im, a.re);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> mul_mi(cx<T> a) {
+  return mk<T>(a.im, -a.re);
+}
+template <typename A, typename T>
+__host__ __device__ __forceinline__ cx<A> widen(cx<T> a) {
+  return mk<A>((A)a.re, (A)a.im);
+}
+
+// ----------------------------------------------------------------------------------------
+// geometry of one grid (fine or coarse)
+// ----------------------------------------------------------------------------------------
+struct Dims {
+  int nx, ny, nz;       // cells
+  int logx, logy;       // log2(nx), log2(ny)
+  int pitch;            // nx/2 + 1: complex entries per spectral x-row
+  double hx, hy, hz;    // spacings
+  __host__ __device__ size_t cells() const { return (size_t)nx * ny * nz; }
+  __host__ __device__ size_t spec() const { return (size_t)pitch * ny * nz; }
+  __host__ __device__ int lines() const { return pitch * ny; }
+};
+
+// Device tables of one grid: FFT twiddles and spectral eigenvalues.
+template <typename T>
+struct Tables {
+  const cx<T>* tw_xm;    // e^{-2 pi i t / (nx/2)}, t < nx/2 (complex FFT inside r2c/c2r)
+  const cx<T>* tw_xn;    // e^{-2 pi i k / nx}, k <= nx/2 (r2c post / c2r pre twiddle)
+  const cx<T>* tw_y;     // e^{-2 pi i t / ny}, t < ny
+  const double* lam_x;   // -(4/hx^2) sin^2(pi kx / nx), kx <= nx/2
+  const double* lam_y;   // -(4/hy^2) sin^2(pi ky / ny), ky < ny
+  const double* ph_x;    // (cos, sin)(2 pi kx / nx), kx <= nx/2, interleaved
+  const double* ph_y;    // (cos, sin)(2 pi ky / ny), ky < ny, interleaved
+};
+
+// Scheme constants of one step kind (first step: gamma0 = 1; later: 3/2).
+struct StepConsts {
+  int first;
+  double gamma0, dt;
+  double cn, cn2, pe;
+  double S, alpha, c_psi;       // Dong splitting (eqs. NS29-NS30)
+  double cos_bot, cos_top;      // static contact angles (eq. NS16)
+  double rho1, rho2, mu1, mu2;  // drop / ambient density and solvent viscosity
+  double rho0, nu_m;            // projection constants (text after eq. NS39)
+  double re, k_sigma, c_j;      // 1/Re scaling, capillary coefficient, J = -c_j grad G
+  double wi, beta;              // Oldroyd-B
+  double ax, ay, az;            // body acceleration
+};
+
+__host__ __device__ __forceinline__ int wrap(int i, int n) { return i & (n - 1); }
+
+}  // namespace drpf

@@ -1,0 +1,262 @@
+// Batched FFT passes of the constant-coefficient solver (the "FFT solver" used for the
+// Helmholtz and Poisson equations, Sec. 3.2.1-3.2.2 of the paper), written for gfx950:
+// every line is staged in LDS, transformed by a Stockham radix-4 sequence (one radix-2
+// stage first when log2(length) is odd) with one butterfly set per thread, and written back
+// with coalesced row accesses.
+//
+//   x pass: real rows of length nx -> nx/2+1 complex (r2c through a length nx/2 complex
+//           FFT of the even/odd-packed row), and the inverse (c2r). Unnormalised.
+//   y pass: complex columns of length ny, in place, on a tile of consecutive kx columns so
+//           that each y-row load is contiguous. Unnormalised.
+#include "kernels.hpp"
+
+namespace drpf {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// In-LDS complex FFT of `nlines` lines of length M (power of two, M >= 2). Element n of
+// line b lives at buf[b * bs + n * es]. Thread t < nlines * max(M/4, 1) owns butterfly set
+// q = t % (M/4) of line t / (M/4). Every thread of the block must call this (barriers).
+// Twiddle table tw[t] = exp(-2 pi i t / M); the inverse uses its conjugate.
+template <typename T, bool INV>
+__device__ void lds_fft(cx<T>* buf, int M, int logM, int nlines, int bs, int es,
+                        const cx<T>* __restrict__ tw) {
+  const int quarter = M >= 4 ? (M >> 2) : 1;
+  const int t = threadIdx.x;
+  const bool active = t < nlines * quarter;
+  const int b = active ? t / quarter : 0;
+  const int q = active ? t - b * quarter : 0;
+  cx<T>* line = buf + b * bs;
+  int Ns = 1;
+  if (logM & 1) {
+    // radix-2 stage (Ns = 1, unit twiddles): butterflies j = q and q + M/4 of M/2
+    const int half = M >> 1;
+    cx<T> v[4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = q + h * quarter;
+      if (active && j < half) {
+        v[2 * h] = line[j * es];
+        v[2 * h + 1] = line[(j + half) * es];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = q + h * quarter;
+      if (active && j < half) {
+        line[(2 * j) * es] = v[2 * h] + v[2 * h + 1];
+        line[(2 * j + 1) * es] = v[2 * h] - v[2 * h + 1];
+      }
+    }
+    __syncthreads();
+    Ns = 2;
+  }
+  for (; Ns < M; Ns <<= 2) {
+    const int j = q;
+    const int k = j & (Ns - 1);
+    cx<T> v[4];
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = line[(j + r * quarter) * es];
+    }
+    __syncthreads();
+    if (active) {
+      const int step = M / (Ns * 4);
+#pragma unroll
+      for (int r = 1; r < 4; ++r) {
+        cx<T> w = tw[r * k * step];
+        if (INV) w = conj(w);
+        v[r] = v[r] * w;
+      }
+      const cx<T> a = v[0] + v[2], bb = v[0] - v[2], c = v[1] + v[3], d = v[1] - v[3];
+      const cx<T> jd = INV ? mul_i(d) : mul_mi(d);
+      const int base = (j - k) * 4 + k;
+      line[base * es] = a + c;
+      line[(base + Ns) * es] = bb + jd;
+      line[(base + 2 * Ns) * es] = a - c;
+      line[(base + 3 * Ns) * es] = bb - jd;
+    }
+    __syncthreads();
+  }
+}
+
+// ---- x pass, forward (r2c) -------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fft_x_fwd(const T* __restrict__ in0,
+                                                      const T* __restrict__ in1,
+                                                      const T* __restrict__ in2,
+                                                      cx<T>* __restrict__ out, int N, int logM,
+                                                      int lines_per_field, int total_lines,
+                                                      int lpb, const cx<T>* __restrict__ twM,
+                                                      const cx<T>* __restrict__ twN) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int M = N >> 1;
+  const int line0 = blockIdx.x * lpb;
+  const int nl = min(lpb, total_lines - line0);
+  // a block never straddles two fields: lpb divides lines_per_field
+  const int field = line0 / lines_per_field;
+  const T* in = field == 0 ? in0 : (field == 1 ? in1 : in2);
+  const T* src = in + (size_t)(line0 - field * lines_per_field) * N;
+  for (int e = threadIdx.x; e < nl * M; e += blockDim.x) buf[e] = mk<T>(src[2 * e], src[2 * e + 1]);
+  __syncthreads();
+  lds_fft<T, false>(buf, M, logM, nl, M, 1, twM);
+  cx<T>* dst = out + (size_t)line0 * (M + 1);
+  const T half = (T)0.5;
+  for (int e = threadIdx.x; e < nl * (M + 1); e += blockDim.x) {
+    const int b = e / (M + 1);
+    const int k = e - b * (M + 1);
+    const cx<T> zk = buf[b * M + (k == M ? 0 : k)];
+    const cx<T> zm = conj(buf[b * M + (k == 0 ? 0 : M - k)]);
+    const cx<T> E = half * (zk + zm);
+    const cx<T> O = half * mul_mi(zk - zm);
+    dst[e] = E + twN[k] * O;
+  }
+}
+
+// ---- x pass, inverse (c2r), up to four output fields with optional addend --------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fft_x_inv(const cx<T>* __restrict__ in, RealSet<T> out,
+                                                      int N, int logM, int lines_per_field,
+                                                      int total_lines, int lpb,
+                                                      const cx<T>* __restrict__ twM,
+                                                      const cx<T>* __restrict__ twN) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int M = N >> 1;
+  const int line0 = blockIdx.x * lpb;
+  const int nl = min(lpb, total_lines - line0);
+  const cx<T>* src = in + (size_t)line0 * (M + 1);
+  for (int e = threadIdx.x; e < nl * M; e += blockDim.x) {
+    const int b = e / M;
+    const int k = e - b * M;
+    const cx<T> xk = src[b * (M + 1) + k];
+    const cx<T> xm = conj(src[b * (M + 1) + (M - k)]);
+    const cx<T> E = xk + xm;
+    const cx<T> O = conj(twN[k]) * (xk - xm);
+    buf[e] = E + mul_i(O);
+  }
+  __syncthreads();
+  lds_fft<T, true>(buf, M, logM, nl, M, 1, twM);
+  const int field = line0 / lines_per_field;
+  T* dst = out.p[field] + (size_t)(line0 - field * lines_per_field) * N;
+  const T* add = out.add[field];
+  if (add != nullptr) {
+    add += (size_t)(line0 - field * lines_per_field) * N;
+    for (int e = threadIdx.x; e < nl * M; e += blockDim.x) {
+      dst[2 * e] = add[2 * e] + buf[e].re;
+      dst[2 * e + 1] = add[2 * e + 1] + buf[e].im;
+    }
+  } else {
+    for (int e = threadIdx.x; e < nl * M; e += blockDim.x) {
+      dst[2 * e] = buf[e].re;
+      dst[2 * e + 1] = buf[e].im;
+    }
+  }
+}
+
+// ---- y pass (c2c, in place) -------------------------------------------------------------
+template <typename T, bool INV>
+__global__ void k_fft_y(cx<T>* __restrict__ data, int Ny, int logNy, int P, int ntiles, int tkx,
+                        const cx<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tile = blockIdx.x % ntiles;
+  const int batch = blockIdx.x / ntiles;
+  const int kx0 = tile * tkx;
+  cx<T>* base = data + (size_t)batch * Ny * P;
+  for (int e = threadIdx.x; e < Ny * tkx; e += blockDim.x) {
+    const int y = e / tkx;
+    const int t = e - y * tkx;
+    const int kx = kx0 + t;
+    buf[e] = kx < P ? base[(size_t)y * P + kx] : mk<T>(0, 0);
+  }
+  __syncthreads();
+  lds_fft<T, INV>(buf, Ny, logNy, tkx, 1, tkx, tw);
+  for (int e = threadIdx.x; e < Ny * tkx; e += blockDim.x) {
+    const int y = e / tkx;
+    const int t = e - y * tkx;
+    const int kx = kx0 + t;
+    if (kx < P) base[(size_t)y * P + kx] = buf[e];
+  }
+}
+
+int x_lines_per_block(int M) {
+  const int quarter = M >= 4 ? M / 4 : 1;
+  return kBlock / quarter;  // M <= 1024 keeps this >= 1
+}
+
+int largest_pow2_divisor(int n, int cap) {
+  int d = 1;
+  while (d * 2 <= cap && n % (d * 2) == 0) d *= 2;
+  return d;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_fft_x_fwd(const Dims& d, const Tables<T>& tb, const T* const in[4], int nfields,
+                            cx<T>* spec, hipStream_t st) {
+  const int M = d.nx / 2;
+  const int lpf = d.ny * d.nz;
+  const int lpb = largest_pow2_divisor(lpf, x_lines_per_block(M));
+  const int total = lpf * nfields;
+  const int blocks = total / lpb;
+  const size_t shm = (size_t)lpb * M * sizeof(cx<T>);
+  hipLaunchKernelGGL(k_fft_x_fwd<T>, dim3(blocks), dim3(kBlock), shm, st, in[0],
+                     nfields > 1 ? in[1] : in[0], nfields > 2 ? in[2] : in[0], spec, d.nx,
+                     d.logx - 1, lpf, total, lpb, tb.tw_xm, tb.tw_xn);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft_x_inv(const Dims& d, const Tables<T>& tb, const cx<T>* spec, RealSet<T> out,
+                            hipStream_t st) {
+  const int M = d.nx / 2;
+  const int lpf = d.ny * d.nz;
+  const int lpb = largest_pow2_divisor(lpf, x_lines_per_block(M));
+  const int total = lpf * out.nfields;
+  const int blocks = total / lpb;
+  const size_t shm = (size_t)lpb * M * sizeof(cx<T>);
+  hipLaunchKernelGGL(k_fft_x_inv<T>, dim3(blocks), dim3(kBlock), shm, st, spec, out, d.nx,
+                     d.logx - 1, lpf, total, lpb, tb.tw_xm, tb.tw_xn);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft_y(const Dims& d, const Tables<T>& tb, cx<T>* spec, int nfields, bool inverse,
+                        hipStream_t st) {
+  if (d.ny == 1) return hipSuccess;
+  const int Ny = d.ny;
+  int tkx = 16;
+  while (tkx > 1 && tkx * Ny > 4096) tkx >>= 1;  // tkx * Ny / 4 <= 1024 threads
+  const int P = d.pitch;
+  const int ntiles = (P + tkx - 1) / tkx;
+  const int batches = d.nz * nfields;
+  int threads = tkx * (Ny >= 4 ? Ny / 4 : 1);
+  threads = ((threads + 63) / 64) * 64;
+  if (threads > 1024) threads = 1024;
+  const size_t shm = (size_t)Ny * tkx * sizeof(cx<T>);
+  if (inverse)
+    hipLaunchKernelGGL((k_fft_y<T, true>), dim3(ntiles * batches), dim3(threads), shm, st, spec, Ny,
+                       d.logy, P, ntiles, tkx, tb.tw_y);
+  else
+    hipLaunchKernelGGL((k_fft_y<T, false>), dim3(ntiles * batches), dim3(threads), shm, st, spec, Ny,
+                       d.logy, P, ntiles, tkx, tb.tw_y);
+  return hipGetLastError();
+}
+
+#define INST(T)                                                                                    \
+  template hipError_t launch_fft_x_fwd<T>(const Dims&, const Tables<T>&, const T* const[4], int,   \
+                                          cx<T>*, hipStream_t);                                    \
+  template hipError_t launch_fft_x_inv<T>(const Dims&, const Tables<T>&, const cx<T>*, RealSet<T>, \
+                                          hipStream_t);                                            \
+  template hipError_t launch_fft_y<T>(const Dims&, const Tables<T>&, cx<T>*, int, bool, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace drpf

@@ -1,0 +1,110 @@
+"""Host-only checks of the C-ABI library: every symbol that include/drpf.h declares is
+exported, and parameter validation / workspace errors are reported before any GPU call."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "drpf.h")
+
+
+def _lib():
+    from paper_2111_04577_amd import binding
+    if not os.path.exists(binding.lib_path):
+        from paper_2111_04577_amd import build_lib
+        build_lib.build()
+    return binding
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(drpf_[a-z_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    B = _lib()
+    L = B.lib()
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _params(**kw):
+    B = _lib()
+    cfg = W.config("C1")
+    p = B.make_params(cfg, 64)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 48), ("nx", 2), ("nz", 3), ("ny", 2), ("ny", 6), ("cn", 0.0), ("pe", -1.0),
+    ("dt", 0.0), ("s_factor", 0.99), ("theta_bottom_deg", 190.0), ("rho_ratio", 0.0),
+    ("precision", 16), ("lz", 0.0),
+])
+def test_validation_rejects(field, value):
+    B = _lib()
+    p = _params(**{field: value})
+    rc = B.lib().drpf_validate(ctypes.byref(p))
+    assert rc == B.DRPF_EINVAL
+    assert len(B.lib().drpf_last_error()) > 0
+
+
+def test_validation_viscoelastic_beta():
+    B = _lib()
+    p = _params(viscoelastic=1, beta=0.0)
+    assert B.lib().drpf_validate(ctypes.byref(p)) == B.DRPF_EINVAL
+    p = _params(viscoelastic=1, beta=0.5, wi=0.5)
+    assert B.lib().drpf_validate(ctypes.byref(p)) == B.DRPF_OK
+
+
+def test_sizes_and_workspace_errors():
+    B = _lib()
+    L = B.lib()
+    p = _params()
+    f, c = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.drpf_field_elems(ctypes.byref(p), ctypes.byref(f), ctypes.byref(c)) == 0
+    assert (f.value, c.value) == (128 * 64, 64 * 32)
+    nb = ctypes.c_size_t()
+    assert L.drpf_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == 0
+    assert nb.value > 8 * f.value
+    h = ctypes.c_void_p()
+    # no workspace, misaligned, too small: rejected on the host before any device call
+    assert L.drpf_init_grid(ctypes.byref(p), None, nb.value, None, ctypes.byref(h)) == B.DRPF_EWORKSPACE
+    assert L.drpf_init_grid(ctypes.byref(p), ctypes.c_void_p(0x1008), nb.value, None,
+                            ctypes.byref(h)) == B.DRPF_EWORKSPACE
+    assert L.drpf_init_grid(ctypes.byref(p), ctypes.c_void_p(0x10000), nb.value - 1, None,
+                            ctypes.byref(h)) == B.DRPF_EWORKSPACE
+    assert b"too small" in L.drpf_last_error()
+    # FP32 needs less
+    p32 = _params(precision=32)
+    nb32 = ctypes.c_size_t()
+    assert L.drpf_workspace_bytes(ctypes.byref(p32), ctypes.byref(nb32)) == 0
+    assert nb32.value < nb.value
+
+
+def test_null_arguments():
+    B = _lib()
+    L = B.lib()
+    assert L.drpf_step(None, None, 1, None) == B.DRPF_EINVAL
+    assert L.drpf_validate(None) == B.DRPF_EINVAL
+    assert L.drpf_destroy(None) == B.DRPF_OK
+
+
+def test_product_path_does_not_import_oracle():
+    """The package and its sources never reference the oracle."""
+    pkg = os.path.join(ROOT, "paper_2111_04577_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "oracle" not in text.lower(), fn
