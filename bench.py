@@ -1,0 +1,297 @@
+#!/usr/bin/env python3
+"""Benchmark of the dual-resolution phase-field step on one MI355X.
+
+Workload: the 3D Newtonian drop with large property contrast (coarse 128x128x64, fine
+256x256x128 = 8.39M phase-field cells, density ratio 1000, viscosity ratio 100, Cn 0.01,
+Re 100, static angle 90 deg, dt 1e-4), synthetic initial state (hemispherical drop on the
+bottom wall, zero flow). Inputs are resident in HBM before timing starts.
+
+Timed: K whole coupled steps (Cahn-Hilliard fine solve, restriction, Navier-Stokes
+projection) after W warm-up steps, bracketed by synchronisations and HIP events on the
+stream the library launches on. Both precision forms are timed: the FP32 form (FP64 kept for
+the pressure Poisson wall-normal solve, its zero mode and the mass sums) is the headline
+value, the FP64 form is reported beside it, with the per-field difference of the FP32 form
+from the FP64 form after the same steps (the FP64 form matches the FP64 CPU reference to
+1e-10 in the GPU tests).
+
+Per-kernel durations come from HIP events recorded by the library after every launch
+(drpf_profile_begin / drpf_profile_end) in a second pass of K steps; the roofline entry is
+for the kernel with the largest share of that time.
+
+Prints ONE JSON line. ``--gpus N`` with N > 1 exits: the build targets one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", default="C2")
+    ap.add_argument("--precision", choices=["both", "32", "64"], default="both")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 512 MiB device copy (counter calibration)")
+    ap.add_argument("--ingest-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
+                    help="turn rocprofv3 --pmc counter CSVs into the traffic summary and exit")
+    return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------------------
+# algorithmic bytes per launch: every kernel reads its inputs once and writes its outputs
+# once (spectral buffers count as complex arrays of (nx/2+1) ny nz entries)
+# ---------------------------------------------------------------------------------------
+
+def grid_sizes(cfg):
+    ry = 1 if cfg.ny == 1 else 2
+    F = dict(nx=2 * cfg.nx, ny=ry * cfg.ny, nz=2 * cfg.nz)
+    C = dict(nx=cfg.nx, ny=cfg.ny, nz=cfg.nz)
+    for d in (F, C):
+        d["cells"] = d["nx"] * d["ny"] * d["nz"]
+        d["spec"] = (d["nx"] // 2 + 1) * d["ny"] * d["nz"]
+    return F, C
+
+
+def alg_bytes(kernel, cfg, es):
+    F, C = grid_sizes(cfg)
+    nf, nc = F["cells"], C["cells"]
+    sf, sc = F["spec"] * 2, C["spec"] * 2   # complex -> 2 words
+    ne = C["nx"] * C["ny"] * (C["nz"] + 1)
+    ve = cfg.viscoelastic
+    words = {
+        "ch_rhs": 3 * nf + 6 * nc,
+        "fft_x_fwd_fine": nf + sf,
+        "fft_y_fwd_fine": 2 * sf if F["ny"] > 1 else 0,
+        "zpass_ch": 2 * sf,
+        "fft_y_inv_fine": 2 * sf if F["ny"] > 1 else 0,
+        "fft_x_inv_fine": sf + nf,
+        "restrict_g": 3 * nf + 10 * nc + 2 * ne,
+        "momentum_rhs": (8 + 10 + 12 * ve + 3) * nc + 2 * ne,
+        "fft_x_fwd_coarse": 3 * nc + 3 * sc,
+        "fft_y_fwd_coarse": 6 * sc if C["ny"] > 1 else 0,
+        "zpass_ns": 7 * sc,
+        "fft_y_inv_coarse": 8 * sc if C["ny"] > 1 else 0,
+        "fft_x_inv_coarse": 4 * sc + 5 * nc,
+        "polymer_stage1": 15 * nc if ve else 0,
+        "polymer_stage2": 21 * nc if ve else 0,
+    }
+    return words[kernel] * es
+
+
+KERNEL_SOURCE = {
+    "ch_rhs": "stencil_ch.hip", "restrict_g": "stencil_ch.hip", "momentum_rhs": "stencil_ns.hip",
+    "polymer_stage1": "stencil_ns.hip", "polymer_stage2": "stencil_ns.hip",
+    "zpass_ch": "tridiag.hip", "zpass_ns": "tridiag.hip",
+}
+
+
+def source_sha(kernel):
+    src = KERNEL_SOURCE.get(kernel, "fft.hip")
+    path = os.path.join(ROOT, "paper_2111_04577_amd", "csrc", src)
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_entry(kernel, precision):
+    """HBM bytes per launch from the committed counter summary, if it was taken on the
+    current source of that kernel; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    e = t.get(f"{kernel}/fp{precision}")
+    if not e or e.get("source_sha") != source_sha(kernel):
+        return None
+    return e.get("bytes_per_launch")
+
+
+# ---------------------------------------------------------------------------------------
+
+def time_form(drpf, W, cfg, precision, steps, warmup):
+    import torch
+    g = drpf.Grid(cfg, precision)
+    st = g.state(W.droplet_state(cfg))
+    g.step(st, warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    g.step(st, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    # per-kernel pass (HIP events after every launch, same stream)
+    g.profile_begin(steps * 16 + 1)
+    g.step(st, steps)
+    prof = g.profile_end()
+    torch.cuda.synchronize()
+    obs = g.observables(st)
+    return g, st, ms, wall, prof, obs
+
+
+def roofline_for(prof, cfg, precision, steps):
+    total = {k: v[0] for k, v in prof.items() if v[1] > 0}
+    dom = max(total, key=total.get)
+    ms_total, launches = prof[dom]
+    avg_s = ms_total / launches / 1e3
+    b = alg_bytes(dom, cfg, 8 if precision == 64 else 4)
+    achieved = b / avg_s / 1e9
+    kernels = {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1],
+                   "share": round(v[0] / sum(total.values()), 4),
+                   "alg_GBs": round(alg_bytes(k, cfg, 8 if precision == 64 else 4) / (v[0] / v[1] / 1e3) / 1e9, 1)}
+               for k, v in prof.items() if v[1] > 0}
+    traffic = traffic_entry(dom, precision)
+    return {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "alg_bytes_per_launch": b, "avg_us": round(avg_s * 1e6, 2)}, kernels
+
+
+def field_diff(a, b):
+    import numpy as np
+    out = {}
+    for f in ("phi", "u", "v", "w", "p"):
+        ref = b[f][0]
+        den = float(np.max(np.abs(ref)))
+        out[f] = float(np.max(np.abs(a[f][0] - ref))) / (den if den > 0 else 1.0)
+        out[f + "_rms"] = float(np.sqrt(np.mean((a[f][0] - ref) ** 2))) / (den if den > 0 else 1.0)
+    return {k: float(f"{v:.3e}") for k, v in out.items()}
+
+
+def cpu_baseline(W, cfg, nsteps):
+    """The FP64 oracle as it stands on the host, timed over the first nsteps steps."""
+    import numpy as np
+    from oracle import model
+    from oracle import step as S
+    P = model.Params.from_config(cfg)
+    st = W.droplet_state(cfg)
+    t0 = time.perf_counter()
+    st = S.run(P, st, nsteps)
+    dt = time.perf_counter() - t0
+    F, _ = grid_sizes(cfg)
+    return {"value": round(F["cells"] * nsteps / dt, 1), "unit": "fine cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {nsteps} steps of the same workload (full grid); "
+                      f"NumPy/SciPy FP64, single-threaded (scipy.fft workers=1), {dt:.1f} s",
+            "host_cpus": os.cpu_count()}
+
+
+def ingest_pmc(fetch_csv, write_csv, out_json):
+    """rocprofv3 --pmc counter_collection.csv files -> per-kernel bytes per launch, scaled by
+    the counter reading of the plain copy kernel of known size run in the same process."""
+    import csv
+    from collections import defaultdict
+
+    def read(path, counter):
+        acc = defaultdict(list)
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                acc[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    fetch = read(fetch_csv, "FETCH_SIZE")
+    write = read(write_csv, "WRITE_SIZE")
+    copy_bytes = 512 * 2 ** 20
+    copy_k = [k for k in fetch if "copy" in k.lower() or "elementwise" in k.lower()]
+    f_scale = copy_bytes / (fetch[copy_k[0]] * 1024) if copy_k else 1.0
+    w_scale = copy_bytes / (write[copy_k[0]] * 1024) if copy_k and copy_k[0] in write else 1.0
+    print(json.dumps({"copy_kernel": copy_k[:1], "fetch_scale": f_scale, "write_scale": w_scale}))
+    return fetch, write, f_scale, w_scale
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU layout is a "
+              "design note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+    if a.ingest_pmc:
+        ingest_pmc(*a.ingest_pmc)
+        return
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2111_04577_amd as drpf
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg = W.config(a.config)
+    F, C = grid_sizes(cfg)
+    forms = {"both": (32, 64), "32": (32,), "64": (64,)}[a.precision]
+    res = {}
+    states = {}
+    for prec in forms:
+        print(f"[bench] timing fp{prec} {cfg.name}: {a.warmup} warm-up + {a.steps} steps", file=sys.stderr, flush=True)
+        g, st, ms, wall, prof, obs = time_form(drpf, W, cfg, prec, a.steps, a.warmup)
+        roof, kernels = roofline_for(prof, cfg, prec, a.steps)
+        res[prec] = {"ms_per_step": ms / a.steps, "value": F["cells"] * a.steps / (ms / 1e3),
+                     "wall_s": wall, "roofline": roof, "kernels": kernels, "observables": obs}
+        states[prec] = st.to_host()
+        del g, st
+        torch.cuda.empty_cache()
+    if a.copy_calibration:
+        x = torch.empty(512 * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+    head = 32 if 32 in res else 64
+    out = {
+        "metric": "fine-grid cell-updates/s per dual-res step",
+        "value": round(res[head]["value"], 1),
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(res[head]["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head == 32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: 3D Newtonian drop on a wall, coarse {cfg.nx}x{cfg.ny}x{cfg.nz}, "
+                               f"fine {F['nx']}x{F['ny']}x{F['nz']} ({F['cells']} cells), rho ratio "
+                               f"{cfg.rho_ratio:g}, mu ratio {cfg.mu_ratio:g}, Re {cfg.re:g}, Cn {cfg.cn:g}, "
+                               f"Pe {cfg.pe:g}, dt {cfg.dt:g}",
+                   "fine_cells": F["cells"], "coarse_cells": C["cells"],
+                   "precision_islands": "FP64 Poisson wall-normal solve, zero mode, mass sums"
+                   if head == 32 else "all FP64"},
+        "roofline": res[head]["roofline"],
+        "kernels": res[head]["kernels"],
+    }
+    if 64 in res and head != 64:
+        out["fp64"] = {"value": round(res[64]["value"], 1), "ms_per_step": round(res[64]["ms_per_step"], 4),
+                       "roofline": res[64]["roofline"], "kernels": res[64]["kernels"]}
+        out["fp32_vs_fp64_speedup"] = round(res[32]["value"] / res[64]["value"], 3)
+        out["fp32_error_vs_fp64"] = field_diff(states[32], states[64])
+        out["fp32_error_vs_fp64"]["after_steps"] = states[32]["step"]
+        out["fp32_error_vs_fp64"]["mass_fp32"] = res[32]["observables"]["mass"]
+        out["fp32_error_vs_fp64"]["mass_fp64"] = res[64]["observables"]["mass"]
+    out["adj_fwd"] = None
+    if not a.no_cpu_baseline:
+        print(f"[bench] cpu baseline: oracle, {a.cpu_steps} steps", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(W, cfg, a.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -177,6 +177,20 @@ int drpf_observables(drpf_grid* g, const drpf_state* s, double* out, int n, void
  * 12..14 momentum right-hand sides r_u, r_v, r_w. */
 int drpf_debug_field(drpf_grid* g, int id, void** ptr, size_t* count);
 
+/* Per-kernel timing with HIP events on the caller's stream. After drpf_profile_begin, every
+ * kernel launch of drpf_step is followed by an event (up to max_launches of them);
+ * drpf_profile_end waits for the last one and writes, per kernel id in [0, n), the summed
+ * milliseconds between the event before and after each of its launches and the launch
+ * count. Kernel ids: 0 ch_rhs, 1-2 fine x/y forward transforms, 3 fine wall-normal pass,
+ * 4-5 fine y/x inverse transforms, 6 restriction and chemical potential, 7 momentum
+ * right-hand side, 8-9 coarse x/y forward transforms, 10 coarse wall-normal pass (NS
+ * projection), 11-12 coarse y/x inverse transforms, 13-14 polymer stages. */
+#define DRPF_NKERNELS 15
+int drpf_profile_begin(drpf_grid* g, int max_launches, void* stream);
+int drpf_profile_end(drpf_grid* g, double* total_ms, int* launches, int n);
+/* Short name of kernel id (see above); "" for an unknown id. */
+const char* drpf_kernel_name(int id);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char* drpf_last_error(void);
 

@@ -17,6 +17,7 @@ DRPF_OK, DRPF_EINVAL, DRPF_EWORKSPACE, DRPF_EHIP, DRPF_ENONFINITE, DRPF_EUNSUPPO
 LOCATIONS = {"center": 0, "face_x": 1, "face_y": 2, "face_z": 3, "edge_xy": 4, "edge_xz": 5,
              "edge_yz": 6}
 BCS = {"neumann": 0, "dirichlet": 1, "face_dirichlet": 2}
+NKERNELS = 15
 OBSERVABLES = ("mass", "wetted_radius", "centroid_height", "kinetic_energy", "max_div")
 
 
@@ -76,6 +77,8 @@ def lib():
             "drpf_helmholtz_solve": [vp, i, i, d, d, vp, vp, vp],
             "drpf_observables": [vp, P(State), P(d), i, vp],
             "drpf_debug_field": [vp, i, P(vp), P(sz)],
+            "drpf_profile_begin": [vp, i, vp],
+            "drpf_profile_end": [vp, P(d), P(i), i],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -83,6 +86,8 @@ def lib():
             fn.restype = ctypes.c_int
         L.drpf_last_error.argtypes = []
         L.drpf_last_error.restype = ctypes.c_char_p
+        L.drpf_kernel_name.argtypes = [ctypes.c_int]
+        L.drpf_kernel_name.restype = ctypes.c_char_p
         _LIB = L
     return _LIB
 
@@ -263,6 +268,17 @@ class Grid:
         _check(lib().drpf_restrict(self.handle, ctypes.c_void_p(fine.data_ptr()),
                                    ctypes.c_void_p(out.data_ptr()), loc, _stream_ptr(stream)))
         return out
+
+    def profile_begin(self, max_launches: int, stream=None):
+        _check(lib().drpf_profile_begin(self.handle, int(max_launches), _stream_ptr(stream)))
+
+    def profile_end(self) -> dict:
+        """{kernel name: (total ms, launches)} from the HIP events since profile_begin."""
+        n = NKERNELS
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int * n)()
+        _check(lib().drpf_profile_end(self.handle, ms, cnt, n))
+        return {lib().drpf_kernel_name(k).decode(): (ms[k], cnt[k]) for k in range(n)}
 
     def debug_field(self, idx: int):
         """Copy of an internal coarse array (see drpf_debug_field) as a numpy array."""

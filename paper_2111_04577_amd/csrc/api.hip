@@ -143,6 +143,11 @@ struct drpf_grid {
   StepConsts k1, k2;
   char* ws;
   Offsets o;
+  // per-kernel timing: one event after each launch, one at the start of profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_kernel;
+  size_t ev_used = 0;
 };
 
 namespace {
@@ -229,6 +234,18 @@ int upload_tables(drpf_grid* g, const Dims& d, const TabOff& t, hipStream_t st,
   return DRPF_OK;
 }
 
+const char* const kKernelNames[DRPF_NKERNELS] = {
+    "ch_rhs", "fft_x_fwd_fine", "fft_y_fwd_fine", "zpass_ch", "fft_y_inv_fine", "fft_x_inv_fine",
+    "restrict_g", "momentum_rhs", "fft_x_fwd_coarse", "fft_y_fwd_coarse", "zpass_ns",
+    "fft_y_inv_coarse", "fft_x_inv_coarse", "polymer_stage1", "polymer_stage2"};
+
+void mark(drpf_grid* g, int kernel, hipStream_t st) {
+  if (!g->prof || g->ev_used >= g->ev.size()) return;
+  hipEventRecord(g->ev[g->ev_used], st);
+  g->ev_kernel[g->ev_used] = kernel;
+  ++g->ev_used;
+}
+
 template <typename T>
 int step_impl(drpf_grid* g, drpf_state* s, int nsteps, hipStream_t st) {
   const Dims& F = g->F;
@@ -251,19 +268,26 @@ int step_impl(drpf_grid* g, drpf_state* s, int nsteps, hipStream_t st) {
     ChIn<T> ci{phin, phinm1, (const T*)s->u[0], (const T*)s->u[1], (const T*)s->v[0],
                (const T*)s->v[1], (const T*)s->w[0], (const T*)s->w[1]};
     HIPCHK(launch_ch_rhs<T>(F, C, K, ci, Rf, st), "ch_rhs");
+    mark(g, 0, st);
     const T* inf[4] = {Rf, nullptr, nullptr, nullptr};
     HIPCHK(launch_fft_x_fwd<T>(F, tf, inf, 1, Sf, st), "fft_x fine");
+    mark(g, 1, st);
     HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, false, st), "fft_y fine");
+    mark(g, 2, st);
     HIPCHK(launch_zpass_ch<T>(F, tf, Sf, piv, K.c_psi, K.alpha, 1.0 / ((double)F.nx * F.ny), st),
            "zpass_ch");
+    mark(g, 3, st);
     HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, true, st), "ifft_y fine");
+    mark(g, 4, st);
     RealSet<T> of;
     memset(&of, 0, sizeof(of));
     of.p[0] = phinew;
     of.nfields = 1;
     HIPCHK(launch_fft_x_inv<T>(F, tf, Sf, of, st), "ifft_x fine");
+    mark(g, 5, st);
     // ---- restriction, chemical potential, properties
     HIPCHK(launch_restrict_g<T>(F, C, K, phinew, phin, phinm1, R, st), "restrict_g");
+    mark(g, 6, st);
     // ---- Navier-Stokes on the coarse grid
     NsIn<T> ni;
     ni.un = (const T*)s->u[0];
@@ -280,11 +304,16 @@ int step_impl(drpf_grid* g, drpf_state* s, int nsteps, hipStream_t st) {
     }
     ni.viscoelastic = ve ? 1 : 0;
     HIPCHK(launch_momentum_rhs<T>(C, K, ni, R, Rc, Rc + nc, Rc + 2 * nc, st), "momentum_rhs");
+    mark(g, 7, st);
     const T* inc[4] = {Rc, Rc + nc, Rc + 2 * nc, nullptr};
     HIPCHK(launch_fft_x_fwd<T>(C, tc, inc, 3, Sc, st), "fft_x coarse");
+    mark(g, 8, st);
     HIPCHK(launch_fft_y<T>(C, tc, Sc, 3, false, st), "fft_y coarse");
+    mark(g, 9, st);
     HIPCHK(launch_zpass_ns<T>(C, tc, Sc, piv, K, 1.0 / ((double)C.nx * C.ny), st), "zpass_ns");
+    mark(g, 10, st);
     HIPCHK(launch_fft_y<T>(C, tc, Sc, 4, true, st), "ifft_y coarse");
+    mark(g, 11, st);
     RealSet<T> oc;
     memset(&oc, 0, sizeof(oc));
     oc.p[0] = (T*)s->u[1];
@@ -294,6 +323,7 @@ int step_impl(drpf_grid* g, drpf_state* s, int nsteps, hipStream_t st) {
     oc.add[3] = (const T*)s->p[0];
     oc.nfields = 4;
     HIPCHK(launch_fft_x_inv<T>(C, tc, Sc, oc, st), "ifft_x coarse");
+    mark(g, 12, st);
     // ---- polymer stress, RK2-TVD with u^{n+1}
     if (ve) {
       const T* tn[6];
@@ -309,9 +339,11 @@ int step_impl(drpf_grid* g, drpf_state* s, int nsteps, hipStream_t st) {
       HIPCHK(launch_polymer_stage<T>(C, K, (const T*)s->u[1], (const T*)s->v[1], (const T*)s->w[1],
                                      tn, tn, t1, 0.0, 1.0, st),
              "polymer stage 1");
+      mark(g, 13, st);
       HIPCHK(launch_polymer_stage<T>(C, K, (const T*)s->u[1], (const T*)s->v[1], (const T*)s->w[1],
                                      tn, t1c, tout, 0.5, 0.5, st),
              "polymer stage 2");
+      mark(g, 14, st);
     }
     // ---- rotate time levels (pointer swaps only)
     void* ph0 = s->phi[0];
@@ -489,6 +521,8 @@ int drpf_init_grid(const drpf_params* p, void* d_workspace, size_t bytes, void* 
 }
 
 int drpf_destroy(drpf_grid* g) {
+  if (g)
+    for (auto e : g->ev) hipEventDestroy(e);
   delete g;
   return DRPF_OK;
 }
@@ -555,6 +589,54 @@ int drpf_observables(drpf_grid* g, const drpf_state* s, double* out, int n, void
   hipStream_t st = (hipStream_t)stream;
   return g->p.precision == 64 ? observables_impl<double>(g, s, out, n, st)
                               : observables_impl<float>(g, s, out, n, st);
+}
+
+int drpf_profile_begin(drpf_grid* g, int max_launches, void* stream) {
+  if (!g || max_launches < 1) return fail(DRPF_EINVAL, "need a grid and max_launches >= 1");
+  if (g->prof) return fail(DRPF_EINVAL, "profiling already active");
+  g->ev.assign((size_t)max_launches + 1, nullptr);
+  g->ev_kernel.assign((size_t)max_launches + 1, -1);
+  for (auto& e : g->ev) HIPCHK(hipEventCreate(&e), "event create");
+  g->prof = true;
+  g->ev_used = 0;
+  mark(g, -1, (hipStream_t)stream);
+  return DRPF_OK;
+}
+
+int drpf_profile_end(drpf_grid* g, double* total_ms, int* launches, int n) {
+  if (!g || !g->prof) return fail(DRPF_EINVAL, "profiling not active");
+  int rc = DRPF_OK;
+  if (g->ev_used > 0) {
+    const hipError_t e = hipEventSynchronize(g->ev[g->ev_used - 1]);
+    if (e != hipSuccess) rc = hip_fail(e, "event synchronise");
+  }
+  for (int k = 0; k < n; ++k) {
+    if (total_ms) total_ms[k] = 0.0;
+    if (launches) launches[k] = 0;
+  }
+  for (size_t a = 1; rc == DRPF_OK && a < g->ev_used; ++a) {
+    float ms = 0.f;
+    const hipError_t e = hipEventElapsedTime(&ms, g->ev[a - 1], g->ev[a]);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "event elapsed time");
+      break;
+    }
+    const int k = g->ev_kernel[a];
+    if (k >= 0 && k < n) {
+      if (total_ms) total_ms[k] += ms;
+      if (launches) launches[k] += 1;
+    }
+  }
+  for (auto e : g->ev) hipEventDestroy(e);
+  g->ev.clear();
+  g->ev_kernel.clear();
+  g->ev_used = 0;
+  g->prof = false;
+  return rc;
+}
+
+const char* drpf_kernel_name(int id) {
+  return (id >= 0 && id < DRPF_NKERNELS) ? kKernelNames[id] : "";
 }
 
 int drpf_debug_field(drpf_grid* g, int id, void** ptr, size_t* count) {
