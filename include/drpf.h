@@ -76,7 +76,8 @@ enum drpf_bc {
 };
 
 typedef struct drpf_params {
-  int nx, ny, nz;              /* coarse cells; powers of two; nx, nz >= 4; ny == 1 or >= 4 */
+  int nx, ny, nz;              /* coarse cells; powers of two; 4 <= nx <= 1024, 4 <= nz <= 512;
+                                  ny == 1 (2D form) or 4 <= ny <= 1024                       */
   double lx, ly, lz;           /* box lengths (> 0)                                         */
   double re, ca, cn, pe;       /* Reynolds, capillary, Cahn, Peclet numbers (> 0)           */
   double wi, beta;             /* Weissenberg number and solvent-viscosity ratio of drop    */

@@ -47,6 +47,9 @@ Dims make_dims(int nx, int ny, int nz, double lx, double ly, double lz) {
   d.hx = lx / nx;
   d.hy = ly / ny;
   d.hz = lz / nz;
+  d.ihx = 1.0 / d.hx;
+  d.ihy = 1.0 / d.hy;
+  d.ihz = 1.0 / d.hz;
   return d;
 }
 
@@ -84,6 +87,15 @@ StepConsts make_consts(const drpf_params& p, bool first) {
   c.ax = p.a_ext[0];
   c.ay = p.a_ext[1];
   c.az = p.a_ext[2];
+  c.inv_dt = 1.0 / p.dt;
+  c.inv_cn2 = 1.0 / c.cn2;
+  c.s_cn2 = c.S / c.cn2;
+  c.pe_cn2 = p.pe / c.cn2;
+  c.g_bot = c.cos_bot / (sqrt(2.0) * p.cn);
+  c.g_top = c.cos_top / (sqrt(2.0) * p.cn);
+  c.inv_re = 1.0 / p.re;
+  c.inv_rho0 = 1.0 / c.rho0;
+  c.inv_wi = 1.0 / p.wi;
   return c;
 }
 
@@ -439,7 +451,8 @@ int drpf_params_default(drpf_params* p) {
 int drpf_validate(const drpf_params* p) {
   if (!p) return fail(DRPF_EINVAL, "null params");
   if (!pow2(p->nx) || p->nx < 4 || p->nx > 1024) return fail(DRPF_EINVAL, "nx must be a power of two in [4, 1024]");
-  if (!pow2(p->nz) || p->nz < 4 || p->nz > 4096) return fail(DRPF_EINVAL, "nz must be a power of two in [4, 4096]");
+  // the wall-normal solve keeps a whole fine column (2 nz rows) in one thread block
+  if (!pow2(p->nz) || p->nz < 4 || p->nz > 512) return fail(DRPF_EINVAL, "nz must be a power of two in [4, 512]");
   if (!(p->ny == 1 || (pow2(p->ny) && p->ny >= 4 && p->ny <= 1024)))
     return fail(DRPF_EINVAL, "ny must be 1 or a power of two in [4, 1024]");
   if (!(p->lx > 0 && p->ly > 0 && p->lz > 0)) return fail(DRPF_EINVAL, "box lengths must be > 0");

@@ -64,6 +64,7 @@ struct Dims {
   int logx, logy;       // log2(nx), log2(ny)
   int pitch;            // nx/2 + 1: complex entries per spectral x-row
   double hx, hy, hz;    // spacings
+  double ihx, ihy, ihz; // their reciprocals
   __host__ __device__ size_t cells() const { return (size_t)nx * ny * nz; }
   __host__ __device__ size_t spec() const { return (size_t)pitch * ny * nz; }
   __host__ __device__ int lines() const { return pitch * ny; }
@@ -93,7 +94,26 @@ struct StepConsts {
   double re, k_sigma, c_j;      // 1/Re scaling, capillary coefficient, J = -c_j grad G
   double wi, beta;              // Oldroyd-B
   double ax, ay, az;            // body acceleration
+  // reciprocals and products formed once on the host
+  double inv_dt, inv_cn2, s_cn2, pe_cn2;  // 1/dt, 1/Cn^2, S/Cn^2, Pe/Cn^2
+  double g_bot, g_top;                    // cos(theta) / (sqrt(2) Cn) at each wall
+  double inv_re, inv_rho0, inv_wi;
 };
+
+// Block shape of the 3D stencil launches: bx threads along x, by along y, one z layer per
+// block row of the grid (gridDim.z = nz, or a multiple of it).
+struct Launch3 {
+  dim3 grid, block;
+};
+inline Launch3 launch3(int nx, int ny, int nz_blocks, int max_threads = 256) {
+  const int bx = nx < 64 ? nx : 64;
+  int by = max_threads / bx;
+  if (by > ny) by = ny;
+  Launch3 l;
+  l.block = dim3(bx, by, 1);
+  l.grid = dim3(nx / bx, ny / by, nz_blocks);
+  return l;
+}
 
 __host__ __device__ __forceinline__ int wrap(int i, int n) { return i & (n - 1); }
 

@@ -1,20 +1,22 @@
 // Coarse-grid (flow) stencils.
 //
 //   momentum_rhs   -- right-hand side r of the velocity Helmholtz equations of eq. NS36,
-//                     (nu_m L - gamma0/dt) u~ = r, for the three components at their own
-//                     faces. r collects -u_hat/dt (eq. NS35), the conservative central
-//                     advection of u*, the diffusive-flux term J.grad(u*)/rho, the split
-//                     pressure gradient (1/rho0) grad p^n + (1/rho - 1/rho0) grad p*, the
-//                     explicit nu_m L u*, the polymer divergence of the second approach
-//                     (eq. NS12, drop = polymer phase), the variable-viscosity stress
-//                     divergence, the capillary force G grad(phi) and the body force.
+//                     (nu_m L - gamma0/dt) u~ = r, for each component at its own faces.
+//                     r collects -u_hat/dt (eq. NS35), the conservative central advection of
+//                     u*, the diffusive-flux term J.grad(u*)/rho, the split pressure gradient
+//                     (1/rho0) grad p^n + (1/rho - 1/rho0) grad p*, the explicit nu_m L u*,
+//                     the polymer divergence of the second approach (eq. NS12, drop = polymer
+//                     phase), the variable-viscosity stress divergence, the capillary force
+//                     G grad(phi) and the body force. One launch covers the three components:
+//                     blockIdx.z runs over (component, z layer), so the component is uniform
+//                     within a block and each thread keeps only one component's terms live.
 //   polymer_stage  -- one stage of the second-order TVD Runge-Kutta update of the polymer
 //                     stress (eqs. NS42, NS44) for the Oldroyd-B law in stress form.
 //
 // Staggering: u[k][j][i] at ((i+1) hx, (j+.5) hy, (k+.5) hz), v at (i+.5, j+1, k+.5),
 // w at (i+.5, j+.5, k+1) with w[nz-1] the top wall; centres at (i+.5, j+.5, k+.5).
 // Wall rules: no-slip ghost = -adjacent for u, v; w = 0 on the walls; Neumann ghost for
-// centred scalars (G, tau).
+// centred scalars (G, tau). Arithmetic in the storage type T.
 #include "kernels.hpp"
 
 namespace drpf {
@@ -28,44 +30,38 @@ struct Field {
   const T* a;
   const T* b;   // level n-1 (extrapolation) or null
   int nx, ny, nz, first;
+  __device__ __forceinline__ size_t idx(int k, int j, int i) const {
+    return ((size_t)k * ny + wrap(j, ny)) * nx + wrap(i, nx);
+  }
   // extrapolated value (u* = 2 u^n - u^{n-1}, or u^n on the first step), in-range k
-  __device__ __forceinline__ double s(int k, int j, int i) const {
-    const size_t id = ((size_t)k * ny + wrap(j, ny)) * nx + wrap(i, nx);
-    return (first || b == nullptr) ? (double)a[id] : 2.0 * (double)a[id] - (double)b[id];
+  __device__ __forceinline__ T s(int k, int j, int i) const {
+    const size_t id = idx(k, j, i);
+    return (first || b == nullptr) ? a[id] : (T)2 * a[id] - b[id];
   }
-  __device__ __forceinline__ double n(int k, int j, int i) const {
-    return (double)a[((size_t)k * ny + wrap(j, ny)) * nx + wrap(i, nx)];
-  }
+  __device__ __forceinline__ T n(int k, int j, int i) const { return a[idx(k, j, i)]; }
   // cell-centred-in-z velocity with no-slip ghosts
-  __device__ __forceinline__ double sd(int k, int j, int i) const {
+  __device__ __forceinline__ T sd(int k, int j, int i) const {
     if (k < 0) return -s(0, j, i);
     if (k >= nz) return -s(nz - 1, j, i);
     return s(k, j, i);
   }
-  // z-face velocity: index -1 is the bottom wall, nz-1 the top wall (stored 0), beyond 0
-  __device__ __forceinline__ double sw(int k, int j, int i) const {
-    if (k < 0 || k >= nz - 1) return 0.0;
+  // z-face velocity: index -1 is the bottom wall, nz-1 the top wall, beyond 0
+  __device__ __forceinline__ T sw(int k, int j, int i) const {
+    if (k < 0 || k >= nz - 1) return (T)0;
     return s(k, j, i);
   }
   // centred scalar with Neumann ghosts
-  __device__ __forceinline__ double sn(int k, int j, int i) const {
-    return s(min(max(k, 0), nz - 1), j, i);
-  }
-  __device__ __forceinline__ double nn(int k, int j, int i) const {
-    return n(min(max(k, 0), nz - 1), j, i);
-  }
+  __device__ __forceinline__ T sn(int k, int j, int i) const { return s(min(max(k, 0), nz - 1), j, i); }
 };
 
 template <typename T>
 struct Coarse {
   const T* a;
   int nx, ny, nz;
-  __device__ __forceinline__ double at(int k, int j, int i) const {
-    return (double)a[((size_t)k * ny + wrap(j, ny)) * nx + wrap(i, nx)];
+  __device__ __forceinline__ T at(int k, int j, int i) const {
+    return a[((size_t)k * ny + wrap(j, ny)) * nx + wrap(i, nx)];
   }
-  __device__ __forceinline__ double atn(int k, int j, int i) const {
-    return at(min(max(k, 0), nz - 1), j, i);
-  }
+  __device__ __forceinline__ T atn(int k, int j, int i) const { return at(min(max(k, 0), nz - 1), j, i); }
 };
 
 // z-edge arrays (nz + 1 layers): layer m is the edge at z = m hz
@@ -73,208 +69,232 @@ template <typename T>
 struct ZEdge {
   const T* a;
   int nx, ny;
-  __device__ __forceinline__ double at(int m, int j, int i) const {
-    return (double)a[((size_t)m * ny + wrap(j, ny)) * nx + wrap(i, nx)];
+  __device__ __forceinline__ T at(int m, int j, int i) const {
+    return a[((size_t)m * ny + wrap(j, ny)) * nx + wrap(i, nx)];
   }
 };
 
 template <typename T>
+struct MomCtx {
+  Field<T> U, V, W, P, Pn;
+  Coarse<T> Gc, phic, muc, muxy;
+  ZEdge<T> muxz, muyz;
+  const T* const* taun;
+  const T* const* taunm1;
+  Restricted<T> R;
+  int nx, ny, nz, first, ve;
+  T ihx, ihy, ihz;
+  T inv_dt, inv_re, ir0, nu_m, k_sigma, c_j;
+  // hat of eq. NS31 at an in-range index
+  __device__ __forceinline__ T hat(const T* a, const T* b, size_t id) const {
+    return first ? a[id] : (T)2 * a[id] - (T)0.5 * b[id];
+  }
+  // J = -c_j grad G at a centre: 2h central differences, Neumann in z
+  __device__ __forceinline__ void Jc(int k, int j, int i, T* J) const {
+    const T h = (T)0.5;
+    J[0] = -c_j * (Gc.at(k, j, i + 1) - Gc.at(k, j, i - 1)) * h * ihx;
+    J[1] = -c_j * (Gc.at(k, j + 1, i) - Gc.at(k, j - 1, i)) * h * ihy;
+    J[2] = -c_j * (Gc.atn(k + 1, j, i) - Gc.atn(k - 1, j, i)) * h * ihz;
+  }
+  // polymer weight (1 + phi_c)/2 tau*, Neumann ghosts
+  __device__ __forceinline__ T Tp(int comp, int k, int j, int i) const {
+    const Field<T> t{taun[comp], taunm1[comp], nx, ny, nz, first};
+    return (T)0.5 * ((T)1 + phic.atn(k, j, i)) * t.sn(k, j, i);
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ T mom_u(const MomCtx<T>& m, int k, int j, int i, size_t id, T ax) {
+  const auto& U = m.U;
+  const auto& V = m.V;
+  const auto& W = m.W;
+  const T h = (T)0.5, ihx = m.ihx, ihy = m.ihy, ihz = m.ihz;
+  const T u0 = U.s(k, j, i);
+  const T uxp = U.s(k, j, i + 1), uxm = U.s(k, j, i - 1);
+  const T uyp = U.s(k, j + 1, i), uym = U.s(k, j - 1, i);
+  const T uzp = U.sd(k + 1, j, i), uzm = U.sd(k - 1, j, i);
+  // advection
+  const T ucr = h * (u0 + uxp), ucl = h * (uxm + u0);
+  T adv = (ucr * ucr - ucl * ucl) * ihx;
+  const T v00 = V.s(k, j, i), v01 = V.s(k, j, i + 1), vm0 = V.s(k, j - 1, i), vm1 = V.s(k, j - 1, i + 1);
+  adv += (h * (v00 + v01) * h * (u0 + uyp) - h * (vm0 + vm1) * h * (uym + u0)) * ihy;
+  const T w00 = W.sw(k, j, i), w01 = W.sw(k, j, i + 1), wm0 = W.sw(k - 1, j, i), wm1 = W.sw(k - 1, j, i + 1);
+  adv += (h * (w00 + w01) * h * (u0 + uzp) - h * (wm0 + wm1) * h * (uzm + u0)) * ihz;
+  // J . grad u*
+  T Ja[3], Jb[3];
+  m.Jc(k, j, i, Ja);
+  m.Jc(k, j, i + 1, Jb);
+  const T jgu = h * (Ja[0] + Jb[0]) * (uxp - uxm) * h * ihx + h * (Ja[1] + Jb[1]) * (uyp - uym) * h * ihy +
+                h * (Ja[2] + Jb[2]) * (uzp - uzm) * h * ihz;
+  // viscous stress divergence
+  T vis = ((T)2 * m.muc.at(k, j, i + 1) * (uxp - u0) * ihx - (T)2 * m.muc.at(k, j, i) * (u0 - uxm) * ihx) * ihx;
+  const T sxyp = m.muxy.at(k, j, i) * ((uyp - u0) * ihy + (v01 - v00) * ihx);
+  const T sxym = m.muxy.at(k, j - 1, i) * ((u0 - uym) * ihy + (vm1 - vm0) * ihx);
+  vis += (sxyp - sxym) * ihy;
+  const T sxzp = m.muxz.at(k + 1, j, i) * ((uzp - u0) * ihz + (w01 - w00) * ihx);
+  const T sxzm = m.muxz.at(k, j, i) * ((u0 - uzm) * ihz + (wm1 - wm0) * ihx);
+  vis += (sxzp - sxzm) * ihz;
+  // polymer divergence
+  T pol = 0;
+  if (m.ve) {
+    const T q = (T)0.25;
+    pol = (m.Tp(0, k, j, i + 1) - m.Tp(0, k, j, i)) * ihx;
+    auto txy = [&](int jj) {
+      return q * (m.Tp(3, k, jj, i) + m.Tp(3, k, jj, i + 1) + m.Tp(3, k, jj + 1, i) + m.Tp(3, k, jj + 1, i + 1));
+    };
+    pol += (txy(j) - txy(j - 1)) * ihy;
+    auto txz = [&](int kk) {
+      return q * (m.Tp(4, kk, j, i) + m.Tp(4, kk, j, i + 1) + m.Tp(4, kk + 1, j, i) + m.Tp(4, kk + 1, j, i + 1));
+    };
+    pol += (txz(k) - txz(k - 1)) * ihz;
+  }
+  const T ri = m.R.ri_x[id];
+  const T gpn = (m.Pn.n(k, j, i + 1) - m.Pn.n(k, j, i)) * ihx;
+  const T gps = (m.P.s(k, j, i + 1) - m.P.s(k, j, i)) * ihx;
+  const T cap = m.R.G_x[id] * (m.phic.at(k, j, i + 1) - m.phic.at(k, j, i)) * ihx;
+  const T lap = (uxp - 2 * u0 + uxm) * ihx * ihx + (uyp - 2 * u0 + uym) * ihy * ihy + (uzp - 2 * u0 + uzm) * ihz * ihz;
+  return -m.hat(U.a, U.b, id) * m.inv_dt + adv + ri * jgu + gpn * m.ir0 + (ri - m.ir0) * gps + m.nu_m * lap -
+         m.inv_re * ri * pol - m.inv_re * ri * vis - m.k_sigma * ri * cap - ax;
+}
+
+template <typename T>
+__device__ __forceinline__ T mom_v(const MomCtx<T>& m, int k, int j, int i, size_t id, T ay) {
+  const auto& U = m.U;
+  const auto& V = m.V;
+  const auto& W = m.W;
+  const T h = (T)0.5, ihx = m.ihx, ihy = m.ihy, ihz = m.ihz;
+  const T v0 = V.s(k, j, i);
+  const T vxp = V.s(k, j, i + 1), vxm = V.s(k, j, i - 1);
+  const T vyp = V.s(k, j + 1, i), vym = V.s(k, j - 1, i);
+  const T vzp = V.sd(k + 1, j, i), vzm = V.sd(k - 1, j, i);
+  const T vcu = h * (v0 + vyp), vcl = h * (vym + v0);
+  T adv = (vcu * vcu - vcl * vcl) * ihy;
+  const T u00 = U.s(k, j, i), u10 = U.s(k, j + 1, i), u0m = U.s(k, j, i - 1), u1m = U.s(k, j + 1, i - 1);
+  adv += (h * (u00 + u10) * h * (v0 + vxp) - h * (u0m + u1m) * h * (vxm + v0)) * ihx;
+  const T w00 = W.sw(k, j, i), w10 = W.sw(k, j + 1, i), wm0 = W.sw(k - 1, j, i), wm1 = W.sw(k - 1, j + 1, i);
+  adv += (h * (w00 + w10) * h * (v0 + vzp) - h * (wm0 + wm1) * h * (vzm + v0)) * ihz;
+  T Ja[3], Jb[3];
+  m.Jc(k, j, i, Ja);
+  m.Jc(k, j + 1, i, Jb);
+  const T jgv = h * (Ja[0] + Jb[0]) * (vxp - vxm) * h * ihx + h * (Ja[1] + Jb[1]) * (vyp - vym) * h * ihy +
+                h * (Ja[2] + Jb[2]) * (vzp - vzm) * h * ihz;
+  T vis = ((T)2 * m.muc.at(k, j + 1, i) * (vyp - v0) * ihy - (T)2 * m.muc.at(k, j, i) * (v0 - vym) * ihy) * ihy;
+  const T sxyp = m.muxy.at(k, j, i) * ((u10 - u00) * ihy + (vxp - v0) * ihx);
+  const T sxym = m.muxy.at(k, j, i - 1) * ((u1m - u0m) * ihy + (v0 - vxm) * ihx);
+  vis += (sxyp - sxym) * ihx;
+  const T syzp = m.muyz.at(k + 1, j, i) * ((vzp - v0) * ihz + (w10 - w00) * ihy);
+  const T syzm = m.muyz.at(k, j, i) * ((v0 - vzm) * ihz + (wm1 - wm0) * ihy);
+  vis += (syzp - syzm) * ihz;
+  T pol = 0;
+  if (m.ve) {
+    const T q = (T)0.25;
+    auto txy = [&](int ii) {
+      return q * (m.Tp(3, k, j, ii) + m.Tp(3, k, j, ii + 1) + m.Tp(3, k, j + 1, ii) + m.Tp(3, k, j + 1, ii + 1));
+    };
+    pol = (txy(i) - txy(i - 1)) * ihx;
+    pol += (m.Tp(1, k, j + 1, i) - m.Tp(1, k, j, i)) * ihy;
+    auto tyz = [&](int kk) {
+      return q * (m.Tp(5, kk, j, i) + m.Tp(5, kk, j + 1, i) + m.Tp(5, kk + 1, j, i) + m.Tp(5, kk + 1, j + 1, i));
+    };
+    pol += (tyz(k) - tyz(k - 1)) * ihz;
+  }
+  const T ri = m.R.ri_y[id];
+  const T gpn = (m.Pn.n(k, j + 1, i) - m.Pn.n(k, j, i)) * ihy;
+  const T gps = (m.P.s(k, j + 1, i) - m.P.s(k, j, i)) * ihy;
+  const T cap = m.R.G_y[id] * (m.phic.at(k, j + 1, i) - m.phic.at(k, j, i)) * ihy;
+  const T lap = (vxp - 2 * v0 + vxm) * ihx * ihx + (vyp - 2 * v0 + vym) * ihy * ihy + (vzp - 2 * v0 + vzm) * ihz * ihz;
+  return -m.hat(V.a, V.b, id) * m.inv_dt + adv + ri * jgv + gpn * m.ir0 + (ri - m.ir0) * gps + m.nu_m * lap -
+         m.inv_re * ri * pol - m.inv_re * ri * vis - m.k_sigma * ri * cap - ay;
+}
+
+template <typename T>
+__device__ __forceinline__ T mom_w(const MomCtx<T>& m, int k, int j, int i, size_t id, T az) {
+  const auto& U = m.U;
+  const auto& V = m.V;
+  const auto& W = m.W;
+  const T h = (T)0.5, ihx = m.ihx, ihy = m.ihy, ihz = m.ihz;
+  const T w0 = W.sw(k, j, i);
+  const T wxp = W.sw(k, j, i + 1), wxm = W.sw(k, j, i - 1);
+  const T wyp = W.sw(k, j + 1, i), wym = W.sw(k, j - 1, i);
+  const T wzp = W.sw(k + 1, j, i), wzm = W.sw(k - 1, j, i);
+  const T wcu = h * (w0 + wzp), wcl = h * (wzm + w0);
+  T adv = (wcu * wcu - wcl * wcl) * ihz;
+  const T u00 = U.s(k, j, i), u10 = U.s(k + 1, j, i), u0m = U.s(k, j, i - 1), u1m = U.s(k + 1, j, i - 1);
+  adv += (h * (u00 + u10) * h * (w0 + wxp) - h * (u0m + u1m) * h * (wxm + w0)) * ihx;
+  const T v00 = V.s(k, j, i), v10 = V.s(k + 1, j, i), v0m = V.s(k, j - 1, i), v1m = V.s(k + 1, j - 1, i);
+  adv += (h * (v00 + v10) * h * (w0 + wyp) - h * (v0m + v1m) * h * (wym + w0)) * ihy;
+  T Ja[3], Jb[3];
+  m.Jc(k, j, i, Ja);
+  m.Jc(k + 1, j, i, Jb);
+  const T jgw = h * (Ja[0] + Jb[0]) * (wxp - wxm) * h * ihx + h * (Ja[1] + Jb[1]) * (wyp - wym) * h * ihy +
+                h * (Ja[2] + Jb[2]) * (wzp - wzm) * h * ihz;
+  T vis = ((T)2 * m.muc.at(k + 1, j, i) * (wzp - w0) * ihz - (T)2 * m.muc.at(k, j, i) * (w0 - wzm) * ihz) * ihz;
+  const T sxzp = m.muxz.at(k + 1, j, i) * ((wxp - w0) * ihx + (u10 - u00) * ihz);
+  const T sxzm = m.muxz.at(k + 1, j, i - 1) * ((w0 - wxm) * ihx + (u1m - u0m) * ihz);
+  vis += (sxzp - sxzm) * ihx;
+  const T syzp = m.muyz.at(k + 1, j, i) * ((wyp - w0) * ihy + (v10 - v00) * ihz);
+  const T syzm = m.muyz.at(k + 1, j - 1, i) * ((w0 - wym) * ihy + (v1m - v0m) * ihz);
+  vis += (syzp - syzm) * ihy;
+  T pol = 0;
+  if (m.ve) {
+    const T q = (T)0.25;
+    auto txz = [&](int ii) {
+      return q * (m.Tp(4, k, j, ii) + m.Tp(4, k, j, ii + 1) + m.Tp(4, k + 1, j, ii) + m.Tp(4, k + 1, j, ii + 1));
+    };
+    auto tyz = [&](int jj) {
+      return q * (m.Tp(5, k, jj, i) + m.Tp(5, k, jj + 1, i) + m.Tp(5, k + 1, jj, i) + m.Tp(5, k + 1, jj + 1, i));
+    };
+    pol = (txz(i) - txz(i - 1)) * ihx + (tyz(j) - tyz(j - 1)) * ihy + (m.Tp(2, k + 1, j, i) - m.Tp(2, k, j, i)) * ihz;
+  }
+  const T ri = m.R.ri_z[id];
+  const T gpn = (m.Pn.n(k + 1, j, i) - m.Pn.n(k, j, i)) * ihz;
+  const T gps = (m.P.s(k + 1, j, i) - m.P.s(k, j, i)) * ihz;
+  const T cap = m.R.G_z[id] * (m.phic.at(k + 1, j, i) - m.phic.at(k, j, i)) * ihz;
+  const T lap = (wxp - 2 * w0 + wxm) * ihx * ihx + (wyp - 2 * w0 + wym) * ihy * ihy + (wzp - 2 * w0 + wzm) * ihz * ihz;
+  return -m.hat(W.a, W.b, id) * m.inv_dt + adv + ri * jgw + gpn * m.ir0 + (ri - m.ir0) * gps + m.nu_m * lap -
+         m.inv_re * ri * pol - m.inv_re * ri * vis - m.k_sigma * ri * cap - az;
+}
+
+template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_momentum_rhs(NsIn<T> in, Restricted<T> R, T* __restrict__ ru, T* __restrict__ rv,
-                   T* __restrict__ rw, int nx, int ny, int nz, double hx, double hy, double hz,
-                   StepConsts c) {
-  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t n = (size_t)nx * ny * nz;
-  if (id >= n) return;
-  const int i = (int)(id % nx);
-  const int j = (int)((id / nx) % ny);
-  const int k = (int)(id / ((size_t)nx * ny));
+                   T* __restrict__ rw, int nx, int ny, int nz, T ihx, T ihy, T ihz, StepConsts c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int comp = blockIdx.z / nz;
+  const int k = blockIdx.z - comp * nz;
   const int f = c.first;
-  const Field<T> U{in.un, in.unm1, nx, ny, nz, f}, V{in.vn, in.vnm1, nx, ny, nz, f},
-      W{in.wn, in.wnm1, nx, ny, nz, f}, P{in.pn, in.pnm1, nx, ny, nz, f};
-  const Field<T> Pn{in.pn, nullptr, nx, ny, nz, 1};
-  const Coarse<T> Gc{R.G_c, nx, ny, nz}, phic{R.phi_c, nx, ny, nz}, muc{R.mu_c, nx, ny, nz},
-      muxy{R.mu_xy, nx, ny, nz};
-  const ZEdge<T> muxz{R.mu_xz, nx, ny}, muyz{R.mu_yz, nx, ny};
-  const double ihx = 1.0 / hx, ihy = 1.0 / hy, ihz = 1.0 / hz;
-  const double dt = c.dt;
-  const double inv_re = 1.0 / c.re;
-  const double ir0 = 1.0 / c.rho0;
-
-  // hat (eq. NS31) of a field at an in-range index
-  auto hat = [&](const T* a, const T* b, size_t idx) -> double {
-    return f ? (double)a[idx] : 2.0 * (double)a[idx] - 0.5 * (double)b[idx];
-  };
-  // J = -c_j grad G at centre (k, j, i): 2h central differences, Neumann in z
-  auto Jc = [&](int kk, int jj, int ii, double* J) {
-    J[0] = -c.c_j * (Gc.at(kk, jj, ii + 1) - Gc.at(kk, jj, ii - 1)) * 0.5 * ihx;
-    J[1] = -c.c_j * (Gc.at(kk, jj + 1, ii) - Gc.at(kk, jj - 1, ii)) * 0.5 * ihy;
-    J[2] = -c.c_j * (Gc.atn(kk + 1, jj, ii) - Gc.atn(kk - 1, jj, ii)) * 0.5 * ihz;
-  };
-  // polymer weight T = (1 + phi_c)/2 * tau*, Neumann ghosts
-  auto Tp = [&](int comp, int kk, int jj, int ii) -> double {
-    const Field<T> t{in.taun[comp], in.taunm1[comp], nx, ny, nz, f};
-    return 0.5 * (1.0 + phic.atn(kk, jj, ii)) * t.sn(kk, jj, ii);
-  };
-  const bool ve = in.viscoelastic != 0;
-  const double ax[3] = {c.ax, c.ay, c.az};
-
-  // ------------------------------------------------------------------ u at x face (i,j,k)
-  {
-    const double u0 = U.s(k, j, i);
-    // advection
-    const double ucr = 0.5 * (u0 + U.s(k, j, i + 1)), ucl = 0.5 * (U.s(k, j, i - 1) + u0);
-    double adv = (ucr * ucr - ucl * ucl) * ihx;
-    const double fyp = 0.5 * (V.s(k, j, i) + V.s(k, j, i + 1)) * 0.5 * (u0 + U.s(k, j + 1, i));
-    const double fym = 0.5 * (V.s(k, j - 1, i) + V.s(k, j - 1, i + 1)) * 0.5 * (U.s(k, j - 1, i) + u0);
-    adv += (fyp - fym) * ihy;
-    const double fzp = 0.5 * (W.sw(k, j, i) + W.sw(k, j, i + 1)) * 0.5 * (u0 + U.sd(k + 1, j, i));
-    const double fzm = 0.5 * (W.sw(k - 1, j, i) + W.sw(k - 1, j, i + 1)) * 0.5 * (U.sd(k - 1, j, i) + u0);
-    adv += (fzp - fzm) * ihz;
-    // J . grad u*
-    double Ja[3], Jb[3];
-    Jc(k, j, i, Ja);
-    Jc(k, j, i + 1, Jb);
-    const double jgu = 0.5 * (Ja[0] + Jb[0]) * (U.s(k, j, i + 1) - U.s(k, j, i - 1)) * 0.5 * ihx +
-                       0.5 * (Ja[1] + Jb[1]) * (U.s(k, j + 1, i) - U.s(k, j - 1, i)) * 0.5 * ihy +
-                       0.5 * (Ja[2] + Jb[2]) * (U.sd(k + 1, j, i) - U.sd(k - 1, j, i)) * 0.5 * ihz;
-    // viscous stress divergence
-    double vis = (2 * muc.at(k, j, i + 1) * (U.s(k, j, i + 1) - u0) * ihx -
-                  2 * muc.at(k, j, i) * (u0 - U.s(k, j, i - 1)) * ihx) * ihx;
-    const double sxyp = muxy.at(k, j, i) * ((U.s(k, j + 1, i) - u0) * ihy + (V.s(k, j, i + 1) - V.s(k, j, i)) * ihx);
-    const double sxym = muxy.at(k, j - 1, i) * ((u0 - U.s(k, j - 1, i)) * ihy + (V.s(k, j - 1, i + 1) - V.s(k, j - 1, i)) * ihx);
-    vis += (sxyp - sxym) * ihy;
-    const double sxzp = muxz.at(k + 1, j, i) * ((U.sd(k + 1, j, i) - u0) * ihz + (W.sw(k, j, i + 1) - W.sw(k, j, i)) * ihx);
-    const double sxzm = muxz.at(k, j, i) * ((u0 - U.sd(k - 1, j, i)) * ihz + (W.sw(k - 1, j, i + 1) - W.sw(k - 1, j, i)) * ihx);
-    vis += (sxzp - sxzm) * ihz;
-    // polymer divergence
-    double pol = 0;
-    if (ve) {
-      pol = (Tp(0, k, j, i + 1) - Tp(0, k, j, i)) * ihx;
-      auto txy = [&](int jj) {
-        return 0.25 * (Tp(3, k, jj, i) + Tp(3, k, jj, i + 1) + Tp(3, k, jj + 1, i) + Tp(3, k, jj + 1, i + 1));
-      };
-      pol += (txy(j) - txy(j - 1)) * ihy;
-      auto txz = [&](int kk) {  // edge between centres kk and kk+1
-        return 0.25 * (Tp(4, kk, j, i) + Tp(4, kk, j, i + 1) + Tp(4, kk + 1, j, i) + Tp(4, kk + 1, j, i + 1));
-      };
-      pol += (txz(k) - txz(k - 1)) * ihz;
-    }
-    const double ri = (double)R.ri_x[id];
-    const double gpn = (Pn.n(k, j, i + 1) - Pn.n(k, j, i)) * ihx;
-    const double gps = (P.s(k, j, i + 1) - P.s(k, j, i)) * ihx;
-    const double cap = (double)R.G_x[id] * (phic.at(k, j, i + 1) - phic.at(k, j, i)) * ihx;
-    const double lap = (U.s(k, j, i + 1) - 2 * u0 + U.s(k, j, i - 1)) * ihx * ihx +
-                       (U.s(k, j + 1, i) - 2 * u0 + U.s(k, j - 1, i)) * ihy * ihy +
-                       (U.sd(k + 1, j, i) - 2 * u0 + U.sd(k - 1, j, i)) * ihz * ihz;
-    const double r = -hat(in.un, in.unm1, id) / dt + adv + ri * jgu + gpn * ir0 + (ri - ir0) * gps +
-                     c.nu_m * lap - inv_re * ri * pol - inv_re * ri * vis - c.k_sigma * ri * cap - ax[0];
-    ru[id] = (T)r;
-  }
-  // ------------------------------------------------------------------ v at y face (i,j,k)
-  {
-    const double v0 = V.s(k, j, i);
-    const double vcu = 0.5 * (v0 + V.s(k, j + 1, i)), vcl = 0.5 * (V.s(k, j - 1, i) + v0);
-    double adv = (vcu * vcu - vcl * vcl) * ihy;
-    const double fxp = 0.5 * (U.s(k, j, i) + U.s(k, j + 1, i)) * 0.5 * (v0 + V.s(k, j, i + 1));
-    const double fxm = 0.5 * (U.s(k, j, i - 1) + U.s(k, j + 1, i - 1)) * 0.5 * (V.s(k, j, i - 1) + v0);
-    adv += (fxp - fxm) * ihx;
-    const double fzp = 0.5 * (W.sw(k, j, i) + W.sw(k, j + 1, i)) * 0.5 * (v0 + V.sd(k + 1, j, i));
-    const double fzm = 0.5 * (W.sw(k - 1, j, i) + W.sw(k - 1, j + 1, i)) * 0.5 * (V.sd(k - 1, j, i) + v0);
-    adv += (fzp - fzm) * ihz;
-    double Ja[3], Jb[3];
-    Jc(k, j, i, Ja);
-    Jc(k, j + 1, i, Jb);
-    const double jgv = 0.5 * (Ja[0] + Jb[0]) * (V.s(k, j, i + 1) - V.s(k, j, i - 1)) * 0.5 * ihx +
-                       0.5 * (Ja[1] + Jb[1]) * (V.s(k, j + 1, i) - V.s(k, j - 1, i)) * 0.5 * ihy +
-                       0.5 * (Ja[2] + Jb[2]) * (V.sd(k + 1, j, i) - V.sd(k - 1, j, i)) * 0.5 * ihz;
-    double vis = (2 * muc.at(k, j + 1, i) * (V.s(k, j + 1, i) - v0) * ihy -
-                  2 * muc.at(k, j, i) * (v0 - V.s(k, j - 1, i)) * ihy) * ihy;
-    const double sxyp = muxy.at(k, j, i) * ((U.s(k, j + 1, i) - U.s(k, j, i)) * ihy + (V.s(k, j, i + 1) - v0) * ihx);
-    const double sxym = muxy.at(k, j, i - 1) * ((U.s(k, j + 1, i - 1) - U.s(k, j, i - 1)) * ihy + (v0 - V.s(k, j, i - 1)) * ihx);
-    vis += (sxyp - sxym) * ihx;
-    const double syzp = muyz.at(k + 1, j, i) * ((V.sd(k + 1, j, i) - v0) * ihz + (W.sw(k, j + 1, i) - W.sw(k, j, i)) * ihy);
-    const double syzm = muyz.at(k, j, i) * ((v0 - V.sd(k - 1, j, i)) * ihz + (W.sw(k - 1, j + 1, i) - W.sw(k - 1, j, i)) * ihy);
-    vis += (syzp - syzm) * ihz;
-    double pol = 0;
-    if (ve) {
-      auto txy = [&](int ii) {
-        return 0.25 * (Tp(3, k, j, ii) + Tp(3, k, j, ii + 1) + Tp(3, k, j + 1, ii) + Tp(3, k, j + 1, ii + 1));
-      };
-      pol = (txy(i) - txy(i - 1)) * ihx;
-      pol += (Tp(1, k, j + 1, i) - Tp(1, k, j, i)) * ihy;
-      auto tyz = [&](int kk) {
-        return 0.25 * (Tp(5, kk, j, i) + Tp(5, kk, j + 1, i) + Tp(5, kk + 1, j, i) + Tp(5, kk + 1, j + 1, i));
-      };
-      pol += (tyz(k) - tyz(k - 1)) * ihz;
-    }
-    const double ri = (double)R.ri_y[id];
-    const double gpn = (Pn.n(k, j + 1, i) - Pn.n(k, j, i)) * ihy;
-    const double gps = (P.s(k, j + 1, i) - P.s(k, j, i)) * ihy;
-    const double cap = (double)R.G_y[id] * (phic.at(k, j + 1, i) - phic.at(k, j, i)) * ihy;
-    const double lap = (V.s(k, j, i + 1) - 2 * v0 + V.s(k, j, i - 1)) * ihx * ihx +
-                       (V.s(k, j + 1, i) - 2 * v0 + V.s(k, j - 1, i)) * ihy * ihy +
-                       (V.sd(k + 1, j, i) - 2 * v0 + V.sd(k - 1, j, i)) * ihz * ihz;
-    const double r = -hat(in.vn, in.vnm1, id) / dt + adv + ri * jgv + gpn * ir0 + (ri - ir0) * gps +
-                     c.nu_m * lap - inv_re * ri * pol - inv_re * ri * vis - c.k_sigma * ri * cap - ax[1];
-    rv[id] = (T)r;
-  }
-  // ------------------------------------------------------------------ w at z face (i,j,k)
-  if (k == nz - 1) {
-    rw[id] = (T)0;
+  MomCtx<T> m{{in.un, in.unm1, nx, ny, nz, f},
+              {in.vn, in.vnm1, nx, ny, nz, f},
+              {in.wn, in.wnm1, nx, ny, nz, f},
+              {in.pn, in.pnm1, nx, ny, nz, f},
+              {in.pn, nullptr, nx, ny, nz, 1},
+              {R.G_c, nx, ny, nz},
+              {R.phi_c, nx, ny, nz},
+              {R.mu_c, nx, ny, nz},
+              {R.mu_xy, nx, ny, nz},
+              {R.mu_xz, nx, ny},
+              {R.mu_yz, nx, ny},
+              in.taun,
+              in.taunm1,
+              R,
+              nx, ny, nz, f, in.viscoelastic,
+              ihx, ihy, ihz,
+              (T)c.inv_dt, (T)c.inv_re, (T)c.inv_rho0, (T)c.nu_m, (T)c.k_sigma, (T)c.c_j};
+  const size_t id = ((size_t)k * ny + j) * nx + i;
+  if (comp == 0) {
+    ru[id] = mom_u(m, k, j, i, id, (T)c.ax);
+  } else if (comp == 1) {
+    rv[id] = mom_v(m, k, j, i, id, (T)c.ay);
   } else {
-    const double w0 = W.sw(k, j, i);
-    const double wcu = 0.5 * (w0 + W.sw(k + 1, j, i)), wcl = 0.5 * (W.sw(k - 1, j, i) + w0);
-    double adv = (wcu * wcu - wcl * wcl) * ihz;
-    const double fxp = 0.5 * (U.s(k, j, i) + U.s(k + 1, j, i)) * 0.5 * (w0 + W.sw(k, j, i + 1));
-    const double fxm = 0.5 * (U.s(k, j, i - 1) + U.s(k + 1, j, i - 1)) * 0.5 * (W.sw(k, j, i - 1) + w0);
-    adv += (fxp - fxm) * ihx;
-    const double fyp = 0.5 * (V.s(k, j, i) + V.s(k + 1, j, i)) * 0.5 * (w0 + W.sw(k, j + 1, i));
-    const double fym = 0.5 * (V.s(k, j - 1, i) + V.s(k + 1, j - 1, i)) * 0.5 * (W.sw(k, j - 1, i) + w0);
-    adv += (fyp - fym) * ihy;
-    double Ja[3], Jb[3];
-    Jc(k, j, i, Ja);
-    Jc(k + 1, j, i, Jb);
-    const double jgw = 0.5 * (Ja[0] + Jb[0]) * (W.sw(k, j, i + 1) - W.sw(k, j, i - 1)) * 0.5 * ihx +
-                       0.5 * (Ja[1] + Jb[1]) * (W.sw(k, j + 1, i) - W.sw(k, j - 1, i)) * 0.5 * ihy +
-                       0.5 * (Ja[2] + Jb[2]) * (W.sw(k + 1, j, i) - W.sw(k - 1, j, i)) * 0.5 * ihz;
-    double vis = (2 * muc.at(k + 1, j, i) * (W.sw(k + 1, j, i) - w0) * ihz -
-                  2 * muc.at(k, j, i) * (w0 - W.sw(k - 1, j, i)) * ihz) * ihz;
-    const double sxzp = muxz.at(k + 1, j, i) * ((W.sw(k, j, i + 1) - w0) * ihx + (U.s(k + 1, j, i) - U.s(k, j, i)) * ihz);
-    const double sxzm = muxz.at(k + 1, j, i - 1) * ((w0 - W.sw(k, j, i - 1)) * ihx + (U.s(k + 1, j, i - 1) - U.s(k, j, i - 1)) * ihz);
-    vis += (sxzp - sxzm) * ihx;
-    const double syzp = muyz.at(k + 1, j, i) * ((W.sw(k, j + 1, i) - w0) * ihy + (V.s(k + 1, j, i) - V.s(k, j, i)) * ihz);
-    const double syzm = muyz.at(k + 1, j - 1, i) * ((w0 - W.sw(k, j - 1, i)) * ihy + (V.s(k + 1, j - 1, i) - V.s(k, j - 1, i)) * ihz);
-    vis += (syzp - syzm) * ihy;
-    double pol = 0;
-    if (ve) {
-      auto txz = [&](int ii) {  // xz edge at z face k between x centres ii and ii+1
-        return 0.25 * (Tp(4, k, j, ii) + Tp(4, k, j, ii + 1) + Tp(4, k + 1, j, ii) + Tp(4, k + 1, j, ii + 1));
-      };
-      auto tyz = [&](int jj) {
-        return 0.25 * (Tp(5, k, jj, i) + Tp(5, k, jj + 1, i) + Tp(5, k + 1, jj, i) + Tp(5, k + 1, jj + 1, i));
-      };
-      pol = (txz(i) - txz(i - 1)) * ihx + (tyz(j) - tyz(j - 1)) * ihy +
-            (Tp(2, k + 1, j, i) - Tp(2, k, j, i)) * ihz;
-    }
-    const double ri = (double)R.ri_z[id];
-    const double gpn = (Pn.n(k + 1, j, i) - Pn.n(k, j, i)) * ihz;
-    const double gps = (P.s(k + 1, j, i) - P.s(k, j, i)) * ihz;
-    const double cap = (double)R.G_z[id] * (phic.at(k + 1, j, i) - phic.at(k, j, i)) * ihz;
-    const double lap = (W.sw(k, j, i + 1) - 2 * w0 + W.sw(k, j, i - 1)) * ihx * ihx +
-                       (W.sw(k, j + 1, i) - 2 * w0 + W.sw(k, j - 1, i)) * ihy * ihy +
-                       (W.sw(k + 1, j, i) - 2 * w0 + W.sw(k - 1, j, i)) * ihz * ihz;
-    const double r = -hat(in.wn, in.wnm1, id) / dt + adv + ri * jgw + gpn * ir0 + (ri - ir0) * gps +
-                     c.nu_m * lap - inv_re * ri * pol - inv_re * ri * vis - c.k_sigma * ri * cap - ax[2];
-    rw[id] = (T)r;
+    rw[id] = k == nz - 1 ? (T)0 : mom_w(m, k, j, i, id, (T)c.az);
   }
 }
 
 // tau component index of the pair (a, b): xx, yy, zz, xy, xz, yz
 __device__ __forceinline__ int tidx(int a, int b) {
   if (a == b) return a;
-  const int s = a + b;  // 1: xy, 2: xz, 3: yz
-  return 2 + s;
+  return 2 + a + b;  // 1: xy, 2: xz, 3: yz
 }
 
 template <typename T>
@@ -289,63 +309,61 @@ struct TauOut {
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_polymer_stage(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
-                    TauSet<T> tn, TauSet<T> tin, TauOut<T> tout, int nx, int ny, int nz, double hx,
-                    double hy, double hz, double dt, double wi, double beta, double c0, double c1) {
-  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t n = (size_t)nx * ny * nz;
-  if (id >= n) return;
-  const int i = (int)(id % nx);
-  const int j = (int)((id / nx) % ny);
-  const int k = (int)(id / ((size_t)nx * ny));
+                    TauSet<T> tn, TauSet<T> tin, TauOut<T> tout, int nx, int ny, int nz, T ihx,
+                    T ihy, T ihz, T dt, T inv_wi, T one_m_beta, T c0, T c1) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  const size_t id = ((size_t)k * ny + j) * nx + i;
   const Coarse<T> U{u, nx, ny, nz}, V{v, nx, ny, nz}, Wf{w, nx, ny, nz};
-  const double ihx = 1.0 / hx, ihy = 1.0 / hy, ihz = 1.0 / hz;
-  auto wv = [&](int kk, int jj, int ii) -> double {
-    return (kk < 0 || kk >= nz - 1) ? 0.0 : Wf.at(kk, jj, ii);
+  const T h = (T)0.5;
+  auto wv = [&](int kk, int jj, int ii) -> T { return (kk < 0 || kk >= nz - 1) ? (T)0 : Wf.at(kk, jj, ii); };
+  // cell-centred velocities, no-slip ghosts (negated) beyond the walls
+  auto uc = [&](int kk, int jj, int ii) -> T {
+    const int kc = min(max(kk, 0), nz - 1);
+    const T val = h * (U.at(kc, jj, ii) + U.at(kc, jj, ii - 1));
+    return kk == kc ? val : -val;
   };
-  // cell-centred velocities
-  auto uc = [&](int kk, int jj, int ii) -> double {
-    if (kk < 0) return -0.5 * (U.at(0, jj, ii) + U.at(0, jj, ii - 1));
-    if (kk >= nz) return -0.5 * (U.at(nz - 1, jj, ii) + U.at(nz - 1, jj, ii - 1));
-    return 0.5 * (U.at(kk, jj, ii) + U.at(kk, jj, ii - 1));
+  auto vc = [&](int kk, int jj, int ii) -> T {
+    const int kc = min(max(kk, 0), nz - 1);
+    const T val = h * (V.at(kc, jj, ii) + V.at(kc, jj - 1, ii));
+    return kk == kc ? val : -val;
   };
-  auto vc = [&](int kk, int jj, int ii) -> double {
-    if (kk < 0) return -0.5 * (V.at(0, jj, ii) + V.at(0, jj - 1, ii));
-    if (kk >= nz) return -0.5 * (V.at(nz - 1, jj, ii) + V.at(nz - 1, jj - 1, ii));
-    return 0.5 * (V.at(kk, jj, ii) + V.at(kk, jj - 1, ii));
-  };
-  auto wc = [&](int kk, int jj, int ii) -> double { return 0.5 * (wv(kk, jj, ii) + wv(kk - 1, jj, ii)); };
+  auto wc = [&](int kk, int jj, int ii) -> T { return h * (wv(kk, jj, ii) + wv(kk - 1, jj, ii)); };
   // L[a][b] = d u_b / d x_a
-  double L[3][3];
-  L[0][0] = (U.at(k, j, i) - U.at(k, j, i - 1)) * ihx;
-  L[1][1] = (V.at(k, j, i) - V.at(k, j - 1, i)) * ihy;
-  L[2][2] = (wv(k, j, i) - wv(k - 1, j, i)) * ihz;
-  L[0][1] = (vc(k, j, i + 1) - vc(k, j, i - 1)) * 0.5 * ihx;
-  L[0][2] = (wc(k, j, i + 1) - wc(k, j, i - 1)) * 0.5 * ihx;
-  L[1][0] = (uc(k, j + 1, i) - uc(k, j - 1, i)) * 0.5 * ihy;
-  L[1][2] = (wc(k, j + 1, i) - wc(k, j - 1, i)) * 0.5 * ihy;
-  L[2][0] = (uc(k + 1, j, i) - uc(k - 1, j, i)) * 0.5 * ihz;
-  L[2][1] = (vc(k + 1, j, i) - vc(k - 1, j, i)) * 0.5 * ihz;
-  double tau[6];
-  for (int m = 0; m < 6; ++m) tau[m] = (double)tin.p[m][id];
-  const double uxp = U.at(k, j, i), uxm = U.at(k, j, i - 1);
-  const double vyp = V.at(k, j, i), vym = V.at(k, j - 1, i);
-  const double wzp = wv(k, j, i), wzm = wv(k - 1, j, i);
+  T L[3][3];
+  const T uxp = U.at(k, j, i), uxm = U.at(k, j, i - 1);
+  const T vyp = V.at(k, j, i), vym = V.at(k, j - 1, i);
+  const T wzp = wv(k, j, i), wzm = wv(k - 1, j, i);
+  L[0][0] = (uxp - uxm) * ihx;
+  L[1][1] = (vyp - vym) * ihy;
+  L[2][2] = (wzp - wzm) * ihz;
+  L[0][1] = (vc(k, j, i + 1) - vc(k, j, i - 1)) * h * ihx;
+  L[0][2] = (wc(k, j, i + 1) - wc(k, j, i - 1)) * h * ihx;
+  L[1][0] = (uc(k, j + 1, i) - uc(k, j - 1, i)) * h * ihy;
+  L[1][2] = (wc(k, j + 1, i) - wc(k, j - 1, i)) * h * ihy;
+  L[2][0] = (uc(k + 1, j, i) - uc(k - 1, j, i)) * h * ihz;
+  L[2][1] = (vc(k + 1, j, i) - vc(k - 1, j, i)) * h * ihz;
+  T tau[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) tau[m] = tin.p[m][id];
   const int pairs[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+#pragma unroll
   for (int m = 0; m < 6; ++m) {
     const int a = pairs[m][0], b = pairs[m][1];
     const Coarse<T> t{tin.p[m], nx, ny, nz};
-    const double t0 = tau[m];
-    const double fxp = uxp * 0.5 * (t0 + t.at(k, j, i + 1));
-    const double fxm = uxm * 0.5 * (t.at(k, j, i - 1) + t0);
-    const double fyp = vyp * 0.5 * (t0 + t.at(k, j + 1, i));
-    const double fym = vym * 0.5 * (t.at(k, j - 1, i) + t0);
-    const double fzp = k < nz - 1 ? wzp * 0.5 * (t0 + t.at(k + 1, j, i)) : 0.0;
-    const double fzm = k > 0 ? wzm * 0.5 * (t.at(k - 1, j, i) + t0) : 0.0;
-    double rh = -((fxp - fxm) * ihx + (fyp - fym) * ihy + (fzp - fzm) * ihz);
+    const T t0 = tau[m];
+    const T fxp = uxp * h * (t0 + t.at(k, j, i + 1));
+    const T fxm = uxm * h * (t.at(k, j, i - 1) + t0);
+    const T fyp = vyp * h * (t0 + t.at(k, j + 1, i));
+    const T fym = vym * h * (t.at(k, j - 1, i) + t0);
+    const T fzp = k < nz - 1 ? wzp * h * (t0 + t.at(k + 1, j, i)) : (T)0;
+    const T fzm = k > 0 ? wzm * h * (t.at(k - 1, j, i) + t0) : (T)0;
+    T rh = -((fxp - fxm) * ihx + (fyp - fym) * ihy + (fzp - fzm) * ihz);
+#pragma unroll
     for (int cc = 0; cc < 3; ++cc) rh += L[cc][a] * tau[tidx(cc, b)] + tau[tidx(a, cc)] * L[cc][b];
-    rh += ((1.0 - beta) * (L[a][b] + L[b][a]) - t0) / wi;
-    const double val = c0 * (double)tn.p[m][id] + c1 * (t0 + dt * rh);
-    tout.p[m][id] = (T)val;
+    rh += (one_m_beta * (L[a][b] + L[b][a]) - t0) * inv_wi;
+    tout.p[m][id] = c0 * tn.p[m][id] + c1 * (t0 + dt * rh);
   }
 }
 
@@ -354,9 +372,9 @@ __global__ void __launch_bounds__(kBlock)
 template <typename T>
 hipError_t launch_momentum_rhs(const Dims& c, const StepConsts& k, NsIn<T> in, Restricted<T> r,
                                T* ru, T* rv, T* rw, hipStream_t st) {
-  const size_t n = c.cells();
-  hipLaunchKernelGGL(k_momentum_rhs<T>, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                     st, in, r, ru, rv, rw, c.nx, c.ny, c.nz, c.hx, c.hy, c.hz, k);
+  const Launch3 L = launch3(c.nx, c.ny, 3 * c.nz);
+  hipLaunchKernelGGL(k_momentum_rhs<T>, L.grid, L.block, 0, st, in, r, ru, rv, rw, c.nx, c.ny, c.nz,
+                     (T)c.ihx, (T)c.ihy, (T)c.ihz, k);
   return hipGetLastError();
 }
 
@@ -371,10 +389,10 @@ hipError_t launch_polymer_stage(const Dims& c, const StepConsts& k, const T* u, 
     ti.p[m] = tau_in[m];
     to.p[m] = tau_out[m];
   }
-  const size_t n = c.cells();
-  hipLaunchKernelGGL(k_polymer_stage<T>, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                     st, u, v, w, tn, ti, to, c.nx, c.ny, c.nz, c.hx, c.hy, c.hz, k.dt, k.wi, k.beta,
-                     c0, c1);
+  const Launch3 L = launch3(c.nx, c.ny, c.nz);
+  hipLaunchKernelGGL(k_polymer_stage<T>, L.grid, L.block, 0, st, u, v, w, tn, ti, to, c.nx, c.ny, c.nz,
+                     (T)c.ihx, (T)c.ihy, (T)c.ihz, (T)k.dt, (T)k.inv_wi, (T)(1.0 - k.beta), (T)c0,
+                     (T)c1);
   return hipGetLastError();
 }
 

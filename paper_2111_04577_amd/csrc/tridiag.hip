@@ -1,18 +1,21 @@
 // Wall-normal pass of the constant-coefficient solver: after the x and y transforms every
 // Fourier mode (kx, ky) leaves a tridiagonal system across the walls,
-//   (a x_{k-1} + (lam_xy - 2a) x_k + a x_{k+1}) * coeff - shift x_k = d_k,
+//   a x_{k-1} + b_k x_k + a x_{k+1} = d_k,   b_k = coeff * (lam_x + lam_y) - 2a - shift,
 // whose end rows carry the wall rule (Neumann ghost = adjacent, no-slip ghost = -adjacent,
-// or the z-face form with zero wall values). One thread owns one mode and runs the Thomas
-// elimination down the z column; consecutive threads own consecutive kx, so each z step of
-// a wavefront is one contiguous load. Elimination factors go to a per-mode scratch column.
+// or the z-face form with zero wall values). The systems are solved by parallel cyclic
+// reduction (PCR) in LDS: a block holds a tile of TL consecutive modes, one thread per
+// (row, mode); the rows of a z level are contiguous in memory, so the tile is loaded and
+// stored with coalesced accesses. Each of the log2(n) PCR steps eliminates the couplings
+// at distance s from every row at once; the reciprocal of every diagonal is kept beside it
+// so that a step costs one division per row.
 //
 // Passes:
 //   zpass_ch  -- the two Helmholtz operators of the Dong splitting (eqs. NS26-NS27),
 //                (L - c_psi) then (L + alpha), applied back to back per mode.
-//   zpass_ns  -- the three velocity Helmholtz solves of eq. NS36, the divergence of the
-//                predicted velocity, the pressure-increment Poisson solve of eq. NS37 in
-//                FP64 with the (0,0) mode pinned and its mean removed, and the correction
-//                of eqs. NS38 (all per mode, in spectral x/y space).
+//   zpass_ns  -- the velocity Helmholtz solves of eq. NS36, the divergence of the predicted
+//                velocity, the pressure-increment Poisson solve of eq. NS37 in FP64 with the
+//                (0,0) mode pinned and its mean removed, and the correction of eq. NS38
+//                (all per mode, in spectral x/y space).
 //   zpass_helmholtz -- one generic solve (the drpf_helmholtz_solve entry point).
 #include "kernels.hpp"
 
@@ -20,223 +23,272 @@ namespace drpf {
 
 namespace {
 
-constexpr int kZBlock = 128;
+// LDS scratch of one PCR: per (row, line) the off-diagonals a, c, the reciprocal of the
+// diagonal, and NR complex right-hand sides. Row-major [row][line].
+template <typename A, int NR>
+struct PcrLds {
+  A* a;
+  A* c;
+  A* ib;
+  cx<A>* d;  // NR planes of n * TL
+};
 
-// Thomas elimination in place on a strided complex column. Arithmetic in A (double for the
-// FP64 islands), storage in T. Rows: b0 (first), bi (interior), bn (last), off-diagonal a.
-// Pivot factors c'_k go to piv[k * pstride]. `scale` multiplies the right-hand side.
-template <typename T, typename A>
-__device__ __forceinline__ void thomas(cx<T>* x, size_t stride, int n, A a, A b0, A bi, A bn,
-                                       A* piv, size_t pstride, A scale) {
-  A cp = 0;
-  cx<A> dp = mk<A>(0, 0);
-  for (int k = 0; k < n; ++k) {
-    const A b = k == 0 ? b0 : (k == n - 1 ? bn : bi);
-    const A inv = (A)1 / (b - a * cp);
-    cx<A> d = widen<A>(x[k * stride]);
-    d = mk<A>(scale * d.re - a * dp.re, scale * d.im - a * dp.im);
-    dp = inv * d;
-    cp = a * inv;
-    piv[k * pstride] = cp;
-    x[k * stride] = mk<T>((T)dp.re, (T)dp.im);
-  }
-  cx<A> xn = dp;
-  for (int k = n - 2; k >= 0; --k) {
-    const cx<A> dk = widen<A>(x[k * stride]);
-    const A c = piv[k * pstride];
-    xn = mk<A>(dk.re - c * xn.re, dk.im - c * xn.im);
-    x[k * stride] = mk<T>((T)xn.re, (T)xn.im);
-  }
-}
-
-// Same elimination on a column kept in double precision registers via a double scratch
-// column `col` (used by the FP64 Poisson island so that FP32 storage never rounds the
-// intermediate elimination values).
-__device__ __forceinline__ void thomas_d(double* colre, double* colim, size_t cstride, int n,
-                                         double a, double b0, double bi, double bn, double* piv,
-                                         size_t pstride) {
-  double cp = 0, dre = 0, dim = 0;
-  for (int k = 0; k < n; ++k) {
-    const double b = k == 0 ? b0 : (k == n - 1 ? bn : bi);
-    const double inv = 1.0 / (b - a * cp);
-    dre = (colre[k * cstride] - a * dre) * inv;
-    dim = (colim[k * cstride] - a * dim) * inv;
-    cp = a * inv;
-    piv[k * pstride] = cp;
-    colre[k * cstride] = dre;
-    colim[k * cstride] = dim;
-  }
-  for (int k = n - 2; k >= 0; --k) {
-    const double c = piv[k * pstride];
-    dre = colre[k * cstride] - c * dre;
-    dim = colim[k * cstride] - c * dim;
-    colre[k * cstride] = dre;
-    colim[k * cstride] = dim;
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kZBlock)
-    k_zpass_helmholtz(cx<T>* __restrict__ S, double* __restrict__ piv, int P, int Ny, int Nz,
-                      const double* __restrict__ lamx, const double* __restrict__ lamy, double hz,
-                      int bc, double coeff, double shift, double scale) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lines = P * Ny;
-  if (l >= lines) return;
-  const int ky = l / P;
-  const int kx = l - ky * P;
-  const size_t stride = (size_t)lines;
-  const double a = coeff / (hz * hz);
-  const double dxy = coeff * (lamx[kx] + lamy[ky]) - shift;
-  cx<T>* col = S + l;
-  double* pv = piv + l;
-  if (bc == 0) {
-    if (shift == 0.0 && kx == 0 && ky == 0) {
-      // singular Neumann Poisson mode: pin x_0 = 0, solve rows 1..Nz-1, remove the mean
-      col[0] = mk<T>(0, 0);
-      thomas<T, double>(col + stride, stride, Nz - 1, a, dxy - 2 * a, dxy - 2 * a, dxy - a,
-                        pv + stride, stride, scale);
-      double mre = 0, mim = 0;
-      for (int k = 0; k < Nz; ++k) {
-        mre += (double)col[k * stride].re;
-        mim += (double)col[k * stride].im;
-      }
-      mre /= Nz;
-      mim /= Nz;
-      for (int k = 0; k < Nz; ++k) {
-        const cx<T> v = col[k * stride];
-        col[k * stride] = mk<T>((T)((double)v.re - mre), (T)((double)v.im - mim));
-      }
+// One PCR solve for the calling thread's row. On entry (a, b, c, d[NR]) hold the thread's
+// row (a = 0 on the first row, c = 0 on the last); on exit d[r] holds x_row. Every thread of
+// the block must call this with the same n.
+template <typename A, int NR>
+__device__ __forceinline__ void pcr(PcrLds<A, NR> L, int n, int TL, int row, int line, A a, A b,
+                                    A c, cx<A>* d) {
+  A ib = (A)1 / b;
+  const int me = row * TL + line;
+  const int plane = n * TL;
+  for (int s = 1; s < n; s <<= 1) {
+    L.a[me] = a;
+    L.c[me] = c;
+    L.ib[me] = ib;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) L.d[r * plane + me] = d[r];
+    __syncthreads();
+    A alpha = 0, gamma = 0, cm = 0, ap = 0, am = 0, cp = 0;
+    cx<A> dm[NR], dp[NR];
+    if (row - s >= 0) {
+      const int m = me - s * TL;
+      alpha = -a * L.ib[m];
+      am = L.a[m];
+      cm = L.c[m];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) dm[r] = L.d[r * plane + m];
     } else {
-      thomas<T, double>(col, stride, Nz, a, dxy - a, dxy - 2 * a, dxy - a, pv, stride, scale);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) dm[r] = mk<A>(0, 0);
     }
+    if (row + s < n) {
+      const int p = me + s * TL;
+      gamma = -c * L.ib[p];
+      ap = L.a[p];
+      cp = L.c[p];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) dp[r] = L.d[r * plane + p];
+    } else {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) dp[r] = mk<A>(0, 0);
+    }
+    b = b + alpha * cm + gamma * ap;
+    a = alpha * am;
+    c = gamma * cp;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      d[r] = mk<A>(d[r].re + alpha * dm[r].re + gamma * dp[r].re,
+                   d[r].im + alpha * dm[r].im + gamma * dp[r].im);
+    ib = (A)1 / b;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) d[r] = ib * d[r];
+}
+
+template <typename A, int NR>
+__device__ __forceinline__ PcrLds<A, NR> carve(unsigned char* base, int n, int TL) {
+  PcrLds<A, NR> L;
+  const size_t plane = (size_t)n * TL;
+  L.a = reinterpret_cast<A*>(base);
+  L.c = L.a + plane;
+  L.ib = L.c + plane;
+  L.d = reinterpret_cast<cx<A>*>(L.ib + plane);
+  return L;
+}
+
+template <typename A, int NR>
+size_t pcr_bytes(int n, int TL) {
+  return (size_t)n * TL * (3 * sizeof(A) + NR * sizeof(cx<A>));
+}
+
+int tile_lines(int n) { return n >= 1024 ? 1 : 1024 / n; }
+
+// ---- generic Helmholtz (drpf_helmholtz_solve) ---------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(1024)
+    k_zpass_helmholtz(cx<T>* __restrict__ S, int P, int Ny, int Nz, const double* __restrict__ lamx,
+                      const double* __restrict__ lamy, double ihz2, int bc, double coeff,
+                      double shift, double scale) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int TL = blockDim.x / Nz;
+  const int line = threadIdx.x % TL;
+  const int row = threadIdx.x / TL;
+  const int lines = P * Ny;
+  const int l = blockIdx.x * TL + line;
+  const bool valid = l < lines;
+  const int lc = valid ? l : lines - 1;
+  const int ky = lc / P, kx = lc - ky * P;
+  const size_t stride = (size_t)lines;
+  const double a = coeff * ihz2;
+  const double dxy = coeff * (lamx[kx] + lamy[ky]) - shift;
+  const bool pinned = bc == 0 && shift == 0.0 && kx == 0 && ky == 0;
+  const int n = bc == 2 ? Nz - 1 : Nz;
+  double ar = row == 0 ? 0.0 : a, cr = row == Nz - 1 ? 0.0 : a, br = dxy - 2 * a;
+  if (bc == 0) {
+    if (row == 0 || row == Nz - 1) br = dxy - a;
   } else if (bc == 1) {
-    thomas<T, double>(col, stride, Nz, a, dxy - 3 * a, dxy - 2 * a, dxy - 3 * a, pv, stride, scale);
+    if (row == 0 || row == Nz - 1) br = dxy - 3 * a;
   } else {
-    thomas<T, double>(col, stride, Nz - 1, a, dxy - 2 * a, dxy - 2 * a, dxy - 2 * a, pv, stride,
-                      scale);
-    col[(Nz - 1) * stride] = mk<T>(0, 0);
+    if (row == Nz - 2) cr = 0.0;
+    if (row == Nz - 1) { ar = 0.0; br = 1.0; }
   }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kZBlock)
-    k_zpass_ch(cx<T>* __restrict__ S, T* __restrict__ piv, int P, int Ny, int Nz,
-               const double* __restrict__ lamx, const double* __restrict__ lamy, double hz,
-               double c_psi, double alpha, double scale) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lines = P * Ny;
-  if (l >= lines) return;
-  const int ky = l / P;
-  const int kx = l - ky * P;
-  const size_t stride = (size_t)lines;
-  const T a = (T)(1.0 / (hz * hz));
-  const double lxy = lamx[kx] + lamy[ky];
-  cx<T>* col = S + l;
-  T* pv = piv + l;
-  // (L_N - c_psi) Psi' = R
-  {
-    const T bi = (T)(lxy - 2.0 / (hz * hz) - c_psi);
-    const T be = (T)(lxy - 1.0 / (hz * hz) - c_psi);
-    thomas<T, T>(col, stride, Nz, a, be, bi, be, pv, stride, (T)scale);
+  cx<double> d[1];
+  d[0] = valid ? widen<double>(S[row * stride + l]) : mk<double>(0, 0);
+  d[0] = scale * d[0];
+  if (bc == 2 && row == Nz - 1) d[0] = mk<double>(0, 0);
+  if (pinned) {
+    if (row == 0) { ar = 0.0; cr = 0.0; br = 1.0; d[0] = mk<double>(0, 0); }
+    if (row == 1) ar = 0.0;
   }
-  // (L_N + alpha) phi = Psi'
-  {
-    const T bi = (T)(lxy - 2.0 / (hz * hz) + alpha);
-    const T be = (T)(lxy - 1.0 / (hz * hz) + alpha);
-    thomas<T, T>(col, stride, Nz, a, be, bi, be, pv, stride, (T)1);
-  }
-}
-
-// NS spectral pass. spec holds four fields of Nz*Ny*P complex each: r_u, r_v, r_w on entry
-// (fields 0-2); on exit u^{n+1}, v^{n+1}, w^{n+1} and the pressure increment p' (field 3).
-// pivd: double scratch with room for 3 columns (pivots, p' real and imaginary parts) per mode.
-template <typename T>
-__global__ void __launch_bounds__(kZBlock)
-    k_zpass_ns(cx<T>* __restrict__ spec, double* __restrict__ pivd, int P, int Ny, int Nz,
-               const double* __restrict__ lamx, const double* __restrict__ lamy,
-               const double* __restrict__ phx, const double* __restrict__ phy, double hx,
-               double hy, double hz, double nu_m, double g_dt, double g_rho_dt, double scale) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lines = P * Ny;
-  if (l >= lines) return;
-  const int ky = l / P;
-  const int kx = l - ky * P;
-  const size_t stride = (size_t)lines;
-  const size_t fsz = (size_t)lines * Nz;
-  cx<T>* U = spec + l;
-  cx<T>* V = spec + fsz + l;
-  cx<T>* W = spec + 2 * fsz + l;
-  cx<T>* Pp = spec + 3 * fsz + l;
-  double* piv = pivd + l;
-  double* pre = pivd + fsz + l;
-  double* pim = pivd + 2 * fsz + l;
-  const double lxy = lamx[kx] + lamy[ky];
-  // ---- velocity Helmholtz solves (nu_m L - gamma0/dt) u~ = r
-  const double a = nu_m / (hz * hz);
-  const double bi = nu_m * lxy - 2 * a - g_dt;
-  const double be = nu_m * lxy - 3 * a - g_dt;
-  thomas<T, double>(U, stride, Nz, a, be, bi, be, piv, stride, scale);
-  if (Ny > 1) thomas<T, double>(V, stride, Nz, a, be, bi, be, piv, stride, scale);
-  thomas<T, double>(W, stride, Nz - 1, a, bi, bi, bi, piv, stride, scale);
-  W[(Nz - 1) * stride] = mk<T>(0, 0);
-  // ---- divergence at centres, spectral in x/y: D_x = (1 - e^{-i th_x}) / hx
-  const double cxr = phx[2 * kx], cxi = phx[2 * kx + 1];
-  const double cyr = phy[2 * ky], cyi = phy[2 * ky + 1];
-  // 1 - e^{-i th} = (1 - cos th) + i sin th
-  const double dxr = (1.0 - cxr) / hx, dxi = cxi / hx;
-  const double dyr = (1.0 - cyr) / hy, dyi = cyi / hy;
-  double wre_prev = 0, wim_prev = 0;
-  for (int k = 0; k < Nz; ++k) {
-    const cx<double> u = widen<double>(U[k * stride]);
-    const cx<double> v = Ny > 1 ? widen<double>(V[k * stride]) : mk<double>(0, 0);
-    const cx<double> w = widen<double>(W[k * stride]);
-    double re = dxr * u.re - dxi * u.im + dyr * v.re - dyi * v.im + (w.re - wre_prev) / hz;
-    double im = dxr * u.im + dxi * u.re + dyr * v.im + dyi * v.re + (w.im - wim_prev) / hz;
-    wre_prev = w.re;
-    wim_prev = w.im;
-    pre[k * stride] = g_rho_dt * re;
-    pim[k * stride] = g_rho_dt * im;
-  }
-  // ---- FP64 Poisson (Neumann) for p'
-  const double ap = 1.0 / (hz * hz);
-  if (kx == 0 && ky == 0) {
-    pre[0] = 0;
-    pim[0] = 0;
-    thomas_d(pre + stride, pim + stride, stride, Nz - 1, ap, lxy - 2 * ap, lxy - 2 * ap, lxy - ap,
-             piv + stride, stride);
+  (void)n;
+  PcrLds<double, 1> L = carve<double, 1>(smem, Nz, TL);
+  pcr<double, 1>(L, Nz, TL, row, line, ar, br, cr, d);
+  // zero-mean of the pinned mode: every thread takes part in the barrier
+  L.d[row * TL + line] = d[0];
+  __syncthreads();
+  if (pinned) {
     double mre = 0, mim = 0;
     for (int k = 0; k < Nz; ++k) {
-      mre += pre[k * stride];
-      mim += pim[k * stride];
+      mre += L.d[k * TL + line].re;
+      mim += L.d[k * TL + line].im;
+    }
+    d[0] = mk<double>(d[0].re - mre / Nz, d[0].im - mim / Nz);
+  }
+  if (valid) S[row * stride + l] = mk<T>((T)d[0].re, (T)d[0].im);
+}
+
+// ---- Cahn-Hilliard pair -------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(1024)
+    k_zpass_ch(cx<T>* __restrict__ S, int P, int Ny, int Nz, const double* __restrict__ lamx,
+               const double* __restrict__ lamy, double ihz2, double c_psi, double alpha,
+               double scale) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int TL = blockDim.x / Nz;
+  const int line = threadIdx.x % TL;
+  const int row = threadIdx.x / TL;
+  const int lines = P * Ny;
+  const int l = blockIdx.x * TL + line;
+  const bool valid = l < lines;
+  const int lc = valid ? l : lines - 1;
+  const int ky = lc / P, kx = lc - ky * P;
+  const size_t stride = (size_t)lines;
+  const double lxy = lamx[kx] + lamy[ky];
+  const T a = (T)ihz2;
+  const T ar = row == 0 ? (T)0 : a, cr = row == Nz - 1 ? (T)0 : a;
+  const bool end = row == 0 || row == Nz - 1;
+  cx<T> d[1];
+  d[0] = valid ? S[row * stride + l] : mk<T>(0, 0);
+  d[0] = (T)scale * d[0];
+  PcrLds<T, 1> L = carve<T, 1>(smem, Nz, TL);
+  // (L_N - c_psi) Psi' = R
+  pcr<T, 1>(L, Nz, TL, row, line, ar, (T)(lxy - (end ? 1.0 : 2.0) * ihz2 - c_psi), cr, d);
+  // (L_N + alpha) phi = Psi'
+  pcr<T, 1>(L, Nz, TL, row, line, ar, (T)(lxy - (end ? 1.0 : 2.0) * ihz2 + alpha), cr, d);
+  if (valid) S[row * stride + l] = d[0];
+}
+
+// ---- Navier-Stokes projection -------------------------------------------------------
+// spec holds four fields of Nz*Ny*P complex each: r_u, r_v, r_w on entry (fields 0-2); on
+// exit u^{n+1}, v^{n+1}, w^{n+1} and the pressure increment p' (field 3).
+template <typename T>
+__global__ void __launch_bounds__(1024)
+    k_zpass_ns(cx<T>* __restrict__ spec, int P, int Ny, int Nz, const double* __restrict__ lamx,
+               const double* __restrict__ lamy, const double* __restrict__ phx,
+               const double* __restrict__ phy, double ihx, double ihy, double ihz, double nu_m,
+               double g_dt, double g_rho_dt, double scale) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int TL = blockDim.x / Nz;
+  const int line = threadIdx.x % TL;
+  const int row = threadIdx.x / TL;
+  const int lines = P * Ny;
+  const int l = blockIdx.x * TL + line;
+  const bool valid = l < lines;
+  const int lc = valid ? l : lines - 1;
+  const int ky = lc / P, kx = lc - ky * P;
+  const size_t stride = (size_t)lines;
+  const size_t fsz = stride * Nz;
+  const size_t at = row * stride + l;
+  const double lxy = lamx[kx] + lamy[ky];
+  const bool end = row == 0 || row == Nz - 1;
+  const T sc = (T)scale;
+  // ---- velocity Helmholtz (nu_m L - gamma0/dt) u~ = r, no-slip walls (u, v)
+  const double av = nu_m * ihz * ihz;
+  cx<T> uv[2];
+  uv[0] = valid ? sc * spec[at] : mk<T>(0, 0);
+  uv[1] = (valid && Ny > 1) ? sc * spec[fsz + at] : mk<T>(0, 0);
+  PcrLds<T, 2> L2 = carve<T, 2>(smem, Nz, TL);
+  pcr<T, 2>(L2, Nz, TL, row, line, row == 0 ? (T)0 : (T)av,
+            (T)(nu_m * lxy - (end ? 3.0 : 2.0) * av - g_dt), row == Nz - 1 ? (T)0 : (T)av, uv);
+  // w on z faces k = 0..Nz-2; the top-wall row is an identity row
+  cx<T> w[1];
+  w[0] = (valid && row < Nz - 1) ? sc * spec[2 * fsz + at] : mk<T>(0, 0);
+  PcrLds<T, 1> L1 = carve<T, 1>(smem, Nz, TL);
+  {
+    const T aw = (T)av;
+    const bool top = row == Nz - 1;
+    pcr<T, 1>(L1, Nz, TL, row, line, (row == 0 || top) ? (T)0 : aw,
+              top ? (T)1 : (T)(nu_m * lxy - 2.0 * av - g_dt), (row >= Nz - 2) ? (T)0 : aw, w);
+    if (top) w[0] = mk<T>(0, 0);
+  }
+  // ---- divergence at centres: D_x = (1 - e^{-i th_x}) / hx, D_z w = (w_k - w_{k-1}) / hz
+  cx<double>* Lw = reinterpret_cast<cx<double>*>(smem);
+  __syncthreads();
+  Lw[row * TL + line] = widen<double>(w[0]);
+  __syncthreads();
+  const double cxr = phx[2 * kx], cxi = phx[2 * kx + 1];
+  const double cyr = phy[2 * ky], cyi = phy[2 * ky + 1];
+  const double dxr = (1.0 - cxr) * ihx, dxi = cxi * ihx;
+  const double dyr = (1.0 - cyr) * ihy, dyi = cyi * ihy;
+  const cx<double> u = widen<double>(uv[0]), v = widen<double>(uv[1]);
+  const cx<double> wk = Lw[row * TL + line];
+  const cx<double> wm = row > 0 ? Lw[(row - 1) * TL + line] : mk<double>(0, 0);
+  cx<double> p[1];
+  p[0] = mk<double>(g_rho_dt * (dxr * u.re - dxi * u.im + dyr * v.re - dyi * v.im + (wk.re - wm.re) * ihz),
+                    g_rho_dt * (dxr * u.im + dxi * u.re + dyr * v.im + dyi * v.re + (wk.im - wm.im) * ihz));
+  __syncthreads();
+  // ---- FP64 Poisson (Neumann) for p'; the (0,0) mode is pinned at row 0, mean removed
+  const double ap = ihz * ihz;
+  const bool pinned = kx == 0 && ky == 0;
+  double pa = row == 0 ? 0.0 : ap, pc = row == Nz - 1 ? 0.0 : ap;
+  double pb = lxy - (end ? 1.0 : 2.0) * ap;
+  if (pinned) {
+    if (row == 0) { pa = 0.0; pc = 0.0; pb = 1.0; p[0] = mk<double>(0, 0); }
+    if (row == 1) pa = 0.0;
+  }
+  PcrLds<double, 1> LP = carve<double, 1>(smem, Nz, TL);
+  pcr<double, 1>(LP, Nz, TL, row, line, pa, pb, pc, p);
+  cx<double>* Lp = reinterpret_cast<cx<double>*>(smem);
+  Lp[row * TL + line] = p[0];
+  __syncthreads();
+  cx<double> pup = row < Nz - 1 ? Lp[(row + 1) * TL + line] : mk<double>(0, 0);
+  if (pinned) {
+    double mre = 0, mim = 0;
+    for (int k = 0; k < Nz; ++k) {
+      mre += Lp[k * TL + line].re;
+      mim += Lp[k * TL + line].im;
     }
     mre /= Nz;
     mim /= Nz;
-    for (int k = 0; k < Nz; ++k) {
-      pre[k * stride] -= mre;
-      pim[k * stride] -= mim;
-    }
-  } else {
-    thomas_d(pre, pim, stride, Nz, ap, lxy - ap, lxy - 2 * ap, lxy - ap, piv, stride);
+    p[0] = mk<double>(p[0].re - mre, p[0].im - mim);
+    pup = mk<double>(pup.re - mre, pup.im - mim);
   }
   // ---- correction u = u~ - c grad p', G_x = (e^{i th_x} - 1) / hx
   const double c = 1.0 / g_rho_dt;
-  const double gxr = (cxr - 1.0) / hx, gxi = cxi / hx;
-  const double gyr = (cyr - 1.0) / hy, gyi = cyi / hy;
-  for (int k = 0; k < Nz; ++k) {
-    const double pr = pre[k * stride], pi = pim[k * stride];
-    const cx<double> u = widen<double>(U[k * stride]);
-    U[k * stride] = mk<T>((T)(u.re - c * (gxr * pr - gxi * pi)), (T)(u.im - c * (gxr * pi + gxi * pr)));
-    if (Ny > 1) {
-      const cx<double> v = widen<double>(V[k * stride]);
-      V[k * stride] = mk<T>((T)(v.re - c * (gyr * pr - gyi * pi)), (T)(v.im - c * (gyr * pi + gyi * pr)));
-    }
-    if (k < Nz - 1) {
-      const double qr = pre[(k + 1) * stride], qi = pim[(k + 1) * stride];
-      const cx<double> w = widen<double>(W[k * stride]);
-      W[k * stride] = mk<T>((T)(w.re - c * (qr - pr) / hz), (T)(w.im - c * (qi - pi) / hz));
-    }
-    Pp[k * stride] = mk<T>((T)pr, (T)pi);
+  const double gxr = (cxr - 1.0) * ihx, gxi = cxi * ihx;
+  const double gyr = (cyr - 1.0) * ihy, gyi = cyi * ihy;
+  const double pr = p[0].re, pi = p[0].im;
+  if (valid) {
+    spec[at] = mk<T>((T)(u.re - c * (gxr * pr - gxi * pi)), (T)(u.im - c * (gxr * pi + gxi * pr)));
+    if (Ny > 1)
+      spec[fsz + at] = mk<T>((T)(v.re - c * (gyr * pr - gyi * pi)), (T)(v.im - c * (gyr * pi + gyi * pr)));
+    const cx<double> wv = wk;
+    spec[2 * fsz + at] = row < Nz - 1
+                             ? mk<T>((T)(wv.re - c * (pup.re - pr) * ihz), (T)(wv.im - c * (pup.im - pi) * ihz))
+                             : mk<T>(0, 0);
+    spec[3 * fsz + at] = mk<T>((T)pr, (T)pi);
   }
 }
 
@@ -245,9 +297,12 @@ __global__ void __launch_bounds__(kZBlock)
 template <typename T>
 hipError_t launch_zpass_helmholtz(const Dims& d, const Tables<T>& tb, cx<T>* spec, double* piv,
                                   int bc, double coeff, double shift, double scale, hipStream_t st) {
+  (void)piv;
+  const int TL = tile_lines(d.nz);
   const int lines = d.lines();
-  hipLaunchKernelGGL(k_zpass_helmholtz<T>, dim3((lines + kZBlock - 1) / kZBlock), dim3(kZBlock), 0,
-                     st, spec, piv, d.pitch, d.ny, d.nz, tb.lam_x, tb.lam_y, d.hz, bc, coeff, shift,
+  const size_t shm = pcr_bytes<double, 1>(d.nz, TL);
+  hipLaunchKernelGGL(k_zpass_helmholtz<T>, dim3((lines + TL - 1) / TL), dim3(TL * d.nz), shm, st, spec,
+                     d.pitch, d.ny, d.nz, tb.lam_x, tb.lam_y, 1.0 / (d.hz * d.hz), bc, coeff, shift,
                      scale);
   return hipGetLastError();
 }
@@ -255,20 +310,27 @@ hipError_t launch_zpass_helmholtz(const Dims& d, const Tables<T>& tb, cx<T>* spe
 template <typename T>
 hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, double* piv,
                            double c_psi, double alpha, double scale, hipStream_t st) {
+  (void)piv;
+  const int TL = tile_lines(d.nz);
   const int lines = d.lines();
-  hipLaunchKernelGGL(k_zpass_ch<T>, dim3((lines + kZBlock - 1) / kZBlock), dim3(kZBlock), 0, st,
-                     spec, reinterpret_cast<T*>(piv), d.pitch, d.ny, d.nz, tb.lam_x, tb.lam_y, d.hz,
-                     c_psi, alpha, scale);
+  const size_t shm = pcr_bytes<T, 1>(d.nz, TL);
+  hipLaunchKernelGGL(k_zpass_ch<T>, dim3((lines + TL - 1) / TL), dim3(TL * d.nz), shm, st, spec,
+                     d.pitch, d.ny, d.nz, tb.lam_x, tb.lam_y, 1.0 / (d.hz * d.hz), c_psi, alpha, scale);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_zpass_ns(const Dims& d, const Tables<T>& tb, cx<T>* spec4, double* piv,
                            const StepConsts& c, double scale, hipStream_t st) {
+  (void)piv;
+  const int TL = tile_lines(d.nz);
   const int lines = d.lines();
-  hipLaunchKernelGGL(k_zpass_ns<T>, dim3((lines + kZBlock - 1) / kZBlock), dim3(kZBlock), 0, st,
-                     spec4, piv, d.pitch, d.ny, d.nz, tb.lam_x, tb.lam_y, tb.ph_x, tb.ph_y, d.hx, d.hy,
-                     d.hz, c.nu_m, c.gamma0 / c.dt, c.gamma0 * c.rho0 / c.dt, scale);
+  size_t shm = pcr_bytes<T, 2>(d.nz, TL);
+  const size_t shm64 = pcr_bytes<double, 1>(d.nz, TL);
+  if (shm64 > shm) shm = shm64;
+  hipLaunchKernelGGL(k_zpass_ns<T>, dim3((lines + TL - 1) / TL), dim3(TL * d.nz), shm, st, spec4,
+                     d.pitch, d.ny, d.nz, tb.lam_x, tb.lam_y, tb.ph_x, tb.ph_y, 1.0 / d.hx, 1.0 / d.hy,
+                     1.0 / d.hz, c.nu_m, c.gamma0 / c.dt, c.gamma0 * c.rho0 / c.dt, scale);
   return hipGetLastError();
 }
 
