@@ -115,6 +115,21 @@ inline Launch3 launch3(int nx, int ny, int nz_blocks, int max_threads = 256) {
   return l;
 }
 
+// Logical tile of a block under XCD-aware ordering. The hardware hands out blocks
+// round-robin over the 8 XCDs of the chip (block b runs on XCD b % 8), and every XCD has
+// its own L2. With the grid linearised x-fastest, this sends consecutive tiles -- whose
+// halos overlap -- to different L2s. The remap gives XCD x the contiguous logical range
+// [x n/8, (x+1) n/8), i.e. its own slab of z layers, so halo re-reads hit its L2.
+__device__ __forceinline__ void xcd_tile(int& bx, int& by, int& bz) {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int nb = gx * gy * gridDim.z;
+  const int b = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+  const int t = (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+  bx = t % gx;
+  by = (t / gx) % gy;
+  bz = t / (gx * gy);
+}
+
 __host__ __device__ __forceinline__ int wrap(int i, int n) { return i & (n - 1); }
 
 }  // namespace drpf

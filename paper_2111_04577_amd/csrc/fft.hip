@@ -17,17 +17,28 @@ namespace {
 constexpr int kBlock = 256;
 
 // In-LDS complex FFT of `nlines` lines of length M (power of two, M >= 2). Element n of
-// line b lives at buf[b * bs + n * es]. Thread t < nlines * max(M/4, 1) owns butterfly set
-// q = t % (M/4) of line t / (M/4). Every thread of the block must call this (barriers).
-// Twiddle table tw[t] = exp(-2 pi i t / M); the inverse uses its conjugate.
-template <typename T, bool INV>
+// line b lives at buf[b * bs + n * es]. Thread t < nlines * max(M/4, 1) owns one butterfly
+// set q of one line b: with LF (line-fast, for column tiles with es = nlines) consecutive
+// lanes take consecutive lines, so a wavefront touches consecutive LDS words; otherwise
+// consecutive lanes take consecutive q of one line (row tiles with es = 1). Every thread of
+// the block must call this (barriers). Twiddles tw[t] = exp(-2 pi i t / M); the inverse
+// uses their conjugates.
+template <typename T, bool INV, bool LF>
 __device__ void lds_fft(cx<T>* buf, int M, int logM, int nlines, int bs, int es,
                         const cx<T>* __restrict__ tw) {
   const int quarter = M >= 4 ? (M >> 2) : 1;
   const int t = threadIdx.x;
   const bool active = t < nlines * quarter;
-  const int b = active ? t / quarter : 0;
-  const int q = active ? t - b * quarter : 0;
+  int b = 0, q = 0;
+  if (active) {
+    if (LF) {
+      q = t / nlines;
+      b = t - q * nlines;
+    } else {
+      b = t / quarter;
+      q = t - b * quarter;
+    }
+  }
   cx<T>* line = buf + b * bs;
   int Ns = 1;
   if (logM & 1) {
@@ -103,7 +114,7 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_fwd(const T* __restrict__ in0,
   const T* src = in + (size_t)(line0 - field * lines_per_field) * N;
   for (int e = threadIdx.x; e < nl * M; e += blockDim.x) buf[e] = mk<T>(src[2 * e], src[2 * e + 1]);
   __syncthreads();
-  lds_fft<T, false>(buf, M, logM, nl, M, 1, twM);
+  lds_fft<T, false, false>(buf, M, logM, nl, M, 1, twM);
   cx<T>* dst = out + (size_t)line0 * (M + 1);
   const T half = (T)0.5;
   for (int e = threadIdx.x; e < nl * (M + 1); e += blockDim.x) {
@@ -140,7 +151,7 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_inv(const cx<T>* __restrict__ 
     buf[e] = E + mul_i(O);
   }
   __syncthreads();
-  lds_fft<T, true>(buf, M, logM, nl, M, 1, twM);
+  lds_fft<T, true, false>(buf, M, logM, nl, M, 1, twM);
   const int field = line0 / lines_per_field;
   T* dst = out.p[field] + (size_t)(line0 - field * lines_per_field) * N;
   const T* add = out.add[field];
@@ -175,7 +186,7 @@ __global__ void k_fft_y(cx<T>* __restrict__ data, int Ny, int logNy, int P, int 
     buf[e] = kx < P ? base[(size_t)y * P + kx] : mk<T>(0, 0);
   }
   __syncthreads();
-  lds_fft<T, INV>(buf, Ny, logNy, tkx, 1, tkx, tw);
+  lds_fft<T, INV, true>(buf, Ny, logNy, tkx, 1, tkx, tw);
   for (int e = threadIdx.x; e < Ny * tkx; e += blockDim.x) {
     const int y = e / tkx;
     const int t = e - y * tkx;

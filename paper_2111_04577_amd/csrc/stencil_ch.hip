@@ -71,9 +71,11 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_ch_rhs(const T* __restrict__ phin, const T* __restrict__ phinm1, Prolonged<T> pv,
              T* __restrict__ out, int nx, int ny, int nz, T ihx, T ihy, T ihz, StepConsts c) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  const int J = blockIdx.y * blockDim.y + threadIdx.y;
-  const int K = blockIdx.z;
+  int bx, by, bz;
+  xcd_tile(bx, by, bz);
+  const int I = bx * blockDim.x + threadIdx.x;
+  const int J = by * blockDim.y + threadIdx.y;
+  const int K = bz;
   const FineView<T> A{phin, nx, ny, nz}, B{phinm1, nx, ny, nz};
   const bool first = c.first != 0;
   auto star = [&](int k, int j, int i) -> T {
@@ -135,14 +137,18 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_restrict_g(const T* __restrict__ phinew, const T* __restrict__ phin,
                  const T* __restrict__ phinm1, Restricted<T> r, int fnx, int fny, int fnz,
-                 T fihx, T fihy, T fihz, int cnx, int cny, int cnz, int ry, StepConsts c) {
+                 T fihx, T fihy, T fihz, int cnx, int cny, int cnz, int ry, int KZ,
+                 StepConsts c) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int CX = blockDim.x, CY = blockDim.y;
-  const int i0 = blockIdx.x * CX, j0 = blockIdx.y * CY, k = blockIdx.z;
-  // G region: fine x 2 i0 .. 2 i0 + 2 CX, y ry j0 .. ry j0 + ry CY, z 2k .. 2k+2 (clamped)
-  const int GX = 2 * CX + 1, GY = ry * CY + 1, GZ = 3;
-  const int PX = GX + 2, PY = GY + 2, PZ = 5;
-  const int X0 = 2 * i0, Y0 = ry * j0, Z0 = 2 * k;
+  int bx, by, bz;
+  xcd_tile(bx, by, bz);
+  const int i0 = bx * CX, j0 = by * CY, k0 = bz * KZ;
+  // G region: fine x 2 i0 .. 2 i0 + 2 CX, y ry j0 .. ry j0 + ry CY, z 2 k0 .. 2 k0 + 2 KZ
+  // (clamped to the top layer); phi^{n+1} tile one cell wider on every side.
+  const int GX = 2 * CX + 1, GY = ry * CY + 1, GZ = 2 * KZ + 1;
+  const int PX = GX + 2, PY = GY + 2, PZ = GZ + 2;
+  const int X0 = 2 * i0, Y0 = ry * j0, Z0 = 2 * k0;
   T* sP = reinterpret_cast<T*>(smem);  // phi^{n+1} on the halo tile, layers clamp(Z0 - 1 + pz)
   T* sG = sP + PX * PY * PZ;           // G on the G region
   const int tid = threadIdx.y * CX + threadIdx.x;
@@ -184,11 +190,14 @@ __global__ void __launch_bounds__(kBlock)
   __syncthreads();
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int i = i0 + tx, j = j0 + ty;
+  for (int kk = 0; kk < KZ; ++kk) {
+  const int k = k0 + kk;
   T phic = 0, Gc = 0, phx = 0, Gx = 0, phy = 0, Gy = 0, phz = 0, Gz = 0;
   T phxy = 0, phxz = 0, phyz = 0, phxz_b = 0, phyz_b = 0;
   const int ndy = ry + 1;
   for (int dz = 0; dz < 3; ++dz) {
-    const int K = min(Z0 + dz, fnz - 1);
+    const int gz = 2 * kk + dz;
+    const int K = min(Z0 + gz, fnz - 1);
     const int pz = pzi(K);
     const T zc = (T)wc(dz, 2), zf = (T)wf(dz, 2);
     for (int dy = 0; dy < ndy; ++dy) {
@@ -197,7 +206,7 @@ __global__ void __launch_bounds__(kBlock)
       for (int dx = 0; dx < 3; ++dx) {
         const int gx = 2 * tx + dx;
         const T p = P(pz, gy + 1, gx + 1);
-        const T G = sG[(dz * GY + gy) * GX + gx];
+        const T G = sG[(gz * GY + gy) * GX + gx];
         const T xc = (T)wc(dx, 2), xf = (T)wf(dx, 2);
         phic += xc * yc * zc * p;
         Gc += xc * yc * zc * G;
@@ -238,6 +247,7 @@ __global__ void __launch_bounds__(kBlock)
   if (k == 0) {
     r.mu_xz[id] = mu(phxz_b);
     r.mu_yz[id] = mu(phyz_b);
+  }
   }
 }
 
@@ -315,11 +325,14 @@ hipError_t launch_restrict_g(const Dims& f, const Dims& c, const StepConsts& k, 
     CX = c.nx < 128 ? c.nx : 128;
     CY = 1;
   }
-  const int GX = 2 * CX + 1, GY = ry * CY + 1;
-  const size_t shm = (size_t)((GX + 2) * (GY + 2) * 5 + GX * GY * 3) * sizeof(T);
-  hipLaunchKernelGGL(k_restrict_g<T>, dim3(c.nx / CX, c.ny / CY, c.nz), dim3(CX, CY, 1), shm, st,
+  // coarse layers per block (the kernel supports KZ > 1, which amortises the z halo, but on
+  // gfx950 the larger LDS tile lowers occupancy more than it saves: one layer measures best)
+  const int KZ = 1;
+  const int GX = 2 * CX + 1, GY = ry * CY + 1, GZ = 2 * KZ + 1;
+  const size_t shm = (size_t)((GX + 2) * (GY + 2) * (GZ + 2) + GX * GY * GZ) * sizeof(T);
+  hipLaunchKernelGGL(k_restrict_g<T>, dim3(c.nx / CX, c.ny / CY, c.nz / KZ), dim3(CX, CY, 1), shm, st,
                      phinew, phin, phinm1, r, f.nx, f.ny, f.nz, (T)f.ihx, (T)f.ihy, (T)f.ihz, c.nx,
-                     c.ny, c.nz, ry, k);
+                     c.ny, c.nz, ry, KZ, k);
   return hipGetLastError();
 }
 

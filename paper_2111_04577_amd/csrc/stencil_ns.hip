@@ -259,10 +259,12 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_momentum_rhs(NsIn<T> in, Restricted<T> R, T* __restrict__ ru, T* __restrict__ rv,
                    T* __restrict__ rw, int nx, int ny, int nz, T ihx, T ihy, T ihz, StepConsts c) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int comp = blockIdx.z / nz;
-  const int k = blockIdx.z - comp * nz;
+  int bx, by, bz;
+  xcd_tile(bx, by, bz);
+  const int i = bx * blockDim.x + threadIdx.x;
+  const int j = by * blockDim.y + threadIdx.y;
+  const int comp = bz / nz;
+  const int k = bz - comp * nz;
   const int f = c.first;
   MomCtx<T> m{{in.un, in.unm1, nx, ny, nz, f},
               {in.vn, in.vnm1, nx, ny, nz, f},
@@ -311,9 +313,11 @@ __global__ void __launch_bounds__(kBlock)
     k_polymer_stage(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
                     TauSet<T> tn, TauSet<T> tin, TauOut<T> tout, int nx, int ny, int nz, T ihx,
                     T ihy, T ihz, T dt, T inv_wi, T one_m_beta, T c0, T c1) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
+  int bx, by, bz;
+  xcd_tile(bx, by, bz);
+  const int i = bx * blockDim.x + threadIdx.x;
+  const int j = by * blockDim.y + threadIdx.y;
+  const int k = bz;
   const size_t id = ((size_t)k * ny + j) * nx + i;
   const Coarse<T> U{u, nx, ny, nz}, V{v, nx, ny, nz}, Wf{w, nx, ny, nz};
   const T h = (T)0.5;
