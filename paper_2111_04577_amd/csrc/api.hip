@@ -109,7 +109,7 @@ struct Carver {
 };
 
 struct TabOff {
-  size_t tw_xm, tw_xn, tw_y, lam_x, lam_y, ph_x, ph_y;
+  size_t tw_xm, tw_xn, tw_y, lam_x, lam_y, ph_x, ph_y, tw_z, tw_zq, lam_z;
 };
 
 struct Offsets {
@@ -129,6 +129,9 @@ Offsets layout(const drpf_params& p, const Dims& F, const Dims& C) {
     t.lam_y = cv.take((size_t)d.ny * 8);
     t.ph_x = cv.take((size_t)d.pitch * 16);
     t.ph_y = cv.take((size_t)d.ny * 16);
+    t.tw_z = cv.take((size_t)d.nz * 2 * es);
+    t.tw_zq = cv.take((size_t)d.nz * 2 * es);
+    t.lam_z = cv.take((size_t)d.nz * 8);
   };
   tabs(F, o.tf);
   tabs(C, o.tc);
@@ -174,6 +177,9 @@ Tables<T> tables(drpf_grid* g, const TabOff& t) {
   tb.lam_y = reinterpret_cast<const double*>(g->ws + t.lam_y);
   tb.ph_x = reinterpret_cast<const double*>(g->ws + t.ph_x);
   tb.ph_y = reinterpret_cast<const double*>(g->ws + t.ph_y);
+  tb.tw_z = reinterpret_cast<const cx<T>*>(g->ws + t.tw_z);
+  tb.tw_zq = reinterpret_cast<const cx<T>*>(g->ws + t.tw_zq);
+  tb.lam_z = reinterpret_cast<const double*>(g->ws + t.lam_z);
   return tb;
 }
 
@@ -243,6 +249,23 @@ int upload_tables(drpf_grid* g, const Dims& d, const TabOff& t, hipStream_t st,
   HIPCHK(put(t.lam_y, ly.data(), ly.size() * 8), "upload eigenvalues");
   HIPCHK(put(t.ph_x, px.data(), px.size() * 8), "upload phases");
   HIPCHK(put(t.ph_y, py.data(), py.size() * 8), "upload phases");
+  tw.assign(2 * d.nz, 0);
+  for (int i = 0; i < d.nz; ++i) {
+    tw[2 * i] = (T)cosl(2 * pi * i / d.nz);
+    tw[2 * i + 1] = (T)-sinl(2 * pi * i / d.nz);
+  }
+  HIPCHK(put(t.tw_z, tw.data(), tw.size() * sizeof(T)), "upload twiddles");
+  for (int m = 0; m < d.nz; ++m) {
+    tw[2 * m] = (T)cosl(pi * m / (2 * d.nz));
+    tw[2 * m + 1] = (T)-sinl(pi * m / (2 * d.nz));
+  }
+  HIPCHK(put(t.tw_zq, tw.data(), tw.size() * sizeof(T)), "upload twiddles");
+  std::vector<double> lz(d.nz);
+  for (int m = 0; m < d.nz; ++m) {
+    const double s = sin(M_PI * m / (2.0 * d.nz));
+    lz[m] = -4.0 / (d.hz * d.hz) * s * s;
+  }
+  HIPCHK(put(t.lam_z, lz.data(), lz.size() * 8), "upload eigenvalues");
   return DRPF_OK;
 }
 

@@ -80,6 +80,10 @@ struct Tables {
   const double* lam_y;   // -(4/hy^2) sin^2(pi ky / ny), ky < ny
   const double* ph_x;    // (cos, sin)(2 pi kx / nx), kx <= nx/2, interleaved
   const double* ph_y;    // (cos, sin)(2 pi ky / ny), ky < ny, interleaved
+  const cx<T>* tw_z;     // e^{-2 pi i t / nz}, t < nz (FFT inside the wall-normal DCT)
+  const cx<T>* tw_zq;    // e^{-i pi m / (2 nz)}, m < nz (DCT-II quarter-wave twiddle)
+  const double* lam_z;   // -(4/hz^2) sin^2(pi m / (2 nz)), m < nz: DCT-II eigenvalues of the
+                         // zero-flux second difference
 };
 
 // Scheme constants of one step kind (first step: gamma0 = 1; later: 3/2).

@@ -11,9 +11,9 @@
 //                  f(phi*)] (the bracket of eq. NS25 times the mixing energy), restriction of
 //                  phi and G to coarse centres / faces / edges (eq. dual2) and the mixture
 //                  properties there (eq. dual3): 1/rho at faces, solvent viscosity at centres
-//                  and edges. A block stages the fine phi^{n+1} tile (with a one-cell halo)
-//                  under its coarse tile in LDS, evaluates G once per fine cell of the tile,
-//                  then every thread sums its coarse cell's 2x2x2 groups from LDS.
+//                  and edges. A block marches up a column of coarse cells with rings of
+//                  fine phi^{n+1} and G layers in LDS; G is evaluated once per fine cell and
+//                  every thread sums its coarse cell's 2x2x2 groups from LDS.
 //   prolong, restrict -- the standalone transfer operators (eqs. dual1, dual2).
 #include "kernels.hpp"
 
@@ -28,7 +28,7 @@ struct FineView {
   const T* a;
   int nx, ny, nz;
   __device__ __forceinline__ T at(int k, int j, int i) const {
-    return a[((size_t)k * ny + wrap(j, ny)) * nx + wrap(i, nx)];
+    return a[(k * ny + wrap(j, ny)) * nx + wrap(i, nx)];
   }
 };
 
@@ -38,11 +38,11 @@ template <typename T>
 struct Prolonged {
   const T *un, *unm1, *vn, *vnm1, *wn, *wnm1;
   int cnx, cny, cnz, ry, first;
-  __device__ __forceinline__ T star(const T* a, const T* b, size_t idx) const {
+  __device__ __forceinline__ T star(const T* a, const T* b, int idx) const {
     return first ? a[idx] : (T)2 * a[idx] - b[idx];
   }
-  __device__ __forceinline__ size_t cidx(int k, int j, int i) const {
-    return ((size_t)k * cny + wrap(j, cny)) * cnx + wrap(i, cnx);
+  __device__ __forceinline__ int cidx(int k, int j, int i) const {
+    return (k * cny + wrap(j, cny)) * cnx + wrap(i, cnx);
   }
   // fine x face I (at x = (I+1) hxf) of fine row (K, J)
   __device__ __forceinline__ T uf(int K, int J, int I) const {
@@ -67,190 +67,268 @@ struct Prolonged {
   }
 };
 
+// Right-hand side of the fused CH solve, z-marching: a block owns TX x TY fine columns and
+// KB consecutive layers. Rings of three layers of phi* and w* (with a one-cell x/y halo) live
+// in LDS; each thread walks up its column, so the x/y neighbours come from LDS, the z
+// neighbours from the ring, and the coarse velocities of eq. dual1 are reloaded only when
+// the column enters a new coarse layer.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_ch_rhs(const T* __restrict__ phin, const T* __restrict__ phinm1, Prolonged<T> pv,
-             T* __restrict__ out, int nx, int ny, int nz, T ihx, T ihy, T ihz, StepConsts c) {
+             T* __restrict__ out, int nx, int ny, int nz, int KB, T ihx, T ihy, T ihz,
+             StepConsts c) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int TX = blockDim.x, TY = blockDim.y;
   int bx, by, bz;
   xcd_tile(bx, by, bz);
-  const int I = bx * blockDim.x + threadIdx.x;
-  const int J = by * blockDim.y + threadIdx.y;
-  const int K = bz;
-  const FineView<T> A{phin, nx, ny, nz}, B{phinm1, nx, ny, nz};
+  const int X0 = bx * TX, Y0 = by * TY, K0 = bz * KB;
+  const int HX = TX + 2, HY = TY + 2, HP = HX * HY;
+  T* sP = reinterpret_cast<T*>(smem);  // 3 slots of phi*
+  T* sW = sP + 3 * HP;                 // 3 slots of w* = f(phi*) - (S/Cn^2) phi*
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int tid = ty * TX + tx, nth = TX * TY;
+  const int I = X0 + tx, J = Y0 + ty;
   const bool first = c.first != 0;
-  auto star = [&](int k, int j, int i) -> T {
-    return first ? A.at(k, j, i) : (T)2 * A.at(k, j, i) - B.at(k, j, i);
-  };
-  const T ihx2 = ihx * ihx, ihy2 = ihy * ihy, ihz2 = ihz * ihz;
-  // phi* on the 7-point stencil, zero-flux ghosts in z
-  const T p0 = star(K, J, I);
-  const T pxp = star(K, J, I + 1), pxm = star(K, J, I - 1);
-  const T pyp = star(K, J + 1, I), pym = star(K, J - 1, I);
-  const T pzp = K + 1 < nz ? star(K + 1, J, I) : p0;
-  const T pzm = K > 0 ? star(K - 1, J, I) : p0;
-  const T phat = first ? A.at(K, J, I) : (T)2 * A.at(K, J, I) - (T)0.5 * B.at(K, J, I);
-  // advection div(u_f* phi*) in flux form, zero wall flux
-  const T h = (T)0.5;
-  const T fxp = pv.uf(K, J, I) * h * (p0 + pxp);
-  const T fxm = pv.uf(K, J, I - 1) * h * (pxm + p0);
-  const T fyp = pv.vf(K, J, I) * h * (p0 + pyp);
-  const T fym = pv.vf(K, J - 1, I) * h * (pym + p0);
-  const T fzp = K + 1 < nz ? pv.wf(K, J, I) * h * (p0 + pzp) : (T)0;
-  const T fzm = K > 0 ? pv.wf(K - 1, J, I) * h * (pzm + p0) : (T)0;
-  const T adv = (fxp - fxm) * ihx + (fyp - fym) * ihy + (fzp - fzm) * ihz;
-  // w* = f(phi*) - (S/Cn^2) phi*,   f = (phi^3 - phi) / Cn^2
   const T icn2 = (T)c.inv_cn2, sc = (T)c.s_cn2;
-  auto wst = [&](T p) -> T { return (p * p * p - p) * icn2 - sc * p; };
-  const T w0 = wst(p0);
-  const T lapw = (wst(pxp) - 2 * w0 + wst(pxm)) * ihx2 + (wst(pyp) - 2 * w0 + wst(pym)) * ihy2 +
-                 (wst(pzp) - 2 * w0 + wst(pzm)) * ihz2;
-  // wetting data b = g(phi*_wall) / hz on the wall-adjacent layers, and L_N b
-  const T gb = (T)c.g_bot * ihz, gt = (T)c.g_top * ihz;
-  auto bval = [&](int k, T p) -> T {
-    T b = 0;
-    if (k == 0) b += gb * ((T)1 - p * p);
-    if (k == nz - 1) b += gt * ((T)1 - p * p);
-    return b;
+  auto load_layer = [&](int Kl, int slot) {
+    const int Kc = min(max(Kl, 0), nz - 1);  // beyond a wall: zero-flux ghost = adjacent layer
+    for (int e = tid; e < HP; e += nth) {
+      const int hy = e / HX, hx = e - hy * HX;
+      const int id = (Kc * ny + wrap(Y0 - 1 + hy, ny)) * nx + wrap(X0 - 1 + hx, nx);
+      const T a = phin[id];
+      const T p = first ? a : (T)2 * a - phinm1[id];
+      sP[slot * HP + e] = p;
+      sW[slot * HP + e] = (p * p * p - p) * icn2 - sc * p;
+    }
   };
-  T lapb = 0;
-  if (K == 0 || K == nz - 1) {
-    const T b0 = bval(K, p0);
-    lapb = (bval(K, pxp) - 2 * b0 + bval(K, pxm)) * ihx2 + (bval(K, pyp) - 2 * b0 + bval(K, pym)) * ihy2;
-    const T bup = K + 1 < nz ? bval(K + 1, pzp) : b0;
-    const T bdn = K > 0 ? bval(K - 1, pzm) : b0;
-    lapb += (bup - 2 * b0 + bdn) * ihz2;
-  } else {
-    // an interior layer next to a wall layer sees b of that layer through its z neighbour
-    if (K == 1) lapb += bval(0, pzm) * ihz2;
-    if (K == nz - 2) lapb += bval(nz - 1, pzp) * ihz2;
+  int sm = 0, s0 = 1, sp = 2;
+  load_layer(K0 - 1, sm);
+  load_layer(K0, s0);
+  // coarse column of this fine column (eq. dual1)
+  const int ry = pv.ry;
+  const int ic = I >> 1, icw = wrap(ic - 1, pv.cnx);
+  const int jc = ry == 2 ? (J >> 1) : 0, jcw = ry == 2 ? wrap(jc - 1, pv.cny) : 0;
+  const int cplane = pv.cnx * pv.cny;
+  const int cu0 = jc * pv.cnx + ic, cu1 = jc * pv.cnx + icw;
+  const int cv1 = jcw * pv.cnx + ic;
+  const T ihx2 = ihx * ihx, ihy2 = ihy * ihy, ihz2 = ihz * ihz, h = (T)0.5;
+  const T gb = (T)c.g_bot * ihz, gt = (T)c.g_top * ihz;
+  T ufp = 0, ufm = 0, vfp = 0, vfm = 0, wk = 0, wkm = 0;
+  int kcur = -1;
+  for (int K = K0; K < K0 + KB; ++K) {
+    load_layer(K + 1, sp);
+    const int k = K >> 1;
+    if (k != kcur) {
+      kcur = k;
+      const int o = k * cplane;
+      const T ua = pv.star(pv.un, pv.unm1, o + cu0), ub = pv.star(pv.un, pv.unm1, o + cu1);
+      const bool iodd = I & 1;
+      ufp = iodd ? ua : h * (ub + ua);
+      ufm = iodd ? h * (ub + ua) : ub;
+      const T va = pv.star(pv.vn, pv.vnm1, o + cu0);
+      if (ry == 2) {
+        const T vb = pv.star(pv.vn, pv.vnm1, o + cv1);
+        const bool jodd = J & 1;
+        vfp = jodd ? va : h * (vb + va);
+        vfm = jodd ? h * (vb + va) : vb;
+      } else {
+        vfp = vfm = va;
+      }
+      wk = k < pv.cnz - 1 ? pv.star(pv.wn, pv.wnm1, o + cu0) : (T)0;
+      wkm = k > 0 ? pv.star(pv.wn, pv.wnm1, o - cplane + cu0) : (T)0;
+    }
+    // fine z faces K (above) and K-1 (below); the walls carry zero flux
+    const T wfp = K == nz - 1 ? (T)0 : ((K & 1) ? wk : h * (wkm + wk));
+    const T wfm = K == 0 ? (T)0 : ((K & 1) ? h * (wkm + wk) : wkm);
+    __syncthreads();
+    const int c0 = (ty + 1) * HX + (tx + 1);
+    const T* P0 = sP + s0 * HP;
+    const T* W0 = sW + s0 * HP;
+    const T p0 = P0[c0], pxp = P0[c0 + 1], pxm = P0[c0 - 1], pyp = P0[c0 + HX], pym = P0[c0 - HX];
+    const T pzp = sP[sp * HP + c0], pzm = sP[sm * HP + c0];
+    const T w0 = W0[c0];
+    const T lapw = (W0[c0 + 1] - 2 * w0 + W0[c0 - 1]) * ihx2 + (W0[c0 + HX] - 2 * w0 + W0[c0 - HX]) * ihy2 +
+                   (sW[sp * HP + c0] - 2 * w0 + sW[sm * HP + c0]) * ihz2;
+    const T adv = (ufp * h * (p0 + pxp) - ufm * h * (pxm + p0)) * ihx +
+                  (vfp * h * (p0 + pyp) - vfm * h * (pym + p0)) * ihy +
+                  (wfp * h * (p0 + pzp) - wfm * h * (pzm + p0)) * ihz;
+    // wetting data b = g(phi*) / hz on the wall-adjacent layers, and L_N b
+    auto bval = [&](int kk, T p) -> T {
+      T b = 0;
+      if (kk == 0) b += gb * ((T)1 - p * p);
+      if (kk == nz - 1) b += gt * ((T)1 - p * p);
+      return b;
+    };
+    T lapb = 0;
+    if (K == 0 || K == nz - 1) {
+      const T b0 = bval(K, p0);
+      lapb = (bval(K, pxp) - 2 * b0 + bval(K, pxm)) * ihx2 + (bval(K, pyp) - 2 * b0 + bval(K, pym)) * ihy2;
+      const T bup = K + 1 < nz ? bval(K + 1, pzp) : b0;
+      const T bdn = K > 0 ? bval(K - 1, pzm) : b0;
+      lapb += (bup - 2 * b0 + bdn) * ihz2;
+    } else {
+      if (K == 1) lapb += bval(0, pzm) * ihz2;
+      if (K == nz - 2) lapb += bval(nz - 1, pzp) * ihz2;
+    }
+    const int id = (K * ny + J) * nx + I;
+    const T phat = first ? phin[id] : (T)2 * phin[id] - (T)0.5 * phinm1[id];
+    const T q = (T)c.pe_cn2 * (phat * (T)c.inv_dt - adv) + lapw;
+    out[id] = q - lapb;
+    __syncthreads();
+    const int t = sm;
+    sm = s0;
+    s0 = sp;
+    sp = t;
   }
-  const T q = (T)c.pe_cn2 * (phat * (T)c.inv_dt - adv) + lapw;
-  out[((size_t)K * ny + J) * nx + I] = q - lapb;
 }
 
-// Per-axis weights of the 1D restriction rules for a fine offset d relative to r * i
-// (r the refinement factor of that axis): centre rule and face rule.
-__device__ __forceinline__ float wc(int d, int r) { return r == 2 ? (d < 2 ? 0.5f : 0.f) : (d == 0 ? 1.f : 0.f); }
-__device__ __forceinline__ float wf(int d, int r) { return r == 2 ? (d >= 1 ? 0.5f : 0.f) : (d <= 1 ? 0.5f : 0.f); }
 
+// Chemical potential, restriction and properties, z-marching: a block owns CX x CY coarse
+// columns and KB coarse layers. A ring of six fine layers of phi^{n+1} (one-cell halo) and a
+// ring of four fine layers of G live in LDS, indexed by the clamped fine layer modulo the
+// ring size; stepping one coarse layer up loads two new phi layers and evaluates G on two
+// new layers (the shared face layer is kept).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_restrict_g(const T* __restrict__ phinew, const T* __restrict__ phin,
                  const T* __restrict__ phinm1, Restricted<T> r, int fnx, int fny, int fnz,
-                 T fihx, T fihy, T fihz, int cnx, int cny, int cnz, int ry, int KZ,
+                 T fihx, T fihy, T fihz, int cnx, int cny, int cnz, int ry, int KB,
                  StepConsts c) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int CX = blockDim.x, CY = blockDim.y;
   int bx, by, bz;
   xcd_tile(bx, by, bz);
-  const int i0 = bx * CX, j0 = by * CY, k0 = bz * KZ;
-  // G region: fine x 2 i0 .. 2 i0 + 2 CX, y ry j0 .. ry j0 + ry CY, z 2 k0 .. 2 k0 + 2 KZ
-  // (clamped to the top layer); phi^{n+1} tile one cell wider on every side.
-  const int GX = 2 * CX + 1, GY = ry * CY + 1, GZ = 2 * KZ + 1;
-  const int PX = GX + 2, PY = GY + 2, PZ = GZ + 2;
-  const int X0 = 2 * i0, Y0 = ry * j0, Z0 = 2 * k0;
-  T* sP = reinterpret_cast<T*>(smem);  // phi^{n+1} on the halo tile, layers clamp(Z0 - 1 + pz)
-  T* sG = sP + PX * PY * PZ;           // G on the G region
+  const int i0 = bx * CX, j0 = by * CY, k0 = bz * KB;
+  const int GX = 2 * CX + 1, GY = ry * CY + 1, GP = GX * GY;
+  const int PX = GX + 2, PY = GY + 2, PP = PX * PY;
+  const int X0 = 2 * i0, Y0 = ry * j0;
+  T* sP = reinterpret_cast<T*>(smem);  // 6 slots of phi^{n+1}
+  T* sG = sP + 6 * PP;                 // 4 slots of G
   const int tid = threadIdx.y * CX + threadIdx.x;
   const int nth = CX * CY;
-  const FineView<T> N{phinew, fnx, fny, fnz}, A{phin, fnx, fny, fnz}, B{phinm1, fnx, fny, fnz};
-  for (int e = tid; e < PX * PY * PZ; e += nth) {
-    const int pz = e / (PX * PY);
-    const int rem = e - pz * PX * PY;
-    const int py = rem / PX;
-    const int px = rem - py * PX;
-    const int Kz = min(max(Z0 - 1 + pz, 0), fnz - 1);
-    sP[e] = N.at(Kz, Y0 - 1 + py, X0 - 1 + px);
-  }
-  __syncthreads();
   const bool first = c.first != 0;
   const T ihx2 = fihx * fihx, ihy2 = fihy * fihy, ihz2 = fihz * fihz;
   const T cn2 = (T)c.cn2, S = (T)c.S;
   const T gb = (T)c.g_bot * fihz, gt = (T)c.g_top * fihz;
-  auto pzi = [&](int Kf) { return min(max(Kf, 0), fnz - 1) - Z0 + 1; };
-  auto P = [&](int pz, int py, int px) -> T { return sP[(pz * PY + py) * PX + px]; };
-  for (int e = tid; e < GX * GY * GZ; e += nth) {
-    const int gz = e / (GX * GY);
-    const int rem = e - gz * GX * GY;
-    const int gy = rem / GX;
-    const int gx = rem - gy * GX;
-    const int K = min(Z0 + gz, fnz - 1);
-    const int pz = pzi(K), py = gy + 1, px = gx + 1;
-    const T p = P(pz, py, px);
-    const T lap = (P(pz, py, px + 1) - 2 * p + P(pz, py, px - 1)) * ihx2 +
-                  (P(pz, py + 1, px) - 2 * p + P(pz, py - 1, px)) * ihy2 +
-                  (P(pzi(K + 1), py, px) - 2 * p + P(pzi(K - 1), py, px)) * ihz2;
-    const T an = A.at(K, Y0 + gy, X0 + gx);
-    const T ps = first ? an : (T)2 * an - B.at(K, Y0 + gy, X0 + gx);
-    T b = 0;
-    if (K == 0) b += gb * ((T)1 - ps * ps);
-    if (K == fnz - 1) b += gt * ((T)1 - ps * ps);
-    sG[e] = -cn2 * (lap + b) + S * (p - ps) + ps * ps * ps - ps;
-  }
+  auto kc = [&](int Kf) { return min(max(Kf, 0), fnz - 1); };
+  auto loadP = [&](int Kf) {
+    const int K = kc(Kf);
+    T* dst = sP + (K % 6) * PP;
+    for (int e = tid; e < PP; e += nth) {
+      const int py = e / PX, px = e - py * PX;
+      dst[e] = phinew[(K * fny + wrap(Y0 - 1 + py, fny)) * fnx + wrap(X0 - 1 + px, fnx)];
+    }
+  };
+  auto computeG = [&](int Kf) {
+    const int K = kc(Kf);
+    const T* Pm = sP + (kc(K - 1) % 6) * PP;
+    const T* P0 = sP + (K % 6) * PP;
+    const T* Pp = sP + (kc(K + 1) % 6) * PP;
+    T* dst = sG + (K % 4) * GP;
+    for (int e = tid; e < GP; e += nth) {
+      const int gy = e / GX, gx = e - gy * GX;
+      const int m = (gy + 1) * PX + gx + 1;
+      const T p = P0[m];
+      const T lap = (P0[m + 1] - 2 * p + P0[m - 1]) * ihx2 + (P0[m + PX] - 2 * p + P0[m - PX]) * ihy2 +
+                    (Pp[m] - 2 * p + Pm[m]) * ihz2;
+      const int id = (K * fny + wrap(Y0 + gy, fny)) * fnx + wrap(X0 + gx, fnx);
+      const T an = phin[id];
+      const T ps = first ? an : (T)2 * an - phinm1[id];
+      T b = 0;
+      if (K == 0) b += gb * ((T)1 - ps * ps);
+      if (K == fnz - 1) b += gt * ((T)1 - ps * ps);
+      dst[e] = -cn2 * (lap + b) + S * (p - ps) + ps * ps * ps - ps;
+    }
+  };
+  for (int Kf = 2 * k0 - 1; Kf <= 2 * k0 + 3; ++Kf) loadP(Kf);
+  __syncthreads();
+  for (int Kf = 2 * k0; Kf <= 2 * k0 + 2; ++Kf) computeG(Kf);
   __syncthreads();
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int i = i0 + tx, j = j0 + ty;
-  for (int kk = 0; kk < KZ; ++kk) {
-  const int k = k0 + kk;
-  T phic = 0, Gc = 0, phx = 0, Gx = 0, phy = 0, Gy = 0, phz = 0, Gz = 0;
-  T phxy = 0, phxz = 0, phyz = 0, phxz_b = 0, phyz_b = 0;
-  const int ndy = ry + 1;
-  for (int dz = 0; dz < 3; ++dz) {
-    const int gz = 2 * kk + dz;
-    const int K = min(Z0 + gz, fnz - 1);
-    const int pz = pzi(K);
-    const T zc = (T)wc(dz, 2), zf = (T)wf(dz, 2);
-    for (int dy = 0; dy < ndy; ++dy) {
-      const int gy = ry * ty + dy;
-      const T yc = (T)wc(dy, ry), yf = (T)wf(dy, ry);
-      for (int dx = 0; dx < 3; ++dx) {
-        const int gx = 2 * tx + dx;
-        const T p = P(pz, gy + 1, gx + 1);
-        const T G = sG[(gz * GY + gy) * GX + gx];
-        const T xc = (T)wc(dx, 2), xf = (T)wf(dx, 2);
-        phic += xc * yc * zc * p;
-        Gc += xc * yc * zc * G;
-        phx += xf * yc * zc * p;
-        Gx += xf * yc * zc * G;
-        phy += xc * yf * zc * p;
-        Gy += xc * yf * zc * G;
-        phz += xc * yc * zf * p;
-        Gz += xc * yc * zf * G;
-        phxy += xf * yf * zc * p;
-        phxz += xf * yc * zf * p;
-        phyz += xc * yf * zf * p;
-        if (dz == 0) {
-          phxz_b += xf * yc * p;
-          phyz_b += xc * yf * p;
-        }
-      }
-    }
-  }
   const T r1 = (T)c.rho1, r2 = (T)c.rho2, m1 = (T)c.mu1, m2 = (T)c.mu2, hf = (T)0.5;
   auto rinv = [&](T ph) { return (T)1 / (hf * ((T)1 + ph) * r1 + hf * ((T)1 - ph) * r2); };
   auto mu = [&](T ph) { return hf * ((T)1 + ph) * m1 + hf * ((T)1 - ph) * m2; };
-  const size_t id = ((size_t)k * cny + j) * cnx + i;
-  r.phi_c[id] = phic;
-  r.G_c[id] = Gc;
-  r.G_x[id] = Gx;
-  r.G_y[id] = Gy;
-  r.G_z[id] = Gz;
-  r.ri_x[id] = rinv(phx);
-  r.ri_y[id] = rinv(phy);
-  r.ri_z[id] = rinv(phz);
-  r.mu_c[id] = mu(phic);
-  r.mu_xy[id] = mu(phxy);
-  // z-edge arrays carry nz + 1 layers: layer k + 1 is the edge at z = (k + 1) hz
-  const size_t plane = (size_t)cnx * cny;
-  r.mu_xz[id + plane] = mu(phxz);
-  r.mu_yz[id + plane] = mu(phyz);
-  if (k == 0) {
-    r.mu_xz[id] = mu(phxz_b);
-    r.mu_yz[id] = mu(phyz_b);
-  }
+  const int plane = cnx * cny;
+  const int ndy = ry + 1;
+  for (int k = k0; k < k0 + KB; ++k) {
+    // Separable sums of the tensor-product rule: per z layer and y row, x sums over the
+    // centre pair (dx 0,1) and the face pair (dx 1,2); then y pairs, then z pairs. The 1/8
+    // weight is applied once at the end (a centre-located y axis without refinement counts
+    // its single cell twice).
+    T pz_[3][4], gz_[3][4];  // per dz: [YcXc, YcXf, YfXc, YfXf]
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz) {
+      const int K = kc(2 * k + dz);
+      const T* P0 = sP + (K % 6) * PP;
+      const T* G0 = sG + (K % 4) * GP;
+      T pxc[3], pxf[3], gxc[3], gxf[3];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const int gy = ry * ty + (dy < ndy ? dy : 0);
+        const T* pr = P0 + (gy + 1) * PX + 2 * tx + 1;
+        const T* gr = G0 + gy * GX + 2 * tx;
+        pxc[dy] = pr[0] + pr[1];
+        pxf[dy] = pr[1] + pr[2];
+        gxc[dy] = gr[0] + gr[1];
+        gxf[dy] = gr[1] + gr[2];
+      }
+      if (ry == 2) {
+        pz_[dz][0] = pxc[0] + pxc[1];
+        pz_[dz][1] = pxf[0] + pxf[1];
+        pz_[dz][2] = pxc[1] + pxc[2];
+        pz_[dz][3] = pxf[1] + pxf[2];
+        gz_[dz][0] = gxc[0] + gxc[1];
+        gz_[dz][1] = gxf[0] + gxf[1];
+        gz_[dz][2] = gxc[1] + gxc[2];
+      } else {
+        pz_[dz][0] = (T)2 * pxc[0];
+        pz_[dz][1] = (T)2 * pxf[0];
+        pz_[dz][2] = pxc[0] + pxc[1];
+        pz_[dz][3] = pxf[0] + pxf[1];
+        gz_[dz][0] = (T)2 * gxc[0];
+        gz_[dz][1] = (T)2 * gxf[0];
+        gz_[dz][2] = gxc[0] + gxc[1];
+      }
+    }
+    const T e8 = (T)0.125;
+    const T phic = e8 * (pz_[0][0] + pz_[1][0]), Gc = e8 * (gz_[0][0] + gz_[1][0]);
+    const T phx = e8 * (pz_[0][1] + pz_[1][1]), Gx = e8 * (gz_[0][1] + gz_[1][1]);
+    const T phy = e8 * (pz_[0][2] + pz_[1][2]), Gy = e8 * (gz_[0][2] + gz_[1][2]);
+    const T phz = e8 * (pz_[1][0] + pz_[2][0]), Gz = e8 * (gz_[1][0] + gz_[2][0]);
+    const T phxy = e8 * (pz_[0][3] + pz_[1][3]);
+    const T phxz = e8 * (pz_[1][1] + pz_[2][1]);
+    const T phyz = e8 * (pz_[1][2] + pz_[2][2]);
+    const T phxz_b = (T)0.25 * pz_[0][1], phyz_b = (T)0.25 * pz_[0][2];
+    const int id = (k * cny + j) * cnx + i;
+    r.phi_c[id] = phic;
+    r.G_c[id] = Gc;
+    r.G_x[id] = Gx;
+    r.G_y[id] = Gy;
+    r.G_z[id] = Gz;
+    r.ri_x[id] = rinv(phx);
+    r.ri_y[id] = rinv(phy);
+    r.ri_z[id] = rinv(phz);
+    r.mu_c[id] = mu(phic);
+    r.mu_xy[id] = mu(phxy);
+    // z-edge arrays carry nz + 1 layers: layer k + 1 is the edge at z = (k + 1) hz
+    r.mu_xz[id + plane] = mu(phxz);
+    r.mu_yz[id + plane] = mu(phyz);
+    if (k == 0) {
+      r.mu_xz[id] = mu(phxz_b);
+      r.mu_yz[id] = mu(phyz_b);
+    }
+    if (k + 1 < k0 + KB) {
+      // next coarse layer: fine phi layers 2k+4, 2k+5 replace 2k-2, 2k-1; G on 2k+3, 2k+4
+      loadP(2 * k + 4);
+      loadP(2 * k + 5);
+      __syncthreads();
+      computeG(2 * k + 3);
+      computeG(2 * k + 4);
+      __syncthreads();
+    }
   }
 }
-
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_prolong(T* __restrict__ uf, T* __restrict__ vf, T* __restrict__ wf, int fnx, int fny,
@@ -307,9 +385,21 @@ hipError_t launch_ch_rhs(const Dims& f, const Dims& c, const StepConsts& k, ChIn
                          hipStream_t st) {
   Prolonged<T> pv{in.un, in.unm1, in.vn, in.vnm1, in.wn, in.wnm1, c.nx, c.ny, c.nz,
                   c.ny == 1 ? 1 : 2, k.first};
-  const Launch3 L = launch3(f.nx, f.ny, f.nz);
-  hipLaunchKernelGGL(k_ch_rhs<T>, L.grid, L.block, 0, st, in.phin, in.phinm1, pv, rhs, f.nx, f.ny,
-                     f.nz, (T)f.ihx, (T)f.ihy, (T)f.ihz, k);
+  int TX, TY;
+  if (f.ny == 1) {
+    TX = f.nx < 256 ? f.nx : 256;
+    TY = 1;
+  } else {
+    TX = f.nx < 64 ? f.nx : 64;
+    TY = f.ny < 4 ? f.ny : 4;
+  }
+  const int tiles = (f.nx / TX) * (f.ny / TY);
+  int KB = 16;
+  while (KB > 2 && (f.nz / KB) * tiles < 1024) KB >>= 1;
+  if (KB > f.nz) KB = f.nz;
+  const size_t shm = (size_t)6 * (TX + 2) * (TY + 2) * sizeof(T);
+  hipLaunchKernelGGL(k_ch_rhs<T>, dim3(f.nx / TX, f.ny / TY, f.nz / KB), dim3(TX, TY, 1), shm, st,
+                     in.phin, in.phinm1, pv, rhs, f.nx, f.ny, f.nz, KB, (T)f.ihx, (T)f.ihy, (T)f.ihz, k);
   return hipGetLastError();
 }
 
@@ -325,14 +415,16 @@ hipError_t launch_restrict_g(const Dims& f, const Dims& c, const StepConsts& k, 
     CX = c.nx < 128 ? c.nx : 128;
     CY = 1;
   }
-  // coarse layers per block (the kernel supports KZ > 1, which amortises the z halo, but on
-  // gfx950 the larger LDS tile lowers occupancy more than it saves: one layer measures best)
-  const int KZ = 1;
-  const int GX = 2 * CX + 1, GY = ry * CY + 1, GZ = 2 * KZ + 1;
-  const size_t shm = (size_t)((GX + 2) * (GY + 2) * (GZ + 2) + GX * GY * GZ) * sizeof(T);
-  hipLaunchKernelGGL(k_restrict_g<T>, dim3(c.nx / CX, c.ny / CY, c.nz / KZ), dim3(CX, CY, 1), shm, st,
+  // coarse layers per block: the z march amortises the fine z halo; keep >= ~1024 blocks
+  const int tiles = (c.nx / CX) * (c.ny / CY);
+  int KB = 8;
+  while (KB > 1 && (c.nz / KB) * tiles < 1024) KB >>= 1;
+  if (KB > c.nz) KB = c.nz;
+  const int GX = 2 * CX + 1, GY = ry * CY + 1;
+  const size_t shm = (size_t)(6 * (GX + 2) * (GY + 2) + 4 * GX * GY) * sizeof(T);
+  hipLaunchKernelGGL(k_restrict_g<T>, dim3(c.nx / CX, c.ny / CY, c.nz / KB), dim3(CX, CY, 1), shm, st,
                      phinew, phin, phinm1, r, f.nx, f.ny, f.nz, (T)f.ihx, (T)f.ihy, (T)f.ihz, c.nx,
-                     c.ny, c.nz, ry, KZ, k);
+                     c.ny, c.nz, ry, KB, k);
   return hipGetLastError();
 }
 

@@ -30,12 +30,13 @@ struct Field {
   const T* a;
   const T* b;   // level n-1 (extrapolation) or null
   int nx, ny, nz, first;
-  __device__ __forceinline__ size_t idx(int k, int j, int i) const {
-    return ((size_t)k * ny + wrap(j, ny)) * nx + wrap(i, nx);
+  // 32-bit element indices: every supported grid has fewer than 2^31 cells per array
+  __device__ __forceinline__ int idx(int k, int j, int i) const {
+    return (k * ny + wrap(j, ny)) * nx + wrap(i, nx);
   }
   // extrapolated value (u* = 2 u^n - u^{n-1}, or u^n on the first step), in-range k
   __device__ __forceinline__ T s(int k, int j, int i) const {
-    const size_t id = idx(k, j, i);
+    const int id = idx(k, j, i);
     return (first || b == nullptr) ? a[id] : (T)2 * a[id] - b[id];
   }
   __device__ __forceinline__ T n(int k, int j, int i) const { return a[idx(k, j, i)]; }
@@ -59,7 +60,7 @@ struct Coarse {
   const T* a;
   int nx, ny, nz;
   __device__ __forceinline__ T at(int k, int j, int i) const {
-    return a[((size_t)k * ny + wrap(j, ny)) * nx + wrap(i, nx)];
+    return a[(k * ny + wrap(j, ny)) * nx + wrap(i, nx)];
   }
   __device__ __forceinline__ T atn(int k, int j, int i) const { return at(min(max(k, 0), nz - 1), j, i); }
 };
@@ -70,7 +71,7 @@ struct ZEdge {
   const T* a;
   int nx, ny;
   __device__ __forceinline__ T at(int m, int j, int i) const {
-    return a[((size_t)m * ny + wrap(j, ny)) * nx + wrap(i, nx)];
+    return a[(m * ny + wrap(j, ny)) * nx + wrap(i, nx)];
   }
 };
 
@@ -86,7 +87,7 @@ struct MomCtx {
   T ihx, ihy, ihz;
   T inv_dt, inv_re, ir0, nu_m, k_sigma, c_j;
   // hat of eq. NS31 at an in-range index
-  __device__ __forceinline__ T hat(const T* a, const T* b, size_t id) const {
+  __device__ __forceinline__ T hat(const T* a, const T* b, int id) const {
     return first ? a[id] : (T)2 * a[id] - (T)0.5 * b[id];
   }
   // J = -c_j grad G at a centre: 2h central differences, Neumann in z
@@ -104,7 +105,7 @@ struct MomCtx {
 };
 
 template <typename T>
-__device__ __forceinline__ T mom_u(const MomCtx<T>& m, int k, int j, int i, size_t id, T ax) {
+__device__ __forceinline__ T mom_u(const MomCtx<T>& m, int k, int j, int i, int id, T ax) {
   const auto& U = m.U;
   const auto& V = m.V;
   const auto& W = m.W;
@@ -158,7 +159,7 @@ __device__ __forceinline__ T mom_u(const MomCtx<T>& m, int k, int j, int i, size
 }
 
 template <typename T>
-__device__ __forceinline__ T mom_v(const MomCtx<T>& m, int k, int j, int i, size_t id, T ay) {
+__device__ __forceinline__ T mom_v(const MomCtx<T>& m, int k, int j, int i, int id, T ay) {
   const auto& U = m.U;
   const auto& V = m.V;
   const auto& W = m.W;
@@ -208,7 +209,7 @@ __device__ __forceinline__ T mom_v(const MomCtx<T>& m, int k, int j, int i, size
 }
 
 template <typename T>
-__device__ __forceinline__ T mom_w(const MomCtx<T>& m, int k, int j, int i, size_t id, T az) {
+__device__ __forceinline__ T mom_w(const MomCtx<T>& m, int k, int j, int i, int id, T az) {
   const auto& U = m.U;
   const auto& V = m.V;
   const auto& W = m.W;
@@ -283,7 +284,7 @@ __global__ void __launch_bounds__(kBlock)
               nx, ny, nz, f, in.viscoelastic,
               ihx, ihy, ihz,
               (T)c.inv_dt, (T)c.inv_re, (T)c.inv_rho0, (T)c.nu_m, (T)c.k_sigma, (T)c.c_j};
-  const size_t id = ((size_t)k * ny + j) * nx + i;
+  const int id = (k * ny + j) * nx + i;
   if (comp == 0) {
     ru[id] = mom_u(m, k, j, i, id, (T)c.ax);
   } else if (comp == 1) {
@@ -318,7 +319,7 @@ __global__ void __launch_bounds__(kBlock)
   const int i = bx * blockDim.x + threadIdx.x;
   const int j = by * blockDim.y + threadIdx.y;
   const int k = bz;
-  const size_t id = ((size_t)k * ny + j) * nx + i;
+  const int id = (k * ny + j) * nx + i;
   const Coarse<T> U{u, nx, ny, nz}, V{v, nx, ny, nz}, Wf{w, nx, ny, nz};
   const T h = (T)0.5;
   auto wv = [&](int kk, int jj, int ii) -> T { return (kk < 0 || kk >= nz - 1) ? (T)0 : Wf.at(kk, jj, ii); };

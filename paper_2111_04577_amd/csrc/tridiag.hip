@@ -11,13 +11,15 @@
 //
 // Passes:
 //   zpass_ch  -- the two Helmholtz operators of the Dong splitting (eqs. NS26-NS27),
-//                (L - c_psi) then (L + alpha), applied back to back per mode.
+//                (L - c_psi) then (L + alpha), applied together per mode through the
+//                wall-normal DCT-II that diagonalises both (see k_zpass_ch).
 //   zpass_ns  -- the velocity Helmholtz solves of eq. NS36, the divergence of the predicted
 //                velocity, the pressure-increment Poisson solve of eq. NS37 in FP64 with the
 //                (0,0) mode pinned and its mean removed, and the correction of eq. NS38
 //                (all per mode, in spectral x/y space).
 //   zpass_helmholtz -- one generic solve (the drpf_helmholtz_solve entry point).
 #include "kernels.hpp"
+#include "lds_fft.hpp"
 
 namespace drpf {
 
@@ -160,34 +162,70 @@ __global__ void __launch_bounds__(1024)
 }
 
 // ---- Cahn-Hilliard pair -------------------------------------------------------------
+// Both CH operators have zero-flux walls, so the DCT-II across the walls diagonalises them
+// exactly (eigenvalue lam_z(m) of the second difference for cos(pi m (k + 1/2) / nz)). The
+// pair (L_N - c_psi)^-1 (L_N + alpha)^-1 becomes: forward DCT, one division by
+// (lam - c_psi)(lam + alpha) per coefficient, inverse DCT. Each DCT is one length-nz complex
+// FFT in LDS (Makhoul's even/odd reordering with a quarter-wave twiddle); the data are
+// complex (x/y spectral coefficients), so the real and imaginary sequences are separated
+// from the pair (V_m, V_{nz-m}). A block holds TL consecutive modes, columns in LDS.
 template <typename T>
 __global__ void __launch_bounds__(1024)
-    k_zpass_ch(cx<T>* __restrict__ S, int P, int Ny, int Nz, const double* __restrict__ lamx,
-               const double* __restrict__ lamy, double ihz2, double c_psi, double alpha,
-               double scale) {
+    k_zpass_ch(cx<T>* __restrict__ S, int P, int Ny, int Nz, int logNz, int TL,
+               const double* __restrict__ lamx, const double* __restrict__ lamy,
+               const double* __restrict__ lamz, const cx<T>* __restrict__ twz,
+               const cx<T>* __restrict__ twq, double c_psi, double alpha, double scale) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int TL = blockDim.x / Nz;
-  const int line = threadIdx.x % TL;
-  const int row = threadIdx.x / TL;
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem);  // [position][mode]
   const int lines = P * Ny;
-  const int l = blockIdx.x * TL + line;
-  const bool valid = l < lines;
-  const int lc = valid ? l : lines - 1;
-  const int ky = lc / P, kx = lc - ky * P;
+  const int l0 = blockIdx.x * TL;
   const size_t stride = (size_t)lines;
-  const double lxy = lamx[kx] + lamy[ky];
-  const T a = (T)ihz2;
-  const T ar = row == 0 ? (T)0 : a, cr = row == Nz - 1 ? (T)0 : a;
-  const bool end = row == 0 || row == Nz - 1;
-  cx<T> d[1];
-  d[0] = valid ? S[row * stride + l] : mk<T>(0, 0);
-  d[0] = (T)scale * d[0];
-  PcrLds<T, 1> L = carve<T, 1>(smem, Nz, TL);
-  // (L_N - c_psi) Psi' = R
-  pcr<T, 1>(L, Nz, TL, row, line, ar, (T)(lxy - (end ? 1.0 : 2.0) * ihz2 - c_psi), cr, d);
-  // (L_N + alpha) phi = Psi'
-  pcr<T, 1>(L, Nz, TL, row, line, ar, (T)(lxy - (end ? 1.0 : 2.0) * ihz2 + alpha), cr, d);
-  if (valid) S[row * stride + l] = d[0];
+  for (int e = threadIdx.x; e < Nz * TL; e += blockDim.x) {
+    const int row = e / TL, t = e - row * TL;
+    const int l = l0 + t;
+    const int pos = (row & 1) ? (Nz - 1 - (row >> 1)) : (row >> 1);
+    buf[pos * TL + t] = l < lines ? S[row * stride + l] : mk<T>(0, 0);
+  }
+  __syncthreads();
+  lds_fft<T, false, true>(buf, Nz, logNz, TL, 1, TL, twz);
+  const int half = Nz >> 1;
+  const T hf = (T)0.5;
+  for (int e = threadIdx.x; e < (half + 1) * TL; e += blockDim.x) {
+    const int m = e / TL, t = e - m * TL;
+    const int l = min(l0 + t, lines - 1);
+    const int ky = l / P, kx = l - ky * P;
+    const double lxy = lamx[kx] + lamy[ky];
+    const int mr = (Nz - m) & (Nz - 1);  // partner N - m (0 and N/2 pair with themselves)
+    const cx<T> Vm = buf[m * TL + t], Vr = buf[mr * TL + t];
+    // forward DCT-II coefficient from (V_m, V_{N-m}): X = Re(w A) + i Re(w B),
+    // A = (V_m + conj V_{N-m}) / 2, B = (V_m - conj V_{N-m}) / (2i)
+    auto dct_out = [&](cx<T> V, cx<T> Vp, cx<T> w) -> cx<T> {
+      const cx<T> A = hf * (V + conj(Vp));
+      const cx<T> B = hf * mul_mi(V - conj(Vp));
+      return mk<T>((w * A).re, (w * B).re);
+    };
+    const double dm = (lxy + lamz[m] - c_psi) * (lxy + lamz[m] + alpha);
+    const cx<T> Fm = (T)(scale / dm) * dct_out(Vm, Vr, twq[m]);
+    // inverse: Y_m = conj(w_m) [(P_m + Q_{N-m}) + i (Q_m - P_{N-m})], X_N = 0
+    if (mr != m) {
+      const double dr = (lxy + lamz[mr] - c_psi) * (lxy + lamz[mr] + alpha);
+      const cx<T> Fr = (T)(scale / dr) * dct_out(Vr, Vm, twq[mr]);
+      buf[m * TL + t] = conj(twq[m]) * mk<T>(Fm.re + Fr.im, Fm.im - Fr.re);
+      buf[mr * TL + t] = conj(twq[mr]) * mk<T>(Fr.re + Fm.im, Fr.im - Fm.re);
+    } else if (m == 0) {
+      buf[t] = Fm;
+    } else {
+      buf[m * TL + t] = conj(twq[m]) * mk<T>(Fm.re + Fm.im, Fm.im - Fm.re);
+    }
+  }
+  __syncthreads();
+  lds_fft<T, true, true>(buf, Nz, logNz, TL, 1, TL, twz);
+  for (int e = threadIdx.x; e < Nz * TL; e += blockDim.x) {
+    const int row = e / TL, t = e - row * TL;
+    const int l = l0 + t;
+    const int pos = (row & 1) ? (Nz - 1 - (row >> 1)) : (row >> 1);
+    if (l < lines) S[row * stride + l] = buf[pos * TL + t];
+  }
 }
 
 // ---- Navier-Stokes projection -------------------------------------------------------
@@ -311,11 +349,19 @@ template <typename T>
 hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, double* piv,
                            double c_psi, double alpha, double scale, hipStream_t st) {
   (void)piv;
-  const int TL = tile_lines(d.nz);
+  int TL = 16;
+  while (TL > 1 && TL * d.nz > 4096) TL >>= 1;
+  int threads = TL * (d.nz >= 4 ? d.nz / 4 : 1);
+  threads = ((threads + 63) / 64) * 64;
+  if (threads > 1024) threads = 1024;
   const int lines = d.lines();
-  const size_t shm = pcr_bytes<T, 1>(d.nz, TL);
-  hipLaunchKernelGGL(k_zpass_ch<T>, dim3((lines + TL - 1) / TL), dim3(TL * d.nz), shm, st, spec,
-                     d.pitch, d.ny, d.nz, tb.lam_x, tb.lam_y, 1.0 / (d.hz * d.hz), c_psi, alpha, scale);
+  int lognz = 0;
+  while ((1 << lognz) < d.nz) ++lognz;
+  const size_t shm = (size_t)d.nz * TL * sizeof(cx<T>);
+  // the inverse transforms are unnormalised: fold 1/nz into the spectral scale
+  hipLaunchKernelGGL(k_zpass_ch<T>, dim3((lines + TL - 1) / TL), dim3(threads), shm, st, spec, d.pitch,
+                     d.ny, d.nz, lognz, TL, tb.lam_x, tb.lam_y, tb.lam_z, tb.tw_z, tb.tw_zq, c_psi, alpha,
+                     scale / d.nz);
   return hipGetLastError();
 }
 
