@@ -195,7 +195,9 @@ __global__ void __launch_bounds__(kBlock)
                  T fihx, T fihy, T fihz, int cnx, int cny, int cnz, int ry, int KB,
                  StepConsts c) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int CX = blockDim.x, CY = blockDim.y;
+  // the block has 2 CY rows of threads: all of them load tiles and evaluate G, the lower CY
+  // rows (one thread per coarse cell) also form the restricted sums
+  const int CX = blockDim.x, CY = blockDim.y / 2;
   int bx, by, bz;
   xcd_tile(bx, by, bz);
   const int i0 = bx * CX, j0 = by * CY, k0 = bz * KB;
@@ -205,7 +207,7 @@ __global__ void __launch_bounds__(kBlock)
   T* sP = reinterpret_cast<T*>(smem);  // 6 slots of phi^{n+1}
   T* sG = sP + 6 * PP;                 // 4 slots of G
   const int tid = threadIdx.y * CX + threadIdx.x;
-  const int nth = CX * CY;
+  const int nth = CX * blockDim.y;
   const bool first = c.first != 0;
   const T ihx2 = fihx * fihx, ihy2 = fihy * fihy, ihz2 = fihz * fihz;
   const T cn2 = (T)c.cn2, S = (T)c.S;
@@ -252,6 +254,7 @@ __global__ void __launch_bounds__(kBlock)
   const int plane = cnx * cny;
   const int ndy = ry + 1;
   for (int k = k0; k < k0 + KB; ++k) {
+    if (ty < CY) {
     // Separable sums of the tensor-product rule: per z layer and y row, x sums over the
     // centre pair (dx 0,1) and the face pair (dx 1,2); then y pairs, then z pairs. The 1/8
     // weight is applied once at the end (a centre-located y axis without refinement counts
@@ -317,6 +320,7 @@ __global__ void __launch_bounds__(kBlock)
     if (k == 0) {
       r.mu_xz[id] = mu(phxz_b);
       r.mu_yz[id] = mu(phyz_b);
+    }
     }
     if (k + 1 < k0 + KB) {
       // next coarse layer: fine phi layers 2k+4, 2k+5 replace 2k-2, 2k-1; G on 2k+3, 2k+4
@@ -422,7 +426,7 @@ hipError_t launch_restrict_g(const Dims& f, const Dims& c, const StepConsts& k, 
   if (KB > c.nz) KB = c.nz;
   const int GX = 2 * CX + 1, GY = ry * CY + 1;
   const size_t shm = (size_t)(6 * (GX + 2) * (GY + 2) + 4 * GX * GY) * sizeof(T);
-  hipLaunchKernelGGL(k_restrict_g<T>, dim3(c.nx / CX, c.ny / CY, c.nz / KB), dim3(CX, CY, 1), shm, st,
+  hipLaunchKernelGGL(k_restrict_g<T>, dim3(c.nx / CX, c.ny / CY, c.nz / KB), dim3(CX, 2 * CY, 1), shm, st,
                      phinew, phin, phinm1, r, f.nx, f.ny, f.nz, (T)f.ihx, (T)f.ihy, (T)f.ihz, c.nx,
                      c.ny, c.nz, ry, KB, k);
   return hipGetLastError();

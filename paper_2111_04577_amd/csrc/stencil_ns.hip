@@ -7,9 +7,8 @@
 //                     (1/rho0) grad p^n + (1/rho - 1/rho0) grad p*, the explicit nu_m L u*,
 //                     the polymer divergence of the second approach (eq. NS12, drop = polymer
 //                     phase), the variable-viscosity stress divergence, the capillary force
-//                     G grad(phi) and the body force. One launch covers the three components:
-//                     blockIdx.z runs over (component, z layer), so the component is uniform
-//                     within a block and each thread keeps only one component's terms live.
+//                     G grad(phi) and the body force. One launch covers the three components
+//                     (uniform per block), interleaved layer by layer.
 //   polymer_stage  -- one stage of the second-order TVD Runge-Kutta update of the polymer
 //                     stress (eqs. NS42, NS44) for the Oldroyd-B law in stress form.
 //
@@ -264,8 +263,10 @@ __global__ void __launch_bounds__(kBlock)
   xcd_tile(bx, by, bz);
   const int i = bx * blockDim.x + threadIdx.x;
   const int j = by * blockDim.y + threadIdx.y;
-  const int comp = bz / nz;
-  const int k = bz - comp * nz;
+  // blockIdx.z = 3 k + component: the three components of one layer are neighbouring tiles,
+  // so each XCD's slab covers all of them and the shared inputs stay in its L2
+  const int k = bz / 3;
+  const int comp = bz - 3 * k;
   const int f = c.first;
   MomCtx<T> m{{in.un, in.unm1, nx, ny, nz, f},
               {in.vn, in.vnm1, nx, ny, nz, f},
