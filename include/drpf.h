@@ -192,6 +192,45 @@ int drpf_profile_end(drpf_grid* g, double* total_ms, int* launches, int n);
 /* Short name of kernel id (see above); "" for an unknown id. */
 const char* drpf_kernel_name(int id);
 
+/* ---- discrete adjoint (FP64 grids only) --------------------------------------------
+ * The transpose of the Jacobian of one drpf_step, for gradients of a functional of the
+ * final state by reverse accumulation. Not in the paper: it differentiates the discrete
+ * step of Sec. 3.2 (every stencil, transfer (eqs. dual1-dual3) and spectral solve
+ * transposed; the fused Dong solve of eqs. NS25-NS27, the velocity Helmholtz solves and the
+ * pseudo-inverse Poisson solve of eqs. NS36-NS37 are symmetric and reused as they are).
+ *
+ * Adjoint state: the same levels as drpf_state without the spare fine buffer. phi[l] fine,
+ * the others coarse; tau only when viscoelastic != 0 (may be null otherwise). */
+typedef struct drpf_adj {
+  void* phi[2];
+  void* u[2];
+  void* v[2];
+  void* w[2];
+  void* p[2];
+  void* tau[2][6];
+} drpf_adj;
+
+/* Bytes of the second device workspace the adjoint needs (forward intermediates of the
+ * recomputed step and the adjoint stage buffers). DRPF_EUNSUPPORTED unless precision 64. */
+int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes);
+
+/* Hands the grid that workspace (device memory, 256-byte aligned, at least the size above;
+ * it stays the caller's and must outlive the grid's adjoint calls). */
+int drpf_adjoint_attach(drpf_grid* g, void* d_workspace, size_t bytes);
+
+/* One reverse step. x_n is the state before the step (its step counter selects the
+ * first-step scheme); it is read only. On entry *lam holds the adjoint of the state after
+ * the step (lam->X[0]: level n+1, lam->X[1]: level n); on exit, with the pointers of *lam
+ * swapped in place (no copies), the adjoint of x_n (lam->X[0]: level n, lam->X[1]: level
+ * n-1). For the functional J = <lam_in, step(x_n)> this is dJ/dx_n; d_grad3 (device, three
+ * doubles) is incremented by (dJ/dtheta_bottom per radian, dJ/dPe, dJ/dWi). The top-wall
+ * layer of both w levels of the adjoint is set to 0 (w is identically 0 there). Recomputes
+ * the forward step internally (the restricted set of the grid's workspace is overwritten).
+ * Queued on `stream`; no synchronisation. DRPF_EUNSUPPORTED for FP32 grids, DRPF_EINVAL
+ * without an attached workspace or with null pointers. */
+int drpf_adjoint_step(drpf_grid* g, const drpf_state* x_n, drpf_adj* lam, double* d_grad3,
+                      void* stream);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char* drpf_last_error(void);
 

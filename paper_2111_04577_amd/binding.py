@@ -51,6 +51,15 @@ class State(ctypes.Structure):
     ]
 
 
+class Adj(ctypes.Structure):
+    _fields_ = [
+        ("phi", ctypes.c_void_p * 2),
+        ("u", ctypes.c_void_p * 2), ("v", ctypes.c_void_p * 2), ("w", ctypes.c_void_p * 2),
+        ("p", ctypes.c_void_p * 2),
+        ("tau", (ctypes.c_void_p * 6) * 2),
+    ]
+
+
 _LIB = None
 
 
@@ -79,6 +88,9 @@ def lib():
             "drpf_debug_field": [vp, i, P(vp), P(sz)],
             "drpf_profile_begin": [vp, i, vp],
             "drpf_profile_end": [vp, P(d), P(i), i],
+            "drpf_adjoint_workspace_bytes": [P(Params), P(sz)],
+            "drpf_adjoint_attach": [vp, vp, sz],
+            "drpf_adjoint_step": [vp, P(State), P(Adj), vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -177,12 +189,116 @@ class DeviceState:
     def step(self) -> int:
         return int(self.c.step)
 
+    def snapshot(self) -> dict:
+        """Device copies of both levels of every field and the step counter."""
+        snap = {"phi": [self.phi[0].clone(), self.phi[1].clone()],
+                "u": [a.clone() for a in self.u], "v": [a.clone() for a in self.v],
+                "w": [a.clone() for a in self.w], "p": [a.clone() for a in self.p],
+                "step": self.step}
+        if self.tau is not None:
+            snap["tau"] = [[a.clone() for a in self.tau[lvl]] for lvl in range(2)]
+        return snap
+
+    @classmethod
+    def view(cls, grid: "Grid", snap: dict, spare):
+        """A state over existing tensors (a snapshot) without copies; ``spare`` is the fine
+        buffer a forward step would write into."""
+        self = cls.__new__(cls)
+        self.grid = grid
+        self.tensors = []
+        self.phi = [snap["phi"][0], snap["phi"][1], spare]
+        for name in ("u", "v", "w", "p"):
+            setattr(self, name, list(snap[name]))
+        self.tau = [list(snap["tau"][lvl]) for lvl in range(2)] if "tau" in snap else None
+        self.tensors = list(self.phi) + self.u + self.v + self.w + self.p
+        if self.tau is not None:
+            self.tensors += self.tau[0] + self.tau[1]
+        self.c = State()
+        self.c.step = int(snap["step"])
+        self._push()
+        return self
+
+    def restore(self, snap: dict):
+        """Copies a snapshot back into this state's buffers (device to device)."""
+        self.phi[0].copy_(snap["phi"][0])
+        self.phi[1].copy_(snap["phi"][1])
+        for name in ("u", "v", "w", "p"):
+            for a in range(2):
+                getattr(self, name)[a].copy_(snap[name][a])
+        if self.tau is not None:
+            for lvl in range(2):
+                for m in range(6):
+                    self.tau[lvl][m].copy_(snap["tau"][lvl][m])
+        self.c.step = int(snap["step"])
+        return self
+
     def to_host(self) -> dict:
         """Copy to FP64 numpy arrays: {phi, u, v, w, p: [level n, level n-1], tau, step}."""
         h = lambda x: x.detach().double().cpu().numpy()
         out = {"phi": [h(self.phi[0]), h(self.phi[1])],
                "u": [h(a) for a in self.u], "v": [h(a) for a in self.v],
                "w": [h(a) for a in self.w], "p": [h(a) for a in self.p], "step": self.step}
+        if self.tau is not None:
+            out["tau"] = [[h(a) for a in self.tau[lvl]] for lvl in range(2)]
+        else:
+            z = np.zeros(self.grid.coarse_shape)
+            out["tau"] = [[z.copy() for _ in range(6)] for _ in range(2)]
+        return out
+
+
+class DeviceAdj:
+    """Adjoint-state tensors (FP64, both levels) plus the drpf_adj struct pointing at them."""
+
+    FIELDS = ("phi", "u", "v", "w", "p")
+
+    def __init__(self, grid: "Grid", host: dict | None = None):
+        import torch
+        self.grid = grid
+        dev = grid.device
+        f64 = torch.float64
+        shape = {"phi": grid.fine_shape}
+        self.tensors = []
+
+        def mk(name, arr=None):
+            sh = shape.get(name, grid.coarse_shape)
+            if arr is None:
+                x = torch.zeros(sh, dtype=f64, device=dev)
+            else:
+                x = torch.as_tensor(np.ascontiguousarray(arr), dtype=f64, device=dev).contiguous().clone()
+            self.tensors.append(x)
+            return x
+
+        for name in self.FIELDS:
+            setattr(self, name, [mk(name, None if host is None else host[name][a]) for a in range(2)])
+        if grid.params.viscoelastic:
+            self.tau = [[mk("tau", None if host is None else host["tau"][lvl][m]) for m in range(6)]
+                        for lvl in range(2)]
+        else:
+            self.tau = None
+        self.c = Adj()
+        self._push()
+
+    def _push(self):
+        for name in self.FIELDS:
+            arr = getattr(self.c, name)
+            for a in range(2):
+                arr[a] = getattr(self, name)[a].data_ptr()
+        if self.tau is not None:
+            for lvl in range(2):
+                for m in range(6):
+                    self.c.tau[lvl][m] = self.tau[lvl][m].data_ptr()
+
+    def _pull(self):
+        by_ptr = {x.data_ptr(): x for x in self.tensors}
+        for name in self.FIELDS:
+            arr = getattr(self.c, name)
+            setattr(self, name, [by_ptr[arr[a]] for a in range(2)])
+        if self.tau is not None:
+            self.tau = [[by_ptr[self.c.tau[lvl][m]] for m in range(6)] for lvl in range(2)]
+
+    def to_host(self) -> dict:
+        h = lambda x: x.detach().cpu().numpy()
+        out = {name: [h(a) for a in getattr(self, name)] for name in self.FIELDS}
         if self.tau is not None:
             out["tau"] = [[h(a) for a in self.tau[lvl]] for lvl in range(2)]
         else:
@@ -232,6 +348,31 @@ class Grid:
         _check(lib().drpf_step(self.handle, ctypes.byref(st.c), int(nsteps), _stream_ptr(stream)))
         st._pull()
         return st
+
+    def attach_adjoint(self, stream=None):
+        """Allocates and attaches the adjoint workspace (FP64 grids)."""
+        import torch
+        if getattr(self, "adj_workspace", None) is not None:
+            return self
+        L = lib()
+        nb = ctypes.c_size_t()
+        _check(L.drpf_adjoint_workspace_bytes(ctypes.byref(self.params), ctypes.byref(nb)))
+        self.adj_workspace = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+        base = self.adj_workspace.data_ptr()
+        _check(L.drpf_adjoint_attach(self.handle, ctypes.c_void_p(base + (-base) % 256),
+                                     ctypes.c_size_t(int(nb.value))))
+        return self
+
+    def adjoint(self, host: dict | None = None) -> DeviceAdj:
+        return DeviceAdj(self, host)
+
+    def adjoint_step(self, st: DeviceState, lam: DeviceAdj, grad3, stream=None):
+        """One reverse step (drpf_adjoint_step): lam goes from the adjoint of step(st) to the
+        adjoint of st; grad3 (device FP64 tensor of 3) is incremented."""
+        _check(lib().drpf_adjoint_step(self.handle, ctypes.byref(st.c), ctypes.byref(lam.c),
+                                       ctypes.c_void_p(grad3.data_ptr()), _stream_ptr(stream)))
+        lam._pull()
+        return lam
 
     def observables(self, st: DeviceState, stream=None) -> dict:
         out = (ctypes.c_double * 5)()

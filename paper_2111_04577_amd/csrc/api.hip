@@ -158,6 +158,8 @@ struct drpf_grid {
   StepConsts k1, k2;
   char* ws;
   Offsets o;
+  // adjoint workspace (FP64 grids), attached by drpf_adjoint_attach
+  char* aws = nullptr;
   // per-kernel timing: one event after each launch, one at the start of profiling
   bool prof = false;
   std::vector<hipEvent_t> ev;
@@ -281,8 +283,24 @@ void mark(drpf_grid* g, int kernel, hipStream_t st) {
   ++g->ev_used;
 }
 
+// Pointers of one step: the two input levels of every field, and where the step writes its
+// results. The outputs may alias the n-1 inputs (u, v, w, p, tau): each output is written only
+// after the last read of that input.
 template <typename T>
-int step_impl(drpf_grid* g, drpf_state* s, int nsteps, hipStream_t st) {
+struct StepIO {
+  const T *phin, *phinm1;
+  T* phinew;
+  const T *un, *unm1, *vn, *vnm1, *wn, *wnm1, *pn, *pnm1;
+  T *uo, *vo, *wo, *po;
+  const T* taun[6];
+  const T* taunm1[6];
+  T* tauo[6];
+};
+
+// One coupled step (Sec. 3.2): Cahn-Hilliard, restriction, Navier-Stokes, polymer stress.
+// Leaves the restricted coarse set and the first polymer stage in the workspace.
+template <typename T>
+int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t st) {
   const Dims& F = g->F;
   const Dims& C = g->C;
   const Tables<T> tf = tables<T>(g, g->o.tf), tc = tables<T>(g, g->o.tc);
@@ -294,92 +312,116 @@ int step_impl(drpf_grid* g, drpf_state* s, int nsteps, hipStream_t st) {
   const Restricted<T> R = rset<T>(g);
   const size_t nc = C.cells();
   const bool ve = g->p.viscoelastic != 0;
+  // ---- Cahn-Hilliard on the fine grid
+  ChIn<T> ci{io.phin, io.phinm1, io.un, io.unm1, io.vn, io.vnm1, io.wn, io.wnm1};
+  HIPCHK(launch_ch_rhs<T>(F, C, K, ci, Rf, st), "ch_rhs");
+  mark(g, 0, st);
+  const T* inf[4] = {Rf, nullptr, nullptr, nullptr};
+  HIPCHK(launch_fft_x_fwd<T>(F, tf, inf, 1, Sf, st), "fft_x fine");
+  mark(g, 1, st);
+  HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, false, st), "fft_y fine");
+  mark(g, 2, st);
+  HIPCHK(launch_zpass_ch<T>(F, tf, Sf, piv, K.c_psi, K.alpha, 1.0 / ((double)F.nx * F.ny), st),
+         "zpass_ch");
+  mark(g, 3, st);
+  HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, true, st), "ifft_y fine");
+  mark(g, 4, st);
+  RealSet<T> of;
+  memset(&of, 0, sizeof(of));
+  of.p[0] = io.phinew;
+  of.nfields = 1;
+  HIPCHK(launch_fft_x_inv<T>(F, tf, Sf, of, st), "ifft_x fine");
+  mark(g, 5, st);
+  // ---- restriction, chemical potential, properties
+  HIPCHK(launch_restrict_g<T>(F, C, K, io.phinew, io.phin, io.phinm1, R, st), "restrict_g");
+  mark(g, 6, st);
+  // ---- Navier-Stokes on the coarse grid
+  NsIn<T> ni;
+  ni.un = io.un;
+  ni.unm1 = io.unm1;
+  ni.vn = io.vn;
+  ni.vnm1 = io.vnm1;
+  ni.wn = io.wn;
+  ni.wnm1 = io.wnm1;
+  ni.pn = io.pn;
+  ni.pnm1 = io.pnm1;
+  for (int m = 0; m < 6; ++m) {
+    ni.taun[m] = ve ? io.taun[m] : nullptr;
+    ni.taunm1[m] = ve ? io.taunm1[m] : nullptr;
+  }
+  ni.viscoelastic = ve ? 1 : 0;
+  HIPCHK(launch_momentum_rhs<T>(C, K, ni, R, Rc, Rc + nc, Rc + 2 * nc, st), "momentum_rhs");
+  mark(g, 7, st);
+  const T* inc[4] = {Rc, Rc + nc, Rc + 2 * nc, nullptr};
+  HIPCHK(launch_fft_x_fwd<T>(C, tc, inc, 3, Sc, st), "fft_x coarse");
+  mark(g, 8, st);
+  HIPCHK(launch_fft_y<T>(C, tc, Sc, 3, false, st), "fft_y coarse");
+  mark(g, 9, st);
+  HIPCHK(launch_zpass_ns<T>(C, tc, Sc, piv, K, 1.0 / ((double)C.nx * C.ny), st), "zpass_ns");
+  mark(g, 10, st);
+  HIPCHK(launch_fft_y<T>(C, tc, Sc, 4, true, st), "ifft_y coarse");
+  mark(g, 11, st);
+  RealSet<T> oc;
+  memset(&oc, 0, sizeof(oc));
+  oc.p[0] = io.uo;
+  oc.p[1] = io.vo;
+  oc.p[2] = io.wo;
+  oc.p[3] = io.po;
+  oc.add[3] = io.pn;
+  oc.nfields = 4;
+  HIPCHK(launch_fft_x_inv<T>(C, tc, Sc, oc, st), "ifft_x coarse");
+  mark(g, 12, st);
+  // ---- polymer stress, RK2-TVD with u^{n+1}
+  if (ve) {
+    T* t1[6];
+    const T* t1c[6];
+    for (int m = 0; m < 6; ++m) {
+      t1[m] = reinterpret_cast<T*>(g->ws + g->o.tau1[m]);
+      t1c[m] = t1[m];
+    }
+    HIPCHK(launch_polymer_stage<T>(C, K, io.uo, io.vo, io.wo, io.taun, io.taun, t1, 0.0, 1.0, st),
+           "polymer stage 1");
+    mark(g, 13, st);
+    HIPCHK(launch_polymer_stage<T>(C, K, io.uo, io.vo, io.wo, io.taun, t1c, io.tauo, 0.5, 0.5, st),
+           "polymer stage 2");
+    mark(g, 14, st);
+  }
+  return DRPF_OK;
+}
+
+template <typename T>
+StepIO<T> state_io(const drpf_state* s) {
+  StepIO<T> io;
+  io.phin = (const T*)s->phi[0];
+  io.phinm1 = (const T*)s->phi[1];
+  io.phinew = (T*)s->phi[2];
+  io.un = (const T*)s->u[0];
+  io.unm1 = (const T*)s->u[1];
+  io.vn = (const T*)s->v[0];
+  io.vnm1 = (const T*)s->v[1];
+  io.wn = (const T*)s->w[0];
+  io.wnm1 = (const T*)s->w[1];
+  io.pn = (const T*)s->p[0];
+  io.pnm1 = (const T*)s->p[1];
+  io.uo = (T*)s->u[1];
+  io.vo = (T*)s->v[1];
+  io.wo = (T*)s->w[1];
+  io.po = (T*)s->p[1];
+  for (int m = 0; m < 6; ++m) {
+    io.taun[m] = (const T*)s->tau[0][m];
+    io.taunm1[m] = (const T*)s->tau[1][m];
+    io.tauo[m] = (T*)s->tau[1][m];
+  }
+  return io;
+}
+
+template <typename T>
+int step_impl(drpf_grid* g, drpf_state* s, int nsteps, hipStream_t st) {
+  const bool ve = g->p.viscoelastic != 0;
   for (int n = 0; n < nsteps; ++n) {
     const StepConsts& K = s->step == 0 ? g->k1 : g->k2;
-    T* phin = (T*)s->phi[0];
-    T* phinm1 = (T*)s->phi[1];
-    T* phinew = (T*)s->phi[2];
-    // ---- Cahn-Hilliard on the fine grid
-    ChIn<T> ci{phin, phinm1, (const T*)s->u[0], (const T*)s->u[1], (const T*)s->v[0],
-               (const T*)s->v[1], (const T*)s->w[0], (const T*)s->w[1]};
-    HIPCHK(launch_ch_rhs<T>(F, C, K, ci, Rf, st), "ch_rhs");
-    mark(g, 0, st);
-    const T* inf[4] = {Rf, nullptr, nullptr, nullptr};
-    HIPCHK(launch_fft_x_fwd<T>(F, tf, inf, 1, Sf, st), "fft_x fine");
-    mark(g, 1, st);
-    HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, false, st), "fft_y fine");
-    mark(g, 2, st);
-    HIPCHK(launch_zpass_ch<T>(F, tf, Sf, piv, K.c_psi, K.alpha, 1.0 / ((double)F.nx * F.ny), st),
-           "zpass_ch");
-    mark(g, 3, st);
-    HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, true, st), "ifft_y fine");
-    mark(g, 4, st);
-    RealSet<T> of;
-    memset(&of, 0, sizeof(of));
-    of.p[0] = phinew;
-    of.nfields = 1;
-    HIPCHK(launch_fft_x_inv<T>(F, tf, Sf, of, st), "ifft_x fine");
-    mark(g, 5, st);
-    // ---- restriction, chemical potential, properties
-    HIPCHK(launch_restrict_g<T>(F, C, K, phinew, phin, phinm1, R, st), "restrict_g");
-    mark(g, 6, st);
-    // ---- Navier-Stokes on the coarse grid
-    NsIn<T> ni;
-    ni.un = (const T*)s->u[0];
-    ni.unm1 = (const T*)s->u[1];
-    ni.vn = (const T*)s->v[0];
-    ni.vnm1 = (const T*)s->v[1];
-    ni.wn = (const T*)s->w[0];
-    ni.wnm1 = (const T*)s->w[1];
-    ni.pn = (const T*)s->p[0];
-    ni.pnm1 = (const T*)s->p[1];
-    for (int m = 0; m < 6; ++m) {
-      ni.taun[m] = ve ? (const T*)s->tau[0][m] : nullptr;
-      ni.taunm1[m] = ve ? (const T*)s->tau[1][m] : nullptr;
-    }
-    ni.viscoelastic = ve ? 1 : 0;
-    HIPCHK(launch_momentum_rhs<T>(C, K, ni, R, Rc, Rc + nc, Rc + 2 * nc, st), "momentum_rhs");
-    mark(g, 7, st);
-    const T* inc[4] = {Rc, Rc + nc, Rc + 2 * nc, nullptr};
-    HIPCHK(launch_fft_x_fwd<T>(C, tc, inc, 3, Sc, st), "fft_x coarse");
-    mark(g, 8, st);
-    HIPCHK(launch_fft_y<T>(C, tc, Sc, 3, false, st), "fft_y coarse");
-    mark(g, 9, st);
-    HIPCHK(launch_zpass_ns<T>(C, tc, Sc, piv, K, 1.0 / ((double)C.nx * C.ny), st), "zpass_ns");
-    mark(g, 10, st);
-    HIPCHK(launch_fft_y<T>(C, tc, Sc, 4, true, st), "ifft_y coarse");
-    mark(g, 11, st);
-    RealSet<T> oc;
-    memset(&oc, 0, sizeof(oc));
-    oc.p[0] = (T*)s->u[1];
-    oc.p[1] = (T*)s->v[1];
-    oc.p[2] = (T*)s->w[1];
-    oc.p[3] = (T*)s->p[1];
-    oc.add[3] = (const T*)s->p[0];
-    oc.nfields = 4;
-    HIPCHK(launch_fft_x_inv<T>(C, tc, Sc, oc, st), "ifft_x coarse");
-    mark(g, 12, st);
-    // ---- polymer stress, RK2-TVD with u^{n+1}
-    if (ve) {
-      const T* tn[6];
-      T* t1[6];
-      T* tout[6];
-      for (int m = 0; m < 6; ++m) {
-        tn[m] = (const T*)s->tau[0][m];
-        t1[m] = reinterpret_cast<T*>(g->ws + g->o.tau1[m]);
-        tout[m] = (T*)s->tau[1][m];
-      }
-      const T* t1c[6];
-      for (int m = 0; m < 6; ++m) t1c[m] = t1[m];
-      HIPCHK(launch_polymer_stage<T>(C, K, (const T*)s->u[1], (const T*)s->v[1], (const T*)s->w[1],
-                                     tn, tn, t1, 0.0, 1.0, st),
-             "polymer stage 1");
-      mark(g, 13, st);
-      HIPCHK(launch_polymer_stage<T>(C, K, (const T*)s->u[1], (const T*)s->v[1], (const T*)s->w[1],
-                                     tn, t1c, tout, 0.5, 0.5, st),
-             "polymer stage 2");
-      mark(g, 14, st);
-    }
+    const int rc = step_one<T>(g, state_io<T>(s), K, st);
+    if (rc) return rc;
     // ---- rotate time levels (pointer swaps only)
     void* ph0 = s->phi[0];
     void* ph1 = s->phi[1];
@@ -436,6 +478,204 @@ int observables_impl(drpf_grid* g, const drpf_state* s, double* out, int n, hipS
   const int m = n < DRPF_OBS_COUNT ? n : DRPF_OBS_COUNT;
   for (int i = 0; i < m; ++i) out[i] = host[i];
   if (host[5] != 0.0) return fail(DRPF_ENONFINITE, "phase field holds non-finite values");
+  return DRPF_OK;
+}
+
+// Adjoint workspace: forward intermediates of the recomputed step, then the adjoint stage
+// buffers (FP64).
+struct AdjLayout {
+  size_t phinew, lG, lQ;                                     // fine
+  size_t unew, vnew, wnew, pnew, taunew[6], lt1[6], lL[9], lu[3];
+  size_t mu[3], lph_f[3], lG_f[3], lX, lY, lZ, lExy, lph_xy, lj[3], J[3], lph_c, lG_c;
+  size_t lExz, lEyz, lph_xz, lph_yz;                         // nz + 1 layers
+  size_t part;
+  int nbA, nbM, nbF;
+  size_t total;
+};
+
+AdjLayout adj_layout(const Dims& F, const Dims& C) {
+  Carver cv;
+  AdjLayout a;
+  const size_t nf = F.cells() * 8, nc = C.cells() * 8, ne = (size_t)C.nx * C.ny * (C.nz + 1) * 8;
+  a.phinew = cv.take(nf);
+  a.lG = cv.take(nf);
+  a.lQ = cv.take(nf);
+  a.unew = cv.take(nc);
+  a.vnew = cv.take(nc);
+  a.wnew = cv.take(nc);
+  a.pnew = cv.take(nc);
+  for (int m = 0; m < 6; ++m) a.taunew[m] = cv.take(nc);
+  for (int m = 0; m < 6; ++m) a.lt1[m] = cv.take(nc);
+  for (int m = 0; m < 9; ++m) a.lL[m] = cv.take(nc);
+  for (int m = 0; m < 3; ++m) a.lu[m] = cv.take(nc);
+  for (int m = 0; m < 3; ++m) a.mu[m] = cv.take(nc);
+  for (int m = 0; m < 3; ++m) a.lph_f[m] = cv.take(nc);
+  for (int m = 0; m < 3; ++m) a.lG_f[m] = cv.take(nc);
+  a.lX = cv.take(nc);
+  a.lY = cv.take(nc);
+  a.lZ = cv.take(nc);
+  a.lExy = cv.take(nc);
+  a.lph_xy = cv.take(nc);
+  for (int m = 0; m < 3; ++m) a.lj[m] = cv.take(nc);
+  for (int m = 0; m < 3; ++m) a.J[m] = cv.take(nc);
+  a.lph_c = cv.take(nc);
+  a.lG_c = cv.take(nc);
+  a.lExz = cv.take(ne);
+  a.lEyz = cv.take(ne);
+  a.lph_xz = cv.take(ne);
+  a.lph_yz = cv.take(ne);
+  a.nbA = adj_blocks(C.nx, C.ny, C.nz);
+  a.nbM = adj_blocks(C.nx, C.ny, 3 * C.nz);
+  a.nbF = adj_blocks(F.nx, F.ny, F.nz);
+  a.part = cv.take((size_t)(2 * a.nbA + a.nbM + 2 * a.nbF) * 8);
+  a.total = cv.off;
+  return a;
+}
+
+int adjoint_impl(drpf_grid* g, const drpf_state* x, drpf_adj* lam, double* d_grad3, hipStream_t st) {
+  using T = double;
+  const Dims& F = g->F;
+  const Dims& C = g->C;
+  const StepConsts& K = x->step == 0 ? g->k1 : g->k2;
+  const bool ve = g->p.viscoelastic != 0;
+  const AdjLayout A = adj_layout(F, C);
+  auto P = [&](size_t off) { return reinterpret_cast<T*>(g->aws + off); };
+  const Tables<T> tf = tables<T>(g, g->o.tf), tc = tables<T>(g, g->o.tc);
+  T* Rc = reinterpret_cast<T*>(g->ws + g->o.rc);
+  cx<T>* Sc = reinterpret_cast<cx<T>*>(g->ws + g->o.sc);
+  cx<T>* Sf = reinterpret_cast<cx<T>*>(g->ws + g->o.sf);
+  double* piv = reinterpret_cast<double*>(g->ws + g->o.piv);
+  const size_t nc = C.cells();
+  // ---- forward recompute of the step from x_n, results into the adjoint workspace
+  StepIO<T> io = state_io<T>(x);
+  io.phinew = P(A.phinew);
+  io.uo = P(A.unew);
+  io.vo = P(A.vnew);
+  io.wo = P(A.wnew);
+  io.po = P(A.pnew);
+  for (int m = 0; m < 6; ++m) io.tauo[m] = P(A.taunew[m]);
+  int rc = step_one<T>(g, io, K, st);
+  if (rc) return rc;
+  double* part = P(A.part);
+  // ---- polymer
+  const T* lu_use[3] = {(const T*)lam->u[0], (const T*)lam->v[0], (const T*)lam->w[0]};
+  if (ve) {
+    const T* lt[6];
+    const T* tn[6];
+    const T* t1[6];
+    T* l1[6];
+    T* lL[9];
+    T* ot0[6];
+    for (int m = 0; m < 6; ++m) {
+      lt[m] = (const T*)lam->tau[0][m];
+      tn[m] = (const T*)x->tau[0][m];
+      t1[m] = reinterpret_cast<const T*>(g->ws + g->o.tau1[m]);
+      l1[m] = P(A.lt1[m]);
+      ot0[m] = (T*)lam->tau[1][m];
+    }
+    for (int m = 0; m < 9; ++m) lL[m] = P(A.lL[m]);
+    HIPCHK(launch_adj_polymer(C, K, P(A.unew), P(A.vnew), P(A.wnew), lt, tn, t1, l1, lL, ot0, lu_use[0],
+                              lu_use[1], lu_use[2], P(A.lu[0]), P(A.lu[1]), P(A.lu[2]), part, st),
+           "adjoint polymer");
+    for (int a = 0; a < 3; ++a) lu_use[a] = P(A.lu[a]);
+  }
+  // ---- projection and velocity Helmholtz, transposed
+  HIPCHK(launch_fft_x_fwd<T>(C, tc, lu_use, 3, Sc, st), "adjoint fft_x coarse");
+  const T* lpin[4] = {(const T*)lam->p[0], nullptr, nullptr, nullptr};
+  HIPCHK(launch_fft_x_fwd<T>(C, tc, lpin, 1, Sc + 3 * C.spec(), st), "adjoint fft_x coarse p");
+  HIPCHK(launch_fft_y<T>(C, tc, Sc, 4, false, st), "adjoint fft_y coarse");
+  HIPCHK(launch_zpass_ns_adj(C, tc, Sc, K, 1.0 / ((double)C.nx * C.ny), st), "adjoint zpass_ns");
+  HIPCHK(launch_fft_y<T>(C, tc, Sc, 3, true, st), "adjoint ifft_y coarse");
+  RealSet<T> oc;
+  memset(&oc, 0, sizeof(oc));
+  oc.p[0] = Rc;
+  oc.p[1] = Rc + nc;
+  oc.p[2] = Rc + 2 * nc;
+  oc.nfields = 3;
+  HIPCHK(launch_fft_x_inv<T>(C, tc, Sc, oc, st), "adjoint ifft_x coarse");
+  // ---- momentum right-hand side, transposed
+  NsIn<T> ni;
+  ni.un = io.un;
+  ni.unm1 = io.unm1;
+  ni.vn = io.vn;
+  ni.vnm1 = io.vnm1;
+  ni.wn = io.wn;
+  ni.wnm1 = io.wnm1;
+  ni.pn = io.pn;
+  ni.pnm1 = io.pnm1;
+  for (int m = 0; m < 6; ++m) {
+    ni.taun[m] = ve ? io.taun[m] : nullptr;
+    ni.taunm1[m] = ve ? io.taunm1[m] : nullptr;
+  }
+  ni.viscoelastic = ve ? 1 : 0;
+  AdjMomBufs b;
+  for (int a = 0; a < 3; ++a) {
+    b.mu[a] = P(A.mu[a]);
+    b.lph_f[a] = P(A.lph_f[a]);
+    b.lG_f[a] = P(A.lG_f[a]);
+    b.lj[a] = P(A.lj[a]);
+    b.J[a] = P(A.J[a]);
+  }
+  b.lX = P(A.lX);
+  b.lY = P(A.lY);
+  b.lZ = P(A.lZ);
+  b.lExy = P(A.lExy);
+  b.lExz = P(A.lExz);
+  b.lEyz = P(A.lEyz);
+  b.lph_xy = P(A.lph_xy);
+  b.lph_xz = P(A.lph_xz);
+  b.lph_yz = P(A.lph_yz);
+  b.lph_c = P(A.lph_c);
+  b.lG_c = P(A.lG_c);
+  T* ot0[6];
+  T* ot1[6];
+  for (int m = 0; m < 6; ++m) {
+    ot0[m] = ve ? (T*)lam->tau[1][m] : nullptr;
+    ot1[m] = ve ? (T*)lam->tau[0][m] : nullptr;
+  }
+  T* const u0 = (T*)lam->u[1];
+  T* const u1 = (T*)lam->u[0];
+  T* const v0 = (T*)lam->v[1];
+  T* const v1 = (T*)lam->v[0];
+  T* const w0 = (T*)lam->w[1];
+  T* const w1 = (T*)lam->w[0];
+  HIPCHK(launch_adj_momentum(C, K, ni, rset<T>(g), Rc, b, (T*)lam->p[1], (T*)lam->p[0], ot0, ot1, u0, u1, v0,
+                             v1, w0, w1, part + 2 * A.nbA, st),
+         "adjoint momentum");
+  // ---- restriction and chemical potential, transposed; then the fused CH solve
+  HIPCHK(launch_adj_restrict_ch(F, C, K, b, (const T*)lam->phi[0], P(A.lG), P(A.lQ), st), "adjoint restrict");
+  const T* inf[4] = {P(A.lQ), nullptr, nullptr, nullptr};
+  HIPCHK(launch_fft_x_fwd<T>(F, tf, inf, 1, Sf, st), "adjoint fft_x fine");
+  HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, false, st), "adjoint fft_y fine");
+  HIPCHK(launch_zpass_ch<T>(F, tf, Sf, piv, K.c_psi, K.alpha, 1.0 / ((double)F.nx * F.ny), st),
+         "adjoint zpass_ch");
+  HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, true, st), "adjoint ifft_y fine");
+  RealSet<T> of;
+  memset(&of, 0, sizeof(of));
+  of.p[0] = P(A.lQ);
+  of.nfields = 1;
+  HIPCHK(launch_fft_x_inv<T>(F, tf, Sf, of, st), "adjoint ifft_x fine");
+  const double sin_bot = sin(g->p.theta_bottom_deg * M_PI / 180.0);
+  const int off_th = 2 * A.nbA + A.nbM, off_pe2 = off_th + A.nbF;
+  HIPCHK(launch_adj_ch(F, C, K, P(A.lQ), P(A.lG), io.phin, io.phinm1, P(A.phinew), io.un, io.unm1, io.vn,
+                       io.vnm1, io.wn, io.wnm1, sin_bot, (T*)lam->phi[1], (T*)lam->phi[0], u0, u1, v0, v1, w0,
+                       w1, part + off_th, part + off_pe2, st),
+         "adjoint Cahn-Hilliard");
+  HIPCHK(launch_adj_final(part, ve ? 2 * A.nbA : 0, 2 * A.nbA, A.nbM, off_th, A.nbF, off_pe2, d_grad3, st),
+         "adjoint gradient sums");
+  // ---- the adjoint of level n was accumulated in the [1] buffers, that of n-1 in [0]
+  auto swap = [](void*& a, void*& b2) {
+    void* t = a;
+    a = b2;
+    b2 = t;
+  };
+  swap(lam->phi[0], lam->phi[1]);
+  swap(lam->u[0], lam->u[1]);
+  swap(lam->v[0], lam->v[1]);
+  swap(lam->w[0], lam->w[1]);
+  swap(lam->p[0], lam->p[1]);
+  if (ve)
+    for (int m = 0; m < 6; ++m) swap(lam->tau[0][m], lam->tau[1][m]);
   return DRPF_OK;
 }
 
@@ -690,6 +930,48 @@ int drpf_debug_field(drpf_grid* g, int id, void** ptr, size_t* count) {
     return DRPF_OK;
   }
   return fail(DRPF_EINVAL, "unknown debug field id");
+}
+
+int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes) {
+  const int rc = drpf_validate(p);
+  if (rc) return rc;
+  if (!bytes) return fail(DRPF_EINVAL, "null output");
+  if (p->precision != 64) return fail(DRPF_EUNSUPPORTED, "the adjoint runs on FP64 grids only");
+  const int ry = p->ny == 1 ? 1 : 2;
+  const Dims F = make_dims(2 * p->nx, ry * p->ny, 2 * p->nz, p->lx, p->ly, p->lz);
+  const Dims C = make_dims(p->nx, p->ny, p->nz, p->lx, p->ly, p->lz);
+  *bytes = adj_layout(F, C).total;
+  return DRPF_OK;
+}
+
+int drpf_adjoint_attach(drpf_grid* g, void* d_workspace, size_t bytes) {
+  if (!g) return fail(DRPF_EINVAL, "null grid");
+  if (g->p.precision != 64) return fail(DRPF_EUNSUPPORTED, "the adjoint runs on FP64 grids only");
+  if (!d_workspace) return fail(DRPF_EWORKSPACE, "null adjoint workspace");
+  if (((uintptr_t)d_workspace & 255) != 0) return fail(DRPF_EWORKSPACE, "adjoint workspace must be 256-byte aligned");
+  const size_t need = adj_layout(g->F, g->C).total;
+  if (bytes < need)
+    return fail(DRPF_EWORKSPACE, "adjoint workspace too small: need " + std::to_string(need) + " bytes");
+  g->aws = (char*)d_workspace;
+  return DRPF_OK;
+}
+
+int drpf_adjoint_step(drpf_grid* g, const drpf_state* x, drpf_adj* lam, double* d_grad3, void* stream) {
+  if (!g || !x || !lam || !d_grad3) return fail(DRPF_EINVAL, "null argument");
+  if (g->p.precision != 64) return fail(DRPF_EUNSUPPORTED, "the adjoint runs on FP64 grids only");
+  if (!g->aws) return fail(DRPF_EINVAL, "no adjoint workspace attached");
+  if (!x->phi[0] || !x->phi[1] || !x->u[0] || !x->u[1] || !x->v[0] || !x->v[1] || !x->w[0] || !x->w[1] ||
+      !x->p[0] || !x->p[1])
+    return fail(DRPF_EINVAL, "null state pointer");
+  for (int l = 0; l < 2; ++l)
+    if (!lam->phi[l] || !lam->u[l] || !lam->v[l] || !lam->w[l] || !lam->p[l])
+      return fail(DRPF_EINVAL, "null adjoint pointer");
+  if (g->p.viscoelastic)
+    for (int l = 0; l < 2; ++l)
+      for (int m = 0; m < 6; ++m)
+        if (!x->tau[l][m] || !lam->tau[l][m]) return fail(DRPF_EINVAL, "null polymer stress pointer");
+  if (x->step < 0) return fail(DRPF_EINVAL, "negative step counter");
+  return adjoint_impl(g, x, lam, d_grad3, (hipStream_t)stream);
 }
 
 }  // extern "C"

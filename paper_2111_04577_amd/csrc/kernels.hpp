@@ -85,6 +85,54 @@ hipError_t launch_polymer_stage(const Dims& c, const StepConsts& k, const T* u, 
                                 const T* w, const T* const tau_n[6], const T* const tau_in[6],
                                 T* const tau_out[6], double c0, double c1, hipStream_t st);
 
+// ---- adjoint.hip (FP64) ----------------------------------------------------------------
+// Adjoint buffers of the momentum stage (coarse; lExz, lEyz, lph_xz, lph_yz have nz + 1
+// layers, the others nz).
+struct AdjMomBufs {
+  double *mu[3], *lph_f[3], *lG_f[3];
+  double *lX, *lY, *lZ, *lExy, *lExz, *lEyz;
+  double *lph_xy, *lph_xz, *lph_yz;
+  double *lj[3], *J[3];
+  double *lph_c, *lG_c;
+};
+// number of blocks of a launch3(nx, ny, nz_blocks) grid (one partial sum per block)
+int adj_blocks(int nx, int ny, int nz_blocks);
+// Polymer RK2 transposed: lt1, lL (9) scratch; out_tau0 += stress adjoint of tau^n; lu, lv,
+// lw = lam_u^{n+1} + velocity adjoint from the polymer update. Partials: dJ/dWi, 2 regions of
+// adj_blocks(nx, ny, nz).
+hipError_t launch_adj_polymer(const Dims& c, const StepConsts& k, const double* u, const double* v,
+                              const double* w, const double* const lam_tau[6],
+                              const double* const tau_n[6], const double* const tau_1[6],
+                              double* const lt1[6], double* const lL[9], double* const out_tau0[6],
+                              const double* lu_in, const double* lv_in, const double* lw_in,
+                              double* lu, double* lv, double* lw, double* part, hipStream_t st);
+// Projection and velocity Helmholtz transposed, per Fourier mode (spec4: lam_u, lam_v, lam_w,
+// lam_p on entry; lam_r (3 fields) on exit).
+hipError_t launch_zpass_ns_adj(const Dims& d, const Tables<double>& tb, cx<double>* spec4,
+                               const StepConsts& c, double scale, hipStream_t st);
+// Momentum right-hand side transposed. lr: lam_r (3 fields of nc). Partials: dJ/dPe through
+// c_j, adj_blocks(nx, ny, 3 nz).
+hipError_t launch_adj_momentum(const Dims& c, const StepConsts& k, NsIn<double> in, Restricted<double> R,
+                               const double* lr, const AdjMomBufs& b, double* lp_n, double* lp_nm1,
+                               double* const out_tau0[6], double* const out_tau1[6], double* u0,
+                               double* u1, double* v0, double* v1, double* w0, double* w1,
+                               double* part, hipStream_t st);
+// Restriction and chemical potential transposed: lG (fine) and the adjoint of phi^{n+1}.
+hipError_t launch_adj_restrict_ch(const Dims& f, const Dims& c, const StepConsts& k, const AdjMomBufs& b,
+                                  const double* lphi_new_in, double* lG, double* lphi, hipStream_t st);
+// Cahn-Hilliard right-hand side and prolongation transposed. Partials: theta and Pe, each
+// adj_blocks(fnx, fny, fnz).
+hipError_t launch_adj_ch(const Dims& f, const Dims& c, const StepConsts& k, const double* lQ,
+                         const double* lG, const double* phin, const double* phinm1,
+                         const double* phinew, const double* un, const double* unm1, const double* vn,
+                         const double* vnm1, const double* wn, const double* wnm1, double sin_bot,
+                         double* lphi_n, double* lphi_nm1, double* u0, double* u1, double* v0,
+                         double* v1, double* w0, double* w1, double* part_theta, double* part_pe,
+                         hipStream_t st);
+// grad3 += (sum of theta partials, Pe partials, Wi partials)
+hipError_t launch_adj_final(const double* part, int n_wi, int off_pe1, int n_pe1, int off_th, int n_f,
+                            int off_pe2, double* grad3, hipStream_t st);
+
 // ---- reduce.hip -----------------------------------------------------------------------
 // Writes DRPF_OBS_COUNT doubles to out_dev (device), using `partial` (device scratch of
 // reduce_partials() doubles). Returns also a non-finite flag in out_dev[DRPF_OBS_COUNT].

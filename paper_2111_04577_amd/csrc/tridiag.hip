@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(1024)
   const double av = nu_m * ihz * ihz;
   cx<T> uv[2];
   uv[0] = valid ? sc * spec[at] : mk<T>(0, 0);
-  uv[1] = (valid && Ny > 1) ? sc * spec[fsz + at] : mk<T>(0, 0);
+  uv[1] = valid ? sc * spec[fsz + at] : mk<T>(0, 0);
   PcrLds<T, 2> L2 = carve<T, 2>(smem, Nz, TL);
   pcr<T, 2>(L2, Nz, TL, row, line, row == 0 ? (T)0 : (T)av,
             (T)(nu_m * lxy - (end ? 3.0 : 2.0) * av - g_dt), row == Nz - 1 ? (T)0 : (T)av, uv);
@@ -320,13 +320,123 @@ __global__ void __launch_bounds__(1024)
   const double pr = p[0].re, pi = p[0].im;
   if (valid) {
     spec[at] = mk<T>((T)(u.re - c * (gxr * pr - gxi * pi)), (T)(u.im - c * (gxr * pi + gxi * pr)));
-    if (Ny > 1)
-      spec[fsz + at] = mk<T>((T)(v.re - c * (gyr * pr - gyi * pi)), (T)(v.im - c * (gyr * pi + gyi * pr)));
+    spec[fsz + at] = mk<T>((T)(v.re - c * (gyr * pr - gyi * pi)), (T)(v.im - c * (gyr * pi + gyi * pr)));
     const cx<double> wv = wk;
     spec[2 * fsz + at] = row < Nz - 1
                              ? mk<T>((T)(wv.re - c * (pup.re - pr) * ihz), (T)(wv.im - c * (pup.im - pi) * ihz))
                              : mk<T>(0, 0);
     spec[3 * fsz + at] = mk<T>((T)pr, (T)pi);
+  }
+}
+
+// ---- Navier-Stokes projection, transposed (FP64) --------------------------------------
+// With Pi = I - G P+ D the projection (P+ the pseudo-inverse of the Neumann Laplacian, whose
+// transpose is itself; G^T = -D with the top-wall w held at zero) and p^{n+1} = p^n + k P+ D u~
+// (k = gamma0 rho0 / dt), the transpose maps (lam_u, lam_p) to
+//   lam_u~ = lam_u - G P+ (D lam_u + k lam_p),
+// and the velocity Helmholtz operators are symmetric, so lam_r = H^{-1} lam_u~ by the same
+// per-mode solves. P+ discards the mean of its right-hand side (the (0,0) line's z-mean)
+// before the pinned solve. spec holds lam_u, lam_v, lam_w, lam_p on entry and lam_r in the
+// first three fields on exit.
+__global__ void __launch_bounds__(1024)
+    k_zpass_ns_adj(cx<double>* __restrict__ spec, int P, int Ny, int Nz, const double* __restrict__ lamx,
+                   const double* __restrict__ lamy, const double* __restrict__ phx,
+                   const double* __restrict__ phy, double ihx, double ihy, double ihz, double nu_m,
+                   double g_dt, double g_rho_dt, double scale) {
+  using T = double;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int TL = blockDim.x / Nz;
+  const int line = threadIdx.x % TL;
+  const int row = threadIdx.x / TL;
+  const int lines = P * Ny;
+  const int l = blockIdx.x * TL + line;
+  const bool valid = l < lines;
+  const int lc = valid ? l : lines - 1;
+  const int ky = lc / P, kx = lc - ky * P;
+  const size_t stride = (size_t)lines;
+  const size_t fsz = stride * Nz;
+  const size_t at = row * stride + l;
+  const double lxy = lamx[kx] + lamy[ky];
+  const bool end = row == 0 || row == Nz - 1;
+  const bool top = row == Nz - 1;
+  const cx<T> u = valid ? scale * spec[at] : mk<T>(0, 0);
+  const cx<T> v = valid ? scale * spec[fsz + at] : mk<T>(0, 0);
+  const cx<T> w = (valid && !top) ? scale * spec[2 * fsz + at] : mk<T>(0, 0);
+  const cx<T> lp = valid ? scale * spec[3 * fsz + at] : mk<T>(0, 0);
+  const double cxr = phx[2 * kx], cxi = phx[2 * kx + 1];
+  const double cyr = phy[2 * ky], cyi = phy[2 * ky + 1];
+  // ---- right-hand side D lam_u + k lam_p
+  cx<T>* Ls = reinterpret_cast<cx<T>*>(smem);
+  Ls[row * TL + line] = w;
+  __syncthreads();
+  const cx<T> wm = row > 0 ? Ls[(row - 1) * TL + line] : mk<T>(0, 0);
+  const double dxr = (1.0 - cxr) * ihx, dxi = cxi * ihx;
+  const double dyr = (1.0 - cyr) * ihy, dyi = cyi * ihy;
+  cx<T> p[1];
+  p[0] = mk<T>(dxr * u.re - dxi * u.im + dyr * v.re - dyi * v.im + (w.re - wm.re) * ihz + g_rho_dt * lp.re,
+               dxr * u.im + dxi * u.re + dyr * v.im + dyi * v.re + (w.im - wm.im) * ihz + g_rho_dt * lp.im);
+  __syncthreads();
+  // ---- the (0,0) line: drop the z-mean of the right-hand side (pseudo-inverse)
+  const bool pinned = kx == 0 && ky == 0;
+  Ls[row * TL + line] = p[0];
+  __syncthreads();
+  if (pinned) {
+    double mre = 0, mim = 0;
+    for (int k = 0; k < Nz; ++k) {
+      mre += Ls[k * TL + line].re;
+      mim += Ls[k * TL + line].im;
+    }
+    p[0] = mk<T>(p[0].re - mre / Nz, p[0].im - mim / Nz);
+  }
+  __syncthreads();
+  // ---- Poisson, pinned at row 0 for the (0,0) line, then its mean removed
+  const double ap = ihz * ihz;
+  double pa = row == 0 ? 0.0 : ap, pc = row == Nz - 1 ? 0.0 : ap;
+  double pb = lxy - (end ? 1.0 : 2.0) * ap;
+  if (pinned) {
+    if (row == 0) { pa = 0.0; pc = 0.0; pb = 1.0; p[0] = mk<T>(0, 0); }
+    if (row == 1) pa = 0.0;
+  }
+  PcrLds<double, 1> LP = carve<double, 1>(smem, Nz, TL);
+  pcr<double, 1>(LP, Nz, TL, row, line, pa, pb, pc, p);
+  cx<T>* Lp = reinterpret_cast<cx<T>*>(smem);
+  Lp[row * TL + line] = p[0];
+  __syncthreads();
+  cx<T> pup = row < Nz - 1 ? Lp[(row + 1) * TL + line] : mk<T>(0, 0);
+  if (pinned) {
+    double mre = 0, mim = 0;
+    for (int k = 0; k < Nz; ++k) {
+      mre += Lp[k * TL + line].re;
+      mim += Lp[k * TL + line].im;
+    }
+    mre /= Nz;
+    mim /= Nz;
+    p[0] = mk<T>(p[0].re - mre, p[0].im - mim);
+    pup = mk<T>(pup.re - mre, pup.im - mim);
+  }
+  __syncthreads();
+  // ---- lam_u~ = lam_u - G q
+  const double gxr = (cxr - 1.0) * ihx, gxi = cxi * ihx;
+  const double gyr = (cyr - 1.0) * ihy, gyi = cyi * ihy;
+  const double pr = p[0].re, pi = p[0].im;
+  cx<T> uv[2];
+  uv[0] = mk<T>(u.re - (gxr * pr - gxi * pi), u.im - (gxr * pi + gxi * pr));
+  uv[1] = mk<T>(v.re - (gyr * pr - gyi * pi), v.im - (gyr * pi + gyi * pr));
+  cx<T> wt[1];
+  wt[0] = top ? mk<T>(0, 0) : mk<T>(w.re - (pup.re - pr) * ihz, w.im - (pup.im - pi) * ihz);
+  // ---- velocity Helmholtz solves (the forward operators, symmetric)
+  const double av = nu_m * ihz * ihz;
+  PcrLds<T, 2> L2 = carve<T, 2>(smem, Nz, TL);
+  pcr<T, 2>(L2, Nz, TL, row, line, row == 0 ? 0.0 : av, nu_m * lxy - (end ? 3.0 : 2.0) * av - g_dt,
+            row == Nz - 1 ? 0.0 : av, uv);
+  PcrLds<T, 1> L1 = carve<T, 1>(smem, Nz, TL);
+  pcr<T, 1>(L1, Nz, TL, row, line, (row == 0 || top) ? 0.0 : av, top ? 1.0 : nu_m * lxy - 2.0 * av - g_dt,
+            (row >= Nz - 2) ? 0.0 : av, wt);
+  if (top) wt[0] = mk<T>(0, 0);
+  if (valid) {
+    spec[at] = uv[0];
+    spec[fsz + at] = uv[1];
+    spec[2 * fsz + at] = wt[0];
   }
 }
 
@@ -377,6 +487,17 @@ hipError_t launch_zpass_ns(const Dims& d, const Tables<T>& tb, cx<T>* spec4, dou
   hipLaunchKernelGGL(k_zpass_ns<T>, dim3((lines + TL - 1) / TL), dim3(TL * d.nz), shm, st, spec4,
                      d.pitch, d.ny, d.nz, tb.lam_x, tb.lam_y, tb.ph_x, tb.ph_y, 1.0 / d.hx, 1.0 / d.hy,
                      1.0 / d.hz, c.nu_m, c.gamma0 / c.dt, c.gamma0 * c.rho0 / c.dt, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_zpass_ns_adj(const Dims& d, const Tables<double>& tb, cx<double>* spec4,
+                               const StepConsts& c, double scale, hipStream_t st) {
+  const int TL = tile_lines(d.nz);
+  const int lines = d.lines();
+  size_t shm = pcr_bytes<double, 2>(d.nz, TL);
+  hipLaunchKernelGGL(k_zpass_ns_adj, dim3((lines + TL - 1) / TL), dim3(TL * d.nz), shm, st, spec4, d.pitch,
+                     d.ny, d.nz, tb.lam_x, tb.lam_y, tb.ph_x, tb.ph_y, 1.0 / d.hx, 1.0 / d.hy, 1.0 / d.hz,
+                     c.nu_m, c.gamma0 / c.dt, c.gamma0 * c.rho0 / c.dt, scale);
   return hipGetLastError();
 }
 

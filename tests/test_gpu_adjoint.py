@@ -1,0 +1,212 @@
+"""GPU parity of the discrete adjoint: drpf_adjoint_step (through the C-ABI) against the
+oracle's adjoint (reverse differentiation of the FP64 oracle step, itself pinned by central
+finite differences in test_oracle_adjoint.py), and trajectory gradients through the
+checkpointed autograd function against the oracle and against central finite differences of
+the GPU forward step.
+
+Tolerances. State adjoints: 1e-10 of the largest adjoint entry over all fields. dJ/dtheta and
+dJ/dWi: 1e-10 relative. dJ/dPe: Pe enters the Cahn-Hilliard step through terms of size
+Pe/(dt Cn^2) that cancel to leave a derivative ~1e7 times smaller; the oracle's reverse
+differentiation sums those terms separately and carries ~1e-9 relative rounding (the GPU
+groups them pointwise), so the bound is 1e-6 relative. Trajectory gradients against central
+differences: 1e-6 relative.
+"""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adjoint as OA
+from oracle import model
+from oracle import step as S
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("phi", "u", "v", "w", "p")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def drpf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2111_04577_amd as P
+    P.lib()
+    return P
+
+
+def adjoint_errors(got, ref, viscoelastic):
+    scale = max(float(np.max(np.abs(ref[f][l]))) for f in FIELDS for l in range(2))
+    errs = {f"{f}{l}": float(np.max(np.abs(got[f][l] - ref[f][l]))) / scale for f in FIELDS for l in range(2)}
+    if viscoelastic:
+        scale_t = max(scale, max(float(np.max(np.abs(ref["tau"][l][c]))) for l in range(2) for c in range(6)))
+        for l in range(2):
+            errs[f"tau{l}"] = max(float(np.max(np.abs(got["tau"][l][c] - ref["tau"][l][c])))
+                                  for c in range(6)) / scale_t
+    return errs
+
+
+def gpu_adjoint_step(drpf, cfg, st, lam):
+    import torch
+    g = drpf.Grid(cfg, 64).attach_adjoint()
+    x = g.state(st)
+    L = g.adjoint(lam)
+    g3 = torch.zeros(3, dtype=torch.float64, device=g.device)
+    g.adjoint_step(x, L, g3)
+    torch.cuda.synchronize()
+    return L.to_host(), g3.cpu().numpy(), x.to_host()
+
+
+def check_grad(g, ref, name_tol=(1e-10, 1e-6, 1e-10)):
+    for a, (tol, name) in enumerate(zip(name_tol, ("theta", "Pe", "Wi"))):
+        if ref[a] == 0.0:
+            assert abs(g[a]) < 1e-300 or abs(g[a]) < 1e-14, (name, g[a])
+            continue
+        assert abs(g[a] - ref[a]) <= tol * abs(ref[a]), (name, g[a], ref[a])
+
+
+STEP_CASES = [
+    ("C4", dict(nx=16, nz=8, noise=1e-2)),          # 2D Oldroyd-B
+    ("C1", dict(nx=16, nz=8, noise=1e-2)),          # 2D Newtonian
+    ("C3", dict(nx=8, ny=4, nz=8, noise=1e-2)),     # 3D Oldroyd-B
+    ("C5", dict(nx=8, ny=4, nz=8, noise=1e-2)),     # 3D Oldroyd-B, density / viscosity contrast
+    ("C2", dict(nx=8, ny=4, nz=8, noise=0.0)),      # 3D Newtonian, ratios 1000 / 100
+]
+
+
+@pytest.mark.parametrize("name,kw", STEP_CASES, ids=[c[0] for c in STEP_CASES])
+@pytest.mark.parametrize("before", [0, 3], ids=["first", "bdf2"])
+def test_adjoint_step_matches_oracle(drpf, name, kw, before):
+    cfg = W.config(name, **kw)
+    P = model.Params.from_config(cfg)
+    st = S.run(P, W.droplet_state(cfg), before)
+    lam = W.adjoint_seed(cfg, 11 + before)
+    say(f"[gpu] adjoint step {name} {cfg.nx}x{cfg.ny}x{cfg.nz} after {before} steps")
+    ref, gref = OA.adjoint_step(P, st, lam)
+    got, g, xh = gpu_adjoint_step(drpf, cfg, st, lam)
+    errs = adjoint_errors(got, ref, cfg.viscoelastic)
+    say("  errors", {k: f"{v:.1e}" for k, v in errs.items()}, "grad", g, gref)
+    assert max(errs.values()) < 1e-10, errs
+    check_grad(g, gref)
+    # x_n is read only
+    for f in FIELDS:
+        for l in range(2):
+            assert np.array_equal(xh[f][l], st[f][l]), f
+
+
+@pytest.mark.parametrize("name,kw", STEP_CASES[:1] + STEP_CASES[2:3], ids=["C4", "C3"])
+def test_adjoint_step_is_linear_and_deterministic(drpf, name, kw):
+    """The adjoint of a*lam1 + b*lam2 is a*adj(lam1) + b*adj(lam2); repeated calls agree bit
+    for bit (fixed-order partial sums)."""
+    cfg = W.config(name, **kw)
+    P = model.Params.from_config(cfg)
+    st = S.run(P, W.droplet_state(cfg), 2)
+    l1, l2 = W.adjoint_seed(cfg, 1), W.adjoint_seed(cfg, 2)
+    comb = {f: [2.0 * l1[f][l] - 0.5 * l2[f][l] for l in range(2)] for f in FIELDS}
+    comb["tau"] = [[2.0 * l1["tau"][l][c] - 0.5 * l2["tau"][l][c] for c in range(6)] for l in range(2)]
+    a1, g1, _ = gpu_adjoint_step(drpf, cfg, st, l1)
+    a2, g2, _ = gpu_adjoint_step(drpf, cfg, st, l2)
+    ac, gc, _ = gpu_adjoint_step(drpf, cfg, st, comb)
+    ac2, gc2, _ = gpu_adjoint_step(drpf, cfg, st, comb)
+    lin = {f: [2.0 * a1[f][l] - 0.5 * a2[f][l] for l in range(2)] for f in FIELDS}
+    lin["tau"] = [[2.0 * a1["tau"][l][c] - 0.5 * a2["tau"][l][c] for c in range(6)] for l in range(2)]
+    errs = adjoint_errors(ac, lin, cfg.viscoelastic)
+    assert max(errs.values()) < 1e-12, errs
+    assert np.allclose(gc, 2.0 * g1 - 0.5 * g2, rtol=1e-10, atol=1e-300)
+    for f in FIELDS:
+        for l in range(2):
+            assert np.array_equal(ac[f][l], ac2[f][l])
+    assert np.array_equal(gc, gc2)
+
+
+def _fd(drpf, cfg, nsteps, which, rel_eps, obs="wetted_radius"):
+    """Central difference of the GPU FP64 forward's observable in one parameter."""
+    import torch
+
+    def J(c):
+        g = drpf.Grid(c, 64)
+        st = g.state(W.droplet_state(c))
+        g.step(st, nsteps)
+        torch.cuda.synchronize()
+        return g.observables(st)[obs]
+
+    if which == "theta":
+        x0 = math.radians(cfg.theta_bottom_deg)
+        e = rel_eps * x0
+        f = lambda x: J(cfg.replace(theta_bottom_deg=math.degrees(x)))
+    else:
+        x0 = getattr(cfg, which)
+        e = rel_eps * x0
+        f = lambda x: J(cfg.replace(**{which: x}))
+    return (f(x0 + e) - f(x0 - e)) / (2 * e)
+
+
+def _autograd(cfg, nsteps, every, observable):
+    import torch
+    import paper_2111_04577_amd.adjoint as ADJ
+    th = torch.tensor(math.radians(cfg.theta_bottom_deg), dtype=torch.float64, requires_grad=True)
+    pe = torch.tensor(cfg.pe, dtype=torch.float64, requires_grad=True)
+    wi = torch.tensor(cfg.wi, dtype=torch.float64, requires_grad=True)
+    outs = ADJ.run(th, pe, wi, cfg, W.droplet_state(cfg), nsteps, every)
+    J = getattr(ADJ, observable)(cfg, outs[0])
+    J.backward()
+    return float(J), np.array([float(th.grad), float(pe.grad), float(wi.grad)])
+
+
+@pytest.mark.parametrize("observable", ["wetted_radius", "centroid_height"])
+def test_trajectory_gradient_small(drpf, observable):
+    """20 steps of a fast-spreading 2D viscoelastic drop, checkpoints every 6 steps (a short
+    last segment): gradients equal the oracle's reverse differentiation through the unrolled
+    steps and central differences of the GPU forward."""
+    cfg = W.config("C4", nx=32, nz=16, cn=0.04, pe=75.0, dt=5e-3, noise=0.0)
+    P = model.Params.from_config(cfg)
+    N = 20
+    say(f"[gpu] trajectory gradient {observable} {cfg.nx}x{cfg.nz} {N} steps")
+    J, g = _autograd(cfg, N, 6, observable)
+    Jr, gr = OA.trajectory_gradient(P, W.droplet_state(cfg), N, getattr(OA, observable))
+    say("  J", J, Jr, "grad", g, gr)
+    assert abs(J - Jr) <= 1e-12 * abs(Jr)
+    check_grad(g, gr, (1e-9, 1e-6, 1e-9))
+    for a, which in enumerate(("theta", "pe", "wi")):
+        fd = _fd(drpf, cfg, N, which, 1e-4, observable)
+        say("  fd", which, fd, g[a])
+        assert abs(fd - g[a]) <= 1e-6 * abs(g[a]), (which, fd, g[a])
+
+
+def test_adjoint_step_full_size_c4(drpf):
+    """One reverse step on the full 2D viscoelastic grid (256x128 coarse, 512x256 fine), after
+    five forward steps, element by element against the oracle."""
+    cfg = W.config("C4", noise=1e-3, seed=5)
+    P = model.Params.from_config(cfg)
+    st = S.run(P, W.droplet_state(cfg), 5)
+    lam = W.adjoint_seed(cfg, 21)
+    say("[gpu] adjoint step C4 full size")
+    ref, gref = OA.adjoint_step(P, st, lam)
+    got, g, _ = gpu_adjoint_step(drpf, cfg, st, lam)
+    errs = adjoint_errors(got, ref, True)
+    say("  errors", {k: f"{v:.1e}" for k, v in errs.items()}, "grad", g, gref)
+    assert max(errs.values()) < 1e-10, errs
+    check_grad(g, gref)
+
+
+def test_gradient_case_c4_fd(drpf):
+    """The gradient case: the full 2D viscoelastic drop, 2000 steps with checkpoints every 50,
+    final wetted radius differentiated with respect to the static angle, Pe and Wi, against
+    central differences (relative step 1e-5) of the GPU FP64 forward."""
+    cfg = W.config("C4")
+    N = cfg.steps
+    say(f"[gpu] gradient case C4 {N} steps")
+    J, g = _autograd(cfg, N, 50, "wetted_radius")
+    say("  J", J, "grad", g)
+    for a, which in enumerate(("theta", "pe", "wi")):
+        fd = _fd(drpf, cfg, N, which, 1e-5)
+        say("  fd", which, fd, g[a], abs(fd - g[a]) / abs(g[a]))
+        assert abs(fd - g[a]) <= 1e-6 * abs(g[a]), (which, fd, g[a])

@@ -19,7 +19,7 @@ import math
 import numpy as np
 
 __all__ = ["Config", "CONFIGS", "config", "initial_phi", "splitmix64_uniform", "fine_shape",
-           "coarse_shape", "droplet_state"]
+           "coarse_shape", "droplet_state", "adjoint_seed"]
 
 
 @dataclasses.dataclass
@@ -154,3 +154,25 @@ def droplet_state(cfg: Config) -> dict:
         "tau": [[z() for _ in range(6)], [z() for _ in range(6)]],
         "step": 0,
     }
+
+
+def adjoint_seed(cfg: Config, seed: int) -> dict:
+    """A state-shaped set of arrays with entries uniform in [-1, 1) from the SplitMix64 stream
+    of ``seed`` (fields in the order phi, u, v, w, p, tau; level n before n-1), used as the
+    adjoint of a state in reverse-step tests. The polymer part is zero for a Newtonian case."""
+    fs, cs = fine_shape(cfg), coarse_shape(cfg)
+    shapes = [fs, fs] + [cs] * 8 + ([cs] * 12 if cfg.viscoelastic else [])
+    n = sum(int(np.prod(s)) for s in shapes)
+    r = 2.0 * splitmix64_uniform(seed, n) - 1.0
+    out, pos = [], 0
+    for s in shapes:
+        m = int(np.prod(s))
+        out.append(np.ascontiguousarray(r[pos:pos + m].reshape(s)))
+        pos += m
+    lam = {"phi": out[0:2], "u": out[2:4], "v": out[4:6], "w": out[6:8], "p": out[8:10]}
+    if cfg.viscoelastic:
+        lam["tau"] = [out[10:16], out[16:22]]
+    else:
+        lam["tau"] = [[np.zeros(cs) for _ in range(6)] for _ in range(2)]
+    lam["step"] = 0
+    return lam
