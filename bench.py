@@ -47,6 +47,13 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration)")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--only-adjoint", action="store_true",
+                    help="run only the gradient case and print its JSON object")
+    ap.add_argument("--adjoint-config", default="C4")
+    ap.add_argument("--adjoint-steps", type=int, default=None,
+                    help="steps of the gradient case (default: the config's own, 2000 for C4)")
+    ap.add_argument("--adjoint-every", type=int, default=50)
     ap.add_argument("--ingest-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
                     help="turn rocprofv3 --pmc counter CSVs into the traffic summary and exit")
     return ap.parse_args()
@@ -177,6 +184,87 @@ def field_diff(a, b):
     return {k: float(f"{v:.3e}") for k, v in out.items()}
 
 
+def time_adjoint(drpf, W, name, nsteps, every):
+    """The gradient case: d(final wetted radius)/d(theta, Pe, Wi) through nsteps FP64 steps with
+    checkpoints every `every` steps (torch.autograd.Function over drpf_step and
+    drpf_adjoint_step). Times the plain forward run, the checkpointed forward and the
+    backward pass with events on the stream the library launches on, and one reverse step
+    (drpf_adjoint_step alone, which recomputes its forward step) against one forward step."""
+    import torch
+    import paper_2111_04577_amd.adjoint as ADJ
+    cfg = W.config(name)
+    nsteps = nsteps or cfg.steps
+    init = W.droplet_state(cfg)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    g = drpf.Grid(cfg, 64)
+    st = g.state(init)
+    g.step(st, 10)
+    st = g.state(init)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record()
+    g.step(st, nsteps)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1)
+    # one reverse step vs one forward step, on the state after nsteps: with the state after
+    # the step handed in (as in the backward pass) and with the full forward recompute
+    g.attach_adjoint()
+    lam = g.adjoint(W.adjoint_seed(cfg, 1))
+    g3 = torch.zeros(3, dtype=torch.float64, device=g.device)
+    x0 = st.snapshot()
+    g.step(st, 1)
+    xs = type(st).struct_of(x0, bool(cfg.viscoelastic))
+    reps = 50
+
+    def per_call(fn):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    adj_step_ms = per_call(lambda: g.adjoint_step(xs, lam, g3, next_state=st))
+    adj_full_ms = per_call(lambda: g.adjoint_step(xs, lam, g3))
+    del g, st, lam, x0
+    th = torch.tensor(math.radians(cfg.theta_bottom_deg), dtype=torch.float64, requires_grad=True)
+    pe = torch.tensor(cfg.pe, dtype=torch.float64, requires_grad=True)
+    wi = torch.tensor(cfg.wi, dtype=torch.float64, requires_grad=True)
+    t0, t1, t2 = ev(), ev(), ev()
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t0.record()
+    outs = ADJ.run(th, pe, wi, cfg, init, nsteps, every)
+    t1.record()
+    J = ADJ.wetted_radius(cfg, outs[0])
+    J.backward()
+    t2.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ckpt_ms, bwd_ms = t0.elapsed_time(t1), t1.elapsed_time(t2)
+    F, _ = grid_sizes(cfg)
+    return {
+        "workload": f"{cfg.name}: 2D Oldroyd-B drop, coarse {cfg.nx}x{cfg.nz}, fine {F['nx']}x{F['nz']}, "
+                    f"{nsteps} steps, checkpoints every {every}, J = final wetted radius, "
+                    f"theta {cfg.theta_bottom_deg:g} deg, Pe {cfg.pe:g}, Wi {cfg.wi:g}",
+        "dtype": "f64",
+        "fwd_ms_per_step": round(fwd_ms / nsteps, 5),
+        "fwd_ckpt_ms_per_step": round(ckpt_ms / nsteps, 5),
+        "bwd_ms_per_step": round(bwd_ms / nsteps, 5),
+        "adj_fwd": round(bwd_ms / fwd_ms, 3),
+        "adjoint_step_ms": round(adj_step_ms, 5),
+        "adjoint_step_vs_fwd_step": round(adj_step_ms / (fwd_ms / nsteps), 3),
+        "adjoint_step_full_recompute_ms": round(adj_full_ms, 5),
+        "gradient_wall_s": round(wall, 3),
+        "J": float(J.detach()),
+        "grad": {"theta_per_rad": float(th.grad), "pe": float(pe.grad), "wi": float(wi.grad)},
+    }
+
+
 def cpu_baseline(W, cfg, nsteps):
     """The FP64 oracle as it stands on the host, timed over the first nsteps steps."""
     import numpy as np
@@ -234,6 +322,9 @@ def main():
     import workloads as W
     import paper_2111_04577_amd as drpf
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.only_adjoint:
+        print(json.dumps(time_adjoint(drpf, W, a.adjoint_config, a.adjoint_steps, a.adjoint_every)), flush=True)
+        return
     cfg = W.config(a.config)
     F, C = grid_sizes(cfg)
     forms = {"both": (32, 64), "32": (32,), "64": (64,)}[a.precision]
@@ -286,7 +377,12 @@ def main():
         out["fp32_error_vs_fp64"]["after_steps"] = states[32]["step"]
         out["fp32_error_vs_fp64"]["mass_fp32"] = res[32]["observables"]["mass"]
         out["fp32_error_vs_fp64"]["mass_fp64"] = res[64]["observables"]["mass"]
-    out["adj_fwd"] = None
+    if not a.no_adjoint:
+        print(f"[bench] gradient case {a.adjoint_config}", file=sys.stderr, flush=True)
+        out["adjoint"] = time_adjoint(drpf, W, a.adjoint_config, a.adjoint_steps, a.adjoint_every)
+        out["adj_fwd"] = out["adjoint"]["adj_fwd"]
+    else:
+        out["adj_fwd"] = None
     if not a.no_cpu_baseline:
         print(f"[bench] cpu baseline: oracle, {a.cpu_steps} steps", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(W, cfg, a.cpu_steps)

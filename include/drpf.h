@@ -219,17 +219,21 @@ int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes);
 int drpf_adjoint_attach(drpf_grid* g, void* d_workspace, size_t bytes);
 
 /* One reverse step. x_n is the state before the step (its step counter selects the
- * first-step scheme); it is read only. On entry *lam holds the adjoint of the state after
- * the step (lam->X[0]: level n+1, lam->X[1]: level n); on exit, with the pointers of *lam
- * swapped in place (no copies), the adjoint of x_n (lam->X[0]: level n, lam->X[1]: level
- * n-1). For the functional J = <lam_in, step(x_n)> this is dJ/dx_n; d_grad3 (device, three
- * doubles) is incremented by (dJ/dtheta_bottom per radian, dJ/dPe, dJ/dWi). The top-wall
- * layer of both w levels of the adjoint is set to 0 (w is identically 0 there). Recomputes
- * the forward step internally (the restricted set of the grid's workspace is overwritten).
- * Queued on `stream`; no synchronisation. DRPF_EUNSUPPORTED for FP32 grids, DRPF_EINVAL
- * without an attached workspace or with null pointers. */
-int drpf_adjoint_step(drpf_grid* g, const drpf_state* x_n, drpf_adj* lam, double* d_grad3,
-                      void* stream);
+ * first-step scheme); it is read only. x_next, if not null, is the state after the step
+ * (drpf_step's result from x_n: level n+1 in [0], level n in [1], step counter x_n's + 1),
+ * read only; then only the restricted coarse set and the first polymer stage are
+ * recomputed, otherwise the whole forward step is. On entry *lam holds the adjoint of the
+ * state after the step (lam->X[0]: level n+1, lam->X[1]: level n); on exit, with the
+ * pointers of *lam swapped in place (no copies), the adjoint of x_n (lam->X[0]: level n,
+ * lam->X[1]: level n-1). For the functional J = <lam_in, step(x_n)> this is dJ/dx_n;
+ * d_grad3 (device, three doubles) is incremented by (dJ/dtheta_bottom per radian, dJ/dPe,
+ * dJ/dWi). The top-wall layer of both w levels of the adjoint is set to 0 (w is identically
+ * 0 there). The restricted set and stage buffers of the grid's workspace are overwritten.
+ * Queued on `stream`; no synchronisation. DRPF_EUNSUPPORTED for FP32 grids; DRPF_EINVAL
+ * without an attached workspace, with null pointers, or with an x_next whose step counter
+ * is not x_n's + 1. */
+int drpf_adjoint_step(drpf_grid* g, const drpf_state* x_n, const drpf_state* x_next, drpf_adj* lam,
+                      double* d_grad3, void* stream);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char* drpf_last_error(void);

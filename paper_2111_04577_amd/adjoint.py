@@ -4,8 +4,10 @@ forward step and its discrete adjoint (drpf_adjoint_step), with checkpointed rec
 The forward pass runs the steps and keeps a device snapshot of the state every ``every``
 steps. The backward pass walks the segments from the last to the first: it restores the
 segment's snapshot, recomputes the segment's states, and applies the adjoint step to each in
-reverse order. Memory: one snapshot per segment plus one segment of states; work: about one
-extra forward step per step, plus the adjoint step (which recomputes its own forward step).
+reverse order, handing each reverse step the state after it, so that the library recomputes
+only the two forward intermediates it needs (the restricted coarse set and the first polymer
+stage). Memory: one snapshot per segment plus one segment of states (a snapshot is one
+device copy); work: one extra forward step per step plus the reverse step.
 
 Differentiable inputs: the bottom static contact angle theta (radians), Pe and Wi. Outputs:
 phi, u, v, w, p at the final level (device tensors, FP64); any torch function of them can be
@@ -50,17 +52,18 @@ def _make_function():
                     getattr(lam, name)[0].copy_(g)
             grad3 = torch.zeros(3, dtype=torch.float64, device=grid.device)
             N, k = ctx.nsteps, ctx.every
-            spare = st.phi[2]
+            ve = bool(grid.params.viscoelastic)
             for s in reversed(range(len(ctx.ckpts))):
                 start, end = s * k, min(N, s * k + k)
                 st.restore(ctx.ckpts[s])
-                seg = []
+                seg = [ctx.ckpts[s]]
                 for n in range(start, end):
+                    grid.step(st, 1)
                     seg.append(st.snapshot())
-                    if n < end - 1:
-                        grid.step(st, 1)
+                structs = [DeviceState.struct_of(x, ve) for x in seg]
                 for n in reversed(range(start, end)):
-                    grid.adjoint_step(DeviceState.view(grid, seg[n - start], spare), lam, grad3)
+                    i = n - start
+                    grid.adjoint_step(structs[i], lam, grad3, next_state=structs[i + 1])
             ctx.lam0 = lam
             out = [grad3[a].to(dtype=x.dtype, device=x.device) if torch.is_tensor(x) else None
                    for a, x in enumerate(ctx.like)]

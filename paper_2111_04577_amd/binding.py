@@ -90,7 +90,7 @@ def lib():
             "drpf_profile_end": [vp, P(d), P(i), i],
             "drpf_adjoint_workspace_bytes": [P(Params), P(sz)],
             "drpf_adjoint_attach": [vp, vp, sz],
-            "drpf_adjoint_step": [vp, P(State), P(Adj), vp, vp],
+            "drpf_adjoint_step": [vp, P(State), P(State), P(Adj), vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -133,28 +133,42 @@ def _stream_ptr(stream):
 
 
 class DeviceState:
-    """State tensors on the device plus the drpf_state struct pointing at them."""
+    """State tensors on the device plus the drpf_state struct pointing at them.
+
+    All arrays are views of one flat device buffer (three fine phi buffers, then u, v, w, p
+    with two levels each, then the polymer stress when viscoelastic), so a snapshot is one
+    device copy."""
 
     def __init__(self, grid: "Grid", host: dict):
         import torch
         self.grid = grid
         dt = grid.torch_dtype
         dev = grid.device
-        t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev).contiguous()
-        fs, cs = grid.fine_shape, grid.coarse_shape
-        self.tensors = []
-
-        def keep(x):
-            self.tensors.append(x)
-            return x
-
-        self.phi = [keep(t(host["phi"][0])), keep(t(host["phi"][1])), keep(torch.zeros(fs, dtype=dt, device=dev))]
-        self.u = [keep(t(a)) for a in host["u"]]
-        self.v = [keep(t(a)) for a in host["v"]]
-        self.w = [keep(t(a)) for a in host["w"]]
-        self.p = [keep(t(a)) for a in host["p"]]
-        if grid.params.viscoelastic:
-            self.tau = [[keep(t(a)) for a in host["tau"][lvl]] for lvl in range(2)]
+        nf = int(np.prod(grid.fine_shape))
+        nc = int(np.prod(grid.coarse_shape))
+        ve = bool(grid.params.viscoelastic)
+        self.flat = torch.empty(3 * nf + (8 + (12 if ve else 0)) * nc, dtype=dt, device=dev)
+        views = []
+        pos = 0
+        for n, shape in [(nf, grid.fine_shape)] * 3 + [(nc, grid.coarse_shape)] * (8 + (12 if ve else 0)):
+            views.append(self.flat[pos:pos + n].view(shape))
+            pos += n
+        self.tensors = views
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dt)
+        self.phi = views[0:3]
+        self.phi[0].copy_(t(host["phi"][0]))
+        self.phi[1].copy_(t(host["phi"][1]))
+        self.phi[2].zero_()
+        for a, name in enumerate(("u", "v", "w", "p")):
+            lv = views[3 + 2 * a:5 + 2 * a]
+            for l in range(2):
+                lv[l].copy_(t(host[name][l]))
+            setattr(self, name, lv)
+        if ve:
+            self.tau = [views[11 + 6 * l:17 + 6 * l] for l in range(2)]
+            for l in range(2):
+                for m in range(6):
+                    self.tau[l][m].copy_(t(host["tau"][l][m]))
         else:
             self.tau = None
         self.c = State()
@@ -185,52 +199,63 @@ class DeviceState:
         if self.tau is not None:
             self.tau = [[by_ptr[c.tau[lvl][m]] for m in range(6)] for lvl in range(2)]
 
+    def _offsets(self):
+        base, es = self.flat.data_ptr(), self.flat.element_size()
+        c = self.c
+        offs = [(c.phi[a] - base) // es for a in range(3)]
+        for name in ("u", "v", "w", "p"):
+            arr = getattr(c, name)
+            offs += [(arr[a] - base) // es for a in range(2)]
+        if self.tau is not None:
+            offs += [(c.tau[l][m] - base) // es for l in range(2) for m in range(6)]
+        return offs
+
     @property
     def step(self) -> int:
         return int(self.c.step)
 
     def snapshot(self) -> dict:
-        """Device copies of both levels of every field and the step counter."""
-        snap = {"phi": [self.phi[0].clone(), self.phi[1].clone()],
-                "u": [a.clone() for a in self.u], "v": [a.clone() for a in self.v],
-                "w": [a.clone() for a in self.w], "p": [a.clone() for a in self.p],
-                "step": self.step}
-        if self.tau is not None:
-            snap["tau"] = [[a.clone() for a in self.tau[lvl]] for lvl in range(2)]
-        return snap
-
-    @classmethod
-    def view(cls, grid: "Grid", snap: dict, spare):
-        """A state over existing tensors (a snapshot) without copies; ``spare`` is the fine
-        buffer a forward step would write into."""
-        self = cls.__new__(cls)
-        self.grid = grid
-        self.tensors = []
-        self.phi = [snap["phi"][0], snap["phi"][1], spare]
-        for name in ("u", "v", "w", "p"):
-            setattr(self, name, list(snap[name]))
-        self.tau = [list(snap["tau"][lvl]) for lvl in range(2)] if "tau" in snap else None
-        self.tensors = list(self.phi) + self.u + self.v + self.w + self.p
-        if self.tau is not None:
-            self.tensors += self.tau[0] + self.tau[1]
-        self.c = State()
-        self.c.step = int(snap["step"])
-        self._push()
-        return self
+        """One device copy of every buffer, with the current level assignment and step."""
+        return {"flat": self.flat.clone(), "offsets": self._offsets(), "step": self.step}
 
     def restore(self, snap: dict):
-        """Copies a snapshot back into this state's buffers (device to device)."""
-        self.phi[0].copy_(snap["phi"][0])
-        self.phi[1].copy_(snap["phi"][1])
+        """Copies a snapshot back into this state's buffers (one device copy)."""
+        self.flat.copy_(snap["flat"])
+        base, es = self.flat.data_ptr(), self.flat.element_size()
+        offs = iter(snap["offsets"])
+        c = self.c
+        for a in range(3):
+            c.phi[a] = base + es * next(offs)
         for name in ("u", "v", "w", "p"):
+            arr = getattr(c, name)
             for a in range(2):
-                getattr(self, name)[a].copy_(snap[name][a])
+                arr[a] = base + es * next(offs)
         if self.tau is not None:
-            for lvl in range(2):
+            for l in range(2):
                 for m in range(6):
-                    self.tau[lvl][m].copy_(snap["tau"][lvl][m])
-        self.c.step = int(snap["step"])
+                    c.tau[l][m] = base + es * next(offs)
+        c.step = int(snap["step"])
+        self._pull()
         return self
+
+    @staticmethod
+    def struct_of(snap: dict, viscoelastic: bool) -> State:
+        """A drpf_state over a snapshot's buffers (no copies); the snapshot must stay alive."""
+        base, es = snap["flat"].data_ptr(), snap["flat"].element_size()
+        offs = iter(snap["offsets"])
+        c = State()
+        for a in range(3):
+            c.phi[a] = base + es * next(offs)
+        for name in ("u", "v", "w", "p"):
+            arr = getattr(c, name)
+            for a in range(2):
+                arr[a] = base + es * next(offs)
+        if viscoelastic:
+            for l in range(2):
+                for m in range(6):
+                    c.tau[l][m] = base + es * next(offs)
+        c.step = int(snap["step"])
+        return c
 
     def to_host(self) -> dict:
         """Copy to FP64 numpy arrays: {phi, u, v, w, p: [level n, level n-1], tau, step}."""
@@ -366,10 +391,16 @@ class Grid:
     def adjoint(self, host: dict | None = None) -> DeviceAdj:
         return DeviceAdj(self, host)
 
-    def adjoint_step(self, st: DeviceState, lam: DeviceAdj, grad3, stream=None):
+    def adjoint_step(self, st, lam: DeviceAdj, grad3, next_state=None, stream=None):
         """One reverse step (drpf_adjoint_step): lam goes from the adjoint of step(st) to the
-        adjoint of st; grad3 (device FP64 tensor of 3) is incremented."""
-        _check(lib().drpf_adjoint_step(self.handle, ctypes.byref(st.c), ctypes.byref(lam.c),
+        adjoint of st; grad3 (device FP64 tensor of 3) is incremented. ``st`` and
+        ``next_state`` (the state after the step, optional) are DeviceState objects or
+        drpf_state structs."""
+        c = st.c if isinstance(st, DeviceState) else st
+        nxt = None
+        if next_state is not None:
+            nxt = ctypes.byref(next_state.c if isinstance(next_state, DeviceState) else next_state)
+        _check(lib().drpf_adjoint_step(self.handle, ctypes.byref(c), nxt, ctypes.byref(lam.c),
                                        ctypes.c_void_p(grad3.data_ptr()), _stream_ptr(stream)))
         lam._pull()
         return lam

@@ -532,7 +532,8 @@ AdjLayout adj_layout(const Dims& F, const Dims& C) {
   return a;
 }
 
-int adjoint_impl(drpf_grid* g, const drpf_state* x, drpf_adj* lam, double* d_grad3, hipStream_t st) {
+int adjoint_impl(drpf_grid* g, const drpf_state* x, const drpf_state* xn, drpf_adj* lam, double* d_grad3,
+                 hipStream_t st) {
   using T = double;
   const Dims& F = g->F;
   const Dims& C = g->C;
@@ -546,16 +547,33 @@ int adjoint_impl(drpf_grid* g, const drpf_state* x, drpf_adj* lam, double* d_gra
   cx<T>* Sf = reinterpret_cast<cx<T>*>(g->ws + g->o.sf);
   double* piv = reinterpret_cast<double*>(g->ws + g->o.piv);
   const size_t nc = C.cells();
-  // ---- forward recompute of the step from x_n, results into the adjoint workspace
+  // ---- forward intermediates: with the state after the step given, only the restricted
+  // coarse set and the first polymer stage are recomputed; otherwise the whole step is,
+  // into the adjoint workspace
   StepIO<T> io = state_io<T>(x);
-  io.phinew = P(A.phinew);
-  io.uo = P(A.unew);
-  io.vo = P(A.vnew);
-  io.wo = P(A.wnew);
-  io.po = P(A.pnew);
-  for (int m = 0; m < 6; ++m) io.tauo[m] = P(A.taunew[m]);
-  int rc = step_one<T>(g, io, K, st);
-  if (rc) return rc;
+  if (xn) {
+    io.phinew = (T*)xn->phi[0];
+    io.uo = (T*)xn->u[0];
+    io.vo = (T*)xn->v[0];
+    io.wo = (T*)xn->w[0];
+    io.po = (T*)xn->p[0];
+    HIPCHK(launch_restrict_g<T>(F, C, K, io.phinew, io.phin, io.phinm1, rset<T>(g), st), "adjoint restrict_g");
+    if (ve) {
+      T* t1[6];
+      for (int m = 0; m < 6; ++m) t1[m] = reinterpret_cast<T*>(g->ws + g->o.tau1[m]);
+      HIPCHK(launch_polymer_stage<T>(C, K, io.uo, io.vo, io.wo, io.taun, io.taun, t1, 0.0, 1.0, st),
+             "adjoint polymer stage 1");
+    }
+  } else {
+    io.phinew = P(A.phinew);
+    io.uo = P(A.unew);
+    io.vo = P(A.vnew);
+    io.wo = P(A.wnew);
+    io.po = P(A.pnew);
+    for (int m = 0; m < 6; ++m) io.tauo[m] = P(A.taunew[m]);
+    const int rc = step_one<T>(g, io, K, st);
+    if (rc) return rc;
+  }
   double* part = P(A.part);
   // ---- polymer
   const T* lu_use[3] = {(const T*)lam->u[0], (const T*)lam->v[0], (const T*)lam->w[0]};
@@ -574,7 +592,7 @@ int adjoint_impl(drpf_grid* g, const drpf_state* x, drpf_adj* lam, double* d_gra
       ot0[m] = (T*)lam->tau[1][m];
     }
     for (int m = 0; m < 9; ++m) lL[m] = P(A.lL[m]);
-    HIPCHK(launch_adj_polymer(C, K, P(A.unew), P(A.vnew), P(A.wnew), lt, tn, t1, l1, lL, ot0, lu_use[0],
+    HIPCHK(launch_adj_polymer(C, K, io.uo, io.vo, io.wo, lt, tn, t1, l1, lL, ot0, lu_use[0],
                               lu_use[1], lu_use[2], P(A.lu[0]), P(A.lu[1]), P(A.lu[2]), part, st),
            "adjoint polymer");
     for (int a = 0; a < 3; ++a) lu_use[a] = P(A.lu[a]);
@@ -657,7 +675,7 @@ int adjoint_impl(drpf_grid* g, const drpf_state* x, drpf_adj* lam, double* d_gra
   HIPCHK(launch_fft_x_inv<T>(F, tf, Sf, of, st), "adjoint ifft_x fine");
   const double sin_bot = sin(g->p.theta_bottom_deg * M_PI / 180.0);
   const int off_th = 2 * A.nbA + A.nbM, off_pe2 = off_th + A.nbF;
-  HIPCHK(launch_adj_ch(F, C, K, P(A.lQ), P(A.lG), io.phin, io.phinm1, P(A.phinew), io.un, io.unm1, io.vn,
+  HIPCHK(launch_adj_ch(F, C, K, P(A.lQ), P(A.lG), io.phin, io.phinm1, io.phinew, io.un, io.unm1, io.vn,
                        io.vnm1, io.wn, io.wnm1, sin_bot, (T*)lam->phi[1], (T*)lam->phi[0], u0, u1, v0, v1, w0,
                        w1, part + off_th, part + off_pe2, st),
          "adjoint Cahn-Hilliard");
@@ -956,7 +974,8 @@ int drpf_adjoint_attach(drpf_grid* g, void* d_workspace, size_t bytes) {
   return DRPF_OK;
 }
 
-int drpf_adjoint_step(drpf_grid* g, const drpf_state* x, drpf_adj* lam, double* d_grad3, void* stream) {
+int drpf_adjoint_step(drpf_grid* g, const drpf_state* x, const drpf_state* x_next, drpf_adj* lam,
+                      double* d_grad3, void* stream) {
   if (!g || !x || !lam || !d_grad3) return fail(DRPF_EINVAL, "null argument");
   if (g->p.precision != 64) return fail(DRPF_EUNSUPPORTED, "the adjoint runs on FP64 grids only");
   if (!g->aws) return fail(DRPF_EINVAL, "no adjoint workspace attached");
@@ -971,7 +990,12 @@ int drpf_adjoint_step(drpf_grid* g, const drpf_state* x, drpf_adj* lam, double* 
       for (int m = 0; m < 6; ++m)
         if (!x->tau[l][m] || !lam->tau[l][m]) return fail(DRPF_EINVAL, "null polymer stress pointer");
   if (x->step < 0) return fail(DRPF_EINVAL, "negative step counter");
-  return adjoint_impl(g, x, lam, d_grad3, (hipStream_t)stream);
+  if (x_next) {
+    if (!x_next->phi[0] || !x_next->u[0] || !x_next->v[0] || !x_next->w[0] || !x_next->p[0])
+      return fail(DRPF_EINVAL, "null pointer in the state after the step");
+    if (x_next->step != x->step + 1) return fail(DRPF_EINVAL, "x_next must be the state one step after x_n");
+  }
+  return adjoint_impl(g, x, x_next, lam, d_grad3, (hipStream_t)stream);
 }
 
 }  // extern "C"
