@@ -108,10 +108,14 @@ KERNEL_SOURCE = {
 
 
 def source_sha(kernel):
-    src = KERNEL_SOURCE.get(kernel, "fft.hip")
-    path = os.path.join(ROOT, "paper_2111_04577_amd", "csrc", src)
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the kernel's source file and of every shared header it may include."""
+    csrc = os.path.join(ROOT, "paper_2111_04577_amd", "csrc")
+    names = [KERNEL_SOURCE.get(kernel, "fft.hip")] + sorted(f for f in os.listdir(csrc) if f.endswith(".hpp"))
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(csrc, n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_entry(kernel, precision):
@@ -284,28 +288,71 @@ def cpu_baseline(W, cfg, nsteps):
 
 
 def ingest_pmc(fetch_csv, write_csv, out_json):
-    """rocprofv3 --pmc counter_collection.csv files -> per-kernel bytes per launch, scaled by
-    the counter reading of the plain copy kernel of known size run in the same process."""
+    """rocprofv3 --pmc counter_collection.csv files (one run with FETCH_SIZE, one with
+    WRITE_SIZE, each of `bench.py --copy-calibration`) -> HBM bytes per launch of every kernel,
+    merged into out_json. Each counter (KiB per dispatch) is scaled by (copy bytes) / (the same
+    counter read on the 512 MiB device copy of that run). Kernels launched on both grids are
+    told apart by their grid size (the larger is the fine grid)."""
     import csv
+    import re
     from collections import defaultdict
 
+    copy_bytes = 512 * 2 ** 20
+
     def read(path, counter):
-        acc = defaultdict(list)
+        per = defaultdict(list)
+        copies = []
         with open(path) as f:
             for row in csv.DictReader(f):
                 if row.get("Counter_Name") != counter:
                     continue
-                acc[row["Kernel_Name"]].append(float(row["Counter_Value"]))
-        return {k: sum(v) / len(v) for k, v in acc.items()}
+                name, val = row["Kernel_Name"], float(row["Counter_Value"])
+                if "copyBuffer" in name or "copy" in name.lower() and "k_" not in name:
+                    copies.append(val)
+                    continue
+                m = re.search(r"(k_\w+)<(float|double)(?:, (true|false))?>", name)
+                if not m:
+                    continue
+                per[(m.group(1), m.group(2), m.group(3), int(row["Grid_Size"]))].append(val)
+        scale = copy_bytes / (max(copies) * 1024) if copies else None
+        return per, scale
 
-    fetch = read(fetch_csv, "FETCH_SIZE")
-    write = read(write_csv, "WRITE_SIZE")
-    copy_bytes = 512 * 2 ** 20
-    copy_k = [k for k in fetch if "copy" in k.lower() or "elementwise" in k.lower()]
-    f_scale = copy_bytes / (fetch[copy_k[0]] * 1024) if copy_k else 1.0
-    w_scale = copy_bytes / (write[copy_k[0]] * 1024) if copy_k and copy_k[0] in write else 1.0
-    print(json.dumps({"copy_kernel": copy_k[:1], "fetch_scale": f_scale, "write_scale": w_scale}))
-    return fetch, write, f_scale, w_scale
+    fetch, fs = read(fetch_csv, "FETCH_SIZE")
+    write, ws = read(write_csv, "WRITE_SIZE")
+    base = {"k_ch_rhs": "ch_rhs", "k_restrict_g": "restrict_g", "k_momentum_rhs": "momentum_rhs",
+            "k_zpass_ch": "zpass_ch", "k_zpass_ns": "zpass_ns"}
+    sizes = defaultdict(set)
+    for (k, t, inv, g) in fetch:
+        sizes[(k, t, inv)].add(g)
+    out = {}
+    if os.path.exists(out_json):
+        with open(out_json) as f:
+            out = json.load(f)
+    for key, vals in fetch.items():
+        k, t, inv, g = key
+        if key not in write or fs is None or ws is None:
+            continue
+        if k in base:
+            name = base[k]
+        elif k in ("k_fft_x_fwd", "k_fft_x_inv", "k_fft_y"):
+            grid = "fine" if g == max(sizes[(k, t, inv)]) else "coarse"
+            kind = {"k_fft_x_fwd": "fft_x_fwd", "k_fft_x_inv": "fft_x_inv"}.get(k)
+            if kind is None:
+                kind = "fft_y_inv" if inv == "true" else "fft_y_fwd"
+            name = f"{kind}_{grid}"
+        else:
+            continue
+        prec = 32 if t == "float" else 64
+        fb = sum(vals) / len(vals) * 1024 * fs
+        wb = sum(write[key]) / len(write[key]) * 1024 * ws
+        out[f"{name}/fp{prec}"] = {"bytes_per_launch": round(fb + wb), "fetch_bytes": round(fb),
+                                   "write_bytes": round(wb), "dispatches": len(vals),
+                                   "source_sha": source_sha(name)}
+    out["_calibration"] = {"copy_bytes": copy_bytes, "fetch_scale": fs, "write_scale": ws}
+    with open(out_json, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    print(json.dumps(out["_calibration"]))
+    return out
 
 
 def main():
