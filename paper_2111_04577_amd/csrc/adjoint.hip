@@ -278,6 +278,7 @@ __global__ void __launch_bounds__(kBlock)
               in.taun,
               in.taunm1,
               R,
+              in.un, in.unm1, in.vn, in.vnm1, in.wn, in.wnm1,
               nx, ny, nz, f, in.viscoelastic,
               ihx, ihy, ihz,
               c.inv_dt, c.inv_re, c.inv_rho0, c.nu_m, c.k_sigma, c.c_j};

@@ -68,14 +68,21 @@ struct MomTerms {
   T hat, adv, jg, gpn, gps, lap, pol, vis, cap, ri;
 };
 
-template <typename T>
-struct MomCtx {
-  Field<T> U, V, W, P, Pn;
-  Coarse<T> Gc, phic, muc, muxy;
+// Inputs of the momentum right-hand side. VA reads the extrapolated velocities (methods s, sd,
+// sw as in Field) and GA the restricted chemical potential at centres (at, atn as in Coarse):
+// from global memory (Field, Coarse) or from LDS rings (the z-marching kernel).
+template <typename T, typename VA, typename GA>
+struct MomCtxG {
+  using value_type = T;
+  VA U, V, W;
+  Field<T> P, Pn;
+  GA Gc;
+  Coarse<T> phic, muc, muxy;
   ZEdge<T> muxz, muyz;
   const T* const* taun;
   const T* const* taunm1;
   Restricted<T> R;
+  const T *un, *unm1, *vn, *vnm1, *wn, *wnm1;  // levels n, n-1 (for the hat of eq. NS31)
   int nx, ny, nz, first, ve;
   T ihx, ihy, ihz;
   T inv_dt, inv_re, ir0, nu_m, k_sigma, c_j;
@@ -98,7 +105,11 @@ struct MomCtx {
 };
 
 template <typename T>
-__device__ __forceinline__ MomTerms<T> mom_u(const MomCtx<T>& m, int k, int j, int i, int id) {
+using MomCtx = MomCtxG<T, Field<T>, Coarse<T>>;
+
+template <typename C>
+__device__ __forceinline__ MomTerms<typename C::value_type> mom_u(const C& m, int k, int j, int i, int id) {
+  using T = typename C::value_type;
   const auto& U = m.U;
   const auto& V = m.V;
   const auto& W = m.W;
@@ -147,11 +158,12 @@ __device__ __forceinline__ MomTerms<T> mom_u(const MomCtx<T>& m, int k, int j, i
   const T gps = (m.P.s(k, j, i + 1) - m.P.s(k, j, i)) * ihx;
   const T cap = m.R.G_x[id] * (m.phic.at(k, j, i + 1) - m.phic.at(k, j, i)) * ihx;
   const T lap = (uxp - 2 * u0 + uxm) * ihx * ihx + (uyp - 2 * u0 + uym) * ihy * ihy + (uzp - 2 * u0 + uzm) * ihz * ihz;
-  return MomTerms<T>{m.hat(U.a, U.b, id), adv, jgu, gpn, gps, lap, pol, vis, cap, ri};
+  return MomTerms<T>{m.hat(m.un, m.unm1, id), adv, jgu, gpn, gps, lap, pol, vis, cap, ri};
 }
 
-template <typename T>
-__device__ __forceinline__ MomTerms<T> mom_v(const MomCtx<T>& m, int k, int j, int i, int id) {
+template <typename C>
+__device__ __forceinline__ MomTerms<typename C::value_type> mom_v(const C& m, int k, int j, int i, int id) {
+  using T = typename C::value_type;
   const auto& U = m.U;
   const auto& V = m.V;
   const auto& W = m.W;
@@ -196,11 +208,12 @@ __device__ __forceinline__ MomTerms<T> mom_v(const MomCtx<T>& m, int k, int j, i
   const T gps = (m.P.s(k, j + 1, i) - m.P.s(k, j, i)) * ihy;
   const T cap = m.R.G_y[id] * (m.phic.at(k, j + 1, i) - m.phic.at(k, j, i)) * ihy;
   const T lap = (vxp - 2 * v0 + vxm) * ihx * ihx + (vyp - 2 * v0 + vym) * ihy * ihy + (vzp - 2 * v0 + vzm) * ihz * ihz;
-  return MomTerms<T>{m.hat(V.a, V.b, id), adv, jgv, gpn, gps, lap, pol, vis, cap, ri};
+  return MomTerms<T>{m.hat(m.vn, m.vnm1, id), adv, jgv, gpn, gps, lap, pol, vis, cap, ri};
 }
 
-template <typename T>
-__device__ __forceinline__ MomTerms<T> mom_w(const MomCtx<T>& m, int k, int j, int i, int id) {
+template <typename C>
+__device__ __forceinline__ MomTerms<typename C::value_type> mom_w(const C& m, int k, int j, int i, int id) {
+  using T = typename C::value_type;
   const auto& U = m.U;
   const auto& V = m.V;
   const auto& W = m.W;
@@ -243,7 +256,7 @@ __device__ __forceinline__ MomTerms<T> mom_w(const MomCtx<T>& m, int k, int j, i
   const T gps = (m.P.s(k + 1, j, i) - m.P.s(k, j, i)) * ihz;
   const T cap = m.R.G_z[id] * (m.phic.at(k + 1, j, i) - m.phic.at(k, j, i)) * ihz;
   const T lap = (wxp - 2 * w0 + wxm) * ihx * ihx + (wyp - 2 * w0 + wym) * ihy * ihy + (wzp - 2 * w0 + wzm) * ihz * ihz;
-  return MomTerms<T>{m.hat(W.a, W.b, id), adv, jgw, gpn, gps, lap, pol, vis, cap, ri};
+  return MomTerms<T>{m.hat(m.wn, m.wnm1, id), adv, jgw, gpn, gps, lap, pol, vis, cap, ri};
 }
 
 

@@ -51,6 +51,7 @@ __global__ void __launch_bounds__(kBlock)
               in.taun,
               in.taunm1,
               R,
+              in.un, in.unm1, in.vn, in.vnm1, in.wn, in.wnm1,
               nx, ny, nz, f, in.viscoelastic,
               ihx, ihy, ihz,
               (T)c.inv_dt, (T)c.inv_re, (T)c.inv_rho0, (T)c.nu_m, (T)c.k_sigma, (T)c.c_j};
@@ -65,6 +66,116 @@ __global__ void __launch_bounds__(kBlock)
     rv[id] = rhs(mom_v(m, k, j, i, id), (T)c.ay);
   } else {
     rw[id] = k == nz - 1 ? (T)0 : rhs(mom_w(m, k, j, i, id), (T)c.az);
+  }
+}
+
+// LDS ring views of the z-marching kernel: per layer a tile of HX x HY points covering the
+// block's TX x TY columns with one point of halo below and two above in x and y (one row when
+// ny == 1), values stored with their wall rule applied.
+template <typename T>
+struct RingV {
+  const T* sl[3];  // layers k-1, k, k+1
+  int k, X0, Y0, ys;
+  __device__ __forceinline__ T s(int kk, int jj, int ii) const {
+    return sl[kk - k + 1][(jj - Y0 + 1) * ys + (ii - X0 + 1)];
+  }
+  __device__ __forceinline__ T sd(int kk, int jj, int ii) const { return s(kk, jj, ii); }
+  __device__ __forceinline__ T sw(int kk, int jj, int ii) const { return s(kk, jj, ii); }
+};
+template <typename T>
+struct RingG {
+  const T* sl[4];  // layers k-1 .. k+2
+  int k, X0, Y0, ys;
+  __device__ __forceinline__ T at(int kk, int jj, int ii) const {
+    return sl[kk - k + 1][(jj - Y0 + 1) * ys + (ii - X0 + 1)];
+  }
+  __device__ __forceinline__ T atn(int kk, int jj, int ii) const { return at(kk, jj, ii); }
+};
+
+// Momentum right-hand side, z-marching: a block owns TX x TY coarse columns and KB layers;
+// the extrapolated velocities (three-layer rings) and G at centres (four-layer ring, for J)
+// live in LDS, every thread forms all three components of its cell from them. The other
+// inputs are read once or twice per cell from global memory.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_momentum_rhs_zm(NsIn<T> in, Restricted<T> R, T* __restrict__ ru, T* __restrict__ rv,
+                      T* __restrict__ rw, int nx, int ny, int nz, int KB, T ihx, T ihy, T ihz,
+                      StepConsts c) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int TX = blockDim.x, TY = blockDim.y;
+  int bx, by, bz;
+  xcd_tile(bx, by, bz);
+  const int X0 = bx * TX, Y0 = by * TY, K0 = bz * KB;
+  const int HX = TX + 3, HY = ny == 1 ? 1 : TY + 3, HP = HX * HY, ys = ny == 1 ? 0 : HX;
+  T* sU = reinterpret_cast<T*>(smem);
+  T* sV = sU + 3 * HP;
+  T* sW = sV + 3 * HP;
+  T* sG = sW + 3 * HP;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int tid = ty * TX + tx, nth = TX * TY;
+  const int i = X0 + tx, j = Y0 + ty;
+  const int f = c.first;
+  const Field<T> U{in.un, in.unm1, nx, ny, nz, f}, V{in.vn, in.vnm1, nx, ny, nz, f},
+      W{in.wn, in.wnm1, nx, ny, nz, f};
+  const Coarse<T> Gc{R.G_c, nx, ny, nz};
+  auto load_vel = [&](int kk) {
+    const int sl = (kk - K0 + 1) % 3;
+    for (int e = tid; e < HP; e += nth) {
+      const int hy = e / HX, hx = e - hy * HX;
+      const int jj = Y0 - 1 + hy, ii = X0 - 1 + hx;
+      sU[sl * HP + e] = U.sd(kk, jj, ii);
+      sV[sl * HP + e] = V.sd(kk, jj, ii);
+      sW[sl * HP + e] = W.sw(kk, jj, ii);
+    }
+  };
+  auto load_g = [&](int kk) {
+    const int sl = (kk - K0 + 1) & 3;
+    for (int e = tid; e < HP; e += nth) {
+      const int hy = e / HX, hx = e - hy * HX;
+      sG[sl * HP + e] = Gc.atn(kk, Y0 - 1 + hy, X0 - 1 + hx);
+    }
+  };
+  load_vel(K0 - 1);
+  load_vel(K0);
+  load_g(K0 - 1);
+  load_g(K0);
+  load_g(K0 + 1);
+  for (int k = K0; k < K0 + KB; ++k) {
+    load_vel(k + 1);
+    load_g(k + 2);
+    __syncthreads();
+    const int v0 = (k - K0) % 3, v1 = (k - K0 + 1) % 3, v2 = (k - K0 + 2) % 3;
+    const RingV<T> Ur{{sU + v0 * HP, sU + v1 * HP, sU + v2 * HP}, k, X0, Y0, ys};
+    const RingV<T> Vr{{sV + v0 * HP, sV + v1 * HP, sV + v2 * HP}, k, X0, Y0, ys};
+    const RingV<T> Wr{{sW + v0 * HP, sW + v1 * HP, sW + v2 * HP}, k, X0, Y0, ys};
+    const RingG<T> Gr{{sG + ((k - K0) & 3) * HP, sG + ((k - K0 + 1) & 3) * HP, sG + ((k - K0 + 2) & 3) * HP,
+                       sG + ((k - K0 + 3) & 3) * HP},
+                      k, X0, Y0, ys};
+    MomCtxG<T, RingV<T>, RingG<T>> m{Ur, Vr, Wr,
+                                     {in.pn, in.pnm1, nx, ny, nz, f},
+                                     {in.pn, nullptr, nx, ny, nz, 1},
+                                     Gr,
+                                     {R.phi_c, nx, ny, nz},
+                                     {R.mu_c, nx, ny, nz},
+                                     {R.mu_xy, nx, ny, nz},
+                                     {R.mu_xz, nx, ny},
+                                     {R.mu_yz, nx, ny},
+                                     in.taun,
+                                     in.taunm1,
+                                     R,
+                                     in.un, in.unm1, in.vn, in.vnm1, in.wn, in.wnm1,
+                                     nx, ny, nz, f, in.viscoelastic,
+                                     ihx, ihy, ihz,
+                                     (T)c.inv_dt, (T)c.inv_re, (T)c.inv_rho0, (T)c.nu_m, (T)c.k_sigma, (T)c.c_j};
+    auto rhs = [&](const MomTerms<T>& t, T a) -> T {
+      return -t.hat * m.inv_dt + t.adv + t.ri * t.jg + t.gpn * m.ir0 + (t.ri - m.ir0) * t.gps + m.nu_m * t.lap -
+             m.inv_re * t.ri * t.pol - m.inv_re * t.ri * t.vis - m.k_sigma * t.ri * t.cap - a;
+    };
+    const int id = (k * ny + j) * nx + i;
+    ru[id] = rhs(mom_u(m, k, j, i, id), (T)c.ax);
+    rv[id] = rhs(mom_v(m, k, j, i, id), (T)c.ay);
+    rw[id] = k == nz - 1 ? (T)0 : rhs(mom_w(m, k, j, i, id), (T)c.az);
+    __syncthreads();
   }
 }
 
@@ -124,9 +235,22 @@ __global__ void __launch_bounds__(kBlock)
 template <typename T>
 hipError_t launch_momentum_rhs(const Dims& c, const StepConsts& k, NsIn<T> in, Restricted<T> r,
                                T* ru, T* rv, T* rw, hipStream_t st) {
-  const Launch3 L = launch3(c.nx, c.ny, 3 * c.nz);
-  hipLaunchKernelGGL(k_momentum_rhs<T>, L.grid, L.block, 0, st, in, r, ru, rv, rw, c.nx, c.ny, c.nz,
-                     (T)c.ihx, (T)c.ihy, (T)c.ihz, k);
+  if (c.ny == 1) {
+    // 2D: too few columns to feed z-marching blocks; one thread per face instead
+    const Launch3 L = launch3(c.nx, c.ny, 3 * c.nz);
+    hipLaunchKernelGGL(k_momentum_rhs<T>, L.grid, L.block, 0, st, in, r, ru, rv, rw, c.nx, c.ny, c.nz,
+                       (T)c.ihx, (T)c.ihy, (T)c.ihz, k);
+    return hipGetLastError();
+  }
+  const int TX = c.nx < 32 ? c.nx : 32;
+  const int TY = c.ny < kBlock / TX ? c.ny : kBlock / TX;
+  const int cols = (c.nx / TX) * (c.ny / TY);
+  int KB = 16;
+  while (KB > c.nz) KB >>= 1;
+  while (KB > 1 && cols * (c.nz / KB) < 1024) KB >>= 1;
+  const size_t shm = (size_t)13 * (TX + 3) * (TY + 3) * sizeof(T);
+  hipLaunchKernelGGL(k_momentum_rhs_zm<T>, dim3(c.nx / TX, c.ny / TY, c.nz / KB), dim3(TX, TY), shm, st, in, r,
+                     ru, rv, rw, c.nx, c.ny, c.nz, KB, (T)c.ihx, (T)c.ihy, (T)c.ihz, k);
   return hipGetLastError();
 }
 
