@@ -136,4 +136,23 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by, int& bz) {
 
 __host__ __device__ __forceinline__ int wrap(int i, int n) { return i & (n - 1); }
 
+// Spectral layout. After the x transform every z layer holds lines() = (nx/2 + 1) ny modes:
+// first the modes kx < nx/2 as ny rows of nx/2 entries (row ky at offset ky nx/2), then the
+// Nyquist modes kx = nx/2 of all ky, contiguous. Every array is [z][line]. Rows of a power-of-
+// two length keep tiles of consecutive kx (the y transform) on cache-line boundaries, and a
+// line's position equals its index, so the wall-normal passes read aligned tiles of
+// consecutive lines. Mode (ky, kx) of line l (P = nx/2 + 1):
+__device__ __forceinline__ void spec_mode(int l, int P, int Ny, int& ky, int& kx) {
+  const int H = P - 1;
+  const int main = H * Ny;
+  if (l < main) {
+    const int lh = __ffs(H) - 1;
+    ky = l >> lh;
+    kx = l & (H - 1);
+  } else {
+    kx = H;
+    ky = l - main;
+  }
+}
+
 }  // namespace drpf

@@ -5,9 +5,11 @@
 // with coalesced row accesses.
 //
 //   x pass: real rows of length nx -> nx/2+1 complex (r2c through a length nx/2 complex
-//           FFT of the even/odd-packed row), and the inverse (c2r). Unnormalised.
+//           FFT of the even/odd-packed row), and the inverse (c2r). Unnormalised. Output in
+//           the spectral layout of common.hpp (Nyquist modes of a layer stored apart).
 //   y pass: complex columns of length ny, in place, on a tile of consecutive kx columns so
-//           that each y-row load is contiguous. Unnormalised.
+//           that each y-row load is contiguous and cache-line aligned; the Nyquist column of
+//           a layer is one contiguous vector. Unnormalised.
 #include "kernels.hpp"
 #include "lds_fft.hpp"
 
@@ -24,7 +26,7 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_fwd(const T* __restrict__ in0,
                                                       const T* __restrict__ in2,
                                                       cx<T>* __restrict__ out, int N, int logM,
                                                       int lines_per_field, int total_lines,
-                                                      int lpb, const cx<T>* __restrict__ twM,
+                                                      int lpb, int Ny, const cx<T>* __restrict__ twM,
                                                       const cx<T>* __restrict__ twN) {
   extern __shared__ unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -38,7 +40,11 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_fwd(const T* __restrict__ in0,
   for (int e = threadIdx.x; e < nl * M; e += blockDim.x) buf[e] = mk<T>(src[2 * e], src[2 * e + 1]);
   __syncthreads();
   lds_fft<T, false, false>(buf, M, logM, nl, M, 1, twM);
-  cx<T>* dst = out + (size_t)line0 * (M + 1);
+  // row r = z Ny + ky of this field
+  const size_t lines = (size_t)(M + 1) * Ny;
+  cx<T>* fbase = out + (size_t)field * lines * (lines_per_field / Ny);
+  const int r0 = line0 - field * lines_per_field;
+  const int lny = __ffs(Ny) - 1;
   const T half = (T)0.5;
   for (int e = threadIdx.x; e < nl * (M + 1); e += blockDim.x) {
     const int b = e / (M + 1);
@@ -47,7 +53,8 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_fwd(const T* __restrict__ in0,
     const cx<T> zm = conj(buf[b * M + (k == 0 ? 0 : M - k)]);
     const cx<T> E = half * (zk + zm);
     const cx<T> O = half * mul_mi(zk - zm);
-    dst[e] = E + twN[k] * O;
+    const int r = r0 + b, z = r >> lny, ky = r & (Ny - 1);
+    fbase[z * lines + (k < M ? (size_t)ky * M + k : (size_t)M * Ny + ky)] = E + twN[k] * O;
   }
 }
 
@@ -55,7 +62,7 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_fwd(const T* __restrict__ in0,
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fft_x_inv(const cx<T>* __restrict__ in, RealSet<T> out,
                                                       int N, int logM, int lines_per_field,
-                                                      int total_lines, int lpb,
+                                                      int total_lines, int lpb, int Ny,
                                                       const cx<T>* __restrict__ twM,
                                                       const cx<T>* __restrict__ twN) {
   extern __shared__ unsigned char smem_raw[];
@@ -63,12 +70,18 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_inv(const cx<T>* __restrict__ 
   const int M = N >> 1;
   const int line0 = blockIdx.x * lpb;
   const int nl = min(lpb, total_lines - line0);
-  const cx<T>* src = in + (size_t)line0 * (M + 1);
+  const int field0 = line0 / lines_per_field;
+  const size_t lines = (size_t)(M + 1) * Ny;
+  const cx<T>* fbase = in + (size_t)field0 * lines * (lines_per_field / Ny);
+  const int r0 = line0 - field0 * lines_per_field;
+  const int lny = __ffs(Ny) - 1;
   for (int e = threadIdx.x; e < nl * M; e += blockDim.x) {
     const int b = e / M;
     const int k = e - b * M;
-    const cx<T> xk = src[b * (M + 1) + k];
-    const cx<T> xm = conj(src[b * (M + 1) + (M - k)]);
+    const int r = r0 + b, z = r >> lny, ky = r & (Ny - 1);
+    const cx<T>* src = fbase + z * lines;
+    const cx<T> xk = src[(size_t)ky * M + k];
+    const cx<T> xm = conj(k == 0 ? src[(size_t)M * Ny + ky] : src[(size_t)ky * M + (M - k)]);
     const cx<T> E = xk + xm;
     const cx<T> O = conj(twN[k]) * (xk - xm);
     buf[e] = E + mul_i(O);
@@ -98,23 +111,32 @@ __global__ void k_fft_y(cx<T>* __restrict__ data, int Ny, int logNy, int P, int 
                         const cx<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int M = P - 1;
   const int tile = blockIdx.x % ntiles;
   const int batch = blockIdx.x / ntiles;
-  const int kx0 = tile * tkx;
   cx<T>* base = data + (size_t)batch * Ny * P;
+  // tiles 0 .. ntiles-2: tkx consecutive kx < M of every row; the last tile: the Nyquist
+  // column (contiguous in ky), in lane 0 of the tile
+  const bool nyq = tile == ntiles - 1;
+  const int kx0 = tile * tkx;
   for (int e = threadIdx.x; e < Ny * tkx; e += blockDim.x) {
     const int y = e / tkx;
     const int t = e - y * tkx;
-    const int kx = kx0 + t;
-    buf[e] = kx < P ? base[(size_t)y * P + kx] : mk<T>(0, 0);
+    if (nyq)
+      buf[e] = t == 0 ? base[(size_t)M * Ny + y] : mk<T>(0, 0);
+    else
+      buf[e] = base[(size_t)y * M + kx0 + t];
   }
   __syncthreads();
   lds_fft<T, INV, true>(buf, Ny, logNy, tkx, 1, tkx, tw);
   for (int e = threadIdx.x; e < Ny * tkx; e += blockDim.x) {
     const int y = e / tkx;
     const int t = e - y * tkx;
-    const int kx = kx0 + t;
-    if (kx < P) base[(size_t)y * P + kx] = buf[e];
+    if (nyq) {
+      if (t == 0) base[(size_t)M * Ny + y] = buf[e];
+    } else {
+      base[(size_t)y * M + kx0 + t] = buf[e];
+    }
   }
 }
 
@@ -142,7 +164,7 @@ hipError_t launch_fft_x_fwd(const Dims& d, const Tables<T>& tb, const T* const i
   const size_t shm = (size_t)lpb * M * sizeof(cx<T>);
   hipLaunchKernelGGL(k_fft_x_fwd<T>, dim3(blocks), dim3(kBlock), shm, st, in[0],
                      nfields > 1 ? in[1] : in[0], nfields > 2 ? in[2] : in[0], spec, d.nx,
-                     d.logx - 1, lpf, total, lpb, tb.tw_xm, tb.tw_xn);
+                     d.logx - 1, lpf, total, lpb, d.ny, tb.tw_xm, tb.tw_xn);
   return hipGetLastError();
 }
 
@@ -156,7 +178,7 @@ hipError_t launch_fft_x_inv(const Dims& d, const Tables<T>& tb, const cx<T>* spe
   const int blocks = total / lpb;
   const size_t shm = (size_t)lpb * M * sizeof(cx<T>);
   hipLaunchKernelGGL(k_fft_x_inv<T>, dim3(blocks), dim3(kBlock), shm, st, spec, out, d.nx,
-                     d.logx - 1, lpf, total, lpb, tb.tw_xm, tb.tw_xn);
+                     d.logx - 1, lpf, total, lpb, d.ny, tb.tw_xm, tb.tw_xn);
   return hipGetLastError();
 }
 
@@ -167,8 +189,9 @@ hipError_t launch_fft_y(const Dims& d, const Tables<T>& tb, cx<T>* spec, int nfi
   const int Ny = d.ny;
   int tkx = 16;
   while (tkx > 1 && tkx * Ny > 4096) tkx >>= 1;  // tkx * Ny / 4 <= 1024 threads
+  while (tkx > d.nx / 2) tkx >>= 1;
   const int P = d.pitch;
-  const int ntiles = (P + tkx - 1) / tkx;
+  const int ntiles = (d.nx / 2) / tkx + 1;  // kx < nx/2 in tiles of tkx, then the Nyquist column
   const int batches = d.nz * nfields;
   int threads = tkx * (Ny >= 4 ? Ny / 4 : 1);
   threads = ((threads + 63) / 64) * 64;

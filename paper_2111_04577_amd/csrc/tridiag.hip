@@ -121,7 +121,8 @@ __global__ void __launch_bounds__(1024)
   const int l = blockIdx.x * TL + line;
   const bool valid = l < lines;
   const int lc = valid ? l : lines - 1;
-  const int ky = lc / P, kx = lc - ky * P;
+  int ky, kx;
+  spec_mode(lc, P, Ny, ky, kx);
   const size_t stride = (size_t)lines;
   const double a = coeff * ihz2;
   const double dxy = coeff * (lamx[kx] + lamy[ky]) - shift;
@@ -193,7 +194,8 @@ __global__ void __launch_bounds__(1024)
   for (int e = threadIdx.x; e < (half + 1) * TL; e += blockDim.x) {
     const int m = e / TL, t = e - m * TL;
     const int l = min(l0 + t, lines - 1);
-    const int ky = l / P, kx = l - ky * P;
+    int ky, kx;
+    spec_mode(l, P, Ny, ky, kx);
     const double lxy = lamx[kx] + lamy[ky];
     const int mr = (Nz - m) & (Nz - 1);  // partner N - m (0 and N/2 pair with themselves)
     const cx<T> Vm = buf[m * TL + t], Vr = buf[mr * TL + t];
@@ -245,7 +247,8 @@ __global__ void __launch_bounds__(1024)
   const int l = blockIdx.x * TL + line;
   const bool valid = l < lines;
   const int lc = valid ? l : lines - 1;
-  const int ky = lc / P, kx = lc - ky * P;
+  int ky, kx;
+  spec_mode(lc, P, Ny, ky, kx);
   const size_t stride = (size_t)lines;
   const size_t fsz = stride * Nz;
   const size_t at = row * stride + l;
@@ -352,7 +355,8 @@ __global__ void __launch_bounds__(1024)
   const int l = blockIdx.x * TL + line;
   const bool valid = l < lines;
   const int lc = valid ? l : lines - 1;
-  const int ky = lc / P, kx = lc - ky * P;
+  int ky, kx;
+  spec_mode(lc, P, Ny, ky, kx);
   const size_t stride = (size_t)lines;
   const size_t fsz = stride * Nz;
   const size_t at = row * stride + l;
