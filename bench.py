@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration)")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-error", action="store_true",
+                    help="skip the FP32-vs-FP64 per-field error runs (C2 500 steps, C3 1000 steps)")
     ap.add_argument("--only-adjoint", action="store_true",
                     help="run only the gradient case and print its JSON object")
     ap.add_argument("--adjoint-config", default="C4")
@@ -178,14 +180,56 @@ def roofline_for(prof, cfg, precision, steps):
 
 
 def field_diff(a, b):
+    """max |a - b| / max |b| and rms(a - b) / max |b| per field (tau: over its six
+    components, when b has a non-zero stress)."""
     import numpy as np
     out = {}
-    for f in ("phi", "u", "v", "w", "p"):
-        ref = b[f][0]
+    pairs = [(f, a[f][0], b[f][0]) for f in ("phi", "u", "v", "w", "p")]
+    if any(float(np.max(np.abs(t))) > 0 for t in b["tau"][0]):
+        pairs.append(("tau", np.stack(a["tau"][0]), np.stack(b["tau"][0])))
+    for f, x, ref in pairs:
         den = float(np.max(np.abs(ref)))
-        out[f] = float(np.max(np.abs(a[f][0] - ref))) / (den if den > 0 else 1.0)
-        out[f + "_rms"] = float(np.sqrt(np.mean((a[f][0] - ref) ** 2))) / (den if den > 0 else 1.0)
+        out[f] = float(np.max(np.abs(x - ref))) / (den if den > 0 else 1.0)
+        out[f + "_rms"] = float(np.sqrt(np.mean((x - ref) ** 2))) / (den if den > 0 else 1.0)
     return {k: float(f"{v:.3e}") for k, v in out.items()}
+
+
+def precision_error(drpf, W, name, nsteps):
+    """Per-field difference of the FP32 form from the FP64 form (which matches the FP64 CPU
+    reference to 1e-10) after nsteps steps of the named workload, and both masses."""
+    import torch
+    cfg = W.config(name)
+    out = {}
+    for prec in (32, 64):
+        g = drpf.Grid(cfg, prec)
+        st = g.state(W.droplet_state(cfg))
+        g.step(st, nsteps)
+        torch.cuda.synchronize()
+        out[prec] = (st.to_host(), g.observables(st)["mass"])
+        del g, st
+        torch.cuda.empty_cache()
+    d = field_diff(out[32][0], out[64][0])
+    d.update({"after_steps": nsteps, "mass_fp32": out[32][1], "mass_fp64": out[64][1],
+              "mass_rel": float(f"{abs(out[32][1] - out[64][1]) / abs(out[64][1]):.3e}")})
+    return d
+
+
+def copy_ceiling(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy bandwidth on this GPU (read + write bytes / time)."""
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def time_adjoint(drpf, W, name, nsteps, every):
@@ -376,14 +420,12 @@ def main():
     F, C = grid_sizes(cfg)
     forms = {"both": (32, 64), "32": (32,), "64": (64,)}[a.precision]
     res = {}
-    states = {}
     for prec in forms:
         print(f"[bench] timing fp{prec} {cfg.name}: {a.warmup} warm-up + {a.steps} steps", file=sys.stderr, flush=True)
         g, st, ms, wall, prof, obs = time_form(drpf, W, cfg, prec, a.steps, a.warmup)
         roof, kernels = roofline_for(prof, cfg, prec, a.steps)
         res[prec] = {"ms_per_step": ms / a.steps, "value": F["cells"] * a.steps / (ms / 1e3),
                      "wall_s": wall, "roofline": roof, "kernels": kernels, "observables": obs}
-        states[prec] = st.to_host()
         del g, st
         torch.cuda.empty_cache()
     if a.copy_calibration:
@@ -416,14 +458,26 @@ def main():
         "roofline": res[head]["roofline"],
         "kernels": res[head]["kernels"],
     }
+    # whole-step algorithmic bytes (sum over the kernels of one step) per step time, against
+    # the HBM peak and a device-copy ceiling measured here
+    ceiling = copy_ceiling(torch)
+    for prec in res:
+        es = 4 if prec == 32 else 8
+        step_bytes = sum(alg_bytes(k, cfg, es) * v["launches"] / a.steps for k, v in res[prec]["kernels"].items())
+        gbs = step_bytes / (res[prec]["ms_per_step"] / 1e3) / 1e9
+        res[prec]["step_bw"] = {"alg_bytes_per_step": int(step_bytes), "achieved": round(gbs, 1),
+                                "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                                "copy_ceiling": round(ceiling, 1), "frac_of_copy": round(gbs / ceiling, 4)}
+    out["step_bandwidth"] = res[head]["step_bw"]
     if 64 in res and head != 64:
         out["fp64"] = {"value": round(res[64]["value"], 1), "ms_per_step": round(res[64]["ms_per_step"], 4),
-                       "roofline": res[64]["roofline"], "kernels": res[64]["kernels"]}
+                       "roofline": res[64]["roofline"], "step_bandwidth": res[64]["step_bw"],
+                       "kernels": res[64]["kernels"]}
         out["fp32_vs_fp64_speedup"] = round(res[32]["value"] / res[64]["value"], 3)
-        out["fp32_error_vs_fp64"] = field_diff(states[32], states[64])
-        out["fp32_error_vs_fp64"]["after_steps"] = states[32]["step"]
-        out["fp32_error_vs_fp64"]["mass_fp32"] = res[32]["observables"]["mass"]
-        out["fp32_error_vs_fp64"]["mass_fp64"] = res[64]["observables"]["mass"]
+        if not a.no_error:
+            print("[bench] FP32 vs FP64 error: C2 500 steps, C3 1000 steps", file=sys.stderr, flush=True)
+            out["fp32_error_vs_fp64"] = {"C2": precision_error(drpf, W, "C2", 500),
+                                         "C3": precision_error(drpf, W, "C3", 1000)}
     if not a.no_adjoint:
         print(f"[bench] gradient case {a.adjoint_config}", file=sys.stderr, flush=True)
         out["adjoint"] = time_adjoint(drpf, W, a.adjoint_config, a.adjoint_steps, a.adjoint_every)

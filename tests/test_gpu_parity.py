@@ -207,6 +207,18 @@ def test_full_size_c2_two_steps(drpf):
     assert obs["max_div"] < 1e-8
 
 
+def test_full_size_c3_four_steps(drpf):
+    """The 3D Oldroyd-B set-up at full size (128x128x64 coarse, 256x256x128 fine, the z-marching
+    momentum launch and the polymer stages at scale): four steps against the oracle, every
+    field including the six stress components."""
+    cfg = W.config("C3")
+    g, st, gh, oh = run_both(drpf, cfg, 4)
+    errs = field_errors(gh, oh, True)
+    say(f"[gpu] C3 full-size errors {errs}")
+    for k, e in errs.items():
+        assert e < TOL, (k, e)
+
+
 def test_deterministic(drpf):
     import torch
     cfg = STEP_CASES[1][1]
