@@ -143,7 +143,11 @@ __global__ void __launch_bounds__(kBlock)
 // columns and KB coarse layers. A ring of six fine layers of phi^{n+1} (one-cell halo) and a
 // ring of four fine layers of G live in LDS, indexed by the clamped fine layer modulo the
 // ring size; stepping one coarse layer up loads two new phi layers and evaluates G on two
-// new layers (the shared face layer is kept).
+// new layers (the shared face layer is kept). The block has 2 CY rows of threads: all of them
+// load tiles and evaluate G; for the restricted sums the lower CY rows form the phi-derived
+// outputs and the upper CY rows the G-derived ones of the same coarse cells. The global loads
+// of the next layers are issued into registers before the sums and written to LDS after them,
+// so that their latency overlaps the arithmetic.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_restrict_g(const T* __restrict__ phinew, const T* __restrict__ phin,
@@ -151,8 +155,7 @@ __global__ void __launch_bounds__(kBlock)
                  T fihx, T fihy, T fihz, int cnx, int cny, int cnz, int ry, int KB,
                  StepConsts c) {
   extern __shared__ __align__(16) unsigned char smem[];
-  // the block has 2 CY rows of threads: all of them load tiles and evaluate G, the lower CY
-  // rows (one thread per coarse cell) also form the restricted sums
+  constexpr int RMAX = 6;  // per-thread share of a tile: PP, GP <= RMAX * threads (launcher)
   const int CX = blockDim.x, CY = blockDim.y / 2;
   int bx, by, bz;
   xcd_tile(bx, by, bz);
@@ -169,40 +172,70 @@ __global__ void __launch_bounds__(kBlock)
   const T cn2 = (T)c.cn2, S = (T)c.S;
   const T gb = (T)c.g_bot * fihz, gt = (T)c.g_top * fihz;
   auto kc = [&](int Kf) { return min(max(Kf, 0), fnz - 1); };
+  auto pidx = [&](int K, int e) {
+    const int py = e / PX, px = e - py * PX;
+    return (K * fny + wrap(Y0 - 1 + py, fny)) * fnx + wrap(X0 - 1 + px, fnx);
+  };
+  auto gidx = [&](int K, int e) {
+    const int gy = e / GX, gx = e - gy * GX;
+    return (K * fny + wrap(Y0 + gy, fny)) * fnx + wrap(X0 + gx, fnx);
+  };
   auto loadP = [&](int Kf) {
     const int K = kc(Kf);
     T* dst = sP + (K % 6) * PP;
-    for (int e = tid; e < PP; e += nth) {
-      const int py = e / PX, px = e - py * PX;
-      dst[e] = phinew[(K * fny + wrap(Y0 - 1 + py, fny)) * fnx + wrap(X0 - 1 + px, fnx)];
-    }
+    for (int e = tid; e < PP; e += nth) dst[e] = phinew[pidx(K, e)];
   };
-  auto computeG = [&](int Kf) {
+  // G on fine layer Kf from the LDS ring of phi^{n+1}; phi* of the tile points given
+  auto computeG_with = [&](int Kf, const T* psr) {
     const int K = kc(Kf);
     const T* Pm = sP + (kc(K - 1) % 6) * PP;
     const T* P0 = sP + (K % 6) * PP;
     const T* Pp = sP + (kc(K + 1) % 6) * PP;
     T* dst = sG + (K % 4) * GP;
-    for (int e = tid; e < GP; e += nth) {
-      const int gy = e / GX, gx = e - gy * GX;
-      const int m = (gy + 1) * PX + gx + 1;
-      const T p = P0[m];
-      const T lap = (P0[m + 1] - 2 * p + P0[m - 1]) * ihx2 + (P0[m + PX] - 2 * p + P0[m - PX]) * ihy2 +
-                    (Pp[m] - 2 * p + Pm[m]) * ihz2;
-      const int id = (K * fny + wrap(Y0 + gy, fny)) * fnx + wrap(X0 + gx, fnx);
-      const T an = phin[id];
-      const T ps = first ? an : (T)2 * an - phinm1[id];
-      T b = 0;
-      if (K == 0) b += gb * ((T)1 - ps * ps);
-      if (K == fnz - 1) b += gt * ((T)1 - ps * ps);
-      dst[e] = -cn2 * (lap + b) + S * (p - ps) + ps * ps * ps - ps;
+#pragma unroll
+    for (int q = 0; q < RMAX; ++q) {
+      const int e = tid + q * nth;
+      if (e < GP) {
+        const int gy = e / GX, gx = e - gy * GX;
+        const int m = (gy + 1) * PX + gx + 1;
+        const T p = P0[m];
+        const T lap = (P0[m + 1] - 2 * p + P0[m - 1]) * ihx2 + (P0[m + PX] - 2 * p + P0[m - PX]) * ihy2 +
+                      (Pp[m] - 2 * p + Pm[m]) * ihz2;
+        const T ps = psr[q];
+        T b = 0;
+        if (K == 0) b += gb * ((T)1 - ps * ps);
+        if (K == fnz - 1) b += gt * ((T)1 - ps * ps);
+        dst[e] = -cn2 * (lap + b) + S * (p - ps) + ps * ps * ps - ps;
+      }
     }
   };
-  for (int Kf = 2 * k0 - 1; Kf <= 2 * k0 + 3; ++Kf) loadP(Kf);
-  __syncthreads();
-  for (int Kf = 2 * k0; Kf <= 2 * k0 + 2; ++Kf) computeG(Kf);
-  __syncthreads();
-  const int tx = threadIdx.x, ty = threadIdx.y;
+  auto load_ps = [&](int Kf, T* psr) {
+    const int K = kc(Kf);
+#pragma unroll
+    for (int q = 0; q < RMAX; ++q) {
+      const int e = tid + q * nth;
+      if (e < GP) {
+        const int id = gidx(K, e);
+        const T an = phin[id];
+        psr[q] = first ? an : (T)2 * an - phinm1[id];
+      }
+    }
+  };
+  {
+    T ps0[RMAX], ps1[RMAX], ps2[RMAX];
+    for (int Kf = 2 * k0 - 1; Kf <= 2 * k0 + 3; ++Kf) loadP(Kf);
+    load_ps(2 * k0, ps0);
+    load_ps(2 * k0 + 1, ps1);
+    load_ps(2 * k0 + 2, ps2);
+    __syncthreads();
+    computeG_with(2 * k0, ps0);
+    computeG_with(2 * k0 + 1, ps1);
+    computeG_with(2 * k0 + 2, ps2);
+    __syncthreads();
+  }
+  const int tx = threadIdx.x;
+  const bool upper = threadIdx.y >= CY;
+  const int ty = upper ? threadIdx.y - CY : threadIdx.y;
   const int i = i0 + tx, j = j0 + ty;
   const T r1 = (T)c.rho1, r2 = (T)c.rho2, m1 = (T)c.mu1, m2 = (T)c.mu2, hf = (T)0.5;
   auto rinv = [&](T ph) { return (T)1 / (hf * ((T)1 + ph) * r1 + hf * ((T)1 - ph) * r2); };
@@ -210,81 +243,93 @@ __global__ void __launch_bounds__(kBlock)
   const int plane = cnx * cny;
   const int ndy = ry + 1;
   for (int k = k0; k < k0 + KB; ++k) {
-    if (ty < CY) {
+    const bool more = k + 1 < k0 + KB;
+    // prefetch: phi^{n+1} on fine layers 2k+4, 2k+5 and phi* on 2k+3, 2k+4
+    T pf4[RMAX], pf5[RMAX], ps3[RMAX], ps4[RMAX];
+    if (more) {
+      const int K4 = kc(2 * k + 4), K5 = kc(2 * k + 5);
+#pragma unroll
+      for (int q = 0; q < RMAX; ++q) {
+        const int e = tid + q * nth;
+        if (e < PP) {
+          pf4[q] = phinew[pidx(K4, e)];
+          pf5[q] = phinew[pidx(K5, e)];
+        }
+      }
+      load_ps(2 * k + 3, ps3);
+      load_ps(2 * k + 4, ps4);
+    }
     // Separable sums of the tensor-product rule: per z layer and y row, x sums over the
     // centre pair (dx 0,1) and the face pair (dx 1,2); then y pairs, then z pairs. The 1/8
     // weight is applied once at the end (a centre-located y axis without refinement counts
-    // its single cell twice).
-    T pz_[3][4], gz_[3][4];  // per dz: [YcXc, YcXf, YfXc, YfXf]
+    // its single cell twice). Lower rows: phi (src sP, ring 6); upper rows: G (sG, ring 4).
+    {
+      T z_[3][4];  // per dz: [YcXc, YcXf, YfXc, YfXf]
 #pragma unroll
-    for (int dz = 0; dz < 3; ++dz) {
-      const int K = kc(2 * k + dz);
-      const T* P0 = sP + (K % 6) * PP;
-      const T* G0 = sG + (K % 4) * GP;
-      T pxc[3], pxf[3], gxc[3], gxf[3];
+      for (int dz = 0; dz < 3; ++dz) {
+        const int K = kc(2 * k + dz);
+        T xc[3], xf[3];
 #pragma unroll
-      for (int dy = 0; dy < 3; ++dy) {
-        const int gy = ry * ty + (dy < ndy ? dy : 0);
-        const T* pr = P0 + (gy + 1) * PX + 2 * tx + 1;
-        const T* gr = G0 + gy * GX + 2 * tx;
-        pxc[dy] = pr[0] + pr[1];
-        pxf[dy] = pr[1] + pr[2];
-        gxc[dy] = gr[0] + gr[1];
-        gxf[dy] = gr[1] + gr[2];
+        for (int dy = 0; dy < 3; ++dy) {
+          const int gy = ry * ty + (dy < ndy ? dy : 0);
+          const T* pr = upper ? sG + (K % 4) * GP + gy * GX + 2 * tx
+                              : sP + (K % 6) * PP + (gy + 1) * PX + 2 * tx + 1;
+          xc[dy] = pr[0] + pr[1];
+          xf[dy] = pr[1] + pr[2];
+        }
+        if (ry == 2) {
+          z_[dz][0] = xc[0] + xc[1];
+          z_[dz][1] = xf[0] + xf[1];
+          z_[dz][2] = xc[1] + xc[2];
+          z_[dz][3] = xf[1] + xf[2];
+        } else {
+          z_[dz][0] = (T)2 * xc[0];
+          z_[dz][1] = (T)2 * xf[0];
+          z_[dz][2] = xc[0] + xc[1];
+          z_[dz][3] = xf[0] + xf[1];
+        }
       }
-      if (ry == 2) {
-        pz_[dz][0] = pxc[0] + pxc[1];
-        pz_[dz][1] = pxf[0] + pxf[1];
-        pz_[dz][2] = pxc[1] + pxc[2];
-        pz_[dz][3] = pxf[1] + pxf[2];
-        gz_[dz][0] = gxc[0] + gxc[1];
-        gz_[dz][1] = gxf[0] + gxf[1];
-        gz_[dz][2] = gxc[1] + gxc[2];
+      const T e8 = (T)0.125;
+      const int id = (k * cny + j) * cnx + i;
+      if (upper) {
+        r.G_c[id] = e8 * (z_[0][0] + z_[1][0]);
+        r.G_x[id] = e8 * (z_[0][1] + z_[1][1]);
+        r.G_y[id] = e8 * (z_[0][2] + z_[1][2]);
+        r.G_z[id] = e8 * (z_[1][0] + z_[2][0]);
       } else {
-        pz_[dz][0] = (T)2 * pxc[0];
-        pz_[dz][1] = (T)2 * pxf[0];
-        pz_[dz][2] = pxc[0] + pxc[1];
-        pz_[dz][3] = pxf[0] + pxf[1];
-        gz_[dz][0] = (T)2 * gxc[0];
-        gz_[dz][1] = (T)2 * gxf[0];
-        gz_[dz][2] = gxc[0] + gxc[1];
+        const T phic = e8 * (z_[0][0] + z_[1][0]);
+        r.phi_c[id] = phic;
+        r.ri_x[id] = rinv(e8 * (z_[0][1] + z_[1][1]));
+        r.ri_y[id] = rinv(e8 * (z_[0][2] + z_[1][2]));
+        r.ri_z[id] = rinv(e8 * (z_[1][0] + z_[2][0]));
+        r.mu_c[id] = mu(phic);
+        r.mu_xy[id] = mu(e8 * (z_[0][3] + z_[1][3]));
+        // z-edge arrays carry nz + 1 layers: layer k + 1 is the edge at z = (k + 1) hz
+        r.mu_xz[id + plane] = mu(e8 * (z_[1][1] + z_[2][1]));
+        r.mu_yz[id + plane] = mu(e8 * (z_[1][2] + z_[2][2]));
+        if (k == 0) {
+          r.mu_xz[id] = mu((T)0.25 * z_[0][1]);
+          r.mu_yz[id] = mu((T)0.25 * z_[0][2]);
+        }
       }
     }
-    const T e8 = (T)0.125;
-    const T phic = e8 * (pz_[0][0] + pz_[1][0]), Gc = e8 * (gz_[0][0] + gz_[1][0]);
-    const T phx = e8 * (pz_[0][1] + pz_[1][1]), Gx = e8 * (gz_[0][1] + gz_[1][1]);
-    const T phy = e8 * (pz_[0][2] + pz_[1][2]), Gy = e8 * (gz_[0][2] + gz_[1][2]);
-    const T phz = e8 * (pz_[1][0] + pz_[2][0]), Gz = e8 * (gz_[1][0] + gz_[2][0]);
-    const T phxy = e8 * (pz_[0][3] + pz_[1][3]);
-    const T phxz = e8 * (pz_[1][1] + pz_[2][1]);
-    const T phyz = e8 * (pz_[1][2] + pz_[2][2]);
-    const T phxz_b = (T)0.25 * pz_[0][1], phyz_b = (T)0.25 * pz_[0][2];
-    const int id = (k * cny + j) * cnx + i;
-    r.phi_c[id] = phic;
-    r.G_c[id] = Gc;
-    r.G_x[id] = Gx;
-    r.G_y[id] = Gy;
-    r.G_z[id] = Gz;
-    r.ri_x[id] = rinv(phx);
-    r.ri_y[id] = rinv(phy);
-    r.ri_z[id] = rinv(phz);
-    r.mu_c[id] = mu(phic);
-    r.mu_xy[id] = mu(phxy);
-    // z-edge arrays carry nz + 1 layers: layer k + 1 is the edge at z = (k + 1) hz
-    r.mu_xz[id + plane] = mu(phxz);
-    r.mu_yz[id + plane] = mu(phyz);
-    if (k == 0) {
-      r.mu_xz[id] = mu(phxz_b);
-      r.mu_yz[id] = mu(phyz_b);
-    }
-    }
-    if (k + 1 < k0 + KB) {
-      // next coarse layer: fine phi layers 2k+4, 2k+5 replace 2k-2, 2k-1; G on 2k+3, 2k+4
-      loadP(2 * k + 4);
-      loadP(2 * k + 5);
+    if (more) {
+      // fine phi layers 2k+4, 2k+5 replace 2k-2, 2k-1; G on 2k+3, 2k+4 replaces 2k-1, 2k
+      const int K4 = kc(2 * k + 4), K5 = kc(2 * k + 5);
+      T* d4 = sP + (K4 % 6) * PP;
+      T* d5 = sP + (K5 % 6) * PP;
       __syncthreads();
-      computeG(2 * k + 3);
-      computeG(2 * k + 4);
+#pragma unroll
+      for (int q = 0; q < RMAX; ++q) {
+        const int e = tid + q * nth;
+        if (e < PP) {
+          d4[e] = pf4[q];
+          d5[e] = pf5[q];
+        }
+      }
+      __syncthreads();
+      computeG_with(2 * k + 3, ps3);
+      computeG_with(2 * k + 4, ps4);
       __syncthreads();
     }
   }
@@ -381,6 +426,8 @@ hipError_t launch_restrict_g(const Dims& f, const Dims& c, const StepConsts& k, 
   while (KB > 1 && (c.nz / KB) * tiles < 1024) KB >>= 1;
   if (KB > c.nz) KB = c.nz;
   const int GX = 2 * CX + 1, GY = ry * CY + 1;
+  // the kernel keeps at most 6 tile points per thread in registers
+  if ((GX + 2) * (GY + 2) > 6 * 2 * CX * CY || GX * GY > 6 * 2 * CX * CY) return hipErrorInvalidConfiguration;
   const size_t shm = (size_t)(6 * (GX + 2) * (GY + 2) + 4 * GX * GY) * sizeof(T);
   hipLaunchKernelGGL(k_restrict_g<T>, dim3(c.nx / CX, c.ny / CY, c.nz / KB), dim3(CX, 2 * CY, 1), shm, st,
                      phinew, phin, phinm1, r, f.nx, f.ny, f.nz, (T)f.ihx, (T)f.ihy, (T)f.ihz, c.nx,
