@@ -33,13 +33,15 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_fwd(const T* __restrict__ in0,
   const int M = N >> 1;
   const int line0 = blockIdx.x * lpb;
   const int nl = min(lpb, total_lines - line0);
+  cx<T>* stw = buf + lpb * M;  // twiddles of the length-M transform, staged in LDS
+  for (int e = threadIdx.x; e < M; e += blockDim.x) stw[e] = twM[e];
   // a block never straddles two fields: lpb divides lines_per_field
   const int field = line0 / lines_per_field;
   const T* in = field == 0 ? in0 : (field == 1 ? in1 : in2);
   const T* src = in + (size_t)(line0 - field * lines_per_field) * N;
   for (int e = threadIdx.x; e < nl * M; e += blockDim.x) buf[e] = mk<T>(src[2 * e], src[2 * e + 1]);
   __syncthreads();
-  lds_fft<T, false, false>(buf, M, logM, nl, M, 1, twM);
+  lds_fft<T, false, false>(buf, M, logM, nl, M, 1, stw);
   // row r = z Ny + ky of this field
   const size_t lines = (size_t)(M + 1) * Ny;
   cx<T>* fbase = out + (size_t)field * lines * (lines_per_field / Ny);
@@ -70,6 +72,8 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_inv(const cx<T>* __restrict__ 
   const int M = N >> 1;
   const int line0 = blockIdx.x * lpb;
   const int nl = min(lpb, total_lines - line0);
+  cx<T>* stw = buf + lpb * M;
+  for (int e = threadIdx.x; e < M; e += blockDim.x) stw[e] = twM[e];
   const int field0 = line0 / lines_per_field;
   const size_t lines = (size_t)(M + 1) * Ny;
   const cx<T>* fbase = in + (size_t)field0 * lines * (lines_per_field / Ny);
@@ -87,7 +91,7 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_inv(const cx<T>* __restrict__ 
     buf[e] = E + mul_i(O);
   }
   __syncthreads();
-  lds_fft<T, true, false>(buf, M, logM, nl, M, 1, twM);
+  lds_fft<T, true, false>(buf, M, logM, nl, M, 1, stw);
   const int field = line0 / lines_per_field;
   T* dst = out.p[field] + (size_t)(line0 - field * lines_per_field) * N;
   const T* add = out.add[field];
@@ -119,6 +123,8 @@ __global__ void k_fft_y(cx<T>* __restrict__ data, int Ny, int logNy, int P, int 
   // column (contiguous in ky), in lane 0 of the tile
   const bool nyq = tile == ntiles - 1;
   const int kx0 = tile * tkx;
+  cx<T>* stw = buf + Ny * tkx;
+  for (int e = threadIdx.x; e < Ny; e += blockDim.x) stw[e] = tw[e];
   for (int e = threadIdx.x; e < Ny * tkx; e += blockDim.x) {
     const int y = e / tkx;
     const int t = e - y * tkx;
@@ -128,7 +134,7 @@ __global__ void k_fft_y(cx<T>* __restrict__ data, int Ny, int logNy, int P, int 
       buf[e] = base[(size_t)y * M + kx0 + t];
   }
   __syncthreads();
-  lds_fft<T, INV, true>(buf, Ny, logNy, tkx, 1, tkx, tw);
+  lds_fft<T, INV, true>(buf, Ny, logNy, tkx, 1, tkx, stw);
   for (int e = threadIdx.x; e < Ny * tkx; e += blockDim.x) {
     const int y = e / tkx;
     const int t = e - y * tkx;
@@ -161,7 +167,7 @@ hipError_t launch_fft_x_fwd(const Dims& d, const Tables<T>& tb, const T* const i
   const int lpb = largest_pow2_divisor(lpf, x_lines_per_block(M));
   const int total = lpf * nfields;
   const int blocks = total / lpb;
-  const size_t shm = (size_t)lpb * M * sizeof(cx<T>);
+  const size_t shm = (size_t)(lpb + 1) * M * sizeof(cx<T>);
   hipLaunchKernelGGL(k_fft_x_fwd<T>, dim3(blocks), dim3(kBlock), shm, st, in[0],
                      nfields > 1 ? in[1] : in[0], nfields > 2 ? in[2] : in[0], spec, d.nx,
                      d.logx - 1, lpf, total, lpb, d.ny, tb.tw_xm, tb.tw_xn);
@@ -176,7 +182,7 @@ hipError_t launch_fft_x_inv(const Dims& d, const Tables<T>& tb, const cx<T>* spe
   const int lpb = largest_pow2_divisor(lpf, x_lines_per_block(M));
   const int total = lpf * out.nfields;
   const int blocks = total / lpb;
-  const size_t shm = (size_t)lpb * M * sizeof(cx<T>);
+  const size_t shm = (size_t)(lpb + 1) * M * sizeof(cx<T>);
   hipLaunchKernelGGL(k_fft_x_inv<T>, dim3(blocks), dim3(kBlock), shm, st, spec, out, d.nx,
                      d.logx - 1, lpf, total, lpb, d.ny, tb.tw_xm, tb.tw_xn);
   return hipGetLastError();
@@ -196,7 +202,7 @@ hipError_t launch_fft_y(const Dims& d, const Tables<T>& tb, cx<T>* spec, int nfi
   int threads = tkx * (Ny >= 4 ? Ny / 4 : 1);
   threads = ((threads + 63) / 64) * 64;
   if (threads > 1024) threads = 1024;
-  const size_t shm = (size_t)Ny * tkx * sizeof(cx<T>);
+  const size_t shm = (size_t)Ny * (tkx + 1) * sizeof(cx<T>);
   if (inverse)
     hipLaunchKernelGGL((k_fft_y<T, true>), dim3(ntiles * batches), dim3(threads), shm, st, spec, Ny,
                        d.logy, P, ntiles, tkx, tb.tw_y);

@@ -178,6 +178,8 @@ __global__ void __launch_bounds__(1024)
                const cx<T>* __restrict__ twq, double c_psi, double alpha, double scale) {
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem);  // [position][mode]
+  cx<T>* stw = buf + Nz * TL;                    // twiddles of the length-Nz transform
+  for (int e = threadIdx.x; e < Nz; e += blockDim.x) stw[e] = twz[e];
   const int lines = P * Ny;
   const int l0 = blockIdx.x * TL;
   const size_t stride = (size_t)lines;
@@ -188,7 +190,7 @@ __global__ void __launch_bounds__(1024)
     buf[pos * TL + t] = l < lines ? S[row * stride + l] : mk<T>(0, 0);
   }
   __syncthreads();
-  lds_fft<T, false, true>(buf, Nz, logNz, TL, 1, TL, twz);
+  lds_fft<T, false, true>(buf, Nz, logNz, TL, 1, TL, stw);
   const int half = Nz >> 1;
   const T hf = (T)0.5;
   for (int e = threadIdx.x; e < (half + 1) * TL; e += blockDim.x) {
@@ -221,7 +223,7 @@ __global__ void __launch_bounds__(1024)
     }
   }
   __syncthreads();
-  lds_fft<T, true, true>(buf, Nz, logNz, TL, 1, TL, twz);
+  lds_fft<T, true, true>(buf, Nz, logNz, TL, 1, TL, stw);
   for (int e = threadIdx.x; e < Nz * TL; e += blockDim.x) {
     const int row = e / TL, t = e - row * TL;
     const int l = l0 + t;
@@ -471,7 +473,7 @@ hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, doub
   const int lines = d.lines();
   int lognz = 0;
   while ((1 << lognz) < d.nz) ++lognz;
-  const size_t shm = (size_t)d.nz * TL * sizeof(cx<T>);
+  const size_t shm = (size_t)d.nz * (TL + 1) * sizeof(cx<T>);
   // the inverse transforms are unnormalised: fold 1/nz into the spectral scale
   hipLaunchKernelGGL(k_zpass_ch<T>, dim3((lines + TL - 1) / TL), dim3(threads), shm, st, spec, d.pitch,
                      d.ny, d.nz, lognz, TL, tb.lam_x, tb.lam_y, tb.lam_z, tb.tw_z, tb.tw_zq, c_psi, alpha,
