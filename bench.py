@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration)")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--others", default="C3,C5",
+                    help="further workloads timed in both forms beside the headline one ('' for none)")
+    ap.add_argument("--other-steps", type=int, default=100)
     ap.add_argument("--no-error", action="store_true",
                     help="skip the FP32-vs-FP64 per-field error runs (C2 500 steps, C3 1000 steps)")
     ap.add_argument("--only-adjoint", action="store_true",
@@ -478,6 +481,33 @@ def main():
             print("[bench] FP32 vs FP64 error: C2 500 steps, C3 1000 steps", file=sys.stderr, flush=True)
             out["fp32_error_vs_fp64"] = {"C2": precision_error(drpf, W, "C2", 500),
                                          "C3": precision_error(drpf, W, "C3", 1000)}
+    others = [x for x in a.others.split(",") if x and x != cfg.name]
+    if others:
+        out["other_workloads"] = {}
+    for name in others:
+        ocfg = W.config(name)
+        OF, OC = grid_sizes(ocfg)
+        ent = {"workload": f"{name}: coarse {ocfg.nx}x{ocfg.ny}x{ocfg.nz}, fine {OF['nx']}x{OF['ny']}x{OF['nz']} "
+                           f"({OF['cells']} cells), {'Oldroyd-B' if ocfg.viscoelastic else 'Newtonian'}, "
+                           f"rho ratio {ocfg.rho_ratio:g}, mu ratio {ocfg.mu_ratio:g}",
+               "steps": a.other_steps}
+        for prec in (32, 64):
+            print(f"[bench] timing fp{prec} {name}: 5 warm-up + {a.other_steps} steps", file=sys.stderr, flush=True)
+            g, st, ms, wall, prof, obs = time_form(drpf, W, ocfg, prec, a.other_steps, 5)
+            roof, kern = roofline_for(prof, ocfg, prec, a.other_steps)
+            es = 4 if prec == 32 else 8
+            step_bytes = sum(alg_bytes(k, ocfg, es) * v["launches"] / a.other_steps for k, v in kern.items())
+            msps = ms / a.other_steps
+            gbs = step_bytes / (msps / 1e3) / 1e9
+            ent[f"fp{prec}"] = {"value": round(OF["cells"] * a.other_steps / (ms / 1e3), 1),
+                                "ms_per_step": round(msps, 4),
+                                "step_bandwidth": {"achieved": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                                                   "frac_of_copy": round(gbs / ceiling, 4)},
+                                "roofline": roof}
+            del g, st
+            torch.cuda.empty_cache()
+        ent["fp32_vs_fp64_speedup"] = round(ent["fp32"]["value"] / ent["fp64"]["value"], 3)
+        out["other_workloads"][name] = ent
     if not a.no_adjoint:
         print(f"[bench] gradient case {a.adjoint_config}", file=sys.stderr, flush=True)
         out["adjoint"] = time_adjoint(drpf, W, a.adjoint_config, a.adjoint_steps, a.adjoint_every)

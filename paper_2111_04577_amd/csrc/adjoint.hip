@@ -275,8 +275,7 @@ __global__ void __launch_bounds__(kBlock)
               {R.mu_xy, nx, ny, nz},
               {R.mu_xz, nx, ny},
               {R.mu_yz, nx, ny},
-              in.taun,
-              in.taunm1,
+              {in.taun, in.taunm1, R.phi_c, nx, ny, nz, f},
               R,
               in.un, in.unm1, in.vn, in.vnm1, in.wn, in.wnm1,
               nx, ny, nz, f, in.viscoelastic,

@@ -68,10 +68,28 @@ struct MomTerms {
   T hat, adv, jg, gpn, gps, lap, pol, vis, cap, ri;
 };
 
+// Polymer stress weighted by the polymer fraction, (1 + phi_c)/2 tau*, at centres with Neumann
+// ghosts, read from global memory.
+template <typename T>
+struct TauW {
+  const T* const* taun;
+  const T* const* taunm1;
+  const T* phic;
+  int nx, ny, nz, first;
+  __device__ __forceinline__ T at(int comp, int k, int j, int i) const {
+    const int kc = min(max(k, 0), nz - 1);
+    const int id = (kc * ny + wrap(j, ny)) * nx + wrap(i, nx);
+    const T a = taun[comp][id];
+    const T ts = first ? a : (T)2 * a - taunm1[comp][id];
+    return (T)0.5 * ((T)1 + phic[id]) * ts;
+  }
+};
+
 // Inputs of the momentum right-hand side. VA reads the extrapolated velocities (methods s, sd,
-// sw as in Field) and GA the restricted chemical potential at centres (at, atn as in Coarse):
-// from global memory (Field, Coarse) or from LDS rings (the z-marching kernel).
-template <typename T, typename VA, typename GA>
+// sw as in Field), GA the restricted chemical potential at centres (at, atn as in Coarse) and
+// TA the weighted polymer stress (at as in TauW): from global memory or from LDS rings (the
+// z-marching kernel).
+template <typename T, typename VA, typename GA, typename TA = TauW<T>>
 struct MomCtxG {
   using value_type = T;
   VA U, V, W;
@@ -79,8 +97,7 @@ struct MomCtxG {
   GA Gc;
   Coarse<T> phic, muc, muxy;
   ZEdge<T> muxz, muyz;
-  const T* const* taun;
-  const T* const* taunm1;
+  TA Tw;
   Restricted<T> R;
   const T *un, *unm1, *vn, *vnm1, *wn, *wnm1;  // levels n, n-1 (for the hat of eq. NS31)
   int nx, ny, nz, first, ve;
@@ -98,10 +115,7 @@ struct MomCtxG {
     J[2] = -c_j * (Gc.atn(k + 1, j, i) - Gc.atn(k - 1, j, i)) * h * ihz;
   }
   // polymer weight (1 + phi_c)/2 tau*, Neumann ghosts
-  __device__ __forceinline__ T Tp(int comp, int k, int j, int i) const {
-    const Field<T> t{taun[comp], taunm1[comp], nx, ny, nz, first};
-    return (T)0.5 * ((T)1 + phic.atn(k, j, i)) * t.sn(k, j, i);
-  }
+  __device__ __forceinline__ T Tp(int comp, int k, int j, int i) const { return Tw.at(comp, k, j, i); }
 };
 
 template <typename T>

@@ -48,8 +48,7 @@ __global__ void __launch_bounds__(kBlock)
               {R.mu_xy, nx, ny, nz},
               {R.mu_xz, nx, ny},
               {R.mu_yz, nx, ny},
-              in.taun,
-              in.taunm1,
+              {in.taun, in.taunm1, R.phi_c, nx, ny, nz, f},
               R,
               in.un, in.unm1, in.vn, in.vnm1, in.wn, in.wnm1,
               nx, ny, nz, f, in.viscoelastic,
@@ -82,6 +81,27 @@ struct RingV {
   __device__ __forceinline__ T sd(int kk, int jj, int ii) const { return s(kk, jj, ii); }
   __device__ __forceinline__ T sw(int kk, int jj, int ii) const { return s(kk, jj, ii); }
 };
+// Weighted polymer stress (1 + phi_c)/2 tau* in LDS: the xz, yz and zz components (read on
+// layers k-1 .. k+1) in three-layer rings, the xx, yy and xy components (read on layer k only)
+// in one slot each; Neumann clamp applied on load.
+template <typename T>
+struct RingT {
+  const T* r3[3][3];  // [xz, yz, zz][layer k-1, k, k+1]
+  const T* r1[3];     // [xx, yy, xy] on layer k
+  int k, X0, Y0, ys;
+  __device__ __forceinline__ T at(int comp, int kk, int jj, int ii) const {
+    const int e = (jj - Y0 + 1) * ys + (ii - X0 + 1);
+    switch (comp) {
+      case 0: return r1[0][e];
+      case 1: return r1[1][e];
+      case 3: return r1[2][e];
+      case 4: return r3[0][kk - k + 1][e];
+      case 5: return r3[1][kk - k + 1][e];
+      default: return r3[2][kk - k + 1][e];
+    }
+  }
+};
+
 template <typename T>
 struct RingG {
   const T* sl[4];  // layers k-1 .. k+2
@@ -111,6 +131,9 @@ __global__ void __launch_bounds__(kBlock)
   T* sV = sU + 3 * HP;
   T* sW = sV + 3 * HP;
   T* sG = sW + 3 * HP;
+  T* sT3 = sG + 4 * HP;  // viscoelastic: [xz, yz, zz] x 3 slots, then [xx, yy, xy]
+  T* sT1 = sT3 + 9 * HP;
+  const bool ve = in.viscoelastic != 0;
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * TX + tx, nth = TX * TY;
   const int i = X0 + tx, j = Y0 + ty;
@@ -128,6 +151,30 @@ __global__ void __launch_bounds__(kBlock)
       sW[sl * HP + e] = W.sw(kk, jj, ii);
     }
   };
+  // weighted stress of the components `comps` (tau index) on layer kk into dst[c] slots
+  auto load_t = [&](int kk, const int* comps, T* const* dst) {
+    const int kc = min(max(kk, 0), nz - 1);
+    for (int e = tid; e < HP; e += nth) {
+      const int hy = e / HX, hx = e - hy * HX;
+      const int id = (kc * ny + wrap(Y0 - 1 + hy, ny)) * nx + wrap(X0 - 1 + hx, nx);
+      const T w = (T)0.5 * ((T)1 + R.phi_c[id]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T a = in.taun[comps[c]][id];
+        dst[c][e] = w * (f ? a : (T)2 * a - in.taunm1[comps[c]][id]);
+      }
+    }
+  };
+  const int c3[3] = {4, 5, 2}, c1[3] = {0, 1, 3};
+  auto load_t3 = [&](int kk) {
+    const int sl = (kk - K0 + 1) % 3;
+    T* const dst[3] = {sT3 + (0 * 3 + sl) * HP, sT3 + (1 * 3 + sl) * HP, sT3 + (2 * 3 + sl) * HP};
+    load_t(kk, c3, dst);
+  };
+  auto load_t1 = [&](int kk) {
+    T* const dst[3] = {sT1, sT1 + HP, sT1 + 2 * HP};
+    load_t(kk, c1, dst);
+  };
   auto load_g = [&](int kk) {
     const int sl = (kk - K0 + 1) & 3;
     for (int e = tid; e < HP; e += nth) {
@@ -140,9 +187,17 @@ __global__ void __launch_bounds__(kBlock)
   load_g(K0 - 1);
   load_g(K0);
   load_g(K0 + 1);
+  if (ve) {
+    load_t3(K0 - 1);
+    load_t3(K0);
+  }
   for (int k = K0; k < K0 + KB; ++k) {
     load_vel(k + 1);
     load_g(k + 2);
+    if (ve) {
+      load_t3(k + 1);
+      load_t1(k);
+    }
     __syncthreads();
     const int v0 = (k - K0) % 3, v1 = (k - K0 + 1) % 3, v2 = (k - K0 + 2) % 3;
     const RingV<T> Ur{{sU + v0 * HP, sU + v1 * HP, sU + v2 * HP}, k, X0, Y0, ys};
@@ -151,7 +206,13 @@ __global__ void __launch_bounds__(kBlock)
     const RingG<T> Gr{{sG + ((k - K0) & 3) * HP, sG + ((k - K0 + 1) & 3) * HP, sG + ((k - K0 + 2) & 3) * HP,
                        sG + ((k - K0 + 3) & 3) * HP},
                       k, X0, Y0, ys};
-    MomCtxG<T, RingV<T>, RingG<T>> m{Ur, Vr, Wr,
+    const int t0 = (k - K0) % 3, t1 = (k - K0 + 1) % 3, t2 = (k - K0 + 2) % 3;
+    const RingT<T> Tr{{{sT3 + t0 * HP, sT3 + t1 * HP, sT3 + t2 * HP},
+                       {sT3 + (3 + t0) * HP, sT3 + (3 + t1) * HP, sT3 + (3 + t2) * HP},
+                       {sT3 + (6 + t0) * HP, sT3 + (6 + t1) * HP, sT3 + (6 + t2) * HP}},
+                      {sT1, sT1 + HP, sT1 + 2 * HP},
+                      k, X0, Y0, ys};
+    MomCtxG<T, RingV<T>, RingG<T>, RingT<T>> m{Ur, Vr, Wr,
                                      {in.pn, in.pnm1, nx, ny, nz, f},
                                      {in.pn, nullptr, nx, ny, nz, 1},
                                      Gr,
@@ -160,8 +221,7 @@ __global__ void __launch_bounds__(kBlock)
                                      {R.mu_xy, nx, ny, nz},
                                      {R.mu_xz, nx, ny},
                                      {R.mu_yz, nx, ny},
-                                     in.taun,
-                                     in.taunm1,
+                                     Tr,
                                      R,
                                      in.un, in.unm1, in.vn, in.vnm1, in.wn, in.wnm1,
                                      nx, ny, nz, f, in.viscoelastic,
@@ -243,12 +303,14 @@ hipError_t launch_momentum_rhs(const Dims& c, const StepConsts& k, NsIn<T> in, R
     return hipGetLastError();
   }
   const int TX = c.nx < 32 ? c.nx : 32;
-  const int TY = c.ny < kBlock / TX ? c.ny : kBlock / TX;
+  int TY = c.ny < kBlock / TX ? c.ny : kBlock / TX;
+  // the weighted polymer stress adds 12 LDS tile layers; FP64 takes half-height tiles
+  if (in.viscoelastic && sizeof(T) == 8 && TY > 4) TY = 4;
   const int cols = (c.nx / TX) * (c.ny / TY);
   int KB = 16;
   while (KB > c.nz) KB >>= 1;
   while (KB > 1 && cols * (c.nz / KB) < 1024) KB >>= 1;
-  const size_t shm = (size_t)13 * (TX + 3) * (TY + 3) * sizeof(T);
+  const size_t shm = (size_t)(in.viscoelastic ? 25 : 13) * (TX + 3) * (TY + 3) * sizeof(T);
   hipLaunchKernelGGL(k_momentum_rhs_zm<T>, dim3(c.nx / TX, c.ny / TY, c.nz / KB), dim3(TX, TY), shm, st, in, r,
                      ru, rv, rw, c.nx, c.ny, c.nz, KB, (T)c.ihx, (T)c.ihy, (T)c.ihz, k);
   return hipGetLastError();

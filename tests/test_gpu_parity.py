@@ -219,6 +219,17 @@ def test_full_size_c3_four_steps(drpf):
         assert e < TOL, (k, e)
 
 
+def test_full_size_c5_one_step(drpf):
+    """The largest set-up (256x256x128 coarse, 512x512x256 = 67.1M fine cells, Oldroyd-B,
+    density and viscosity contrast): one step against the oracle, every field."""
+    cfg = W.config("C5")
+    g, st, gh, oh = run_both(drpf, cfg, 1)
+    errs = field_errors(gh, oh, True)
+    say(f"[gpu] C5 full-size errors {errs}")
+    for k, e in errs.items():
+        assert e < TOL, (k, e)
+
+
 def test_deterministic(drpf):
     import torch
     cfg = STEP_CASES[1][1]
