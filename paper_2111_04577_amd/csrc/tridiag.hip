@@ -107,6 +107,13 @@ size_t pcr_bytes(int n, int TL) {
 
 int tile_lines(int n) { return n >= 1024 ? 1 : 1024 / n; }
 
+// Lines per block: the default tile, halved while the grid would have fewer than 256 blocks
+// (2D grids have only nx/2 + 1 lines; one block per CU at least keeps every CU busy).
+int spread_lines(int tl, int lines) {
+  while (tl > 1 && (lines + tl - 1) / tl < 256) tl >>= 1;
+  return tl;
+}
+
 // ---- generic Helmholtz (drpf_helmholtz_solve) ---------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(1024)
@@ -452,8 +459,8 @@ template <typename T>
 hipError_t launch_zpass_helmholtz(const Dims& d, const Tables<T>& tb, cx<T>* spec, double* piv,
                                   int bc, double coeff, double shift, double scale, hipStream_t st) {
   (void)piv;
-  const int TL = tile_lines(d.nz);
   const int lines = d.lines();
+  const int TL = spread_lines(tile_lines(d.nz), lines);
   const size_t shm = pcr_bytes<double, 1>(d.nz, TL);
   hipLaunchKernelGGL(k_zpass_helmholtz<T>, dim3((lines + TL - 1) / TL), dim3(TL * d.nz), shm, st, spec,
                      d.pitch, d.ny, d.nz, tb.lam_x, tb.lam_y, 1.0 / (d.hz * d.hz), bc, coeff, shift,
@@ -467,6 +474,7 @@ hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, doub
   (void)piv;
   int TL = 16;
   while (TL > 1 && TL * d.nz > 4096) TL >>= 1;
+  TL = spread_lines(TL, d.lines());
   int threads = TL * (d.nz >= 4 ? d.nz / 4 : 1);
   threads = ((threads + 63) / 64) * 64;
   if (threads > 1024) threads = 1024;
@@ -485,8 +493,8 @@ template <typename T>
 hipError_t launch_zpass_ns(const Dims& d, const Tables<T>& tb, cx<T>* spec4, double* piv,
                            const StepConsts& c, double scale, hipStream_t st) {
   (void)piv;
-  const int TL = tile_lines(d.nz);
   const int lines = d.lines();
+  const int TL = spread_lines(tile_lines(d.nz), lines);
   size_t shm = pcr_bytes<T, 2>(d.nz, TL);
   const size_t shm64 = pcr_bytes<double, 1>(d.nz, TL);
   if (shm64 > shm) shm = shm64;
@@ -498,8 +506,8 @@ hipError_t launch_zpass_ns(const Dims& d, const Tables<T>& tb, cx<T>* spec4, dou
 
 hipError_t launch_zpass_ns_adj(const Dims& d, const Tables<double>& tb, cx<double>* spec4,
                                const StepConsts& c, double scale, hipStream_t st) {
-  const int TL = tile_lines(d.nz);
   const int lines = d.lines();
+  const int TL = spread_lines(tile_lines(d.nz), lines);
   size_t shm = pcr_bytes<double, 2>(d.nz, TL);
   hipLaunchKernelGGL(k_zpass_ns_adj, dim3((lines + TL - 1) / TL), dim3(TL * d.nz), shm, st, spec4, d.pitch,
                      d.ny, d.nz, tb.lam_x, tb.lam_y, tb.ph_x, tb.ph_y, 1.0 / d.hx, 1.0 / d.hy, 1.0 / d.hz,
