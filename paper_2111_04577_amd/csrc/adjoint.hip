@@ -832,11 +832,16 @@ __global__ void __launch_bounds__(kBlock)
   sh[1][t] = pe;
   sh[2][t] = wi;
   __syncthreads();
-  if (t < 3) {
-    D s = 0;
-    for (int u = 0; u < (int)blockDim.x; ++u) s += sh[t][u];
-    grad3[t] += s;
+  // pairwise tree in a fixed order (blockDim.x is a power of two)
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      sh[0][t] += sh[0][t + h];
+      sh[1][t] += sh[1][t + h];
+      sh[2][t] += sh[2][t + h];
+    }
+    __syncthreads();
   }
+  if (t < 3) grad3[t] += sh[t][0];
 }
 
 }  // namespace

@@ -107,10 +107,11 @@ size_t pcr_bytes(int n, int TL) {
 
 int tile_lines(int n) { return n >= 1024 ? 1 : 1024 / n; }
 
-// Lines per block: the default tile, halved while the grid would have fewer than 256 blocks
-// (2D grids have only nx/2 + 1 lines; one block per CU at least keeps every CU busy).
-int spread_lines(int tl, int lines) {
-  while (tl > 1 && (lines + tl - 1) / tl < 256) tl >>= 1;
+// Lines per block: the default tile, halved while the grid would have fewer than `target`
+// blocks. Small blocks keep the barrier rounds of a wall-normal pass cheap and let several
+// blocks interleave on a CU; 2D grids have only nx/2 + 1 lines.
+int spread_lines(int tl, int lines, int target) {
+  while (tl > 1 && (lines + tl - 1) / tl < target) tl >>= 1;
   return tl;
 }
 
@@ -460,7 +461,7 @@ hipError_t launch_zpass_helmholtz(const Dims& d, const Tables<T>& tb, cx<T>* spe
                                   int bc, double coeff, double shift, double scale, hipStream_t st) {
   (void)piv;
   const int lines = d.lines();
-  const int TL = spread_lines(tile_lines(d.nz), lines);
+  const int TL = spread_lines(tile_lines(d.nz), lines, 2048);
   const size_t shm = pcr_bytes<double, 1>(d.nz, TL);
   hipLaunchKernelGGL(k_zpass_helmholtz<T>, dim3((lines + TL - 1) / TL), dim3(TL * d.nz), shm, st, spec,
                      d.pitch, d.ny, d.nz, tb.lam_x, tb.lam_y, 1.0 / (d.hz * d.hz), bc, coeff, shift,
@@ -474,7 +475,7 @@ hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, doub
   (void)piv;
   int TL = 16;
   while (TL > 1 && TL * d.nz > 4096) TL >>= 1;
-  TL = spread_lines(TL, d.lines());
+  TL = spread_lines(TL, d.lines(), 2048);
   int threads = TL * (d.nz >= 4 ? d.nz / 4 : 1);
   threads = ((threads + 63) / 64) * 64;
   if (threads > 1024) threads = 1024;
@@ -494,7 +495,7 @@ hipError_t launch_zpass_ns(const Dims& d, const Tables<T>& tb, cx<T>* spec4, dou
                            const StepConsts& c, double scale, hipStream_t st) {
   (void)piv;
   const int lines = d.lines();
-  const int TL = spread_lines(tile_lines(d.nz), lines);
+  const int TL = spread_lines(tile_lines(d.nz), lines, 2048);
   size_t shm = pcr_bytes<T, 2>(d.nz, TL);
   const size_t shm64 = pcr_bytes<double, 1>(d.nz, TL);
   if (shm64 > shm) shm = shm64;
@@ -507,7 +508,7 @@ hipError_t launch_zpass_ns(const Dims& d, const Tables<T>& tb, cx<T>* spec4, dou
 hipError_t launch_zpass_ns_adj(const Dims& d, const Tables<double>& tb, cx<double>* spec4,
                                const StepConsts& c, double scale, hipStream_t st) {
   const int lines = d.lines();
-  const int TL = spread_lines(tile_lines(d.nz), lines);
+  const int TL = spread_lines(tile_lines(d.nz), lines, 2048);
   size_t shm = pcr_bytes<double, 2>(d.nz, TL);
   hipLaunchKernelGGL(k_zpass_ns_adj, dim3((lines + TL - 1) / TL), dim3(TL * d.nz), shm, st, spec4, d.pitch,
                      d.ny, d.nz, tb.lam_x, tb.lam_y, tb.ph_x, tb.ph_y, 1.0 / d.hx, 1.0 / d.hy, 1.0 / d.hz,
