@@ -475,7 +475,7 @@ hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, doub
   (void)piv;
   int TL = 16;
   while (TL > 1 && TL * d.nz > 4096) TL >>= 1;
-  TL = spread_lines(TL, d.lines(), 2048);
+  TL = spread_lines(TL, d.lines(), sizeof(T) == 8 ? 4096 : 2048);  // measured best per precision
   int threads = TL * (d.nz >= 4 ? d.nz / 4 : 1);
   threads = ((threads + 63) / 64) * 64;
   if (threads > 1024) threads = 1024;
