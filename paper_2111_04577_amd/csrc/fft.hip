@@ -193,7 +193,8 @@ hipError_t launch_fft_y(const Dims& d, const Tables<T>& tb, cx<T>* spec, int nfi
                         hipStream_t st) {
   if (d.ny == 1) return hipSuccess;
   const int Ny = d.ny;
-  int tkx = 16;
+  // tiles of 128 bytes per row (16 complex FP32 or 8 complex FP64 columns): one cache line
+  int tkx = (int)(128 / sizeof(cx<T>));
   while (tkx > 1 && tkx * Ny > 4096) tkx >>= 1;  // tkx * Ny / 4 <= 1024 threads
   while (tkx > d.nx / 2) tkx >>= 1;
   const int P = d.pitch;

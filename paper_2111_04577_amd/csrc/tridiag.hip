@@ -473,9 +473,10 @@ template <typename T>
 hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, double* piv,
                            double c_psi, double alpha, double scale, hipStream_t st) {
   (void)piv;
-  int TL = 16;
+  // tiles of 128 bytes per row (16 complex FP32 or 8 complex FP64 modes): one cache line
+  int TL = (int)(128 / sizeof(cx<T>));
   while (TL > 1 && TL * d.nz > 4096) TL >>= 1;
-  TL = spread_lines(TL, d.lines(), sizeof(T) == 8 ? 4096 : 2048);  // measured best per precision
+  TL = spread_lines(TL, d.lines(), 2048);
   int threads = TL * (d.nz >= 4 ? d.nz / 4 : 1);
   threads = ((threads + 63) / 64) * 64;
   if (threads > 1024) threads = 1024;
