@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 512 MiB device copy (counter calibration)")
+                    help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--others", default="C3,C5",
                     help="further workloads timed in both forms beside the headline one ('' for none)")
@@ -338,13 +338,13 @@ def ingest_pmc(fetch_csv, write_csv, out_json):
     """rocprofv3 --pmc counter_collection.csv files (one run with FETCH_SIZE, one with
     WRITE_SIZE, each of `bench.py --copy-calibration`) -> HBM bytes per launch of every kernel,
     merged into out_json. Each counter (KiB per dispatch) is scaled by (copy bytes) / (the same
-    counter read on the 512 MiB device copy of that run). Kernels launched on both grids are
+    counter read on the 1 GiB device copy of that run). Kernels launched on both grids are
     told apart by their grid size (the larger is the fine grid)."""
     import csv
     import re
     from collections import defaultdict
 
-    copy_bytes = 512 * 2 ** 20
+    copy_bytes = 2 ** 30  # the largest copy dispatch of the run: 1 GiB (calibration, copy ceiling)
 
     def read(path, counter):
         per = defaultdict(list)
@@ -367,6 +367,7 @@ def ingest_pmc(fetch_csv, write_csv, out_json):
     fetch, fs = read(fetch_csv, "FETCH_SIZE")
     write, ws = read(write_csv, "WRITE_SIZE")
     base = {"k_ch_rhs": "ch_rhs", "k_restrict_g": "restrict_g", "k_momentum_rhs": "momentum_rhs",
+            "k_momentum_rhs_zm": "momentum_rhs",
             "k_zpass_ch": "zpass_ch", "k_zpass_ns": "zpass_ns"}
     sizes = defaultdict(set)
     for (k, t, inv, g) in fetch:
@@ -432,7 +433,7 @@ def main():
         del g, st
         torch.cuda.empty_cache()
     if a.copy_calibration:
-        x = torch.empty(512 * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+        x = torch.empty(2 ** 30 // 8, dtype=torch.float64, device="cuda")
         y = torch.empty_like(x)
         for _ in range(3):
             y.copy_(x)

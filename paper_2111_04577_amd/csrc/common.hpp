@@ -134,6 +134,13 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by, int& bz) {
   bz = t / (gx * gy);
 }
 
+// One-dimensional form of xcd_tile: the logical block index, so that consecutive logical
+// blocks (which share cache lines) run on the same XCD.
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+}
+
 __host__ __device__ __forceinline__ int wrap(int i, int n) { return i & (n - 1); }
 
 // Spectral layout. After the x transform every z layer holds lines() = (nx/2 + 1) ny modes:

@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(1024)
   const int line = threadIdx.x % TL;
   const int row = threadIdx.x / TL;
   const int lines = P * Ny;
-  const int l = blockIdx.x * TL + line;
+  const int l = xcd_block() * TL + line;
   const bool valid = l < lines;
   const int lc = valid ? l : lines - 1;
   int ky, kx;
@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(1024)
   cx<T>* stw = buf + Nz * TL;                    // twiddles of the length-Nz transform
   for (int e = threadIdx.x; e < Nz; e += blockDim.x) stw[e] = twz[e];
   const int lines = P * Ny;
-  const int l0 = blockIdx.x * TL;
+  const int l0 = xcd_block() * TL;
   const size_t stride = (size_t)lines;
   for (int e = threadIdx.x; e < Nz * TL; e += blockDim.x) {
     const int row = e / TL, t = e - row * TL;
@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(1024)
   const int line = threadIdx.x % TL;
   const int row = threadIdx.x / TL;
   const int lines = P * Ny;
-  const int l = blockIdx.x * TL + line;
+  const int l = xcd_block() * TL + line;
   const bool valid = l < lines;
   const int lc = valid ? l : lines - 1;
   int ky, kx;
@@ -362,7 +362,7 @@ __global__ void __launch_bounds__(1024)
   const int line = threadIdx.x % TL;
   const int row = threadIdx.x / TL;
   const int lines = P * Ny;
-  const int l = blockIdx.x * TL + line;
+  const int l = xcd_block() * TL + line;
   const bool valid = l < lines;
   const int lc = valid ? l : lines - 1;
   int ky, kx;
