@@ -143,6 +143,17 @@ __device__ __forceinline__ int xcd_block() {
 
 __host__ __device__ __forceinline__ int wrap(int i, int n) { return i & (n - 1); }
 
+// Element at a byte offset from a base pointer. With a uniform base and a 32-bit per-lane
+// offset the load takes the scalar-base + vector-offset form (no 64-bit address per lane).
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* base, unsigned byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T* base, unsigned byte_off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
 // Spectral layout. After the x transform every z layer holds lines() = (nx/2 + 1) ny modes:
 // first the modes kx < nx/2 as ny rows of nx/2 entries (row ky at offset ky nx/2), then the
 // Nyquist modes kx = nx/2 of all ky, contiguous. Every array is [z][line]. Rows of a power-of-

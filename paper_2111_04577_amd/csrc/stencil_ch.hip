@@ -25,11 +25,16 @@ constexpr int kBlock = 256;
 
 // Right-hand side of the fused CH solve, z-marching: a block owns TX x TY fine columns and
 // KB consecutive layers. Rings of three layers of phi* and w* (with a one-cell x/y halo) live
-// in LDS; each thread walks up its column, so the x/y neighbours come from LDS, the z
-// neighbours from the ring, and the coarse velocities of eq. dual1 are reloaded only when
-// the column enters a new coarse layer.
-template <typename T>
+// in LDS; each thread walks up its column, so the x/y neighbours come from LDS and the z
+// neighbours from the ring. Each thread owns at most R points of the halo tile (in-layer
+// offsets computed once); the tile of the layer after next and the centre values of the next
+// layer are loaded one step ahead into registers, so that their latency overlaps the
+// arithmetic of the current layer. The coarse velocities of eq. dual1 are reloaded only when
+// the column enters a new coarse layer. The 3D FP32 form is held to 64 registers, so that the
+// 8 blocks per CU of a 256 x 256 x 128 grid are resident at once.
+template <typename T, int R>
 __global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && R == 2 ? 8 : 4)))
     k_ch_rhs(const T* __restrict__ phin, const T* __restrict__ phinm1, Prolonged<T> pv,
              T* __restrict__ out, int nx, int ny, int nz, int KB, T ihx, T ihy, T ihz,
              StepConsts c) {
@@ -46,20 +51,45 @@ __global__ void __launch_bounds__(kBlock)
   const int I = X0 + tx, J = Y0 + ty;
   const bool first = c.first != 0;
   const T icn2 = (T)c.inv_cn2, sc = (T)c.s_cn2;
-  auto load_layer = [&](int Kl, int slot) {
-    const int Kc = min(max(Kl, 0), nz - 1);  // beyond a wall: zero-flux ghost = adjacent layer
-    for (int e = tid; e < HP; e += nth) {
-      const int hy = e / HX, hx = e - hy * HX;
-      const int id = (Kc * ny + wrap(Y0 - 1 + hy, ny)) * nx + wrap(X0 - 1 + hx, nx);
-      const T a = phin[id];
-      const T p = first ? a : (T)2 * a - phinm1[id];
-      sP[slot * HP + e] = p;
-      sW[slot * HP + e] = (p * p * p - p) * icn2 - sc * p;
+  const size_t layer = (size_t)ny * nx;
+  // in-layer byte offsets: the loads take a uniform layer base plus a 32-bit lane offset
+  unsigned hOff[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int e = tid + q * nth;
+    const int hy = e / HX, hx = e - hy * HX;
+    hOff[q] = e < HP ? (unsigned)(wrap(Y0 - 1 + hy, ny) * nx + wrap(X0 - 1 + hx, nx)) * sizeof(T) : 0u;
+  }
+  auto has = [&](int q) { return tid + q * nth < HP; };
+  // beyond a wall the zero-flux ghost is the adjacent layer
+  auto kcl = [&](int Kl) { return min(max(Kl, 0), nz - 1); };
+  auto load_tile = [&](int Kl, T* a, T* b) {
+    const T* pa = phin + kcl(Kl) * layer;
+    const T* pb = phinm1 + kcl(Kl) * layer;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (has(q)) {
+        a[q] = ld_at(pa, hOff[q]);
+        if (!first) b[q] = ld_at(pb, hOff[q]);
+      }
     }
   };
-  int sm = 0, s0 = 1, sp = 2;
-  load_layer(K0 - 1, sm);
-  load_layer(K0, s0);
+  auto store_tile = [&](int slot, const T* a, const T* b) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (has(q)) {
+        const T p = first ? a[q] : (T)2 * a[q] - b[q];
+        sP[slot * HP + tid + q * nth] = p;
+        sW[slot * HP + tid + q * nth] = (p * p * p - p) * icn2 - sc * p;
+      }
+    }
+  };
+  const unsigned cid = (J * nx + I) * sizeof(T);
+  auto load_centre = [&](int Kl) -> T {
+    const T* pa = phin + Kl * layer;
+    const T* pb = phinm1 + Kl * layer;
+    return first ? ld_at(pa, cid) : (T)2 * ld_at(pa, cid) - (T)0.5 * ld_at(pb, cid);
+  };
   // coarse column of this fine column (eq. dual1)
   const int ry = pv.ry;
   const int ic = I >> 1, icw = wrap(ic - 1, pv.cnx);
@@ -67,31 +97,64 @@ __global__ void __launch_bounds__(kBlock)
   const int cplane = pv.cnx * pv.cny;
   const int cu0 = jc * pv.cnx + ic, cu1 = jc * pv.cnx + icw;
   const int cv1 = jcw * pv.cnx + ic;
+  // raw coarse values of one coarse layer: u at cu0, cu1; v at cu0, cv1; w at k and k - 1,
+  // each at levels n and n - 1
+  auto load_vel = [&](int k, T* vn, T* vm) {
+    const int o = k * cplane;
+    vn[0] = pv.un[o + cu0];
+    vn[1] = pv.un[o + cu1];
+    vn[2] = pv.vn[o + cu0];
+    vn[3] = ry == 2 ? pv.vn[o + cv1] : (T)0;
+    vn[4] = k < pv.cnz - 1 ? pv.wn[o + cu0] : (T)0;
+    vn[5] = k > 0 ? pv.wn[o - cplane + cu0] : (T)0;
+    if (!first) {
+      vm[0] = pv.unm1[o + cu0];
+      vm[1] = pv.unm1[o + cu1];
+      vm[2] = pv.vnm1[o + cu0];
+      vm[3] = ry == 2 ? pv.vnm1[o + cv1] : (T)0;
+      vm[4] = k < pv.cnz - 1 ? pv.wnm1[o + cu0] : (T)0;
+      vm[5] = k > 0 ? pv.wnm1[o - cplane + cu0] : (T)0;
+    }
+  };
   const T ihx2 = ihx * ihx, ihy2 = ihy * ihy, ihz2 = ihz * ihz, h = (T)0.5;
   const T gb = (T)c.g_bot * ihz, gt = (T)c.g_top * ihz;
+  T ta[R], tb[R];
+  int sm = 0, s0 = 1, sp = 2;
+  load_tile(K0 - 1, ta, tb);
+  store_tile(sm, ta, tb);
+  load_tile(K0, ta, tb);
+  store_tile(s0, ta, tb);
+  load_tile(K0 + 1, ta, tb);
+  T phat_next = load_centre(K0);
   T ufp = 0, ufm = 0, vfp = 0, vfm = 0, wk = 0, wkm = 0;
   int kcur = -1;
   for (int K = K0; K < K0 + KB; ++K) {
-    load_layer(K + 1, sp);
     const int k = K >> 1;
     if (k != kcur) {
       kcur = k;
-      const int o = k * cplane;
-      const T ua = pv.star(pv.un, pv.unm1, o + cu0), ub = pv.star(pv.un, pv.unm1, o + cu1);
+      T vn[6], vm[6], s[6];
+      load_vel(k, vn, vm);
+#pragma unroll
+      for (int m = 0; m < 6; ++m) s[m] = first ? vn[m] : (T)2 * vn[m] - vm[m];
       const bool iodd = I & 1;
-      ufp = iodd ? ua : h * (ub + ua);
-      ufm = iodd ? h * (ub + ua) : ub;
-      const T va = pv.star(pv.vn, pv.vnm1, o + cu0);
+      ufp = iodd ? s[0] : h * (s[1] + s[0]);
+      ufm = iodd ? h * (s[1] + s[0]) : s[1];
       if (ry == 2) {
-        const T vb = pv.star(pv.vn, pv.vnm1, o + cv1);
         const bool jodd = J & 1;
-        vfp = jodd ? va : h * (vb + va);
-        vfm = jodd ? h * (vb + va) : vb;
+        vfp = jodd ? s[2] : h * (s[3] + s[2]);
+        vfm = jodd ? h * (s[3] + s[2]) : s[3];
       } else {
-        vfp = vfm = va;
+        vfp = vfm = s[2];
       }
-      wk = k < pv.cnz - 1 ? pv.star(pv.wn, pv.wnm1, o + cu0) : (T)0;
-      wkm = k > 0 ? pv.star(pv.wn, pv.wnm1, o - cplane + cu0) : (T)0;
+      wk = s[4];
+      wkm = s[5];
+    }
+    const T phat = phat_next;
+    // layer K + 1 enters the ring; the layer after it and the next centre values go out
+    store_tile(sp, ta, tb);
+    if (K + 1 < K0 + KB) {
+      load_tile(K + 2, ta, tb);
+      phat_next = load_centre(K + 1);
     }
     // fine z faces K (above) and K-1 (below); the walls carry zero flux
     const T wfp = K == nz - 1 ? (T)0 : ((K & 1) ? wk : h * (wkm + wk));
@@ -126,10 +189,8 @@ __global__ void __launch_bounds__(kBlock)
       if (K == 1) lapb += bval(0, pzm) * ihz2;
       if (K == nz - 2) lapb += bval(nz - 1, pzp) * ihz2;
     }
-    const int id = (K * ny + J) * nx + I;
-    const T phat = first ? phin[id] : (T)2 * phin[id] - (T)0.5 * phinm1[id];
     const T q = (T)c.pe_cn2 * (phat * (T)c.inv_dt - adv) + lapw;
-    out[id] = q - lapb;
+    st_at(out + K * layer, cid, q - lapb);
     __syncthreads();
     const int t = sm;
     sm = s0;
@@ -140,22 +201,22 @@ __global__ void __launch_bounds__(kBlock)
 
 
 // Chemical potential, restriction and properties, z-marching: a block owns CX x CY coarse
-// columns and KB coarse layers. A ring of six fine layers of phi^{n+1} (one-cell halo) and a
-// ring of four fine layers of G live in LDS, indexed by the clamped fine layer modulo the
-// ring size; stepping one coarse layer up loads two new phi layers and evaluates G on two
-// new layers (the shared face layer is kept). The block has 2 CY rows of threads: all of them
-// load tiles and evaluate G; for the restricted sums the lower CY rows form the phi-derived
-// outputs and the upper CY rows the G-derived ones of the same coarse cells. The global loads
-// of the next layers are issued into registers before the sums and written to LDS after them,
-// so that their latency overlaps the arithmetic.
-template <typename T>
+// columns and KB coarse layers. A ring of four fine layers of phi^{n+1} (one-cell halo) and a
+// ring of three fine layers of G live in LDS, indexed by the clamped fine layer modulo the
+// ring size; stepping one coarse layer up replaces two phi layers and evaluates G on two new
+// layers. The block has 2 CY rows of threads: all of them load tiles and evaluate G; for the
+// restricted sums the lower CY rows form the phi-derived outputs and the upper CY rows the
+// G-derived ones of the same coarse cells. Each thread owns at most R points of a tile (their
+// in-layer offsets are computed once); the global loads of the layers that the next step
+// needs are issued one step ahead into registers, so that they are in flight while the
+// block evaluates G and forms the next sums.
+template <typename T, int R>
 __global__ void __launch_bounds__(kBlock)
     k_restrict_g(const T* __restrict__ phinew, const T* __restrict__ phin,
                  const T* __restrict__ phinm1, Restricted<T> r, int fnx, int fny, int fnz,
                  T fihx, T fihy, T fihz, int cnx, int cny, int cnz, int ry, int KB,
                  StepConsts c) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int RMAX = 6;  // per-thread share of a tile: PP, GP <= RMAX * threads (launcher)
   const int CX = blockDim.x, CY = blockDim.y / 2;
   int bx, by, bz;
   xcd_tile(bx, by, bz);
@@ -163,41 +224,67 @@ __global__ void __launch_bounds__(kBlock)
   const int GX = 2 * CX + 1, GY = ry * CY + 1, GP = GX * GY;
   const int PX = GX + 2, PY = GY + 2, PP = PX * PY;
   const int X0 = 2 * i0, Y0 = ry * j0;
-  T* sP = reinterpret_cast<T*>(smem);  // 6 slots of phi^{n+1}
-  T* sG = sP + 6 * PP;                 // 4 slots of G
+  T* sP = reinterpret_cast<T*>(smem);  // 4 slots of phi^{n+1}
+  T* sG = sP + 4 * PP;                 // 3 slots of G
   const int tid = threadIdx.y * CX + threadIdx.x;
   const int nth = CX * blockDim.y;
   const bool first = c.first != 0;
   const T ihx2 = fihx * fihx, ihy2 = fihy * fihy, ihz2 = fihz * fihz;
   const T cn2 = (T)c.cn2, S = (T)c.S;
   const T gb = (T)c.g_bot * fihz, gt = (T)c.g_top * fihz;
+  const size_t layer = (size_t)fny * fnx;
   auto kc = [&](int Kf) { return min(max(Kf, 0), fnz - 1); };
-  auto pidx = [&](int K, int e) {
-    const int py = e / PX, px = e - py * PX;
-    return (K * fny + wrap(Y0 - 1 + py, fny)) * fnx + wrap(X0 - 1 + px, fnx);
-  };
-  auto gidx = [&](int K, int e) {
-    const int gy = e / GX, gx = e - gy * GX;
-    return (K * fny + wrap(Y0 + gy, fny)) * fnx + wrap(X0 + gx, fnx);
-  };
-  auto loadP = [&](int Kf) {
-    const int K = kc(Kf);
-    T* dst = sP + (K % 6) * PP;
-    for (int e = tid; e < PP; e += nth) dst[e] = phinew[pidx(K, e)];
-  };
-  // G on fine layer Kf from the LDS ring of phi^{n+1}; phi* of the tile points given
-  auto computeG_with = [&](int Kf, const T* psr) {
-    const int K = kc(Kf);
-    const T* Pm = sP + (kc(K - 1) % 6) * PP;
-    const T* P0 = sP + (K % 6) * PP;
-    const T* Pp = sP + (kc(K + 1) % 6) * PP;
-    T* dst = sG + (K % 4) * GP;
+  // per-thread tile points: in-layer byte offsets of the phi tile (with halo) and of the G
+  // tile (a uniform layer base plus a 32-bit lane offset), and the LDS index of each G point
+  // in the phi tile
+  unsigned pOff[R], gOff[R];
+  int gM[R];
 #pragma unroll
-    for (int q = 0; q < RMAX; ++q) {
-      const int e = tid + q * nth;
-      if (e < GP) {
-        const int gy = e / GX, gx = e - gy * GX;
-        const int m = (gy + 1) * PX + gx + 1;
+  for (int q = 0; q < R; ++q) {
+    const int e = tid + q * nth;
+    const int py = e / PX, px = e - py * PX;
+    const int gy = e / GX, gx = e - gy * GX;
+    pOff[q] = e < PP ? (unsigned)(wrap(Y0 - 1 + py, fny) * fnx + wrap(X0 - 1 + px, fnx)) * sizeof(T) : 0u;
+    gOff[q] = e < GP ? (unsigned)(wrap(Y0 + gy, fny) * fnx + wrap(X0 + gx, fnx)) * sizeof(T) : 0u;
+    gM[q] = e < GP ? (gy + 1) * PX + gx + 1 : 0;
+  }
+  auto inP = [&](int q) { return tid + q * nth < PP; };
+  auto inG = [&](int q) { return tid + q * nth < GP; };
+  auto load_p = [&](int Kf, T* v) {
+    const T* src = phinew + kc(Kf) * layer;
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      if (inP(q)) v[q] = ld_at(src, pOff[q]);
+  };
+  auto store_p = [&](int Kf, const T* v) {
+    T* dst = sP + (kc(Kf) & 3) * PP;
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      if (inP(q)) dst[tid + q * nth] = v[q];
+  };
+  // phi* at the G points of fine layer Kf
+  auto load_ps = [&](int Kf, T* v) {
+    const T* a = phin + kc(Kf) * layer;
+    const T* b = phinm1 + kc(Kf) * layer;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (inG(q)) {
+        const T an = ld_at(a, gOff[q]);
+        v[q] = first ? an : (T)2 * an - ld_at(b, gOff[q]);
+      }
+    }
+  };
+  // G on fine layer Kf from the phi ring and phi* at the G points
+  auto compute_g = [&](int Kf, const T* psr) {
+    const int K = kc(Kf);
+    const T* Pm = sP + (kc(K - 1) & 3) * PP;
+    const T* P0 = sP + (K & 3) * PP;
+    const T* Pp = sP + (kc(K + 1) & 3) * PP;
+    T* dst = sG + (K % 3) * GP;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (inG(q)) {
+        const int m = gM[q];
         const T p = P0[m];
         const T lap = (P0[m + 1] - 2 * p + P0[m - 1]) * ihx2 + (P0[m + PX] - 2 * p + P0[m - PX]) * ihy2 +
                       (Pp[m] - 2 * p + Pm[m]) * ihz2;
@@ -205,33 +292,43 @@ __global__ void __launch_bounds__(kBlock)
         T b = 0;
         if (K == 0) b += gb * ((T)1 - ps * ps);
         if (K == fnz - 1) b += gt * ((T)1 - ps * ps);
-        dst[e] = -cn2 * (lap + b) + S * (p - ps) + ps * ps * ps - ps;
+        dst[tid + q * nth] = -cn2 * (lap + b) + S * (p - ps) + ps * ps * ps - ps;
       }
     }
   };
-  auto load_ps = [&](int Kf, T* psr) {
-    const int K = kc(Kf);
-#pragma unroll
-    for (int q = 0; q < RMAX; ++q) {
-      const int e = tid + q * nth;
-      if (e < GP) {
-        const int id = gidx(K, e);
-        const T an = phin[id];
-        psr[q] = first ? an : (T)2 * an - phinm1[id];
-      }
-    }
-  };
+  // registers in flight: phi on the two fine layers and phi* on the two G layers that the
+  // next step brings in
+  T pfa[R], pfb[R], psa[R], psb[R];
   {
-    T ps0[RMAX], ps1[RMAX], ps2[RMAX];
-    for (int Kf = 2 * k0 - 1; Kf <= 2 * k0 + 3; ++Kf) loadP(Kf);
+    // G on fine layers 2k0 .. 2k0+2 needs phi on 2k0-1 .. 2k0+3; with a ring of four the
+    // layer 2k0+3 enters after G on 2k0 and 2k0+1 (its slot is that of 2k0-1)
+    T ps0[R], ps1[R];
+    load_p(2 * k0 - 1, pfa);
+    load_p(2 * k0, pfb);
     load_ps(2 * k0, ps0);
     load_ps(2 * k0 + 1, ps1);
-    load_ps(2 * k0 + 2, ps2);
+    store_p(2 * k0 - 1, pfa);
+    store_p(2 * k0, pfb);
+    load_p(2 * k0 + 1, pfa);
+    load_p(2 * k0 + 2, pfb);
+    store_p(2 * k0 + 1, pfa);
+    store_p(2 * k0 + 2, pfb);
+    load_p(2 * k0 + 3, pfa);
     __syncthreads();
-    computeG_with(2 * k0, ps0);
-    computeG_with(2 * k0 + 1, ps1);
-    computeG_with(2 * k0 + 2, ps2);
+    compute_g(2 * k0, ps0);
+    compute_g(2 * k0 + 1, ps1);
+    load_ps(2 * k0 + 2, ps0);
     __syncthreads();
+    store_p(2 * k0 + 3, pfa);
+    __syncthreads();
+    compute_g(2 * k0 + 2, ps0);
+    __syncthreads();
+    if (KB > 1) {
+      load_p(2 * k0 + 4, pfa);
+      load_p(2 * k0 + 5, pfb);
+      load_ps(2 * k0 + 3, psa);
+      load_ps(2 * k0 + 4, psb);
+    }
   }
   const int tx = threadIdx.x;
   const bool upper = threadIdx.y >= CY;
@@ -243,26 +340,10 @@ __global__ void __launch_bounds__(kBlock)
   const int plane = cnx * cny;
   const int ndy = ry + 1;
   for (int k = k0; k < k0 + KB; ++k) {
-    const bool more = k + 1 < k0 + KB;
-    // prefetch: phi^{n+1} on fine layers 2k+4, 2k+5 and phi* on 2k+3, 2k+4
-    T pf4[RMAX], pf5[RMAX], ps3[RMAX], ps4[RMAX];
-    if (more) {
-      const int K4 = kc(2 * k + 4), K5 = kc(2 * k + 5);
-#pragma unroll
-      for (int q = 0; q < RMAX; ++q) {
-        const int e = tid + q * nth;
-        if (e < PP) {
-          pf4[q] = phinew[pidx(K4, e)];
-          pf5[q] = phinew[pidx(K5, e)];
-        }
-      }
-      load_ps(2 * k + 3, ps3);
-      load_ps(2 * k + 4, ps4);
-    }
     // Separable sums of the tensor-product rule: per z layer and y row, x sums over the
     // centre pair (dx 0,1) and the face pair (dx 1,2); then y pairs, then z pairs. The 1/8
     // weight is applied once at the end (a centre-located y axis without refinement counts
-    // its single cell twice). Lower rows: phi (src sP, ring 6); upper rows: G (sG, ring 4).
+    // its single cell twice). Lower rows: phi (ring of 4); upper rows: G (ring of 3).
     {
       T z_[3][4];  // per dz: [YcXc, YcXf, YfXc, YfXf]
 #pragma unroll
@@ -272,8 +353,8 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
           const int gy = ry * ty + (dy < ndy ? dy : 0);
-          const T* pr = upper ? sG + (K % 4) * GP + gy * GX + 2 * tx
-                              : sP + (K % 6) * PP + (gy + 1) * PX + 2 * tx + 1;
+          const T* pr = upper ? sG + (K % 3) * GP + gy * GX + 2 * tx
+                              : sP + (K & 3) * PP + (gy + 1) * PX + 2 * tx + 1;
           xc[dy] = pr[0] + pr[1];
           xf[dy] = pr[1] + pr[2];
         }
@@ -313,23 +394,27 @@ __global__ void __launch_bounds__(kBlock)
         }
       }
     }
-    if (more) {
-      // fine phi layers 2k+4, 2k+5 replace 2k-2, 2k-1; G on 2k+3, 2k+4 replaces 2k-1, 2k
-      const int K4 = kc(2 * k + 4), K5 = kc(2 * k + 5);
-      T* d4 = sP + (K4 % 6) * PP;
-      T* d5 = sP + (K5 % 6) * PP;
+    if (k + 1 < k0 + KB) {
+      // phi on 2k+4, 2k+5 replaces 2k, 2k+1 (no longer read); G on 2k+3, 2k+4 replaces
+      // 2k, 2k+1. The loads for the step after next go out before G is evaluated.
       __syncthreads();
+      store_p(2 * k + 4, pfa);
+      store_p(2 * k + 5, pfb);
+      T p3[R], p4[R];
 #pragma unroll
-      for (int q = 0; q < RMAX; ++q) {
-        const int e = tid + q * nth;
-        if (e < PP) {
-          d4[e] = pf4[q];
-          d5[e] = pf5[q];
-        }
+      for (int q = 0; q < R; ++q) {
+        p3[q] = psa[q];
+        p4[q] = psb[q];
+      }
+      if (k + 2 < k0 + KB) {
+        load_p(2 * k + 6, pfa);
+        load_p(2 * k + 7, pfb);
+        load_ps(2 * k + 5, psa);
+        load_ps(2 * k + 6, psb);
       }
       __syncthreads();
-      computeG_with(2 * k + 3, ps3);
-      computeG_with(2 * k + 4, ps4);
+      compute_g(2 * k + 3, p3);
+      compute_g(2 * k + 4, p4);
       __syncthreads();
     }
   }
@@ -402,9 +487,17 @@ hipError_t launch_ch_rhs(const Dims& f, const Dims& c, const StepConsts& k, ChIn
   int KB = 16;
   while (KB > 2 && (f.nz / KB) * tiles < 1024) KB >>= 1;
   if (KB > f.nz) KB = f.nz;
-  const size_t shm = (size_t)6 * (TX + 2) * (TY + 2) * sizeof(T);
-  hipLaunchKernelGGL(k_ch_rhs<T>, dim3(f.nx / TX, f.ny / TY, f.nz / KB), dim3(TX, TY, 1), shm, st,
-                     in.phin, in.phinm1, pv, rhs, f.nx, f.ny, f.nz, KB, (T)f.ihx, (T)f.ihy, (T)f.ihz, k);
+  const int HP = (TX + 2) * (TY + 2);
+  const int need = (HP + TX * TY - 1) / (TX * TY);
+  if (need > 4) return hipErrorInvalidConfiguration;
+  const size_t shm = (size_t)6 * HP * sizeof(T);
+  const dim3 grid(f.nx / TX, f.ny / TY, f.nz / KB), block(TX, TY, 1);
+  if (need <= 2)
+    hipLaunchKernelGGL((k_ch_rhs<T, 2>), grid, block, shm, st, in.phin, in.phinm1, pv, rhs, f.nx, f.ny,
+                       f.nz, KB, (T)f.ihx, (T)f.ihy, (T)f.ihz, k);
+  else
+    hipLaunchKernelGGL((k_ch_rhs<T, 4>), grid, block, shm, st, in.phin, in.phinm1, pv, rhs, f.nx, f.ny,
+                       f.nz, KB, (T)f.ihx, (T)f.ihy, (T)f.ihz, k);
   return hipGetLastError();
 }
 
@@ -426,12 +519,18 @@ hipError_t launch_restrict_g(const Dims& f, const Dims& c, const StepConsts& k, 
   while (KB > 1 && (c.nz / KB) * tiles < 1024) KB >>= 1;
   if (KB > c.nz) KB = c.nz;
   const int GX = 2 * CX + 1, GY = ry * CY + 1;
-  // the kernel keeps at most 6 tile points per thread in registers
-  if ((GX + 2) * (GY + 2) > 6 * 2 * CX * CY || GX * GY > 6 * 2 * CX * CY) return hipErrorInvalidConfiguration;
-  const size_t shm = (size_t)(6 * (GX + 2) * (GY + 2) + 4 * GX * GY) * sizeof(T);
-  hipLaunchKernelGGL(k_restrict_g<T>, dim3(c.nx / CX, c.ny / CY, c.nz / KB), dim3(CX, 2 * CY, 1), shm, st,
-                     phinew, phin, phinm1, r, f.nx, f.ny, f.nz, (T)f.ihx, (T)f.ihy, (T)f.ihz, c.nx,
-                     c.ny, c.nz, ry, KB, k);
+  const int PP = (GX + 2) * (GY + 2), nth = 2 * CX * CY;
+  // each thread keeps at most R points of a tile in registers
+  const int need = (PP + nth - 1) / nth;
+  if (need > 6) return hipErrorInvalidConfiguration;
+  const size_t shm = (size_t)(4 * PP + 3 * GX * GY) * sizeof(T);
+  const dim3 grid(c.nx / CX, c.ny / CY, c.nz / KB), block(CX, 2 * CY, 1);
+  if (need <= 3)
+    hipLaunchKernelGGL((k_restrict_g<T, 3>), grid, block, shm, st, phinew, phin, phinm1, r, f.nx, f.ny,
+                       f.nz, (T)f.ihx, (T)f.ihy, (T)f.ihz, c.nx, c.ny, c.nz, ry, KB, k);
+  else
+    hipLaunchKernelGGL((k_restrict_g<T, 6>), grid, block, shm, st, phinew, phin, phinm1, r, f.nx, f.ny,
+                       f.nz, (T)f.ihx, (T)f.ihy, (T)f.ihz, c.nx, c.ny, c.nz, ry, KB, k);
   return hipGetLastError();
 }
 

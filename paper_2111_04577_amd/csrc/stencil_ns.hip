@@ -115,9 +115,13 @@ struct RingG {
 // Momentum right-hand side, z-marching: a block owns TX x TY coarse columns and KB layers;
 // the extrapolated velocities (three-layer rings) and G at centres (four-layer ring, for J)
 // live in LDS, every thread forms all three components of its cell from them. The other
-// inputs are read once or twice per cell from global memory.
-template <typename T>
+// inputs are read once or twice per cell from global memory. VE selects the Oldroyd-B form
+// (the weighted polymer stress rings and the divergence term); each thread loads at most RP
+// points of a halo tile. The Newtonian FP64 form is held
+// to 128 registers, so that four 256-thread blocks share a CU.
+template <typename T, bool VE, int RP>
 __global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && !VE ? 4 : 1)))
     k_momentum_rhs_zm(NsIn<T> in, Restricted<T> R, T* __restrict__ ru, T* __restrict__ rv,
                       T* __restrict__ rw, int nx, int ny, int nz, int KB, T ihx, T ihy, T ihz,
                       StepConsts c) {
@@ -133,35 +137,58 @@ __global__ void __launch_bounds__(kBlock)
   T* sG = sW + 3 * HP;
   T* sT3 = sG + 4 * HP;  // viscoelastic: [xz, yz, zz] x 3 slots, then [xx, yy, xy]
   T* sT1 = sT3 + 9 * HP;
-  const bool ve = in.viscoelastic != 0;
+  constexpr bool ve = VE;
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * TX + tx, nth = TX * TY;
   const int i = X0 + tx, j = Y0 + ty;
   const int f = c.first;
   const Field<T> U{in.un, in.unm1, nx, ny, nz, f}, V{in.vn, in.vnm1, nx, ny, nz, f},
       W{in.wn, in.wnm1, nx, ny, nz, f};
-  const Coarse<T> Gc{R.G_c, nx, ny, nz};
+  // halo tile points of this thread (at most RP): in-layer byte offsets (a uniform layer base
+  // plus a 32-bit lane offset), computed once. The wall rules depend on the layer only.
+  unsigned hOff[RP];
+#pragma unroll
+  for (int q = 0; q < RP; ++q) {
+    const int e = tid + q * nth;
+    const int hy = e / HX, hx = e - hy * HX;
+    hOff[q] = e < HP ? (unsigned)(wrap(Y0 - 1 + hy, ny) * nx + wrap(X0 - 1 + hx, nx)) * (unsigned)sizeof(T) : 0u;
+  }
+  auto for_tile = [&](auto&& fn) {
+#pragma unroll
+    for (int q = 0; q < RP; ++q)
+      if (tid + q * nth < HP) fn(tid + q * nth, hOff[q]);
+  };
+  const size_t layer = (size_t)ny * nx;
+  auto star_at = [&](const T* a, const T* b, unsigned o) {
+    return f ? ld_at(a, o) : (T)2 * ld_at(a, o) - ld_at(b, o);
+  };
+  // extrapolated velocities on layer kk: no-slip ghosts (minus the adjacent layer) for u, v
+  // beyond the walls; w is zero on and beyond the walls
   auto load_vel = [&](int kk) {
     const int sl = (kk - K0 + 1) % 3;
-    for (int e = tid; e < HP; e += nth) {
-      const int hy = e / HX, hx = e - hy * HX;
-      const int jj = Y0 - 1 + hy, ii = X0 - 1 + hx;
-      sU[sl * HP + e] = U.sd(kk, jj, ii);
-      sV[sl * HP + e] = V.sd(kk, jj, ii);
-      sW[sl * HP + e] = W.sw(kk, jj, ii);
-    }
+    const int kc = min(max(kk, 0), nz - 1);
+    const T sg = (kk < 0 || kk >= nz) ? (T)-1 : (T)1;
+    const bool wz = kk < 0 || kk >= nz - 1;
+    const size_t o = kc * layer;
+    const T *ua = in.un + o, *ub = in.unm1 + o, *va = in.vn + o, *vb = in.vnm1 + o;
+    const T *wa = in.wn + o, *wb = in.wnm1 + o;
+    for_tile([&](int e, unsigned off) {
+      sU[sl * HP + e] = sg * star_at(ua, ub, off);
+      sV[sl * HP + e] = sg * star_at(va, vb, off);
+      sW[sl * HP + e] = wz ? (T)0 : star_at(wa, wb, off);
+    });
   };
   // weighted stress of the components `comps` (tau index) on layer kk into dst[c] slots
   auto load_t = [&](int kk, const int* comps, T* const* dst) {
-    const int kc = min(max(kk, 0), nz - 1);
-    for (int e = tid; e < HP; e += nth) {
-      const int hy = e / HX, hx = e - hy * HX;
-      const int id = (kc * ny + wrap(Y0 - 1 + hy, ny)) * nx + wrap(X0 - 1 + hx, nx);
-      const T w = (T)0.5 * ((T)1 + R.phi_c[id]);
+    const size_t o = min(max(kk, 0), nz - 1) * layer;
+#pragma unroll 1
+    for (int q = 0; q < RP; ++q) {
+      const int e = tid + q * nth;
+      if (e < HP) {
+        const T w = (T)0.5 * ((T)1 + ld_at(R.phi_c + o, hOff[q]));
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const T a = in.taun[comps[c]][id];
-        dst[c][e] = w * (f ? a : (T)2 * a - in.taunm1[comps[c]][id]);
+        for (int c = 0; c < 3; ++c)
+          dst[c][e] = w * star_at(in.taun[comps[c]] + o, in.taunm1[comps[c]] + o, hOff[q]);
       }
     }
   };
@@ -177,10 +204,8 @@ __global__ void __launch_bounds__(kBlock)
   };
   auto load_g = [&](int kk) {
     const int sl = (kk - K0 + 1) & 3;
-    for (int e = tid; e < HP; e += nth) {
-      const int hy = e / HX, hx = e - hy * HX;
-      sG[sl * HP + e] = Gc.atn(kk, Y0 - 1 + hy, X0 - 1 + hx);
-    }
+    const T* g = R.G_c + min(max(kk, 0), nz - 1) * layer;
+    for_tile([&](int e, unsigned off) { sG[sl * HP + e] = ld_at(g, off); });
   };
   load_vel(K0 - 1);
   load_vel(K0);
@@ -224,7 +249,7 @@ __global__ void __launch_bounds__(kBlock)
                                      Tr,
                                      R,
                                      in.un, in.unm1, in.vn, in.vnm1, in.wn, in.wnm1,
-                                     nx, ny, nz, f, in.viscoelastic,
+                                     nx, ny, nz, f, VE ? 1 : 0,
                                      ihx, ihy, ihz,
                                      (T)c.inv_dt, (T)c.inv_re, (T)c.inv_rho0, (T)c.nu_m, (T)c.k_sigma, (T)c.c_j};
     auto rhs = [&](const MomTerms<T>& t, T a) -> T {
@@ -311,8 +336,19 @@ hipError_t launch_momentum_rhs(const Dims& c, const StepConsts& k, NsIn<T> in, R
   while (KB > c.nz) KB >>= 1;
   while (KB > 1 && cols * (c.nz / KB) < 1024) KB >>= 1;
   const size_t shm = (size_t)(in.viscoelastic ? 25 : 13) * (TX + 3) * (TY + 3) * sizeof(T);
-  hipLaunchKernelGGL(k_momentum_rhs_zm<T>, dim3(c.nx / TX, c.ny / TY, c.nz / KB), dim3(TX, TY), shm, st, in, r,
-                     ru, rv, rw, c.nx, c.ny, c.nz, KB, (T)c.ihx, (T)c.ihy, (T)c.ihz, k);
+  const dim3 grid(c.nx / TX, c.ny / TY, c.nz / KB), block(TX, TY);
+  // halo points per thread: 2 for tiles of 32 x 4 and up, 4 for the small tiles of small grids
+  const int need = ((TX + 3) * (TY + 3) + TX * TY - 1) / (TX * TY);
+  if (need > 4) return hipErrorInvalidConfiguration;
+#define DRPF_MOM(VE, RP)                                                                           \
+  hipLaunchKernelGGL((k_momentum_rhs_zm<T, VE, RP>), grid, block, shm, st, in, r, ru, rv, rw, c.nx, \
+                     c.ny, c.nz, KB, (T)c.ihx, (T)c.ihy, (T)c.ihz, k)
+  if (in.viscoelastic) {
+    if (need <= 2) DRPF_MOM(true, 2); else DRPF_MOM(true, 4);
+  } else {
+    if (need <= 2) DRPF_MOM(false, 2); else DRPF_MOM(false, 4);
+  }
+#undef DRPF_MOM
   return hipGetLastError();
 }
 
