@@ -224,10 +224,14 @@ __global__ void __launch_bounds__(kBlock)
   const int GX = 2 * CX + 1, GY = ry * CY + 1, GP = GX * GY;
   const int PX = GX + 2, PY = GY + 2, PP = PX * PY;
   const int X0 = 2 * i0, Y0 = ry * j0;
-  T* sP = reinterpret_cast<T*>(smem);  // 4 slots of phi^{n+1}
-  T* sG = sP + 4 * PP;                 // 3 slots of G
   const int tid = threadIdx.y * CX + threadIdx.x;
   const int nth = CX * blockDim.y;
+  // rings of 4 phi slots (PP entries) and 3 G slots (GP entries), then a scratch area of
+  // R nth - GP entries: the points past a tile are computed and stored there, so that no tile
+  // loop branches
+  T* sP = reinterpret_cast<T*>(smem);
+  T* sG = sP + 4 * PP;
+  T* sX = sG + 3 * GP;
   const bool first = c.first != 0;
   const T ihx2 = fihx * fihx, ihy2 = fihy * fihy, ihz2 = fihz * fihz;
   const T cn2 = (T)c.cn2, S = (T)c.S;
@@ -236,7 +240,8 @@ __global__ void __launch_bounds__(kBlock)
   auto kc = [&](int Kf) { return min(max(Kf, 0), fnz - 1); };
   // per-thread tile points: in-layer byte offsets of the phi tile (with halo) and of the G
   // tile (a uniform layer base plus a 32-bit lane offset), and the LDS index of each G point
-  // in the phi tile
+  // in the phi tile. Points past a tile read the layer's first element and an interior LDS
+  // point.
   unsigned pOff[R], gOff[R];
   int gM[R];
 #pragma unroll
@@ -246,21 +251,20 @@ __global__ void __launch_bounds__(kBlock)
     const int gy = e / GX, gx = e - gy * GX;
     pOff[q] = e < PP ? (unsigned)(wrap(Y0 - 1 + py, fny) * fnx + wrap(X0 - 1 + px, fnx)) * sizeof(T) : 0u;
     gOff[q] = e < GP ? (unsigned)(wrap(Y0 + gy, fny) * fnx + wrap(X0 + gx, fnx)) * sizeof(T) : 0u;
-    gM[q] = e < GP ? (gy + 1) * PX + gx + 1 : 0;
+    gM[q] = e < GP ? (gy + 1) * PX + gx + 1 : PX + 1;
   }
-  auto inP = [&](int q) { return tid + q * nth < PP; };
-  auto inG = [&](int q) { return tid + q * nth < GP; };
   auto load_p = [&](int Kf, T* v) {
     const T* src = phinew + kc(Kf) * layer;
 #pragma unroll
-    for (int q = 0; q < R; ++q)
-      if (inP(q)) v[q] = ld_at(src, pOff[q]);
+    for (int q = 0; q < R; ++q) v[q] = ld_at(src, pOff[q]);
   };
   auto store_p = [&](int Kf, const T* v) {
     T* dst = sP + (kc(Kf) & 3) * PP;
 #pragma unroll
-    for (int q = 0; q < R; ++q)
-      if (inP(q)) dst[tid + q * nth] = v[q];
+    for (int q = 0; q < R; ++q) {
+      const int e = tid + q * nth;
+      *(e < PP ? dst + e : sX + (e - PP)) = v[q];
+    }
   };
   // phi* at the G points of fine layer Kf
   auto load_ps = [&](int Kf, T* v) {
@@ -268,10 +272,8 @@ __global__ void __launch_bounds__(kBlock)
     const T* b = phinm1 + kc(Kf) * layer;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      if (inG(q)) {
-        const T an = ld_at(a, gOff[q]);
-        v[q] = first ? an : (T)2 * an - ld_at(b, gOff[q]);
-      }
+      const T an = ld_at(a, gOff[q]);
+      v[q] = first ? an : (T)2 * an - ld_at(b, gOff[q]);
     }
   };
   // G on fine layer Kf from the phi ring and phi* at the G points
@@ -283,7 +285,8 @@ __global__ void __launch_bounds__(kBlock)
     T* dst = sG + (K % 3) * GP;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      if (inG(q)) {
+      {
+        const int e = tid + q * nth;
         const int m = gM[q];
         const T p = P0[m];
         const T lap = (P0[m + 1] - 2 * p + P0[m - 1]) * ihx2 + (P0[m + PX] - 2 * p + P0[m - PX]) * ihy2 +
@@ -292,7 +295,7 @@ __global__ void __launch_bounds__(kBlock)
         T b = 0;
         if (K == 0) b += gb * ((T)1 - ps * ps);
         if (K == fnz - 1) b += gt * ((T)1 - ps * ps);
-        dst[tid + q * nth] = -cn2 * (lap + b) + S * (p - ps) + ps * ps * ps - ps;
+        *(e < GP ? dst + e : sX + (e - GP)) = -cn2 * (lap + b) + S * (p - ps) + ps * ps * ps - ps;
       }
     }
   };
@@ -523,8 +526,9 @@ hipError_t launch_restrict_g(const Dims& f, const Dims& c, const StepConsts& k, 
   // each thread keeps at most R points of a tile in registers
   const int need = (PP + nth - 1) / nth;
   if (need > 6) return hipErrorInvalidConfiguration;
-  const size_t shm = (size_t)(4 * PP + 3 * GX * GY) * sizeof(T);
   const dim3 grid(c.nx / CX, c.ny / CY, c.nz / KB), block(CX, 2 * CY, 1);
+  const int GP = GX * GY, Rk = need <= 3 ? 3 : 6;
+  const size_t shm = (size_t)(4 * PP + 3 * GP + Rk * nth - GP) * sizeof(T);
   if (need <= 3)
     hipLaunchKernelGGL((k_restrict_g<T, 3>), grid, block, shm, st, phinew, phin, phinm1, r, f.nx, f.ny,
                        f.nz, (T)f.ihx, (T)f.ihy, (T)f.ihz, c.nx, c.ny, c.nz, ry, KB, k);
