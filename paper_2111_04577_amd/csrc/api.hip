@@ -350,6 +350,8 @@ int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t
     ni.taunm1[m] = ve ? io.taunm1[m] : nullptr;
   }
   ni.viscoelastic = ve ? 1 : 0;
+  // the first three stage-1 polymer arrays are free until the polymer update
+  for (int a = 0; a < 3; ++a) ni.pol[a] = ve ? reinterpret_cast<T*>(g->ws + g->o.tau1[a]) : nullptr;
   HIPCHK(launch_momentum_rhs<T>(C, K, ni, R, Rc, Rc + nc, Rc + 2 * nc, st), "momentum_rhs");
   mark(g, 7, st);
   const T* inc[4] = {Rc, Rc + nc, Rc + 2 * nc, nullptr};

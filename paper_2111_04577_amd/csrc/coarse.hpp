@@ -72,6 +72,7 @@ struct MomTerms {
 // ghosts, read from global memory.
 template <typename T>
 struct TauW {
+  static constexpr bool pre = false;
   const T* const* taun;
   const T* const* taunm1;
   const T* phic;
@@ -85,10 +86,43 @@ struct TauW {
   }
 };
 
+// Divergence of the weighted polymer stress at the u, v and w faces of cell (k, j, i), from an
+// accessor tp(comp, k, j, i) of the weighted stress at centres (comp: xx, yy, zz, xy, xz, yz):
+// the normal component by a face difference, the shear components averaged to the edges
+// first.
+template <typename T, typename TP>
+__device__ __forceinline__ T polymer_div_u(const TP& tp, int k, int j, int i, T ihx, T ihy, T ihz) {
+  const T q = (T)0.25;
+  auto txy = [&](int jj) { return q * (tp(3, k, jj, i) + tp(3, k, jj, i + 1) + tp(3, k, jj + 1, i) + tp(3, k, jj + 1, i + 1)); };
+  auto txz = [&](int kk) { return q * (tp(4, kk, j, i) + tp(4, kk, j, i + 1) + tp(4, kk + 1, j, i) + tp(4, kk + 1, j, i + 1)); };
+  return (tp(0, k, j, i + 1) - tp(0, k, j, i)) * ihx + (txy(j) - txy(j - 1)) * ihy + (txz(k) - txz(k - 1)) * ihz;
+}
+template <typename T, typename TP>
+__device__ __forceinline__ T polymer_div_v(const TP& tp, int k, int j, int i, T ihx, T ihy, T ihz) {
+  const T q = (T)0.25;
+  auto txy = [&](int ii) { return q * (tp(3, k, j, ii) + tp(3, k, j, ii + 1) + tp(3, k, j + 1, ii) + tp(3, k, j + 1, ii + 1)); };
+  auto tyz = [&](int kk) { return q * (tp(5, kk, j, i) + tp(5, kk, j + 1, i) + tp(5, kk + 1, j, i) + tp(5, kk + 1, j + 1, i)); };
+  return (txy(i) - txy(i - 1)) * ihx + (tp(1, k, j + 1, i) - tp(1, k, j, i)) * ihy + (tyz(k) - tyz(k - 1)) * ihz;
+}
+template <typename T, typename TP>
+__device__ __forceinline__ T polymer_div_w(const TP& tp, int k, int j, int i, T ihx, T ihy, T ihz) {
+  const T q = (T)0.25;
+  auto txz = [&](int ii) { return q * (tp(4, k, j, ii) + tp(4, k, j, ii + 1) + tp(4, k + 1, j, ii) + tp(4, k + 1, j, ii + 1)); };
+  auto tyz = [&](int jj) { return q * (tp(5, k, jj, i) + tp(5, k, jj + 1, i) + tp(5, k + 1, jj, i) + tp(5, k + 1, jj + 1, i)); };
+  return (txz(i) - txz(i - 1)) * ihx + (tyz(j) - tyz(j - 1)) * ihy + (tp(2, k + 1, j, i) - tp(2, k, j, i)) * ihz;
+}
+
+// The three face divergences precomputed by a separate pass (arrays shaped like u, v, w).
+template <typename T>
+struct PolPre {
+  static constexpr bool pre = true;
+  const T* p[3];
+};
+
 // Inputs of the momentum right-hand side. VA reads the extrapolated velocities (methods s, sd,
 // sw as in Field), GA the restricted chemical potential at centres (at, atn as in Coarse) and
-// TA the weighted polymer stress (at as in TauW): from global memory or from LDS rings (the
-// z-marching kernel).
+// TA the weighted polymer stress (at as in TauW, from global memory or LDS rings; or PolPre,
+// whose pre flag says that the face divergences are given).
 template <typename T, typename VA, typename GA, typename TA = TauW<T>>
 struct MomCtxG {
   using value_type = T;
@@ -156,16 +190,10 @@ __device__ __forceinline__ MomTerms<typename C::value_type> mom_u(const C& m, in
   // polymer divergence
   T pol = 0;
   if (m.ve) {
-    const T q = (T)0.25;
-    pol = (m.Tp(0, k, j, i + 1) - m.Tp(0, k, j, i)) * ihx;
-    auto txy = [&](int jj) {
-      return q * (m.Tp(3, k, jj, i) + m.Tp(3, k, jj, i + 1) + m.Tp(3, k, jj + 1, i) + m.Tp(3, k, jj + 1, i + 1));
-    };
-    pol += (txy(j) - txy(j - 1)) * ihy;
-    auto txz = [&](int kk) {
-      return q * (m.Tp(4, kk, j, i) + m.Tp(4, kk, j, i + 1) + m.Tp(4, kk + 1, j, i) + m.Tp(4, kk + 1, j, i + 1));
-    };
-    pol += (txz(k) - txz(k - 1)) * ihz;
+    if constexpr (decltype(m.Tw)::pre)
+      pol = m.Tw.p[0][id];
+    else
+      pol = polymer_div_u<T>([&](int c, int kk, int jj, int ii) { return m.Tp(c, kk, jj, ii); }, k, j, i, ihx, ihy, ihz);
   }
   const T ri = m.R.ri_x[id];
   const T gpn = (m.Pn.n(k, j, i + 1) - m.Pn.n(k, j, i)) * ihx;
@@ -206,16 +234,10 @@ __device__ __forceinline__ MomTerms<typename C::value_type> mom_v(const C& m, in
   vis += (syzp - syzm) * ihz;
   T pol = 0;
   if (m.ve) {
-    const T q = (T)0.25;
-    auto txy = [&](int ii) {
-      return q * (m.Tp(3, k, j, ii) + m.Tp(3, k, j, ii + 1) + m.Tp(3, k, j + 1, ii) + m.Tp(3, k, j + 1, ii + 1));
-    };
-    pol = (txy(i) - txy(i - 1)) * ihx;
-    pol += (m.Tp(1, k, j + 1, i) - m.Tp(1, k, j, i)) * ihy;
-    auto tyz = [&](int kk) {
-      return q * (m.Tp(5, kk, j, i) + m.Tp(5, kk, j + 1, i) + m.Tp(5, kk + 1, j, i) + m.Tp(5, kk + 1, j + 1, i));
-    };
-    pol += (tyz(k) - tyz(k - 1)) * ihz;
+    if constexpr (decltype(m.Tw)::pre)
+      pol = m.Tw.p[1][id];
+    else
+      pol = polymer_div_v<T>([&](int c, int kk, int jj, int ii) { return m.Tp(c, kk, jj, ii); }, k, j, i, ihx, ihy, ihz);
   }
   const T ri = m.R.ri_y[id];
   const T gpn = (m.Pn.n(k, j + 1, i) - m.Pn.n(k, j, i)) * ihy;
@@ -256,14 +278,10 @@ __device__ __forceinline__ MomTerms<typename C::value_type> mom_w(const C& m, in
   vis += (syzp - syzm) * ihy;
   T pol = 0;
   if (m.ve) {
-    const T q = (T)0.25;
-    auto txz = [&](int ii) {
-      return q * (m.Tp(4, k, j, ii) + m.Tp(4, k, j, ii + 1) + m.Tp(4, k + 1, j, ii) + m.Tp(4, k + 1, j, ii + 1));
-    };
-    auto tyz = [&](int jj) {
-      return q * (m.Tp(5, k, jj, i) + m.Tp(5, k, jj + 1, i) + m.Tp(5, k + 1, jj, i) + m.Tp(5, k + 1, jj + 1, i));
-    };
-    pol = (txz(i) - txz(i - 1)) * ihx + (tyz(j) - tyz(j - 1)) * ihy + (m.Tp(2, k + 1, j, i) - m.Tp(2, k, j, i)) * ihz;
+    if constexpr (decltype(m.Tw)::pre)
+      pol = m.Tw.p[2][id];
+    else
+      pol = polymer_div_w<T>([&](int c, int kk, int jj, int ii) { return m.Tp(c, kk, jj, ii); }, k, j, i, ihx, ihy, ihz);
   }
   const T ri = m.R.ri_z[id];
   const T gpn = (m.Pn.n(k + 1, j, i) - m.Pn.n(k, j, i)) * ihz;

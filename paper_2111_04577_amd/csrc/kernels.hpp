@@ -75,6 +75,9 @@ struct NsIn {
   const T* taun[6];
   const T* taunm1[6];
   int viscoelastic;
+  // 3D viscoelastic: scratch for the face divergences of the weighted polymer stress (three
+  // coarse arrays, written and read within launch_momentum_rhs)
+  T* pol[3];
 };
 template <typename T>
 hipError_t launch_momentum_rhs(const Dims& c, const StepConsts& k, NsIn<T> in, Restricted<T> r,

@@ -112,16 +112,106 @@ struct RingG {
   __device__ __forceinline__ T atn(int kk, int jj, int ii) const { return at(kk, jj, ii); }
 };
 
+// Halo tile of a z-marching block: TX x TY coarse columns with one point of halo below and two
+// above in x and y. Each thread owns at most RP tile points; their in-layer byte offsets (a
+// uniform layer base plus a 32-bit lane offset) are computed once.
+template <typename T, int RP>
+struct HaloTile {
+  int HX, HP, tid, nth;
+  unsigned off[RP];
+  __device__ __forceinline__ HaloTile(int TX, int TY, int X0, int Y0, int nx, int ny) {
+    HX = TX + 3;
+    HP = HX * (TY + 3);
+    tid = threadIdx.y * TX + threadIdx.x;
+    nth = TX * TY;
+#pragma unroll
+    for (int q = 0; q < RP; ++q) {
+      const int e = tid + q * nth;
+      const int hy = e / HX, hx = e - hy * HX;
+      off[q] = e < HP ? (unsigned)(wrap(Y0 - 1 + hy, ny) * nx + wrap(X0 - 1 + hx, nx)) * (unsigned)sizeof(T) : 0u;
+    }
+  }
+  // fn(tile index, byte offset) for every point of this thread
+  template <typename F>
+  __device__ __forceinline__ void each(F&& fn) const {
+#pragma unroll
+    for (int q = 0; q < RP; ++q)
+      if (tid + q * nth < HP) fn(tid + q * nth, off[q]);
+  }
+};
+
+// Divergence of the weighted polymer stress (1 + phi_c)/2 tau* at the u, v and w faces,
+// z-marching like the momentum kernel: the xz, yz and zz components (read on layers k-1 ..
+// k+1) in three-layer LDS rings, the xx, yy and xy components (layer k only) in one slot each,
+// Neumann clamp on load. The results go to three arrays shaped like u, v, w (the top-wall w
+// face gets zero); the momentum kernel reads them at its own faces.
+template <typename T, int RP>
+__global__ void __launch_bounds__(kBlock)
+    k_polymer_div_zm(NsIn<T> in, const T* __restrict__ phic, int nx, int ny, int nz, int KB, T ihx,
+                     T ihy, T ihz, int first) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int TX = blockDim.x, TY = blockDim.y;
+  int bx, by, bz;
+  xcd_tile(bx, by, bz);
+  const int X0 = bx * TX, Y0 = by * TY, K0 = bz * KB;
+  const HaloTile<T, RP> H(TX, TY, X0, Y0, nx, ny);
+  const int HP = H.HP;
+  T* sT3 = reinterpret_cast<T*>(smem);  // [xz, yz, zz] x 3 slots
+  T* sT1 = sT3 + 9 * HP;                // [xx, yy, xy]
+  const size_t layer = (size_t)ny * nx;
+  const int i = X0 + threadIdx.x, j = Y0 + threadIdx.y;
+  auto load_t = [&](int kk, const int* comps, T* const* dst) {
+    const size_t o = min(max(kk, 0), nz - 1) * layer;
+    H.each([&](int e, unsigned off) {
+      const T w = (T)0.5 * ((T)1 + ld_at(phic + o, off));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T a = ld_at(in.taun[comps[c]] + o, off);
+        dst[c][e] = w * (first ? a : (T)2 * a - ld_at(in.taunm1[comps[c]] + o, off));
+      }
+    });
+  };
+  const int c3[3] = {4, 5, 2}, c1[3] = {0, 1, 3};
+  auto load_t3 = [&](int kk) {
+    const int sl = (kk - K0 + 1) % 3;
+    T* const dst[3] = {sT3 + (0 * 3 + sl) * HP, sT3 + (1 * 3 + sl) * HP, sT3 + (2 * 3 + sl) * HP};
+    load_t(kk, c3, dst);
+  };
+  auto load_t1 = [&](int kk) {
+    T* const dst[3] = {sT1, sT1 + HP, sT1 + 2 * HP};
+    load_t(kk, c1, dst);
+  };
+  load_t3(K0 - 1);
+  load_t3(K0);
+  for (int k = K0; k < K0 + KB; ++k) {
+    load_t3(k + 1);
+    load_t1(k);
+    __syncthreads();
+    const int t0 = (k - K0) % 3, t1 = (k - K0 + 1) % 3, t2 = (k - K0 + 2) % 3;
+    const RingT<T> Tr{{{sT3 + t0 * HP, sT3 + t1 * HP, sT3 + t2 * HP},
+                       {sT3 + (3 + t0) * HP, sT3 + (3 + t1) * HP, sT3 + (3 + t2) * HP},
+                       {sT3 + (6 + t0) * HP, sT3 + (6 + t1) * HP, sT3 + (6 + t2) * HP}},
+                      {sT1, sT1 + HP, sT1 + 2 * HP},
+                      k, X0, Y0, H.HX};
+    auto tp = [&](int c, int kk, int jj, int ii) { return Tr.at(c, kk, jj, ii); };
+    const int id = (k * ny + j) * nx + i;
+    in.pol[0][id] = polymer_div_u<T>(tp, k, j, i, ihx, ihy, ihz);
+    in.pol[1][id] = polymer_div_v<T>(tp, k, j, i, ihx, ihy, ihz);
+    in.pol[2][id] = k == nz - 1 ? (T)0 : polymer_div_w<T>(tp, k, j, i, ihx, ihy, ihz);
+    __syncthreads();
+  }
+}
+
 // Momentum right-hand side, z-marching: a block owns TX x TY coarse columns and KB layers;
 // the extrapolated velocities (three-layer rings) and G at centres (four-layer ring, for J)
 // live in LDS, every thread forms all three components of its cell from them. The other
-// inputs are read once or twice per cell from global memory. VE selects the Oldroyd-B form
-// (the weighted polymer stress rings and the divergence term); each thread loads at most RP
-// points of a halo tile. The Newtonian FP64 form is held
-// to 128 registers, so that four 256-thread blocks share a CU.
+// inputs are read once or twice per cell from global memory; VE (Oldroyd-B) adds the face
+// divergences of the weighted polymer stress, given by k_polymer_div_zm. Each thread loads at
+// most RP points of a halo tile. The FP64 form is held to 128 registers, so that four
+// 256-thread blocks share a CU.
 template <typename T, bool VE, int RP>
 __global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && !VE ? 4 : 1)))
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 1)))
     k_momentum_rhs_zm(NsIn<T> in, Restricted<T> R, T* __restrict__ ru, T* __restrict__ rv,
                       T* __restrict__ rw, int nx, int ny, int nz, int KB, T ihx, T ihy, T ihz,
                       StepConsts c) {
@@ -130,34 +220,14 @@ __global__ void __launch_bounds__(kBlock)
   int bx, by, bz;
   xcd_tile(bx, by, bz);
   const int X0 = bx * TX, Y0 = by * TY, K0 = bz * KB;
-  const int HX = TX + 3, HY = ny == 1 ? 1 : TY + 3, HP = HX * HY, ys = ny == 1 ? 0 : HX;
+  const HaloTile<T, RP> H(TX, TY, X0, Y0, nx, ny);
+  const int HP = H.HP, ys = H.HX;
   T* sU = reinterpret_cast<T*>(smem);
   T* sV = sU + 3 * HP;
   T* sW = sV + 3 * HP;
   T* sG = sW + 3 * HP;
-  T* sT3 = sG + 4 * HP;  // viscoelastic: [xz, yz, zz] x 3 slots, then [xx, yy, xy]
-  T* sT1 = sT3 + 9 * HP;
-  constexpr bool ve = VE;
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  const int tid = ty * TX + tx, nth = TX * TY;
-  const int i = X0 + tx, j = Y0 + ty;
+  const int i = X0 + threadIdx.x, j = Y0 + threadIdx.y;
   const int f = c.first;
-  const Field<T> U{in.un, in.unm1, nx, ny, nz, f}, V{in.vn, in.vnm1, nx, ny, nz, f},
-      W{in.wn, in.wnm1, nx, ny, nz, f};
-  // halo tile points of this thread (at most RP): in-layer byte offsets (a uniform layer base
-  // plus a 32-bit lane offset), computed once. The wall rules depend on the layer only.
-  unsigned hOff[RP];
-#pragma unroll
-  for (int q = 0; q < RP; ++q) {
-    const int e = tid + q * nth;
-    const int hy = e / HX, hx = e - hy * HX;
-    hOff[q] = e < HP ? (unsigned)(wrap(Y0 - 1 + hy, ny) * nx + wrap(X0 - 1 + hx, nx)) * (unsigned)sizeof(T) : 0u;
-  }
-  auto for_tile = [&](auto&& fn) {
-#pragma unroll
-    for (int q = 0; q < RP; ++q)
-      if (tid + q * nth < HP) fn(tid + q * nth, hOff[q]);
-  };
   const size_t layer = (size_t)ny * nx;
   auto star_at = [&](const T* a, const T* b, unsigned o) {
     return f ? ld_at(a, o) : (T)2 * ld_at(a, o) - ld_at(b, o);
@@ -172,57 +242,25 @@ __global__ void __launch_bounds__(kBlock)
     const size_t o = kc * layer;
     const T *ua = in.un + o, *ub = in.unm1 + o, *va = in.vn + o, *vb = in.vnm1 + o;
     const T *wa = in.wn + o, *wb = in.wnm1 + o;
-    for_tile([&](int e, unsigned off) {
+    H.each([&](int e, unsigned off) {
       sU[sl * HP + e] = sg * star_at(ua, ub, off);
       sV[sl * HP + e] = sg * star_at(va, vb, off);
       sW[sl * HP + e] = wz ? (T)0 : star_at(wa, wb, off);
     });
   };
-  // weighted stress of the components `comps` (tau index) on layer kk into dst[c] slots
-  auto load_t = [&](int kk, const int* comps, T* const* dst) {
-    const size_t o = min(max(kk, 0), nz - 1) * layer;
-#pragma unroll 1
-    for (int q = 0; q < RP; ++q) {
-      const int e = tid + q * nth;
-      if (e < HP) {
-        const T w = (T)0.5 * ((T)1 + ld_at(R.phi_c + o, hOff[q]));
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-          dst[c][e] = w * star_at(in.taun[comps[c]] + o, in.taunm1[comps[c]] + o, hOff[q]);
-      }
-    }
-  };
-  const int c3[3] = {4, 5, 2}, c1[3] = {0, 1, 3};
-  auto load_t3 = [&](int kk) {
-    const int sl = (kk - K0 + 1) % 3;
-    T* const dst[3] = {sT3 + (0 * 3 + sl) * HP, sT3 + (1 * 3 + sl) * HP, sT3 + (2 * 3 + sl) * HP};
-    load_t(kk, c3, dst);
-  };
-  auto load_t1 = [&](int kk) {
-    T* const dst[3] = {sT1, sT1 + HP, sT1 + 2 * HP};
-    load_t(kk, c1, dst);
-  };
   auto load_g = [&](int kk) {
     const int sl = (kk - K0 + 1) & 3;
     const T* g = R.G_c + min(max(kk, 0), nz - 1) * layer;
-    for_tile([&](int e, unsigned off) { sG[sl * HP + e] = ld_at(g, off); });
+    H.each([&](int e, unsigned off) { sG[sl * HP + e] = ld_at(g, off); });
   };
   load_vel(K0 - 1);
   load_vel(K0);
   load_g(K0 - 1);
   load_g(K0);
   load_g(K0 + 1);
-  if (ve) {
-    load_t3(K0 - 1);
-    load_t3(K0);
-  }
   for (int k = K0; k < K0 + KB; ++k) {
     load_vel(k + 1);
     load_g(k + 2);
-    if (ve) {
-      load_t3(k + 1);
-      load_t1(k);
-    }
     __syncthreads();
     const int v0 = (k - K0) % 3, v1 = (k - K0 + 1) % 3, v2 = (k - K0 + 2) % 3;
     const RingV<T> Ur{{sU + v0 * HP, sU + v1 * HP, sU + v2 * HP}, k, X0, Y0, ys};
@@ -231,13 +269,8 @@ __global__ void __launch_bounds__(kBlock)
     const RingG<T> Gr{{sG + ((k - K0) & 3) * HP, sG + ((k - K0 + 1) & 3) * HP, sG + ((k - K0 + 2) & 3) * HP,
                        sG + ((k - K0 + 3) & 3) * HP},
                       k, X0, Y0, ys};
-    const int t0 = (k - K0) % 3, t1 = (k - K0 + 1) % 3, t2 = (k - K0 + 2) % 3;
-    const RingT<T> Tr{{{sT3 + t0 * HP, sT3 + t1 * HP, sT3 + t2 * HP},
-                       {sT3 + (3 + t0) * HP, sT3 + (3 + t1) * HP, sT3 + (3 + t2) * HP},
-                       {sT3 + (6 + t0) * HP, sT3 + (6 + t1) * HP, sT3 + (6 + t2) * HP}},
-                      {sT1, sT1 + HP, sT1 + 2 * HP},
-                      k, X0, Y0, ys};
-    MomCtxG<T, RingV<T>, RingG<T>, RingT<T>> m{Ur, Vr, Wr,
+    const PolPre<T> Pp{{in.pol[0], in.pol[1], in.pol[2]}};
+    MomCtxG<T, RingV<T>, RingG<T>, PolPre<T>> m{Ur, Vr, Wr,
                                      {in.pn, in.pnm1, nx, ny, nz, f},
                                      {in.pn, nullptr, nx, ny, nz, 1},
                                      Gr,
@@ -246,7 +279,7 @@ __global__ void __launch_bounds__(kBlock)
                                      {R.mu_xy, nx, ny, nz},
                                      {R.mu_xz, nx, ny},
                                      {R.mu_yz, nx, ny},
-                                     Tr,
+                                     Pp,
                                      R,
                                      in.un, in.unm1, in.vn, in.vnm1, in.wn, in.wnm1,
                                      nx, ny, nz, f, VE ? 1 : 0,
@@ -328,18 +361,28 @@ hipError_t launch_momentum_rhs(const Dims& c, const StepConsts& k, NsIn<T> in, R
     return hipGetLastError();
   }
   const int TX = c.nx < 32 ? c.nx : 32;
-  int TY = c.ny < kBlock / TX ? c.ny : kBlock / TX;
-  // the weighted polymer stress adds 12 LDS tile layers; FP64 takes half-height tiles
-  if (in.viscoelastic && sizeof(T) == 8 && TY > 4) TY = 4;
+  const int TY = c.ny < kBlock / TX ? c.ny : kBlock / TX;
   const int cols = (c.nx / TX) * (c.ny / TY);
   int KB = 16;
   while (KB > c.nz) KB >>= 1;
   while (KB > 1 && cols * (c.nz / KB) < 1024) KB >>= 1;
-  const size_t shm = (size_t)(in.viscoelastic ? 25 : 13) * (TX + 3) * (TY + 3) * sizeof(T);
   const dim3 grid(c.nx / TX, c.ny / TY, c.nz / KB), block(TX, TY);
   // halo points per thread: 2 for tiles of 32 x 4 and up, 4 for the small tiles of small grids
-  const int need = ((TX + 3) * (TY + 3) + TX * TY - 1) / (TX * TY);
+  const int HP = (TX + 3) * (TY + 3);
+  const int need = (HP + TX * TY - 1) / (TX * TY);
   if (need > 4) return hipErrorInvalidConfiguration;
+  if (in.viscoelastic) {
+    if (!in.pol[0] || !in.pol[1] || !in.pol[2]) return hipErrorInvalidValue;
+    // the face divergences of the weighted polymer stress first (12 LDS tile slots)
+    const size_t shp = (size_t)12 * HP * sizeof(T);
+    if (need <= 2)
+      hipLaunchKernelGGL((k_polymer_div_zm<T, 2>), grid, block, shp, st, in, r.phi_c, c.nx, c.ny, c.nz, KB,
+                         (T)c.ihx, (T)c.ihy, (T)c.ihz, k.first);
+    else
+      hipLaunchKernelGGL((k_polymer_div_zm<T, 4>), grid, block, shp, st, in, r.phi_c, c.nx, c.ny, c.nz, KB,
+                         (T)c.ihx, (T)c.ihy, (T)c.ihz, k.first);
+  }
+  const size_t shm = (size_t)13 * HP * sizeof(T);
 #define DRPF_MOM(VE, RP)                                                                           \
   hipLaunchKernelGGL((k_momentum_rhs_zm<T, VE, RP>), grid, block, shm, st, in, r, ru, rv, rw, c.nx, \
                      c.ny, c.nz, KB, (T)c.ihx, (T)c.ihy, (T)c.ihz, k)
