@@ -357,17 +357,21 @@ def ingest_pmc(fetch_csv, write_csv, out_json):
                 if "copyBuffer" in name or "copy" in name.lower() and "k_" not in name:
                     copies.append(val)
                     continue
-                m = re.search(r"(k_\w+)<(float|double)(?:, (true|false))?>", name)
+                # template arguments: the element type, then (fft_y) the direction flag, then
+                # launch-shape parameters that do not name a different operation
+                m = re.search(r"(k_\w+)<(float|double)((?:, \w+)*)>", name)
                 if not m:
                     continue
-                per[(m.group(1), m.group(2), m.group(3), int(row["Grid_Size"]))].append(val)
+                flag = re.search(r"\b(true|false)\b", m.group(3)) if m.group(1) == "k_fft_y" else None
+                per[(m.group(1), m.group(2), flag.group(1) if flag else None,
+                     int(row["Grid_Size"]))].append(val)
         scale = copy_bytes / (max(copies) * 1024) if copies else None
         return per, scale
 
     fetch, fs = read(fetch_csv, "FETCH_SIZE")
     write, ws = read(write_csv, "WRITE_SIZE")
     base = {"k_ch_rhs": "ch_rhs", "k_restrict_g": "restrict_g", "k_momentum_rhs": "momentum_rhs",
-            "k_momentum_rhs_zm": "momentum_rhs",
+            "k_momentum_rhs_zm": "momentum_rhs", "k_polymer_div_zm": "polymer_div",
             "k_zpass_ch": "zpass_ch", "k_zpass_ns": "zpass_ns"}
     sizes = defaultdict(set)
     for (k, t, inv, g) in fetch:

@@ -147,8 +147,8 @@ struct HaloTile {
 // face gets zero); the momentum kernel reads them at its own faces.
 template <typename T, int RP>
 __global__ void __launch_bounds__(kBlock)
-    k_polymer_div_zm(NsIn<T> in, const T* __restrict__ phic, int nx, int ny, int nz, int KB, T ihx,
-                     T ihy, T ihz, int first) {
+    k_polymer_div_zm(NsIn<T> in, const T* __restrict__ phic, int first, int nx, int ny, int nz, int KB,
+                     T ihx, T ihy, T ihz) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int TX = blockDim.x, TY = blockDim.y;
   int bx, by, bz;
@@ -183,7 +183,8 @@ __global__ void __launch_bounds__(kBlock)
   };
   load_t3(K0 - 1);
   load_t3(K0);
-  for (int k = K0; k < K0 + KB; ++k) {
+  const int K1 = min(K0 + KB, nz);  // the last block of a column may march fewer layers
+  for (int k = K0; k < K1; ++k) {
     load_t3(k + 1);
     load_t1(k);
     __syncthreads();
@@ -207,14 +208,12 @@ __global__ void __launch_bounds__(kBlock)
 // live in LDS, every thread forms all three components of its cell from them. The other
 // inputs are read once or twice per cell from global memory; VE (Oldroyd-B) adds the face
 // divergences of the weighted polymer stress, given by k_polymer_div_zm. Each thread loads at
-// most RP points of a halo tile. The FP64 form is held to 128 registers, so that four
-// 256-thread blocks share a CU.
+// most RP points of a halo tile.
 template <typename T, bool VE, int RP>
 __global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 1)))
     k_momentum_rhs_zm(NsIn<T> in, Restricted<T> R, T* __restrict__ ru, T* __restrict__ rv,
-                      T* __restrict__ rw, int nx, int ny, int nz, int KB, T ihx, T ihy, T ihz,
-                      StepConsts c) {
+                      T* __restrict__ rw, StepConsts c, int nx, int ny, int nz, int KB, T ihx, T ihy,
+                      T ihz) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int TX = blockDim.x, TY = blockDim.y;
   int bx, by, bz;
@@ -258,7 +257,8 @@ __global__ void __launch_bounds__(kBlock)
   load_g(K0 - 1);
   load_g(K0);
   load_g(K0 + 1);
-  for (int k = K0; k < K0 + KB; ++k) {
+  const int K1 = min(K0 + KB, nz);  // the last block of a column may march fewer layers
+  for (int k = K0; k < K1; ++k) {
     load_vel(k + 1);
     load_g(k + 2);
     __syncthreads();
@@ -350,6 +350,22 @@ __global__ void __launch_bounds__(kBlock)
 
 }  // namespace
 
+// Layers per block of a z-marching launch over `cols` column tiles: as many blocks as the
+// device holds at once (one round, no tail of late blocks), each marching ceil(nz / blocks per
+// column) layers.
+template <typename K>
+int march_layers(K kernel, int threads, size_t shm, int cols, int nz) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, shm) != hipSuccess || nb < 1) nb = 1;
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      ncu < 1)
+    ncu = 1;
+  int zb = nb * ncu / cols;
+  zb = zb < 1 ? 1 : (zb > nz ? nz : zb);
+  return (nz + zb - 1) / zb;
+}
+
 template <typename T>
 hipError_t launch_momentum_rhs(const Dims& c, const StepConsts& k, NsIn<T> in, Restricted<T> r,
                                T* ru, T* rv, T* rw, hipStream_t st) {
@@ -363,29 +379,27 @@ hipError_t launch_momentum_rhs(const Dims& c, const StepConsts& k, NsIn<T> in, R
   const int TX = c.nx < 32 ? c.nx : 32;
   const int TY = c.ny < kBlock / TX ? c.ny : kBlock / TX;
   const int cols = (c.nx / TX) * (c.ny / TY);
-  int KB = 16;
-  while (KB > c.nz) KB >>= 1;
-  while (KB > 1 && cols * (c.nz / KB) < 1024) KB >>= 1;
-  const dim3 grid(c.nx / TX, c.ny / TY, c.nz / KB), block(TX, TY);
+  const dim3 block(TX, TY);
   // halo points per thread: 2 for tiles of 32 x 4 and up, 4 for the small tiles of small grids
   const int HP = (TX + 3) * (TY + 3);
   const int need = (HP + TX * TY - 1) / (TX * TY);
   if (need > 4) return hipErrorInvalidConfiguration;
+  auto go = [&](auto kernel, size_t shm, auto... args) {
+    const int KB = march_layers(kernel, TX * TY, shm, cols, c.nz);
+    const dim3 grid(c.nx / TX, c.ny / TY, (c.nz + KB - 1) / KB);
+    hipLaunchKernelGGL(kernel, grid, block, shm, st, args..., KB, (T)c.ihx, (T)c.ihy, (T)c.ihz);
+  };
   if (in.viscoelastic) {
     if (!in.pol[0] || !in.pol[1] || !in.pol[2]) return hipErrorInvalidValue;
     // the face divergences of the weighted polymer stress first (12 LDS tile slots)
     const size_t shp = (size_t)12 * HP * sizeof(T);
     if (need <= 2)
-      hipLaunchKernelGGL((k_polymer_div_zm<T, 2>), grid, block, shp, st, in, r.phi_c, c.nx, c.ny, c.nz, KB,
-                         (T)c.ihx, (T)c.ihy, (T)c.ihz, k.first);
+      go(k_polymer_div_zm<T, 2>, shp, in, (const T*)r.phi_c, k.first, c.nx, c.ny, c.nz);
     else
-      hipLaunchKernelGGL((k_polymer_div_zm<T, 4>), grid, block, shp, st, in, r.phi_c, c.nx, c.ny, c.nz, KB,
-                         (T)c.ihx, (T)c.ihy, (T)c.ihz, k.first);
+      go(k_polymer_div_zm<T, 4>, shp, in, (const T*)r.phi_c, k.first, c.nx, c.ny, c.nz);
   }
   const size_t shm = (size_t)13 * HP * sizeof(T);
-#define DRPF_MOM(VE, RP)                                                                           \
-  hipLaunchKernelGGL((k_momentum_rhs_zm<T, VE, RP>), grid, block, shm, st, in, r, ru, rv, rw, c.nx, \
-                     c.ny, c.nz, KB, (T)c.ihx, (T)c.ihy, (T)c.ihz, k)
+#define DRPF_MOM(VE, RP) go(k_momentum_rhs_zm<T, VE, RP>, shm, in, r, ru, rv, rw, k, c.nx, c.ny, c.nz)
   if (in.viscoelastic) {
     if (need <= 2) DRPF_MOM(true, 2); else DRPF_MOM(true, 4);
   } else {
