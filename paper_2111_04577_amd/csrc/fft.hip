@@ -41,22 +41,29 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_fwd(const T* __restrict__ in0,
   const T* src = in + (size_t)(line0 - field * lines_per_field) * N;
   for (int e = threadIdx.x; e < nl * M; e += blockDim.x) buf[e] = mk<T>(src[2 * e], src[2 * e + 1]);
   __syncthreads();
-  lds_fft<T, false, false>(buf, M, logM, nl, M, 1, stw);
+  lds_fft<T, false, false>(buf, M, logM, nl, 0, stw);
   // row r = z Ny + ky of this field
   const size_t lines = (size_t)(M + 1) * Ny;
   cx<T>* fbase = out + (size_t)field * lines * (lines_per_field / Ny);
   const int r0 = line0 - field * lines_per_field;
   const int lny = __ffs(Ny) - 1;
   const T half = (T)0.5;
-  for (int e = threadIdx.x; e < nl * (M + 1); e += blockDim.x) {
-    const int b = e / (M + 1);
-    const int k = e - b * (M + 1);
-    const cx<T> zk = buf[b * M + (k == M ? 0 : k)];
-    const cx<T> zm = conj(buf[b * M + (k == 0 ? 0 : M - k)]);
+  auto mode = [&](int b, int k) {
+    const cx<T> zk = buf[(b << logM) + (k == M ? 0 : k)];
+    const cx<T> zm = conj(buf[(b << logM) + (k == 0 ? 0 : M - k)]);
     const cx<T> E = half * (zk + zm);
     const cx<T> O = half * mul_mi(zk - zm);
+    return E + twN[k] * O;
+  };
+  // modes k < M, then the Nyquist mode of every row
+  for (int e = threadIdx.x; e < nl * M; e += blockDim.x) {
+    const int b = e >> logM, k = e & (M - 1);
     const int r = r0 + b, z = r >> lny, ky = r & (Ny - 1);
-    fbase[z * lines + (k < M ? (size_t)ky * M + k : (size_t)M * Ny + ky)] = E + twN[k] * O;
+    fbase[z * lines + (size_t)ky * M + k] = mode(b, k);
+  }
+  for (int b = threadIdx.x; b < nl; b += blockDim.x) {
+    const int r = r0 + b, z = r >> lny, ky = r & (Ny - 1);
+    fbase[z * lines + (size_t)M * Ny + ky] = mode(b, M);
   }
 }
 
@@ -80,8 +87,8 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_inv(const cx<T>* __restrict__ 
   const int r0 = line0 - field0 * lines_per_field;
   const int lny = __ffs(Ny) - 1;
   for (int e = threadIdx.x; e < nl * M; e += blockDim.x) {
-    const int b = e / M;
-    const int k = e - b * M;
+    const int b = e >> logM;
+    const int k = e & (M - 1);
     const int r = r0 + b, z = r >> lny, ky = r & (Ny - 1);
     const cx<T>* src = fbase + z * lines;
     const cx<T> xk = src[(size_t)ky * M + k];
@@ -91,7 +98,7 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_inv(const cx<T>* __restrict__ 
     buf[e] = E + mul_i(O);
   }
   __syncthreads();
-  lds_fft<T, true, false>(buf, M, logM, nl, M, 1, stw);
+  lds_fft<T, true, false>(buf, M, logM, nl, 0, stw);
   const int field = line0 / lines_per_field;
   T* dst = out.p[field] + (size_t)(line0 - field * lines_per_field) * N;
   const T* add = out.add[field];
@@ -124,20 +131,21 @@ __global__ void k_fft_y(cx<T>* __restrict__ data, int Ny, int logNy, int P, int 
   const bool nyq = tile == ntiles - 1;
   const int kx0 = tile * tkx;
   cx<T>* stw = buf + Ny * tkx;
+  const int ltk = __ffs(tkx) - 1;  // tkx is a power of two
   for (int e = threadIdx.x; e < Ny; e += blockDim.x) stw[e] = tw[e];
   for (int e = threadIdx.x; e < Ny * tkx; e += blockDim.x) {
-    const int y = e / tkx;
-    const int t = e - y * tkx;
+    const int y = e >> ltk;
+    const int t = e & (tkx - 1);
     if (nyq)
       buf[e] = t == 0 ? base[(size_t)M * Ny + y] : mk<T>(0, 0);
     else
       buf[e] = base[(size_t)y * M + kx0 + t];
   }
   __syncthreads();
-  lds_fft<T, INV, true>(buf, Ny, logNy, tkx, 1, tkx, stw);
+  lds_fft<T, INV, true>(buf, Ny, logNy, tkx, ltk, stw);
   for (int e = threadIdx.x; e < Ny * tkx; e += blockDim.x) {
-    const int y = e / tkx;
-    const int t = e - y * tkx;
+    const int y = e >> ltk;
+    const int t = e & (tkx - 1);
     if (nyq) {
       if (t == 0) base[(size_t)M * Ny + y] = buf[e];
     } else {

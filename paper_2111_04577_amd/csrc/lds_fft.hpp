@@ -5,79 +5,81 @@
 
 namespace drpf {
 
-// In-LDS complex FFT of `nlines` lines of length M (power of two, M >= 2). Element n of
-// line b lives at buf[b * bs + n * es]. Thread t < nlines * max(M/4, 1) owns one butterfly
-// set q of one line b: with LF (line-fast, for column tiles with es = nlines) consecutive
-// lanes take consecutive lines, so a wavefront touches consecutive LDS words; otherwise
-// consecutive lanes take consecutive q of one line (row tiles with es = 1). Every thread of
-// the block must call this (barriers). Twiddles tw[t] = exp(-2 pi i t / M); the inverse
-// uses their conjugates.
+// In-LDS complex FFT of `nlines` lines of length M = 2^logM (M >= 1). Two layouts:
+//   LF (line-fast, column tiles): element n of line b at buf[(n << lnl) + b], nlines = 2^lnl;
+//       consecutive lanes take consecutive lines, so a wavefront touches consecutive LDS words;
+//   otherwise (row tiles): element n of line b at buf[(b << logM) + n]; consecutive lanes
+//       take consecutive butterfly sets of one line; lnl is unused and nlines any count.
+// Thread t < nlines * max(M/4, 1) owns one butterfly set q of one line b. Every thread of the
+// block must call this (barriers). Twiddles tw[t] = exp(-2 pi i t / M); the inverse uses their
+// conjugates. All index arithmetic is shifts and masks (every extent is a power of two).
 template <typename T, bool INV, bool LF>
-__device__ __forceinline__ void lds_fft(cx<T>* buf, int M, int logM, int nlines, int bs, int es,
-                        const cx<T>* __restrict__ tw) {
-  const int quarter = M >= 4 ? (M >> 2) : 1;
+__device__ __forceinline__ void lds_fft(cx<T>* buf, int M, int logM, int nlines, int lnl,
+                                        const cx<T>* __restrict__ tw) {
+  const int lq = logM >= 2 ? logM - 2 : 0;
+  const int quarter = 1 << lq;
   const int t = threadIdx.x;
-  const bool active = t < nlines * quarter;
+  const bool active = t < (nlines << lq);
   int b = 0, q = 0;
   if (active) {
     if (LF) {
-      q = t / nlines;
-      b = t - q * nlines;
+      q = t >> lnl;
+      b = t & ((1 << lnl) - 1);
     } else {
-      b = t / quarter;
-      q = t - b * quarter;
+      b = t >> lq;
+      q = t & (quarter - 1);
     }
   }
-  cx<T>* line = buf + b * bs;
-  int Ns = 1;
+  // LDS index of element n of this thread's line
+  auto at = [&](int n) -> cx<T>& { return LF ? buf[(n << lnl) + b] : buf[(b << logM) + n]; };
+  int lNs = 0;
   if (logM & 1) {
     // radix-2 stage (Ns = 1, unit twiddles): butterflies j = q and q + M/4 of M/2
     const int half = M >> 1;
     cx<T> v[4];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int j = q + h * quarter;
+      const int j = q + (h << lq);
       if (active && j < half) {
-        v[2 * h] = line[j * es];
-        v[2 * h + 1] = line[(j + half) * es];
+        v[2 * h] = at(j);
+        v[2 * h + 1] = at(j + half);
       }
     }
     __syncthreads();
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int j = q + h * quarter;
+      const int j = q + (h << lq);
       if (active && j < half) {
-        line[(2 * j) * es] = v[2 * h] + v[2 * h + 1];
-        line[(2 * j + 1) * es] = v[2 * h] - v[2 * h + 1];
+        at(2 * j) = v[2 * h] + v[2 * h + 1];
+        at(2 * j + 1) = v[2 * h] - v[2 * h + 1];
       }
     }
     __syncthreads();
-    Ns = 2;
+    lNs = 1;
   }
-  for (; Ns < M; Ns <<= 2) {
+  for (; lNs < logM; lNs += 2) {
+    const int Ns = 1 << lNs;
     const int j = q;
     const int k = j & (Ns - 1);
     cx<T> v[4];
     if (active) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = line[(j + r * quarter) * es];
+      for (int r = 0; r < 4; ++r) v[r] = at(j + (r << lq));
     }
     __syncthreads();
     if (active) {
-      const int step = M / (Ns * 4);
+      // twiddle index r k M / (4 Ns)
+      const int w1 = k << (logM - lNs - 2);
+      cx<T> w[3] = {tw[w1], tw[2 * w1], tw[3 * w1]};
 #pragma unroll
-      for (int r = 1; r < 4; ++r) {
-        cx<T> w = tw[r * k * step];
-        if (INV) w = conj(w);
-        v[r] = v[r] * w;
-      }
+      for (int r = 1; r < 4; ++r) v[r] = v[r] * (INV ? conj(w[r - 1]) : w[r - 1]);
       const cx<T> a = v[0] + v[2], bb = v[0] - v[2], c = v[1] + v[3], d = v[1] - v[3];
       const cx<T> jd = INV ? mul_i(d) : mul_mi(d);
-      const int base = (j - k) * 4 + k;
-      line[base * es] = a + c;
-      line[(base + Ns) * es] = bb + jd;
-      line[(base + 2 * Ns) * es] = a - c;
-      line[(base + 3 * Ns) * es] = bb - jd;
+      const int base = ((j - k) << 2) + k;
+      at(base) = a + c;
+      at(base + Ns) = bb + jd;
+      at(base + 2 * Ns) = a - c;
+      at(base + 3 * Ns) = bb - jd;
     }
     __syncthreads();
   }

@@ -191,22 +191,25 @@ __global__ void __launch_bounds__(1024)
   const int lines = P * Ny;
   const int l0 = xcd_block() * TL;
   const size_t stride = (size_t)lines;
+  const int ltl = __ffs(TL) - 1;  // TL is a power of two
   for (int e = threadIdx.x; e < Nz * TL; e += blockDim.x) {
-    const int row = e / TL, t = e - row * TL;
+    const int row = e >> ltl, t = e & (TL - 1);
     const int l = l0 + t;
     const int pos = (row & 1) ? (Nz - 1 - (row >> 1)) : (row >> 1);
-    buf[pos * TL + t] = l < lines ? S[row * stride + l] : mk<T>(0, 0);
+    buf[(pos << ltl) + t] = l < lines ? S[row * stride + l] : mk<T>(0, 0);
   }
   __syncthreads();
-  lds_fft<T, false, true>(buf, Nz, logNz, TL, 1, TL, stw);
+  lds_fft<T, false, true>(buf, Nz, logNz, TL, ltl, stw);
   const int half = Nz >> 1;
   const T hf = (T)0.5;
   for (int e = threadIdx.x; e < (half + 1) * TL; e += blockDim.x) {
-    const int m = e / TL, t = e - m * TL;
+    const int m = e >> ltl, t = e & (TL - 1);
     const int l = min(l0 + t, lines - 1);
     int ky, kx;
     spec_mode(l, P, Ny, ky, kx);
-    const double lxy = lamx[kx] + lamy[ky];
+    // the eigenvalue factors in the storage type: lambda <= 0, alpha < 0 < c_psi, so neither
+    // factor cancels
+    const T lxy = (T)(lamx[kx] + lamy[ky]);
     const int mr = (Nz - m) & (Nz - 1);  // partner N - m (0 and N/2 pair with themselves)
     const cx<T> Vm = buf[m * TL + t], Vr = buf[mr * TL + t];
     // forward DCT-II coefficient from (V_m, V_{N-m}): X = Re(w A) + i Re(w B),
@@ -216,12 +219,13 @@ __global__ void __launch_bounds__(1024)
       const cx<T> B = hf * mul_mi(V - conj(Vp));
       return mk<T>((w * A).re, (w * B).re);
     };
-    const double dm = (lxy + lamz[m] - c_psi) * (lxy + lamz[m] + alpha);
-    const cx<T> Fm = (T)(scale / dm) * dct_out(Vm, Vr, twq[m]);
+    const T cp = (T)c_psi, al = (T)alpha, sc = (T)scale;
+    const T lm = lxy + (T)lamz[m];
+    const cx<T> Fm = (sc / ((lm - cp) * (lm + al))) * dct_out(Vm, Vr, twq[m]);
     // inverse: Y_m = conj(w_m) [(P_m + Q_{N-m}) + i (Q_m - P_{N-m})], X_N = 0
     if (mr != m) {
-      const double dr = (lxy + lamz[mr] - c_psi) * (lxy + lamz[mr] + alpha);
-      const cx<T> Fr = (T)(scale / dr) * dct_out(Vr, Vm, twq[mr]);
+      const T lr = lxy + (T)lamz[mr];
+      const cx<T> Fr = (sc / ((lr - cp) * (lr + al))) * dct_out(Vr, Vm, twq[mr]);
       buf[m * TL + t] = conj(twq[m]) * mk<T>(Fm.re + Fr.im, Fm.im - Fr.re);
       buf[mr * TL + t] = conj(twq[mr]) * mk<T>(Fr.re + Fm.im, Fr.im - Fm.re);
     } else if (m == 0) {
@@ -231,12 +235,12 @@ __global__ void __launch_bounds__(1024)
     }
   }
   __syncthreads();
-  lds_fft<T, true, true>(buf, Nz, logNz, TL, 1, TL, stw);
+  lds_fft<T, true, true>(buf, Nz, logNz, TL, ltl, stw);
   for (int e = threadIdx.x; e < Nz * TL; e += blockDim.x) {
-    const int row = e / TL, t = e - row * TL;
+    const int row = e >> ltl, t = e & (TL - 1);
     const int l = l0 + t;
     const int pos = (row & 1) ? (Nz - 1 - (row >> 1)) : (row >> 1);
-    if (l < lines) S[row * stride + l] = buf[pos * TL + t];
+    if (l < lines) S[row * stride + l] = buf[(pos << ltl) + t];
   }
 }
 
