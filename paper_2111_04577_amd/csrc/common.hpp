@@ -134,6 +134,22 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by, int& bz) {
   bz = t / (gx * gy);
 }
 
+// Layers per block of a z-marching launch over `cols` column tiles: as many blocks as the
+// device holds at once (one round, no tail of late blocks), each marching ceil(nz / blocks per
+// column) layers.
+template <typename K>
+inline int march_layers(K kernel, int threads, size_t shm, int cols, int nz) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, shm) != hipSuccess || nb < 1) nb = 1;
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      ncu < 1)
+    ncu = 1;
+  int zb = nb * ncu / cols;
+  zb = zb < 1 ? 1 : (zb > nz ? nz : zb);
+  return (nz + zb - 1) / zb;
+}
+
 // One-dimensional form of xcd_tile: the logical block index, so that consecutive logical
 // blocks (which share cache lines) run on the same XCD.
 __device__ __forceinline__ int xcd_block() {

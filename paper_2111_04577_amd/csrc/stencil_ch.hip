@@ -221,6 +221,7 @@ __global__ void __launch_bounds__(kBlock)
   int bx, by, bz;
   xcd_tile(bx, by, bz);
   const int i0 = bx * CX, j0 = by * CY, k0 = bz * KB;
+  const int k1 = min(k0 + KB, cnz);  // the last block of a column may march fewer layers
   const int GX = 2 * CX + 1, GY = ry * CY + 1, GP = GX * GY;
   const int PX = GX + 2, PY = GY + 2, PP = PX * PY;
   const int X0 = 2 * i0, Y0 = ry * j0;
@@ -326,7 +327,7 @@ __global__ void __launch_bounds__(kBlock)
     __syncthreads();
     compute_g(2 * k0 + 2, ps0);
     __syncthreads();
-    if (KB > 1) {
+    if (k1 - k0 > 1) {
       load_p(2 * k0 + 4, pfa);
       load_p(2 * k0 + 5, pfb);
       load_ps(2 * k0 + 3, psa);
@@ -342,7 +343,7 @@ __global__ void __launch_bounds__(kBlock)
   auto mu = [&](T ph) { return hf * ((T)1 + ph) * m1 + hf * ((T)1 - ph) * m2; };
   const int plane = cnx * cny;
   const int ndy = ry + 1;
-  for (int k = k0; k < k0 + KB; ++k) {
+  for (int k = k0; k < k1; ++k) {
     // Separable sums of the tensor-product rule: per z layer and y row, x sums over the
     // centre pair (dx 0,1) and the face pair (dx 1,2); then y pairs, then z pairs. The 1/8
     // weight is applied once at the end (a centre-located y axis without refinement counts
@@ -397,7 +398,7 @@ __global__ void __launch_bounds__(kBlock)
         }
       }
     }
-    if (k + 1 < k0 + KB) {
+    if (k + 1 < k1) {
       // phi on 2k+4, 2k+5 replaces 2k, 2k+1 (no longer read); G on 2k+3, 2k+4 replaces
       // 2k, 2k+1. The loads for the step after next go out before G is evaluated.
       __syncthreads();
@@ -409,7 +410,7 @@ __global__ void __launch_bounds__(kBlock)
         p3[q] = psa[q];
         p4[q] = psb[q];
       }
-      if (k + 2 < k0 + KB) {
+      if (k + 2 < k1) {
         load_p(2 * k + 6, pfa);
         load_p(2 * k + 7, pfb);
         load_ps(2 * k + 5, psa);
@@ -516,25 +517,26 @@ hipError_t launch_restrict_g(const Dims& f, const Dims& c, const StepConsts& k, 
     CX = c.nx < 128 ? c.nx : 128;
     CY = 1;
   }
-  // coarse layers per block: the z march amortises the fine z halo; keep >= ~1024 blocks
-  const int tiles = (c.nx / CX) * (c.ny / CY);
-  int KB = 8;
-  while (KB > 1 && (c.nz / KB) * tiles < 1024) KB >>= 1;
-  if (KB > c.nz) KB = c.nz;
   const int GX = 2 * CX + 1, GY = ry * CY + 1;
   const int PP = (GX + 2) * (GY + 2), nth = 2 * CX * CY;
   // each thread keeps at most R points of a tile in registers
   const int need = (PP + nth - 1) / nth;
   if (need > 6) return hipErrorInvalidConfiguration;
-  const dim3 grid(c.nx / CX, c.ny / CY, c.nz / KB), block(CX, 2 * CY, 1);
   const int GP = GX * GY, Rk = need <= 3 ? 3 : 6;
   const size_t shm = (size_t)(4 * PP + 3 * GP + Rk * nth - GP) * sizeof(T);
-  if (need <= 3)
-    hipLaunchKernelGGL((k_restrict_g<T, 3>), grid, block, shm, st, phinew, phin, phinm1, r, f.nx, f.ny,
-                       f.nz, (T)f.ihx, (T)f.ihy, (T)f.ihz, c.nx, c.ny, c.nz, ry, KB, k);
+  const int cols = (c.nx / CX) * (c.ny / CY);
+  const dim3 block(CX, 2 * CY, 1);
+  // coarse layers per block: the march amortises the fine z halo; one round of blocks
+  auto go = [&](auto kernel) {
+    const int KB = march_layers(kernel, nth, shm, cols, c.nz);
+    const dim3 grid(c.nx / CX, c.ny / CY, (c.nz + KB - 1) / KB);
+    hipLaunchKernelGGL(kernel, grid, block, shm, st, phinew, phin, phinm1, r, f.nx, f.ny, f.nz, (T)f.ihx,
+                       (T)f.ihy, (T)f.ihz, c.nx, c.ny, c.nz, ry, KB, k);
+  };
+  if (Rk == 3)
+    go(k_restrict_g<T, 3>);
   else
-    hipLaunchKernelGGL((k_restrict_g<T, 6>), grid, block, shm, st, phinew, phin, phinm1, r, f.nx, f.ny,
-                       f.nz, (T)f.ihx, (T)f.ihy, (T)f.ihz, c.nx, c.ny, c.nz, ry, KB, k);
+    go(k_restrict_g<T, 6>);
   return hipGetLastError();
 }
 

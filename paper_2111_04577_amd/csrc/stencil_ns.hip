@@ -350,22 +350,6 @@ __global__ void __launch_bounds__(kBlock)
 
 }  // namespace
 
-// Layers per block of a z-marching launch over `cols` column tiles: as many blocks as the
-// device holds at once (one round, no tail of late blocks), each marching ceil(nz / blocks per
-// column) layers.
-template <typename K>
-int march_layers(K kernel, int threads, size_t shm, int cols, int nz) {
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, shm) != hipSuccess || nb < 1) nb = 1;
-  int dev = 0, ncu = 0;
-  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      ncu < 1)
-    ncu = 1;
-  int zb = nb * ncu / cols;
-  zb = zb < 1 ? 1 : (zb > nz ? nz : zb);
-  return (nz + zb - 1) / zb;
-}
-
 template <typename T>
 hipError_t launch_momentum_rhs(const Dims& c, const StepConsts& k, NsIn<T> in, Restricted<T> r,
                                T* ru, T* rv, T* rw, hipStream_t st) {
