@@ -10,9 +10,11 @@ total drop viscosity, the wall gap as length, a velocity U. Then
   G = phi^3 - phi - Cn^2 lap(phi),
 * the capillary force G grad(phi) of eq. NS2, divided by rho_d U^2 / L, carries
   K_sigma = 3 / (2 sqrt(2) Re Ca Cn),
-* the polymer stress is scaled by mu_d U / L, so the Oldroyd-B law (eq. NS4, alpha = 0)
-  reads tau + Wi tau_upper-convected = (1 - beta)(grad u + grad u^T) and enters momentum
-  as (1 / (Re rho)) div[(1 + phi)/2 tau]  (second approach, eq. NS12).
+* the polymer stress is scaled by mu_d U / L, so the Giesekus law (eq. NS4) reads
+  tau + Wi tau_upper-convected + alpha Wi/(1 - beta) tau.tau = (1 - beta)(grad u + grad u^T)
+  (alpha = 0: Oldroyd-B), i.e. tau = (1 - beta)/Wi (c - I) with the conformation law of
+  eq. NS18, and enters momentum as (1 / (Re rho)) div[(1 + phi)/2 tau]  (second approach,
+  eq. NS12).
 
 The Dong splitting constants follow eqs. NS29-NS30 with the stabilisation
 S = s_factor * Cn * sqrt(4 gamma0 Pe / dt), s_factor >= 1; the projection constants follow
@@ -46,6 +48,8 @@ class Params:
     s_factor: float = 1.0
     a_ext: tuple = (0.0, 0.0, 0.0)
     viscoelastic: int = 0
+    constitutive: int = 0          # 0: stress form, 1: log-conformation (lcr.py)
+    giesekus_alpha: float = 0.0    # Giesekus mobility; 0 is Oldroyd-B
 
     @classmethod
     def from_config(cls, cfg) -> "Params":

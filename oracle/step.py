@@ -8,7 +8,8 @@ weights and extrapolation of eqs. NS31-NS32.
 
 State dictionary (FP64 numpy arrays): ``phi``, ``u``, ``v``, ``w``, ``p`` -- each a list
 [level n, level n-1]; ``tau`` -- [level n, level n-1], each a list of the six components
-(xx, yy, zz, xy, xz, yz); ``step`` -- int.
+(xx, yy, zz, xy, xz, yz); ``theta`` -- the six components of the log-conformation at level n
+(advanced only by the log-conformation form, lcr.py); ``step`` -- int.
 """
 from __future__ import annotations
 
@@ -17,6 +18,7 @@ import math
 import numpy as np
 
 from . import discrete as D
+from . import lcr
 from .model import Params, constants
 
 XX, YY, ZZ, XY, XZ, YZ = range(6)
@@ -324,7 +326,7 @@ def navier_stokes(P: Params, st, R, C):
 
 
 # ---------------------------------------------------------------------------------------
-# polymer stress (Sec. 3.2.3, Oldroyd-B in stress form)
+# polymer stress (Sec. 3.2.3, Giesekus / Oldroyd-B in stress form)
 # ---------------------------------------------------------------------------------------
 
 
@@ -357,8 +359,9 @@ _PAIRS = {(0, 0): XX, (1, 1): YY, (2, 2): ZZ, (0, 1): XY, (1, 0): XY, (0, 2): XZ
 
 
 def polymer_rhs(P: Params, tau, u, v, w, L):
-    """RH of eq. NS40-NS41 in stress form (Oldroyd-B):
-    -div(u tau) + (grad u)^T.tau + tau.(grad u) + [(1-beta)(grad u + grad u^T) - tau] / Wi,
+    """RH of eq. NS40-NS41 in stress form (Giesekus; Oldroyd-B at alpha = 0):
+    -div(u tau) + (grad u)^T.tau + tau.(grad u) + [(1-beta)(grad u + grad u^T) - tau] / Wi
+    - alpha/(1-beta) tau.tau,
     index form RH_ab = -div(u tau_ab) + L_ca tau_cb + tau_ac L_cb + ..., L_ab = du_b/dx_a.
     Advection: flux form with face-mean stress and zero wall flux."""
     hx, hy, hz = P.h
@@ -373,6 +376,9 @@ def polymer_rhs(P: Params, tau, u, v, w, L):
         for c in range(3):
             rh = rh + L[c][a] * tau[_PAIRS[(c, b)]] + tau[_PAIRS[(a, c)]] * L[c][b]
         rh = rh + ((1.0 - P.beta) * (L[a][b] + L[b][a]) - t) / P.wi
+        if P.giesekus_alpha != 0.0:
+            tt = sum(tau[_PAIRS[(a, c)]] * tau[_PAIRS[(c, b)]] for c in range(3))
+            rh = rh - P.giesekus_alpha / (1.0 - P.beta) * tt
         out.append(rh)
     return out
 
@@ -398,7 +404,10 @@ def step(P: Params, st, return_parts=False):
     phi_new, G, phis, Psi = cahn_hilliard(P, st, C)
     R = restricted_set(P, phi_new, G, C)
     u, v, w, p, dp = navier_stokes(P, st, R, C)
-    if P.viscoelastic:
+    theta = st.get("theta")
+    if P.viscoelastic and P.constitutive == 1:
+        theta, tau = lcr.polymer(P, st["theta"], u, v, w, velocity_gradient(P, u, v, w))
+    elif P.viscoelastic:
         tau = polymer(P, st["tau"][0], u, v, w)
     else:
         tau = [np.zeros_like(st["p"][0]) for _ in range(6)]
@@ -409,6 +418,8 @@ def step(P: Params, st, return_parts=False):
         "tau": [tau, st["tau"][0]],
         "step": st["step"] + 1,
     }
+    if theta is not None:
+        new["theta"] = theta
     if return_parts:
         return new, {"G": G, "phi_star": phis, "Psi": Psi, "R": R, "dp": dp}
     return new

@@ -47,6 +47,8 @@ class Config:
     s_factor: float = 1.0
     a_ext: tuple = (0.0, 0.0, 0.0)
     viscoelastic: int = 0
+    constitutive: int = 0       # 0: stress form, 1: log-conformation
+    giesekus_alpha: float = 0.0
     steps: int = 10
     radius: float = 0.25
     centre: tuple | None = None  # (x, y) of the drop foot on the bottom wall
@@ -143,7 +145,7 @@ def initial_phi(cfg: Config) -> np.ndarray:
 
 def droplet_state(cfg: Config) -> dict:
     """Full initial state as FP64 numpy arrays: both time levels equal (the first step is a
-    one-level start), velocity, pressure and polymer stress zero."""
+    one-level start), velocity, pressure and polymer stress zero, log-conformation zero."""
     phi = initial_phi(cfg)
     cs = coarse_shape(cfg)
     z = lambda: np.zeros(cs)
@@ -152,6 +154,7 @@ def droplet_state(cfg: Config) -> dict:
         "u": [z(), z()], "v": [z(), z()], "w": [z(), z()],
         "p": [z(), z()],
         "tau": [[z() for _ in range(6)], [z() for _ in range(6)]],
+        "theta": [z() for _ in range(6)],  # log-conformation (c = I)
         "step": 0,
     }
 
