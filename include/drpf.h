@@ -87,8 +87,15 @@ typedef struct drpf_params {
   double dt;                   /* time step (> 0)                                           */
   double s_factor;             /* stabilisation S as a multiple of the bound of eq. NS30, >= 1 */
   double a_ext[3];             /* body acceleration (x, y, z)                               */
-  int viscoelastic;            /* 1: drop phase carries an Oldroyd-B polymer stress         */
+  int viscoelastic;            /* 1: drop phase carries a polymer stress (Oldroyd-B, or
+                                  Giesekus when giesekus_alpha > 0)                         */
   int precision;               /* 64 or 32: element type of every device array              */
+  int constitutive;            /* form of the polymer update: 0 stress form (eq. NS4 with the
+                                  RK2-TVD of eqs. NS42-NS44 on tau), 1 log-conformation
+                                  (eqs. NS22, NS40-NS46 on Theta = log c); 1 needs
+                                  viscoelastic                                               */
+  double giesekus_alpha;       /* Giesekus mobility alpha in [0, 0.5] (eqs. NS4, NS18); 0 is
+                                  Oldroyd-B; > 0 needs viscoelastic and beta < 1            */
 } drpf_params;
 
 /* Device pointers of one solution state. Level n is index 0, level n-1 index 1.
@@ -98,7 +105,11 @@ typedef struct drpf_params {
  * coarse fields [0] points to level n+1 (stored in the former n-1 buffer) and [1] to level
  * n. tau[level][c], c = xx, yy, zz, xy, xz, yz, is read and written only when
  * viscoelastic != 0. step counts completed steps; step == 0 takes the one-level start
- * (gamma0 = 1, extrapolations replaced by level n). */
+ * (gamma0 = 1, extrapolations replaced by level n). theta[c] (same component order, coarse
+ * centres) is the log-conformation Theta = log c at level n, read and overwritten in place with
+ * level n+1 only when constitutive == 1 (it must then be non-null; zero means c = I); the step
+ * then writes tau of level n+1 from it (eq. NS46), and the momentum equation uses tau as in
+ * the stress form. */
 typedef struct drpf_state {
   void* phi[3];
   void* u[2];
@@ -107,6 +118,7 @@ typedef struct drpf_state {
   void* p[2];
   void* tau[2][6];
   long long step;
+  void* theta[6];
 } drpf_state;
 
 typedef struct drpf_grid drpf_grid;
@@ -211,7 +223,8 @@ typedef struct drpf_adj {
 } drpf_adj;
 
 /* Bytes of the second device workspace the adjoint needs (forward intermediates of the
- * recomputed step and the adjoint stage buffers). DRPF_EUNSUPPORTED unless precision 64. */
+ * recomputed step and the adjoint stage buffers). DRPF_EUNSUPPORTED unless precision 64 and
+ * the polymer update is the Oldroyd-B stress form (constitutive 0, giesekus_alpha 0). */
 int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes);
 
 /* Hands the grid that workspace (device memory, 256-byte aligned, at least the size above;

@@ -91,10 +91,11 @@ def conformation(theta_m):
 
 
 def stress(P: Params, theta_comps):
-    """tau_p = (1 - beta)/Wi (c - I) (eq. NS17 in the scaling of model.py)."""
-    c = conformation(to_matrix(theta_comps))
-    c = c - np.eye(3)
-    return [(1.0 - P.beta) / P.wi * x for x in from_matrix(c)]
+    """tau_p = (1 - beta)/Wi (c - I) (eq. NS17 in the scaling of model.py), with
+    c - I = R diag(exp(theta) - 1) R^T (eq. NS46) and exp(theta) - 1 evaluated by expm1."""
+    th, R = eig(to_matrix(theta_comps))
+    cm = (R * np.expm1(th)[..., None, :]) @ np.swapaxes(R, -1, -2)
+    return [(1.0 - P.beta) / P.wi * x for x in from_matrix(cm)]
 
 
 def advection(P: Params, q, u, v, w):

@@ -38,6 +38,7 @@ class Params(ctypes.Structure):
         ("dt", ctypes.c_double), ("s_factor", ctypes.c_double),
         ("a_ext", ctypes.c_double * 3),
         ("viscoelastic", ctypes.c_int), ("precision", ctypes.c_int),
+        ("constitutive", ctypes.c_int), ("giesekus_alpha", ctypes.c_double),
     ]
 
 
@@ -48,6 +49,7 @@ class State(ctypes.Structure):
         ("p", ctypes.c_void_p * 2),
         ("tau", (ctypes.c_void_p * 6) * 2),
         ("step", ctypes.c_longlong),
+        ("theta", ctypes.c_void_p * 6),
     ]
 
 
@@ -136,8 +138,8 @@ class DeviceState:
     """State tensors on the device plus the drpf_state struct pointing at them.
 
     All arrays are views of one flat device buffer (three fine phi buffers, then u, v, w, p
-    with two levels each, then the polymer stress when viscoelastic), so a snapshot is one
-    device copy."""
+    with two levels each, then the polymer stress when viscoelastic, then the log-conformation
+    when the update takes that form), so a snapshot is one device copy."""
 
     def __init__(self, grid: "Grid", host: dict):
         import torch
@@ -147,10 +149,12 @@ class DeviceState:
         nf = int(np.prod(grid.fine_shape))
         nc = int(np.prod(grid.coarse_shape))
         ve = bool(grid.params.viscoelastic)
-        self.flat = torch.empty(3 * nf + (8 + (12 if ve else 0)) * nc, dtype=dt, device=dev)
+        lcr = grid.params.constitutive == 1
+        ncoarse = 8 + (12 if ve else 0) + (6 if lcr else 0)
+        self.flat = torch.empty(3 * nf + ncoarse * nc, dtype=dt, device=dev)
         views = []
         pos = 0
-        for n, shape in [(nf, grid.fine_shape)] * 3 + [(nc, grid.coarse_shape)] * (8 + (12 if ve else 0)):
+        for n, shape in [(nf, grid.fine_shape)] * 3 + [(nc, grid.coarse_shape)] * ncoarse:
             views.append(self.flat[pos:pos + n].view(shape))
             pos += n
         self.tensors = views
@@ -171,6 +175,12 @@ class DeviceState:
                     self.tau[l][m].copy_(t(host["tau"][l][m]))
         else:
             self.tau = None
+        if lcr:
+            self.theta = views[23:29]
+            for m in range(6):
+                self.theta[m].copy_(t(host["theta"][m]))
+        else:
+            self.theta = None
         self.c = State()
         self.c.step = int(host.get("step", 0))
         self._push()
@@ -187,6 +197,9 @@ class DeviceState:
             for lvl in range(2):
                 for m in range(6):
                     c.tau[lvl][m] = self.tau[lvl][m].data_ptr()
+        if self.theta is not None:
+            for m in range(6):
+                c.theta[m] = self.theta[m].data_ptr()
 
     def _pull(self):
         """Re-associate tensors with the pointers the library rotated."""
@@ -208,6 +221,8 @@ class DeviceState:
             offs += [(arr[a] - base) // es for a in range(2)]
         if self.tau is not None:
             offs += [(c.tau[l][m] - base) // es for l in range(2) for m in range(6)]
+        if self.theta is not None:
+            offs += [(c.theta[m] - base) // es for m in range(6)]
         return offs
 
     @property
@@ -234,6 +249,9 @@ class DeviceState:
             for l in range(2):
                 for m in range(6):
                     c.tau[l][m] = base + es * next(offs)
+        if self.theta is not None:
+            for m in range(6):
+                c.theta[m] = base + es * next(offs)
         c.step = int(snap["step"])
         self._pull()
         return self
@@ -268,6 +286,8 @@ class DeviceState:
         else:
             z = np.zeros(self.grid.coarse_shape)
             out["tau"] = [[z.copy() for _ in range(6)] for _ in range(2)]
+        if self.theta is not None:
+            out["theta"] = [h(a) for a in self.theta]
         return out
 
 

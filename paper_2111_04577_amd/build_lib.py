@@ -15,7 +15,7 @@ SRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdrpf.so")
 SOURCES = ["api.hip", "fft.hip", "tridiag.hip", "stencil_ch.hip", "stencil_ns.hip", "reduce.hip",
-           "adjoint.hip"]
+           "adjoint.hip", "lcr.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -96,6 +96,7 @@ StepConsts make_consts(const drpf_params& p, bool first) {
   c.inv_re = 1.0 / p.re;
   c.inv_rho0 = 1.0 / c.rho0;
   c.inv_wi = 1.0 / p.wi;
+  c.giesekus = p.giesekus_alpha;
   return c;
 }
 
@@ -295,6 +296,7 @@ struct StepIO {
   const T* taun[6];
   const T* taunm1[6];
   T* tauo[6];
+  T* theta[6];  // log-conformation, level n in, level n+1 out (constitutive 1)
 };
 
 // One coupled step (Sec. 3.2): Cahn-Hilliard, restriction, Navier-Stokes, polymer stress.
@@ -381,12 +383,25 @@ int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t
       t1[m] = reinterpret_cast<T*>(g->ws + g->o.tau1[m]);
       t1c[m] = t1[m];
     }
-    HIPCHK(launch_polymer_stage<T>(C, K, io.uo, io.vo, io.wo, io.taun, io.taun, t1, 0.0, 1.0, st),
-           "polymer stage 1");
-    mark(g, 13, st);
-    HIPCHK(launch_polymer_stage<T>(C, K, io.uo, io.vo, io.wo, io.taun, t1c, io.tauo, 0.5, 0.5, st),
-           "polymer stage 2");
-    mark(g, 14, st);
+    if (g->p.constitutive == 1) {
+      // log-conformation (eqs. NS42-NS46): Theta^(1) in the stage buffer, Theta^{n+1} in place,
+      // then tau^{n+1} from it
+      const T* thn[6];
+      for (int m = 0; m < 6; ++m) thn[m] = io.theta[m];
+      HIPCHK(launch_lcr_stage<T>(C, K, io.uo, io.vo, io.wo, thn, thn, t1, nullptr, 0.0, 1.0, st),
+             "log-conformation stage 1");
+      mark(g, 13, st);
+      HIPCHK(launch_lcr_stage<T>(C, K, io.uo, io.vo, io.wo, thn, t1c, io.theta, io.tauo, 0.5, 0.5, st),
+             "log-conformation stage 2");
+      mark(g, 14, st);
+    } else {
+      HIPCHK(launch_polymer_stage<T>(C, K, io.uo, io.vo, io.wo, io.taun, io.taun, t1, 0.0, 1.0, st),
+             "polymer stage 1");
+      mark(g, 13, st);
+      HIPCHK(launch_polymer_stage<T>(C, K, io.uo, io.vo, io.wo, io.taun, t1c, io.tauo, 0.5, 0.5, st),
+             "polymer stage 2");
+      mark(g, 14, st);
+    }
   }
   return DRPF_OK;
 }
@@ -413,6 +428,7 @@ StepIO<T> state_io(const drpf_state* s) {
     io.taun[m] = (const T*)s->tau[0][m];
     io.taunm1[m] = (const T*)s->tau[1][m];
     io.tauo[m] = (T*)s->tau[1][m];
+    io.theta[m] = (T*)s->theta[m];
   }
   return io;
 }
@@ -748,6 +764,13 @@ int drpf_validate(const drpf_params* p) {
   if (!(p->rho_ratio > 0 && p->mu_ratio > 0)) return fail(DRPF_EINVAL, "density and viscosity ratios must be > 0");
   if (p->viscoelastic && !(p->wi > 0 && p->beta > 0 && p->beta <= 1))
     return fail(DRPF_EINVAL, "viscoelastic drop needs Wi > 0 and beta in (0, 1]");
+  if (!(p->constitutive == 0 || p->constitutive == 1)) return fail(DRPF_EINVAL, "constitutive must be 0 or 1");
+  if (p->constitutive == 1 && !p->viscoelastic)
+    return fail(DRPF_EINVAL, "the log-conformation form needs viscoelastic");
+  if (!(p->giesekus_alpha >= 0 && p->giesekus_alpha <= 0.5))
+    return fail(DRPF_EINVAL, "giesekus_alpha must lie in [0, 0.5]");
+  if (p->giesekus_alpha > 0 && !(p->viscoelastic && p->beta < 1))
+    return fail(DRPF_EINVAL, "a Giesekus term needs viscoelastic and beta < 1");
   if (!(p->precision == 64 || p->precision == 32)) return fail(DRPF_EINVAL, "precision must be 64 or 32");
   for (int a = 0; a < 3; ++a)
     if (!isfinite(p->a_ext[a])) return fail(DRPF_EINVAL, "a_ext must be finite");
@@ -833,6 +856,9 @@ int drpf_step(drpf_grid* g, drpf_state* s, int nsteps, void* stream) {
     for (int l = 0; l < 2; ++l)
       for (int m = 0; m < 6; ++m)
         if (!s->tau[l][m]) return fail(DRPF_EINVAL, "null polymer stress pointer");
+  if (g->p.constitutive == 1)
+    for (int m = 0; m < 6; ++m)
+      if (!s->theta[m]) return fail(DRPF_EINVAL, "null log-conformation pointer");
   if (s->step < 0) return fail(DRPF_EINVAL, "negative step counter");
   hipStream_t st = (hipStream_t)stream;
   return g->p.precision == 64 ? step_impl<double>(g, s, nsteps, st) : step_impl<float>(g, s, nsteps, st);
@@ -957,6 +983,8 @@ int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes) {
   if (rc) return rc;
   if (!bytes) return fail(DRPF_EINVAL, "null output");
   if (p->precision != 64) return fail(DRPF_EUNSUPPORTED, "the adjoint runs on FP64 grids only");
+  if (p->constitutive != 0 || p->giesekus_alpha != 0)
+    return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
   const int ry = p->ny == 1 ? 1 : 2;
   const Dims F = make_dims(2 * p->nx, ry * p->ny, 2 * p->nz, p->lx, p->ly, p->lz);
   const Dims C = make_dims(p->nx, p->ny, p->nz, p->lx, p->ly, p->lz);
@@ -967,6 +995,8 @@ int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes) {
 int drpf_adjoint_attach(drpf_grid* g, void* d_workspace, size_t bytes) {
   if (!g) return fail(DRPF_EINVAL, "null grid");
   if (g->p.precision != 64) return fail(DRPF_EUNSUPPORTED, "the adjoint runs on FP64 grids only");
+  if (g->p.constitutive != 0 || g->p.giesekus_alpha != 0)
+    return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
   if (!d_workspace) return fail(DRPF_EWORKSPACE, "null adjoint workspace");
   if (((uintptr_t)d_workspace & 255) != 0) return fail(DRPF_EWORKSPACE, "adjoint workspace must be 256-byte aligned");
   const size_t need = adj_layout(g->F, g->C).total;
@@ -980,6 +1010,8 @@ int drpf_adjoint_step(drpf_grid* g, const drpf_state* x, const drpf_state* x_nex
                       double* d_grad3, void* stream) {
   if (!g || !x || !lam || !d_grad3) return fail(DRPF_EINVAL, "null argument");
   if (g->p.precision != 64) return fail(DRPF_EUNSUPPORTED, "the adjoint runs on FP64 grids only");
+  if (g->p.constitutive != 0 || g->p.giesekus_alpha != 0)
+    return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
   if (!g->aws) return fail(DRPF_EINVAL, "no adjoint workspace attached");
   if (!x->phi[0] || !x->phi[1] || !x->u[0] || !x->u[1] || !x->v[0] || !x->v[1] || !x->w[0] || !x->w[1] ||
       !x->p[0] || !x->p[1])

@@ -96,12 +96,13 @@ struct StepConsts {
   double rho1, rho2, mu1, mu2;  // drop / ambient density and solvent viscosity
   double rho0, nu_m;            // projection constants (text after eq. NS39)
   double re, k_sigma, c_j;      // 1/Re scaling, capillary coefficient, J = -c_j grad G
-  double wi, beta;              // Oldroyd-B
+  double wi, beta;              // polymer: Weissenberg number, solvent-viscosity ratio
   double ax, ay, az;            // body acceleration
   // reciprocals and products formed once on the host
   double inv_dt, inv_cn2, s_cn2, pe_cn2;  // 1/dt, 1/Cn^2, S/Cn^2, Pe/Cn^2
   double g_bot, g_top;                    // cos(theta) / (sqrt(2) Cn) at each wall
   double inv_re, inv_rho0, inv_wi;
+  double giesekus;              // Giesekus mobility alpha (0: Oldroyd-B)
 };
 
 // Block shape of the 3D stencil launches: bx threads along x, by along y, one z layer per

@@ -82,6 +82,13 @@ struct NsIn {
 template <typename T>
 hipError_t launch_momentum_rhs(const Dims& c, const StepConsts& k, NsIn<T> in, Restricted<T> r,
                                T* ru, T* rv, T* rw, hipStream_t st);
+// Log-conformation form (lcr.hip): one RK2-TVD stage on Theta = log c,
+// out = c0 * theta_n + c1 * (theta_in + dt RH(theta_in)), u fixed; with tau_out non-null also
+// tau_p of the new Theta. theta_n and theta_out may alias.
+template <typename T>
+hipError_t launch_lcr_stage(const Dims& c, const StepConsts& k, const T* u, const T* v, const T* w,
+                            const T* const theta_n[6], const T* const theta_in[6], T* const theta_out[6],
+                            T* const tau_out[6], double c0, double c1, hipStream_t st);
 // One RK2-TVD stage: out = c0 * tau_n + c1 * (tau_in + dt RH(tau_in)), u fixed.
 template <typename T>
 hipError_t launch_polymer_stage(const Dims& c, const StepConsts& k, const T* u, const T* v,

@@ -7,10 +7,13 @@
 //                     (1/rho0) grad p^n + (1/rho - 1/rho0) grad p*, the explicit nu_m L u*,
 //                     the polymer divergence of the second approach (eq. NS12, drop = polymer
 //                     phase), the variable-viscosity stress divergence, the capillary force
-//                     G grad(phi) and the body force. One launch covers the three components
-//                     (uniform per block), interleaved layer by layer.
+//                     G grad(phi) and the body force. 3D grids march up columns (every thread
+//                     forms the three components of its cell); 2D grids take one thread per
+//                     face. The Oldroyd-B/Giesekus polymer divergence comes from its own
+//                     z-marching pass (polymer_div).
 //   polymer_stage  -- one stage of the second-order TVD Runge-Kutta update of the polymer
-//                     stress (eqs. NS42, NS44) for the Oldroyd-B law in stress form.
+//                     stress (eqs. NS42, NS44) in stress form: the Giesekus law, with
+//                     -alpha/(1 - beta) tau.tau (alpha = 0: Oldroyd-B).
 //
 // Staggering: u[k][j][i] at ((i+1) hx, (j+.5) hy, (k+.5) hz), v at (i+.5, j+1, k+.5),
 // w at (i+.5, j+.5, k+1) with w[nz-1] the top wall; centres at (i+.5, j+.5, k+.5).
@@ -310,7 +313,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_polymer_stage(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
                     TauSet<T> tn, TauSet<T> tin, TauOut<T> tout, int nx, int ny, int nz, T ihx,
-                    T ihy, T ihz, T dt, T inv_wi, T one_m_beta, T c0, T c1) {
+                    T ihy, T ihz, T dt, T inv_wi, T one_m_beta, T gk, T c0, T c1) {
   int bx, by, bz;
   xcd_tile(bx, by, bz);
   const int i = bx * blockDim.x + threadIdx.x;
@@ -344,6 +347,13 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) rh += L[cc][a] * tau[tidx(cc, b)] + tau[tidx(a, cc)] * L[cc][b];
     rh += (one_m_beta * (L[a][b] + L[b][a]) - t0) * inv_wi;
+    // Giesekus: - alpha/(1 - beta) (tau.tau)_ab
+    if (gk != (T)0) {
+      T tt = 0;
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) tt += tau[tidx(a, cc)] * tau[tidx(cc, b)];
+      rh -= gk * tt;
+    }
     tout.p[m][id] = c0 * tn.p[m][id] + c1 * (t0 + dt * rh);
   }
 }
@@ -406,8 +416,8 @@ hipError_t launch_polymer_stage(const Dims& c, const StepConsts& k, const T* u, 
   }
   const Launch3 L = launch3(c.nx, c.ny, c.nz);
   hipLaunchKernelGGL(k_polymer_stage<T>, L.grid, L.block, 0, st, u, v, w, tn, ti, to, c.nx, c.ny, c.nz,
-                     (T)c.ihx, (T)c.ihy, (T)c.ihz, (T)k.dt, (T)k.inv_wi, (T)(1.0 - k.beta), (T)c0,
-                     (T)c1);
+                     (T)c.ihx, (T)c.ihy, (T)c.ihz, (T)k.dt, (T)k.inv_wi, (T)(1.0 - k.beta),
+                     (T)(k.giesekus == 0.0 ? 0.0 : k.giesekus / (1.0 - k.beta)), (T)c0, (T)c1);
   return hipGetLastError();
 }
 

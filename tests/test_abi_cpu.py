@@ -67,6 +67,29 @@ def test_validation_viscoelastic_beta():
     assert B.lib().drpf_validate(ctypes.byref(p)) == B.DRPF_OK
 
 
+def test_validation_polymer_forms():
+    B = _lib()
+    L = B.lib()
+    ok = dict(viscoelastic=1, beta=0.5, wi=0.5)
+    for kw, rc in [(dict(constitutive=1), B.DRPF_EINVAL),               # needs viscoelastic
+                   (dict(ok, constitutive=2), B.DRPF_EINVAL),
+                   (dict(ok, giesekus_alpha=0.6), B.DRPF_EINVAL),
+                   (dict(ok, giesekus_alpha=-0.1), B.DRPF_EINVAL),
+                   (dict(viscoelastic=1, beta=1.0, wi=0.5, giesekus_alpha=0.2), B.DRPF_EINVAL),
+                   (dict(giesekus_alpha=0.2), B.DRPF_EINVAL),
+                   (dict(ok, constitutive=1, giesekus_alpha=0.5), B.DRPF_OK),
+                   (dict(ok, giesekus_alpha=0.3), B.DRPF_OK)]:
+        p = _params(**kw)
+        assert L.drpf_validate(ctypes.byref(p)) == rc, kw
+    # the adjoint covers the Oldroyd-B stress form only
+    nb = ctypes.c_size_t()
+    for kw in (dict(ok, constitutive=1), dict(ok, giesekus_alpha=0.2)):
+        p = _params(**kw)
+        assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_EUNSUPPORTED
+    p = _params(**ok)
+    assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_OK
+
+
 def test_sizes_and_workspace_errors():
     B = _lib()
     L = B.lib()
