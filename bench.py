@@ -48,11 +48,11 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--others", default="C3,C5",
+    ap.add_argument("--others", default="C3,C5,C3L",
                     help="further workloads timed in both forms beside the headline one ('' for none)")
     ap.add_argument("--other-steps", type=int, default=100)
     ap.add_argument("--no-error", action="store_true",
-                    help="skip the FP32-vs-FP64 per-field error runs (C2 500 steps, C3 1000 steps)")
+                    help="skip the FP32-vs-FP64 per-field error runs (C2 500 steps, C3 and C3L 1000 steps)")
     ap.add_argument("--only-adjoint", action="store_true",
                     help="run only the gradient case and print its JSON object")
     ap.add_argument("--adjoint-config", default="C4")
@@ -99,8 +99,9 @@ def alg_bytes(kernel, cfg, es):
         "zpass_ns": 7 * sc,
         "fft_y_inv_coarse": 8 * sc if C["ny"] > 1 else 0,
         "fft_x_inv_coarse": 4 * sc + 5 * nc,
+        # log-conformation: stage 2 also writes tau from the new Theta
         "polymer_stage1": 15 * nc if ve else 0,
-        "polymer_stage2": 21 * nc if ve else 0,
+        "polymer_stage2": (27 if cfg.constitutive == 1 else 21) * nc if ve else 0,
     }
     return words[kernel] * es
 
@@ -483,17 +484,22 @@ def main():
                        "kernels": res[64]["kernels"]}
         out["fp32_vs_fp64_speedup"] = round(res[32]["value"] / res[64]["value"], 3)
         if not a.no_error:
-            print("[bench] FP32 vs FP64 error: C2 500 steps, C3 1000 steps", file=sys.stderr, flush=True)
+            print("[bench] FP32 vs FP64 error: C2 500 steps, C3 and C3L 1000 steps", file=sys.stderr, flush=True)
             out["fp32_error_vs_fp64"] = {"C2": precision_error(drpf, W, "C2", 500),
-                                         "C3": precision_error(drpf, W, "C3", 1000)}
+                                         "C3": precision_error(drpf, W, "C3", 1000),
+                                         "C3L": precision_error(drpf, W, "C3L", 1000)}
     others = [x for x in a.others.split(",") if x and x != cfg.name]
     if others:
         out["other_workloads"] = {}
     for name in others:
         ocfg = W.config(name)
         OF, OC = grid_sizes(ocfg)
+        law = "Newtonian"
+        if ocfg.viscoelastic:
+            law = f"Giesekus alpha {ocfg.giesekus_alpha:g}" if ocfg.giesekus_alpha else "Oldroyd-B"
+            law += ", log-conformation" if ocfg.constitutive == 1 else ", stress form"
         ent = {"workload": f"{name}: coarse {ocfg.nx}x{ocfg.ny}x{ocfg.nz}, fine {OF['nx']}x{OF['ny']}x{OF['nz']} "
-                           f"({OF['cells']} cells), {'Oldroyd-B' if ocfg.viscoelastic else 'Newtonian'}, "
+                           f"({OF['cells']} cells), {law}, "
                            f"rho ratio {ocfg.rho_ratio:g}, mu ratio {ocfg.mu_ratio:g}",
                "steps": a.other_steps}
         for prec in (32, 64):

@@ -9,8 +9,8 @@
 // (e^d m_ij + m_ji) d / expm1(d), d = theta_j - theta_i, equal to the paper's expression for
 // distinct eigenvalues and to its limit m_ij + m_ji for equal ones (at c = I the paper's rule
 // Omega = 0, B = sym K); the relaxation sign is the one that relaxes c to I. The second stage
-// also diagonalises Theta^{n+1} and writes tau_p = (1 - beta)/Wi (c - I) (eq. NS46), formed as
-// R diag(expm1(theta)) R^T.
+// also diagonalises Theta^{n+1} (a Jacobi started in the eigenframe of Theta^(1), O(dt) away)
+// and writes tau_p = (1 - beta)/Wi (c - I) (eq. NS46), formed as V diag(expm1(theta)) V^T.
 //
 // One thread per coarse cell. The per-cell eigensolve (cyclic Jacobi) and the source are FP64
 // in both precision forms; the advection is the stress form's central flux form with Neumann
@@ -24,8 +24,8 @@ namespace {
 constexpr int kBlock = 256;
 
 // Cyclic Jacobi for a symmetric 3x3 matrix: on exit a is diagonal (the eigenvalues) and the
-// columns of v are the eigenvectors. Stops when the off-diagonal mass is below 1e-36 of the
-// diagonal mass (relative 1e-18 per entry) or after 16 sweeps.
+// columns of v are the eigenvectors. Stops when the off-diagonal mass is below 1e-32 of the
+// diagonal mass (relative 1e-16 per entry, FP64 round-off) or after 16 sweeps.
 __device__ __forceinline__ void jacobi3(double a[3][3], double v[3][3]) {
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -34,7 +34,7 @@ __device__ __forceinline__ void jacobi3(double a[3][3], double v[3][3]) {
   for (int sweep = 0; sweep < 16; ++sweep) {
     const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
     const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
-    if (off == 0.0 || off <= 1e-36 * dia) break;
+    if (off == 0.0 || off <= 1e-32 * dia) break;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       const int p = r == 2 ? 1 : 0, q = r == 0 ? 1 : 2;
@@ -190,16 +190,29 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
   for (int m = 0; m < 6; ++m) thout.p[m][id] = (T)out[m];
   if (LAST) {
-    // tau_p = (1 - beta)/Wi (c - I), c - I = R diag(expm1(theta)) R^T, from the stored Theta
-    double o6[6];
+    // tau_p = (1 - beta)/Wi (c - I), c - I = V diag(expm1(theta)) V^T for the eigenpairs of the
+    // stored Theta^{n+1}. It differs from Theta_in by O(dt), so its Jacobi starts in the
+    // eigenframe R of Theta_in: B = R^T Theta^{n+1} R is nearly diagonal, V = R Q.
+    double o6[6], Tn[3][3], TR[3][3], B[3][3], Q[3][3], Vq[3][3];
 #pragma unroll
     for (int m = 0; m < 6; ++m) o6[m] = (double)(T)out[m];
-    double B[3][3], Q[3][3];
-    unpack6(o6, B);
+    unpack6(o6, Tn);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) TR[a][b] = Tn[a][0] * R[0][b] + Tn[a][1] * R[1][b] + Tn[a][2] * R[2][b];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = a; b < 3; ++b) B[a][b] = B[b][a] = R[0][a] * TR[0][b] + R[1][a] * TR[1][b] + R[2][a] * TR[2][b];
     jacobi3(B, Q);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) Vq[a][b] = R[a][0] * Q[0][b] + R[a][1] * Q[1][b] + R[a][2] * Q[2][b];
     const double e[3] = {expm1(B[0][0]), expm1(B[1][1]), expm1(B[2][2])};
     double cm[6];
-    rdr6(Q, e, cm);
+    rdr6(Vq, e, cm);
 #pragma unroll
     for (int m = 0; m < 6; ++m) tauout.p[m][id] = (T)(tau_scale * cm[m]);
   }

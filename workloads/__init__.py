@@ -88,6 +88,10 @@ CONFIGS: dict[str, Config] = {
     "C5": _c(name="C5", nx=256, ny=256, nz=128, lx=2.0, ly=2.0, lz=1.0, re=1.0, ca=1.0,
              cn=0.01, pe=300.0, wi=2.0, beta=0.3, theta_bottom_deg=45.0, rho_ratio=100.0,
              mu_ratio=10.0, dt=5e-5, steps=200, radius=0.25, viscoelastic=1),
+    # C3 with the log-conformation update of the paper and a Giesekus term.
+    "C3L": _c(name="C3L", nx=128, ny=128, nz=64, lx=2.0, ly=2.0, lz=1.0, re=1.0, ca=1.0,
+              cn=0.01, pe=300.0, wi=1.0, beta=0.5, theta_bottom_deg=120.0, dt=5e-5,
+              steps=1000, radius=0.25, viscoelastic=1, constitutive=1, giesekus_alpha=0.2),
 }
 
 
