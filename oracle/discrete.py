@@ -144,8 +144,10 @@ def helmholtz(rhs, coeff, shift, kind, h):
 # ---------------------------------------------------------------------------------------
 
 
-def prolong(u, v, w, ry):
-    """Coarse face velocities -> fine face velocities (eq. dual1, Rudman's interpolation).
+def prolong(u, v, w, ry, r=2):
+    """Coarse face velocities -> fine face velocities (eq. dual1, Rudman's interpolation);
+    with refinement r = 1 (single resolution) the phase field lives on the flow grid and the
+    face velocities are used as they are.
 
     Along the component's own axis, a fine face that coincides with a coarse face takes
     its value and the fine face through a coarse cell centre takes the mean of the two
@@ -153,6 +155,8 @@ def prolong(u, v, w, ry):
     The bottom-wall w is 0. The result keeps the discrete divergence of every fine cell
     equal to that of its coarse parent cell.
     """
+    if r == 1:
+        return u.copy(), v.copy(), w.copy()
     nz, ny, nx = u.shape
 
     def rep(a, axes):
@@ -182,11 +186,12 @@ def prolong(u, v, w, ry):
 
 
 def _restrict_axis(f, axis, loc, r, wall):
-    """1D rule of eq. dual2 along one axis. 'c': coarse centre i averages fine (r i .. r i +
-    r - 1); 'f': coarse face i (at (i+1) h) averages the two fine cells on either side of
-    it. Periodic axes wrap; on the wall axis the faces run from the bottom wall (index -1)
-    to the top wall (nz - 1), and a fine neighbour beyond a wall is replaced by the
-    wall-adjacent fine cell (Neumann ghost), giving nz + 1 face layers."""
+    """1D rule of eq. dual2 along one axis (refinement r = 2, or r = 1 when the axis is not
+    refined). 'c': coarse centre i averages fine (r i .. r i + r - 1); 'f': coarse face i (at
+    (i+1) h) averages the two fine cells on either side of it. Periodic axes wrap; on the
+    wall axis the faces run from the bottom wall (index -1) to the top wall (nz - 1), and a
+    fine neighbour beyond a wall is replaced by the wall-adjacent fine cell (Neumann ghost),
+    giving nz + 1 face layers."""
     n = f.shape[axis]
     take = lambda idx: np.take(f, idx, axis=axis)
     if loc == "c":
@@ -194,9 +199,9 @@ def _restrict_axis(f, axis, loc, r, wall):
             return f.copy()
         return 0.5 * (take(np.arange(0, n, 2)) + take(np.arange(1, n, 2)))
     if wall:
-        kf = np.arange(-1, n // 2)
-        a = np.clip(2 * kf + 1, 0, n - 1)
-        b = np.clip(2 * kf + 2, 0, n - 1)
+        kf = np.arange(-1, n // r)
+        a = np.clip(r * kf + r - 1, 0, n - 1)
+        b = np.clip(r * kf + r, 0, n - 1)
         return 0.5 * (take(a) + take(b))
     if r == 1:
         return 0.5 * (f + np.roll(f, -1, axis=axis))
@@ -206,14 +211,16 @@ def _restrict_axis(f, axis, loc, r, wall):
     return 0.5 * (take(a) + take(b))
 
 
-def restrict(f, loc, ry):
+def restrict(f, loc, ry, r=2):
     """Fine cell-centred field -> coarse location ``loc`` = (z, y, x) letters in {'c','f'}
-    (eq. dual2, extended to 3D as a tensor product of the 1D rules). A z face location
-    returns nz + 1 layers (bottom wall .. top wall)."""
+    (eq. dual2, extended to 3D as a tensor product of the 1D rules; refinement r in x and z,
+    ry in y). A z face location returns nz + 1 layers (bottom wall .. top wall). With r = ry
+    = 1 (single resolution) a centre is the cell itself, a face the mean of its two cells and
+    an edge the mean of its four."""
     lz, ly, lx = loc
-    g = _restrict_axis(f, 2, lx, 2, False)
+    g = _restrict_axis(f, 2, lx, r, False)
     g = _restrict_axis(g, 1, ly, ry, False)
-    g = _restrict_axis(g, 0, lz, 2, True)
+    g = _restrict_axis(g, 0, lz, r, True)
     return g
 
 

@@ -50,6 +50,7 @@ class Params:
     viscoelastic: int = 0
     constitutive: int = 0          # 0: stress form, 1: log-conformation (lcr.py)
     giesekus_alpha: float = 0.0    # Giesekus mobility; 0 is Oldroyd-B
+    refine: int = 2                # phase-field grid refinement: 2 dual resolution, 1 single
 
     @classmethod
     def from_config(cls, cfg) -> "Params":
@@ -60,7 +61,7 @@ class Params:
     @property
     def ry(self) -> int:
         """Refinement factor in y (1 for a 2D case with a single y cell)."""
-        return 1 if self.ny == 1 else 2
+        return 1 if self.ny == 1 else self.refine
 
     @property
     def h(self):
@@ -68,11 +69,13 @@ class Params:
 
     @property
     def hf(self):
-        return (self.lx / (2 * self.nx), self.ly / (self.ry * self.ny), self.lz / (2 * self.nz))
+        r = self.refine
+        return (self.lx / (r * self.nx), self.ly / (self.ry * self.ny), self.lz / (r * self.nz))
 
     @property
     def fine_shape(self):
-        return (2 * self.nz, self.ry * self.ny, 2 * self.nx)
+        r = self.refine
+        return (r * self.nz, self.ry * self.ny, r * self.nx)
 
     @property
     def coarse_shape(self):

@@ -71,7 +71,7 @@ def cahn_hilliard(P: Params, st, C):
     us = _levels(st["u"], first)[0]
     vs = _levels(st["v"], first)[0]
     ws = _levels(st["w"], first)[0]
-    uf, vf, wf = D.prolong(us, vs, ws, P.ry)                        # eq. dual1
+    uf, vf, wf = D.prolong(us, vs, ws, P.ry, P.refine)              # eq. dual1
     A = advection_fine(phis, uf, vf, wf, hf)
     fstar = (phis ** 3 - phis) / cn2                                  # eq. NS6, eta = Cn
     Q = (P.pe / cn2) * (phih / P.dt - A) + D.lap_neumann(fstar - (C.S / cn2) * phis, hf)  # NS28
@@ -93,7 +93,7 @@ def restricted_set(P: Params, phi, G, C):
     centres, G and 1/rho at the three face sets, solvent viscosity at centres and at the
     three edge sets. z-face and z-edge arrays carry nz + 1 layers (wall .. wall)."""
     ry = P.ry
-    R = lambda f, loc: D.restrict(f, loc, ry)
+    R = lambda f, loc: D.restrict(f, loc, ry, P.refine)
     out = {}
     out["phi_c"] = R(phi, "ccc")
     out["G_c"] = R(G, "ccc")

@@ -25,7 +25,7 @@ __all__ = ["Config", "CONFIGS", "config", "initial_phi", "splitmix64_uniform", "
 @dataclasses.dataclass
 class Config:
     """One problem set-up. Sizes are coarse-grid cell counts; the phase-field grid is
-    twice as fine in x and z, and in y when ny > 1."""
+    ``refine`` times as fine in x and z, and in y when ny > 1 (refine 1: one grid)."""
     name: str
     nx: int
     ny: int
@@ -49,6 +49,7 @@ class Config:
     viscoelastic: int = 0
     constitutive: int = 0       # 0: stress form, 1: log-conformation
     giesekus_alpha: float = 0.0
+    refine: int = 2             # phase-field grid: 2 dual resolution, 1 single resolution
     steps: int = 10
     radius: float = 0.25
     centre: tuple | None = None  # (x, y) of the drop foot on the bottom wall
@@ -104,7 +105,8 @@ def coarse_shape(cfg: Config) -> tuple[int, int, int]:
 
 
 def fine_shape(cfg: Config) -> tuple[int, int, int]:
-    return (2 * cfg.nz, 1 if cfg.ny == 1 else 2 * cfg.ny, 2 * cfg.nx)
+    r = cfg.refine
+    return (r * cfg.nz, 1 if cfg.ny == 1 else r * cfg.ny, r * cfg.nx)
 
 
 _GOLDEN = 0x9E3779B97F4A7C15
