@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--others", default="C3,C5,C3L",
+    ap.add_argument("--others", default="C3,C5,C3L,C2S,C3S",
                     help="further workloads timed in both forms beside the headline one ('' for none)")
     ap.add_argument("--other-steps", type=int, default=100)
     ap.add_argument("--no-error", action="store_true",
@@ -519,6 +519,25 @@ def main():
             torch.cuda.empty_cache()
         ent["fp32_vs_fp64_speedup"] = round(ent["fp32"]["value"] / ent["fp64"]["value"], 3)
         out["other_workloads"][name] = ent
+    # dual- vs single-resolution step time at the same phase-field grid (256x256x128):
+    # C2 / C2S (Newtonian) and C3 / C3S (Oldroyd-B)
+    ow = out.get("other_workloads", {})
+    pairs = {"newtonian": (res, "C2S"), "viscoelastic": (ow.get("C3"), "C3S")}
+    dvs = {}
+    for kind, (dual, sname) in pairs.items():
+        if dual is None or sname not in ow:
+            continue
+        dvs[kind] = {}
+        for prec in (32, 64):
+            d = dual.get(prec) if kind == "newtonian" else dual.get(f"fp{prec}")
+            if d is None:
+                continue
+            t_dual = d["ms_per_step"]
+            t_single = ow[sname][f"fp{prec}"]["ms_per_step"]
+            dvs[kind][f"fp{prec}"] = {"dual_ms": round(t_dual, 4), "single_ms": round(t_single, 4),
+                                      "speedup": round(t_single / t_dual, 3)}
+    if dvs:
+        out["dual_vs_single_resolution"] = dvs
     if not a.no_adjoint:
         print(f"[bench] gradient case {a.adjoint_config}", file=sys.stderr, flush=True)
         out["adjoint"] = time_adjoint(drpf, W, a.adjoint_config, a.adjoint_steps, a.adjoint_every)

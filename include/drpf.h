@@ -96,6 +96,11 @@ typedef struct drpf_params {
                                   viscoelastic                                               */
   double giesekus_alpha;       /* Giesekus mobility alpha in [0, 0.5] (eqs. NS4, NS18); 0 is
                                   Oldroyd-B; > 0 needs viscoelastic and beta < 1            */
+  int refine;                  /* phase-field grid: 2 (or 0) the dual resolution of Sec. 3.1,
+                                  twice the flow grid in x, z (and y in 3D); 1 a single
+                                  resolution (the phase field on the flow grid, faces and
+                                  edges by two- and four-cell means). The transfer and
+                                  adjoint entry points need 2.                               */
 } drpf_params;
 
 /* Device pointers of one solution state. Level n is index 0, level n-1 index 1.

@@ -39,6 +39,7 @@ class Params(ctypes.Structure):
         ("a_ext", ctypes.c_double * 3),
         ("viscoelastic", ctypes.c_int), ("precision", ctypes.c_int),
         ("constitutive", ctypes.c_int), ("giesekus_alpha", ctypes.c_double),
+        ("refine", ctypes.c_int),
     ]
 
 
@@ -374,8 +375,9 @@ class Grid:
                                 ctypes.c_size_t(int(nb.value)), _stream_ptr(stream),
                                 ctypes.byref(self.handle)))
         p = self.params
-        ry = 1 if p.ny == 1 else 2
-        self.fine_shape = (2 * p.nz, ry * p.ny, 2 * p.nx)
+        r = 1 if p.refine == 1 else 2
+        ry = 1 if p.ny == 1 else r
+        self.fine_shape = (r * p.nz, ry * p.ny, r * p.nx)
         self.coarse_shape = (p.nz, p.ny, p.nx)
 
     def __del__(self):

@@ -53,6 +53,14 @@ Dims make_dims(int nx, int ny, int nz, double lx, double ly, double lz) {
   return d;
 }
 
+// Phase-field grid: refine times the flow grid in x and z, and in y for 3D grids (refine 0 is
+// taken as 2, dual resolution; 1 is a single resolution).
+Dims fine_dims(const drpf_params& p) {
+  const int r = p.refine == 1 ? 1 : 2;
+  const int ry = p.ny == 1 ? 1 : r;
+  return make_dims(r * p.nx, ry * p.ny, r * p.nz, p.lx, p.ly, p.lz);
+}
+
 // Scheme constants (own derivation of the paper's formulas; see the header of this file).
 StepConsts make_consts(const drpf_params& p, bool first) {
   StepConsts c;
@@ -335,7 +343,10 @@ int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t
   HIPCHK(launch_fft_x_inv<T>(F, tf, Sf, of, st), "ifft_x fine");
   mark(g, 5, st);
   // ---- restriction, chemical potential, properties
-  HIPCHK(launch_restrict_g<T>(F, C, K, io.phinew, io.phin, io.phinm1, R, st), "restrict_g");
+  if (g->p.refine == 1)
+    HIPCHK(launch_props_single<T>(C, K, io.phinew, io.phin, io.phinm1, R, st), "props_single");
+  else
+    HIPCHK(launch_restrict_g<T>(F, C, K, io.phinew, io.phin, io.phinm1, R, st), "restrict_g");
   mark(g, 6, st);
   // ---- Navier-Stokes on the coarse grid
   NsIn<T> ni;
@@ -744,6 +755,7 @@ int drpf_params_default(drpf_params* p) {
   p->s_factor = 1.0;
   p->viscoelastic = 0;
   p->precision = 64;
+  p->refine = 2;
   return DRPF_OK;
 }
 
@@ -765,6 +777,7 @@ int drpf_validate(const drpf_params* p) {
   if (p->viscoelastic && !(p->wi > 0 && p->beta > 0 && p->beta <= 1))
     return fail(DRPF_EINVAL, "viscoelastic drop needs Wi > 0 and beta in (0, 1]");
   if (!(p->constitutive == 0 || p->constitutive == 1)) return fail(DRPF_EINVAL, "constitutive must be 0 or 1");
+  if (!(p->refine == 0 || p->refine == 1 || p->refine == 2)) return fail(DRPF_EINVAL, "refine must be 1 or 2");
   if (p->constitutive == 1 && !p->viscoelastic)
     return fail(DRPF_EINVAL, "the log-conformation form needs viscoelastic");
   if (!(p->giesekus_alpha >= 0 && p->giesekus_alpha <= 0.5))
@@ -781,8 +794,7 @@ int drpf_field_elems(const drpf_params* p, size_t* fine, size_t* coarse) {
   const int rc = drpf_validate(p);
   if (rc) return rc;
   if (!fine || !coarse) return fail(DRPF_EINVAL, "null output");
-  const size_t ry = p->ny == 1 ? 1 : 2;
-  *fine = (size_t)(2 * p->nx) * (ry * p->ny) * (2 * p->nz);
+  *fine = fine_dims(*p).cells();
   *coarse = (size_t)p->nx * p->ny * p->nz;
   return DRPF_OK;
 }
@@ -791,8 +803,7 @@ int drpf_workspace_bytes(const drpf_params* p, size_t* bytes) {
   const int rc = drpf_validate(p);
   if (rc) return rc;
   if (!bytes) return fail(DRPF_EINVAL, "null output");
-  const int ry = p->ny == 1 ? 1 : 2;
-  const Dims F = make_dims(2 * p->nx, ry * p->ny, 2 * p->nz, p->lx, p->ly, p->lz);
+  const Dims F = fine_dims(*p);
   const Dims C = make_dims(p->nx, p->ny, p->nz, p->lx, p->ly, p->lz);
   *bytes = layout(*p, F, C).total;
   return DRPF_OK;
@@ -811,8 +822,7 @@ int drpf_init_grid(const drpf_params* p, void* d_workspace, size_t bytes, void* 
     return fail(DRPF_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
   drpf_grid* g = new drpf_grid;
   g->p = *p;
-  const int ry = p->ny == 1 ? 1 : 2;
-  g->F = make_dims(2 * p->nx, ry * p->ny, 2 * p->nz, p->lx, p->ly, p->lz);
+  g->F = fine_dims(*p);
   g->C = make_dims(p->nx, p->ny, p->nz, p->lx, p->ly, p->lz);
   g->k1 = make_consts(*p, true);
   g->k2 = make_consts(*p, false);
@@ -867,6 +877,7 @@ int drpf_step(drpf_grid* g, drpf_state* s, int nsteps, void* stream) {
 int drpf_prolong(drpf_grid* g, const void* u, const void* v, const void* w, void* uf, void* vf,
                  void* wf, void* stream) {
   if (!g || !u || !v || !w || !uf || !vf || !wf) return fail(DRPF_EINVAL, "null argument");
+  if (g->p.refine == 1) return fail(DRPF_EUNSUPPORTED, "no dual grid: single resolution");
   hipStream_t st = (hipStream_t)stream;
   if (g->p.precision == 64)
     HIPCHK(launch_prolong<double>(g->F, g->C, (const double*)u, (const double*)v, (const double*)w,
@@ -881,6 +892,7 @@ int drpf_prolong(drpf_grid* g, const void* u, const void* v, const void* w, void
 
 int drpf_restrict(drpf_grid* g, const void* fine, void* coarse, int location, void* stream) {
   if (!g || !fine || !coarse) return fail(DRPF_EINVAL, "null argument");
+  if (g->p.refine == 1) return fail(DRPF_EUNSUPPORTED, "no dual grid: single resolution");
   if (location < DRPF_CENTER || location > DRPF_EDGE_YZ) return fail(DRPF_EINVAL, "bad location");
   hipStream_t st = (hipStream_t)stream;
   if (g->p.precision == 64)
@@ -985,8 +997,8 @@ int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes) {
   if (p->precision != 64) return fail(DRPF_EUNSUPPORTED, "the adjoint runs on FP64 grids only");
   if (p->constitutive != 0 || p->giesekus_alpha != 0)
     return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
-  const int ry = p->ny == 1 ? 1 : 2;
-  const Dims F = make_dims(2 * p->nx, ry * p->ny, 2 * p->nz, p->lx, p->ly, p->lz);
+  if (p->refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
+  const Dims F = fine_dims(*p);
   const Dims C = make_dims(p->nx, p->ny, p->nz, p->lx, p->ly, p->lz);
   *bytes = adj_layout(F, C).total;
   return DRPF_OK;
@@ -997,6 +1009,7 @@ int drpf_adjoint_attach(drpf_grid* g, void* d_workspace, size_t bytes) {
   if (g->p.precision != 64) return fail(DRPF_EUNSUPPORTED, "the adjoint runs on FP64 grids only");
   if (g->p.constitutive != 0 || g->p.giesekus_alpha != 0)
     return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
+  if (g->p.refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
   if (!d_workspace) return fail(DRPF_EWORKSPACE, "null adjoint workspace");
   if (((uintptr_t)d_workspace & 255) != 0) return fail(DRPF_EWORKSPACE, "adjoint workspace must be 256-byte aligned");
   const size_t need = adj_layout(g->F, g->C).total;
@@ -1012,6 +1025,7 @@ int drpf_adjoint_step(drpf_grid* g, const drpf_state* x, const drpf_state* x_nex
   if (g->p.precision != 64) return fail(DRPF_EUNSUPPORTED, "the adjoint runs on FP64 grids only");
   if (g->p.constitutive != 0 || g->p.giesekus_alpha != 0)
     return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
+  if (g->p.refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
   if (!g->aws) return fail(DRPF_EINVAL, "no adjoint workspace attached");
   if (!x->phi[0] || !x->phi[1] || !x->u[0] || !x->u[1] || !x->v[0] || !x->v[1] || !x->w[0] || !x->w[1] ||
       !x->p[0] || !x->p[1])

@@ -21,6 +21,7 @@ template <typename T>
 struct Prolonged {
   const T *un, *unm1, *vn, *vnm1, *wn, *wnm1;
   int cnx, cny, cnz, ry, first;
+  int single;  // 1: single resolution (the phase field on the flow grid; uf etc. not used)
   __device__ __forceinline__ T star(const T* a, const T* b, int idx) const {
     return first ? a[idx] : (T)2 * a[idx] - b[idx];
   }

@@ -61,6 +61,10 @@ struct Restricted {
 template <typename T>
 hipError_t launch_restrict_g(const Dims& f, const Dims& c, const StepConsts& k, const T* phinew,
                              const T* phin, const T* phinm1, Restricted<T> r, hipStream_t st);
+// Single resolution: the restricted set from the phase field on the flow grid (c = the grid).
+template <typename T>
+hipError_t launch_props_single(const Dims& c, const StepConsts& k, const T* phinew, const T* phin,
+                               const T* phinm1, Restricted<T> r, hipStream_t st);
 template <typename T>
 hipError_t launch_prolong(const Dims& f, const Dims& c, const T* u, const T* v, const T* w, T* uf,
                           T* vf, T* wf, hipStream_t st);

@@ -121,6 +121,14 @@ __global__ void __launch_bounds__(kBlock)
   const int k = bz;
   const int id = (k * ny + j) * nx + i;
   const Coarse<T> U{u, nx, ny, nz}, V{v, nx, ny, nz}, Wf{w, nx, ny, nz};
+  // eigenframe of Theta_in at this cell first (the neighbours are needed only for advection)
+  double th6[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) th6[m] = (double)thin.p[m][id];
+  double A[3][3], R[3][3];
+  unpack6(th6, A);
+  jacobi3(A, R);
+  const double th[3] = {A[0][0], A[1][1], A[2][2]};
   // L[a][b] = du_b/dx_a, so K_ij = L[j][i]
   T L[3][3];
   velocity_gradient(U, V, Wf, k, j, i, nz, ihx, ihy, ihz, L);
@@ -129,30 +137,6 @@ __global__ void __launch_bounds__(kBlock)
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) K[a][b] = (double)L[b][a];
-  // advection: -div(u Theta) in flux form, face-mean values, zero wall flux
-  const T h = (T)0.5;
-  const T uxp = U.at(k, j, i), uxm = U.at(k, j, i - 1);
-  const T vyp = V.at(k, j, i), vym = V.at(k, j - 1, i);
-  const T wzp = k < nz - 1 ? Wf.at(k, j, i) : (T)0, wzm = k > 0 ? Wf.at(k - 1, j, i) : (T)0;
-  double th6[6], adv[6];
-#pragma unroll
-  for (int m = 0; m < 6; ++m) {
-    const Coarse<T> t{thin.p[m], nx, ny, nz};
-    const T t0 = thin.p[m][id];
-    th6[m] = (double)t0;
-    const T fxp = uxp * h * (t0 + t.at(k, j, i + 1));
-    const T fxm = uxm * h * (t.at(k, j, i - 1) + t0);
-    const T fyp = vyp * h * (t0 + t.at(k, j + 1, i));
-    const T fym = vym * h * (t.at(k, j - 1, i) + t0);
-    const T fzp = k < nz - 1 ? wzp * h * (t0 + t.at(k + 1, j, i)) : (T)0;
-    const T fzm = k > 0 ? wzm * h * (t.at(k - 1, j, i) + t0) : (T)0;
-    adv[m] = -(double)((fxp - fxm) * ihx + (fyp - fym) * ihy + (fzp - fzm) * ihz);
-  }
-  // eigenframe of Theta_in
-  double A[3][3], R[3][3];
-  unpack6(th6, A);
-  jacobi3(A, R);
-  const double th[3] = {A[0][0], A[1][1], A[2][2]};
   // M = R^T K R
   double KR[3][3], M[3][3];
 #pragma unroll
@@ -180,12 +164,26 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int b = 0; b < 3; ++b) RS[a][b] = R[a][0] * S[0][b] + R[a][1] * S[1][b] + R[a][2] * S[2][b];
   const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
+  // advection: -div(u Theta) in flux form, face-mean values, zero wall flux
+  const T h = (T)0.5;
+  const T uxp = U.at(k, j, i), uxm = U.at(k, j, i - 1);
+  const T vyp = V.at(k, j, i), vym = V.at(k, j - 1, i);
+  const T wzp = k < nz - 1 ? Wf.at(k, j, i) : (T)0, wzm = k > 0 ? Wf.at(k - 1, j, i) : (T)0;
   double out[6];
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
+    const Coarse<T> t{thin.p[m], nx, ny, nz};
+    const T t0 = (T)th6[m];
+    const T fxp = uxp * h * (t0 + t.at(k, j, i + 1));
+    const T fxm = uxm * h * (t.at(k, j, i - 1) + t0);
+    const T fyp = vyp * h * (t0 + t.at(k, j + 1, i));
+    const T fym = vym * h * (t.at(k, j - 1, i) + t0);
+    const T fzp = k < nz - 1 ? wzp * h * (t0 + t.at(k + 1, j, i)) : (T)0;
+    const T fzm = k > 0 ? wzm * h * (t.at(k - 1, j, i) + t0) : (T)0;
+    const double adv = -(double)((fxp - fxm) * ihx + (fyp - fym) * ihy + (fzp - fzm) * ihz);
     const int a = pa[m], b = pb[m];
     const double src = RS[a][0] * R[b][0] + RS[a][1] * R[b][1] + RS[a][2] * R[b][2];
-    out[m] = c0 * (double)thn.p[m][id] + c1 * (th6[m] + dt * (adv[m] + src));
+    out[m] = c0 * (double)thn.p[m][id] + c1 * (th6[m] + dt * (adv + src));
   }
 #pragma unroll
   for (int m = 0; m < 6; ++m) thout.p[m][id] = (T)out[m];

@@ -14,6 +14,8 @@
 //                  and edges. A block marches up a column of coarse cells with rings of
 //                  fine phi^{n+1} and G layers in LDS; G is evaluated once per fine cell and
 //                  every thread sums its coarse cell's 2x2x2 groups from LDS.
+//   g_single, props_single -- the same set when the phase field lives on the flow grid
+//                  (single resolution): G and phi at the cells, then face and edge means.
 //   prolong, restrict -- the standalone transfer operators (eqs. dual1, dual2).
 #include "fine.hpp"
 
@@ -31,10 +33,11 @@ constexpr int kBlock = 256;
 // layer are loaded one step ahead into registers, so that their latency overlaps the
 // arithmetic of the current layer. The coarse velocities of eq. dual1 are reloaded only when
 // the column enters a new coarse layer. The 3D FP32 form is held to 64 registers, so that the
-// 8 blocks per CU of a 256 x 256 x 128 grid are resident at once.
-template <typename T, int R>
+// 8 blocks per CU of a 256 x 256 x 128 grid are resident at once. SR: single resolution (the
+// phase field on the flow grid; the face velocities are taken as they are).
+template <typename T, int R, bool SR>
 __global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && R == 2 ? 8 : 4)))
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && R == 2 && !SR ? 8 : 4)))
     k_ch_rhs(const T* __restrict__ phin, const T* __restrict__ phinm1, Prolonged<T> pv,
              T* __restrict__ out, int nx, int ny, int nz, int KB, T ihx, T ihy, T ihz,
              StepConsts c) {
@@ -90,10 +93,12 @@ __global__ void __launch_bounds__(kBlock)
     const T* pb = phinm1 + Kl * layer;
     return first ? ld_at(pa, cid) : (T)2 * ld_at(pa, cid) - (T)0.5 * ld_at(pb, cid);
   };
-  // coarse column of this fine column (eq. dual1)
+  // coarse column of this fine column (eq. dual1); with a single resolution the column itself
   const int ry = pv.ry;
-  const int ic = I >> 1, icw = wrap(ic - 1, pv.cnx);
-  const int jc = ry == 2 ? (J >> 1) : 0, jcw = ry == 2 ? wrap(jc - 1, pv.cny) : 0;
+  constexpr bool sr = SR;  // single resolution (pv.single)
+  const bool vy = pv.cny > 1;
+  const int ic = sr ? I : (I >> 1), icw = wrap(ic - 1, pv.cnx);
+  const int jc = ry == 2 ? (J >> 1) : J, jcw = vy ? wrap(jc - 1, pv.cny) : 0;
   const int cplane = pv.cnx * pv.cny;
   const int cu0 = jc * pv.cnx + ic, cu1 = jc * pv.cnx + icw;
   const int cv1 = jcw * pv.cnx + ic;
@@ -104,14 +109,14 @@ __global__ void __launch_bounds__(kBlock)
     vn[0] = pv.un[o + cu0];
     vn[1] = pv.un[o + cu1];
     vn[2] = pv.vn[o + cu0];
-    vn[3] = ry == 2 ? pv.vn[o + cv1] : (T)0;
+    vn[3] = vy ? pv.vn[o + cv1] : (T)0;
     vn[4] = k < pv.cnz - 1 ? pv.wn[o + cu0] : (T)0;
     vn[5] = k > 0 ? pv.wn[o - cplane + cu0] : (T)0;
     if (!first) {
       vm[0] = pv.unm1[o + cu0];
       vm[1] = pv.unm1[o + cu1];
       vm[2] = pv.vnm1[o + cu0];
-      vm[3] = ry == 2 ? pv.vnm1[o + cv1] : (T)0;
+      vm[3] = vy ? pv.vnm1[o + cv1] : (T)0;
       vm[4] = k < pv.cnz - 1 ? pv.wnm1[o + cu0] : (T)0;
       vm[5] = k > 0 ? pv.wnm1[o - cplane + cu0] : (T)0;
     }
@@ -129,20 +134,28 @@ __global__ void __launch_bounds__(kBlock)
   T ufp = 0, ufm = 0, vfp = 0, vfm = 0, wk = 0, wkm = 0;
   int kcur = -1;
   for (int K = K0; K < K0 + KB; ++K) {
-    const int k = K >> 1;
+    const int k = sr ? K : (K >> 1);
     if (k != kcur) {
       kcur = k;
       T vn[6], vm[6], s[6];
       load_vel(k, vn, vm);
 #pragma unroll
       for (int m = 0; m < 6; ++m) s[m] = first ? vn[m] : (T)2 * vn[m] - vm[m];
-      const bool iodd = I & 1;
-      ufp = iodd ? s[0] : h * (s[1] + s[0]);
-      ufm = iodd ? h * (s[1] + s[0]) : s[1];
+      if (sr) {
+        ufp = s[0];
+        ufm = s[1];
+      } else {
+        const bool iodd = I & 1;
+        ufp = iodd ? s[0] : h * (s[1] + s[0]);
+        ufm = iodd ? h * (s[1] + s[0]) : s[1];
+      }
       if (ry == 2) {
         const bool jodd = J & 1;
         vfp = jodd ? s[2] : h * (s[3] + s[2]);
         vfm = jodd ? h * (s[3] + s[2]) : s[3];
+      } else if (vy) {
+        vfp = s[2];
+        vfm = s[3];
       } else {
         vfp = vfm = s[2];
       }
@@ -157,8 +170,8 @@ __global__ void __launch_bounds__(kBlock)
       phat_next = load_centre(K + 1);
     }
     // fine z faces K (above) and K-1 (below); the walls carry zero flux
-    const T wfp = K == nz - 1 ? (T)0 : ((K & 1) ? wk : h * (wkm + wk));
-    const T wfm = K == 0 ? (T)0 : ((K & 1) ? h * (wkm + wk) : wkm);
+    const T wfp = K == nz - 1 ? (T)0 : (sr || (K & 1) ? wk : h * (wkm + wk));
+    const T wfm = K == 0 ? (T)0 : (sr ? wkm : ((K & 1) ? h * (wkm + wk) : wkm));
     __syncthreads();
     const int c0 = (ty + 1) * HX + (tx + 1);
     const T* P0 = sP + s0 * HP;
@@ -423,6 +436,71 @@ __global__ void __launch_bounds__(kBlock)
     }
   }
 }
+// Single resolution (the phase field on the flow grid): chemical potential G^{n+1} (the
+// bracket of eq. NS25 times the mixing energy, as restrict_g) and phi at the cells.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_g_single(const T* __restrict__ phinew, const T* __restrict__ phin,
+               const T* __restrict__ phinm1, Restricted<T> r, int nx, int ny, int nz, T ihx, T ihy,
+               T ihz, StepConsts c) {
+  int bx, by, bz;
+  xcd_tile(bx, by, bz);
+  const int i = bx * blockDim.x + threadIdx.x, j = by * blockDim.y + threadIdx.y, k = bz;
+  const int id = (k * ny + j) * nx + i;
+  auto at = [&](int kk, int jj, int ii) {
+    return phinew[(min(max(kk, 0), nz - 1) * ny + wrap(jj, ny)) * nx + wrap(ii, nx)];
+  };
+  const T p = phinew[id];
+  const T lap = (at(k, j, i + 1) - 2 * p + at(k, j, i - 1)) * (ihx * ihx) +
+                (at(k, j + 1, i) - 2 * p + at(k, j - 1, i)) * (ihy * ihy) +
+                (at(k + 1, j, i) - 2 * p + at(k - 1, j, i)) * (ihz * ihz);
+  const T an = phin[id];
+  const T ps = c.first ? an : (T)2 * an - phinm1[id];
+  T b = 0;
+  if (k == 0) b += (T)c.g_bot * ihz * ((T)1 - ps * ps);
+  if (k == nz - 1) b += (T)c.g_top * ihz * ((T)1 - ps * ps);
+  r.G_c[id] = -(T)c.cn2 * (lap + b) + (T)c.S * (p - ps) + ps * ps * ps - ps;
+  r.phi_c[id] = p;
+}
+
+// Single resolution: the face and edge quantities of the restricted set from the cell
+// values (eq. dual2's rule without refinement: a face is the mean of its two cells, an edge
+// the mean of its four, each as a mean along x, then y, then z; the wall ghost is the
+// adjacent cell) and the mixture properties of eq. dual3.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_props_single(Restricted<T> r, int nx, int ny, int nz, StepConsts c) {
+  int bx, by, bz;
+  xcd_tile(bx, by, bz);
+  const int i = bx * blockDim.x + threadIdx.x, j = by * blockDim.y + threadIdx.y, k = bz;
+  const int id = (k * ny + j) * nx + i;
+  const int plane = nx * ny;
+  auto P = [&](int kk, int jj, int ii) { return r.phi_c[(min(max(kk, 0), nz - 1) * ny + wrap(jj, ny)) * nx + wrap(ii, nx)]; };
+  auto Gv = [&](int kk, int jj, int ii) { return r.G_c[(min(max(kk, 0), nz - 1) * ny + wrap(jj, ny)) * nx + wrap(ii, nx)]; };
+  const T h = (T)0.5;
+  const T r1 = (T)c.rho1, r2 = (T)c.rho2, m1 = (T)c.mu1, m2 = (T)c.mu2;
+  auto rinv = [&](T ph) { return (T)1 / (h * ((T)1 + ph) * r1 + h * ((T)1 - ph) * r2); };
+  auto mu = [&](T ph) { return h * ((T)1 + ph) * m1 + h * ((T)1 - ph) * m2; };
+  const T p0 = P(k, j, i);
+  r.G_x[id] = h * (Gv(k, j, i) + Gv(k, j, i + 1));
+  r.G_y[id] = h * (Gv(k, j, i) + Gv(k, j + 1, i));
+  r.G_z[id] = h * (Gv(k, j, i) + Gv(k + 1, j, i));
+  r.ri_x[id] = rinv(h * (p0 + P(k, j, i + 1)));
+  r.ri_y[id] = rinv(h * (p0 + P(k, j + 1, i)));
+  r.ri_z[id] = rinv(h * (p0 + P(k + 1, j, i)));
+  r.mu_c[id] = mu(p0);
+  r.mu_xy[id] = mu(h * (h * (p0 + P(k, j, i + 1)) + h * (P(k, j + 1, i) + P(k, j + 1, i + 1))));
+  // z-edge arrays carry nz + 1 layers: layer m is the edge at z = m hz
+  auto exz = [&](int m) { return mu(h * (h * (P(m - 1, j, i) + P(m - 1, j, i + 1)) + h * (P(m, j, i) + P(m, j, i + 1)))); };
+  auto eyz = [&](int m) { return mu(h * (h * (P(m - 1, j, i) + P(m - 1, j + 1, i)) + h * (P(m, j, i) + P(m, j + 1, i)))); };
+  r.mu_xz[id + plane] = exz(k + 1);
+  r.mu_yz[id + plane] = eyz(k + 1);
+  if (k == 0) {
+    r.mu_xz[id] = exz(0);
+    r.mu_yz[id] = eyz(0);
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_prolong(T* __restrict__ uf, T* __restrict__ vf, T* __restrict__ wf, int fnx, int fny,
@@ -477,8 +555,9 @@ __global__ void __launch_bounds__(kBlock)
 template <typename T>
 hipError_t launch_ch_rhs(const Dims& f, const Dims& c, const StepConsts& k, ChIn<T> in, T* rhs,
                          hipStream_t st) {
+  const int single = f.nx == c.nx ? 1 : 0;  // the phase field on the flow grid
   Prolonged<T> pv{in.un, in.unm1, in.vn, in.vnm1, in.wn, in.wnm1, c.nx, c.ny, c.nz,
-                  c.ny == 1 ? 1 : 2, k.first};
+                  (c.ny == 1 || single) ? 1 : 2, k.first, single};
   int TX, TY;
   if (f.ny == 1) {
     TX = f.nx < 256 ? f.nx : 256;
@@ -496,12 +575,15 @@ hipError_t launch_ch_rhs(const Dims& f, const Dims& c, const StepConsts& k, ChIn
   if (need > 4) return hipErrorInvalidConfiguration;
   const size_t shm = (size_t)6 * HP * sizeof(T);
   const dim3 grid(f.nx / TX, f.ny / TY, f.nz / KB), block(TX, TY, 1);
-  if (need <= 2)
-    hipLaunchKernelGGL((k_ch_rhs<T, 2>), grid, block, shm, st, in.phin, in.phinm1, pv, rhs, f.nx, f.ny,
-                       f.nz, KB, (T)f.ihx, (T)f.ihy, (T)f.ihz, k);
-  else
-    hipLaunchKernelGGL((k_ch_rhs<T, 4>), grid, block, shm, st, in.phin, in.phinm1, pv, rhs, f.nx, f.ny,
-                       f.nz, KB, (T)f.ihx, (T)f.ihy, (T)f.ihz, k);
+#define DRPF_CH(R, SR)                                                                          \
+  hipLaunchKernelGGL((k_ch_rhs<T, R, SR>), grid, block, shm, st, in.phin, in.phinm1, pv, rhs, f.nx, \
+                     f.ny, f.nz, KB, (T)f.ihx, (T)f.ihy, (T)f.ihz, k)
+  if (single) {
+    if (need <= 2) DRPF_CH(2, true); else DRPF_CH(4, true);
+  } else {
+    if (need <= 2) DRPF_CH(2, false); else DRPF_CH(4, false);
+  }
+#undef DRPF_CH
   return hipGetLastError();
 }
 
@@ -537,6 +619,16 @@ hipError_t launch_restrict_g(const Dims& f, const Dims& c, const StepConsts& k, 
     go(k_restrict_g<T, 3>);
   else
     go(k_restrict_g<T, 6>);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_props_single(const Dims& c, const StepConsts& k, const T* phinew, const T* phin,
+                               const T* phinm1, Restricted<T> r, hipStream_t st) {
+  const Launch3 L = launch3(c.nx, c.ny, c.nz);
+  hipLaunchKernelGGL(k_g_single<T>, L.grid, L.block, 0, st, phinew, phin, phinm1, r, c.nx, c.ny, c.nz,
+                     (T)c.ihx, (T)c.ihy, (T)c.ihz, k);
+  hipLaunchKernelGGL(k_props_single<T>, L.grid, L.block, 0, st, r, c.nx, c.ny, c.nz, k);
   return hipGetLastError();
 }
 
@@ -578,7 +670,9 @@ hipError_t launch_restrict(const Dims& f, const Dims& c, const T* fine, T* coars
                                            const T*, const T*, Restricted<T>, hipStream_t);       \
   template hipError_t launch_prolong<T>(const Dims&, const Dims&, const T*, const T*, const T*,   \
                                         T*, T*, T*, hipStream_t);                                 \
-  template hipError_t launch_restrict<T>(const Dims&, const Dims&, const T*, T*, int, hipStream_t);
+  template hipError_t launch_restrict<T>(const Dims&, const Dims&, const T*, T*, int, hipStream_t); \
+  template hipError_t launch_props_single<T>(const Dims&, const StepConsts&, const T*, const T*,   \
+                                             const T*, Restricted<T>, hipStream_t);
 INST(double)
 INST(float)
 #undef INST

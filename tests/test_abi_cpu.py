@@ -88,6 +88,15 @@ def test_validation_polymer_forms():
         assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_EUNSUPPORTED
     p = _params(**ok)
     assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_OK
+    # single resolution: refine 1 or 2 (0 reads as 2); no adjoint; the phase field on the flow grid
+    for r, rc in ((3, B.DRPF_EINVAL), (-1, B.DRPF_EINVAL), (0, B.DRPF_OK), (1, B.DRPF_OK)):
+        p = _params(refine=r)
+        assert L.drpf_validate(ctypes.byref(p)) == rc, r
+    p = _params(refine=1)
+    assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_EUNSUPPORTED
+    f, c = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.drpf_field_elems(ctypes.byref(p), ctypes.byref(f), ctypes.byref(c)) == B.DRPF_OK
+    assert f.value == c.value
 
 
 def test_sizes_and_workspace_errors():

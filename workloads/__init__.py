@@ -89,6 +89,14 @@ CONFIGS: dict[str, Config] = {
     "C5": _c(name="C5", nx=256, ny=256, nz=128, lx=2.0, ly=2.0, lz=1.0, re=1.0, ca=1.0,
              cn=0.01, pe=300.0, wi=2.0, beta=0.3, theta_bottom_deg=45.0, rho_ratio=100.0,
              mu_ratio=10.0, dt=5e-5, steps=200, radius=0.25, viscoelastic=1),
+    # C2 and C3 at a single resolution: everything on the 256x256x128 grid that carries the
+    # phase field of C2 / C3 (the baselines of the dual-resolution comparison).
+    "C2S": _c(name="C2S", nx=256, ny=256, nz=128, lx=2.0, ly=2.0, lz=1.0, re=100.0, ca=1.0,
+              cn=0.01, pe=300.0, theta_bottom_deg=90.0, rho_ratio=1000.0, mu_ratio=100.0,
+              dt=1e-4, steps=500, radius=0.25, refine=1),
+    "C3S": _c(name="C3S", nx=256, ny=256, nz=128, lx=2.0, ly=2.0, lz=1.0, re=1.0, ca=1.0,
+              cn=0.01, pe=300.0, wi=1.0, beta=0.5, theta_bottom_deg=120.0, dt=5e-5,
+              steps=1000, radius=0.25, viscoelastic=1, refine=1),
     # C3 with the log-conformation update of the paper and a Giesekus term.
     "C3L": _c(name="C3L", nx=128, ny=128, nz=64, lx=2.0, ly=2.0, lz=1.0, re=1.0, ca=1.0,
               cn=0.01, pe=300.0, wi=1.0, beta=0.5, theta_bottom_deg=120.0, dt=5e-5,
