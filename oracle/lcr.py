@@ -22,14 +22,15 @@ Readings (the paper is silent or garbled here):
   last ratio evaluated as exp(-theta_i) d / expm1(d), d = theta_j - theta_i (its value 1 at
   d = 0): the paper's expression for distinct eigenvalues, its limit for equal ones, which for
   c = I is the paper's rule.
-* Advection: the second-order central flux form of the stress-form update (the paper's
-  WENO5-Z is a separate item), Neumann at the walls, zero wall flux.
+* Advection: the stress form's flux form, second-order central or (P.advection = 1) the
+  paper's WENO-Z (weno.py), zero wall flux.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from . import discrete as D
+from . import weno
 from .model import Params
 
 XX, YY, ZZ, XY, XZ, YZ = range(6)
@@ -99,7 +100,10 @@ def stress(P: Params, theta_comps):
 
 
 def advection(P: Params, q, u, v, w):
-    """-div(u q) in flux form with face-mean values and zero wall flux (as the stress form)."""
+    """-div(u q) in flux form with face-mean values (or the WENO-Z face values) and zero wall
+    flux, as the stress form."""
+    if P.advection == 1:
+        return -weno.divergence(q, u, v, w, P.h, D)
     hx, hy, hz = P.h
     fx = u * 0.5 * (q + D.xp(q))
     fy = v * 0.5 * (q + D.yp(q))

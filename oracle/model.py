@@ -51,6 +51,7 @@ class Params:
     constitutive: int = 0          # 0: stress form, 1: log-conformation (lcr.py)
     giesekus_alpha: float = 0.0    # Giesekus mobility; 0 is Oldroyd-B
     refine: int = 2                # phase-field grid refinement: 2 dual resolution, 1 single
+    advection: int = 0             # 0: second-order central flux, 1: fifth-order WENO-Z (weno.py)
 
     @classmethod
     def from_config(cls, cfg) -> "Params":

@@ -19,6 +19,7 @@ import numpy as np
 
 from . import discrete as D
 from . import lcr
+from . import weno
 from .model import Params, constants
 
 XX, YY, ZZ, XY, XZ, YZ = range(6)
@@ -51,9 +52,11 @@ def wall_data(P: Params, phis):
     return b
 
 
-def advection_fine(phis, uf, vf, wf, hf):
-    """div(u phi) in flux form with the mean of the two adjacent cells on each face and
-    zero flux through the walls."""
+def advection_fine(phis, uf, vf, wf, hf, scheme=0):
+    """div(u phi) in flux form with the mean of the two adjacent cells on each face (scheme 1:
+    the WENO-Z face value, weno.py) and zero flux through the walls."""
+    if scheme == 1:
+        return weno.divergence(phis, uf, vf, wf, hf, D)
     hx, hy, hz = hf
     fx = uf * 0.5 * (phis + D.xp(phis))
     fy = vf * 0.5 * (phis + D.yp(phis))
@@ -72,7 +75,7 @@ def cahn_hilliard(P: Params, st, C):
     vs = _levels(st["v"], first)[0]
     ws = _levels(st["w"], first)[0]
     uf, vf, wf = D.prolong(us, vs, ws, P.ry, P.refine)              # eq. dual1
-    A = advection_fine(phis, uf, vf, wf, hf)
+    A = advection_fine(phis, uf, vf, wf, hf, P.advection)
     fstar = (phis ** 3 - phis) / cn2                                  # eq. NS6, eta = Cn
     Q = (P.pe / cn2) * (phih / P.dt - A) + D.lap_neumann(fstar - (C.S / cn2) * phis, hf)  # NS28
     b = wall_data(P, phis)
@@ -363,16 +366,19 @@ def polymer_rhs(P: Params, tau, u, v, w, L):
     -div(u tau) + (grad u)^T.tau + tau.(grad u) + [(1-beta)(grad u + grad u^T) - tau] / Wi
     - alpha/(1-beta) tau.tau,
     index form RH_ab = -div(u tau_ab) + L_ca tau_cb + tau_ac L_cb + ..., L_ab = du_b/dx_a.
-    Advection: flux form with face-mean stress and zero wall flux."""
+    Advection: flux form with face-mean stress (or the WENO-Z face value) and zero wall flux."""
     hx, hy, hz = P.h
     out = []
     for a, b in ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)):
         t = tau[_PAIRS[(a, b)]]
-        fx = u * 0.5 * (t + D.xp(t))
-        fy = v * 0.5 * (t + D.yp(t))
-        fz = w * 0.5 * (t + D.zp_neu(t))
-        fz[-1] = 0.0
-        rh = -((fx - D.xm(fx)) / hx + (fy - D.ym(fy)) / hy + (fz - D.zm_face(fz)) / hz)
+        if P.advection == 1:
+            rh = -weno.divergence(t, u, v, w, P.h, D)
+        else:
+            fx = u * 0.5 * (t + D.xp(t))
+            fy = v * 0.5 * (t + D.yp(t))
+            fz = w * 0.5 * (t + D.zp_neu(t))
+            fz[-1] = 0.0
+            rh = -((fx - D.xm(fx)) / hx + (fy - D.ym(fy)) / hy + (fz - D.zm_face(fz)) / hz)
         for c in range(3):
             rh = rh + L[c][a] * tau[_PAIRS[(c, b)]] + tau[_PAIRS[(a, c)]] * L[c][b]
         rh = rh + ((1.0 - P.beta) * (L[a][b] + L[b][a]) - t) / P.wi

@@ -50,6 +50,7 @@ class Config:
     constitutive: int = 0       # 0: stress form, 1: log-conformation
     giesekus_alpha: float = 0.0
     refine: int = 2             # phase-field grid: 2 dual resolution, 1 single resolution
+    advection: int = 0          # 0: second-order central flux, 1: fifth-order WENO-Z
     steps: int = 10
     radius: float = 0.25
     centre: tuple | None = None  # (x, y) of the drop foot on the bottom wall
