@@ -8,7 +8,8 @@
 * at a jump the face values stay within the data (no new extrema) and pick the smooth side;
 * the flux form conserves: the periodic sum of the divergence is zero, and the coupled step
   with WENO-Z advection conserves the phase-field mass;
-* the mirror ghost at a wall: a field symmetric about the wall face gives no flux through it.
+* the mirror ghost at a wall: a field constant in z carries w q through every face, and a
+  wall-bounded column equals the upper half of its even periodic extension (both walls).
 """
 from __future__ import annotations
 
@@ -102,6 +103,31 @@ def test_periodic_sum_and_mirror_wall():
     w = rng.standard_normal((6, 4, 8))
     fz = weno.face_flux(qc, w, 0, True)
     assert np.max(np.abs(fz - 0.7 * w)) < 1e-15
+
+
+def test_mirror_wall_equals_even_periodic_extension():
+    """The mirror ghosts are the even extension: a wall-bounded column of n cells equals the
+    upper half of the periodic column of 2n cells made of the column reflected below it, with
+    the face velocities odd about the bottom wall (zero on both walls). The periodic branch uses
+    true neighbours only, so this checks the ghost indices at both walls."""
+    rng = np.random.default_rng(21)
+    n = 8
+    q = rng.standard_normal((n, 3, 4))
+    w = rng.standard_normal((n, 3, 4))
+    w[-1] = 0.0                                # top wall face
+    fz = weno.face_flux(q, w, 0, True)
+    fz[-1] = 0.0
+    div_wall = fz - D.zm_face(fz)
+    Q = np.concatenate([q[::-1], q], axis=0)  # Q[n + k] = q[k], Q[n - 1 - k] = q[k]
+    Wp = np.zeros_like(Q)
+    Wp[n:] = w                                 # face between Q[f], Q[f + 1]; Wp[2n - 1] = 0 (top)
+    for f in range(n - 1):                     # the reflected faces; Wp[n - 1] = 0 (bottom wall)
+        Wp[f] = -w[n - 2 - f]
+    Fp = weno.face_flux(Q, Wp, 0, False)
+    div_per = Fp - np.roll(Fp, 1, axis=0)
+    assert np.max(np.abs(div_per[n:] - div_wall)) < 1e-13 * np.max(np.abs(div_wall))
+    # and the lower half mirrors the upper one
+    assert np.max(np.abs(div_per[:n][::-1] - div_wall)) < 1e-13 * np.max(np.abs(div_wall))
 
 
 def test_coupled_step_conserves_mass_with_weno():
