@@ -139,6 +139,67 @@ def helmholtz(rhs, coeff, shift, kind, h):
     return np.ascontiguousarray(np.fft.ifft2(Y, axes=(1, 2)).real)
 
 
+def helmholtz_robin(rhs, coeff, shift, d, h):
+    """Solve ``coeff * (L_N + d W) x - shift * x = rhs`` exactly, W the indicator of the two
+    wall-adjacent layers: the cell-centred Laplacian whose wall ghost carries a term linear in
+    the wall-adjacent value (a Robin condition), d = -kappa / hz.
+
+    FFT in x and y; in z the eigenvectors of the symmetric wall-normal matrix (second
+    difference with Neumann ghosts plus d on the two corner entries), from numpy.linalg.eigh.
+    """
+    nz, ny, nx = rhs.shape
+    hx, hy, hz = h
+    _, TR = _wall_normal_matrices(nz, hz, d)
+    lam_z, V = np.linalg.eigh(TR)
+    X = np.fft.fft2(rhs, axes=(1, 2))
+    lam_xy = _eig_periodic(ny, hy)[:, None] + _eig_periodic(nx, hx)[None, :]
+    Z = np.tensordot(V.T, X, axes=(1, 0))
+    Z = Z / (coeff * (lam_z[:, None, None] + lam_xy[None, :, :]) - shift)
+    Y = np.tensordot(V, Z, axes=(1, 0))
+    return np.ascontiguousarray(np.fft.ifft2(Y, axes=(1, 2)).real)
+
+
+def _wall_normal_matrices(nz, hz, d):
+    """Dense z second differences: Neumann ghosts, and the same plus d on the two corners."""
+    T = np.zeros((nz, nz))
+    for k in range(nz):
+        T[k, k] = -2.0 / hz ** 2
+        if k > 0:
+            T[k, k - 1] = 1.0 / hz ** 2
+        else:
+            T[k, k] += 1.0 / hz ** 2
+        if k < nz - 1:
+            T[k, k + 1] = 1.0 / hz ** 2
+        else:
+            T[k, k] += 1.0 / hz ** 2
+    TR = T.copy()
+    TR[0, 0] += d
+    TR[nz - 1, nz - 1] += d
+    return T, TR
+
+
+def ch_relaxed_solve(rhs, s, c, d, h):
+    """Solve [L_N (L_N + d W) - s L_N + c] x = rhs exactly (W the indicator of the two
+    wall-adjacent layers): eq. NS25 with the relaxed wall condition of eq. NS34.
+
+    FFT in x and y; for every Fourier mode (wavenumber shift mu of the x-y Laplacian) the
+    nz x nz matrix (T + mu)(T_R + mu) - s (T + mu) + c is built densely and solved with
+    numpy.linalg.solve.
+    """
+    nz, ny, nx = rhs.shape
+    hx, hy, hz = h
+    T, TR = _wall_normal_matrices(nz, hz, d)
+    X = np.fft.fft2(rhs, axes=(1, 2))
+    lam_xy = _eig_periodic(ny, hy)[:, None] + _eig_periodic(nx, hx)[None, :]
+    Y = np.empty_like(X)
+    I = np.eye(nz)
+    for j in range(ny):
+        mus = lam_xy[j]
+        M = np.stack([(T + mu * I) @ (TR + mu * I) - s * (T + mu * I) + c * I for mu in mus])
+        Y[:, j, :] = np.linalg.solve(M, X[:, j, :].T[:, :, None])[:, :, 0].T
+    return np.ascontiguousarray(np.fft.ifft2(Y, axes=(1, 2)).real)
+
+
 # ---------------------------------------------------------------------------------------
 # dual-grid transfer (Sec. 3.1)
 # ---------------------------------------------------------------------------------------

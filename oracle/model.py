@@ -52,6 +52,7 @@ class Params:
     giesekus_alpha: float = 0.0    # Giesekus mobility; 0 is Oldroyd-B
     refine: int = 2                # phase-field grid refinement: 2 dual resolution, 1 single
     advection: int = 0             # 0: second-order central flux, 1: fifth-order WENO-Z (weno.py)
+    d_w: float = 0.0               # wall relaxation D_w of eq. NS15 (0: static contact angle)
 
     @classmethod
     def from_config(cls, cfg) -> "Params":

@@ -79,6 +79,8 @@ def cahn_hilliard(P: Params, st, C):
     fstar = (phis ** 3 - phis) / cn2                                  # eq. NS6, eta = Cn
     Q = (P.pe / cn2) * (phih / P.dt - A) + D.lap_neumann(fstar - (C.S / cn2) * phis, hf)  # NS28
     b = wall_data(P, phis)
+    if P.d_w > 0.0:
+        return _cahn_hilliard_relaxed(P, C, Q, b, phis, phih)
     # Eq. NS26 with the boundary condition of eq. NS33, and eq. NS27 with that of eq. NS34.
     # With L_N the Laplacian with homogeneous-Neumann ghosts and L_w = L_N + b the one with
     # the wetting ghosts, NS25 reads (L_N - c_psi)(L_N + alpha) phi = Q - L_N b; setting
@@ -88,6 +90,39 @@ def cahn_hilliard(P: Params, st, C):
     # Chemical potential at n+1: lambda times the bracket of eq. NS25, i.e.
     # Cn^2 [-L_w phi + (S/Cn^2)(phi - phi*) + f(phi*)].
     G = -cn2 * (D.lap_neumann(phi_new, hf) + b) + C.S * (phi_new - phis) + phis ** 3 - phis
+    return phi_new, G, phis, Psi
+
+
+def _cahn_hilliard_relaxed(P: Params, C, Q, b, phis, phih):
+    """Eqs. NS25-NS34 with the wall relaxation D_w > 0 of eq. NS15.
+
+    Eq. NS34 adds D_w (gamma0 phi^{n+1} - phi_hat) / dt to the wall derivative of phi^{n+1}
+    (the wall value is the wall-adjacent cell's, as for the static data b; the term
+    D_w u* . grad phi* is zero at the stationary no-slip walls). With kappa = D_w gamma0 / dt
+    the ghost of the wall-adjacent cell becomes adjacent + hz (g - kappa phi^{n+1} +
+    kappa phi_hat / gamma0): L_w phi = L_R phi + b_R, L_R = L_N + dL with dL = -kappa / hz
+    on the wall-adjacent layers, b_R = b + (kappa / hz) phi_hat / gamma0 there.
+
+    Eq. NS33 carries the wall derivative of phi^{n+1} itself, so the two Helmholtz problems
+    are solved together: NS25 is [L_N L_R - (S/Cn^2) L_N + c] phi^{n+1} = Q - L_N b_R with
+    c = gamma0 Pe / (Cn^2 dt), the outer Laplacian keeping the zero-flux walls of the chemical
+    potential (mass is conserved exactly). Psi = (L_R + alpha) phi^{n+1} + b_R (eq. NS27).
+    """
+    hf = P.hf
+    cn2 = P.cn ** 2
+    kap = P.d_w * C.gamma0 / P.dt
+    hz = hf[2]
+    dL = np.zeros_like(phis)
+    dL[0] = -kap / hz
+    dL[-1] = -kap / hz
+    bR = b.copy()
+    bR[0] += (kap / hz) * phih[0] / C.gamma0
+    bR[-1] += (kap / hz) * phih[-1] / C.gamma0
+    c = C.gamma0 * P.pe / (cn2 * P.dt)
+    phi_new = D.ch_relaxed_solve(Q - D.lap_neumann(bR, hf), C.S / cn2, c, -kap / hz, hf)
+    lw = D.lap_neumann(phi_new, hf) + dL * phi_new + bR
+    Psi = lw + C.alpha * phi_new
+    G = -cn2 * lw + C.S * (phi_new - phis) + phis ** 3 - phis
     return phi_new, G, phis, Psi
 
 

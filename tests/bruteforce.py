@@ -14,10 +14,11 @@ def idx(shape):
     return lambda k, j, i: (k * ny + j) * nx + i
 
 
-def dense_operator(shape, h, coeff, shift, kind):
+def dense_operator(shape, h, coeff, shift, kind, kappa=0.0):
     """Dense matrix of coeff * Laplacian - shift * I on a z-bounded box.
     kind 'neumann': ghost = adjacent cell; 'dirichlet': ghost = -adjacent;
-    'wface': unknowns are the interior z faces k = 0..nz-2, wall faces are 0."""
+    'wface': unknowns are the interior z faces k = 0..nz-2, wall faces are 0;
+    'robin': ghost = adjacent - hz kappa adjacent (a wall derivative -kappa times the value)."""
     nz, ny, nx = shape
     hx, hy, hz = h
     nzu = nz - 1 if kind == "wface" else nz
@@ -42,6 +43,8 @@ def dense_operator(shape, h, coeff, shift, kind):
                         A[r, r] += coeff / hz ** 2
                     elif kind == "dirichlet":
                         A[r, r] -= coeff / hz ** 2
+                    elif kind == "robin":
+                        A[r, r] += coeff / hz ** 2 * (1.0 - hz * kappa)
                     # 'wface': wall value 0 contributes nothing
     return A
 

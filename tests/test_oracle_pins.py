@@ -54,6 +54,36 @@ def test_dong_factorisation(sf, first):
 # --------------------------------------------------------------------------------------
 
 
+@pytest.mark.parametrize("shape", [(6, 4, 8), (5, 1, 8)])
+def test_robin_helmholtz_matches_dense_solve(shape):
+    rng = np.random.default_rng(17)
+    h = (0.13, 0.21, 0.17)
+    coeff, shift, kappa = 0.7, 3.3, 9.0
+    A = BF.dense_operator(shape, h, coeff, shift, "robin", kappa)
+    rhs = rng.standard_normal(shape)
+    ref = np.linalg.solve(A, rhs.ravel()).reshape(shape)
+    x = D.helmholtz_robin(rhs, coeff, shift, -kappa / h[2], h)
+    assert np.max(np.abs(x - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # no relaxation: the Neumann solve
+    x0 = D.helmholtz_robin(rhs, coeff, shift, 0.0, h)
+    assert np.max(np.abs(x0 - D.helmholtz(rhs, coeff, shift, "neumann", h))) <= 1e-12 * np.max(np.abs(x0))
+
+
+@pytest.mark.parametrize("shape", [(6, 4, 8), (5, 1, 8)])
+def test_relaxed_ch_operator_matches_dense_solve(shape):
+    """[L_N L_R - s L_N + c] from the product of loop-built dense matrices."""
+    rng = np.random.default_rng(19)
+    h = (0.13, 0.21, 0.17)
+    s, c, kappa = 40.0, 900.0, 9.0
+    LN = BF.dense_operator(shape, h, 1.0, 0.0, "neumann")
+    LR = BF.dense_operator(shape, h, 1.0, 0.0, "robin", kappa)
+    A = LN @ LR - s * LN + c * np.eye(LN.shape[0])
+    rhs = rng.standard_normal(shape)
+    ref = np.linalg.solve(A, rhs.ravel()).reshape(shape)
+    x = D.ch_relaxed_solve(rhs, s, c, -kappa / h[2], h)
+    assert np.max(np.abs(x - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
 @pytest.mark.parametrize("kind", ["neumann", "dirichlet", "wface"])
 @pytest.mark.parametrize("shape", [(6, 4, 8), (5, 1, 8)])
 def test_helmholtz_matches_dense_solve(kind, shape):
@@ -188,13 +218,15 @@ def _random_state(P, rng, amp_u=0.3):
             "tau": [[z() for _ in range(6)], [z() for _ in range(6)]], "step": 3}
 
 
-@pytest.mark.parametrize("ny,first", [(1, False), (2, False), (2, True)])
-def test_ch_solves_unsplit_equation(ny, first):
+@pytest.mark.parametrize("ny,first,d_w", [(1, False, 0.0), (2, False, 0.0), (2, True, 0.0),
+                                          (1, False, 0.05), (2, False, 0.05), (2, True, 0.05)])
+def test_ch_solves_unsplit_equation(ny, first, d_w):
     """phi^{n+1} satisfies the unsplit eq. NS25 with the wetting ghost of eq. NS34 and the
-    zero-flux outer Laplacian, evaluated cell by cell."""
+    zero-flux outer Laplacian, evaluated cell by cell. With wall relaxation (D_w > 0) the ghost
+    of eq. NS34 holds phi^{n+1} itself."""
     rng = np.random.default_rng(21)
     P = _params(nx=4, ny=ny, nz=4, ly=0.25 * ny, theta_bottom_deg=60.0, theta_top_deg=110.0,
-                s_factor=1.3)
+                s_factor=1.3, d_w=d_w)
     st = _random_state(P, rng)
     if first:
         st["step"] = 0
@@ -241,12 +273,16 @@ def test_ch_solves_unsplit_equation(ny, first):
     def at(a, K, J, I):
         return a[K, J % nyf, I % nxf]
 
+    def wall_derivative(K, J, I, c):
+        # eq. NS34: n . grad phi^{n+1} = g(phi*) - D_w (gamma0 phi^{n+1} - phi_hat) / dt
+        return gw[K][J, I] - d_w * (C.gamma0 * c - ph[K, J, I]) / P.dt
+
     def lap_w(a, K, J, I):
         c = a[K, J, I]
         s = (at(a, K, J, I + 1) - 2 * c + at(a, K, J, I - 1)) / hf[0] ** 2
         s += (at(a, K, J + 1, I) - 2 * c + at(a, K, J - 1, I)) / hf[1] ** 2
-        up = a[K + 1, J, I] if K + 1 < nzf else c + hf[2] * gw[nzf - 1][J, I]
-        dn = a[K - 1, J, I] if K > 0 else c + hf[2] * gw[0][J, I]
+        up = a[K + 1, J, I] if K + 1 < nzf else c + hf[2] * wall_derivative(nzf - 1, J, I, c)
+        dn = a[K - 1, J, I] if K > 0 else c + hf[2] * wall_derivative(0, J, I, c)
         return s + (up - 2 * c + dn) / hf[2] ** 2
 
     inner = np.zeros_like(phi)

@@ -51,6 +51,7 @@ class Config:
     giesekus_alpha: float = 0.0
     refine: int = 2             # phase-field grid: 2 dual resolution, 1 single resolution
     advection: int = 0          # 0: second-order central flux, 1: fifth-order WENO-Z
+    d_w: float = 0.0             # wall relaxation D_w of eq. NS15
     steps: int = 10
     radius: float = 0.25
     centre: tuple | None = None  # (x, y) of the drop foot on the bottom wall
@@ -102,6 +103,12 @@ CONFIGS: dict[str, Config] = {
     "C3L": _c(name="C3L", nx=128, ny=128, nz=64, lx=2.0, ly=2.0, lz=1.0, re=1.0, ca=1.0,
               cn=0.01, pe=300.0, wi=1.0, beta=0.5, theta_bottom_deg=120.0, dt=5e-5,
               steps=1000, radius=0.25, viscoelastic=1, constitutive=1, giesekus_alpha=0.2),
+    # C3L with the fifth-order WENO-Z advection of the phase field and of the log-conformation:
+    # the full scheme of the paper's three-dimensional viscoelastic runs.
+    "C3P": _c(name="C3P", nx=128, ny=128, nz=64, lx=2.0, ly=2.0, lz=1.0, re=1.0, ca=1.0,
+              cn=0.01, pe=300.0, wi=1.0, beta=0.5, theta_bottom_deg=120.0, dt=5e-5,
+              steps=1000, radius=0.25, viscoelastic=1, constitutive=1, giesekus_alpha=0.2,
+              advection=1),
 }
 
 
