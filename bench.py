@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--others", default="C3,C5,C3L,C2S,C3S",
+    ap.add_argument("--others", default="C3,C5,C3L,C3P,C2R,C2S,C3S",
                     help="further workloads timed in both forms beside the headline one ('' for none)")
     ap.add_argument("--other-steps", type=int, default=100)
     ap.add_argument("--no-error", action="store_true",
@@ -86,7 +86,9 @@ def alg_bytes(kernel, cfg, es):
     ne = C["nx"] * C["ny"] * (C["nz"] + 1)
     ve = cfg.viscoelastic
     words = {
-        "ch_rhs": 3 * nf + 6 * nc,
+        # with WENO-Z the advection arrives precomputed (read once) instead of the velocities
+        "ch_rhs": 4 * nf if cfg.advection == 1 else 3 * nf + 6 * nc,
+        "weno_adv_fine": 3 * nf + 6 * nc if cfg.advection == 1 else 0,
         "fft_x_fwd_fine": nf + sf,
         "fft_y_fwd_fine": 2 * sf if F["ny"] > 1 else 0,
         "zpass_ch": 2 * sf,
@@ -107,7 +109,7 @@ def alg_bytes(kernel, cfg, es):
 
 
 KERNEL_SOURCE = {
-    "ch_rhs": "stencil_ch.hip", "restrict_g": "stencil_ch.hip", "momentum_rhs": "stencil_ns.hip",
+    "ch_rhs": "stencil_ch.hip", "restrict_g": "stencil_ch.hip", "weno_adv_fine": "stencil_ch.hip", "momentum_rhs": "stencil_ns.hip",
     "polymer_stage1": "stencil_ns.hip", "polymer_stage2": "stencil_ns.hip",
     "zpass_ch": "tridiag.hip", "zpass_ns": "tridiag.hip",
 }
@@ -158,7 +160,7 @@ def time_form(drpf, W, cfg, precision, steps, warmup):
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     # per-kernel pass (HIP events after every launch, same stream)
-    g.profile_begin(steps * 16 + 1)
+    g.profile_begin(steps * 17 + 1)
     g.step(st, steps)
     prof = g.profile_end()
     torch.cuda.synchronize()
@@ -498,6 +500,9 @@ def main():
         if ocfg.viscoelastic:
             law = f"Giesekus alpha {ocfg.giesekus_alpha:g}" if ocfg.giesekus_alpha else "Oldroyd-B"
             law += ", log-conformation" if ocfg.constitutive == 1 else ", stress form"
+        law += ", WENO-Z advection" if ocfg.advection == 1 else ", central advection"
+        if ocfg.d_w > 0:
+            law += f", relaxed walls D_w {ocfg.d_w:g}"
         ent = {"workload": f"{name}: coarse {ocfg.nx}x{ocfg.ny}x{ocfg.nz}, fine {OF['nx']}x{OF['ny']}x{OF['nz']} "
                            f"({OF['cells']} cells), {law}, "
                            f"rho ratio {ocfg.rho_ratio:g}, mu ratio {ocfg.mu_ratio:g}",

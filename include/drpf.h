@@ -101,6 +101,15 @@ typedef struct drpf_params {
                                   resolution (the phase field on the flow grid, faces and
                                   edges by two- and four-cell means). The transfer and
                                   adjoint entry points need 2.                               */
+  int advection;               /* advection of the phase field (eq. NS25) and of the polymer
+                                  (eq. NS41): 0 second-order central flux form; 1 fifth-order
+                                  WENO-Z face values (Sec. 3.2.1, 3.2.3). The adjoint needs 0 */
+  double d_w;                  /* wall relaxation D_w >= 0 of eq. NS15, discretised as eq.
+                                  NS34 at both walls: the wall derivative of phi^{n+1} gains
+                                  D_w (gamma0 phi^{n+1} - phi_hat) / dt at the wall-adjacent
+                                  cell (a Robin condition; NS25 is solved with it and with
+                                  NS33 exactly). 0 (default): static contact angles. The
+                                  adjoint needs 0                                            */
 } drpf_params;
 
 /* Device pointers of one solution state. Level n is index 0, level n-1 index 1.
@@ -202,8 +211,9 @@ int drpf_debug_field(drpf_grid* g, int id, void** ptr, size_t* count);
  * count. Kernel ids: 0 ch_rhs, 1-2 fine x/y forward transforms, 3 fine wall-normal pass,
  * 4-5 fine y/x inverse transforms, 6 restriction and chemical potential, 7 momentum
  * right-hand side, 8-9 coarse x/y forward transforms, 10 coarse wall-normal pass (NS
- * projection), 11-12 coarse y/x inverse transforms, 13-14 polymer stages. */
-#define DRPF_NKERNELS 15
+ * projection), 11-12 coarse y/x inverse transforms, 13-14 polymer stages, 15 WENO-Z
+ * advection of the phase field (advection 1 only; it precedes ch_rhs). */
+#define DRPF_NKERNELS 16
 int drpf_profile_begin(drpf_grid* g, int max_launches, void* stream);
 int drpf_profile_end(drpf_grid* g, double* total_ms, int* launches, int n);
 /* Short name of kernel id (see above); "" for an unknown id. */

@@ -105,6 +105,9 @@ StepConsts make_consts(const drpf_params& p, bool first) {
   c.inv_rho0 = 1.0 / c.rho0;
   c.inv_wi = 1.0 / p.wi;
   c.giesekus = p.giesekus_alpha;
+  c.advection = p.advection;
+  c.relax_kappa = p.d_w * c.gamma0 / p.dt;
+  c.inv_gamma0 = 1.0 / c.gamma0;
   return c;
 }
 
@@ -283,7 +286,7 @@ int upload_tables(drpf_grid* g, const Dims& d, const TabOff& t, hipStream_t st,
 const char* const kKernelNames[DRPF_NKERNELS] = {
     "ch_rhs", "fft_x_fwd_fine", "fft_y_fwd_fine", "zpass_ch", "fft_y_inv_fine", "fft_x_inv_fine",
     "restrict_g", "momentum_rhs", "fft_x_fwd_coarse", "fft_y_fwd_coarse", "zpass_ns",
-    "fft_y_inv_coarse", "fft_x_inv_coarse", "polymer_stage1", "polymer_stage2"};
+    "fft_y_inv_coarse", "fft_x_inv_coarse", "polymer_stage1", "polymer_stage2", "weno_adv_fine"};
 
 void mark(drpf_grid* g, int kernel, hipStream_t st) {
   if (!g->prof || g->ev_used >= g->ev.size()) return;
@@ -323,7 +326,14 @@ int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t
   const size_t nc = C.cells();
   const bool ve = g->p.viscoelastic != 0;
   // ---- Cahn-Hilliard on the fine grid
-  ChIn<T> ci{io.phin, io.phinm1, io.un, io.unm1, io.vn, io.vnm1, io.wn, io.wnm1};
+  ChIn<T> ci{io.phin, io.phinm1, io.un, io.unm1, io.vn, io.vnm1, io.wn, io.wnm1, nullptr};
+  if (g->p.advection == 1) {
+    // WENO-Z advection first, into the fine spectral buffer (free until the transform)
+    T* adv = reinterpret_cast<T*>(Sf);
+    HIPCHK(launch_weno_adv_fine<T>(F, C, K, ci, adv, st), "weno advection");
+    mark(g, 15, st);
+    ci.adv = adv;
+  }
   HIPCHK(launch_ch_rhs<T>(F, C, K, ci, Rf, st), "ch_rhs");
   mark(g, 0, st);
   const T* inf[4] = {Rf, nullptr, nullptr, nullptr};
@@ -331,7 +341,8 @@ int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t
   mark(g, 1, st);
   HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, false, st), "fft_y fine");
   mark(g, 2, st);
-  HIPCHK(launch_zpass_ch<T>(F, tf, Sf, piv, K.c_psi, K.alpha, 1.0 / ((double)F.nx * F.ny), st),
+  HIPCHK(launch_zpass_ch<T>(F, tf, Sf, piv, K.c_psi, K.alpha, 1.0 / ((double)F.nx * F.ny),
+                            -K.relax_kappa / F.hz, st),
          "zpass_ch");
   mark(g, 3, st);
   HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, true, st), "ifft_y fine");
@@ -694,7 +705,7 @@ int adjoint_impl(drpf_grid* g, const drpf_state* x, const drpf_state* xn, drpf_a
   const T* inf[4] = {P(A.lQ), nullptr, nullptr, nullptr};
   HIPCHK(launch_fft_x_fwd<T>(F, tf, inf, 1, Sf, st), "adjoint fft_x fine");
   HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, false, st), "adjoint fft_y fine");
-  HIPCHK(launch_zpass_ch<T>(F, tf, Sf, piv, K.c_psi, K.alpha, 1.0 / ((double)F.nx * F.ny), st),
+  HIPCHK(launch_zpass_ch<T>(F, tf, Sf, piv, K.c_psi, K.alpha, 1.0 / ((double)F.nx * F.ny), 0.0, st),
          "adjoint zpass_ch");
   HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, true, st), "adjoint ifft_y fine");
   RealSet<T> of;
@@ -778,6 +789,8 @@ int drpf_validate(const drpf_params* p) {
     return fail(DRPF_EINVAL, "viscoelastic drop needs Wi > 0 and beta in (0, 1]");
   if (!(p->constitutive == 0 || p->constitutive == 1)) return fail(DRPF_EINVAL, "constitutive must be 0 or 1");
   if (!(p->refine == 0 || p->refine == 1 || p->refine == 2)) return fail(DRPF_EINVAL, "refine must be 1 or 2");
+  if (!(p->advection == 0 || p->advection == 1)) return fail(DRPF_EINVAL, "advection must be 0 or 1");
+  if (!(p->d_w >= 0.0 && p->d_w < 1e30)) return fail(DRPF_EINVAL, "d_w must be finite and >= 0");
   if (p->constitutive == 1 && !p->viscoelastic)
     return fail(DRPF_EINVAL, "the log-conformation form needs viscoelastic");
   if (!(p->giesekus_alpha >= 0 && p->giesekus_alpha <= 0.5))
@@ -998,6 +1011,8 @@ int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes) {
   if (p->constitutive != 0 || p->giesekus_alpha != 0)
     return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
   if (p->refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
+  if (p->advection != 0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the central advection only");
+  if (p->d_w != 0.0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers static contact angles only");
   const Dims F = fine_dims(*p);
   const Dims C = make_dims(p->nx, p->ny, p->nz, p->lx, p->ly, p->lz);
   *bytes = adj_layout(F, C).total;
@@ -1010,6 +1025,8 @@ int drpf_adjoint_attach(drpf_grid* g, void* d_workspace, size_t bytes) {
   if (g->p.constitutive != 0 || g->p.giesekus_alpha != 0)
     return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
   if (g->p.refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
+  if (g->p.advection != 0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the central advection only");
+  if (g->p.d_w != 0.0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers static contact angles only");
   if (!d_workspace) return fail(DRPF_EWORKSPACE, "null adjoint workspace");
   if (((uintptr_t)d_workspace & 255) != 0) return fail(DRPF_EWORKSPACE, "adjoint workspace must be 256-byte aligned");
   const size_t need = adj_layout(g->F, g->C).total;
@@ -1026,6 +1043,8 @@ int drpf_adjoint_step(drpf_grid* g, const drpf_state* x, const drpf_state* x_nex
   if (g->p.constitutive != 0 || g->p.giesekus_alpha != 0)
     return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
   if (g->p.refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
+  if (g->p.advection != 0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the central advection only");
+  if (g->p.d_w != 0.0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers static contact angles only");
   if (!g->aws) return fail(DRPF_EINVAL, "no adjoint workspace attached");
   if (!x->phi[0] || !x->phi[1] || !x->u[0] || !x->u[1] || !x->v[0] || !x->v[1] || !x->w[0] || !x->w[1] ||
       !x->p[0] || !x->p[1])

@@ -103,6 +103,10 @@ struct StepConsts {
   double g_bot, g_top;                    // cos(theta) / (sqrt(2) Cn) at each wall
   double inv_re, inv_rho0, inv_wi;
   double giesekus;              // Giesekus mobility alpha (0: Oldroyd-B)
+  int advection;                // 0: second-order central flux, 1: WENO-Z (phase field, polymer)
+  // wall relaxation (eq. NS34 with D_w > 0): kappa = D_w gamma0 / dt; the wall ghost of phi
+  // then carries (kappa / hz)(phi_hat / gamma0 - phi^{n+1}). 0: static contact angle
+  double relax_kappa, inv_gamma0;
 };
 
 // Block shape of the 3D stencil launches: bx threads along x, by along y, one z layer per

@@ -21,7 +21,7 @@ template <typename T>
 struct Prolonged {
   const T *un, *unm1, *vn, *vnm1, *wn, *wnm1;
   int cnx, cny, cnz, ry, first;
-  int single;  // 1: single resolution (the phase field on the flow grid; uf etc. not used)
+  int single;  // 1: single resolution (the phase field on the flow grid: faces as they are)
   __device__ __forceinline__ T star(const T* a, const T* b, int idx) const {
     return first ? a[idx] : (T)2 * a[idx] - b[idx];
   }
@@ -30,11 +30,13 @@ struct Prolonged {
   }
   // fine x face I (at x = (I+1) hxf) of fine row (K, J)
   __device__ __forceinline__ T uf(int K, int J, int I) const {
+    if (single) return star(un, unm1, cidx(K, J, I));
     const int k = K >> 1, j = ry == 2 ? (J >> 1) : J, i = I >> 1;
     if (I & 1) return star(un, unm1, cidx(k, j, i));
     return (T)0.5 * (star(un, unm1, cidx(k, j, i - 1)) + star(un, unm1, cidx(k, j, i)));
   }
   __device__ __forceinline__ T vf(int K, int J, int I) const {
+    if (single) return star(vn, vnm1, cidx(K, J, I));
     const int k = K >> 1, i = I >> 1;
     if (ry == 1) return star(vn, vnm1, cidx(k, 0, i));
     const int j = J >> 1;
@@ -43,6 +45,7 @@ struct Prolonged {
   }
   // fine z face K (at z = (K+1) hzf), K in [-1, 2 cnz - 1]; walls are 0
   __device__ __forceinline__ T wf(int K, int J, int I) const {
+    if (single) return (K < 0 || K >= cnz - 1) ? (T)0 : star(wn, wnm1, cidx(K, J, I));
     if (K < 0 || K >= 2 * cnz - 1) return (T)0;
     const int k = K >> 1, j = ry == 2 ? (J >> 1) : J, i = I >> 1;
     if (K & 1) return star(wn, wnm1, cidx(k, j, i));

@@ -33,10 +33,11 @@ hipError_t launch_fft_y(const Dims& d, const Tables<T>& tb, cx<T>* spec, int nfi
 template <typename T>
 hipError_t launch_zpass_helmholtz(const Dims& d, const Tables<T>& tb, cx<T>* spec, double* piv,
                                   int bc, double coeff, double shift, double scale, hipStream_t st);
-// Cahn-Hilliard: (L - c_psi) then (L + alpha), both Neumann.
+// Cahn-Hilliard: (L - c_psi) then (L + alpha), both Neumann; with dwall != 0 the fused
+// operator gains L dW (dW: dwall on the two wall-adjacent rows), the relaxed walls of eq. NS34.
 template <typename T>
 hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, double* piv,
-                           double c_psi, double alpha, double scale, hipStream_t st);
+                           double c_psi, double alpha, double scale, double dwall, hipStream_t st);
 // Navier-Stokes: velocity Helmholtz x3, divergence, FP64 Poisson, correction.
 template <typename T>
 hipError_t launch_zpass_ns(const Dims& d, const Tables<T>& tb, cx<T>* spec4, double* piv,
@@ -48,7 +49,13 @@ struct ChIn {
   const T* phin;
   const T* phinm1;
   const T *un, *unm1, *vn, *vnm1, *wn, *wnm1;  // coarse faces
+  const T* adv;  // if not null: div(u phi*) precomputed (WENO-Z), fine cells
 };
+// div(u_f phi*) on the fine grid with WENO-Z face values (the advection of eq. NS25 in the
+// paper's scheme), into adv (fine cells).
+template <typename T>
+hipError_t launch_weno_adv_fine(const Dims& f, const Dims& c, const StepConsts& k, ChIn<T> in, T* adv,
+                                hipStream_t st);
 template <typename T>
 hipError_t launch_ch_rhs(const Dims& f, const Dims& c, const StepConsts& k, ChIn<T> in, T* rhs,
                          hipStream_t st);

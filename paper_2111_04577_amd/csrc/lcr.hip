@@ -13,9 +13,10 @@
 // and writes tau_p = (1 - beta)/Wi (c - I) (eq. NS46), formed as V diag(expm1(theta)) V^T.
 //
 // One thread per coarse cell. The per-cell eigensolve (cyclic Jacobi) and the source are FP64
-// in both precision forms; the advection is the stress form's central flux form with Neumann
-// walls and zero wall flux.
+// in both precision forms; the advection is the stress form's flux form (central, or WENO-Z
+// face values) with zero wall flux.
 #include "coarse.hpp"
+#include "weno.hpp"
 
 namespace drpf {
 
@@ -108,7 +109,7 @@ struct ThetaOut {
 // One stage: out = c0 Theta_n + c1 (Theta_in + dt RH(Theta_in)); LAST also writes tau_p from
 // the new Theta. Theta_n and out may be the same arrays (each thread reads Theta_n at its own
 // cell only; neighbours are read from Theta_in).
-template <typename T, bool LAST>
+template <typename T, bool LAST, bool WENO>
 __global__ void __launch_bounds__(kBlock)
     k_lcr_stage(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
                 ThetaSet<T> thn, ThetaSet<T> thin, ThetaOut<T> thout, ThetaOut<T> tauout, int nx,
@@ -170,17 +171,25 @@ __global__ void __launch_bounds__(kBlock)
   const T vyp = V.at(k, j, i), vym = V.at(k, j - 1, i);
   const T wzp = k < nz - 1 ? Wf.at(k, j, i) : (T)0, wzm = k > 0 ? Wf.at(k - 1, j, i) : (T)0;
   double out[6];
+  const WenoOffsets<T> wo(k, j, WENO ? i : 0, nx, ny, nz);
+  const NbrOffsets<T> no(k, j, i, nx, ny, nz);
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
-    const Coarse<T> t{thin.p[m], nx, ny, nz};
     const T t0 = (T)th6[m];
-    const T fxp = uxp * h * (t0 + t.at(k, j, i + 1));
-    const T fxm = uxm * h * (t.at(k, j, i - 1) + t0);
-    const T fyp = vyp * h * (t0 + t.at(k, j + 1, i));
-    const T fym = vym * h * (t.at(k, j - 1, i) + t0);
-    const T fzp = k < nz - 1 ? wzp * h * (t0 + t.at(k + 1, j, i)) : (T)0;
-    const T fzm = k > 0 ? wzm * h * (t.at(k - 1, j, i) + t0) : (T)0;
-    const double adv = -(double)((fxp - fxm) * ihx + (fyp - fym) * ihy + (fzp - fzm) * ihz);
+    double adv;
+    if (WENO) {
+      // WENO-Z face values, three cells either way, mirrored beyond the walls
+      adv = (double)wo.advection(thin.p[m], uxm, uxp, vym, vyp, wzm, wzp, ihx, ihy, ihz);
+    } else {
+      const T* q = thin.p[m];
+      const T fxp = uxp * h * (t0 + ld_at(q, no.xp));
+      const T fxm = uxm * h * (ld_at(q, no.xm) + t0);
+      const T fyp = vyp * h * (t0 + ld_at(q, no.yp));
+      const T fym = vym * h * (ld_at(q, no.ym) + t0);
+      const T fzp = k < nz - 1 ? wzp * h * (t0 + ld_at(q, no.zp)) : (T)0;
+      const T fzm = k > 0 ? wzm * h * (ld_at(q, no.zm) + t0) : (T)0;
+      adv = -(double)((fxp - fxm) * ihx + (fyp - fym) * ihy + (fzp - fzm) * ihz);
+    }
     const int a = pa[m], b = pb[m];
     const double src = RS[a][0] * R[b][0] + RS[a][1] * R[b][1] + RS[a][2] * R[b][2];
     out[m] = c0 * (double)thn.p[m][id] + c1 * (th6[m] + dt * (adv + src));
@@ -232,12 +241,16 @@ hipError_t launch_lcr_stage(const Dims& c, const StepConsts& k, const T* u, cons
   }
   const Launch3 L = launch3(c.nx, c.ny, c.nz);
   const double tau_scale = (1.0 - k.beta) / k.wi;
-  if (tau_out)
-    hipLaunchKernelGGL((k_lcr_stage<T, true>), L.grid, L.block, 0, st, u, v, w, tn, ti, to, ta, c.nx, c.ny,
-                       c.nz, (T)c.ihx, (T)c.ihy, (T)c.ihz, k.dt, k.inv_wi, k.giesekus, c0, c1, tau_scale);
-  else
-    hipLaunchKernelGGL((k_lcr_stage<T, false>), L.grid, L.block, 0, st, u, v, w, tn, ti, to, ta, c.nx, c.ny,
-                       c.nz, (T)c.ihx, (T)c.ihy, (T)c.ihz, k.dt, k.inv_wi, k.giesekus, c0, c1, tau_scale);
+#define DRPF_LCR(LAST, WENO)                                                                      \
+  hipLaunchKernelGGL((k_lcr_stage<T, LAST, WENO>), L.grid, L.block, 0, st, u, v, w, tn, ti, to, ta, c.nx, \
+                     c.ny, c.nz, (T)c.ihx, (T)c.ihy, (T)c.ihz, k.dt, k.inv_wi, k.giesekus, c0, c1,      \
+                     tau_scale)
+  if (k.advection == 1) {
+    if (tau_out) DRPF_LCR(true, true); else DRPF_LCR(false, true);
+  } else {
+    if (tau_out) DRPF_LCR(true, false); else DRPF_LCR(false, false);
+  }
+#undef DRPF_LCR
   return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@
 //                  (single resolution): G and phi at the cells, then face and edge means.
 //   prolong, restrict -- the standalone transfer operators (eqs. dual1, dual2).
 #include "fine.hpp"
+#include "weno.hpp"
 
 namespace drpf {
 
@@ -35,12 +36,13 @@ constexpr int kBlock = 256;
 // the column enters a new coarse layer. The 3D FP32 form is held to 64 registers, so that the
 // 8 blocks per CU of a 256 x 256 x 128 grid are resident at once. SR: single resolution (the
 // phase field on the flow grid; the face velocities are taken as they are).
-template <typename T, int R, bool SR>
+template <typename T, int R, int MODE, bool RELAX>
 __global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && R == 2 && !SR ? 8 : 4)))
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && R == 2 && MODE == 0 && !RELAX ? 8
+                                       : (RELAX && sizeof(T) == 8 ? 3 : 4))))
     k_ch_rhs(const T* __restrict__ phin, const T* __restrict__ phinm1, Prolonged<T> pv,
-             T* __restrict__ out, int nx, int ny, int nz, int KB, T ihx, T ihy, T ihz,
-             StepConsts c) {
+             T* __restrict__ out, const T* __restrict__ advp, int nx, int ny, int nz, int KB, T ihx,
+             T ihy, T ihz, StepConsts c) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int TX = blockDim.x, TY = blockDim.y;
   int bx, by, bz;
@@ -95,7 +97,8 @@ __global__ void __launch_bounds__(kBlock)
   };
   // coarse column of this fine column (eq. dual1); with a single resolution the column itself
   const int ry = pv.ry;
-  constexpr bool sr = SR;  // single resolution (pv.single)
+  constexpr bool sr = MODE == 1;   // single resolution (pv.single)
+  constexpr bool pre = MODE == 2;  // advection given (WENO-Z), no velocities needed
   const bool vy = pv.cny > 1;
   const int ic = sr ? I : (I >> 1), icw = wrap(ic - 1, pv.cnx);
   const int jc = ry == 2 ? (J >> 1) : J, jcw = vy ? wrap(jc - 1, pv.cny) : 0;
@@ -123,6 +126,12 @@ __global__ void __launch_bounds__(kBlock)
   };
   const T ihx2 = ihx * ihx, ihy2 = ihy * ihy, ihz2 = ihz * ihz, h = (T)0.5;
   const T gb = (T)c.g_bot * ihz, gt = (T)c.g_top * ihz;
+  constexpr bool relax = RELAX;  // relaxed walls (eq. NS34 with D_w > 0)
+  const T kg = RELAX ? (T)(c.relax_kappa * c.inv_gamma0) * ihz : (T)0;
+  auto phat_at = [&](int Kl, int Jl, int Il) -> T {
+    const int id = (Kl * ny + wrap(Jl, ny)) * nx + wrap(Il, nx);
+    return first ? phin[id] : (T)2 * phin[id] - (T)0.5 * phinm1[id];
+  };
   T ta[R], tb[R];
   int sm = 0, s0 = 1, sp = 2;
   load_tile(K0 - 1, ta, tb);
@@ -135,7 +144,7 @@ __global__ void __launch_bounds__(kBlock)
   int kcur = -1;
   for (int K = K0; K < K0 + KB; ++K) {
     const int k = sr ? K : (K >> 1);
-    if (k != kcur) {
+    if (!pre && k != kcur) {
       kcur = k;
       T vn[6], vm[6], s[6];
       load_vel(k, vn, vm);
@@ -181,26 +190,33 @@ __global__ void __launch_bounds__(kBlock)
     const T w0 = W0[c0];
     const T lapw = (W0[c0 + 1] - 2 * w0 + W0[c0 - 1]) * ihx2 + (W0[c0 + HX] - 2 * w0 + W0[c0 - HX]) * ihy2 +
                    (sW[sp * HP + c0] - 2 * w0 + sW[sm * HP + c0]) * ihz2;
-    const T adv = (ufp * h * (p0 + pxp) - ufm * h * (pxm + p0)) * ihx +
+    const T adv = pre ? ld_at(advp + K * layer, cid) :
+                        (ufp * h * (p0 + pxp) - ufm * h * (pxm + p0)) * ihx +
                   (vfp * h * (p0 + pyp) - vfm * h * (pym + p0)) * ihy +
                   (wfp * h * (p0 + pzp) - wfm * h * (pzm + p0)) * ihz;
-    // wetting data b = g(phi*) / hz on the wall-adjacent layers, and L_N b
-    auto bval = [&](int kk, T p) -> T {
+    // wetting data b = g(phi*) / hz on the wall-adjacent layers, and L_N b; relaxed walls
+    // (eq. NS34, D_w > 0) add (kappa / hz) phi_hat / gamma0 to it, phi_hat read on those
+    // layers only
+    auto bval = [&](int kk, T p, T ph) -> T {
       T b = 0;
       if (kk == 0) b += gb * ((T)1 - p * p);
       if (kk == nz - 1) b += gt * ((T)1 - p * p);
+      if (RELAX && (kk == 0 || kk == nz - 1)) b += kg * ph;
       return b;
     };
     T lapb = 0;
     if (K == 0 || K == nz - 1) {
-      const T b0 = bval(K, p0);
-      lapb = (bval(K, pxp) - 2 * b0 + bval(K, pxm)) * ihx2 + (bval(K, pyp) - 2 * b0 + bval(K, pym)) * ihy2;
-      const T bup = K + 1 < nz ? bval(K + 1, pzp) : b0;
-      const T bdn = K > 0 ? bval(K - 1, pzm) : b0;
+      const T b0 = bval(K, p0, relax ? phat_at(K, J, I) : (T)0);
+      lapb = (bval(K, pxp, relax ? phat_at(K, J, I + 1) : (T)0) - 2 * b0 +
+              bval(K, pxm, relax ? phat_at(K, J, I - 1) : (T)0)) * ihx2 +
+             (bval(K, pyp, relax ? phat_at(K, J + 1, I) : (T)0) - 2 * b0 +
+              bval(K, pym, relax ? phat_at(K, J - 1, I) : (T)0)) * ihy2;
+      const T bup = K + 1 < nz ? bval(K + 1, pzp, (T)0) : b0;
+      const T bdn = K > 0 ? bval(K - 1, pzm, (T)0) : b0;
       lapb += (bup - 2 * b0 + bdn) * ihz2;
     } else {
-      if (K == 1) lapb += bval(0, pzm) * ihz2;
-      if (K == nz - 2) lapb += bval(nz - 1, pzp) * ihz2;
+      if (K == 1) lapb += bval(0, pzm, relax ? phat_at(0, J, I) : (T)0) * ihz2;
+      if (K == nz - 2) lapb += bval(nz - 1, pzp, relax ? phat_at(nz - 1, J, I) : (T)0) * ihz2;
     }
     const T q = (T)c.pe_cn2 * (phat * (T)c.inv_dt - adv) + lapw;
     st_at(out + K * layer, cid, q - lapb);
@@ -223,7 +239,7 @@ __global__ void __launch_bounds__(kBlock)
 // in-layer offsets are computed once); the global loads of the layers that the next step
 // needs are issued one step ahead into registers, so that they are in flight while the
 // block evaluates G and forms the next sums.
-template <typename T, int R>
+template <typename T, int R, bool RELAX>
 __global__ void __launch_bounds__(kBlock)
     k_restrict_g(const T* __restrict__ phinew, const T* __restrict__ phin,
                  const T* __restrict__ phinm1, Restricted<T> r, int fnx, int fny, int fnz,
@@ -250,6 +266,9 @@ __global__ void __launch_bounds__(kBlock)
   const T ihx2 = fihx * fihx, ihy2 = fihy * fihy, ihz2 = fihz * fihz;
   const T cn2 = (T)c.cn2, S = (T)c.S;
   const T gb = (T)c.g_bot * fihz, gt = (T)c.g_top * fihz;
+  constexpr bool relax = RELAX;  // relaxed walls (eq. NS34 with D_w > 0)
+  const T kk = RELAX ? (T)c.relax_kappa * fihz : (T)0;
+  const T kg = RELAX ? (T)(c.relax_kappa * c.inv_gamma0) * fihz : (T)0;
   const size_t layer = (size_t)fny * fnx;
   auto kc = [&](int Kf) { return min(max(Kf, 0), fnz - 1); };
   // per-thread tile points: in-layer byte offsets of the phi tile (with halo) and of the G
@@ -309,6 +328,12 @@ __global__ void __launch_bounds__(kBlock)
         T b = 0;
         if (K == 0) b += gb * ((T)1 - ps * ps);
         if (K == fnz - 1) b += gt * ((T)1 - ps * ps);
+        if (relax && (K == 0 || K == fnz - 1)) {
+          // relaxed walls: (kappa / hz)(phi_hat / gamma0 - phi^{n+1}) in the wall ghost
+          const T an = ld_at(phin + K * layer, gOff[q]);
+          const T ph = first ? an : (T)2 * an - (T)0.5 * ld_at(phinm1 + K * layer, gOff[q]);
+          b += kg * ph - kk * p;
+        }
         *(e < GP ? dst + e : sX + (e - GP)) = -cn2 * (lap + b) + S * (p - ps) + ps * ps * ps - ps;
       }
     }
@@ -436,6 +461,37 @@ __global__ void __launch_bounds__(kBlock)
     }
   }
 }
+// div(u_f phi*) on the fine grid with WENO-Z face values (eq. NS25's advection in the paper's
+// scheme): one thread per fine cell, phi* = 2 phi^n - phi^{n-1} (phi^n on the first step)
+// read at the cell and three cells either way along each axis (mirrored beyond the walls),
+// face velocities prolonged on the fly (eq. dual1; as they are at a single resolution).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_weno_adv_fine(const T* __restrict__ phin, const T* __restrict__ phinm1, Prolonged<T> pv,
+                    T* __restrict__ adv, int nx, int ny, int nz, T ihx, T ihy, T ihz) {
+  int bx, by, bz;
+  xcd_tile(bx, by, bz);
+  const int I = bx * blockDim.x + threadIdx.x, J = by * blockDim.y + threadIdx.y, K = bz;
+  const bool first = pv.first != 0;
+  auto ps = [&](int kk, int jj, int ii) {
+    const int id = (kk * ny + wrap(jj, ny)) * nx + wrap(ii, nx);
+    const T a = phin[id];
+    return first ? a : (T)2 * a - phinm1[id];
+  };
+  T vx[7], vy[7], vz[7];
+#pragma unroll
+  for (int d = -3; d <= 3; ++d) {
+    vx[d + 3] = ps(K, J, I + d);
+    vy[d + 3] = ps(K, J + d, I);
+    vz[d + 3] = ps(mirror_index(K + d, nz), J, I);
+  }
+  const T dx = weno_div1(vx, pv.uf(K, J, I - 1), pv.uf(K, J, I));
+  const T dy = weno_div1(vy, pv.vf(K, J - 1, I), pv.vf(K, J, I));
+  // the wall faces (K = -1 and the top face of the last layer) carry no flux
+  const T dz = weno_div1(vz, pv.wf(K - 1, J, I), pv.wf(K, J, I));
+  adv[(K * ny + J) * nx + I] = dx * ihx + dy * ihy + dz * ihz;
+}
+
 // Single resolution (the phase field on the flow grid): chemical potential G^{n+1} (the
 // bracket of eq. NS25 times the mixing energy, as restrict_g) and phi at the cells.
 template <typename T>
@@ -459,6 +515,11 @@ __global__ void __launch_bounds__(kBlock)
   T b = 0;
   if (k == 0) b += (T)c.g_bot * ihz * ((T)1 - ps * ps);
   if (k == nz - 1) b += (T)c.g_top * ihz * ((T)1 - ps * ps);
+  if (c.relax_kappa != 0.0 && (k == 0 || k == nz - 1)) {
+    // relaxed walls: (kappa / hz)(phi_hat / gamma0 - phi^{n+1}) in the wall ghost
+    const T ph = c.first ? an : (T)2 * an - (T)0.5 * phinm1[id];
+    b += (T)(c.relax_kappa * c.inv_gamma0) * ihz * ph - (T)c.relax_kappa * ihz * p;
+  }
   r.G_c[id] = -(T)c.cn2 * (lap + b) + (T)c.S * (p - ps) + ps * ps * ps - ps;
   r.phi_c[id] = p;
 }
@@ -575,14 +636,22 @@ hipError_t launch_ch_rhs(const Dims& f, const Dims& c, const StepConsts& k, ChIn
   if (need > 4) return hipErrorInvalidConfiguration;
   const size_t shm = (size_t)6 * HP * sizeof(T);
   const dim3 grid(f.nx / TX, f.ny / TY, f.nz / KB), block(TX, TY, 1);
-#define DRPF_CH(R, SR)                                                                          \
-  hipLaunchKernelGGL((k_ch_rhs<T, R, SR>), grid, block, shm, st, in.phin, in.phinm1, pv, rhs, f.nx, \
-                     f.ny, f.nz, KB, (T)f.ihx, (T)f.ihy, (T)f.ihz, k)
-  if (single) {
-    if (need <= 2) DRPF_CH(2, true); else DRPF_CH(4, true);
+#define DRPF_CH(R, MODE, RELAX)                                                                  \
+  hipLaunchKernelGGL((k_ch_rhs<T, R, MODE, RELAX>), grid, block, shm, st, in.phin, in.phinm1, pv,   \
+                     rhs, in.adv, f.nx, f.ny, f.nz, KB, (T)f.ihx, (T)f.ihy, (T)f.ihz, k)
+#define DRPF_CH_R(MODE, RELAX)      \
+  if (need <= 2)                    \
+    DRPF_CH(2, MODE, RELAX);        \
+  else                              \
+    DRPF_CH(4, MODE, RELAX)
+  // mode: 0 dual resolution, 1 single resolution, 2 advection given
+  const int mode = in.adv ? 2 : (single ? 1 : 0);
+  if (k.relax_kappa != 0.0) {
+    if (mode == 2) { DRPF_CH_R(2, true); } else if (mode == 1) { DRPF_CH_R(1, true); } else { DRPF_CH_R(0, true); }
   } else {
-    if (need <= 2) DRPF_CH(2, false); else DRPF_CH(4, false);
+    if (mode == 2) { DRPF_CH_R(2, false); } else if (mode == 1) { DRPF_CH_R(1, false); } else { DRPF_CH_R(0, false); }
   }
+#undef DRPF_CH_R
 #undef DRPF_CH
   return hipGetLastError();
 }
@@ -615,10 +684,23 @@ hipError_t launch_restrict_g(const Dims& f, const Dims& c, const StepConsts& k, 
     hipLaunchKernelGGL(kernel, grid, block, shm, st, phinew, phin, phinm1, r, f.nx, f.ny, f.nz, (T)f.ihx,
                        (T)f.ihy, (T)f.ihz, c.nx, c.ny, c.nz, ry, KB, k);
   };
-  if (Rk == 3)
-    go(k_restrict_g<T, 3>);
-  else
-    go(k_restrict_g<T, 6>);
+  if (k.relax_kappa != 0.0) {
+    if (Rk == 3) go(k_restrict_g<T, 3, true>); else go(k_restrict_g<T, 6, true>);
+  } else {
+    if (Rk == 3) go(k_restrict_g<T, 3, false>); else go(k_restrict_g<T, 6, false>);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_weno_adv_fine(const Dims& f, const Dims& c, const StepConsts& k, ChIn<T> in, T* adv,
+                                hipStream_t st) {
+  const int single = f.nx == c.nx ? 1 : 0;
+  Prolonged<T> pv{in.un, in.unm1, in.vn, in.vnm1, in.wn, in.wnm1, c.nx, c.ny, c.nz,
+                  (c.ny == 1 || single) ? 1 : 2, k.first, single};
+  const Launch3 L = launch3(f.nx, f.ny, f.nz);
+  hipLaunchKernelGGL(k_weno_adv_fine<T>, L.grid, L.block, 0, st, in.phin, in.phinm1, pv, adv, f.nx, f.ny,
+                     f.nz, (T)f.ihx, (T)f.ihy, (T)f.ihz);
   return hipGetLastError();
 }
 
@@ -672,7 +754,9 @@ hipError_t launch_restrict(const Dims& f, const Dims& c, const T* fine, T* coars
                                         T*, T*, T*, hipStream_t);                                 \
   template hipError_t launch_restrict<T>(const Dims&, const Dims&, const T*, T*, int, hipStream_t); \
   template hipError_t launch_props_single<T>(const Dims&, const StepConsts&, const T*, const T*,   \
-                                             const T*, Restricted<T>, hipStream_t);
+                                             const T*, Restricted<T>, hipStream_t);               \
+  template hipError_t launch_weno_adv_fine<T>(const Dims&, const Dims&, const StepConsts&, ChIn<T>,  \
+                                              T*, hipStream_t);
 INST(double)
 INST(float)
 #undef INST

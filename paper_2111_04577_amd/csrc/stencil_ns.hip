@@ -13,13 +13,15 @@
 //                     z-marching pass (polymer_div).
 //   polymer_stage  -- one stage of the second-order TVD Runge-Kutta update of the polymer
 //                     stress (eqs. NS42, NS44) in stress form: the Giesekus law, with
-//                     -alpha/(1 - beta) tau.tau (alpha = 0: Oldroyd-B).
+//                     -alpha/(1 - beta) tau.tau (alpha = 0: Oldroyd-B); central or WENO-Z
+//                     advection.
 //
 // Staggering: u[k][j][i] at ((i+1) hx, (j+.5) hy, (k+.5) hz), v at (i+.5, j+1, k+.5),
 // w at (i+.5, j+.5, k+1) with w[nz-1] the top wall; centres at (i+.5, j+.5, k+.5).
 // Wall rules: no-slip ghost = -adjacent for u, v; w = 0 on the walls; Neumann ghost for
 // centred scalars (G, tau). Arithmetic in the storage type T.
 #include "coarse.hpp"
+#include "weno.hpp"
 
 namespace drpf {
 
@@ -309,7 +311,7 @@ struct TauOut {
   T* p[6];
 };
 
-template <typename T>
+template <typename T, bool WENO>
 __global__ void __launch_bounds__(kBlock)
     k_polymer_stage(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
                     TauSet<T> tn, TauSet<T> tin, TauOut<T> tout, int nx, int ny, int nz, T ihx,
@@ -332,18 +334,26 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
   for (int m = 0; m < 6; ++m) tau[m] = tin.p[m][id];
   const int pairs[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+  const WenoOffsets<T> wo(k, j, WENO ? i : 0, nx, ny, nz);
+  const NbrOffsets<T> no(k, j, i, nx, ny, nz);
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
     const int a = pairs[m][0], b = pairs[m][1];
-    const Coarse<T> t{tin.p[m], nx, ny, nz};
     const T t0 = tau[m];
-    const T fxp = uxp * h * (t0 + t.at(k, j, i + 1));
-    const T fxm = uxm * h * (t.at(k, j, i - 1) + t0);
-    const T fyp = vyp * h * (t0 + t.at(k, j + 1, i));
-    const T fym = vym * h * (t.at(k, j - 1, i) + t0);
-    const T fzp = k < nz - 1 ? wzp * h * (t0 + t.at(k + 1, j, i)) : (T)0;
-    const T fzm = k > 0 ? wzm * h * (t.at(k - 1, j, i) + t0) : (T)0;
-    T rh = -((fxp - fxm) * ihx + (fyp - fym) * ihy + (fzp - fzm) * ihz);
+    T rh;
+    if (WENO) {
+      // WENO-Z face values, three cells either way, mirrored beyond the walls
+      rh = wo.advection(tin.p[m], uxm, uxp, vym, vyp, wzm, wzp, ihx, ihy, ihz);
+    } else {
+      const T* q = tin.p[m];
+      const T fxp = uxp * h * (t0 + ld_at(q, no.xp));
+      const T fxm = uxm * h * (ld_at(q, no.xm) + t0);
+      const T fyp = vyp * h * (t0 + ld_at(q, no.yp));
+      const T fym = vym * h * (ld_at(q, no.ym) + t0);
+      const T fzp = k < nz - 1 ? wzp * h * (t0 + ld_at(q, no.zp)) : (T)0;
+      const T fzm = k > 0 ? wzm * h * (ld_at(q, no.zm) + t0) : (T)0;
+      rh = -((fxp - fxm) * ihx + (fyp - fym) * ihy + (fzp - fzm) * ihz);
+    }
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) rh += L[cc][a] * tau[tidx(cc, b)] + tau[tidx(a, cc)] * L[cc][b];
     rh += (one_m_beta * (L[a][b] + L[b][a]) - t0) * inv_wi;
@@ -415,9 +425,15 @@ hipError_t launch_polymer_stage(const Dims& c, const StepConsts& k, const T* u, 
     to.p[m] = tau_out[m];
   }
   const Launch3 L = launch3(c.nx, c.ny, c.nz);
-  hipLaunchKernelGGL(k_polymer_stage<T>, L.grid, L.block, 0, st, u, v, w, tn, ti, to, c.nx, c.ny, c.nz,
-                     (T)c.ihx, (T)c.ihy, (T)c.ihz, (T)k.dt, (T)k.inv_wi, (T)(1.0 - k.beta),
-                     (T)(k.giesekus == 0.0 ? 0.0 : k.giesekus / (1.0 - k.beta)), (T)c0, (T)c1);
+  const T gk = (T)(k.giesekus == 0.0 ? 0.0 : k.giesekus / (1.0 - k.beta));
+  if (k.advection == 1)
+    hipLaunchKernelGGL((k_polymer_stage<T, true>), L.grid, L.block, 0, st, u, v, w, tn, ti, to, c.nx, c.ny,
+                       c.nz, (T)c.ihx, (T)c.ihy, (T)c.ihz, (T)k.dt, (T)k.inv_wi, (T)(1.0 - k.beta), gk, (T)c0,
+                       (T)c1);
+  else
+    hipLaunchKernelGGL((k_polymer_stage<T, false>), L.grid, L.block, 0, st, u, v, w, tn, ti, to, c.nx, c.ny,
+                       c.nz, (T)c.ihx, (T)c.ihy, (T)c.ihz, (T)k.dt, (T)k.inv_wi, (T)(1.0 - k.beta), gk, (T)c0,
+                       (T)c1);
   return hipGetLastError();
 }
 

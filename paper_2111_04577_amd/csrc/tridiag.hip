@@ -178,12 +178,12 @@ __global__ void __launch_bounds__(1024)
 // FFT in LDS (Makhoul's even/odd reordering with a quarter-wave twiddle); the data are
 // complex (x/y spectral coefficients), so the real and imaginary sequences are separated
 // from the pair (V_m, V_{nz-m}). A block holds TL consecutive modes, columns in LDS.
-template <typename T>
+template <typename T, bool ROBIN>
 __global__ void __launch_bounds__(1024)
     k_zpass_ch(cx<T>* __restrict__ S, int P, int Ny, int Nz, int logNz, int TL,
                const double* __restrict__ lamx, const double* __restrict__ lamy,
                const double* __restrict__ lamz, const cx<T>* __restrict__ twz,
-               const cx<T>* __restrict__ twq, double c_psi, double alpha, double scale) {
+               const cx<T>* __restrict__ twq, double c_psi, double alpha, double scale, double dwall) {
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem);  // [position][mode]
   cx<T>* stw = buf + Nz * TL;                    // twiddles of the length-Nz transform
@@ -202,36 +202,125 @@ __global__ void __launch_bounds__(1024)
   lds_fft<T, false, true>(buf, Nz, logNz, TL, ltl, stw);
   const int half = Nz >> 1;
   const T hf = (T)0.5;
-  for (int e = threadIdx.x; e < (half + 1) * TL; e += blockDim.x) {
-    const int m = e >> ltl, t = e & (TL - 1);
-    const int l = min(l0 + t, lines - 1);
-    int ky, kx;
-    spec_mode(l, P, Ny, ky, kx);
-    // the eigenvalue factors in the storage type: lambda <= 0, alpha < 0 < c_psi, so neither
-    // factor cancels
-    const T lxy = (T)(lamx[kx] + lamy[ky]);
-    const int mr = (Nz - m) & (Nz - 1);  // partner N - m (0 and N/2 pair with themselves)
-    const cx<T> Vm = buf[m * TL + t], Vr = buf[mr * TL + t];
-    // forward DCT-II coefficient from (V_m, V_{N-m}): X = Re(w A) + i Re(w B),
-    // A = (V_m + conj V_{N-m}) / 2, B = (V_m - conj V_{N-m}) / (2i)
-    auto dct_out = [&](cx<T> V, cx<T> Vp, cx<T> w) -> cx<T> {
-      const cx<T> A = hf * (V + conj(Vp));
-      const cx<T> B = hf * mul_mi(V - conj(Vp));
-      return mk<T>((w * A).re, (w * B).re);
-    };
-    const T cp = (T)c_psi, al = (T)alpha, sc = (T)scale;
-    const T lm = lxy + (T)lamz[m];
-    const cx<T> Fm = (sc / ((lm - cp) * (lm + al))) * dct_out(Vm, Vr, twq[m]);
-    // inverse: Y_m = conj(w_m) [(P_m + Q_{N-m}) + i (Q_m - P_{N-m})], X_N = 0
+  const T cp = (T)c_psi, al = (T)alpha, sc = (T)scale;
+  // forward DCT-II coefficient from (V_m, V_{N-m}): X = Re(w A) + i Re(w B),
+  // A = (V_m + conj V_{N-m}) / 2, B = (V_m - conj V_{N-m}) / (2i)
+  auto dct_out = [&](cx<T> V, cx<T> Vp, cx<T> w) -> cx<T> {
+    const cx<T> A = hf * (V + conj(Vp));
+    const cx<T> B = hf * mul_mi(V - conj(Vp));
+    return mk<T>((w * A).re, (w * B).re);
+  };
+  // inverse: Y_m = conj(w_m) [(P_m + Q_{N-m}) + i (Q_m - P_{N-m})], X_N = 0
+  auto inverse_in = [&](int m, int mr, int t, cx<T> Fm, cx<T> Fr) {
     if (mr != m) {
-      const T lr = lxy + (T)lamz[mr];
-      const cx<T> Fr = (sc / ((lr - cp) * (lr + al))) * dct_out(Vr, Vm, twq[mr]);
       buf[m * TL + t] = conj(twq[m]) * mk<T>(Fm.re + Fr.im, Fm.im - Fr.re);
       buf[mr * TL + t] = conj(twq[mr]) * mk<T>(Fr.re + Fm.im, Fr.im - Fm.re);
     } else if (m == 0) {
       buf[t] = Fm;
     } else {
       buf[m * TL + t] = conj(twq[m]) * mk<T>(Fm.re + Fm.im, Fm.im - Fm.re);
+    }
+  };
+  if (!ROBIN) {
+    for (int e = threadIdx.x; e < (half + 1) * TL; e += blockDim.x) {
+      const int m = e >> ltl, t = e & (TL - 1);
+      const int l = min(l0 + t, lines - 1);
+      int ky, kx;
+      spec_mode(l, P, Ny, ky, kx);
+      // the eigenvalue factors in the storage type: lambda <= 0, alpha < 0 < c_psi, so neither
+      // factor cancels
+      const T lxy = (T)(lamx[kx] + lamy[ky]);
+      const int mr = (Nz - m) & (Nz - 1);  // partner N - m (0 and N/2 pair with themselves)
+      const cx<T> Vm = buf[m * TL + t], Vr = buf[mr * TL + t];
+      const T lm = lxy + (T)lamz[m];
+      const cx<T> Fm = (sc / ((lm - cp) * (lm + al))) * dct_out(Vm, Vr, twq[m]);
+      cx<T> Fr = Fm;
+      if (mr != m) {
+        const T lr = lxy + (T)lamz[mr];
+        Fr = (sc / ((lr - cp) * (lr + al))) * dct_out(Vr, Vm, twq[mr]);
+      }
+      inverse_in(m, mr, t, Fm, Fr);
+    }
+  } else {
+    // Relaxed walls (eq. NS34 with D_w > 0): the operator is (L - c_psi)(L + alpha) + L dW,
+    // d = dwall on the two wall-adjacent rows, a rank-two change of the Neumann product that
+    // the DCT diagonalises. With F0 = X / A (A = (lambda - c_psi)(lambda + alpha), X the DCT
+    // of the right-hand side, both scaled) the solution is F_m = F0_m - G_m s_m, G_m = d
+    // lambda_m c_m / (N A_m), c_m = cos(pi m / 2N) = (row 0 of the DCT basis), s_m the sum
+    // (m even) or difference (m odd) of the two wall values; since the inverse transform is
+    // x_k = sum_m W_m F_m cos(pi m (k + 1/2) / N), W = (1, 2, 2, ...), the sum and difference
+    // solve sigma = P_e / (1 + H_e), delta = P_o / (1 + H_o) with P = 2 sum W c F0 and
+    // H = 2 sum W c G over even or odd m. H >= 0 (d < 0, lambda <= 0, A > 0).
+    for (int e = threadIdx.x; e < (half + 1) * TL; e += blockDim.x) {
+      const int m = e >> ltl, t = e & (TL - 1);
+      const int l = min(l0 + t, lines - 1);
+      int ky, kx;
+      spec_mode(l, P, Ny, ky, kx);
+      const T lxy = (T)(lamx[kx] + lamy[ky]);
+      const int mr = (Nz - m) & (Nz - 1);
+      const cx<T> Vm = buf[m * TL + t], Vr = buf[mr * TL + t];
+      const T lm = lxy + (T)lamz[m];
+      buf[m * TL + t] = (sc / ((lm - cp) * (lm + al))) * dct_out(Vm, Vr, twq[m]);
+      if (mr != m) {
+        const T lr = lxy + (T)lamz[mr];
+        buf[mr * TL + t] = (sc / ((lr - cp) * (lr + al))) * dct_out(Vr, Vm, twq[mr]);
+      }
+    }
+    __syncthreads();
+    // partial sums over m = ch, ch + NC, ... per mode, then their totals
+    const int NC = min((int)(blockDim.x >> ltl), 16);
+    // after the twiddles, rounded up to 16 bytes: the wall sums [TL][2], then the partials
+    const size_t so = ((size_t)(Nz * TL + Nz) * sizeof(cx<T>) + 15) & ~(size_t)15;
+    cx<double>* sd = reinterpret_cast<cx<double>*>(smem + so);
+    double* part = reinterpret_cast<double*>(sd + 2 * TL);  // [NC][TL][6]
+    auto g_of = [&](int m, double lxy) {
+      const double lm = lxy + lamz[m];
+      return dwall * lm * (double)twq[m].re / ((double)Nz * (lm - c_psi) * (lm + alpha));
+    };
+    for (int e = threadIdx.x; e < NC * TL; e += blockDim.x) {
+      const int t = e & (TL - 1), ch = e >> ltl;
+      const int l = min(l0 + t, lines - 1);
+      int ky, kx;
+      spec_mode(l, P, Ny, ky, kx);
+      const double lxy = lamx[kx] + lamy[ky];
+      double acc[6] = {0, 0, 0, 0, 0, 0};  // P_e (re, im), P_o (re, im), H_e, H_o
+      for (int m = ch; m < Nz; m += NC) {
+        const double wc = (m == 0 ? 2.0 : 4.0) * (double)twq[m].re;
+        const cx<T> F = buf[m * TL + t];
+        const int o = (m & 1) * 2;
+        acc[o] += wc * (double)F.re;
+        acc[o + 1] += wc * (double)F.im;
+        acc[4 + (m & 1)] += wc * g_of(m, lxy);
+      }
+#pragma unroll
+      for (int q = 0; q < 6; ++q) part[(ch * TL + t) * 6 + q] = acc[q];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < TL; t += blockDim.x) {
+      double a[6] = {0, 0, 0, 0, 0, 0};
+      for (int ch = 0; ch < NC; ++ch)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) a[q] += part[(ch * TL + t) * 6 + q];
+      sd[2 * t] = mk<double>(a[0] / (1.0 + a[4]), a[1] / (1.0 + a[4]));      // sigma
+      sd[2 * t + 1] = mk<double>(a[2] / (1.0 + a[5]), a[3] / (1.0 + a[5]));  // delta
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < (half + 1) * TL; e += blockDim.x) {
+      const int m = e >> ltl, t = e & (TL - 1);
+      const int l = min(l0 + t, lines - 1);
+      int ky, kx;
+      spec_mode(l, P, Ny, ky, kx);
+      const double lxy = lamx[kx] + lamy[ky];
+      const int mr = (Nz - m) & (Nz - 1);
+      auto corrected = [&](int mm) -> cx<T> {
+        const cx<T> F = buf[mm * TL + t];
+        const cx<double> s = sd[2 * t + (mm & 1)];
+        const double g = g_of(mm, lxy);
+        return mk<T>((T)((double)F.re - g * s.re), (T)((double)F.im - g * s.im));
+      };
+      const cx<T> Fm = corrected(m);
+      const cx<T> Fr = mr != m ? corrected(mr) : Fm;
+      inverse_in(m, mr, t, Fm, Fr);
     }
   }
   __syncthreads();
@@ -475,7 +564,7 @@ hipError_t launch_zpass_helmholtz(const Dims& d, const Tables<T>& tb, cx<T>* spe
 
 template <typename T>
 hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, double* piv,
-                           double c_psi, double alpha, double scale, hipStream_t st) {
+                           double c_psi, double alpha, double scale, double dwall, hipStream_t st) {
   (void)piv;
   // tiles of 128 bytes per row (16 complex FP32 or 8 complex FP64 modes): one cache line
   int TL = (int)(128 / sizeof(cx<T>));
@@ -487,11 +576,20 @@ hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, doub
   const int lines = d.lines();
   int lognz = 0;
   while ((1 << lognz) < d.nz) ++lognz;
-  const size_t shm = (size_t)d.nz * (TL + 1) * sizeof(cx<T>);
+  size_t shm = (size_t)d.nz * (TL + 1) * sizeof(cx<T>);
   // the inverse transforms are unnormalised: fold 1/nz into the spectral scale
-  hipLaunchKernelGGL(k_zpass_ch<T>, dim3((lines + TL - 1) / TL), dim3(threads), shm, st, spec, d.pitch,
-                     d.ny, d.nz, lognz, TL, tb.lam_x, tb.lam_y, tb.lam_z, tb.tw_z, tb.tw_zq, c_psi, alpha,
-                     scale / d.nz);
+  if (dwall == 0.0) {
+    hipLaunchKernelGGL((k_zpass_ch<T, false>), dim3((lines + TL - 1) / TL), dim3(threads), shm, st, spec,
+                       d.pitch, d.ny, d.nz, lognz, TL, tb.lam_x, tb.lam_y, tb.lam_z, tb.tw_z, tb.tw_zq, c_psi,
+                       alpha, scale / d.nz, 0.0);
+  } else {
+    // relaxed walls: partial sums (at most 16 per mode, 6 doubles each) and the wall sums
+    const int nc = (threads / TL) < 16 ? threads / TL : 16;
+    shm = ((shm + 15) & ~(size_t)15) + (size_t)2 * TL * sizeof(cx<double>) + (size_t)6 * nc * TL * sizeof(double);
+    hipLaunchKernelGGL((k_zpass_ch<T, true>), dim3((lines + TL - 1) / TL), dim3(threads), shm, st, spec,
+                       d.pitch, d.ny, d.nz, lognz, TL, tb.lam_x, tb.lam_y, tb.lam_z, tb.tw_z, tb.tw_zq, c_psi,
+                       alpha, scale / d.nz, dwall);
+  }
   return hipGetLastError();
 }
 
@@ -525,7 +623,7 @@ hipError_t launch_zpass_ns_adj(const Dims& d, const Tables<double>& tb, cx<doubl
   template hipError_t launch_zpass_helmholtz<T>(const Dims&, const Tables<T>&, cx<T>*, double*,  \
                                                 int, double, double, double, hipStream_t);       \
   template hipError_t launch_zpass_ch<T>(const Dims&, const Tables<T>&, cx<T>*, double*, double, \
-                                         double, double, hipStream_t);                           \
+                                         double, double, double, hipStream_t);                   \
   template hipError_t launch_zpass_ns<T>(const Dims&, const Tables<T>&, cx<T>*, double*,         \
                                          const StepConsts&, double, hipStream_t);
 INST(double)

@@ -99,6 +99,31 @@ def test_validation_polymer_forms():
     assert f.value == c.value
 
 
+def test_validation_advection_scheme():
+    """advection 0 (central) or 1 (WENO-Z); the adjoint covers the central form only."""
+    B = _lib()
+    L = B.lib()
+    for a, rc in ((2, B.DRPF_EINVAL), (-1, B.DRPF_EINVAL), (0, B.DRPF_OK), (1, B.DRPF_OK)):
+        p = _params(advection=a)
+        assert L.drpf_validate(ctypes.byref(p)) == rc, a
+    nb = ctypes.c_size_t()
+    p = _params(advection=1)
+    assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_EUNSUPPORTED
+
+
+def test_validation_wall_relaxation():
+    """d_w >= 0 and finite; the adjoint covers static contact angles only."""
+    B = _lib()
+    L = B.lib()
+    for d, rc in ((-0.1, B.DRPF_EINVAL), (float("inf"), B.DRPF_EINVAL), (float("nan"), B.DRPF_EINVAL),
+                  (0.0, B.DRPF_OK), (0.5, B.DRPF_OK)):
+        p = _params(d_w=d)
+        assert L.drpf_validate(ctypes.byref(p)) == rc, d
+    nb = ctypes.c_size_t()
+    p = _params(d_w=0.1)
+    assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_EUNSUPPORTED
+
+
 def test_sizes_and_workspace_errors():
     B = _lib()
     L = B.lib()

@@ -103,6 +103,10 @@ CONFIGS: dict[str, Config] = {
     "C3L": _c(name="C3L", nx=128, ny=128, nz=64, lx=2.0, ly=2.0, lz=1.0, re=1.0, ca=1.0,
               cn=0.01, pe=300.0, wi=1.0, beta=0.5, theta_bottom_deg=120.0, dt=5e-5,
               steps=1000, radius=0.25, viscoelastic=1, constitutive=1, giesekus_alpha=0.2),
+    # C2 with relaxed walls (eq. NS15 with D_w = 0.1): the Robin form of the wall-normal pass.
+    "C2R": _c(name="C2R", nx=128, ny=128, nz=64, lx=2.0, ly=2.0, lz=1.0, re=100.0, ca=1.0,
+              cn=0.01, pe=300.0, theta_bottom_deg=90.0, rho_ratio=1000.0, mu_ratio=100.0,
+              dt=1e-4, steps=500, radius=0.25, d_w=0.1),
     # C3L with the fifth-order WENO-Z advection of the phase field and of the log-conformation:
     # the full scheme of the paper's three-dimensional viscoelastic runs.
     "C3P": _c(name="C3P", nx=128, ny=128, nz=64, lx=2.0, ly=2.0, lz=1.0, re=1.0, ca=1.0,
