@@ -461,35 +461,122 @@ __global__ void __launch_bounds__(kBlock)
     }
   }
 }
-// div(u_f phi*) on the fine grid with WENO-Z face values (eq. NS25's advection in the paper's
-// scheme): one thread per fine cell, phi* = 2 phi^n - phi^{n-1} (phi^n on the first step)
-// read at the cell and three cells either way along each axis (mirrored beyond the walls),
-// face velocities prolonged on the fly (eq. dual1; as they are at a single resolution).
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-    k_weno_adv_fine(const T* __restrict__ phin, const T* __restrict__ phinm1, Prolonged<T> pv,
-                    T* __restrict__ adv, int nx, int ny, int nz, T ihx, T ihy, T ihz) {
+// div(u_f phi*) on the fine grid with WENO-Z face values (the advection of eq. NS25), phi* =
+// 2 phi^n - phi^{n-1} (phi^n on the first step), face velocities prolonged on the fly (eq.
+// dual1; as they are at a single resolution). A z-march that evaluates every face once: a
+// block owns TX x TY fine columns and KB layers; phi* of the current layer with a three-cell
+// halo sits in LDS, each thread keeps phi* of its column from K-4 to K+3 in registers (z
+// mirrored at the walls), the x- and y-face fluxes of the layer go to LDS (faces spread over
+// the threads, the x overhang on the first wave and the y overhang on the second), and the z
+// flux through the top face becomes the next layer's bottom flux. Y3D = false: the 2D form
+// (one cell in y, no y flux).
+template <typename T, bool Y3D>
+__global__ void __launch_bounds__(256)
+    k_weno_adv_zm(const T* __restrict__ phin, const T* __restrict__ phinm1, Prolonged<T> pv,
+                  T* __restrict__ adv, int nx, int ny, int nz, int KB, T ihx, T ihy, T ihz) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int TX = blockDim.x, TY = blockDim.y;
   int bx, by, bz;
   xcd_tile(bx, by, bz);
-  const int I = bx * blockDim.x + threadIdx.x, J = by * blockDim.y + threadIdx.y, K = bz;
+  const int X0 = bx * TX, Y0 = by * TY, K0 = bz * KB;
+  const int K1 = min(K0 + KB, nz);
+  const int HX = TX + 6, HY = Y3D ? TY + 6 : 1, HP = HX * HY;
+  T* sT = reinterpret_cast<T*>(smem);  // phi* of the layer [HY][HX]
+  T* sFx = sT + HP;                     // x-face fluxes [TY][TX + 1]
+  T* sFy = sFx + TY * (TX + 1);         // y-face fluxes [TY + 1][TX]
+  const int tx = threadIdx.x, ty = threadIdx.y, nth = TX * TY;
+  const int tid = ty * TX + tx;
+  const int I = X0 + tx, J = Y0 + ty;
   const bool first = pv.first != 0;
-  auto ps = [&](int kk, int jj, int ii) {
-    const int id = (kk * ny + wrap(jj, ny)) * nx + wrap(ii, nx);
-    const T a = phin[id];
-    return first ? a : (T)2 * a - phinm1[id];
+  const size_t layer = (size_t)ny * nx;
+  auto ps_at = [&](int Kl, int off) -> T {
+    const size_t id = (size_t)Kl * layer + off;
+    return first ? phin[id] : (T)2 * phin[id] - phinm1[id];
   };
-  T vx[7], vy[7], vz[7];
+  const int col = J * nx + I;
+  T zw[8];  // phi* at K-4 .. K+3 of this column
 #pragma unroll
-  for (int d = -3; d <= 3; ++d) {
-    vx[d + 3] = ps(K, J, I + d);
-    vy[d + 3] = ps(K, J + d, I);
-    vz[d + 3] = ps(mirror_index(K + d, nz), J, I);
+  for (int d = 0; d < 8; ++d) zw[d] = ps_at(mirror_index(K0 - 4 + d, nz), col);
+  T fbot = weno_flux(pv.wf(K0 - 1, J, I), zw[1], zw[2], zw[3], zw[4], zw[5], zw[6]);
+  // this thread's tile points and faces, the same on every layer: decomposed once (at most
+  // NT tile points and two faces of each direction per thread; checked by the launcher)
+  constexpr int NT = Y3D ? 4 : 2;
+  const int nfx = (TX + 1) * TY, nfy = TX * (TY + 1);
+  int tOff[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const int e = tid + q * nth;
+    const int hy = e / HX, hx = e - hy * HX;
+    tOff[q] = e < HP ? (Y3D ? wrap(Y0 - 3 + hy, ny) : 0) * nx + wrap(X0 - 3 + hx, nx) : -1;
   }
-  const T dx = weno_div1(vx, pv.uf(K, J, I - 1), pv.uf(K, J, I));
-  const T dy = weno_div1(vy, pv.vf(K, J - 1, I), pv.vf(K, J, I));
-  // the wall faces (K = -1 and the top face of the last layer) carry no flux
-  const T dz = weno_div1(vz, pv.wf(K - 1, J, I), pv.wf(K, J, I));
-  adv[(K * ny + J) * nx + I] = dx * ihx + dy * ihy + dz * ihz;
+  int xr[2], xc[2], yr[2], yc[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int f = tid + q * nth;
+    xr[q] = f < nfx ? f / (TX + 1) : -1;
+    xc[q] = f < nfx ? f - xr[q] * (TX + 1) : 0;
+    // the y faces rotated by one wave, so that their overhang lands on another wave than x's
+    const int g = (f + 64) % nfy;
+    yr[q] = f < nfy ? g / TX : -1;
+    yc[q] = f < nfy ? g - yr[q] * TX : 0;
+  }
+  // the tile of the next layer is loaded while the current one is evaluated
+  T pa[NT], pb[NT];
+  auto load_tile = [&](int Kl) {
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      if (tOff[q] >= 0) {
+        const size_t id = (size_t)Kl * layer + tOff[q];
+        pa[q] = phin[id];
+        if (!first) pb[q] = phinm1[id];
+      }
+    }
+  };
+  load_tile(K0);
+  // x and y face velocities of the thread's faces: constant over the two fine layers of a
+  // coarse layer (dual resolution), so formed when the coarse layer changes
+  T xu[2] = {0, 0}, yv[2] = {0, 0};
+  for (int K = K0; K < K1; ++K) {
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+      if (tOff[q] >= 0) sT[tid + q * nth] = first ? pa[q] : (T)2 * pa[q] - pb[q];
+    if (K + 1 < K1) load_tile(K + 1);
+    if (pv.single || K == K0 || (K & 1) == 0) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (xr[q] >= 0) xu[q] = pv.uf(K, Y0 + xr[q], X0 - 1 + xc[q]);
+        if (Y3D && yr[q] >= 0) yv[q] = pv.vf(K, Y0 - 1 + yr[q], X0 + yc[q]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (xr[q] >= 0) {
+        const int r = xr[q], c = xc[q];
+        const T* v = sT + (Y3D ? r + 3 : 0) * HX + c;  // cells X0 - 3 + c .. X0 + 2 + c
+        sFx[r * (TX + 1) + c] = weno_flux(xu[q], v[0], v[1], v[2], v[3], v[4], v[5]);
+      }
+    }
+    if (Y3D) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (yr[q] >= 0) {
+          const int r = yr[q], c = yc[q];
+          const T* v = sT + r * HX + c + 3;  // rows Y0 - 3 + r .. Y0 + 2 + r
+          sFy[r * TX + c] = weno_flux(yv[q], v[0], v[HX], v[2 * HX], v[3 * HX], v[4 * HX], v[5 * HX]);
+        }
+      }
+    }
+    const T ftop = weno_flux(pv.wf(K, J, I), zw[2], zw[3], zw[4], zw[5], zw[6], zw[7]);
+    __syncthreads();
+    T d = (sFx[ty * (TX + 1) + tx + 1] - sFx[ty * (TX + 1) + tx]) * ihx + (ftop - fbot) * ihz;
+    if (Y3D) d += (sFy[(ty + 1) * TX + tx] - sFy[ty * TX + tx]) * ihy;
+    adv[(size_t)K * layer + col] = d;
+    fbot = ftop;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) zw[q] = zw[q + 1];
+    if (K + 1 < K1) zw[7] = ps_at(mirror_index(K + 4, nz), col);
+  }
 }
 
 // Single resolution (the phase field on the flow grid): chemical potential G^{n+1} (the
@@ -698,9 +785,27 @@ hipError_t launch_weno_adv_fine(const Dims& f, const Dims& c, const StepConsts& 
   const int single = f.nx == c.nx ? 1 : 0;
   Prolonged<T> pv{in.un, in.unm1, in.vn, in.vnm1, in.wn, in.wnm1, c.nx, c.ny, c.nz,
                   (c.ny == 1 || single) ? 1 : 2, k.first, single};
-  const Launch3 L = launch3(f.nx, f.ny, f.nz);
-  hipLaunchKernelGGL(k_weno_adv_fine<T>, L.grid, L.block, 0, st, in.phin, in.phinm1, pv, adv, f.nx, f.ny,
-                     f.nz, (T)f.ihx, (T)f.ihy, (T)f.ihz);
+  // z-march: 64 x 4 columns (2D: up to 256 x 1), KB layers per block, at least 1024 blocks
+  const bool y3d = f.ny > 1;
+  const int TX = y3d ? (f.nx < 64 ? f.nx : 64) : (f.nx < 256 ? f.nx : 256);
+  const int TY = y3d ? (f.ny < 256 / TX ? f.ny : 256 / TX) : 1;
+  const int tiles = (f.nx / TX) * (f.ny / TY);
+  int KB = 16;
+  while (KB > 2 && ((f.nz + KB - 1) / KB) * tiles < 1024) KB >>= 1;
+  if (KB > f.nz) KB = f.nz;
+  const int HY = y3d ? TY + 6 : 1;
+  // the kernel holds at most 4 (3D) or 2 (2D) tile points and two faces per direction per thread
+  const int nth = TX * TY;
+  if ((TX + 6) * HY > (y3d ? 4 : 2) * nth || (TX + 1) * TY > 2 * nth || TX * (TY + 1) > 2 * nth)
+    return hipErrorInvalidConfiguration;
+  const size_t shm = (size_t)((TX + 6) * HY + (TX + 1) * TY + TX * (TY + 1)) * sizeof(T);
+  const dim3 grid(f.nx / TX, f.ny / TY, (f.nz + KB - 1) / KB), block(TX, TY, 1);
+  if (y3d)
+    hipLaunchKernelGGL((k_weno_adv_zm<T, true>), grid, block, shm, st, in.phin, in.phinm1, pv, adv, f.nx,
+                       f.ny, f.nz, KB, (T)f.ihx, (T)f.ihy, (T)f.ihz);
+  else
+    hipLaunchKernelGGL((k_weno_adv_zm<T, false>), grid, block, shm, st, in.phin, in.phinm1, pv, adv, f.nx,
+                       f.ny, f.nz, KB, (T)f.ihx, (T)f.ihy, (T)f.ihz);
   return hipGetLastError();
 }
 
