@@ -101,6 +101,9 @@ def alg_bytes(kernel, cfg, es):
         "zpass_ns": 7 * sc,
         "fft_y_inv_coarse": 8 * sc if C["ny"] > 1 else 0,
         "fft_x_inv_coarse": 4 * sc + 5 * nc,
+        # the x and y passes in one kernel: the spectral round trip between them is gone
+        "fft_xy_fwd_coarse": 3 * nc + 3 * sc,
+        "fft_xy_inv_coarse": 4 * sc + 5 * nc,
         # log-conformation: stage 2 also writes tau from the new Theta
         "polymer_stage1": 15 * nc if ve else 0,
         "polymer_stage2": (27 if cfg.constitutive == 1 else 21) * nc if ve else 0,

@@ -212,8 +212,10 @@ int drpf_debug_field(drpf_grid* g, int id, void** ptr, size_t* count);
  * 4-5 fine y/x inverse transforms, 6 restriction and chemical potential, 7 momentum
  * right-hand side, 8-9 coarse x/y forward transforms, 10 coarse wall-normal pass (NS
  * projection), 11-12 coarse y/x inverse transforms, 13-14 polymer stages, 15 WENO-Z
- * advection of the phase field (advection 1 only; it precedes ch_rhs). */
-#define DRPF_NKERNELS 16
+ * advection of the phase field (advection 1 only; it precedes ch_rhs), 16-17 the coarse x and
+ * y transforms in one kernel, forward and inverse (in place of 8-9 and 11-12 where a coarse
+ * layer fits in one block's LDS: 128 x 128 in either precision). */
+#define DRPF_NKERNELS 18
 int drpf_profile_begin(drpf_grid* g, int max_launches, void* stream);
 int drpf_profile_end(drpf_grid* g, double* total_ms, int* launches, int n);
 /* Short name of kernel id (see above); "" for an unknown id. */

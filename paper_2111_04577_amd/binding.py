@@ -17,7 +17,7 @@ DRPF_OK, DRPF_EINVAL, DRPF_EWORKSPACE, DRPF_EHIP, DRPF_ENONFINITE, DRPF_EUNSUPPO
 LOCATIONS = {"center": 0, "face_x": 1, "face_y": 2, "face_z": 3, "edge_xy": 4, "edge_xz": 5,
              "edge_yz": 6}
 BCS = {"neumann": 0, "dirichlet": 1, "face_dirichlet": 2}
-NKERNELS = 16
+NKERNELS = 18
 OBSERVABLES = ("mass", "wetted_radius", "centroid_height", "kinetic_energy", "max_div")
 
 

@@ -286,7 +286,8 @@ int upload_tables(drpf_grid* g, const Dims& d, const TabOff& t, hipStream_t st,
 const char* const kKernelNames[DRPF_NKERNELS] = {
     "ch_rhs", "fft_x_fwd_fine", "fft_y_fwd_fine", "zpass_ch", "fft_y_inv_fine", "fft_x_inv_fine",
     "restrict_g", "momentum_rhs", "fft_x_fwd_coarse", "fft_y_fwd_coarse", "zpass_ns",
-    "fft_y_inv_coarse", "fft_x_inv_coarse", "polymer_stage1", "polymer_stage2", "weno_adv_fine"};
+    "fft_y_inv_coarse", "fft_x_inv_coarse", "polymer_stage1", "polymer_stage2", "weno_adv_fine",
+    "fft_xy_fwd_coarse", "fft_xy_inv_coarse"};
 
 void mark(drpf_grid* g, int kernel, hipStream_t st) {
   if (!g->prof || g->ev_used >= g->ev.size()) return;
@@ -379,14 +380,19 @@ int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t
   HIPCHK(launch_momentum_rhs<T>(C, K, ni, R, Rc, Rc + nc, Rc + 2 * nc, st), "momentum_rhs");
   mark(g, 7, st);
   const T* inc[4] = {Rc, Rc + nc, Rc + 2 * nc, nullptr};
-  HIPCHK(launch_fft_x_fwd<T>(C, tc, inc, 3, Sc, st), "fft_x coarse");
-  mark(g, 8, st);
-  HIPCHK(launch_fft_y<T>(C, tc, Sc, 3, false, st), "fft_y coarse");
-  mark(g, 9, st);
+  // a coarse layer that fits in one block's LDS takes the x and y passes in one kernel
+  const bool fused = fft_xy_fits<T>(C);
+  if (fused) {
+    HIPCHK(launch_fft_xy_fwd<T>(C, tc, inc, 3, Sc, st), "fft_xy coarse");
+    mark(g, 16, st);
+  } else {
+    HIPCHK(launch_fft_x_fwd<T>(C, tc, inc, 3, Sc, st), "fft_x coarse");
+    mark(g, 8, st);
+    HIPCHK(launch_fft_y<T>(C, tc, Sc, 3, false, st), "fft_y coarse");
+    mark(g, 9, st);
+  }
   HIPCHK(launch_zpass_ns<T>(C, tc, Sc, piv, K, 1.0 / ((double)C.nx * C.ny), st), "zpass_ns");
   mark(g, 10, st);
-  HIPCHK(launch_fft_y<T>(C, tc, Sc, 4, true, st), "ifft_y coarse");
-  mark(g, 11, st);
   RealSet<T> oc;
   memset(&oc, 0, sizeof(oc));
   oc.p[0] = io.uo;
@@ -395,8 +401,15 @@ int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t
   oc.p[3] = io.po;
   oc.add[3] = io.pn;
   oc.nfields = 4;
-  HIPCHK(launch_fft_x_inv<T>(C, tc, Sc, oc, st), "ifft_x coarse");
-  mark(g, 12, st);
+  if (fused) {
+    HIPCHK(launch_fft_xy_inv<T>(C, tc, Sc, oc, st), "ifft_xy coarse");
+    mark(g, 17, st);
+  } else {
+    HIPCHK(launch_fft_y<T>(C, tc, Sc, 4, true, st), "ifft_y coarse");
+    mark(g, 11, st);
+    HIPCHK(launch_fft_x_inv<T>(C, tc, Sc, oc, st), "ifft_x coarse");
+    mark(g, 12, st);
+  }
   // ---- polymer stress, RK2-TVD with u^{n+1}
   if (ve) {
     T* t1[6];

@@ -154,6 +154,129 @@ __global__ void k_fft_y(cx<T>* __restrict__ data, int Ny, int logNy, int P, int 
   }
 }
 
+// ---- x and y passes together, one block per layer of one field --------------------------
+// A whole layer (ny rows of nx reals; M = nx/2) in LDS: [ny][M] complex plus the Nyquist
+// column. Forward: the half-length x transform of every row, the r2c split in place (pairs k
+// and M - k, k = 0 giving mode 0 and the Nyquist mode), then the y transform of every column
+// and of the Nyquist column, written in the spectral layout. The inverse runs the same steps
+// backwards, with the addend of the real output. The same arithmetic as the separate passes,
+// without the spectral round trip between them; used where a layer fits in a block's LDS.
+template <typename T, int REP>
+__global__ void __launch_bounds__(1024)
+    k_fft_xy_fwd(const T* __restrict__ in0, const T* __restrict__ in1, const T* __restrict__ in2,
+                 cx<T>* __restrict__ out, int N, int logM, int Ny, int logNy, int nz,
+                 const cx<T>* __restrict__ twM, const cx<T>* __restrict__ twN,
+                 const cx<T>* __restrict__ twY) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int M = N >> 1;
+  cx<T>* A = reinterpret_cast<cx<T>*>(smem_raw);  // [Ny][M]
+  cx<T>* Q = A + (Ny << logM);                     // Nyquist column [Ny]
+  cx<T>* sM = Q + Ny;                              // x twiddles [M]
+  cx<T>* sY = sM + M;                              // y twiddles [Ny]
+  const int field = blockIdx.x / nz, z = blockIdx.x - field * nz;
+  const T* in = field == 0 ? in0 : (field == 1 ? in1 : in2);
+  const T* src = in + (size_t)z * Ny * N;
+  for (int e = threadIdx.x; e < M; e += blockDim.x) sM[e] = twM[e];
+  for (int e = threadIdx.x; e < Ny; e += blockDim.x) sY[e] = twY[e];
+  const int n = Ny << logM;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) A[e] = mk<T>(src[2 * e], src[2 * e + 1]);
+  __syncthreads();
+  lds_fft_rep<T, false, false, REP>(A, M, logM, Ny, 0, sM);
+  const int half = M >> 1;
+  const T hf = (T)0.5;
+  // mode k from z_k and conj(z_{M-k}) of the half-length transform
+  auto split = [&](cx<T> zk, cx<T> zmc, int k) {
+    const cx<T> E = hf * (zk + zmc);
+    const cx<T> O = hf * mul_mi(zk - zmc);
+    return E + twN[k] * O;
+  };
+  for (int e = threadIdx.x; e < Ny * (half + 1); e += blockDim.x) {
+    const int y = e / (half + 1), k = e - y * (half + 1);
+    cx<T>* row = A + (y << logM);
+    if (k == 0) {
+      const cx<T> a = row[0];
+      row[0] = split(a, conj(a), 0);
+      Q[y] = split(a, conj(a), M);
+    } else if (k == half) {
+      const cx<T> a = row[half];
+      row[half] = split(a, conj(a), half);
+    } else {
+      const cx<T> a = row[k], b = row[M - k];
+      row[k] = split(a, conj(b), k);
+      row[M - k] = split(b, conj(a), M - k);
+    }
+  }
+  __syncthreads();
+  lds_fft_rep<T, false, true, REP>(A, Ny, logNy, M, logM, sY);
+  lds_fft<T, false, true>(Q, Ny, logNy, 1, 0, sY);
+  const size_t lines = (size_t)(M + 1) * Ny;
+  cx<T>* dst = out + (size_t)field * lines * nz + (size_t)z * lines;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = A[e];
+  for (int e = threadIdx.x; e < Ny; e += blockDim.x) dst[(size_t)M * Ny + e] = Q[e];
+}
+
+template <typename T, int REP>
+__global__ void __launch_bounds__(1024)
+    k_fft_xy_inv(const cx<T>* __restrict__ in, RealSet<T> out, int N, int logM, int Ny, int logNy,
+                 int nz, const cx<T>* __restrict__ twM, const cx<T>* __restrict__ twN,
+                 const cx<T>* __restrict__ twY) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int M = N >> 1;
+  cx<T>* A = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* Q = A + (Ny << logM);
+  cx<T>* sM = Q + Ny;
+  cx<T>* sY = sM + M;
+  const int field = blockIdx.x / nz, z = blockIdx.x - field * nz;
+  const size_t lines = (size_t)(M + 1) * Ny;
+  const cx<T>* src = in + (size_t)field * lines * nz + (size_t)z * lines;
+  for (int e = threadIdx.x; e < M; e += blockDim.x) sM[e] = twM[e];
+  for (int e = threadIdx.x; e < Ny; e += blockDim.x) sY[e] = twY[e];
+  const int n = Ny << logM;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) A[e] = src[e];
+  for (int e = threadIdx.x; e < Ny; e += blockDim.x) Q[e] = src[(size_t)M * Ny + e];
+  __syncthreads();
+  lds_fft_rep<T, true, true, REP>(A, Ny, logNy, M, logM, sY);
+  lds_fft<T, true, true>(Q, Ny, logNy, 1, 0, sY);
+  // c2r: z_k = E + i O, E = X_k + conj(X_{M-k}), O = conj(w_k)(X_k - conj(X_{M-k})), with
+  // X_{M-0} read as the Nyquist mode
+  const int half = M >> 1;
+  auto join = [&](cx<T> xk, cx<T> xmc, int k) {
+    const cx<T> E = xk + xmc;
+    const cx<T> O = conj(twN[k]) * (xk - xmc);
+    return E + mul_i(O);
+  };
+  for (int e = threadIdx.x; e < Ny * (half + 1); e += blockDim.x) {
+    const int y = e / (half + 1), k = e - y * (half + 1);
+    cx<T>* row = A + (y << logM);
+    if (k == 0) {
+      row[0] = join(row[0], conj(Q[y]), 0);
+    } else if (k == half) {
+      const cx<T> a = row[half];
+      row[half] = join(a, conj(a), half);
+    } else {
+      const cx<T> a = row[k], b = row[M - k];
+      row[k] = join(a, conj(b), k);
+      row[M - k] = join(b, conj(a), M - k);
+    }
+  }
+  __syncthreads();
+  lds_fft_rep<T, true, false, REP>(A, M, logM, Ny, 0, sM);
+  T* dst = out.p[field] + (size_t)z * Ny * N;
+  const T* add = out.add[field];
+  if (add != nullptr) {
+    add += (size_t)z * Ny * N;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+      dst[2 * e] = add[2 * e] + A[e].re;
+      dst[2 * e + 1] = add[2 * e + 1] + A[e].im;
+    }
+  } else {
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+      dst[2 * e] = A[e].re;
+      dst[2 * e + 1] = A[e].im;
+    }
+  }
+}
+
 int x_lines_per_block(int M) {
   const int quarter = M >= 4 ? M / 4 : 1;
   return kBlock / quarter;  // M <= 1024 keeps this >= 1
@@ -196,6 +319,55 @@ hipError_t launch_fft_x_inv(const Dims& d, const Tables<T>& tb, const cx<T>* spe
   return hipGetLastError();
 }
 
+// LDS of one layer in the fused x-y passes, and the butterfly sets per thread (1024 threads)
+template <typename T>
+size_t fft_xy_lds(const Dims& d) {
+  return ((size_t)(d.nx / 2) * d.ny + 2 * (size_t)d.ny + d.nx / 2) * sizeof(cx<T>);
+}
+int fft_xy_rep(const Dims& d) {
+  const int M = d.nx / 2;
+  const int sx = (M >= 4 ? M / 4 : 1) * d.ny, sy = (d.ny >= 4 ? d.ny / 4 : 1) * M;
+  const int sets = sx > sy ? sx : sy;
+  return sets <= 2048 ? 2 : (sets <= 4096 ? 4 : 0);
+}
+
+template <typename T>
+bool fft_xy_fits(const Dims& d) {
+  return d.ny > 1 && fft_xy_lds<T>(d) <= (size_t)160 * 1024 && fft_xy_rep(d) != 0;
+}
+
+template <typename T>
+hipError_t launch_fft_xy_fwd(const Dims& d, const Tables<T>& tb, const T* const in[4], int nfields,
+                             cx<T>* spec, hipStream_t st) {
+  if (!fft_xy_fits<T>(d)) return hipErrorInvalidConfiguration;
+  const size_t shm = fft_xy_lds<T>(d);
+  const dim3 grid(nfields * d.nz), block(1024);
+  const T* i1 = nfields > 1 ? in[1] : in[0];
+  const T* i2 = nfields > 2 ? in[2] : in[0];
+  if (fft_xy_rep(d) == 2)
+    hipLaunchKernelGGL((k_fft_xy_fwd<T, 2>), grid, block, shm, st, in[0], i1, i2, spec, d.nx, d.logx - 1,
+                       d.ny, d.logy, d.nz, tb.tw_xm, tb.tw_xn, tb.tw_y);
+  else
+    hipLaunchKernelGGL((k_fft_xy_fwd<T, 4>), grid, block, shm, st, in[0], i1, i2, spec, d.nx, d.logx - 1,
+                       d.ny, d.logy, d.nz, tb.tw_xm, tb.tw_xn, tb.tw_y);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft_xy_inv(const Dims& d, const Tables<T>& tb, const cx<T>* spec, RealSet<T> out,
+                             hipStream_t st) {
+  if (!fft_xy_fits<T>(d)) return hipErrorInvalidConfiguration;
+  const size_t shm = fft_xy_lds<T>(d);
+  const dim3 grid(out.nfields * d.nz), block(1024);
+  if (fft_xy_rep(d) == 2)
+    hipLaunchKernelGGL((k_fft_xy_inv<T, 2>), grid, block, shm, st, spec, out, d.nx, d.logx - 1, d.ny,
+                       d.logy, d.nz, tb.tw_xm, tb.tw_xn, tb.tw_y);
+  else
+    hipLaunchKernelGGL((k_fft_xy_inv<T, 4>), grid, block, shm, st, spec, out, d.nx, d.logx - 1, d.ny,
+                       d.logy, d.nz, tb.tw_xm, tb.tw_xn, tb.tw_y);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_fft_y(const Dims& d, const Tables<T>& tb, cx<T>* spec, int nfields, bool inverse,
                         hipStream_t st) {
@@ -226,7 +398,12 @@ hipError_t launch_fft_y(const Dims& d, const Tables<T>& tb, cx<T>* spec, int nfi
                                           cx<T>*, hipStream_t);                                    \
   template hipError_t launch_fft_x_inv<T>(const Dims&, const Tables<T>&, const cx<T>*, RealSet<T>, \
                                           hipStream_t);                                            \
-  template hipError_t launch_fft_y<T>(const Dims&, const Tables<T>&, cx<T>*, int, bool, hipStream_t);
+  template hipError_t launch_fft_y<T>(const Dims&, const Tables<T>&, cx<T>*, int, bool, hipStream_t); \
+  template bool fft_xy_fits<T>(const Dims&);                                                        \
+  template hipError_t launch_fft_xy_fwd<T>(const Dims&, const Tables<T>&, const T* const[4], int,  \
+                                           cx<T>*, hipStream_t);                                   \
+  template hipError_t launch_fft_xy_inv<T>(const Dims&, const Tables<T>&, const cx<T>*, RealSet<T>, \
+                                           hipStream_t);
 INST(double)
 INST(float)
 #undef INST

@@ -25,6 +25,16 @@ hipError_t launch_fft_x_inv(const Dims& d, const Tables<T>& tb, const cx<T>* spe
 template <typename T>
 hipError_t launch_fft_y(const Dims& d, const Tables<T>& tb, cx<T>* spec, int nfields, bool inverse,
                         hipStream_t st);
+// The x and y passes in one kernel, a block per layer of a field (coarse layers that fit in
+// a block's LDS; fft_xy_fits says whether they do).
+template <typename T>
+bool fft_xy_fits(const Dims& d);
+template <typename T>
+hipError_t launch_fft_xy_fwd(const Dims& d, const Tables<T>& tb, const T* const in[4], int nfields,
+                             cx<T>* spec, hipStream_t st);
+template <typename T>
+hipError_t launch_fft_xy_inv(const Dims& d, const Tables<T>& tb, const cx<T>* spec, RealSet<T> out,
+                             hipStream_t st);
 
 // ---- tridiag.hip ----------------------------------------------------------------------
 // bc: 0 Neumann, 1 Dirichlet (centred), 2 Dirichlet (z faces). Solves coeff L x - shift x =
