@@ -378,7 +378,8 @@ def ingest_pmc(fetch_csv, write_csv, out_json):
     write, ws = read(write_csv, "WRITE_SIZE")
     base = {"k_ch_rhs": "ch_rhs", "k_restrict_g": "restrict_g", "k_momentum_rhs": "momentum_rhs",
             "k_momentum_rhs_zm": "momentum_rhs", "k_polymer_div_zm": "polymer_div",
-            "k_zpass_ch": "zpass_ch", "k_zpass_ns": "zpass_ns"}
+            "k_zpass_ch": "zpass_ch", "k_zpass_ns": "zpass_ns",
+            "k_fft_xy_fwd": "fft_xy_fwd_coarse", "k_fft_xy_inv": "fft_xy_inv_coarse"}
     sizes = defaultdict(set)
     for (k, t, inv, g) in fetch:
         sizes[(k, t, inv)].add(g)
