@@ -126,7 +126,7 @@ struct TabOff {
 
 struct Offsets {
   TabOff tf, tc;
-  size_t rf, sf, piv, rc, sc, rset[12], tau1[6], part, obs, total;
+  size_t rf, sf, rc, sc, rset[12], tau1[6], part, obs, total;
 };
 
 Offsets layout(const drpf_params& p, const Dims& F, const Dims& C) {
@@ -149,8 +149,6 @@ Offsets layout(const drpf_params& p, const Dims& F, const Dims& C) {
   tabs(C, o.tc);
   o.rf = cv.take(F.cells() * es);
   o.sf = cv.take(F.spec() * 2 * es);
-  const size_t pf = (size_t)F.lines() * F.nz, pc = (size_t)3 * C.lines() * C.nz;
-  o.piv = cv.take((pf > pc ? pf : pc) * 8);
   o.rc = cv.take(3 * C.cells() * es);
   o.sc = cv.take(4 * C.spec() * 2 * es);
   const size_t nc = C.cells(), ne = (size_t)C.nx * C.ny * (C.nz + 1);
@@ -320,7 +318,6 @@ int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t
   const Tables<T> tf = tables<T>(g, g->o.tf), tc = tables<T>(g, g->o.tc);
   T* Rf = reinterpret_cast<T*>(g->ws + g->o.rf);
   cx<T>* Sf = reinterpret_cast<cx<T>*>(g->ws + g->o.sf);
-  double* piv = reinterpret_cast<double*>(g->ws + g->o.piv);
   T* Rc = reinterpret_cast<T*>(g->ws + g->o.rc);
   cx<T>* Sc = reinterpret_cast<cx<T>*>(g->ws + g->o.sc);
   const Restricted<T> R = rset<T>(g);
@@ -342,7 +339,7 @@ int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t
   mark(g, 1, st);
   HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, false, st), "fft_y fine");
   mark(g, 2, st);
-  HIPCHK(launch_zpass_ch<T>(F, tf, Sf, piv, K.c_psi, K.alpha, 1.0 / ((double)F.nx * F.ny),
+  HIPCHK(launch_zpass_ch<T>(F, tf, Sf, K.c_psi, K.alpha, 1.0 / ((double)F.nx * F.ny),
                             -K.relax_kappa / F.hz, st),
          "zpass_ch");
   mark(g, 3, st);
@@ -391,7 +388,7 @@ int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t
     HIPCHK(launch_fft_y<T>(C, tc, Sc, 3, false, st), "fft_y coarse");
     mark(g, 9, st);
   }
-  HIPCHK(launch_zpass_ns<T>(C, tc, Sc, piv, K, 1.0 / ((double)C.nx * C.ny), st), "zpass_ns");
+  HIPCHK(launch_zpass_ns<T>(C, tc, Sc, K, 1.0 / ((double)C.nx * C.ny), st), "zpass_ns");
   mark(g, 10, st);
   RealSet<T> oc;
   memset(&oc, 0, sizeof(oc));
@@ -503,11 +500,10 @@ int helmholtz_impl(drpf_grid* g, int which, int bc, double coeff, double shift, 
   const Dims& d = which == DRPF_GRID_FINE ? g->F : g->C;
   const Tables<T> tb = tables<T>(g, which == DRPF_GRID_FINE ? g->o.tf : g->o.tc);
   cx<T>* S = reinterpret_cast<cx<T>*>(g->ws + (which == DRPF_GRID_FINE ? g->o.sf : g->o.sc));
-  double* piv = reinterpret_cast<double*>(g->ws + g->o.piv);
   const T* in[4] = {(const T*)rhs, nullptr, nullptr, nullptr};
   HIPCHK(launch_fft_x_fwd<T>(d, tb, in, 1, S, st), "fft_x");
   HIPCHK(launch_fft_y<T>(d, tb, S, 1, false, st), "fft_y");
-  HIPCHK(launch_zpass_helmholtz<T>(d, tb, S, piv, bc, coeff, shift, 1.0 / ((double)d.nx * d.ny), st),
+  HIPCHK(launch_zpass_helmholtz<T>(d, tb, S, bc, coeff, shift, 1.0 / ((double)d.nx * d.ny), st),
          "zpass");
   HIPCHK(launch_fft_y<T>(d, tb, S, 1, true, st), "ifft_y");
   RealSet<T> o;
@@ -598,7 +594,6 @@ int adjoint_impl(drpf_grid* g, const drpf_state* x, const drpf_state* xn, drpf_a
   T* Rc = reinterpret_cast<T*>(g->ws + g->o.rc);
   cx<T>* Sc = reinterpret_cast<cx<T>*>(g->ws + g->o.sc);
   cx<T>* Sf = reinterpret_cast<cx<T>*>(g->ws + g->o.sf);
-  double* piv = reinterpret_cast<double*>(g->ws + g->o.piv);
   const size_t nc = C.cells();
   // ---- forward intermediates: with the state after the step given, only the restricted
   // coarse set and the first polymer stage are recomputed; otherwise the whole step is,
@@ -718,7 +713,7 @@ int adjoint_impl(drpf_grid* g, const drpf_state* x, const drpf_state* xn, drpf_a
   const T* inf[4] = {P(A.lQ), nullptr, nullptr, nullptr};
   HIPCHK(launch_fft_x_fwd<T>(F, tf, inf, 1, Sf, st), "adjoint fft_x fine");
   HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, false, st), "adjoint fft_y fine");
-  HIPCHK(launch_zpass_ch<T>(F, tf, Sf, piv, K.c_psi, K.alpha, 1.0 / ((double)F.nx * F.ny), 0.0, st),
+  HIPCHK(launch_zpass_ch<T>(F, tf, Sf, K.c_psi, K.alpha, 1.0 / ((double)F.nx * F.ny), 0.0, st),
          "adjoint zpass_ch");
   HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, true, st), "adjoint ifft_y fine");
   RealSet<T> of;

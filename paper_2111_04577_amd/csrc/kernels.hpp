@@ -41,17 +41,17 @@ hipError_t launch_fft_xy_inv(const Dims& d, const Tables<T>& tb, const cx<T>* sp
 // (scale * spec) in place per Fourier mode; Neumann with shift 0 pins the zero mode and
 // removes its mean.
 template <typename T>
-hipError_t launch_zpass_helmholtz(const Dims& d, const Tables<T>& tb, cx<T>* spec, double* piv,
-                                  int bc, double coeff, double shift, double scale, hipStream_t st);
+hipError_t launch_zpass_helmholtz(const Dims& d, const Tables<T>& tb, cx<T>* spec, int bc,
+                                  double coeff, double shift, double scale, hipStream_t st);
 // Cahn-Hilliard: (L - c_psi) then (L + alpha), both Neumann; with dwall != 0 the fused
 // operator gains L dW (dW: dwall on the two wall-adjacent rows), the relaxed walls of eq. NS34.
 template <typename T>
-hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, double* piv,
-                           double c_psi, double alpha, double scale, double dwall, hipStream_t st);
+hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, double c_psi,
+                           double alpha, double scale, double dwall, hipStream_t st);
 // Navier-Stokes: velocity Helmholtz x3, divergence, FP64 Poisson, correction.
 template <typename T>
-hipError_t launch_zpass_ns(const Dims& d, const Tables<T>& tb, cx<T>* spec4, double* piv,
-                           const StepConsts& c, double scale, hipStream_t st);
+hipError_t launch_zpass_ns(const Dims& d, const Tables<T>& tb, cx<T>* spec4, const StepConsts& c,
+                           double scale, hipStream_t st);
 
 // ---- stencil_ch.hip -------------------------------------------------------------------
 template <typename T>

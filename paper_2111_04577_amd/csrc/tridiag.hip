@@ -550,9 +550,8 @@ __global__ void __launch_bounds__(1024)
 }  // namespace
 
 template <typename T>
-hipError_t launch_zpass_helmholtz(const Dims& d, const Tables<T>& tb, cx<T>* spec, double* piv,
-                                  int bc, double coeff, double shift, double scale, hipStream_t st) {
-  (void)piv;
+hipError_t launch_zpass_helmholtz(const Dims& d, const Tables<T>& tb, cx<T>* spec, int bc,
+                                  double coeff, double shift, double scale, hipStream_t st) {
   const int lines = d.lines();
   const int TL = spread_lines(tile_lines(d.nz), lines, 2048);
   const size_t shm = pcr_bytes<double, 1>(d.nz, TL);
@@ -563,9 +562,8 @@ hipError_t launch_zpass_helmholtz(const Dims& d, const Tables<T>& tb, cx<T>* spe
 }
 
 template <typename T>
-hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, double* piv,
-                           double c_psi, double alpha, double scale, double dwall, hipStream_t st) {
-  (void)piv;
+hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, double c_psi,
+                           double alpha, double scale, double dwall, hipStream_t st) {
   // tiles of 128 bytes per row (16 complex FP32 or 8 complex FP64 modes): one cache line
   int TL = (int)(128 / sizeof(cx<T>));
   while (TL > 1 && TL * d.nz > 4096) TL >>= 1;
@@ -594,9 +592,8 @@ hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, doub
 }
 
 template <typename T>
-hipError_t launch_zpass_ns(const Dims& d, const Tables<T>& tb, cx<T>* spec4, double* piv,
-                           const StepConsts& c, double scale, hipStream_t st) {
-  (void)piv;
+hipError_t launch_zpass_ns(const Dims& d, const Tables<T>& tb, cx<T>* spec4, const StepConsts& c,
+                           double scale, hipStream_t st) {
   const int lines = d.lines();
   const int TL = spread_lines(tile_lines(d.nz), lines, 2048);
   size_t shm = pcr_bytes<T, 2>(d.nz, TL);
@@ -620,11 +617,11 @@ hipError_t launch_zpass_ns_adj(const Dims& d, const Tables<double>& tb, cx<doubl
 }
 
 #define INST(T)                                                                                  \
-  template hipError_t launch_zpass_helmholtz<T>(const Dims&, const Tables<T>&, cx<T>*, double*,  \
+  template hipError_t launch_zpass_helmholtz<T>(const Dims&, const Tables<T>&, cx<T>*,  \
                                                 int, double, double, double, hipStream_t);       \
-  template hipError_t launch_zpass_ch<T>(const Dims&, const Tables<T>&, cx<T>*, double*, double, \
+  template hipError_t launch_zpass_ch<T>(const Dims&, const Tables<T>&, cx<T>*, double, \
                                          double, double, double, hipStream_t);                   \
-  template hipError_t launch_zpass_ns<T>(const Dims&, const Tables<T>&, cx<T>*, double*,         \
+  template hipError_t launch_zpass_ns<T>(const Dims&, const Tables<T>&, cx<T>*,         \
                                          const StepConsts&, double, hipStream_t);
 INST(double)
 INST(float)
