@@ -251,6 +251,13 @@ __global__ void __launch_bounds__(1024)
     // x_k = sum_m W_m F_m cos(pi m (k + 1/2) / N), W = (1, 2, 2, ...), the sum and difference
     // solve sigma = P_e / (1 + H_e), delta = P_o / (1 + H_o) with P = 2 sum W c F0 and
     // H = 2 sum W c G over even or odd m. H >= 0 (d < 0, lambda <= 0, A > 0).
+    // after the twiddles, rounded up to 16 bytes: the wall sums [TL][2], the partials
+    // [NC][TL][6], then G [Nz][TL] in the storage type
+    const int NC = min((int)(blockDim.x >> ltl), 16);
+    const size_t so = ((size_t)(Nz * TL + Nz) * sizeof(cx<T>) + 15) & ~(size_t)15;
+    cx<double>* sd = reinterpret_cast<cx<double>*>(smem + so);
+    double* part = reinterpret_cast<double*>(sd + 2 * TL);
+    T* sG = reinterpret_cast<T*>(part + 6 * NC * TL);
     for (int e = threadIdx.x; e < (half + 1) * TL; e += blockDim.x) {
       const int m = e >> ltl, t = e & (TL - 1);
       const int l = min(l0 + t, lines - 1);
@@ -259,30 +266,22 @@ __global__ void __launch_bounds__(1024)
       const T lxy = (T)(lamx[kx] + lamy[ky]);
       const int mr = (Nz - m) & (Nz - 1);
       const cx<T> Vm = buf[m * TL + t], Vr = buf[mr * TL + t];
+      // 1/A once per entry: F0 = scale X / A and G = d lambda c / (N A)
       const T lm = lxy + (T)lamz[m];
-      buf[m * TL + t] = (sc / ((lm - cp) * (lm + al))) * dct_out(Vm, Vr, twq[m]);
+      const T im = (T)1 / ((lm - cp) * (lm + al));
+      buf[m * TL + t] = (sc * im) * dct_out(Vm, Vr, twq[m]);
+      sG[m * TL + t] = (T)dwall * lm * twq[m].re * im / (T)Nz;
       if (mr != m) {
         const T lr = lxy + (T)lamz[mr];
-        buf[mr * TL + t] = (sc / ((lr - cp) * (lr + al))) * dct_out(Vr, Vm, twq[mr]);
+        const T ir = (T)1 / ((lr - cp) * (lr + al));
+        buf[mr * TL + t] = (sc * ir) * dct_out(Vr, Vm, twq[mr]);
+        sG[mr * TL + t] = (T)dwall * lr * twq[mr].re * ir / (T)Nz;
       }
     }
     __syncthreads();
     // partial sums over m = ch, ch + NC, ... per mode, then their totals
-    const int NC = min((int)(blockDim.x >> ltl), 16);
-    // after the twiddles, rounded up to 16 bytes: the wall sums [TL][2], then the partials
-    const size_t so = ((size_t)(Nz * TL + Nz) * sizeof(cx<T>) + 15) & ~(size_t)15;
-    cx<double>* sd = reinterpret_cast<cx<double>*>(smem + so);
-    double* part = reinterpret_cast<double*>(sd + 2 * TL);  // [NC][TL][6]
-    auto g_of = [&](int m, double lxy) {
-      const double lm = lxy + lamz[m];
-      return dwall * lm * (double)twq[m].re / ((double)Nz * (lm - c_psi) * (lm + alpha));
-    };
     for (int e = threadIdx.x; e < NC * TL; e += blockDim.x) {
       const int t = e & (TL - 1), ch = e >> ltl;
-      const int l = min(l0 + t, lines - 1);
-      int ky, kx;
-      spec_mode(l, P, Ny, ky, kx);
-      const double lxy = lamx[kx] + lamy[ky];
       double acc[6] = {0, 0, 0, 0, 0, 0};  // P_e (re, im), P_o (re, im), H_e, H_o
       for (int m = ch; m < Nz; m += NC) {
         const double wc = (m == 0 ? 2.0 : 4.0) * (double)twq[m].re;
@@ -290,32 +289,33 @@ __global__ void __launch_bounds__(1024)
         const int o = (m & 1) * 2;
         acc[o] += wc * (double)F.re;
         acc[o + 1] += wc * (double)F.im;
-        acc[4 + (m & 1)] += wc * g_of(m, lxy);
+        acc[4 + (m & 1)] += wc * (double)sG[m * TL + t];
       }
 #pragma unroll
       for (int q = 0; q < 6; ++q) part[(ch * TL + t) * 6 + q] = acc[q];
     }
     __syncthreads();
+    // totals: one thread per (quantity, mode), into the first chunk's slots
+    for (int e = threadIdx.x; e < 6 * TL; e += blockDim.x) {
+      const int t = e % TL, q = e / TL;
+      double a = 0;
+      for (int ch = 0; ch < NC; ++ch) a += part[(ch * TL + t) * 6 + q];
+      part[t * 6 + q] = a;
+    }
+    __syncthreads();
     for (int t = threadIdx.x; t < TL; t += blockDim.x) {
-      double a[6] = {0, 0, 0, 0, 0, 0};
-      for (int ch = 0; ch < NC; ++ch)
-#pragma unroll
-        for (int q = 0; q < 6; ++q) a[q] += part[(ch * TL + t) * 6 + q];
+      const double* a = part + t * 6;
       sd[2 * t] = mk<double>(a[0] / (1.0 + a[4]), a[1] / (1.0 + a[4]));      // sigma
       sd[2 * t + 1] = mk<double>(a[2] / (1.0 + a[5]), a[3] / (1.0 + a[5]));  // delta
     }
     __syncthreads();
     for (int e = threadIdx.x; e < (half + 1) * TL; e += blockDim.x) {
       const int m = e >> ltl, t = e & (TL - 1);
-      const int l = min(l0 + t, lines - 1);
-      int ky, kx;
-      spec_mode(l, P, Ny, ky, kx);
-      const double lxy = lamx[kx] + lamy[ky];
       const int mr = (Nz - m) & (Nz - 1);
       auto corrected = [&](int mm) -> cx<T> {
         const cx<T> F = buf[mm * TL + t];
         const cx<double> s = sd[2 * t + (mm & 1)];
-        const double g = g_of(mm, lxy);
+        const double g = (double)sG[mm * TL + t];
         return mk<T>((T)((double)F.re - g * s.re), (T)((double)F.im - g * s.im));
       };
       const cx<T> Fm = corrected(m);
@@ -583,7 +583,8 @@ hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, doub
   } else {
     // relaxed walls: partial sums (at most 16 per mode, 6 doubles each) and the wall sums
     const int nc = (threads / TL) < 16 ? threads / TL : 16;
-    shm = ((shm + 15) & ~(size_t)15) + (size_t)2 * TL * sizeof(cx<double>) + (size_t)6 * nc * TL * sizeof(double);
+    shm = ((shm + 15) & ~(size_t)15) + (size_t)2 * TL * sizeof(cx<double>) + (size_t)6 * nc * TL * sizeof(double) +
+          (size_t)d.nz * TL * sizeof(T);
     hipLaunchKernelGGL((k_zpass_ch<T, true>), dim3((lines + TL - 1) / TL), dim3(threads), shm, st, spec,
                        d.pitch, d.ny, d.nz, lognz, TL, tb.lam_x, tb.lam_y, tb.lam_z, tb.tw_z, tb.tw_zq, c_psi,
                        alpha, scale / d.nz, dwall);
