@@ -417,8 +417,8 @@ def ingest_pmc(fetch_csv, write_csv, out_json):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU layout is a "
-              "design note, not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {a.gpus}): the step is not decomposed across GPUs",
+              file=sys.stderr)
         sys.exit(2)
     if a.ingest_pmc:
         ingest_pmc(*a.ingest_pmc)

@@ -50,7 +50,7 @@ extern "C" {
 #define DRPF_EWORKSPACE 2    /* workspace missing, too small or misaligned             */
 #define DRPF_EHIP 3          /* a HIP runtime call or kernel launch failed             */
 #define DRPF_ENONFINITE 4    /* a non-finite value was found (drpf_observables)         */
-#define DRPF_EUNSUPPORTED 5  /* valid but not supported by this build                  */
+#define DRPF_EUNSUPPORTED 5  /* valid but not supported by this library                */
 
 /* Locations for drpf_restrict (eq. dual2 generalised to 3D as a tensor product of the
  * 1D rules: along a centre-located axis coarse index i averages fine 2i and 2i+1; along a
