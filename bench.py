@@ -52,7 +52,7 @@ def parse():
                     help="further workloads timed in both forms beside the headline one ('' for none)")
     ap.add_argument("--other-steps", type=int, default=100)
     ap.add_argument("--no-error", action="store_true",
-                    help="skip the FP32-vs-FP64 per-field error runs (C2 500 steps, C3 and C3L 1000 steps)")
+                    help="skip the FP32-vs-FP64 per-field error runs (C2 500 steps, C3, C3L and C3P 1000 steps)")
     ap.add_argument("--only-adjoint", action="store_true",
                     help="run only the gradient case and print its JSON object")
     ap.add_argument("--adjoint-config", default="C4")
@@ -490,10 +490,12 @@ def main():
                        "kernels": res[64]["kernels"]}
         out["fp32_vs_fp64_speedup"] = round(res[32]["value"] / res[64]["value"], 3)
         if not a.no_error:
-            print("[bench] FP32 vs FP64 error: C2 500 steps, C3 and C3L 1000 steps", file=sys.stderr, flush=True)
+            print("[bench] FP32 vs FP64 error: C2 500 steps, C3, C3L and C3P 1000 steps", file=sys.stderr,
+                  flush=True)
             out["fp32_error_vs_fp64"] = {"C2": precision_error(drpf, W, "C2", 500),
                                          "C3": precision_error(drpf, W, "C3", 1000),
-                                         "C3L": precision_error(drpf, W, "C3L", 1000)}
+                                         "C3L": precision_error(drpf, W, "C3L", 1000),
+                                         "C3P": precision_error(drpf, W, "C3P", 1000)}
     others = [x for x in a.others.split(",") if x and x != cfg.name]
     if others:
         out["other_workloads"] = {}
