@@ -289,7 +289,8 @@ const char* const kKernelNames[DRPF_NKERNELS] = {
 
 void mark(drpf_grid* g, int kernel, hipStream_t st) {
   if (!g->prof || g->ev_used >= g->ev.size()) return;
-  hipEventRecord(g->ev[g->ev_used], st);
+  // a failed record shows up as an error of drpf_profile_end's elapsed-time query
+  (void)hipEventRecord(g->ev[g->ev_used], st);
   g->ev_kernel[g->ev_used] = kernel;
   ++g->ev_used;
 }
@@ -872,7 +873,7 @@ int drpf_init_grid(const drpf_params* p, void* d_workspace, size_t bytes, void* 
 
 int drpf_destroy(drpf_grid* g) {
   if (g)
-    for (auto e : g->ev) hipEventDestroy(e);
+    for (auto e : g->ev) (void)hipEventDestroy(e);
   delete g;
   return DRPF_OK;
 }
@@ -982,7 +983,7 @@ int drpf_profile_end(drpf_grid* g, double* total_ms, int* launches, int n) {
       if (launches) launches[k] += 1;
     }
   }
-  for (auto e : g->ev) hipEventDestroy(e);
+  for (auto e : g->ev) (void)hipEventDestroy(e);
   g->ev.clear();
   g->ev_kernel.clear();
   g->ev_used = 0;

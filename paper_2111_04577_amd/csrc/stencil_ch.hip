@@ -373,7 +373,7 @@ __global__ void __launch_bounds__(kBlock)
     }
   }
   const int tx = threadIdx.x;
-  const bool upper = threadIdx.y >= CY;
+  const bool upper = (int)threadIdx.y >= CY;
   const int ty = upper ? threadIdx.y - CY : threadIdx.y;
   const int i = i0 + tx, j = j0 + ty;
   const T r1 = (T)c.rho1, r2 = (T)c.rho2, m1 = (T)c.mu1, m2 = (T)c.mu2, hf = (T)0.5;
@@ -823,7 +823,7 @@ template <typename T>
 hipError_t launch_prolong(const Dims& f, const Dims& c, const T* u, const T* v, const T* w, T* uf,
                           T* vf, T* wf, hipStream_t st) {
   // first = 1: the star extrapolation reduces to the given level
-  Prolonged<T> pv{u, u, v, v, w, w, c.nx, c.ny, c.nz, c.ny == 1 ? 1 : 2, 1};
+  Prolonged<T> pv{u, u, v, v, w, w, c.nx, c.ny, c.nz, c.ny == 1 ? 1 : 2, 1, 0};
   const Launch3 L = launch3(f.nx, f.ny, f.nz);
   hipLaunchKernelGGL(k_prolong<T>, L.grid, L.block, 0, st, uf, vf, wf, f.nx, f.ny, pv);
   return hipGetLastError();

@@ -3,7 +3,6 @@ inputs. FP64 results must agree to 1e-10 relative per field (max |gpu - oracle| 
 max |oracle|); linear operators to 1e-12; transfers to a few ulps."""
 from __future__ import annotations
 
-import math
 import sys
 
 import numpy as np

@@ -17,7 +17,6 @@ from __future__ import annotations
 import math
 
 import numpy as np
-import pytest
 from scipy.integrate import solve_ivp
 
 import workloads as W
