@@ -18,7 +18,7 @@ Per-kernel durations come from HIP events recorded by the library after every la
 (drpf_profile_begin / drpf_profile_end) in a second pass of K steps; the roofline entry is
 for the kernel with the largest share of that time.
 
-Prints ONE JSON line. ``--gpus N`` with N > 1 exits: the build targets one GPU.
+Prints ONE JSON line. ``--gpus N`` with N > 1 exits: the library targets one GPU.
 """
 from __future__ import annotations
 
@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--config", default="C2")
     ap.add_argument("--precision", choices=["both", "32", "64"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -70,8 +70,9 @@ def parse():
 # ---------------------------------------------------------------------------------------
 
 def grid_sizes(cfg):
-    ry = 1 if cfg.ny == 1 else 2
-    F = dict(nx=2 * cfg.nx, ny=ry * cfg.ny, nz=2 * cfg.nz)
+    r = 1 if cfg.refine == 1 else 2  # single resolution: the phase field on the flow grid
+    ry = 1 if cfg.ny == 1 else r
+    F = dict(nx=r * cfg.nx, ny=ry * cfg.ny, nz=r * cfg.nz)
     C = dict(nx=cfg.nx, ny=cfg.ny, nz=cfg.nz)
     for d in (F, C):
         d["cells"] = d["nx"] * d["ny"] * d["nz"]
@@ -94,7 +95,9 @@ def alg_bytes(kernel, cfg, es):
         "zpass_ch": 2 * sf,
         "fft_y_inv_fine": 2 * sf if F["ny"] > 1 else 0,
         "fft_x_inv_fine": sf + nf,
-        "restrict_g": 3 * nf + 10 * nc + 2 * ne,
+        # single resolution: G and phi at the cells (2 N_c written), then faces and edges from
+        # them (2 N_c read back) in a second kernel, both under this timing id
+        "restrict_g": 3 * nf + (12 if cfg.refine == 1 else 10) * nc + 2 * ne,
         "momentum_rhs": (8 + 10 + 12 * ve + 3) * nc + 2 * ne,
         "fft_x_fwd_coarse": 3 * nc + 3 * sc,
         "fft_y_fwd_coarse": 6 * sc if C["ny"] > 1 else 0,
@@ -112,7 +115,8 @@ def alg_bytes(kernel, cfg, es):
 
 
 KERNEL_SOURCE = {
-    "ch_rhs": "stencil_ch.hip", "restrict_g": "stencil_ch.hip", "weno_adv_fine": "stencil_ch.hip", "momentum_rhs": "stencil_ns.hip",
+    "ch_rhs": "stencil_ch.hip", "restrict_g": "stencil_ch.hip", "weno_adv_fine": "stencil_ch.hip",
+    "momentum_rhs": "stencil_ns.hip",
     "polymer_stage1": "stencil_ns.hip", "polymer_stage2": "stencil_ns.hip",
     "zpass_ch": "tridiag.hip", "zpass_ns": "tridiag.hip",
 }
