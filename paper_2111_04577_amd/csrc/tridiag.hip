@@ -334,6 +334,100 @@ __global__ void __launch_bounds__(1024)
 }
 
 // ---- Navier-Stokes projection -------------------------------------------------------
+// Reciprocal of a diagonal entry: the hardware estimate refined by Newton-Raphson steps
+// (r <- r + r (1 - b r)), one for FP32 and two for FP64, each squaring the relative error of
+// the estimate; the diagonals of the projection's systems are far from zero and overflow.
+__device__ __forceinline__ float recip(float b) {
+  const float r = __builtin_amdgcn_rcpf(b);
+  return fmaf(r, fmaf(-b, r, 1.0f), r);
+}
+__device__ __forceinline__ double recip(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  return fma(r, fma(-b, r, 1.0), r);
+}
+
+// PCR over several symmetric systems at once: NM matrices with NR right-hand sides,
+// right-hand side r belonging to matrix (MAP >> r) & 1, so that one barrier pair per
+// reduction step serves them all. A reduction step keeps a symmetric matrix symmetric (the
+// coupling of row i to row i - s equals that of row i - s to row i), so a row takes from each
+// neighbour only its reciprocal diagonal, its outer coupling and its right-hand sides:
+//   b_i <- b_i - a_i^2 / b_{i-s} - c_i^2 / b_{i+s},  a_i <- -a_i a_{i-s} / b_{i-s},
+//   c_i <- -c_i c_{i+s} / b_{i+s},  d_i <- d_i - a_i d_{i-s} / b_{i-s} - c_i d_{i+s} / b_{i+s}.
+// On entry (a, b, c, d) hold the thread's row (a = 0 on the first row, c = 0 on the last); on
+// exit d holds the solution. LDS: NM planes each of a, c and 1/b, then NR complex planes,
+// each [row][line] of n * TL entries.
+template <typename A, int NM, int NR, int MAP>
+__device__ __forceinline__ void pcr_sym(unsigned char* base, int n, int TL, int row, int line,
+                                        A (&a)[NM], A (&b)[NM], A (&c)[NM], cx<A> (&d)[NR]) {
+  const int plane = n * TL;
+  const int me = row * TL + line;
+  A* La = reinterpret_cast<A*>(base);
+  A* Lc = La + NM * plane;
+  A* Lib = Lc + NM * plane;
+  cx<A>* Ld = reinterpret_cast<cx<A>*>(Lib + NM * plane);
+  A ib[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) ib[m] = recip(b[m]);
+  for (int s = 1; s < n; s <<= 1) {
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      La[m * plane + me] = a[m];
+      Lc[m * plane + me] = c[m];
+      Lib[m * plane + me] = ib[m];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) Ld[r * plane + me] = d[r];
+    __syncthreads();
+    A al[NM], ga[NM], am[NM], cp[NM];
+    cx<A> dm[NR], dp[NR];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) al[m] = ga[m] = am[m] = cp[m] = (A)0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) dm[r] = dp[r] = mk<A>(0, 0);
+    if (row - s >= 0) {
+      const int q = me - s * TL;
+#pragma unroll
+      for (int m = 0; m < NM; ++m) {
+        al[m] = -a[m] * Lib[m * plane + q];
+        am[m] = La[m * plane + q];
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) dm[r] = Ld[r * plane + q];
+    }
+    if (row + s < n) {
+      const int q = me + s * TL;
+#pragma unroll
+      for (int m = 0; m < NM; ++m) {
+        ga[m] = -c[m] * Lib[m * plane + q];
+        cp[m] = Lc[m * plane + q];
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) dp[r] = Ld[r * plane + q];
+    }
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      b[m] = b[m] + al[m] * a[m] + ga[m] * c[m];
+      a[m] = al[m] * am[m];
+      c[m] = ga[m] * cp[m];
+      ib[m] = recip(b[m]);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int m = (MAP >> r) & 1;
+      d[r] = mk<A>(d[r].re + al[m] * dm[r].re + ga[m] * dp[r].re, d[r].im + al[m] * dm[r].im + ga[m] * dp[r].im);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) d[r] = ib[(MAP >> r) & 1] * d[r];
+}
+
+template <typename A, int NM, int NR>
+size_t pcr_sym_bytes(int n, int TL) {
+  return (size_t)n * TL * (3 * NM * sizeof(A) + NR * sizeof(cx<A>));
+}
+
 // spec holds four fields of Nz*Ny*P complex each: r_u, r_v, r_w on entry (fields 0-2); on
 // exit u^{n+1}, v^{n+1}, w^{n+1} and the pressure increment p' (field 3).
 template <typename T>
@@ -356,54 +450,49 @@ __global__ void __launch_bounds__(1024)
   const size_t fsz = stride * Nz;
   const size_t at = row * stride + l;
   const double lxy = lamx[kx] + lamy[ky];
-  const bool end = row == 0 || row == Nz - 1;
+  const bool top = row == Nz - 1;
+  const bool end = row == 0 || top;
   const T sc = (T)scale;
-  // ---- velocity Helmholtz (nu_m L - gamma0/dt) u~ = r, no-slip walls (u, v)
+  // ---- velocity Helmholtz (nu_m L - gamma0/dt) u~ = r: no-slip walls for u and v at cell
+  // centres; w on z faces k = 0..Nz-2, the top-wall row an identity row. Both operators are
+  // reduced together.
   const double av = nu_m * ihz * ihz;
-  cx<T> uv[2];
-  uv[0] = valid ? sc * spec[at] : mk<T>(0, 0);
-  uv[1] = valid ? sc * spec[fsz + at] : mk<T>(0, 0);
-  PcrLds<T, 2> L2 = carve<T, 2>(smem, Nz, TL);
-  pcr<T, 2>(L2, Nz, TL, row, line, row == 0 ? (T)0 : (T)av,
-            (T)(nu_m * lxy - (end ? 3.0 : 2.0) * av - g_dt), row == Nz - 1 ? (T)0 : (T)av, uv);
-  // w on z faces k = 0..Nz-2; the top-wall row is an identity row
-  cx<T> w[1];
-  w[0] = (valid && row < Nz - 1) ? sc * spec[2 * fsz + at] : mk<T>(0, 0);
-  PcrLds<T, 1> L1 = carve<T, 1>(smem, Nz, TL);
-  {
-    const T aw = (T)av;
-    const bool top = row == Nz - 1;
-    pcr<T, 1>(L1, Nz, TL, row, line, (row == 0 || top) ? (T)0 : aw,
-              top ? (T)1 : (T)(nu_m * lxy - 2.0 * av - g_dt), (row >= Nz - 2) ? (T)0 : aw, w);
-    if (top) w[0] = mk<T>(0, 0);
-  }
+  T a[2], b[2], c[2];
+  cx<T> d[3];
+  d[0] = valid ? sc * spec[at] : mk<T>(0, 0);
+  d[1] = valid ? sc * spec[fsz + at] : mk<T>(0, 0);
+  d[2] = (valid && !top) ? sc * spec[2 * fsz + at] : mk<T>(0, 0);
+  a[0] = row == 0 ? (T)0 : (T)av;
+  c[0] = top ? (T)0 : (T)av;
+  b[0] = (T)(nu_m * lxy - (end ? 3.0 : 2.0) * av - g_dt);
+  a[1] = (row == 0 || top) ? (T)0 : (T)av;
+  c[1] = (row >= Nz - 2) ? (T)0 : (T)av;
+  b[1] = top ? (T)1 : (T)(nu_m * lxy - 2.0 * av - g_dt);
+  pcr_sym<T, 2, 3, 4>(smem, Nz, TL, row, line, a, b, c, d);
+  if (top) d[2] = mk<T>(0, 0);
   // ---- divergence at centres: D_x = (1 - e^{-i th_x}) / hx, D_z w = (w_k - w_{k-1}) / hz
   cx<double>* Lw = reinterpret_cast<cx<double>*>(smem);
-  __syncthreads();
-  Lw[row * TL + line] = widen<double>(w[0]);
+  const cx<double> u = widen<double>(d[0]), v = widen<double>(d[1]), wk = widen<double>(d[2]);
+  Lw[row * TL + line] = wk;
   __syncthreads();
   const double cxr = phx[2 * kx], cxi = phx[2 * kx + 1];
   const double cyr = phy[2 * ky], cyi = phy[2 * ky + 1];
   const double dxr = (1.0 - cxr) * ihx, dxi = cxi * ihx;
   const double dyr = (1.0 - cyr) * ihy, dyi = cyi * ihy;
-  const cx<double> u = widen<double>(uv[0]), v = widen<double>(uv[1]);
-  const cx<double> wk = Lw[row * TL + line];
   const cx<double> wm = row > 0 ? Lw[(row - 1) * TL + line] : mk<double>(0, 0);
   cx<double> p[1];
   p[0] = mk<double>(g_rho_dt * (dxr * u.re - dxi * u.im + dyr * v.re - dyi * v.im + (wk.re - wm.re) * ihz),
                     g_rho_dt * (dxr * u.im + dxi * u.re + dyr * v.im + dyi * v.re + (wk.im - wm.im) * ihz));
   __syncthreads();
-  // ---- FP64 Poisson (Neumann) for p'; the (0,0) mode is pinned at row 0, mean removed
+  // ---- FP64 Poisson (Neumann) for p'; the (0,0) mode is pinned at row 0, its mean removed
   const double ap = ihz * ihz;
   const bool pinned = kx == 0 && ky == 0;
-  double pa = row == 0 ? 0.0 : ap, pc = row == Nz - 1 ? 0.0 : ap;
-  double pb = lxy - (end ? 1.0 : 2.0) * ap;
+  double pa[1] = {row == 0 ? 0.0 : ap}, pc[1] = {top ? 0.0 : ap}, pb[1] = {lxy - (end ? 1.0 : 2.0) * ap};
   if (pinned) {
-    if (row == 0) { pa = 0.0; pc = 0.0; pb = 1.0; p[0] = mk<double>(0, 0); }
-    if (row == 1) pa = 0.0;
+    if (row == 0) { pa[0] = 0.0; pc[0] = 0.0; pb[0] = 1.0; p[0] = mk<double>(0, 0); }
+    if (row == 1) pa[0] = 0.0;
   }
-  PcrLds<double, 1> LP = carve<double, 1>(smem, Nz, TL);
-  pcr<double, 1>(LP, Nz, TL, row, line, pa, pb, pc, p);
+  pcr_sym<double, 1, 1, 0>(smem, Nz, TL, row, line, pa, pb, pc, p);
   cx<double>* Lp = reinterpret_cast<cx<double>*>(smem);
   Lp[row * TL + line] = p[0];
   __syncthreads();
@@ -420,17 +509,15 @@ __global__ void __launch_bounds__(1024)
     pup = mk<double>(pup.re - mre, pup.im - mim);
   }
   // ---- correction u = u~ - c grad p', G_x = (e^{i th_x} - 1) / hx
-  const double c = 1.0 / g_rho_dt;
+  const double cg = 1.0 / g_rho_dt;
   const double gxr = (cxr - 1.0) * ihx, gxi = cxi * ihx;
   const double gyr = (cyr - 1.0) * ihy, gyi = cyi * ihy;
   const double pr = p[0].re, pi = p[0].im;
   if (valid) {
-    spec[at] = mk<T>((T)(u.re - c * (gxr * pr - gxi * pi)), (T)(u.im - c * (gxr * pi + gxi * pr)));
-    spec[fsz + at] = mk<T>((T)(v.re - c * (gyr * pr - gyi * pi)), (T)(v.im - c * (gyr * pi + gyi * pr)));
-    const cx<double> wv = wk;
-    spec[2 * fsz + at] = row < Nz - 1
-                             ? mk<T>((T)(wv.re - c * (pup.re - pr) * ihz), (T)(wv.im - c * (pup.im - pi) * ihz))
-                             : mk<T>(0, 0);
+    spec[at] = mk<T>((T)(u.re - cg * (gxr * pr - gxi * pi)), (T)(u.im - cg * (gxr * pi + gxi * pr)));
+    spec[fsz + at] = mk<T>((T)(v.re - cg * (gyr * pr - gyi * pi)), (T)(v.im - cg * (gyr * pi + gyi * pr)));
+    spec[2 * fsz + at] = top ? mk<T>(0, 0)
+                             : mk<T>((T)(wk.re - cg * (pup.re - pr) * ihz), (T)(wk.im - cg * (pup.im - pi) * ihz));
     spec[3 * fsz + at] = mk<T>((T)pr, (T)pi);
   }
 }
@@ -596,11 +683,15 @@ template <typename T>
 hipError_t launch_zpass_ns(const Dims& d, const Tables<T>& tb, cx<T>* spec4, const StepConsts& c,
                            double scale, hipStream_t st) {
   const int lines = d.lines();
-  const int TL = spread_lines(tile_lines(d.nz), lines, 2048);
-  size_t shm = pcr_bytes<T, 2>(d.nz, TL);
-  const size_t shm64 = pcr_bytes<double, 1>(d.nz, TL);
-  if (shm64 > shm) shm = shm64;
-  hipLaunchKernelGGL(k_zpass_ns<T>, dim3((lines + TL - 1) / TL), dim3(TL * d.nz), shm, st, spec4,
+  auto shm_of = [&](int tl) {
+    const size_t a = pcr_sym_bytes<T, 2, 3>(d.nz, tl), b = pcr_sym_bytes<double, 1, 1>(d.nz, tl);
+    return a > b ? a : b;
+  };
+  // at most 64 KB of LDS per block (the FP64 form of a 1024-thread block would need 96 KB)
+  int TL = tile_lines(d.nz);
+  while (TL > 1 && shm_of(TL) > 65536) TL >>= 1;
+  TL = spread_lines(TL, lines, 2048);
+  hipLaunchKernelGGL(k_zpass_ns<T>, dim3((lines + TL - 1) / TL), dim3(TL * d.nz), shm_of(TL), st, spec4,
                      d.pitch, d.ny, d.nz, tb.lam_x, tb.lam_y, tb.ph_x, tb.ph_y, 1.0 / d.hx, 1.0 / d.hy,
                      1.0 / d.hz, c.nu_m, c.gamma0 / c.dt, c.gamma0 * c.rho0 / c.dt, scale);
   return hipGetLastError();
