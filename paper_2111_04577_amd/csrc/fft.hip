@@ -39,7 +39,9 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_fwd(const T* __restrict__ in0,
   const int field = line0 / lines_per_field;
   const T* in = field == 0 ? in0 : (field == 1 ? in1 : in2);
   const T* src = in + (size_t)(line0 - field * lines_per_field) * N;
-  for (int e = threadIdx.x; e < nl * M; e += blockDim.x) buf[e] = mk<T>(src[2 * e], src[2 * e + 1]);
+  // a row of N reals read as N/2 (even, odd) pairs: rows start at even offsets of arrays
+  // aligned to at least 16 bytes, so each pair is one aligned load
+  for (int e = threadIdx.x; e < nl * M; e += blockDim.x) buf[e] = reinterpret_cast<const cx<T>*>(src)[e];
   __syncthreads();
   lds_fft<T, false, false>(buf, M, logM, nl, 0, stw);
   // row r = z Ny + ky of this field
@@ -105,14 +107,11 @@ __global__ void __launch_bounds__(kBlock) k_fft_x_inv(const cx<T>* __restrict__ 
   if (add != nullptr) {
     add += (size_t)(line0 - field * lines_per_field) * N;
     for (int e = threadIdx.x; e < nl * M; e += blockDim.x) {
-      dst[2 * e] = add[2 * e] + buf[e].re;
-      dst[2 * e + 1] = add[2 * e + 1] + buf[e].im;
+      const cx<T> a = reinterpret_cast<const cx<T>*>(add)[e];
+      reinterpret_cast<cx<T>*>(dst)[e] = mk<T>(a.re + buf[e].re, a.im + buf[e].im);
     }
   } else {
-    for (int e = threadIdx.x; e < nl * M; e += blockDim.x) {
-      dst[2 * e] = buf[e].re;
-      dst[2 * e + 1] = buf[e].im;
-    }
+    for (int e = threadIdx.x; e < nl * M; e += blockDim.x) reinterpret_cast<cx<T>*>(dst)[e] = buf[e];
   }
 }
 
@@ -179,7 +178,7 @@ __global__ void __launch_bounds__(1024)
   for (int e = threadIdx.x; e < M; e += blockDim.x) sM[e] = twM[e];
   for (int e = threadIdx.x; e < Ny; e += blockDim.x) sY[e] = twY[e];
   const int n = Ny << logM;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) A[e] = mk<T>(src[2 * e], src[2 * e + 1]);
+  for (int e = threadIdx.x; e < n; e += blockDim.x) A[e] = reinterpret_cast<const cx<T>*>(src)[e];
   __syncthreads();
   lds_fft_rep<T, false, false, REP>(A, M, logM, Ny, 0, sM);
   const int half = M >> 1;
@@ -207,8 +206,7 @@ __global__ void __launch_bounds__(1024)
     }
   }
   __syncthreads();
-  lds_fft_rep<T, false, true, REP>(A, Ny, logNy, M, logM, sY);
-  lds_fft<T, false, true>(Q, Ny, logNy, 1, 0, sY);
+  lds_fft_rep<T, false, true, REP, true>(A, Ny, logNy, M, logM, sY, Q);
   const size_t lines = (size_t)(M + 1) * Ny;
   cx<T>* dst = out + (size_t)field * lines * nz + (size_t)z * lines;
   for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = A[e];
@@ -235,8 +233,7 @@ __global__ void __launch_bounds__(1024)
   for (int e = threadIdx.x; e < n; e += blockDim.x) A[e] = src[e];
   for (int e = threadIdx.x; e < Ny; e += blockDim.x) Q[e] = src[(size_t)M * Ny + e];
   __syncthreads();
-  lds_fft_rep<T, true, true, REP>(A, Ny, logNy, M, logM, sY);
-  lds_fft<T, true, true>(Q, Ny, logNy, 1, 0, sY);
+  lds_fft_rep<T, true, true, REP, true>(A, Ny, logNy, M, logM, sY, Q);
   // c2r: z_k = E + i O, E = X_k + conj(X_{M-k}), O = conj(w_k)(X_k - conj(X_{M-k})), with
   // X_{M-0} read as the Nyquist mode
   const int half = M >> 1;
@@ -266,14 +263,11 @@ __global__ void __launch_bounds__(1024)
   if (add != nullptr) {
     add += (size_t)z * Ny * N;
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
-      dst[2 * e] = add[2 * e] + A[e].re;
-      dst[2 * e + 1] = add[2 * e + 1] + A[e].im;
+      const cx<T> a = reinterpret_cast<const cx<T>*>(add)[e];
+      reinterpret_cast<cx<T>*>(dst)[e] = mk<T>(a.re + A[e].re, a.im + A[e].im);
     }
   } else {
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-      dst[2 * e] = A[e].re;
-      dst[2 * e + 1] = A[e].im;
-    }
+    for (int e = threadIdx.x; e < n; e += blockDim.x) reinterpret_cast<cx<T>*>(dst)[e] = A[e];
   }
 }
 

@@ -88,14 +88,17 @@ __device__ __forceinline__ void lds_fft(cx<T>* buf, int M, int logM, int nlines,
 // The same transform with REP butterfly sets per thread: set s = threadIdx.x + r blockDim.x,
 // r < REP, of the nlines * max(M/4, 1) sets (line and set numbered as in lds_fft). For
 // batches that need more sets than a block has threads (a whole coarse layer in one block).
-template <typename T, bool INV, bool LF, int REP>
+// With XL, one more line of the same length, contiguous at xl, is transformed in the same
+// stages (its sets on threads 0 .. max(M/4, 1) - 1), sharing their barriers.
+template <typename T, bool INV, bool LF, int REP, bool XL = false>
 __device__ __forceinline__ void lds_fft_rep(cx<T>* buf, int M, int logM, int nlines, int lnl,
-                                            const cx<T>* __restrict__ tw) {
+                                            const cx<T>* __restrict__ tw, cx<T>* xl = nullptr) {
+  constexpr int NS = REP + (XL ? 1 : 0);
   const int lq = logM >= 2 ? logM - 2 : 0;
   const int quarter = 1 << lq;
   const int nsets = nlines << lq;
-  int bs[REP], qs[REP];
-  bool act[REP];
+  int bs[NS], qs[NS];
+  bool act[NS];
 #pragma unroll
   for (int r = 0; r < REP; ++r) {
     const int s = threadIdx.x + r * blockDim.x;
@@ -103,30 +106,38 @@ __device__ __forceinline__ void lds_fft_rep(cx<T>* buf, int M, int logM, int nli
     qs[r] = LF ? s >> lnl : s & (quarter - 1);
     bs[r] = LF ? s & ((1 << lnl) - 1) : s >> lq;
   }
-  auto at = [&](int b, int n) -> cx<T>& { return LF ? buf[(n << lnl) + b] : buf[(b << logM) + n]; };
+  if (XL) {
+    act[NS - 1] = (int)threadIdx.x < quarter;
+    qs[NS - 1] = threadIdx.x;
+    bs[NS - 1] = 0;
+  }
+  auto at = [&](int r, int n) -> cx<T>& {
+    if (XL && r == NS - 1) return xl[n];
+    return LF ? buf[(n << lnl) + bs[r]] : buf[(bs[r] << logM) + n];
+  };
   int lNs = 0;
   if (logM & 1) {
     const int half = M >> 1;
-    cx<T> v[REP][4];
+    cx<T> v[NS][4];
 #pragma unroll
-    for (int r = 0; r < REP; ++r)
+    for (int r = 0; r < NS; ++r)
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int j = qs[r] + (h << lq);
         if (act[r] && j < half) {
-          v[r][2 * h] = at(bs[r], j);
-          v[r][2 * h + 1] = at(bs[r], j + half);
+          v[r][2 * h] = at(r, j);
+          v[r][2 * h + 1] = at(r, j + half);
         }
       }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < REP; ++r)
+    for (int r = 0; r < NS; ++r)
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int j = qs[r] + (h << lq);
         if (act[r] && j < half) {
-          at(bs[r], 2 * j) = v[r][2 * h] + v[r][2 * h + 1];
-          at(bs[r], 2 * j + 1) = v[r][2 * h] - v[r][2 * h + 1];
+          at(r, 2 * j) = v[r][2 * h] + v[r][2 * h + 1];
+          at(r, 2 * j + 1) = v[r][2 * h] - v[r][2 * h + 1];
         }
       }
     __syncthreads();
@@ -134,16 +145,16 @@ __device__ __forceinline__ void lds_fft_rep(cx<T>* buf, int M, int logM, int nli
   }
   for (; lNs < logM; lNs += 2) {
     const int Ns = 1 << lNs;
-    cx<T> v[REP][4];
+    cx<T> v[NS][4];
 #pragma unroll
-    for (int r = 0; r < REP; ++r)
+    for (int r = 0; r < NS; ++r)
       if (act[r]) {
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) v[r][rr] = at(bs[r], qs[r] + (rr << lq));
+        for (int rr = 0; rr < 4; ++rr) v[r][rr] = at(r, qs[r] + (rr << lq));
       }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < REP; ++r) {
+    for (int r = 0; r < NS; ++r) {
       if (act[r]) {
         const int j = qs[r];
         const int k = j & (Ns - 1);
@@ -155,10 +166,10 @@ __device__ __forceinline__ void lds_fft_rep(cx<T>* buf, int M, int logM, int nli
                     d = v[r][1] - v[r][3];
         const cx<T> jd = INV ? mul_i(d) : mul_mi(d);
         const int base = ((j - k) << 2) + k;
-        at(bs[r], base) = a + c;
-        at(bs[r], base + Ns) = bb + jd;
-        at(bs[r], base + 2 * Ns) = a - c;
-        at(bs[r], base + 3 * Ns) = bb - jd;
+        at(r, base) = a + c;
+        at(r, base + Ns) = bb + jd;
+        at(r, base + 2 * Ns) = a - c;
+        at(r, base + 3 * Ns) = bb - jd;
       }
     }
     __syncthreads();
