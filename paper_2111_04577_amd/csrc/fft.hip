@@ -189,8 +189,11 @@ __global__ void __launch_bounds__(1024)
     const cx<T> O = hf * mul_mi(zk - zmc);
     return E + twN[k] * O;
   };
-  for (int e = threadIdx.x; e < Ny * (half + 1); e += blockDim.x) {
-    const int y = e / (half + 1), k = e - y * (half + 1);
+  // pairs k < half of every row (shifts and masks), then k = half of every row
+  const int lh = logM - 1, nmain = Ny << lh;
+  for (int e = threadIdx.x; e < nmain + Ny; e += blockDim.x) {
+    const bool mid = e >= nmain;
+    const int y = mid ? e - nmain : e >> lh, k = mid ? half : e & (half - 1);
     cx<T>* row = A + (y << logM);
     if (k == 0) {
       const cx<T> a = row[0];
@@ -242,8 +245,11 @@ __global__ void __launch_bounds__(1024)
     const cx<T> O = conj(twN[k]) * (xk - xmc);
     return E + mul_i(O);
   };
-  for (int e = threadIdx.x; e < Ny * (half + 1); e += blockDim.x) {
-    const int y = e / (half + 1), k = e - y * (half + 1);
+  // pairs k < half of every row (shifts and masks), then k = half of every row
+  const int lh = logM - 1, nmain = Ny << lh;
+  for (int e = threadIdx.x; e < nmain + Ny; e += blockDim.x) {
+    const bool mid = e >= nmain;
+    const int y = mid ? e - nmain : e >> lh, k = mid ? half : e & (half - 1);
     cx<T>* row = A + (y << logM);
     if (k == 0) {
       row[0] = join(row[0], conj(Q[y]), 0);
