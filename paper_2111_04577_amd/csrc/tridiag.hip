@@ -7,7 +7,8 @@
 // (row, mode); the rows of a z level are contiguous in memory, so the tile is loaded and
 // stored with coalesced accesses. Each of the log2(n) PCR steps eliminates the couplings
 // at distance s from every row at once; the reciprocal of every diagonal is kept beside it
-// so that a step costs one division per row.
+// so that a step costs one reciprocal per row. Every operator here is symmetric, which the
+// reduction preserves and uses (pcr_sym).
 //
 // Passes:
 //   zpass_ch  -- the two Helmholtz operators of the Dong splitting (eqs. NS26-NS27),
@@ -25,84 +26,98 @@ namespace drpf {
 
 namespace {
 
-// LDS scratch of one PCR: per (row, line) the off-diagonals a, c, the reciprocal of the
-// diagonal, and NR complex right-hand sides. Row-major [row][line].
-template <typename A, int NR>
-struct PcrLds {
-  A* a;
-  A* c;
-  A* ib;
-  cx<A>* d;  // NR planes of n * TL
-};
+// Reciprocal of a diagonal entry: the hardware estimate refined by Newton-Raphson steps
+// (r <- r + r (1 - b r)), one for FP32 and two for FP64, each squaring the relative error of
+// the estimate; the diagonals of the projection's systems are far from zero and overflow.
+__device__ __forceinline__ float recip(float b) {
+  const float r = __builtin_amdgcn_rcpf(b);
+  return fmaf(r, fmaf(-b, r, 1.0f), r);
+}
+__device__ __forceinline__ double recip(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  return fma(r, fma(-b, r, 1.0), r);
+}
 
-// One PCR solve for the calling thread's row. On entry (a, b, c, d[NR]) hold the thread's
-// row (a = 0 on the first row, c = 0 on the last); on exit d[r] holds x_row. Every thread of
-// the block must call this with the same n.
-template <typename A, int NR>
-__device__ __forceinline__ void pcr(PcrLds<A, NR> L, int n, int TL, int row, int line, A a, A b,
-                                    A c, cx<A>* d) {
-  A ib = (A)1 / b;
-  const int me = row * TL + line;
+// PCR over several symmetric systems at once: NM matrices with NR right-hand sides,
+// right-hand side r belonging to matrix (MAP >> r) & 1, so that one barrier pair per
+// reduction step serves them all. A reduction step keeps a symmetric matrix symmetric (the
+// coupling of row i to row i - s equals that of row i - s to row i), so a row takes from each
+// neighbour only its reciprocal diagonal, its outer coupling and its right-hand sides:
+//   b_i <- b_i - a_i^2 / b_{i-s} - c_i^2 / b_{i+s},  a_i <- -a_i a_{i-s} / b_{i-s},
+//   c_i <- -c_i c_{i+s} / b_{i+s},  d_i <- d_i - a_i d_{i-s} / b_{i-s} - c_i d_{i+s} / b_{i+s}.
+// On entry (a, b, c, d) hold the thread's row (a = 0 on the first row, c = 0 on the last); on
+// exit d holds the solution. LDS: NM planes each of a, c and 1/b, then NR complex planes,
+// each [row][line] of n * TL entries.
+template <typename A, int NM, int NR, int MAP>
+__device__ __forceinline__ void pcr_sym(unsigned char* base, int n, int TL, int row, int line,
+                                        A (&a)[NM], A (&b)[NM], A (&c)[NM], cx<A> (&d)[NR]) {
   const int plane = n * TL;
+  const int me = row * TL + line;
+  A* La = reinterpret_cast<A*>(base);
+  A* Lc = La + NM * plane;
+  A* Lib = Lc + NM * plane;
+  cx<A>* Ld = reinterpret_cast<cx<A>*>(Lib + NM * plane);
+  A ib[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) ib[m] = recip(b[m]);
   for (int s = 1; s < n; s <<= 1) {
-    L.a[me] = a;
-    L.c[me] = c;
-    L.ib[me] = ib;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) L.d[r * plane + me] = d[r];
+    for (int m = 0; m < NM; ++m) {
+      La[m * plane + me] = a[m];
+      Lc[m * plane + me] = c[m];
+      Lib[m * plane + me] = ib[m];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) Ld[r * plane + me] = d[r];
     __syncthreads();
-    A alpha = 0, gamma = 0, cm = 0, ap = 0, am = 0, cp = 0;
+    A al[NM], ga[NM], am[NM], cp[NM];
     cx<A> dm[NR], dp[NR];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) al[m] = ga[m] = am[m] = cp[m] = (A)0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) dm[r] = dp[r] = mk<A>(0, 0);
     if (row - s >= 0) {
-      const int m = me - s * TL;
-      alpha = -a * L.ib[m];
-      am = L.a[m];
-      cm = L.c[m];
+      const int q = me - s * TL;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) dm[r] = L.d[r * plane + m];
-    } else {
+      for (int m = 0; m < NM; ++m) {
+        al[m] = -a[m] * Lib[m * plane + q];
+        am[m] = La[m * plane + q];
+      }
 #pragma unroll
-      for (int r = 0; r < NR; ++r) dm[r] = mk<A>(0, 0);
+      for (int r = 0; r < NR; ++r) dm[r] = Ld[r * plane + q];
     }
     if (row + s < n) {
-      const int p = me + s * TL;
-      gamma = -c * L.ib[p];
-      ap = L.a[p];
-      cp = L.c[p];
+      const int q = me + s * TL;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) dp[r] = L.d[r * plane + p];
-    } else {
+      for (int m = 0; m < NM; ++m) {
+        ga[m] = -c[m] * Lib[m * plane + q];
+        cp[m] = Lc[m * plane + q];
+      }
 #pragma unroll
-      for (int r = 0; r < NR; ++r) dp[r] = mk<A>(0, 0);
+      for (int r = 0; r < NR; ++r) dp[r] = Ld[r * plane + q];
     }
-    b = b + alpha * cm + gamma * ap;
-    a = alpha * am;
-    c = gamma * cp;
 #pragma unroll
-    for (int r = 0; r < NR; ++r)
-      d[r] = mk<A>(d[r].re + alpha * dm[r].re + gamma * dp[r].re,
-                   d[r].im + alpha * dm[r].im + gamma * dp[r].im);
-    ib = (A)1 / b;
+    for (int m = 0; m < NM; ++m) {
+      b[m] = b[m] + al[m] * a[m] + ga[m] * c[m];
+      a[m] = al[m] * am[m];
+      c[m] = ga[m] * cp[m];
+      ib[m] = recip(b[m]);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int m = (MAP >> r) & 1;
+      d[r] = mk<A>(d[r].re + al[m] * dm[r].re + ga[m] * dp[r].re, d[r].im + al[m] * dm[r].im + ga[m] * dp[r].im);
+    }
     __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < NR; ++r) d[r] = ib * d[r];
+  for (int r = 0; r < NR; ++r) d[r] = ib[(MAP >> r) & 1] * d[r];
 }
 
-template <typename A, int NR>
-__device__ __forceinline__ PcrLds<A, NR> carve(unsigned char* base, int n, int TL) {
-  PcrLds<A, NR> L;
-  const size_t plane = (size_t)n * TL;
-  L.a = reinterpret_cast<A*>(base);
-  L.c = L.a + plane;
-  L.ib = L.c + plane;
-  L.d = reinterpret_cast<cx<A>*>(L.ib + plane);
-  return L;
-}
-
-template <typename A, int NR>
-size_t pcr_bytes(int n, int TL) {
-  return (size_t)n * TL * (3 * sizeof(A) + NR * sizeof(cx<A>));
+template <typename A, int NM, int NR>
+size_t pcr_sym_bytes(int n, int TL) {
+  return (size_t)n * TL * (3 * NM * sizeof(A) + NR * sizeof(cx<A>));
 }
 
 int tile_lines(int n) { return n >= 1024 ? 1 : 1024 / n; }
@@ -154,16 +169,19 @@ __global__ void __launch_bounds__(1024)
     if (row == 1) ar = 0.0;
   }
   (void)n;
-  PcrLds<double, 1> L = carve<double, 1>(smem, Nz, TL);
-  pcr<double, 1>(L, Nz, TL, row, line, ar, br, cr, d);
+  {
+    double a1[1] = {ar}, b1[1] = {br}, c1[1] = {cr};
+    pcr_sym<double, 1, 1, 0>(smem, Nz, TL, row, line, a1, b1, c1, d);
+  }
   // zero-mean of the pinned mode: every thread takes part in the barrier
-  L.d[row * TL + line] = d[0];
+  cx<double>* Ld = reinterpret_cast<cx<double>*>(smem);
+  Ld[row * TL + line] = d[0];
   __syncthreads();
   if (pinned) {
     double mre = 0, mim = 0;
     for (int k = 0; k < Nz; ++k) {
-      mre += L.d[k * TL + line].re;
-      mim += L.d[k * TL + line].im;
+      mre += Ld[k * TL + line].re;
+      mim += Ld[k * TL + line].im;
     }
     d[0] = mk<double>(d[0].re - mre / Nz, d[0].im - mim / Nz);
   }
@@ -334,100 +352,6 @@ __global__ void __launch_bounds__(1024)
 }
 
 // ---- Navier-Stokes projection -------------------------------------------------------
-// Reciprocal of a diagonal entry: the hardware estimate refined by Newton-Raphson steps
-// (r <- r + r (1 - b r)), one for FP32 and two for FP64, each squaring the relative error of
-// the estimate; the diagonals of the projection's systems are far from zero and overflow.
-__device__ __forceinline__ float recip(float b) {
-  const float r = __builtin_amdgcn_rcpf(b);
-  return fmaf(r, fmaf(-b, r, 1.0f), r);
-}
-__device__ __forceinline__ double recip(double b) {
-  double r = __builtin_amdgcn_rcp(b);
-  r = fma(r, fma(-b, r, 1.0), r);
-  return fma(r, fma(-b, r, 1.0), r);
-}
-
-// PCR over several symmetric systems at once: NM matrices with NR right-hand sides,
-// right-hand side r belonging to matrix (MAP >> r) & 1, so that one barrier pair per
-// reduction step serves them all. A reduction step keeps a symmetric matrix symmetric (the
-// coupling of row i to row i - s equals that of row i - s to row i), so a row takes from each
-// neighbour only its reciprocal diagonal, its outer coupling and its right-hand sides:
-//   b_i <- b_i - a_i^2 / b_{i-s} - c_i^2 / b_{i+s},  a_i <- -a_i a_{i-s} / b_{i-s},
-//   c_i <- -c_i c_{i+s} / b_{i+s},  d_i <- d_i - a_i d_{i-s} / b_{i-s} - c_i d_{i+s} / b_{i+s}.
-// On entry (a, b, c, d) hold the thread's row (a = 0 on the first row, c = 0 on the last); on
-// exit d holds the solution. LDS: NM planes each of a, c and 1/b, then NR complex planes,
-// each [row][line] of n * TL entries.
-template <typename A, int NM, int NR, int MAP>
-__device__ __forceinline__ void pcr_sym(unsigned char* base, int n, int TL, int row, int line,
-                                        A (&a)[NM], A (&b)[NM], A (&c)[NM], cx<A> (&d)[NR]) {
-  const int plane = n * TL;
-  const int me = row * TL + line;
-  A* La = reinterpret_cast<A*>(base);
-  A* Lc = La + NM * plane;
-  A* Lib = Lc + NM * plane;
-  cx<A>* Ld = reinterpret_cast<cx<A>*>(Lib + NM * plane);
-  A ib[NM];
-#pragma unroll
-  for (int m = 0; m < NM; ++m) ib[m] = recip(b[m]);
-  for (int s = 1; s < n; s <<= 1) {
-#pragma unroll
-    for (int m = 0; m < NM; ++m) {
-      La[m * plane + me] = a[m];
-      Lc[m * plane + me] = c[m];
-      Lib[m * plane + me] = ib[m];
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r) Ld[r * plane + me] = d[r];
-    __syncthreads();
-    A al[NM], ga[NM], am[NM], cp[NM];
-    cx<A> dm[NR], dp[NR];
-#pragma unroll
-    for (int m = 0; m < NM; ++m) al[m] = ga[m] = am[m] = cp[m] = (A)0;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) dm[r] = dp[r] = mk<A>(0, 0);
-    if (row - s >= 0) {
-      const int q = me - s * TL;
-#pragma unroll
-      for (int m = 0; m < NM; ++m) {
-        al[m] = -a[m] * Lib[m * plane + q];
-        am[m] = La[m * plane + q];
-      }
-#pragma unroll
-      for (int r = 0; r < NR; ++r) dm[r] = Ld[r * plane + q];
-    }
-    if (row + s < n) {
-      const int q = me + s * TL;
-#pragma unroll
-      for (int m = 0; m < NM; ++m) {
-        ga[m] = -c[m] * Lib[m * plane + q];
-        cp[m] = Lc[m * plane + q];
-      }
-#pragma unroll
-      for (int r = 0; r < NR; ++r) dp[r] = Ld[r * plane + q];
-    }
-#pragma unroll
-    for (int m = 0; m < NM; ++m) {
-      b[m] = b[m] + al[m] * a[m] + ga[m] * c[m];
-      a[m] = al[m] * am[m];
-      c[m] = ga[m] * cp[m];
-      ib[m] = recip(b[m]);
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const int m = (MAP >> r) & 1;
-      d[r] = mk<A>(d[r].re + al[m] * dm[r].re + ga[m] * dp[r].re, d[r].im + al[m] * dm[r].im + ga[m] * dp[r].im);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int r = 0; r < NR; ++r) d[r] = ib[(MAP >> r) & 1] * d[r];
-}
-
-template <typename A, int NM, int NR>
-size_t pcr_sym_bytes(int n, int TL) {
-  return (size_t)n * TL * (3 * NM * sizeof(A) + NR * sizeof(cx<A>));
-}
-
 // spec holds four fields of Nz*Ny*P complex each: r_u, r_v, r_w on entry (fields 0-2); on
 // exit u^{n+1}, v^{n+1}, w^{n+1} and the pressure increment p' (field 3).
 template <typename T>
@@ -591,8 +515,10 @@ __global__ void __launch_bounds__(1024)
     if (row == 0) { pa = 0.0; pc = 0.0; pb = 1.0; p[0] = mk<T>(0, 0); }
     if (row == 1) pa = 0.0;
   }
-  PcrLds<double, 1> LP = carve<double, 1>(smem, Nz, TL);
-  pcr<double, 1>(LP, Nz, TL, row, line, pa, pb, pc, p);
+  {
+    double pa1[1] = {pa}, pb1[1] = {pb}, pc1[1] = {pc};
+    pcr_sym<double, 1, 1, 0>(smem, Nz, TL, row, line, pa1, pb1, pc1, p);
+  }
   cx<T>* Lp = reinterpret_cast<cx<T>*>(smem);
   Lp[row * TL + line] = p[0];
   __syncthreads();
@@ -618,15 +544,16 @@ __global__ void __launch_bounds__(1024)
   uv[1] = mk<T>(v.re - (gyr * pr - gyi * pi), v.im - (gyr * pi + gyi * pr));
   cx<T> wt[1];
   wt[0] = top ? mk<T>(0, 0) : mk<T>(w.re - (pup.re - pr) * ihz, w.im - (pup.im - pi) * ihz);
-  // ---- velocity Helmholtz solves (the forward operators, symmetric)
+  // ---- velocity Helmholtz solves (the forward operators, symmetric), reduced together
   const double av = nu_m * ihz * ihz;
-  PcrLds<T, 2> L2 = carve<T, 2>(smem, Nz, TL);
-  pcr<T, 2>(L2, Nz, TL, row, line, row == 0 ? 0.0 : av, nu_m * lxy - (end ? 3.0 : 2.0) * av - g_dt,
-            row == Nz - 1 ? 0.0 : av, uv);
-  PcrLds<T, 1> L1 = carve<T, 1>(smem, Nz, TL);
-  pcr<T, 1>(L1, Nz, TL, row, line, (row == 0 || top) ? 0.0 : av, top ? 1.0 : nu_m * lxy - 2.0 * av - g_dt,
-            (row >= Nz - 2) ? 0.0 : av, wt);
-  if (top) wt[0] = mk<T>(0, 0);
+  T a[2] = {row == 0 ? 0.0 : av, (row == 0 || top) ? 0.0 : av};
+  T b[2] = {nu_m * lxy - (end ? 3.0 : 2.0) * av - g_dt, top ? 1.0 : nu_m * lxy - 2.0 * av - g_dt};
+  T c[2] = {row == Nz - 1 ? 0.0 : av, (row >= Nz - 2) ? 0.0 : av};
+  cx<T> d[3] = {uv[0], uv[1], wt[0]};
+  pcr_sym<T, 2, 3, 4>(smem, Nz, TL, row, line, a, b, c, d);
+  uv[0] = d[0];
+  uv[1] = d[1];
+  wt[0] = top ? mk<T>(0, 0) : d[2];
   if (valid) {
     spec[at] = uv[0];
     spec[fsz + at] = uv[1];
@@ -641,7 +568,7 @@ hipError_t launch_zpass_helmholtz(const Dims& d, const Tables<T>& tb, cx<T>* spe
                                   double coeff, double shift, double scale, hipStream_t st) {
   const int lines = d.lines();
   const int TL = spread_lines(tile_lines(d.nz), lines, 2048);
-  const size_t shm = pcr_bytes<double, 1>(d.nz, TL);
+  const size_t shm = pcr_sym_bytes<double, 1, 1>(d.nz, TL);
   hipLaunchKernelGGL(k_zpass_helmholtz<T>, dim3((lines + TL - 1) / TL), dim3(TL * d.nz), shm, st, spec,
                      d.pitch, d.ny, d.nz, tb.lam_x, tb.lam_y, 1.0 / (d.hz * d.hz), bc, coeff, shift,
                      scale);
@@ -700,8 +627,15 @@ hipError_t launch_zpass_ns(const Dims& d, const Tables<T>& tb, cx<T>* spec4, con
 hipError_t launch_zpass_ns_adj(const Dims& d, const Tables<double>& tb, cx<double>* spec4,
                                const StepConsts& c, double scale, hipStream_t st) {
   const int lines = d.lines();
-  const int TL = spread_lines(tile_lines(d.nz), lines, 2048);
-  size_t shm = pcr_bytes<double, 2>(d.nz, TL);
+  auto shm_of = [&](int tl) {
+    const size_t a = pcr_sym_bytes<double, 2, 3>(d.nz, tl), b = pcr_sym_bytes<double, 1, 1>(d.nz, tl);
+    return a > b ? a : b;
+  };
+  // at most 64 KB of LDS per block, as in the forward pass
+  int TL = tile_lines(d.nz);
+  while (TL > 1 && shm_of(TL) > 65536) TL >>= 1;
+  TL = spread_lines(TL, lines, 2048);
+  const size_t shm = shm_of(TL);
   hipLaunchKernelGGL(k_zpass_ns_adj, dim3((lines + TL - 1) / TL), dim3(TL * d.nz), shm, st, spec4, d.pitch,
                      d.ny, d.nz, tb.lam_x, tb.lam_y, tb.ph_x, tb.ph_y, 1.0 / d.hx, 1.0 / d.hy, 1.0 / d.hz,
                      c.nu_m, c.gamma0 / c.dt, c.gamma0 * c.rho0 / c.dt, scale);
