@@ -251,11 +251,11 @@ __global__ void __launch_bounds__(1024)
       const int mr = (Nz - m) & (Nz - 1);  // partner N - m (0 and N/2 pair with themselves)
       const cx<T> Vm = buf[m * TL + t], Vr = buf[mr * TL + t];
       const T lm = lxy + (T)lamz[m];
-      const cx<T> Fm = (sc / ((lm - cp) * (lm + al))) * dct_out(Vm, Vr, twq[m]);
+      const cx<T> Fm = (sc * recip((lm - cp) * (lm + al))) * dct_out(Vm, Vr, twq[m]);
       cx<T> Fr = Fm;
       if (mr != m) {
         const T lr = lxy + (T)lamz[mr];
-        Fr = (sc / ((lr - cp) * (lr + al))) * dct_out(Vr, Vm, twq[mr]);
+        Fr = (sc * recip((lr - cp) * (lr + al))) * dct_out(Vr, Vm, twq[mr]);
       }
       inverse_in(m, mr, t, Fm, Fr);
     }
@@ -286,12 +286,12 @@ __global__ void __launch_bounds__(1024)
       const cx<T> Vm = buf[m * TL + t], Vr = buf[mr * TL + t];
       // 1/A once per entry: F0 = scale X / A and G = d lambda c / (N A)
       const T lm = lxy + (T)lamz[m];
-      const T im = (T)1 / ((lm - cp) * (lm + al));
+      const T im = recip((lm - cp) * (lm + al));
       buf[m * TL + t] = (sc * im) * dct_out(Vm, Vr, twq[m]);
       sG[m * TL + t] = (T)dwall * lm * twq[m].re * im / (T)Nz;
       if (mr != m) {
         const T lr = lxy + (T)lamz[mr];
-        const T ir = (T)1 / ((lr - cp) * (lr + al));
+        const T ir = recip((lr - cp) * (lr + al));
         buf[mr * TL + t] = (sc * ir) * dct_out(Vr, Vm, twq[mr]);
         sG[mr * TL + t] = (T)dwall * lr * twq[mr].re * ir / (T)Nz;
       }
