@@ -191,8 +191,9 @@ __global__ void __launch_bounds__(1024)
 // ---- Cahn-Hilliard pair -------------------------------------------------------------
 // Both CH operators have zero-flux walls, so the DCT-II across the walls diagonalises them
 // exactly (eigenvalue lam_z(m) of the second difference for cos(pi m (k + 1/2) / nz)). The
-// pair (L_N - c_psi)^-1 (L_N + alpha)^-1 becomes: forward DCT, one division by
-// (lam - c_psi)(lam + alpha) per coefficient, inverse DCT. Each DCT is one length-nz complex
+// pair (L_N - c_psi)^-1 (L_N + alpha)^-1 becomes: forward DCT, one multiplication by the
+// reciprocal of (lam - c_psi)(lam + alpha) per coefficient (recip: both factors are bounded
+// away from zero, since lam <= 0, alpha < 0 < c_psi), inverse DCT. Each DCT is one length-nz complex
 // FFT in LDS (Makhoul's even/odd reordering with a quarter-wave twiddle); the data are
 // complex (x/y spectral coefficients), so the real and imaginary sequences are separated
 // from the pair (V_m, V_{nz-m}). A block holds TL consecutive modes, columns in LDS.
