@@ -1,6 +1,7 @@
 // C-ABI of the drpf library: parameter validation, scheme constants, workspace layout,
 // host-built transform tables, and the per-step launch sequence (Sec. 3.2 of the paper:
 // Cahn-Hilliard on the fine grid, restriction, Navier-Stokes projection, polymer stress).
+#include <limits.h>
 #include <math.h>
 #include <string.h>
 
@@ -1023,6 +1024,9 @@ int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes) {
   if (p->advection != 0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the central advection only");
   if (p->d_w != 0.0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers static contact angles only");
   const Dims F = fine_dims(*p);
+  // the transposed fine-grid kernels index a fine field with 32-bit integers
+  if (F.cells() > (size_t)INT_MAX)
+    return fail(DRPF_EUNSUPPORTED, "the adjoint needs a phase-field grid of at most 2^31 - 1 cells");
   const Dims C = make_dims(p->nx, p->ny, p->nz, p->lx, p->ly, p->lz);
   *bytes = adj_layout(F, C).total;
   return DRPF_OK;

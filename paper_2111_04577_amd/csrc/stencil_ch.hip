@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(kBlock)
   constexpr bool relax = RELAX;  // relaxed walls (eq. NS34 with D_w > 0)
   const T kg = RELAX ? (T)(c.relax_kappa * c.inv_gamma0) * ihz : (T)0;
   auto phat_at = [&](int Kl, int Jl, int Il) -> T {
-    const int id = (Kl * ny + wrap(Jl, ny)) * nx + wrap(Il, nx);
+    const size_t id = ((size_t)Kl * ny + wrap(Jl, ny)) * nx + wrap(Il, nx);
     return first ? phin[id] : (T)2 * phin[id] - (T)0.5 * phinm1[id];
   };
   T ta[R], tb[R];

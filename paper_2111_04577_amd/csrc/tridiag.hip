@@ -164,6 +164,23 @@ __global__ void __launch_bounds__(1024)
   d[0] = valid ? widen<double>(S[row * stride + l]) : mk<double>(0, 0);
   d[0] = scale * d[0];
   if (bc == 2 && row == Nz - 1) d[0] = mk<double>(0, 0);
+  // the singular (0,0) Neumann line: the pseudo-inverse drops the z-mean of the right-hand
+  // side first (the pinned row then reproduces the remaining equations exactly); every
+  // thread takes part in the barriers
+  {
+    cx<double>* Ls = reinterpret_cast<cx<double>*>(smem);
+    Ls[row * TL + line] = d[0];
+    __syncthreads();
+    if (pinned) {
+      double mre = 0, mim = 0;
+      for (int k = 0; k < Nz; ++k) {
+        mre += Ls[k * TL + line].re;
+        mim += Ls[k * TL + line].im;
+      }
+      d[0] = mk<double>(d[0].re - mre / Nz, d[0].im - mim / Nz);
+    }
+    __syncthreads();
+  }
   if (pinned) {
     if (row == 0) { ar = 0.0; cr = 0.0; br = 1.0; d[0] = mk<double>(0, 0); }
     if (row == 1) ar = 0.0;

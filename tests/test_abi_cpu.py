@@ -124,6 +124,23 @@ def test_validation_wall_relaxation():
     assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_EUNSUPPORTED
 
 
+def test_adjoint_grid_bound():
+    """The transposed fine kernels index with 32-bit integers: the largest grid the step
+    accepts (coarse 1024x1024x512, fine 2^32 cells) has no adjoint, one fine cell count
+    below 2^31 has."""
+    B = _lib()
+    L = B.lib()
+    nb = ctypes.c_size_t()
+    big = _params(nx=1024, ny=1024, nz=512, viscoelastic=1, beta=0.5, wi=0.5)
+    assert L.drpf_validate(ctypes.byref(big)) == B.DRPF_OK
+    assert L.drpf_adjoint_workspace_bytes(ctypes.byref(big), ctypes.byref(nb)) == B.DRPF_EUNSUPPORTED
+    assert b"2^31" in L.drpf_last_error()
+    ok = _params(nx=1024, ny=512, nz=512, viscoelastic=1, beta=0.5, wi=0.5)   # 2^31 fine cells
+    assert L.drpf_adjoint_workspace_bytes(ctypes.byref(ok), ctypes.byref(nb)) == B.DRPF_EUNSUPPORTED
+    ok = _params(nx=1024, ny=256, nz=512, viscoelastic=1, beta=0.5, wi=0.5)   # 2^30
+    assert L.drpf_adjoint_workspace_bytes(ctypes.byref(ok), ctypes.byref(nb)) == B.DRPF_OK
+
+
 def test_sizes_and_workspace_errors():
     B = _lib()
     L = B.lib()

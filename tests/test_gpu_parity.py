@@ -73,11 +73,15 @@ SMALL2D = W.config("C1", nx=32, nz=16, ly=2.0 / 32, noise=1e-3, seed=2)
 
 @pytest.mark.parametrize("cfg", [SMALL3D, SMALL2D], ids=["3d", "2d"])
 @pytest.mark.parametrize("which", ["fine", "coarse"])
-@pytest.mark.parametrize("bc,coeff,shift", [("neumann", 1.0, 0.0), ("neumann", 0.7, 37.0),
-                                             ("dirichlet", 0.3, 5.0), ("face_dirichlet", 2.0, 11.0)])
-def test_helmholtz_solve(drpf, cfg, which, bc, coeff, shift):
+@pytest.mark.parametrize("bc,coeff,shift,offset", [
+    ("neumann", 1.0, 0.0, 0.0), ("neumann", 1.0, 0.0, 0.75), ("neumann", 0.7, 37.0, 0.0),
+    ("dirichlet", 0.3, 5.0, 0.0), ("face_dirichlet", 2.0, 11.0, 0.0)])
+def test_helmholtz_solve(drpf, cfg, which, bc, coeff, shift, offset):
+    """Against the oracle's exact solve; the singular Neumann Poisson problem (shift 0) with a
+    right-hand side of non-zero mean (offset) returns the pseudo-inverse's zero-mean
+    solution, as the oracle does."""
     import torch
-    say(f"[gpu] helmholtz {cfg.name} {which} {bc}")
+    say(f"[gpu] helmholtz {cfg.name} {which} {bc} offset {offset}")
     g = drpf.Grid(cfg, 64)
     shape = g.fine_shape if which == "fine" else g.coarse_shape
     P = model.Params.from_config(cfg)
@@ -85,7 +89,7 @@ def test_helmholtz_solve(drpf, cfg, which, bc, coeff, shift):
     rng = np.random.default_rng(17)
     rhs = rng.standard_normal(shape)
     if bc == "neumann" and shift == 0.0:
-        rhs -= rhs.mean()
+        rhs += offset - rhs.mean()
     if bc == "face_dirichlet":
         rhs[-1] = 0.0
     x = g.helmholtz_solve(torch.tensor(rhs, device="cuda"), which, bc, coeff, shift)
@@ -190,43 +194,88 @@ def test_c1_hundred_steps(drpf):
     assert o_g["max_div"] < 1e-9
 
 
-def test_full_size_c2_two_steps(drpf):
-    """Launch configuration of the benchmark (128x128x64 coarse, 256x256x128 fine): two
-    steps against the oracle, plus mass conservation and discrete incompressibility."""
-    cfg = W.config("C2")
-    g, st, gh, oh = run_both(drpf, cfg, 2)
-    errs = field_errors(gh, oh, False)
-    say(f"[gpu] C2 full-size errors {errs}")
-    for k, e in errs.items():
-        assert e < TOL, (k, e)
-    obs = g.observables(st)
+# Stated per-field bounds of the FP32 form (storage, stencils, transforms and the CH and
+# velocity solves in FP32; the pressure Poisson, its zero mode and the mass sums in FP64)
+# against the FP64 oracle: max |x - x_ref| / max |x_ref| after the stated number of steps.
+# Each is about twice the error measured with the current kernels (which are deterministic):
+# C2 20 steps phi 1.0e-5, u 5.5e-5, v 3.4e-5, w 1.7e-4, p 2.8e-5; C3 20 steps phi 1.3e-5,
+# u 3.8e-5, v 3.2e-5, w 7.6e-5, p 7.3e-5, tau 2.9e-5; C5 2 steps phi 1.6e-6, u 7.3e-5,
+# v 7.8e-5, w 1.7e-4, p 7.0e-5, tau 8.9e-5.
+FP32_BOUND = {
+    "C2": {"phi": 2e-5, "u": 1e-4, "v": 1e-4, "w": 4e-4, "p": 1e-4},
+    "C3": {"phi": 3e-5, "u": 1e-4, "v": 1e-4, "w": 2e-4, "p": 2e-4, "tau": 1e-4},
+    "C5": {"phi": 4e-6, "u": 2e-4, "v": 2e-4, "w": 4e-4, "p": 2e-4, "tau": 2e-4},
+}
+FULL_STEPS = {"C2": 20, "C3": 20, "C5": 2}
+
+
+def run_forms(drpf, cfg, nsteps):
+    """The oracle once, then the GPU FP64 and FP32 forms from the same input."""
+    import torch
     P = model.Params.from_config(cfg)
+    oh = W.droplet_state(cfg)
+    for n in range(nsteps):
+        oh = S.step(P, oh)
+        say(f"[gpu] oracle {cfg.name} step {n + 1} of {nsteps}")
+    out = {}
+    for prec in (64, 32):
+        say(f"[gpu] config {cfg.name} coarse {cfg.nx}x{cfg.ny}x{cfg.nz} steps {nsteps} fp{prec}")
+        g = drpf.Grid(cfg, prec)
+        st = g.state(W.droplet_state(cfg))
+        g.step(st, nsteps)
+        torch.cuda.synchronize()
+        out[prec] = (st.to_host(), g.observables(st))
+        del g, st
+        torch.cuda.empty_cache()
+    return P, oh, out
+
+
+def check_forms(cfg, P, oh, out, nsteps):
+    e64 = field_errors(out[64][0], oh, cfg.viscoelastic)
+    e32 = field_errors(out[32][0], oh, cfg.viscoelastic)
+    say(f"[gpu] {cfg.name} {nsteps} steps fp64 errors {e64}")
+    say(f"[gpu] {cfg.name} {nsteps} steps fp32 errors {e32}")
+    for k, e in e64.items():
+        assert e < TOL, ("fp64", k, e)
+    for k, e in e32.items():
+        assert e < FP32_BOUND[cfg.name][k], ("fp32", k, e, FP32_BOUND[cfg.name][k])
     m0 = S.observables(P, W.droplet_state(cfg))["mass"]
-    assert abs(obs["mass"] - m0) < 1e-12 * np.sum(np.abs(gh["phi"][0])) * np.prod(P.hf)
-    assert obs["max_div"] < 1e-8
+    scale = np.sum(np.abs(oh["phi"][0])) * np.prod(P.hf)
+    assert abs(out[64][1]["mass"] - m0) < 1e-12 * scale
+    assert abs(out[32][1]["mass"] - m0) < 1e-6 * scale
+    assert out[64][1]["max_div"] < 1e-8
 
 
-def test_full_size_c3_four_steps(drpf):
-    """The 3D Oldroyd-B set-up at full size (128x128x64 coarse, 256x256x128 fine, the z-marching
-    momentum launch and the polymer stages at scale): four steps against the oracle, every
-    field including the six stress components."""
+@pytest.mark.timeout(900)
+def test_full_size_c2_both_forms(drpf):
+    """Launch configuration of the benchmark's Newtonian workload (128x128x64 coarse,
+    256x256x128 fine, density ratio 1000, viscosity ratio 100): 20 steps against the oracle,
+    the FP64 form at 1e-10 and the FP32 form at its stated per-field bounds; mass
+    conservation and discrete incompressibility."""
+    cfg = W.config("C2")
+    n = FULL_STEPS["C2"]
+    check_forms(cfg, *run_forms(drpf, cfg, n), n)
+
+
+@pytest.mark.timeout(900)
+def test_full_size_c3_both_forms(drpf):
+    """The 3D Oldroyd-B set-up at full size (128x128x64 coarse, 256x256x128 fine, the
+    z-marching momentum launch and the polymer stages at scale): 20 steps against the oracle,
+    every field including the six stress components, in both forms."""
     cfg = W.config("C3")
-    g, st, gh, oh = run_both(drpf, cfg, 4)
-    errs = field_errors(gh, oh, True)
-    say(f"[gpu] C3 full-size errors {errs}")
-    for k, e in errs.items():
-        assert e < TOL, (k, e)
+    n = FULL_STEPS["C3"]
+    check_forms(cfg, *run_forms(drpf, cfg, n), n)
 
 
-def test_full_size_c5_one_step(drpf):
+@pytest.mark.timeout(900)
+def test_full_size_c5_both_forms(drpf):
     """The largest set-up (256x256x128 coarse, 512x512x256 = 67.1M fine cells, Oldroyd-B,
-    density and viscosity contrast): one step against the oracle, every field."""
+    density and viscosity contrast; coarse x and y transforms in separate passes): two steps,
+    so that the second-order (BDF2) step runs at these launch shapes, against the oracle in
+    both forms."""
     cfg = W.config("C5")
-    g, st, gh, oh = run_both(drpf, cfg, 1)
-    errs = field_errors(gh, oh, True)
-    say(f"[gpu] C5 full-size errors {errs}")
-    for k, e in errs.items():
-        assert e < TOL, (k, e)
+    n = FULL_STEPS["C5"]
+    check_forms(cfg, *run_forms(drpf, cfg, n), n)
 
 
 def test_deterministic(drpf):
