@@ -225,9 +225,10 @@ def constants(P: Params, first, pe):
 def step(P: Params, st, theta, pe, wi):
     """One coupled step on tensors; st holds lists of tensors like the NumPy oracle state."""
     if (P.d_w != 0.0 or P.advection != 0 or P.constitutive != 0 or P.giesekus_alpha != 0.0
-            or P.refine != 2):
+            or P.refine != 2 or P.moving_walls):
         raise NotImplementedError("the differentiable step covers the dual-resolution step with "
-                                  "static walls, central advection and the Oldroyd-B stress form")
+                                  "static walls at rest, central advection and the Oldroyd-B "
+                                  "stress form")
     first = st["step"] == 0
     C = constants(P, first, pe)
     hf, h = P.hf, P.h

@@ -10,7 +10,8 @@ ny > 1), phase field at fine cell centres.
 Wall ghost rules (second-order central differences, Sec. 3.2):
 * homogeneous Neumann (phase field, chemical potential, pressure increment, polymer stress,
   eqs. NS14, NS37 and the closing paragraph of Sec. 3.2.3): ghost = adjacent cell;
-* no-slip (eq. NS13, wall at rest) for cell-centred-in-z velocity: ghost = -adjacent;
+* no-slip (eq. NS13, u = u_w) for cell-centred-in-z velocity: ghost = 2 u_w - adjacent
+  (-adjacent for a wall at rest);
 * w lives on z faces: its wall values are 0.
 """
 from __future__ import annotations
@@ -47,12 +48,16 @@ def zm_neu(a):
     return np.concatenate([a[:1], a[:-1]], axis=0)
 
 
-def zp_dir(a):
-    return np.concatenate([a[1:], -a[-1:]], axis=0)
+def zp_dir(a, wall=0.0):
+    """a[k+1] of a cell-centred field with the no-slip ghost above the top wall: the wall value
+    is the mean of the ghost and the adjacent cell, ghost = 2 wall - adjacent (eq. NS13,
+    u = u_w; 0 for a wall at rest)."""
+    return np.concatenate([a[1:], 2.0 * wall - a[-1:]], axis=0)
 
 
-def zm_dir(a):
-    return np.concatenate([-a[:1], a[:-1]], axis=0)
+def zm_dir(a, wall=0.0):
+    """a[k-1] with the no-slip ghost below the bottom wall (ghost = 2 wall - adjacent)."""
+    return np.concatenate([2.0 * wall - a[:1], a[:-1]], axis=0)
 
 
 def zm_face(w):
@@ -79,8 +84,10 @@ def lap_neumann(a, h):
     return _lap_xy(a, h) + (zp_neu(a) - 2 * a + zm_neu(a)) / h[2] ** 2
 
 
-def lap_dirichlet(a, h):
-    return _lap_xy(a, h) + (zp_dir(a) - 2 * a + zm_dir(a)) / h[2] ** 2
+def lap_dirichlet(a, h, walls=(0.0, 0.0)):
+    """Laplacian of a cell-centred field with no-slip ghosts for the wall values
+    walls = (bottom, top)."""
+    return _lap_xy(a, h) + (zp_dir(a, walls[1]) - 2 * a + zm_dir(a, walls[0])) / h[2] ** 2
 
 
 def lap_wface(w, h):
@@ -98,7 +105,33 @@ def _eig_periodic(n, h):
     return -4.0 / h ** 2 * np.sin(np.pi * np.arange(n) / n) ** 2
 
 
-def helmholtz(rhs, coeff, shift, kind, h):
+def wall_vector(shape, kind, h, walls):
+    """The part of ``L x`` that the wall data carry, as a field b with ``L x = L_0 x + b``
+    (L_0 the operator with homogeneous wall data): on the wall-adjacent layers,
+    'neumann' -- walls = outward normal derivatives (g_bottom, g_top); the ghost is the
+      adjacent value plus hz g, so b = g / hz;
+    'dirichlet' -- walls = wall values; ghost = 2 wall - adjacent, so b = 2 wall / hz^2;
+    'wface' -- walls = wall values of the face field at z = 0 and z = lz, next to the
+      unknowns k = 0 and k = nz - 2: b = wall / hz^2 there.
+    Each wall entry is a scalar or an (ny, nx) array."""
+    nz = shape[0]
+    hz = h[2]
+    b = np.zeros(shape)
+    if kind == "neumann":
+        b[0] += walls[0] / hz
+        b[-1] += walls[1] / hz
+    elif kind == "dirichlet":
+        b[0] += 2.0 * walls[0] / hz ** 2
+        b[-1] += 2.0 * walls[1] / hz ** 2
+    elif kind == "wface":
+        b[0] += walls[0] / hz ** 2
+        b[nz - 2] += walls[1] / hz ** 2
+    else:
+        raise ValueError(kind)
+    return b
+
+
+def helmholtz(rhs, coeff, shift, kind, h, walls=None):
     """Solve ``coeff * L x - shift * x = rhs`` exactly.
 
     ``kind``: 'neumann' (cell-centred in z, homogeneous Neumann walls), 'dirichlet'
@@ -108,7 +141,15 @@ def helmholtz(rhs, coeff, shift, kind, h):
     the wall-normal second difference: DCT-II (Neumann), DST-II (Dirichlet, centred),
     DST-I of length nz-1 (Dirichlet, faces). A singular Neumann Poisson problem
     (shift == 0) returns the zero-mean solution.
+    ``walls`` (bottom, top): inhomogeneous wall data for L (``wall_vector``); the known part
+    moves to the right-hand side, coeff L_0 x - shift x = rhs - coeff b. For 'wface' layer
+    nz-1 of the result is then the top-wall value.
     """
+    if walls is not None:
+        x = helmholtz(rhs - coeff * wall_vector(rhs.shape, kind, h, walls), coeff, shift, kind, h)
+        if kind == "wface":
+            x[-1] = walls[1]
+        return x
     nz, ny, nx = rhs.shape
     hx, hy, hz = h
     X = np.fft.fft2(rhs, axes=(1, 2))

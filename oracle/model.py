@@ -53,6 +53,8 @@ class Params:
     refine: int = 2                # phase-field grid refinement: 2 dual resolution, 1 single
     advection: int = 0             # 0: second-order central flux, 1: fifth-order WENO-Z (weno.py)
     d_w: float = 0.0               # wall relaxation D_w of eq. NS15 (0: static contact angle)
+    u_wall_bottom: tuple = (0.0, 0.0)  # wall velocity (x, y) at z = 0 (eq. NS13, u = u_w)
+    u_wall_top: tuple = (0.0, 0.0)     # wall velocity (x, y) at z = lz
 
     @classmethod
     def from_config(cls, cfg) -> "Params":
@@ -60,6 +62,14 @@ class Params:
         return cls(**{k: getattr(cfg, k) for k in names})
 
     # --- grid ---------------------------------------------------------------------------
+    def walls(self, comp: int):
+        """(bottom, top) wall values of the tangential velocity component comp (0: u, 1: v)."""
+        return (float(self.u_wall_bottom[comp]), float(self.u_wall_top[comp]))
+
+    @property
+    def moving_walls(self) -> bool:
+        return any(float(x) != 0.0 for x in tuple(self.u_wall_bottom) + tuple(self.u_wall_top))
+
     @property
     def ry(self) -> int:
         """Refinement factor in y (1 for a 2D case with a single y cell)."""

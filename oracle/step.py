@@ -150,9 +150,10 @@ def restricted_set(P: Params, phi, G, C):
 # ---------------------------------------------------------------------------------------
 
 
-def _zc_dir(a):
-    """Cell-centred velocity with no-slip ghosts: (a[k-1], a[k+1])."""
-    return D.zm_dir(a), D.zp_dir(a)
+def _zc_dir(a, walls):
+    """Cell-centred velocity with no-slip ghosts for the wall values (bottom, top):
+    (a[k-1], a[k+1])."""
+    return D.zm_dir(a, walls[0]), D.zp_dir(a, walls[1])
 
 
 def momentum_rhs(P: Params, st, R, C):
@@ -160,8 +161,10 @@ def momentum_rhs(P: Params, st, R, C):
     (nu_m L u~ - gamma0/dt u~ = r), including the -u_hat/dt term of eq. NS35, the
     extrapolated velocity u* in every explicit term, p^n and p* in the pressure split,
     the polymer divergence of approach 2 (eq. NS12, drop = polymer phase) and the
-    capillary force. Returns (r_u, r_v, r_w) with r_w[nz-1] = 0 (top wall)."""
+    capillary force. Tangential velocities take the wall values of eq. NS13 (u = u_w) through
+    their ghosts. Returns (r_u, r_v, r_w) with r_w[nz-1] = 0 (top wall)."""
     hx, hy, hz = P.h
+    uw, vw = P.walls(0), P.walls(1)
     first = st["step"] == 0
     us, uh = _levels(st["u"], first)
     vs, vh = _levels(st["v"], first)
@@ -208,8 +211,11 @@ def momentum_rhs(P: Params, st, R, C):
         return 0.5 * (ae + D.yp(ae))
 
     # u at xz edges (z layers k = -1..nz-1) with no-slip ghosts, w at xz edges
-    def u_on_zedges(a):
-        ext = np.concatenate([-a[:1], a, -a[-1:]], axis=0)  # k = -1 .. nz
+    def with_ghosts(a, walls):
+        return np.concatenate([2.0 * walls[0] - a[:1], a, 2.0 * walls[1] - a[-1:]], axis=0)  # k = -1 .. nz
+
+    def u_on_zedges(a, walls):
+        ext = with_ghosts(a, walls)
         return 0.5 * (ext[:-1] + ext[1:])                   # edges k = -1 .. nz-1
 
     def w_ext(a):
@@ -222,7 +228,7 @@ def momentum_rhs(P: Params, st, R, C):
     adv_u = (uc * uc - ucl * ucl) / hx
     fy = 0.5 * (vs + D.xp(vs)) * 0.5 * (us + D.yp(us))     # at xy edge (i, j)
     adv_u += (fy - D.ym(fy)) / hy
-    fz = 0.5 * (w_ext(ws) + D.xp(w_ext(ws))) * u_on_zedges(us)  # xz edges k=-1..nz-1
+    fz = 0.5 * (w_ext(ws) + D.xp(w_ext(ws))) * u_on_zedges(us, uw)  # xz edges k=-1..nz-1
     adv_u += (fz[1:] - fz[:-1]) / hz
 
     # v at y faces
@@ -231,16 +237,16 @@ def momentum_rhs(P: Params, st, R, C):
     adv_v = (vc * vc - vcl * vcl) / hy
     fx = 0.5 * (us + D.yp(us)) * 0.5 * (vs + D.xp(vs))     # at xy edge (i, j)
     adv_v += (fx - D.xm(fx)) / hx
-    fz = 0.5 * (w_ext(ws) + D.yp(w_ext(ws))) * u_on_zedges(vs)
+    fz = 0.5 * (w_ext(ws) + D.yp(w_ext(ws))) * u_on_zedges(vs, vw)
     adv_v += (fz[1:] - fz[:-1]) / hz
 
     # w at z faces (k = 0..nz-2 meaningful)
     wcu = 0.5 * (ws + D.zp_face(ws))          # centre k+1
     wcl = 0.5 * (D.zm_face(ws) + ws)          # centre k
     adv_w = (wcu * wcu - wcl * wcl) / hz
-    fx = 0.5 * (us + D.zp_dir(us)) * 0.5 * (ws + D.xp(ws))   # xz edge (i, k), k = 0..nz-1
+    fx = 0.5 * (us + D.zp_dir(us, uw[1])) * 0.5 * (ws + D.xp(ws))   # xz edge (i, k), k = 0..nz-1
     adv_w += (fx - D.xm(fx)) / hx
-    fy = 0.5 * (vs + D.zp_dir(vs)) * 0.5 * (ws + D.yp(ws))
+    fy = 0.5 * (vs + D.zp_dir(vs, vw[1])) * 0.5 * (ws + D.yp(ws))
     adv_w += (fy - D.ym(fy)) / hy
 
     # ---- J . grad u* / rho
@@ -255,13 +261,13 @@ def momentum_rhs(P: Params, st, R, C):
 
     dudx = (D.xp(us) - D.xm(us)) / (2 * hx)
     dudy = (D.yp(us) - D.ym(us)) / (2 * hy)
-    zm, zp = _zc_dir(us)
+    zm, zp = _zc_dir(us, uw)
     dudz = (zp - zm) / (2 * hz)
     jgu = face_avg_x(jx) * dudx + face_avg_x(jy) * dudy + face_avg_x(jz) * dudz
 
     dvdx = (D.xp(vs) - D.xm(vs)) / (2 * hx)
     dvdy = (D.yp(vs) - D.ym(vs)) / (2 * hy)
-    zm, zp = _zc_dir(vs)
+    zm, zp = _zc_dir(vs, vw)
     dvdz = (zp - zm) / (2 * hz)
     jgv = face_avg_y(jx) * dvdx + face_avg_y(jy) * dvdy + face_avg_y(jz) * dvdz
 
@@ -277,7 +283,7 @@ def momentum_rhs(P: Params, st, R, C):
     vis_u = (sxx_r - sxx_l) / hx
     sxy = mu_xy * ((D.yp(us) - us) / hy + (D.xp(vs) - vs) / hx)    # xy edge (i, j)
     vis_u += (sxy - D.ym(sxy)) / hy
-    ue = np.concatenate([-us[:1], us, -us[-1:]], axis=0)           # k = -1 .. nz
+    ue = with_ghosts(us, uw)                                       # k = -1 .. nz
     we = w_ext(ws)                                                 # k = -1 .. nz-1
     sxz = mu_xz * ((ue[1:] - ue[:-1]) / hz + (D.xp(we) - we) / hx)  # xz edges k=-1..nz-1
     vis_u += (sxz[1:] - sxz[:-1]) / hz
@@ -286,7 +292,7 @@ def momentum_rhs(P: Params, st, R, C):
     syy_l = 2 * mu_c * (vs - D.ym(vs)) / hy
     vis_v = (syy_r - syy_l) / hy
     vis_v += (sxy - D.xm(sxy)) / hx
-    ve = np.concatenate([-vs[:1], vs, -vs[-1:]], axis=0)
+    ve = with_ghosts(vs, vw)
     syz = mu_yz * ((ve[1:] - ve[:-1]) / hz + (D.yp(we) - we) / hy)
     vis_v += (syz[1:] - syz[:-1]) / hz
     # z-momentum (faces k = 0 .. nz-2): edges k = 0 .. nz-2 are layers 1 .. nz-1
@@ -321,7 +327,7 @@ def momentum_rhs(P: Params, st, R, C):
            R["G_z"][1:] * (D.zp_neu(phic) - phic) / hz)
 
     rinv = (R["rinv_x"], R["rinv_y"], R["rinv_z"][1:])
-    lap = (D.lap_dirichlet(us, P.h), D.lap_dirichlet(vs, P.h), D.lap_wface(ws, P.h))
+    lap = (D.lap_dirichlet(us, P.h, uw), D.lap_dirichlet(vs, P.h, vw), D.lap_wface(ws, P.h))
     hats = (uh, vh, wh)
     advs = (adv_u, adv_v, adv_w)
     jgs = (jgu, jgv, jgw)
@@ -347,8 +353,10 @@ def navier_stokes(P: Params, st, R, C):
     Returns (u, v, w, p) at n+1 and the pressure increment."""
     ru, rv, rw = momentum_rhs(P, st, R, C)
     g = C.gamma0 / P.dt
-    ut = D.helmholtz(ru, C.nu_m, g, "dirichlet", P.h)
-    vt = D.helmholtz(rv, C.nu_m, g, "dirichlet", P.h)
+    # moving walls (eq. NS13): the no-slip ghosts of the implicit Laplacian carry u_w
+    walls = (lambda c: P.walls(c)) if P.moving_walls else (lambda c: None)
+    ut = D.helmholtz(ru, C.nu_m, g, "dirichlet", P.h, walls(0))
+    vt = D.helmholtz(rv, C.nu_m, g, "dirichlet", P.h, walls(1))
     wt = D.helmholtz(rw, C.nu_m, g, "wface", P.h)
     # Eq. NS37 with the coefficient that makes eq. NS38 divergence free.
     div = D.divergence(ut, vt, wt, P.h)
@@ -371,7 +379,8 @@ def navier_stokes(P: Params, st, R, C):
 def velocity_gradient(P: Params, u, v, w):
     """grad u at cell centres, as L[a][b] = d u_b / d x_a. Diagonal entries from the compact
     face difference; off-diagonal entries from the 2h central difference of the
-    cell-centred velocity, whose wall ghost is the negated adjacent value."""
+    cell-centred velocity, whose wall ghost is twice the wall velocity (eq. NS13) minus the
+    adjacent value."""
     hx, hy, hz = P.h
     uc = 0.5 * (u + D.xm(u))
     vc = 0.5 * (v + D.ym(v))
@@ -388,7 +397,8 @@ def velocity_gradient(P: Params, u, v, w):
         if b != 1:
             L[1][b] = (D.yp(f) - D.ym(f)) / (2 * hy)
         if b != 2:
-            L[2][b] = (D.zp_dir(f) - D.zm_dir(f)) / (2 * hz)
+            wb, wt = P.walls(b)
+            L[2][b] = (D.zp_dir(f, wt) - D.zm_dir(f, wb)) / (2 * hz)
     return L
 
 
@@ -441,6 +451,9 @@ def polymer(P: Params, tau_n, u, v, w):
 def step(P: Params, st, return_parts=False):
     """Advance the state by one coupled step; returns the new state (inputs untouched)."""
     first = st["step"] == 0
+    if P.d_w > 0.0 and P.moving_walls:
+        # eq. NS15 then carries the wall advection D_w u_w . grad(phi), not implemented here
+        raise NotImplementedError("relaxed walls (d_w > 0) with moving walls")
     C = constants(P, first)
     phi_new, G, phis, Psi = cahn_hilliard(P, st, C)
     R = restricted_set(P, phi_new, G, C)

@@ -45,10 +45,14 @@ sin, cos = sp.sin, sp.cos
 # --------------------------------------------------------------------------------------
 
 
-def _fields(two_d: bool):
-    """Two time levels of every input. Velocities vanish on both walls and are odd about
-    them (sin(m pi z)); scalars are even about them (cos(m pi z)). In 2D nothing depends
-    on y and v = 0."""
+UWB, UWT = (0.35, -0.2), (-0.5, 0.45)   # wall velocities (x, y) at z = 0 and z = lz
+
+
+def _fields(two_d: bool, moving: bool = False):
+    """Two time levels of every input. Velocities take the wall values on both walls and,
+    less those values, are odd about them (a linear profile between the walls plus sin(m pi z)
+    terms), so that the no-slip ghost 2 u_w - adjacent is exact; scalars are even about the
+    walls (cos(m pi z)). In 2D nothing depends on y and v = 0."""
     cy = (lambda a: 1) if two_d else (lambda a: cos(KY * Y + a))
     sy = (lambda a: 0) if two_d else (lambda a: sin(KY * Y + a))
     F = {}
@@ -65,6 +69,12 @@ def _fields(two_d: bool):
     F["wA"] = sin(KZ * Z) * (0.3 * sin(KX * X - 0.5) + 0.45 * cy(0.2) + 0.1) \
         + 0.1 * sin(2 * KZ * Z) * cos(KX * X + 0.25) * cy(0.0)
     F["wB"] = 0.35 * sin(KZ * Z) * cos(KX * X) * cy(0.8)
+    if moving:
+        F["uA"] += UWB[0] + (UWT[0] - UWB[0]) * Z / LZ
+        F["uB"] += UWB[0] + (UWT[0] - UWB[0]) * Z / LZ
+        if not two_d:
+            F["vA"] += UWB[1] + (UWT[1] - UWB[1]) * Z / LZ
+            F["vB"] += UWB[1] + (UWT[1] - UWB[1]) * Z / LZ
     F["pA"] = cos(KZ * Z) * cos(KX * X + 0.2) * cy(-0.1) + 0.3 * cos(2 * KZ * Z)
     F["pB"] = 0.5 * sin(KX * X) * cos(KZ * Z) + 0.2 * cy(0.5)
     F["phi"] = 0.6 * cos(KZ * Z) * sin(KX * X + 0.5) * cy(0.3) + 0.2 * cos(2 * KZ * Z)
@@ -102,11 +112,14 @@ def _sample(expr, n_shape, h, loc):
 VLOC = ("ccf", "cfc", "fcc")     # u at x faces, v at y faces, w at z faces
 
 
-def _params(n, two_d):
+def _params(n, two_d, moving=False):
     ny = 1 if two_d else n
+    ub, ut = (UWB, UWT) if moving else ((0.0, 0.0), (0.0, 0.0))
+    if two_d:
+        ub, ut = (ub[0], 0.0), (ut[0], 0.0)
     return model.Params(nx=n, ny=ny, nz=n, lx=LX, ly=LY, lz=LZ, re=3.0, ca=1.0, cn=0.05,
                         pe=10.0, dt=0.25, viscoelastic=1, beta=0.4, wi=0.7,
-                        a_ext=(0.3, -0.2, 0.5))
+                        a_ext=(0.3, -0.2, 0.5), u_wall_bottom=ub, u_wall_top=ut)
 
 
 def _constants():
@@ -213,10 +226,10 @@ TERMS = ("adv", "jgrad", "press", "lap", "pol", "visc", "cap", "total")
 
 
 @functools.lru_cache(maxsize=None)
-def _problem(n, two_d):
+def _problem(n, two_d, moving):
     """Discrete inputs and the continuous terms sampled at each component's points."""
-    F = _fields(two_d)
-    P = _params(n, two_d)
+    F = _fields(two_d, moving)
+    P = _params(n, two_d, moving)
     C = _constants()
     st, R = _discrete_inputs(F, P)
     cont = _continuous_terms(F, P, C)
@@ -233,9 +246,9 @@ def _problem(n, two_d):
     return P, C, st, R, comps, ref
 
 
-def _term_errors(mod, n, two_d):
+def _term_errors(mod, n, two_d, moving=False):
     """Max error of each term over its component arrays, relative to the term's size."""
-    P, C, st, R, comps, ref = _problem(n, two_d)
+    P, C, st, R, comps, ref = _problem(n, two_d, moving)
     disc = _discrete_terms(mod, P, st, R, C)
     errs = {}
     for name in TERMS:
@@ -253,10 +266,13 @@ def _term_errors(mod, n, two_d):
 NS = (12, 24, 48)
 
 
-@pytest.fixture(scope="module", params=[False, True], ids=["3d", "2d"])
+CASES = [(False, False), (True, False), (False, True), (True, True)]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=["3d", "2d", "3d-moving-walls", "2d-moving-walls"])
 def momentum_errors(request):
-    two_d = request.param
-    return two_d, [_term_errors(S, n, two_d) for n in NS]
+    two_d, moving = request.param
+    return two_d, [_term_errors(S, n, two_d, moving) for n in NS]
 
 
 @pytest.mark.parametrize("term", TERMS)
@@ -297,9 +313,9 @@ def test_velocity_gradient_exact_on_linear_fields():
             assert np.max(np.abs(got - A[a, b])) <= 1e-12, (a, b)
 
 
-def _grad_errors(mod, n):
-    F = _fields(False)
-    P = _params(n, False)
+def _grad_errors(mod, n, moving=False):
+    F = _fields(False, moving)
+    P = _params(n, False, moving)
     co = (X, Y, Z)
     U = [F["uA"], F["vA"], F["wA"]]
     arrs = [_sample(U[b], P.coarse_shape, P.h, VLOC[b]) for b in range(3)]
@@ -312,9 +328,10 @@ def _grad_errors(mod, n):
     return errs
 
 
-def test_velocity_gradient_second_order():
+@pytest.mark.parametrize("moving", [False, True], ids=["walls-at-rest", "moving-walls"])
+def test_velocity_gradient_second_order(moving):
     """All nine entries converge at second order on smooth no-slip fields, walls included."""
-    e = [_grad_errors(S, n) for n in NS]
+    e = [_grad_errors(S, n, moving) for n in NS]
     r1, r2 = e[0] / e[1], e[1] / e[2]
     assert np.all(r2 > 3.3) and np.all(r2 < 4.7), (r2, e[2])
     assert np.all(r1 > 3.0), r1
@@ -325,12 +342,12 @@ def test_velocity_gradient_second_order():
 # --------------------------------------------------------------------------------------
 
 
-def _polymer_errors(mod, n, alpha):
+def _polymer_errors(mod, n, alpha, moving=False):
     """RH_ab = -div(u tau_ab) + L_ca tau_cb + tau_ac L_cb + [(1-beta)(L_ab + L_ba) - tau_ab]
     / Wi - alpha / (1 - beta) (tau.tau)_ab against the discrete one (the advection in the flux
     form the oracle uses; equal to u.grad(tau) for a divergence-free velocity)."""
-    F = _fields(False)
-    P = dataclasses.replace(_params(n, False), giesekus_alpha=alpha)
+    F = _fields(False, moving)
+    P = dataclasses.replace(_params(n, False, moving), giesekus_alpha=alpha)
     co = (X, Y, Z)
     U = [F["uA"], F["vA"], F["wA"]]
     pairs = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
@@ -354,9 +371,9 @@ def _polymer_errors(mod, n, alpha):
     return np.array(errs)
 
 
-@pytest.mark.parametrize("alpha", [0.0, 0.3])
-def test_polymer_rhs_second_order(alpha):
-    e = [_polymer_errors(S, n, alpha) for n in NS]
+@pytest.mark.parametrize("alpha,moving", [(0.0, False), (0.3, False), (0.3, True)])
+def test_polymer_rhs_second_order(alpha, moving):
+    e = [_polymer_errors(S, n, alpha, moving) for n in NS]
     r1, r2 = e[0] / e[1], e[1] / e[2]
     assert np.all(r2 > 3.3) and np.all(r2 < 4.7), (r2, e[2])
     assert np.all(r1 > 3.0), r1
@@ -374,8 +391,14 @@ MISTAKES = {
         "adv_w += (fx - D.xm(fx)) / hx",
         "adv_w += (D.xp(fx) - fx) / hx"),
     "advection w at xz edges": (
-        "fz = 0.5 * (w_ext(ws) + D.xp(w_ext(ws))) * u_on_zedges(us)",
-        "fz = w_ext(ws) * u_on_zedges(us)"),
+        "fz = 0.5 * (w_ext(ws) + D.xp(w_ext(ws))) * u_on_zedges(us, uw)",
+        "fz = w_ext(ws) * u_on_zedges(us, uw)"),
+    "wall ghost without twice the wall value": (
+        "return np.concatenate([2.0 * walls[0] - a[:1], a, 2.0 * walls[1] - a[-1:]], axis=0)",
+        "return np.concatenate([walls[0] - a[:1], a, walls[1] - a[-1:]], axis=0)"),
+    "wall velocity of the gradient swapped": (
+        "L[2][b] = (D.zp_dir(f, wt) - D.zm_dir(f, wb)) / (2 * hz)",
+        "L[2][b] = (D.zp_dir(f, wb) - D.zm_dir(f, wt)) / (2 * hz)"),
     "J without face average": (
         "face_avg_x(jz) * dudz", "jz * dudz"),
     "J z difference sign": (
@@ -438,13 +461,16 @@ def _second_order(e0, e1):
 
 def _pins_hold(mod):
     """The convergence pins above on the two coarser grids (the first failure ends it)."""
-    for two_d in (False, True):
-        e = [_term_errors(mod, n, two_d) for n in NS[:2]]
+    for two_d, moving in CASES:
+        e = [_term_errors(mod, n, two_d, moving) for n in NS[:2]]
         if not all(_second_order(e[0][t], e[1][t]) for t in TERMS):
             return False
-    if not _second_order(*[_grad_errors(mod, n) for n in NS[:2]]):
-        return False
-    return _second_order(*[_polymer_errors(mod, n, 0.0) for n in NS[:2]])
+    for moving in (False, True):
+        if not _second_order(*[_grad_errors(mod, n, moving) for n in NS[:2]]):
+            return False
+        if not _second_order(*[_polymer_errors(mod, n, 0.0, moving) for n in NS[:2]]):
+            return False
+    return True
 
 
 def test_pins_hold_on_the_oracle_itself():

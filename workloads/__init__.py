@@ -52,6 +52,8 @@ class Config:
     refine: int = 2             # phase-field grid: 2 dual resolution, 1 single resolution
     advection: int = 0          # 0: second-order central flux, 1: fifth-order WENO-Z
     d_w: float = 0.0             # wall relaxation D_w of eq. NS15
+    u_wall_bottom: tuple = (0.0, 0.0)   # tangential wall velocity (x, y) at z = 0
+    u_wall_top: tuple = (0.0, 0.0)      # tangential wall velocity (x, y) at z = lz
     steps: int = 10
     radius: float = 0.25
     centre: tuple | None = None  # (x, y) of the drop foot on the bottom wall
