@@ -152,7 +152,7 @@ def helmholtz(rhs, coeff, shift, kind, h, walls=None):
         return x
     nz, ny, nx = rhs.shape
     hx, hy, hz = h
-    X = np.fft.fft2(rhs, axes=(1, 2))
+    X = sfft.fft2(rhs, axes=(1, 2))
     lam_xy = _eig_periodic(ny, hy)[:, None] + _eig_periodic(nx, hx)[None, :]
     if kind == "neumann":
         Z = sfft.dct(X, type=2, axis=0, norm="ortho")
@@ -177,7 +177,7 @@ def helmholtz(rhs, coeff, shift, kind, h, walls=None):
     else:
         Y = np.zeros((nz,) + Z.shape[1:], dtype=complex)
         Y[: nz - 1] = sfft.idst(Z, type=1, axis=0, norm="ortho")
-    return np.ascontiguousarray(np.fft.ifft2(Y, axes=(1, 2)).real)
+    return np.ascontiguousarray(sfft.ifft2(Y, axes=(1, 2)).real)
 
 
 def helmholtz_robin(rhs, coeff, shift, d, h):
@@ -192,12 +192,12 @@ def helmholtz_robin(rhs, coeff, shift, d, h):
     hx, hy, hz = h
     _, TR = _wall_normal_matrices(nz, hz, d)
     lam_z, V = np.linalg.eigh(TR)
-    X = np.fft.fft2(rhs, axes=(1, 2))
+    X = sfft.fft2(rhs, axes=(1, 2))
     lam_xy = _eig_periodic(ny, hy)[:, None] + _eig_periodic(nx, hx)[None, :]
     Z = np.tensordot(V.T, X, axes=(1, 0))
     Z = Z / (coeff * (lam_z[:, None, None] + lam_xy[None, :, :]) - shift)
     Y = np.tensordot(V, Z, axes=(1, 0))
-    return np.ascontiguousarray(np.fft.ifft2(Y, axes=(1, 2)).real)
+    return np.ascontiguousarray(sfft.ifft2(Y, axes=(1, 2)).real)
 
 
 def _wall_normal_matrices(nz, hz, d):
@@ -230,7 +230,7 @@ def ch_relaxed_solve(rhs, s, c, d, h):
     nz, ny, nx = rhs.shape
     hx, hy, hz = h
     T, TR = _wall_normal_matrices(nz, hz, d)
-    X = np.fft.fft2(rhs, axes=(1, 2))
+    X = sfft.fft2(rhs, axes=(1, 2))
     lam_xy = _eig_periodic(ny, hy)[:, None] + _eig_periodic(nx, hx)[None, :]
     Y = np.empty_like(X)
     I = np.eye(nz)
@@ -238,7 +238,7 @@ def ch_relaxed_solve(rhs, s, c, d, h):
         mus = lam_xy[j]
         M = np.stack([(T + mu * I) @ (TR + mu * I) - s * (T + mu * I) + c * I for mu in mus])
         Y[:, j, :] = np.linalg.solve(M, X[:, j, :].T[:, :, None])[:, :, 0].T
-    return np.ascontiguousarray(np.fft.ifft2(Y, axes=(1, 2)).real)
+    return np.ascontiguousarray(sfft.ifft2(Y, axes=(1, 2)).real)
 
 
 # ---------------------------------------------------------------------------------------
