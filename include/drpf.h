@@ -49,7 +49,8 @@ extern "C" {
 #define DRPF_EINVAL 1        /* invalid argument or parameter set                      */
 #define DRPF_EWORKSPACE 2    /* workspace missing, too small or misaligned             */
 #define DRPF_EHIP 3          /* a HIP runtime call or kernel launch failed             */
-#define DRPF_ENONFINITE 4    /* a non-finite value was found (drpf_observables)         */
+#define DRPF_ENONFINITE 4    /* a non-finite value was found (drpf_observables, or
+                                drpf_step with check_finite_every > 0)                  */
 #define DRPF_EUNSUPPORTED 5  /* valid but not supported by this library                */
 
 /* Locations for drpf_restrict (eq. dual2 generalised to 3D as a tensor product of the
@@ -110,6 +111,18 @@ typedef struct drpf_params {
                                   cell (a Robin condition; NS25 is solved with it and with
                                   NS33 exactly). 0 (default): static contact angles. The
                                   adjoint needs 0                                            */
+  double u_wall_bottom[2];     /* tangential wall velocity (x, y) at z = 0 and ...            */
+  double u_wall_top[2];        /* ... at z = lz: the no-slip condition u = u_w of eq. NS13
+                                  (ghost = 2 u_w - adjacent in every stencil and in the
+                                  implicit velocity solves). Finite; 0 (default): walls at
+                                  rest. Moving walls need d_w == 0 (DRPF_EUNSUPPORTED
+                                  otherwise: eq. NS15 would gain the wall advection of phi);
+                                  the adjoint needs walls at rest                            */
+  int check_finite_every;      /* > 0: drpf_step checks the phase field and the velocities for
+                                  NaN/Inf after every check_finite_every-th step (counted by the
+                                  state's step counter), synchronising the stream there, and
+                                  stops with DRPF_ENONFINITE at the first failed check. 0
+                                  (default): no checks, fully asynchronous                   */
 } drpf_params;
 
 /* Device pointers of one solution state. Level n is index 0, level n-1 index 1.
@@ -136,6 +149,39 @@ typedef struct drpf_state {
 } drpf_state;
 
 typedef struct drpf_grid drpf_grid;
+
+/* Fields of a state, for drpf_state_layout. */
+enum drpf_field {
+  DRPF_FIELD_PHI = 0,   /* phase field at fine cell centres                                */
+  DRPF_FIELD_U = 1,     /* x velocity at x faces                                           */
+  DRPF_FIELD_V = 2,     /* y velocity at y faces                                           */
+  DRPF_FIELD_W = 3,     /* z velocity at z faces (layer nz-1 is the top wall)              */
+  DRPF_FIELD_P = 4,     /* pressure at coarse centres                                      */
+  DRPF_FIELD_TAU = 5,   /* polymer stress at coarse centres, 6 components                  */
+  DRPF_FIELD_THETA = 6, /* log-conformation at coarse centres, 6 components                */
+  DRPF_NFIELDS = 7
+};
+
+/* Shape, strides and placement of one field's device arrays. Element (i, j, k) of an array
+ * sits at offset i*stride[0] + j*stride[1] + k*stride[2] (elements) and at the point
+ * (origin[0] + i*spacing[0], origin[1] + j*spacing[1], origin[2] + k*spacing[2]). */
+typedef struct drpf_field_layout {
+  int n[3];             /* extents in x, y, z                                              */
+  size_t stride[3];     /* element strides in x, y, z: 1, n[0], n[0]*n[1]                  */
+  size_t elems;         /* elements of one array: n[0]*n[1]*n[2]                           */
+  int arrays;           /* device arrays of this field in a drpf_state: 3 for PHI (levels
+                           n, n-1 and the spare buffer), 2 for U..P, 12 for TAU (2 levels x
+                           6 components) when viscoelastic, 6 for THETA when constitutive
+                           == 1, else 0                                                    */
+  double origin[3];     /* coordinates of element (0, 0, 0)                                */
+  double spacing[3];    /* grid spacings                                                   */
+} drpf_field_layout;
+
+typedef struct drpf_layout {
+  int elem_bytes;                           /* 8 (precision 64) or 4 (precision 32)          */
+  drpf_field_layout field[DRPF_NFIELDS];
+  size_t state_bytes;                       /* sum over fields of arrays * elems * elem_bytes */
+} drpf_layout;
 
 /* Observables returned by drpf_observables, in this order. */
 enum drpf_observable {
@@ -170,8 +216,17 @@ int drpf_init_grid(const drpf_params* p, void* d_workspace, size_t bytes, void* 
 /* Releases the host handle (the workspace stays the caller's). */
 int drpf_destroy(drpf_grid* g);
 
+/* Fills *out with the element counts, strides, placement on the staggered grids (Sec. 3.1:
+ * pressure and stress at cell centres, each velocity component at the faces normal to it,
+ * the phase field at the centres of the refined grid) and array counts of every field of a
+ * drpf_state for this grid. Host only. DRPF_EINVAL for null arguments. */
+int drpf_state_layout(const drpf_grid* g, drpf_layout* out);
+
 /* Advances `s` by `nsteps` coupled steps (Sec. 3.2: CH, restriction, NS projection,
- * polymer), rotating the state pointers after each step as described above. */
+ * polymer), rotating the state pointers after each step as described above. With
+ * check_finite_every > 0 the state is checked after every step whose new step counter is a
+ * multiple of it; a failed check returns DRPF_ENONFINITE with s holding the state after that
+ * step (its counter says which) and the remaining steps not taken. */
 int drpf_step(drpf_grid* g, drpf_state* s, int nsteps, void* stream);
 
 /* Coarse face velocities (u, v, w) -> fine face velocities (uf, vf, wf) by eq. dual1
@@ -188,10 +243,20 @@ int drpf_restrict(drpf_grid* g, const void* fine, void* coarse, int location, vo
  * second-order Laplacian L (periodic x, y; boundary kind `bc` in z) by FFT in x and y and
  * a batched tridiagonal solve per Fourier mode across the walls (the "FFT solver" of
  * Sec. 3.2.1-3.2.2). coeff > 0, shift >= 0; shift == 0 is allowed only with
- * DRPF_BC_NEUMANN and returns the zero-mean solution. For DRPF_BC_FACE_DIRICHLET layer
- * nz-1 of rhs is ignored and that layer of x is set to 0. rhs and x may alias. */
+ * DRPF_BC_NEUMANN and returns the pseudo-inverse's solution: the z-mean of the right-hand
+ * side's (0,0) Fourier mode is dropped and the result has zero mean.
+ * wall_data: null for homogeneous walls, else a device array of 2 * nx * ny elements of the
+ * grid's x-y layer, the bottom wall's layer then the top wall's, giving
+ *   DRPF_BC_NEUMANN: the outward normal derivative g (ghost = adjacent + hz g; the wetting
+ *     data of eq. NS34 has this form),
+ *   DRPF_BC_DIRICHLET: the wall value (ghost = 2 value - adjacent; u = u_w of eq. NS13),
+ *   DRPF_BC_FACE_DIRICHLET: the value of the face field on the wall itself.
+ * The known wall terms move to the right-hand side (the workspace's spectral buffers and
+ * right-hand-side buffer are overwritten). For DRPF_BC_FACE_DIRICHLET layer nz-1 of rhs is
+ * ignored and that layer of x is set to the top wall's value (0 without wall data). rhs and
+ * x may alias; wall_data must not overlap x. */
 int drpf_helmholtz_solve(drpf_grid* g, int which_grid, int bc, double coeff, double shift,
-                         const void* rhs, void* x, void* stream);
+                         const void* rhs, const void* wall_data, void* x, void* stream);
 
 /* Computes the first min(n, DRPF_OBS_COUNT) observables of level n of `s` in FP64 into
  * the host array out. Synchronises `stream`. DRPF_ENONFINITE if the phase field holds a
@@ -214,8 +279,9 @@ int drpf_debug_field(drpf_grid* g, int id, void** ptr, size_t* count);
  * projection), 11-12 coarse y/x inverse transforms, 13-14 polymer stages, 15 WENO-Z
  * advection of the phase field (advection 1 only; it precedes ch_rhs), 16-17 the coarse x and
  * y transforms in one kernel, forward and inverse (in place of 8-9 and 11-12 where a coarse
- * layer fits in one block's LDS: 128 x 128 in either precision). */
-#define DRPF_NKERNELS 18
+ * layer fits in one block's LDS: 128 x 128 in either precision), 18 both polymer stages in one
+ * pass (in place of 13-14 for 3D grids with central advection and the stress form). */
+#define DRPF_NKERNELS 19
 int drpf_profile_begin(drpf_grid* g, int max_launches, void* stream);
 int drpf_profile_end(drpf_grid* g, double* total_ms, int* launches, int n);
 /* Short name of kernel id (see above); "" for an unknown id. */

@@ -17,7 +17,7 @@ DRPF_OK, DRPF_EINVAL, DRPF_EWORKSPACE, DRPF_EHIP, DRPF_ENONFINITE, DRPF_EUNSUPPO
 LOCATIONS = {"center": 0, "face_x": 1, "face_y": 2, "face_z": 3, "edge_xy": 4, "edge_xz": 5,
              "edge_yz": 6}
 BCS = {"neumann": 0, "dirichlet": 1, "face_dirichlet": 2}
-NKERNELS = 18
+NKERNELS = 19
 OBSERVABLES = ("mass", "wetted_radius", "centroid_height", "kinetic_energy", "max_div")
 
 
@@ -40,7 +40,24 @@ class Params(ctypes.Structure):
         ("viscoelastic", ctypes.c_int), ("precision", ctypes.c_int),
         ("constitutive", ctypes.c_int), ("giesekus_alpha", ctypes.c_double),
         ("refine", ctypes.c_int), ("advection", ctypes.c_int), ("d_w", ctypes.c_double),
+        ("u_wall_bottom", ctypes.c_double * 2), ("u_wall_top", ctypes.c_double * 2),
+        ("check_finite_every", ctypes.c_int),
     ]
+
+
+FIELDS = ("phi", "u", "v", "w", "p", "tau", "theta")
+
+
+class FieldLayout(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int * 3), ("stride", ctypes.c_size_t * 3), ("elems", ctypes.c_size_t),
+        ("arrays", ctypes.c_int), ("origin", ctypes.c_double * 3), ("spacing", ctypes.c_double * 3),
+    ]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("elem_bytes", ctypes.c_int), ("field", FieldLayout * len(FIELDS)),
+                ("state_bytes", ctypes.c_size_t)]
 
 
 class State(ctypes.Structure):
@@ -86,7 +103,8 @@ def lib():
             "drpf_step": [vp, P(State), i, vp],
             "drpf_prolong": [vp, vp, vp, vp, vp, vp, vp, vp],
             "drpf_restrict": [vp, vp, vp, i, vp],
-            "drpf_helmholtz_solve": [vp, i, i, d, d, vp, vp, vp],
+            "drpf_helmholtz_solve": [vp, i, i, d, d, vp, vp, vp, vp],
+            "drpf_state_layout": [vp, P(Layout)],
             "drpf_observables": [vp, P(State), P(d), i, vp],
             "drpf_debug_field": [vp, i, P(vp), P(sz)],
             "drpf_profile_begin": [vp, i, vp],
@@ -121,8 +139,8 @@ def make_params(cfg, precision=64) -> Params:
             continue
         if hasattr(cfg, name):
             val = getattr(cfg, name)
-            if name == "a_ext":
-                p.a_ext[:] = [float(x) for x in val]
+            if name in ("a_ext", "u_wall_bottom", "u_wall_top"):
+                getattr(p, name)[:] = [float(x) for x in val]
             else:
                 setattr(p, name, val)
     p.precision = int(precision)
@@ -392,9 +410,25 @@ class Grid:
         return DeviceState(self, host)
 
     def step(self, st: DeviceState, nsteps: int = 1, stream=None):
-        _check(lib().drpf_step(self.handle, ctypes.byref(st.c), int(nsteps), _stream_ptr(stream)))
+        """drpf_step. A failed finite check (check_finite_every > 0) raises DrpfError with code
+        DRPF_ENONFINITE after the state has taken the steps up to and including the failed
+        one (st.step says which)."""
+        rc = lib().drpf_step(self.handle, ctypes.byref(st.c), int(nsteps), _stream_ptr(stream))
         st._pull()
+        _check(rc)
         return st
+
+    def layout(self) -> dict:
+        """drpf_state_layout as {field: {n, stride, elems, arrays, origin, spacing}} plus
+        elem_bytes and state_bytes."""
+        L = Layout()
+        _check(lib().drpf_state_layout(self.handle, ctypes.byref(L)))
+        out = {"elem_bytes": L.elem_bytes, "state_bytes": int(L.state_bytes)}
+        for f, name in enumerate(FIELDS):
+            fl = L.field[f]
+            out[name] = {"n": tuple(fl.n), "stride": tuple(int(x) for x in fl.stride), "elems": int(fl.elems),
+                         "arrays": fl.arrays, "origin": tuple(fl.origin), "spacing": tuple(fl.spacing)}
+        return out
 
     def attach_adjoint(self, stream=None):
         """Allocates and attaches the adjoint workspace (FP64 grids)."""
@@ -437,12 +471,15 @@ class Grid:
         return d
 
     def helmholtz_solve(self, rhs, which="fine", bc="neumann", coeff=1.0, shift=0.0, out=None,
-                        stream=None):
+                        wall=None, stream=None):
+        """drpf_helmholtz_solve; ``wall`` (optional device tensor of two x-y layers, bottom then
+        top) carries the inhomogeneous wall data of the boundary kind."""
         import torch
         x = torch.empty_like(rhs) if out is None else out
+        wp = ctypes.c_void_p(wall.data_ptr()) if wall is not None else None
         _check(lib().drpf_helmholtz_solve(self.handle, 0 if which == "fine" else 1, BCS[bc],
                                           float(coeff), float(shift), ctypes.c_void_p(rhs.data_ptr()),
-                                          ctypes.c_void_p(x.data_ptr()), _stream_ptr(stream)))
+                                          wp, ctypes.c_void_p(x.data_ptr()), _stream_ptr(stream)))
         return x
 
     def prolong(self, u, v, w, stream=None):

@@ -31,6 +31,10 @@ int hip_fail(hipError_t e, const char* where) {
   } while (0)
 
 bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+bool moving_walls(const drpf_params& p) {
+  return p.u_wall_bottom[0] != 0.0 || p.u_wall_bottom[1] != 0.0 || p.u_wall_top[0] != 0.0 ||
+         p.u_wall_top[1] != 0.0;
+}
 int ilog2(int n) {
   int l = 0;
   while ((1 << l) < n) ++l;
@@ -109,6 +113,10 @@ StepConsts make_consts(const drpf_params& p, bool first) {
   c.advection = p.advection;
   c.relax_kappa = p.d_w * c.gamma0 / p.dt;
   c.inv_gamma0 = 1.0 / c.gamma0;
+  for (int a = 0; a < 2; ++a) {
+    c.uwb[a] = p.u_wall_bottom[a];
+    c.uwt[a] = p.u_wall_top[a];
+  }
   return c;
 }
 
@@ -286,7 +294,7 @@ const char* const kKernelNames[DRPF_NKERNELS] = {
     "ch_rhs", "fft_x_fwd_fine", "fft_y_fwd_fine", "zpass_ch", "fft_y_inv_fine", "fft_x_inv_fine",
     "restrict_g", "momentum_rhs", "fft_x_fwd_coarse", "fft_y_fwd_coarse", "zpass_ns",
     "fft_y_inv_coarse", "fft_x_inv_coarse", "polymer_stage1", "polymer_stage2", "weno_adv_fine",
-    "fft_xy_fwd_coarse", "fft_xy_inv_coarse"};
+    "fft_xy_fwd_coarse", "fft_xy_inv_coarse", "polymer_rk2"};
 
 void mark(drpf_grid* g, int kernel, hipStream_t st) {
   if (!g->prof || g->ev_used >= g->ev.size()) return;
@@ -428,6 +436,10 @@ int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t
       HIPCHK(launch_lcr_stage<T>(C, K, io.uo, io.vo, io.wo, thn, t1c, io.theta, io.tauo, 0.5, 0.5, st),
              "log-conformation stage 2");
       mark(g, 14, st);
+    } else if (polymer_rk2_fused<T>(C, K)) {
+      // both stages in one pass; tau^(1) is not stored
+      HIPCHK(launch_polymer_rk2<T>(C, K, io.uo, io.vo, io.wo, io.taun, io.tauo, st), "polymer RK2");
+      mark(g, 18, st);
     } else {
       HIPCHK(launch_polymer_stage<T>(C, K, io.uo, io.vo, io.wo, io.taun, io.taun, t1, 0.0, 1.0, st),
              "polymer stage 1");
@@ -467,9 +479,28 @@ StepIO<T> state_io(const drpf_state* s) {
   return io;
 }
 
+// Finiteness of the phase field (count of non-finite values) and of the velocities (their
+// kinetic-energy sum) of level n of s, from the observables reduction; synchronises st.
+template <typename T>
+int check_finite(drpf_grid* g, const drpf_state* s, hipStream_t st) {
+  double* part = reinterpret_cast<double*>(g->ws + g->o.part);
+  double* obs = reinterpret_cast<double*>(g->ws + g->o.obs);
+  HIPCHK(launch_observables<T>(g->F, g->C, (const T*)s->phi[0], (const T*)s->u[0], (const T*)s->v[0],
+                               (const T*)s->w[0], part, obs, st),
+         "finite check");
+  double host[6];
+  HIPCHK(hipMemcpyAsync(host, obs, 6 * sizeof(double), hipMemcpyDeviceToHost, st), "copy finite check");
+  HIPCHK(hipStreamSynchronize(st), "synchronise finite check");
+  if (host[5] != 0.0 || !isfinite(host[3]))
+    return fail(DRPF_ENONFINITE, "non-finite " + std::string(host[5] != 0.0 ? "phase field" : "velocity") +
+                                     " after step " + std::to_string(s->step));
+  return DRPF_OK;
+}
+
 template <typename T>
 int step_impl(drpf_grid* g, drpf_state* s, int nsteps, hipStream_t st) {
   const bool ve = g->p.viscoelastic != 0;
+  const int every = g->p.check_finite_every;
   for (int n = 0; n < nsteps; ++n) {
     const StepConsts& K = s->step == 0 ? g->k1 : g->k2;
     const int rc = step_one<T>(g, state_io<T>(s), K, st);
@@ -492,17 +523,28 @@ int step_impl(drpf_grid* g, drpf_state* s, int nsteps, hipStream_t st) {
         s->tau[1][m] = tmp;
       }
     s->step += 1;
+    if (every > 0 && s->step % every == 0) {
+      const int cf = check_finite<T>(g, s, st);
+      if (cf) return cf;
+    }
   }
   return DRPF_OK;
 }
 
 template <typename T>
 int helmholtz_impl(drpf_grid* g, int which, int bc, double coeff, double shift, const void* rhs,
-                   void* x, hipStream_t st) {
+                   const void* wall, void* x, hipStream_t st) {
   const Dims& d = which == DRPF_GRID_FINE ? g->F : g->C;
   const Tables<T> tb = tables<T>(g, which == DRPF_GRID_FINE ? g->o.tf : g->o.tc);
   cx<T>* S = reinterpret_cast<cx<T>*>(g->ws + (which == DRPF_GRID_FINE ? g->o.sf : g->o.sc));
   const T* in[4] = {(const T*)rhs, nullptr, nullptr, nullptr};
+  if (wall) {
+    // the known wall terms move to the right-hand side: rhs - coeff b into the grid's
+    // right-hand-side buffer, which the transforms then read
+    T* R = reinterpret_cast<T*>(g->ws + (which == DRPF_GRID_FINE ? g->o.rf : g->o.rc));
+    HIPCHK(launch_wall_rhs<T>(d, bc, coeff, (const T*)rhs, (const T*)wall, R, st), "wall data");
+    in[0] = R;
+  }
   HIPCHK(launch_fft_x_fwd<T>(d, tb, in, 1, S, st), "fft_x");
   HIPCHK(launch_fft_y<T>(d, tb, S, 1, false, st), "fft_y");
   HIPCHK(launch_zpass_helmholtz<T>(d, tb, S, bc, coeff, shift, 1.0 / ((double)d.nx * d.ny), st),
@@ -513,6 +555,8 @@ int helmholtz_impl(drpf_grid* g, int which, int bc, double coeff, double shift, 
   o.p[0] = (T*)x;
   o.nfields = 1;
   HIPCHK(launch_fft_x_inv<T>(d, tb, S, o, st), "ifft_x");
+  if (wall && bc == DRPF_BC_FACE_DIRICHLET)
+    HIPCHK(launch_top_layer<T>(d, (const T*)wall + (size_t)d.nx * d.ny, (T*)x, st), "top wall layer");
   return DRPF_OK;
 }
 
@@ -623,6 +667,13 @@ int adjoint_impl(drpf_grid* g, const drpf_state* x, const drpf_state* xn, drpf_a
     for (int m = 0; m < 6; ++m) io.tauo[m] = P(A.taunew[m]);
     const int rc = step_one<T>(g, io, K, st);
     if (rc) return rc;
+    if (ve && polymer_rk2_fused<T>(C, K)) {
+      // the fused forward update keeps no first stage: recompute it for the transposed update
+      T* t1[6];
+      for (int m = 0; m < 6; ++m) t1[m] = reinterpret_cast<T*>(g->ws + g->o.tau1[m]);
+      HIPCHK(launch_polymer_stage<T>(C, K, io.uo, io.vo, io.wo, io.taun, io.taun, t1, 0.0, 1.0, st),
+             "adjoint polymer stage 1");
+    }
   }
   double* part = P(A.part);
   // ---- polymer
@@ -810,6 +861,12 @@ int drpf_validate(const drpf_params* p) {
   if (!(p->precision == 64 || p->precision == 32)) return fail(DRPF_EINVAL, "precision must be 64 or 32");
   for (int a = 0; a < 3; ++a)
     if (!isfinite(p->a_ext[a])) return fail(DRPF_EINVAL, "a_ext must be finite");
+  for (int a = 0; a < 2; ++a)
+    if (!isfinite(p->u_wall_bottom[a]) || !isfinite(p->u_wall_top[a]))
+      return fail(DRPF_EINVAL, "wall velocities must be finite");
+  if (p->check_finite_every < 0) return fail(DRPF_EINVAL, "check_finite_every must be >= 0");
+  if (p->d_w > 0.0 && moving_walls(*p))
+    return fail(DRPF_EUNSUPPORTED, "relaxed walls (d_w > 0) need walls at rest");
   return DRPF_OK;
 }
 
@@ -879,6 +936,43 @@ int drpf_destroy(drpf_grid* g) {
   return DRPF_OK;
 }
 
+int drpf_state_layout(const drpf_grid* g, drpf_layout* out) {
+  if (!g || !out) return fail(DRPF_EINVAL, "null grid or output");
+  memset(out, 0, sizeof(*out));
+  out->elem_bytes = g->p.precision == 32 ? 4 : 8;
+  // origin offsets in cells: centres at +1/2, a component's own faces at +1
+  const double ctr[3] = {0.5, 0.5, 0.5};
+  const double fx[3] = {1.0, 0.5, 0.5}, fy[3] = {0.5, 1.0, 0.5}, fz[3] = {0.5, 0.5, 1.0};
+  const int ve = g->p.viscoelastic != 0, lcr = g->p.constitutive == 1;
+  struct Spec {
+    const Dims* d;
+    const double* off;
+    int arrays;
+  } spec[DRPF_NFIELDS] = {{&g->F, ctr, 3}, {&g->C, fx, 2}, {&g->C, fy, 2}, {&g->C, fz, 2},
+                          {&g->C, ctr, 2}, {&g->C, ctr, ve ? 12 : 0}, {&g->C, ctr, lcr ? 6 : 0}};
+  size_t total = 0;
+  for (int f = 0; f < DRPF_NFIELDS; ++f) {
+    drpf_field_layout& L = out->field[f];
+    const Dims& d = *spec[f].d;
+    L.n[0] = d.nx;
+    L.n[1] = d.ny;
+    L.n[2] = d.nz;
+    L.stride[0] = 1;
+    L.stride[1] = (size_t)d.nx;
+    L.stride[2] = (size_t)d.nx * d.ny;
+    L.elems = d.cells();
+    L.arrays = spec[f].arrays;
+    const double h[3] = {d.hx, d.hy, d.hz};
+    for (int a = 0; a < 3; ++a) {
+      L.spacing[a] = h[a];
+      L.origin[a] = spec[f].off[a] * h[a];
+    }
+    total += (size_t)L.arrays * L.elems * out->elem_bytes;
+  }
+  out->state_bytes = total;
+  return DRPF_OK;
+}
+
 int drpf_step(drpf_grid* g, drpf_state* s, int nsteps, void* stream) {
   if (!g || !s) return fail(DRPF_EINVAL, "null grid or state");
   if (nsteps < 0) return fail(DRPF_EINVAL, "nsteps must be >= 0");
@@ -928,7 +1022,7 @@ int drpf_restrict(drpf_grid* g, const void* fine, void* coarse, int location, vo
 }
 
 int drpf_helmholtz_solve(drpf_grid* g, int which_grid, int bc, double coeff, double shift,
-                         const void* rhs, void* x, void* stream) {
+                         const void* rhs, const void* wall_data, void* x, void* stream) {
   if (!g || !rhs || !x) return fail(DRPF_EINVAL, "null argument");
   if (which_grid != DRPF_GRID_FINE && which_grid != DRPF_GRID_COARSE) return fail(DRPF_EINVAL, "bad grid");
   if (bc < DRPF_BC_NEUMANN || bc > DRPF_BC_FACE_DIRICHLET) return fail(DRPF_EINVAL, "bad boundary kind");
@@ -936,8 +1030,8 @@ int drpf_helmholtz_solve(drpf_grid* g, int which_grid, int bc, double coeff, dou
     return fail(DRPF_EINVAL, "need coeff > 0 and shift >= 0");
   if (shift == 0 && bc != DRPF_BC_NEUMANN) return fail(DRPF_EINVAL, "shift 0 only with Neumann walls");
   hipStream_t st = (hipStream_t)stream;
-  return g->p.precision == 64 ? helmholtz_impl<double>(g, which_grid, bc, coeff, shift, rhs, x, st)
-                              : helmholtz_impl<float>(g, which_grid, bc, coeff, shift, rhs, x, st);
+  return g->p.precision == 64 ? helmholtz_impl<double>(g, which_grid, bc, coeff, shift, rhs, wall_data, x, st)
+                              : helmholtz_impl<float>(g, which_grid, bc, coeff, shift, rhs, wall_data, x, st);
 }
 
 int drpf_observables(drpf_grid* g, const drpf_state* s, double* out, int n, void* stream) {
@@ -1023,6 +1117,7 @@ int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes) {
   if (p->refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
   if (p->advection != 0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the central advection only");
   if (p->d_w != 0.0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers static contact angles only");
+  if (moving_walls(*p)) return fail(DRPF_EUNSUPPORTED, "the adjoint covers walls at rest only");
   const Dims F = fine_dims(*p);
   // the transposed fine-grid kernels index a fine field with 32-bit integers
   if (F.cells() > (size_t)INT_MAX)

@@ -1,8 +1,9 @@
 // Coarse-grid accessors and the terms of the momentum right-hand side (eq. NS36), shared by
 // the forward momentum kernel and its adjoint. Staggering: u[k][j][i] at ((i+1) hx,
 // (j+.5) hy, (k+.5) hz), v at (i+.5, j+1, k+.5), w at (i+.5, j+.5, k+1) with w[nz-1] the top
-// wall; centres at (i+.5, j+.5, k+.5). Wall rules: no-slip ghost = -adjacent for u, v; w = 0
-// on the walls; Neumann ghost for centred scalars (G, tau).
+// wall; centres at (i+.5, j+.5, k+.5). Wall rules: no-slip ghost = 2 u_w - adjacent for u, v
+// (eq. NS13; -adjacent for walls at rest); w = 0 on the walls; Neumann ghost for centred
+// scalars (G, tau).
 #pragma once
 
 #include "kernels.hpp"
@@ -14,6 +15,7 @@ struct Field {
   const T* a;
   const T* b;   // level n-1 (extrapolation) or null
   int nx, ny, nz, first;
+  T wb = 0, wt = 0;  // wall values at z = 0 and z = lz (no-slip components)
   // 32-bit element indices: every supported grid has fewer than 2^31 cells per array
   __device__ __forceinline__ int idx(int k, int j, int i) const {
     return (k * ny + wrap(j, ny)) * nx + wrap(i, nx);
@@ -24,10 +26,10 @@ struct Field {
     return (first || b == nullptr) ? a[id] : (T)2 * a[id] - b[id];
   }
   __device__ __forceinline__ T n(int k, int j, int i) const { return a[idx(k, j, i)]; }
-  // cell-centred-in-z velocity with no-slip ghosts
+  // cell-centred-in-z velocity with no-slip ghosts (2 wall - adjacent)
   __device__ __forceinline__ T sd(int k, int j, int i) const {
-    if (k < 0) return -s(0, j, i);
-    if (k >= nz) return -s(nz - 1, j, i);
+    if (k < 0) return (T)2 * wb - s(0, j, i);
+    if (k >= nz) return (T)2 * wt - s(nz - 1, j, i);
     return s(k, j, i);
   }
   // z-face velocity: index -1 is the bottom wall, nz-1 the top wall, beyond 0
@@ -298,24 +300,41 @@ __device__ __forceinline__ int tidx(int a, int b) {
   return 2 + a + b;  // 1: xy, 2: xz, 3: yz
 }
 
+// Tangential wall velocities (eq. NS13): u and v at z = 0 (ub, vb) and z = lz (ut, vt).
+template <typename T>
+struct Walls {
+  T ub = 0, ut = 0, vb = 0, vt = 0;
+};
+
+template <typename T>
+__host__ __device__ inline Walls<T> walls_of(const StepConsts& k) {
+  Walls<T> w;
+  w.ub = (T)k.uwb[0];
+  w.ut = (T)k.uwt[0];
+  w.vb = (T)k.uwb[1];
+  w.vt = (T)k.uwt[1];
+  return w;
+}
+
 // Velocity gradient at the centre (k, j, i) as L[a][b] = d u_b / d x_a: diagonal entries from
 // the compact face difference, off-diagonal ones from the 2h central difference of the
-// cell-centred velocity, whose wall ghost is the negated adjacent value.
-template <typename T>
-__device__ __forceinline__ void velocity_gradient(const Coarse<T>& U, const Coarse<T>& V,
-                                                  const Coarse<T>& W, int k, int j, int i, int nz,
-                                                  T ihx, T ihy, T ihz, T L[3][3]) {
+// cell-centred velocity, whose wall ghost is twice the wall velocity minus the adjacent value.
+// A reads the face velocities by at(k, j, i) (Coarse, or an LDS view).
+template <typename T, typename A>
+__device__ __forceinline__ void velocity_gradient(const A& U, const A& V, const A& W, int k, int j,
+                                                  int i, int nz, T ihx, T ihy, T ihz, T L[3][3],
+                                                  const Walls<T>& wl = Walls<T>{}) {
   const T h = (T)0.5;
   auto wv = [&](int kk, int jj, int ii) -> T { return (kk < 0 || kk >= nz - 1) ? (T)0 : W.at(kk, jj, ii); };
   auto uc = [&](int kk, int jj, int ii) -> T {
     const int kc = min(max(kk, 0), nz - 1);
     const T val = h * (U.at(kc, jj, ii) + U.at(kc, jj, ii - 1));
-    return kk == kc ? val : -val;
+    return kk == kc ? val : (T)2 * (kk < kc ? wl.ub : wl.ut) - val;
   };
   auto vc = [&](int kk, int jj, int ii) -> T {
     const int kc = min(max(kk, 0), nz - 1);
     const T val = h * (V.at(kc, jj, ii) + V.at(kc, jj - 1, ii));
-    return kk == kc ? val : -val;
+    return kk == kc ? val : (T)2 * (kk < kc ? wl.vb : wl.vt) - val;
   };
   auto wc = [&](int kk, int jj, int ii) -> T { return h * (wv(kk, jj, ii) + wv(kk - 1, jj, ii)); };
   L[0][0] = (U.at(k, j, i) - U.at(k, j, i - 1)) * ihx;

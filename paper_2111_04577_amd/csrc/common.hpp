@@ -107,6 +107,9 @@ struct StepConsts {
   // wall relaxation (eq. NS34 with D_w > 0): kappa = D_w gamma0 / dt; the wall ghost of phi
   // then carries (kappa / hz)(phi_hat / gamma0 - phi^{n+1}). 0: static contact angle
   double relax_kappa, inv_gamma0;
+  // tangential wall velocities (x, y) at z = 0 and z = lz (eq. NS13, u = u_w): the no-slip
+  // ghost of u and v is 2 u_w - adjacent
+  double uwb[2], uwt[2];
 };
 
 // Block shape of the 3D stencil launches: bx threads along x, by along y, one z layer per

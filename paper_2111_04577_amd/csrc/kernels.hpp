@@ -43,6 +43,16 @@ hipError_t launch_fft_xy_inv(const Dims& d, const Tables<T>& tb, const cx<T>* sp
 template <typename T>
 hipError_t launch_zpass_helmholtz(const Dims& d, const Tables<T>& tb, cx<T>* spec, int bc,
                                   double coeff, double shift, double scale, hipStream_t st);
+// Wall data of a solve moved to its right-hand side: out = rhs - coeff b, b nonzero on the
+// layers next to the walls (bc 0: wall[] = outward normal derivative g, b = g / hz; bc 1: wall
+// value, b = 2 wall / hz^2; bc 2: wall value of the face field, b = wall / hz^2 on faces 0 and
+// nz-2, and layer nz-1 of out is 0). wall holds the bottom then the top x-y layer.
+template <typename T>
+hipError_t launch_wall_rhs(const Dims& d, int bc, double coeff, const T* rhs, const T* wall, T* out,
+                           hipStream_t st);
+// x[nz-1][.][.] = top (one x-y layer)
+template <typename T>
+hipError_t launch_top_layer(const Dims& d, const T* top, T* x, hipStream_t st);
 // Cahn-Hilliard: (L - c_psi) then (L + alpha), both Neumann; with dwall != 0 the fused
 // operator gains L dW (dW: dwall on the two wall-adjacent rows), the relaxed walls of eq. NS34.
 template <typename T>
@@ -110,6 +120,13 @@ template <typename T>
 hipError_t launch_lcr_stage(const Dims& c, const StepConsts& k, const T* u, const T* v, const T* w,
                             const T* const theta_n[6], const T* const theta_in[6], T* const theta_out[6],
                             T* const tau_out[6], double c0, double c1, hipStream_t st);
+// Both RK2-TVD stages in one pass (3D grids, central advection; polymer_rk2_fused says whether
+// the grid and scheme take it): tau_out = tau^{n+1} from tau_n, u fixed; tau^(1) is not stored.
+template <typename T>
+bool polymer_rk2_fused(const Dims& c, const StepConsts& k);
+template <typename T>
+hipError_t launch_polymer_rk2(const Dims& c, const StepConsts& k, const T* u, const T* v, const T* w,
+                              const T* const tau_n[6], T* const tau_out[6], hipStream_t st);
 // One RK2-TVD stage: out = c0 * tau_n + c1 * (tau_in + dt RH(tau_in)), u fixed.
 template <typename T>
 hipError_t launch_polymer_stage(const Dims& c, const StepConsts& k, const T* u, const T* v,

@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(kBlock)
     k_lcr_stage(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
                 ThetaSet<T> thn, ThetaSet<T> thin, ThetaOut<T> thout, ThetaOut<T> tauout, int nx,
                 int ny, int nz, T ihx, T ihy, T ihz, double dt, double inv_wi, double alpha,
-                double c0, double c1, double tau_scale) {
+                double c0, double c1, double tau_scale, Walls<T> wl) {
   int bx, by, bz;
   xcd_tile(bx, by, bz);
   const int i = bx * blockDim.x + threadIdx.x;
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(kBlock)
   const double th[3] = {A[0][0], A[1][1], A[2][2]};
   // L[a][b] = du_b/dx_a, so K_ij = L[j][i]
   T L[3][3];
-  velocity_gradient(U, V, Wf, k, j, i, nz, ihx, ihy, ihz, L);
+  velocity_gradient(U, V, Wf, k, j, i, nz, ihx, ihy, ihz, L, wl);
   double K[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -241,10 +241,11 @@ hipError_t launch_lcr_stage(const Dims& c, const StepConsts& k, const T* u, cons
   }
   const Launch3 L = launch3(c.nx, c.ny, c.nz);
   const double tau_scale = (1.0 - k.beta) / k.wi;
+  const Walls<T> wl = walls_of<T>(k);
 #define DRPF_LCR(LAST, WENO)                                                                      \
   hipLaunchKernelGGL((k_lcr_stage<T, LAST, WENO>), L.grid, L.block, 0, st, u, v, w, tn, ti, to, ta, c.nx, \
                      c.ny, c.nz, (T)c.ihx, (T)c.ihy, (T)c.ihz, k.dt, k.inv_wi, k.giesekus, c0, c1,      \
-                     tau_scale)
+                     tau_scale, wl)
   if (k.advection == 1) {
     if (tau_out) DRPF_LCR(true, true); else DRPF_LCR(false, true);
   } else {

@@ -18,8 +18,8 @@
 //
 // Staggering: u[k][j][i] at ((i+1) hx, (j+.5) hy, (k+.5) hz), v at (i+.5, j+1, k+.5),
 // w at (i+.5, j+.5, k+1) with w[nz-1] the top wall; centres at (i+.5, j+.5, k+.5).
-// Wall rules: no-slip ghost = -adjacent for u, v; w = 0 on the walls; Neumann ghost for
-// centred scalars (G, tau). Arithmetic in the storage type T.
+// Wall rules: no-slip ghost = 2 u_w - adjacent for u, v (eq. NS13, u = u_w); w = 0 on the
+// walls; Neumann ghost for centred scalars (G, tau). Arithmetic in the storage type T.
 #include "coarse.hpp"
 #include "weno.hpp"
 
@@ -42,8 +42,8 @@ __global__ void __launch_bounds__(kBlock)
   const int k = bz / 3;
   const int comp = bz - 3 * k;
   const int f = c.first;
-  MomCtx<T> m{{in.un, in.unm1, nx, ny, nz, f},
-              {in.vn, in.vnm1, nx, ny, nz, f},
+  MomCtx<T> m{{in.un, in.unm1, nx, ny, nz, f, (T)c.uwb[0], (T)c.uwt[0]},
+              {in.vn, in.vnm1, nx, ny, nz, f, (T)c.uwb[1], (T)c.uwt[1]},
               {in.wn, in.wnm1, nx, ny, nz, f},
               {in.pn, in.pnm1, nx, ny, nz, f},
               {in.pn, nullptr, nx, ny, nz, 1},
@@ -236,19 +236,21 @@ __global__ void __launch_bounds__(kBlock)
   auto star_at = [&](const T* a, const T* b, unsigned o) {
     return f ? ld_at(a, o) : (T)2 * ld_at(a, o) - ld_at(b, o);
   };
-  // extrapolated velocities on layer kk: no-slip ghosts (minus the adjacent layer) for u, v
-  // beyond the walls; w is zero on and beyond the walls
+  // extrapolated velocities on layer kk: no-slip ghosts (twice the wall velocity minus the
+  // adjacent layer) for u, v beyond the walls; w is zero on and beyond the walls
   auto load_vel = [&](int kk) {
     const int sl = (kk - K0 + 1) % 3;
     const int kc = min(max(kk, 0), nz - 1);
     const T sg = (kk < 0 || kk >= nz) ? (T)-1 : (T)1;
+    const T bu = kk < 0 ? (T)(2.0 * c.uwb[0]) : kk >= nz ? (T)(2.0 * c.uwt[0]) : (T)0;
+    const T bv = kk < 0 ? (T)(2.0 * c.uwb[1]) : kk >= nz ? (T)(2.0 * c.uwt[1]) : (T)0;
     const bool wz = kk < 0 || kk >= nz - 1;
     const size_t o = kc * layer;
     const T *ua = in.un + o, *ub = in.unm1 + o, *va = in.vn + o, *vb = in.vnm1 + o;
     const T *wa = in.wn + o, *wb = in.wnm1 + o;
     H.each([&](int e, unsigned off) {
-      sU[sl * HP + e] = sg * star_at(ua, ub, off);
-      sV[sl * HP + e] = sg * star_at(va, vb, off);
+      sU[sl * HP + e] = bu + sg * star_at(ua, ub, off);
+      sV[sl * HP + e] = bv + sg * star_at(va, vb, off);
       sW[sl * HP + e] = wz ? (T)0 : star_at(wa, wb, off);
     });
   };
@@ -315,7 +317,7 @@ template <typename T, bool WENO>
 __global__ void __launch_bounds__(kBlock)
     k_polymer_stage(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
                     TauSet<T> tn, TauSet<T> tin, TauOut<T> tout, int nx, int ny, int nz, T ihx,
-                    T ihy, T ihz, T dt, T inv_wi, T one_m_beta, T gk, T c0, T c1) {
+                    T ihy, T ihz, T dt, T inv_wi, T one_m_beta, T gk, T c0, T c1, Walls<T> wl) {
   int bx, by, bz;
   xcd_tile(bx, by, bz);
   const int i = bx * blockDim.x + threadIdx.x;
@@ -326,7 +328,7 @@ __global__ void __launch_bounds__(kBlock)
   const T h = (T)0.5;
   // L[a][b] = d u_b / d x_a
   T L[3][3];
-  velocity_gradient(U, V, Wf, k, j, i, nz, ihx, ihy, ihz, L);
+  velocity_gradient(U, V, Wf, k, j, i, nz, ihx, ihy, ihz, L, wl);
   const T uxp = U.at(k, j, i), uxm = U.at(k, j, i - 1);
   const T vyp = V.at(k, j, i), vym = V.at(k, j - 1, i);
   const T wzp = k < nz - 1 ? Wf.at(k, j, i) : (T)0, wzm = k > 0 ? Wf.at(k - 1, j, i) : (T)0;
@@ -365,6 +367,291 @@ __global__ void __launch_bounds__(kBlock)
       rh -= gk * tt;
     }
     tout.p[m][id] = c0 * tn.p[m][id] + c1 * (t0 + dt * rh);
+  }
+}
+
+// LDS view of coarse layers in a three-slot ring (slot (k - K0 + 3) mod 3) over a block's box
+// (its tile with two cells of halo in x and y): at(k, j, i) for unwrapped global j, i inside
+// the box.
+template <typename T>
+struct BoxRing {
+  const T* base;
+  int plane, K0, X0, Y0, BX;
+  __device__ __forceinline__ T at(int k, int j, int i) const {
+    return base[((k - K0 + 3) % 3) * plane + (j - Y0 + 2) * BX + (i - X0 + 2)];
+  }
+};
+
+// Right-hand side RH of the stress equation (eqs. NS40-NS41 in stress form) at one cell, for
+// all six components: t0 the cell's stress, S the LDS planes (component c at S + c * plane)
+// holding the stress of the cell's layer at box index e (x neighbours e -+ 1, y neighbours e -+ BX),
+// zm / zp the stress of the cells below and above (used only where lo / hi: no flux through
+// a wall), L the velocity gradient and u-, u+, v-, v+, w-, w+ the face velocities.
+template <typename T>
+__device__ __forceinline__ void stress_rhs(const T t0[6], const T* S, int plane, int e, int BX,
+                                           const T zm[6], const T zp[6], bool lo, bool hi,
+                                           const T L[3][3], const T f[6], T ihx, T ihy, T ihz,
+                                           T inv_wi, T omb, T gk, T rh[6]) {
+  const T h = (T)0.5;
+  const int pairs[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    const int a = pairs[m][0], b = pairs[m][1];
+    const T* q = S + m * plane;
+    const T c = t0[m];
+    const T fxp = f[1] * h * (c + q[e + 1]);
+    const T fxm = f[0] * h * (q[e - 1] + c);
+    const T fyp = f[3] * h * (c + q[e + BX]);
+    const T fym = f[2] * h * (q[e - BX] + c);
+    const T fzp = hi ? f[5] * h * (c + zp[m]) : (T)0;
+    const T fzm = lo ? f[4] * h * (zm[m] + c) : (T)0;
+    T r = -((fxp - fxm) * ihx + (fyp - fym) * ihy + (fzp - fzm) * ihz);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) r += L[cc][a] * t0[tidx(cc, b)] + t0[tidx(a, cc)] * L[cc][b];
+    r += (omb * (L[a][b] + L[b][a]) - c) * inv_wi;
+    if (gk != (T)0) {
+      T tt = 0;
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) tt += t0[tidx(a, cc)] * t0[tidx(cc, b)];
+      r -= gk * tt;
+    }
+    rh[m] = r;
+  }
+}
+
+// Both stages of the RK2-TVD polymer update (eqs. NS42, NS44) with u^{n+1} fixed, in one
+// z-marching pass over 3D grids, central advection: a block owns TX x TY columns and KB layers.
+// Stage 1 gives tau^(1) on the tile and on the ring of cells around it whose tau^(1) the
+// stage-2 advection of the tile reads (2 (TX + TY) cells per layer, recomputed by the
+// neighbouring block too); tau^(1) stays in LDS (the layer being finished) and in registers
+// (the cell's own column), and never goes to memory. LDS per block: tau^n of the stage-1 layer
+// and tau^(1) of the stage-2 layer over the box (tile plus two cells of halo), and three-layer
+// rings of u, v, w over the box, from which the velocity gradient of eq. NS41 is formed (the
+// tile cell keeps its own for stage 2). Each thread loads at
+// most RP box points.
+template <typename T, int RP, int WPE, bool PF>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+    k_polymer_rk2_zm(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
+                     TauSet<T> tn, TauOut<T> tout, int nx, int ny, int nz, int KB, T ihx, T ihy,
+                     T ihz, T dt, T inv_wi, T omb, T gk, Walls<T> wl) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int TX = blockDim.x, TY = blockDim.y;
+  int bx, by, bz;
+  xcd_tile(bx, by, bz);
+  const int X0 = bx * TX, Y0 = by * TY, K0 = bz * KB;
+  const int K1 = min(K0 + KB, nz);
+  const int BX = TX + 4, BOX = BX * (TY + 4);
+  const int tid = threadIdx.y * TX + threadIdx.x, nth = TX * TY;
+  T* sTn = reinterpret_cast<T*>(smem);  // 6 planes: tau^n of the stage-1 layer
+  T* sT1 = sTn + 6 * BOX;               // 6 planes: tau^(1) of the stage-2 layer
+  T* sU = sT1 + 6 * BOX;                // 3-slot rings of u, v, w
+  T* sV = sU + 3 * BOX;
+  T* sW = sV + 3 * BOX;
+  const BoxRing<T> Ur{sU, BOX, K0, X0, Y0, BX}, Vr{sV, BOX, K0, X0, Y0, BX}, Wr{sW, BOX, K0, X0, Y0, BX};
+  const size_t layer = (size_t)nx * ny;
+  // this thread's box points and their in-layer byte offsets
+  int bpos[RP];
+  unsigned off[RP];
+#pragma unroll
+  for (int q = 0; q < RP; ++q) {
+    const int e = tid + q * nth;
+    bpos[q] = e < BOX ? e : -1;
+    const int hy = e / BX, hx = e - hy * BX;
+    off[q] = e < BOX ? (unsigned)(wrap(Y0 - 2 + hy, ny) * nx + wrap(X0 - 2 + hx, nx)) * (unsigned)sizeof(T) : 0u;
+  }
+  // own tile cell and, for the first 2 (TX + TY) threads, one ring cell
+  const int i = X0 + threadIdx.x, j = Y0 + threadIdx.y;
+  const int eo = (threadIdx.y + 2) * BX + threadIdx.x + 2;
+  const unsigned oo = (unsigned)(j * nx + i) * (unsigned)sizeof(T);
+  const bool has_h = tid < 2 * (TX + TY);
+  int hi_ = X0, hj = Y0;
+  if (tid < TX) {
+    hi_ = X0 + tid;
+    hj = Y0 - 1;
+  } else if (tid < 2 * TX) {
+    hi_ = X0 + tid - TX;
+    hj = Y0 + TY;
+  } else if (tid < 2 * TX + TY) {
+    hi_ = X0 - 1;
+    hj = Y0 + tid - 2 * TX;
+  } else {
+    hi_ = X0 + TX;
+    hj = Y0 + tid - 2 * TX - TY;
+  }
+  const int eh = (hj - Y0 + 2) * BX + (hi_ - X0 + 2);
+  const unsigned oh = (unsigned)(wrap(hj, ny) * nx + wrap(hi_, nx)) * (unsigned)sizeof(T);
+
+  // Every access is the array's base plus a 32-bit byte offset (layer offset + in-layer
+  // offset; the launcher keeps arrays below 4 GB), so that no 64-bit per-lane address is
+  // formed or kept. With PF the box loads of the next layer are issued one layer ahead into
+  // registers (FP32, which has the registers for it); otherwise they go straight to LDS.
+  const unsigned lbytes = (unsigned)(layer * sizeof(T));
+  T rt[PF ? RP : 1][6], rv[PF ? RP : 1][3];
+  auto fetch_tau = [&](int m) {
+    const unsigned o = (unsigned)m * lbytes;
+#pragma unroll
+    for (int q = 0; q < RP; ++q)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) rt[PF ? q : 0][c] = bpos[q] >= 0 ? ld_at(tn.p[c], o + off[q]) : (T)0;
+  };
+  auto put_tau = [&]() {
+#pragma unroll
+    for (int q = 0; q < RP; ++q)
+      if (bpos[q] >= 0)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sTn[c * BOX + bpos[q]] = rt[q][c];
+  };
+  auto fetch_vel = [&](int l) {
+    const unsigned o = (unsigned)l * lbytes;
+#pragma unroll
+    for (int q = 0; q < RP; ++q) {
+      rv[PF ? q : 0][0] = bpos[q] >= 0 ? ld_at(u, o + off[q]) : (T)0;
+      rv[PF ? q : 0][1] = bpos[q] >= 0 ? ld_at(v, o + off[q]) : (T)0;
+      rv[PF ? q : 0][2] = bpos[q] >= 0 ? ld_at(w, o + off[q]) : (T)0;
+    }
+  };
+  auto put_vel = [&](int l) {
+    const int sl = ((l - K0 + 3) % 3) * BOX;
+#pragma unroll
+    for (int q = 0; q < RP; ++q)
+      if (bpos[q] >= 0) {
+        sU[sl + bpos[q]] = rv[q][0];
+        sV[sl + bpos[q]] = rv[q][1];
+        sW[sl + bpos[q]] = rv[q][2];
+      }
+  };
+  auto box_tau = [&](int m) {
+    const unsigned o = (unsigned)m * lbytes;
+#pragma unroll
+    for (int q = 0; q < RP; ++q)
+      if (bpos[q] >= 0)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sTn[c * BOX + bpos[q]] = ld_at(tn.p[c], o + off[q]);
+  };
+  auto box_vel = [&](int l) {
+    const unsigned o = (unsigned)l * lbytes;
+    const int sl = ((l - K0 + 3) % 3) * BOX;
+#pragma unroll
+    for (int q = 0; q < RP; ++q)
+      if (bpos[q] >= 0) {
+        sU[sl + bpos[q]] = ld_at(u, o + off[q]);
+        sV[sl + bpos[q]] = ld_at(v, o + off[q]);
+        sW[sl + bpos[q]] = ld_at(w, o + off[q]);
+      }
+  };
+  auto load_col = [&](int m, unsigned oc, T (&t)[6]) {
+    const unsigned o = (unsigned)m * lbytes + oc;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) t[c] = ld_at(tn.p[c], o);
+  };
+  // velocity gradient and face velocities (u-, u+, v-, v+, w-, w+) of a cell from the rings
+  auto kinematics = [&](int m, int jj, int ii, T (&L)[3][3], T (&f)[6]) {
+    velocity_gradient(Ur, Vr, Wr, m, jj, ii, nz, ihx, ihy, ihz, L, wl);
+    f[0] = Ur.at(m, jj, ii - 1);
+    f[1] = Ur.at(m, jj, ii);
+    f[2] = Vr.at(m, jj - 1, ii);
+    f[3] = Vr.at(m, jj, ii);
+    f[4] = m > 0 ? Wr.at(m - 1, jj, ii) : (T)0;
+    f[5] = m < nz - 1 ? Wr.at(m, jj, ii) : (T)0;
+  };
+
+  const int mlo = K0 > 0 ? K0 - 1 : 0;
+  if (mlo > 0) box_vel(mlo - 1);
+  box_vel(mlo);
+  if constexpr (PF) {
+    fetch_tau(mlo);
+    if (mlo + 1 < nz) fetch_vel(mlo + 1);
+  }
+  // own column, carried up the march: tau^n of layer m - 1 (tA), tau^(1) of layers k - 1 and k
+  // (t1p, t1c) and the kinematics of layer k (Lk, fk) for stage 2 at k = m - 1
+  T tA[6], t1p[6], t1c[6], Lk[3][3], fk[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) tA[c] = t1p[c] = t1c[c] = fk[c] = (T)0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Lk[a][b] = (T)0;
+  if (mlo > 0) load_col(mlo - 1, oo, tA);
+  for (int m = mlo; m <= K1; ++m) {
+    // tau^n of layer m and the velocities of layer m + 1 into LDS; the own column above
+    T tB[6], tC[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) tC[c] = (T)0;
+    if constexpr (PF) {
+      if (m < nz) put_tau();
+      if (m + 1 < nz) put_vel(m + 1);
+      if (m + 1 < nz) load_col(m + 1, oo, tC);
+      __syncthreads();
+      if (m + 1 < nz) fetch_tau(m + 1);
+      if (m + 2 < nz) fetch_vel(m + 2);
+    } else {
+      if (m < nz) box_tau(m);
+      if (m + 1 < nz) box_vel(m + 1);
+      if (m + 1 < nz) load_col(m + 1, oo, tC);
+      __syncthreads();
+    }
+    // ---- stage 1 at layer m, own cell: tau^(1) = tau^n + dt RH(tau^n)
+    T t1o[6], Lm[3][3], fm[6], rh[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) t1o[c] = tB[c] = (T)0;
+    if (m < nz) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) tB[c] = sTn[c * BOX + eo];
+      kinematics(m, j, i, Lm, fm);
+      stress_rhs<T>(tB, sTn, BOX, eo, BX, tA, tC, m > 0, m < nz - 1, Lm, fm, ihx, ihy, ihz, inv_wi, omb, gk, rh);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) t1o[c] = tB[c] + dt * rh[c];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- stage 2 at layer k = m - 1: tau^{n+1} = tau^n / 2 + (tau^(1) + dt RH(tau^(1))) / 2
+    const int k = m - 1;
+    if (k >= K0) {
+      stress_rhs<T>(t1c, sT1, BOX, eo, BX, t1p, t1o, k > 0, k < nz - 1, Lk, fk, ihx, ihy, ihz, inv_wi, omb, gk, rh);
+      const unsigned o = (unsigned)k * lbytes + oo;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) st_at(tout.p[c], o, (T)0.5 * tA[c] + (T)0.5 * (t1c[c] + dt * rh[c]));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- stage 1 at layer m, ring cell (needed only for stage 2 of this block's layers); its
+    // column's tau^n above and below straight from memory
+    T t1h[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) t1h[c] = (T)0;
+    const bool ring = has_h && m >= K0 && m < K1;
+    if (ring) {
+      T hm[6], h0[6], hp[6], Lh[3][3], fh[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        hm[c] = hp[c] = (T)0;
+        h0[c] = sTn[c * BOX + eh];
+      }
+      if (m > 0) load_col(m - 1, oh, hm);
+      if (m < nz - 1) load_col(m + 1, oh, hp);
+      kinematics(m, hj, hi_, Lh, fh);
+      stress_rhs<T>(h0, sTn, BOX, eh, BX, hm, hp, m > 0, m < nz - 1, Lh, fh, ihx, ihy, ihz, inv_wi, omb, gk, rh);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) t1h[c] = h0[c] + dt * rh[c];
+    }
+    __syncthreads();
+    // tau^(1) of layer m becomes the stage-2 layer of the next step
+    if (m < nz) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sT1[c * BOX + eo] = t1o[c];
+      if (ring)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sT1[c * BOX + eh] = t1h[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      t1p[c] = t1c[c];
+      t1c[c] = t1o[c];
+      fk[c] = fm[c];
+      tA[c] = tB[c];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) Lk[a][b] = Lm[a][b];
   }
 }
 
@@ -426,18 +713,64 @@ hipError_t launch_polymer_stage(const Dims& c, const StepConsts& k, const T* u, 
   }
   const Launch3 L = launch3(c.nx, c.ny, c.nz);
   const T gk = (T)(k.giesekus == 0.0 ? 0.0 : k.giesekus / (1.0 - k.beta));
+  const Walls<T> wl = walls_of<T>(k);
   if (k.advection == 1)
     hipLaunchKernelGGL((k_polymer_stage<T, true>), L.grid, L.block, 0, st, u, v, w, tn, ti, to, c.nx, c.ny,
                        c.nz, (T)c.ihx, (T)c.ihy, (T)c.ihz, (T)k.dt, (T)k.inv_wi, (T)(1.0 - k.beta), gk, (T)c0,
-                       (T)c1);
+                       (T)c1, wl);
   else
     hipLaunchKernelGGL((k_polymer_stage<T, false>), L.grid, L.block, 0, st, u, v, w, tn, ti, to, c.nx, c.ny,
                        c.nz, (T)c.ihx, (T)c.ihy, (T)c.ihz, (T)k.dt, (T)k.inv_wi, (T)(1.0 - k.beta), gk, (T)c0,
-                       (T)c1);
+                       (T)c1, wl);
+  return hipGetLastError();
+}
+
+template <typename T>
+bool polymer_rk2_fused(const Dims& c, const StepConsts& k) {
+  // 3D, central advection, and arrays addressed by 32-bit byte offsets
+  return c.ny > 1 && k.advection == 0 && c.cells() * sizeof(T) < ((size_t)1 << 32);
+}
+
+template <typename T>
+hipError_t launch_polymer_rk2(const Dims& c, const StepConsts& k, const T* u, const T* v, const T* w,
+                              const T* const tau_n[6], T* const tau_out[6], hipStream_t st) {
+  if (!polymer_rk2_fused<T>(c, k)) return hipErrorInvalidValue;
+  TauSet<T> tn;
+  TauOut<T> to;
+  for (int m = 0; m < 6; ++m) {
+    tn.p[m] = tau_n[m];
+    to.p[m] = tau_out[m];
+  }
+  const int TX = c.nx < 32 ? c.nx : 32;
+  const int TY = c.ny < kBlock / TX ? c.ny : kBlock / TX;
+  const int cols = (c.nx / TX) * (c.ny / TY);
+  const int BOX = (TX + 4) * (TY + 4);
+  const int need = (BOX + TX * TY - 1) / (TX * TY);
+  if (need > 4 || 2 * (TX + TY) > TX * TY) return hipErrorInvalidConfiguration;
+  const size_t shm = (size_t)21 * BOX * sizeof(T);
+  const T gk = (T)(k.giesekus == 0.0 ? 0.0 : k.giesekus / (1.0 - k.beta));
+  const Walls<T> wl = walls_of<T>(k);
+  auto go = [&](auto kernel) {
+    const int KB = march_layers(kernel, TX * TY, shm, cols, c.nz);
+    const dim3 grid(c.nx / TX, c.ny / TY, (c.nz + KB - 1) / KB);
+    hipLaunchKernelGGL(kernel, grid, dim3(TX, TY), shm, st, u, v, w, tn, to, c.nx, c.ny, c.nz, KB, (T)c.ihx,
+                       (T)c.ihy, (T)c.ihz, (T)k.dt, (T)k.inv_wi, (T)(1.0 - k.beta), gk, wl);
+  };
+  // registers: 2 waves per SIMD (the LDS of a 32 x 8 tile in FP64 allows two blocks per CU
+  // anyway)
+  constexpr int WPE = 2;
+  constexpr bool PF = sizeof(T) == 4;
+  if (need <= 2)
+    go(k_polymer_rk2_zm<T, 2, WPE, PF>);
+  else
+    go(k_polymer_rk2_zm<T, 4, WPE, PF>);
   return hipGetLastError();
 }
 
 #define INST(T)                                                                                  \
+  template bool polymer_rk2_fused<T>(const Dims&, const StepConsts&);                            \
+  template hipError_t launch_polymer_rk2<T>(const Dims&, const StepConsts&, const T*, const T*,   \
+                                            const T*, const T* const[6], T* const[6], hipStream_t); \
   template hipError_t launch_momentum_rhs<T>(const Dims&, const StepConsts&, NsIn<T>,             \
                                              Restricted<T>, T*, T*, T*, hipStream_t);             \
   template hipError_t launch_polymer_stage<T>(const Dims&, const StepConsts&, const T*, const T*, \

@@ -205,6 +205,34 @@ __global__ void __launch_bounds__(1024)
   if (valid) S[row * stride + l] = mk<T>((T)d[0].re, (T)d[0].im);
 }
 
+// ---- wall data of the generic solve moved to the right-hand side ----------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_wall_rhs(const T* __restrict__ rhs, const T* __restrict__ wall, T* __restrict__ out, int layer,
+               int nz, int bc, T cb, T ct) {
+  const size_t n = (size_t)layer * nz;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(id / layer);
+    const size_t e = id - (size_t)k * layer;
+    T r = rhs[id];
+    if (bc == 2) {
+      if (k == nz - 1) r = (T)0;
+      if (k == 0) r -= cb * wall[e];
+      if (k == nz - 2) r -= ct * wall[layer + e];
+    } else {
+      if (k == 0) r -= cb * wall[e];
+      if (k == nz - 1) r -= ct * wall[layer + e];
+    }
+    out[id] = r;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_top_layer(const T* __restrict__ top, T* __restrict__ x, int layer, size_t base) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < layer; e += gridDim.x * blockDim.x) x[base + e] = top[e];
+}
+
 // ---- Cahn-Hilliard pair -------------------------------------------------------------
 // Both CH operators have zero-flux walls, so the DCT-II across the walls diagonalises them
 // exactly (eigenvalue lam_z(m) of the second difference for cos(pi m (k + 1/2) / nz)). The
@@ -372,12 +400,13 @@ __global__ void __launch_bounds__(1024)
 // ---- Navier-Stokes projection -------------------------------------------------------
 // spec holds four fields of Nz*Ny*P complex each: r_u, r_v, r_w on entry (fields 0-2); on
 // exit u^{n+1}, v^{n+1}, w^{n+1} and the pressure increment p' (field 3).
-template <typename T>
-__global__ void __launch_bounds__(1024)
+// WPE: waves per SIMD the registers must allow (two 1024-thread blocks per CU take 8).
+template <typename T, int WPE>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WPE)))
     k_zpass_ns(cx<T>* __restrict__ spec, int P, int Ny, int Nz, const double* __restrict__ lamx,
                const double* __restrict__ lamy, const double* __restrict__ phx,
                const double* __restrict__ phy, double ihx, double ihy, double ihz, double nu_m,
-               double g_dt, double g_rho_dt, double scale) {
+               double g_dt, double g_rho_dt, double scale, double4 wall) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int TL = blockDim.x / Nz;
   const int line = threadIdx.x % TL;
@@ -395,6 +424,9 @@ __global__ void __launch_bounds__(1024)
   const bool top = row == Nz - 1;
   const bool end = row == 0 || top;
   const T sc = (T)scale;
+  // moving walls (eq. NS13): the no-slip ghosts of u and v carry 2 u_w, a layer constant in x
+  // and y; moved to the right-hand side it is -nu_m 2 u_w / hz^2 on the wall rows of the (0,0)
+  // mode (wall = that term for u at the bottom and top, v at the bottom and top)
   // ---- velocity Helmholtz (nu_m L - gamma0/dt) u~ = r: no-slip walls for u and v at cell
   // centres; w on z faces k = 0..Nz-2, the top-wall row an identity row. Both operators are
   // reduced together.
@@ -404,6 +436,10 @@ __global__ void __launch_bounds__(1024)
   d[0] = valid ? sc * spec[at] : mk<T>(0, 0);
   d[1] = valid ? sc * spec[fsz + at] : mk<T>(0, 0);
   d[2] = (valid && !top) ? sc * spec[2 * fsz + at] : mk<T>(0, 0);
+  if (l == 0 && end) {
+    d[0].re += (T)(row == 0 ? wall.x : wall.y);
+    d[1].re += (T)(row == 0 ? wall.z : wall.w);
+  }
   a[0] = row == 0 ? (T)0 : (T)av;
   c[0] = top ? (T)0 : (T)av;
   b[0] = (T)(nu_m * lxy - (end ? 3.0 : 2.0) * av - g_dt);
@@ -594,6 +630,27 @@ hipError_t launch_zpass_helmholtz(const Dims& d, const Tables<T>& tb, cx<T>* spe
 }
 
 template <typename T>
+hipError_t launch_wall_rhs(const Dims& d, int bc, double coeff, const T* rhs, const T* wall, T* out,
+                           hipStream_t st) {
+  const int layer = d.nx * d.ny;
+  const double ihz = 1.0 / d.hz;
+  // coefficient of the wall value in b (both walls alike), times coeff
+  const double c = coeff * (bc == 0 ? ihz : bc == 1 ? 2.0 * ihz * ihz : ihz * ihz);
+  const size_t n = (size_t)layer * d.nz;
+  const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_wall_rhs<T>, dim3(blocks), dim3(256), 0, st, rhs, wall, out, layer, d.nz, bc, (T)c, (T)c);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_top_layer(const Dims& d, const T* top, T* x, hipStream_t st) {
+  const int layer = d.nx * d.ny;
+  const int blocks = (layer + 255) / 256 < 1024 ? (layer + 255) / 256 : 1024;
+  hipLaunchKernelGGL(k_top_layer<T>, dim3(blocks), dim3(256), 0, st, top, x, layer, (size_t)(d.nz - 1) * layer);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, double c_psi,
                            double alpha, double scale, double dwall, hipStream_t st) {
   // tiles of 128 bytes per row (16 complex FP32 or 8 complex FP64 modes): one cache line
@@ -636,9 +693,14 @@ hipError_t launch_zpass_ns(const Dims& d, const Tables<T>& tb, cx<T>* spec4, con
   int TL = tile_lines(d.nz);
   while (TL > 1 && shm_of(TL) > 65536) TL >>= 1;
   TL = spread_lines(TL, lines, 2048);
-  hipLaunchKernelGGL(k_zpass_ns<T>, dim3((lines + TL - 1) / TL), dim3(TL * d.nz), shm_of(TL), st, spec4,
+  const double bw = -2.0 * c.nu_m / (d.hz * d.hz);
+  const double4 wall = make_double4(bw * c.uwb[0], bw * c.uwt[0], bw * c.uwb[1], bw * c.uwt[1]);
+  // FP32: registers for two blocks of 1024 threads per CU; FP64 (whose LDS allows one such
+  // block) unconstrained
+  constexpr int WPE = sizeof(T) == 4 ? 8 : 4;
+  hipLaunchKernelGGL((k_zpass_ns<T, WPE>), dim3((lines + TL - 1) / TL), dim3(TL * d.nz), shm_of(TL), st, spec4,
                      d.pitch, d.ny, d.nz, tb.lam_x, tb.lam_y, tb.ph_x, tb.ph_y, 1.0 / d.hx, 1.0 / d.hy,
-                     1.0 / d.hz, c.nu_m, c.gamma0 / c.dt, c.gamma0 * c.rho0 / c.dt, scale);
+                     1.0 / d.hz, c.nu_m, c.gamma0 / c.dt, c.gamma0 * c.rho0 / c.dt, scale, wall);
   return hipGetLastError();
 }
 
@@ -663,6 +725,9 @@ hipError_t launch_zpass_ns_adj(const Dims& d, const Tables<double>& tb, cx<doubl
 #define INST(T)                                                                                  \
   template hipError_t launch_zpass_helmholtz<T>(const Dims&, const Tables<T>&, cx<T>*,  \
                                                 int, double, double, double, hipStream_t);       \
+  template hipError_t launch_wall_rhs<T>(const Dims&, int, double, const T*, const T*, T*,     \
+                                         hipStream_t);                                          \
+  template hipError_t launch_top_layer<T>(const Dims&, const T*, T*, hipStream_t);             \
   template hipError_t launch_zpass_ch<T>(const Dims&, const Tables<T>&, cx<T>*, double, \
                                          double, double, double, hipStream_t);                   \
   template hipError_t launch_zpass_ns<T>(const Dims&, const Tables<T>&, cx<T>*,         \

@@ -141,6 +141,73 @@ def test_adjoint_grid_bound():
     assert L.drpf_adjoint_workspace_bytes(ctypes.byref(ok), ctypes.byref(nb)) == B.DRPF_OK
 
 
+def test_validation_walls_and_checks():
+    """Wall velocities finite; check_finite_every >= 0; moving walls need d_w == 0 and have no
+    adjoint."""
+    B = _lib()
+    L = B.lib()
+    nb = ctypes.c_size_t()
+    p = _params()
+    p.u_wall_top[0] = float("nan")
+    assert L.drpf_validate(ctypes.byref(p)) == B.DRPF_EINVAL
+    p = _params(check_finite_every=-1)
+    assert L.drpf_validate(ctypes.byref(p)) == B.DRPF_EINVAL
+    p = _params(check_finite_every=10)
+    assert L.drpf_validate(ctypes.byref(p)) == B.DRPF_OK
+    p = _params()
+    p.u_wall_bottom[1] = 0.5
+    assert L.drpf_validate(ctypes.byref(p)) == B.DRPF_OK
+    assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_EUNSUPPORTED
+    p.d_w = 0.1
+    assert L.drpf_validate(ctypes.byref(p)) == B.DRPF_EUNSUPPORTED
+
+
+C_PROBE = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "drpf.h"
+#define OFF(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
+int main(void) {
+  printf("drpf_params %zu\n", sizeof(drpf_params));
+  OFF(drpf_params, a_ext); OFF(drpf_params, d_w); OFF(drpf_params, u_wall_bottom);
+  OFF(drpf_params, u_wall_top); OFF(drpf_params, check_finite_every);
+  printf("drpf_state %zu\n", sizeof(drpf_state));
+  OFF(drpf_state, step); OFF(drpf_state, theta);
+  printf("drpf_adj %zu\n", sizeof(drpf_adj));
+  printf("drpf_field_layout %zu\n", sizeof(drpf_field_layout));
+  OFF(drpf_field_layout, elems); OFF(drpf_field_layout, arrays); OFF(drpf_field_layout, origin);
+  printf("drpf_layout %zu\n", sizeof(drpf_layout));
+  OFF(drpf_layout, field); OFF(drpf_layout, state_bytes);
+  return 0;
+}
+"""
+
+
+def test_ctypes_structs_match_header(tmp_path):
+    """Sizes and field offsets of the binding's ctypes structures equal the C compiler's for
+    include/drpf.h."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    B = _lib()
+    src = tmp_path / "probe.c"
+    src.write_text(C_PROBE)
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                             check=True).stdout.splitlines())
+    classes = {"drpf_params": B.Params, "drpf_state": B.State, "drpf_adj": B.Adj,
+               "drpf_field_layout": B.FieldLayout, "drpf_layout": B.Layout}
+    for key, val in out.items():
+        if "." in key:
+            cname, field = key.split(".")
+            assert getattr(classes[cname], field).offset == int(val), key
+        else:
+            assert ctypes.sizeof(classes[key]) == int(val), key
+
+
 def test_sizes_and_workspace_errors():
     B = _lib()
     L = B.lib()

@@ -54,6 +54,7 @@ class Config:
     d_w: float = 0.0             # wall relaxation D_w of eq. NS15
     u_wall_bottom: tuple = (0.0, 0.0)   # tangential wall velocity (x, y) at z = 0
     u_wall_top: tuple = (0.0, 0.0)      # tangential wall velocity (x, y) at z = lz
+    check_finite_every: int = 0          # library option: finite checks every n steps (0: none)
     steps: int = 10
     radius: float = 0.25
     centre: tuple | None = None  # (x, y) of the drop foot on the bottom wall
