@@ -1,18 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the dual-resolution phase-field step on one MI355X.
 
-Workload: the 3D Newtonian drop with large property contrast (coarse 128x128x64, fine
-256x256x128 = 8.39M phase-field cells, density ratio 1000, viscosity ratio 100, Cn 0.01,
-Re 100, static angle 90 deg, dt 1e-4), synthetic initial state (hemispherical drop on the
-bottom wall, zero flow). Inputs are resident in HBM before timing starts.
+Workload (headline): the largest single-GPU set-up, a 3D Oldroyd-B drop with density ratio 100
+and viscosity ratio 10 (coarse 256x256x128, fine 512x512x256 = 67.1M phase-field cells, Wi 2,
+beta 0.3, Cn 0.01, Re 1, static angle 45 deg, dt 5e-5), synthetic initial state
+(hemispherical drop on the bottom wall, zero flow and stress). Inputs are resident in HBM
+before timing starts.
 
 Timed: K whole coupled steps (Cahn-Hilliard fine solve, restriction, Navier-Stokes
-projection) after W warm-up steps, bracketed by synchronisations and HIP events on the
-stream the library launches on. Both precision forms are timed: the FP32 form (FP64 kept for
-the pressure Poisson wall-normal solve, its zero mode and the mass sums) is the headline
-value, the FP64 form is reported beside it, with the per-field difference of the FP32 form
-from the FP64 form after the same steps (the FP64 form matches the FP64 CPU reference to
-1e-10 in the GPU tests).
+projection, polymer stress) after W warm-up steps, bracketed by synchronisations and HIP
+events on the stream the library launches on. Both precision forms are timed: the FP32 form
+(FP64 kept for the pressure Poisson wall-normal solve, its zero mode and the mass sums) is the
+headline value, the FP64 form is reported beside it; the workload's own protocol (10 warm-up,
+200 timed steps) is timed too when K and W differ from it.
+
+Accuracy beside the rate: the FP32 and FP64 forms against the FP64 oracle after the steps of
+the oracle's timed sample (the CPU baseline runs the oracle on the same workload), and the
+FP32 form against the FP64 form over long runs of smaller workloads.
 
 Per-kernel durations come from HIP events recorded by the library after every launch
 (drpf_profile_begin / drpf_profile_end) in a second pass of K steps; the roofline entry is
@@ -41,14 +45,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default="C2")
+    ap.add_argument("--config", default="C5")
     ap.add_argument("--precision", choices=["both", "32", "64"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-steps", type=int, default=2,
+                    help="steps of the oracle sample (each leg); also the step count of the accuracy check")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--others", default="C3,C5,C3L,C3P,C2R,C2S,C3S",
+    ap.add_argument("--others", default="C2,C3,C3L,C3P,C2R,C2S,C3S",
                     help="further workloads timed in both forms beside the headline one ('' for none)")
     ap.add_argument("--other-steps", type=int, default=100)
     ap.add_argument("--no-error", action="store_true",
@@ -59,8 +64,8 @@ def parse():
     ap.add_argument("--adjoint-steps", type=int, default=None,
                     help="steps of the gradient case (default: the config's own, 2000 for C4)")
     ap.add_argument("--adjoint-every", type=int, default=50)
-    ap.add_argument("--ingest-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
-                    help="turn rocprofv3 --pmc counter CSVs into the traffic summary and exit")
+    ap.add_argument("--ingest-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON", "WORKLOAD"),
+                    help="turn rocprofv3 --pmc counter CSVs of one workload into the traffic summary and exit")
     return ap.parse_args()
 
 
@@ -110,6 +115,8 @@ def alg_bytes(kernel, cfg, es):
         # log-conformation: stage 2 also writes tau from the new Theta
         "polymer_stage1": 15 * nc if ve else 0,
         "polymer_stage2": (27 if cfg.constitutive == 1 else 21) * nc if ve else 0,
+        # both stages in one pass: u, v, w and tau^n read, tau^{n+1} written
+        "polymer_rk2": 15 * nc if ve else 0,
     }
     return words[kernel] * es
 
@@ -117,7 +124,7 @@ def alg_bytes(kernel, cfg, es):
 KERNEL_SOURCE = {
     "ch_rhs": "stencil_ch.hip", "restrict_g": "stencil_ch.hip", "weno_adv_fine": "stencil_ch.hip",
     "momentum_rhs": "stencil_ns.hip",
-    "polymer_stage1": "stencil_ns.hip", "polymer_stage2": "stencil_ns.hip",
+    "polymer_stage1": "stencil_ns.hip", "polymer_stage2": "stencil_ns.hip", "polymer_rk2": "stencil_ns.hip",
     "zpass_ch": "tridiag.hip", "zpass_ns": "tridiag.hip",
 }
 
@@ -133,15 +140,15 @@ def source_sha(kernel):
     return h.hexdigest()[:16]
 
 
-def traffic_entry(kernel, precision):
-    """HBM bytes per launch from the committed counter summary, if it was taken on the
-    current source of that kernel; else None."""
+def traffic_entry(kernel, precision, workload):
+    """HBM bytes per launch of a kernel on a workload from the committed counter summary, if
+    it was taken on that workload and on the current source of that kernel; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    e = t.get(f"{kernel}/fp{precision}")
+    e = t.get(f"{kernel}/fp{precision}/{workload}")
     if not e or e.get("source_sha") != source_sha(kernel):
         return None
     return e.get("bytes_per_launch")
@@ -186,7 +193,7 @@ def roofline_for(prof, cfg, precision, steps):
                    "share": round(v[0] / sum(total.values()), 4),
                    "alg_GBs": round(alg_bytes(k, cfg, 8 if precision == 64 else 4) / (v[0] / v[1] / 1e3) / 1e9, 1)}
                for k, v in prof.items() if v[1] > 0}
-    traffic = traffic_entry(dom, precision)
+    traffic = traffic_entry(dom, precision, cfg.name)
     return {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "alg_bytes_per_launch": b, "avg_us": round(avg_s * 1e6, 2)}, kernels
@@ -326,30 +333,81 @@ def time_adjoint(drpf, W, name, nsteps, every):
     }
 
 
-def cpu_baseline(W, cfg, nsteps):
-    """The FP64 oracle as it stands on the host, timed over the first nsteps steps."""
+def host_info():
+    """Host CPU model, logical CPU count and the NumPy / SciPy versions."""
     import numpy as np
+    import scipy
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_cpus": os.cpu_count(), "numpy": np.__version__, "scipy": scipy.__version__}
+
+
+def cpu_baseline(W, cfg, nsteps):
+    """The FP64 oracle as it stands on the host, timed over the first nsteps steps of the
+    workload, twice: with scipy.fft on every logical CPU (the transforms of its solves; its
+    elementwise NumPy work is single-threaded either way) and on one. Returns the record and
+    the oracle state after the steps."""
+    import scipy.fft as sfft
     from oracle import model
     from oracle import step as S
     P = model.Params.from_config(cfg)
-    st = W.droplet_state(cfg)
-    t0 = time.perf_counter()
-    st = S.run(P, st, nsteps)
-    dt = time.perf_counter() - t0
     F, _ = grid_sizes(cfg)
-    return {"value": round(F["cells"] * nsteps / dt, 1), "unit": "fine cell-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"first {nsteps} steps of the same workload (full grid); "
-                      f"NumPy/SciPy FP64, single-threaded (scipy.fft workers=1), {dt:.1f} s",
-            "host_cpus": os.cpu_count()}
+    legs = {}
+    state = None
+    ncpu = os.cpu_count() or 1
+    for workers in (ncpu, 1):
+        st = W.droplet_state(cfg)
+        with sfft.set_workers(workers):
+            t0 = time.perf_counter()
+            for _ in range(nsteps):
+                st = S.step(P, st)
+            dt = time.perf_counter() - t0
+        legs[workers] = (F["cells"] * nsteps / dt, dt)
+        if state is None:
+            state = st
+        del st
+    info = host_info()
+    sample = (f"first {nsteps} steps of the same workload ({cfg.name}, full grid, {F['cells']} fine cells); "
+              f"NumPy/SciPy FP64 oracle; scipy.fft workers = {ncpu} for its transforms, elementwise NumPy "
+              f"single-threaded; {legs[ncpu][1]:.1f} s")
+    rec = {"value": round(legs[ncpu][0], 1), "unit": "fine cell-updates/s", "cores": ncpu, "kind": "oracle",
+           "sample": sample,
+           "one_core": {"value": round(legs[1][0], 1), "cores": 1, "seconds": round(legs[1][1], 2),
+                        "sample": f"the same {nsteps} steps with scipy.fft workers = 1"}}
+    rec.update(info)
+    return rec, state
 
 
-def ingest_pmc(fetch_csv, write_csv, out_json):
+def accuracy_vs_oracle(drpf, W, cfg, nsteps, oracle_state):
+    """Per-field error of both GPU forms against the oracle after nsteps steps from the same
+    initial state (max |x - x_ref| / max |x_ref| and rms / max |x_ref|)."""
+    import torch
+    out = {"after_steps": nsteps, "workload": cfg.name}
+    for prec in (32, 64):
+        g = drpf.Grid(cfg, prec)
+        st = g.state(W.droplet_state(cfg))
+        g.step(st, nsteps)
+        torch.cuda.synchronize()
+        out[f"fp{prec}"] = field_diff(st.to_host(), oracle_state)
+        del g, st
+        torch.cuda.empty_cache()
+    return out
+
+
+def ingest_pmc(fetch_csv, write_csv, out_json, workload):
     """rocprofv3 --pmc counter_collection.csv files (one run with FETCH_SIZE, one with
-    WRITE_SIZE, each of `bench.py --copy-calibration`) -> HBM bytes per launch of every kernel,
-    merged into out_json. Each counter (KiB per dispatch) is scaled by (copy bytes) / (the same
-    counter read on the 1 GiB device copy of that run). Kernels launched on both grids are
-    told apart by their grid size (the larger is the fine grid)."""
+    WRITE_SIZE, each of `bench.py --copy-calibration` on one workload) -> HBM bytes per launch
+    of every kernel on that workload, merged into out_json under kernel/precision/workload.
+    Each counter (KiB per dispatch) is scaled by (copy bytes) / (the same counter read on the
+    1 GiB device copy of that run). Kernels launched on both grids are told apart by their
+    grid size (the larger is the fine grid)."""
     import csv
     import re
     from collections import defaultdict
@@ -381,7 +439,7 @@ def ingest_pmc(fetch_csv, write_csv, out_json):
     fetch, fs = read(fetch_csv, "FETCH_SIZE")
     write, ws = read(write_csv, "WRITE_SIZE")
     base = {"k_ch_rhs": "ch_rhs", "k_restrict_g": "restrict_g", "k_momentum_rhs": "momentum_rhs",
-            "k_momentum_rhs_zm": "momentum_rhs", "k_polymer_div_zm": "polymer_div",
+            "k_momentum_rhs_zm": "momentum_rhs", "k_polymer_div_zm": "polymer_div", "k_polymer_rk2_zm": "polymer_rk2",
             "k_zpass_ch": "zpass_ch", "k_zpass_ns": "zpass_ns",
             "k_fft_xy_fwd": "fft_xy_fwd_coarse", "k_fft_xy_inv": "fft_xy_inv_coarse"}
     sizes = defaultdict(set)
@@ -408,7 +466,7 @@ def ingest_pmc(fetch_csv, write_csv, out_json):
         prec = 32 if t == "float" else 64
         fb = sum(vals) / len(vals) * 1024 * fs
         wb = sum(write[key]) / len(write[key]) * 1024 * ws
-        out[f"{name}/fp{prec}"] = {"bytes_per_launch": round(fb + wb), "fetch_bytes": round(fb),
+        out[f"{name}/fp{prec}/{workload}"] = {"bytes_per_launch": round(fb + wb), "fetch_bytes": round(fb),
                                    "write_bytes": round(wb), "dispatches": len(vals),
                                    "source_sha": source_sha(name)}
     out["_calibration"] = {"copy_bytes": copy_bytes, "fetch_scale": fs, "write_scale": ws}
@@ -416,6 +474,72 @@ def ingest_pmc(fetch_csv, write_csv, out_json):
         json.dump(out, f, indent=1, sort_keys=True)
     print(json.dumps(out["_calibration"]))
     return out
+
+
+def survey_bytes_per_cell(cfg, es):
+    """Compulsory bytes per fine cell-update of the hot-path byte model (each stage reads its
+    inputs and writes its outputs once, spectral intermediates not counted): 11 fine words plus
+    60 coarse words per coarse cell (Newtonian) or 110 (viscoelastic), a coarse cell being 8
+    fine cells in 3D and 4 in 2D (where the velocity has two components and the stress three:
+    21.5 and 28.25 words)."""
+    if cfg.ny == 1:
+        words = 28.25 if cfg.viscoelastic else 21.5
+    else:
+        words = 24.75 if cfg.viscoelastic else 18.5
+    return words * es
+
+
+def describe(cfg):
+    F, _ = grid_sizes(cfg)
+    law = "Newtonian"
+    if cfg.viscoelastic:
+        law = f"Giesekus alpha {cfg.giesekus_alpha:g}" if cfg.giesekus_alpha else f"Oldroyd-B Wi {cfg.wi:g} beta {cfg.beta:g}"
+        law += ", log-conformation" if cfg.constitutive == 1 else ", stress form"
+    law += ", WENO-Z advection" if cfg.advection == 1 else ", central advection"
+    if cfg.d_w > 0:
+        law += f", relaxed walls D_w {cfg.d_w:g}"
+    if cfg.refine == 1:
+        law += ", single resolution"
+    dim = "2D" if cfg.ny == 1 else "3D"
+    return (f"{cfg.name}: {dim} drop on a wall, {law}, coarse {cfg.nx}x{cfg.ny}x{cfg.nz}, fine "
+            f"{F['nx']}x{F['ny']}x{F['nz']} ({F['cells']} cells), rho ratio {cfg.rho_ratio:g}, mu ratio "
+            f"{cfg.mu_ratio:g}, Re {cfg.re:g}, Cn {cfg.cn:g}, Pe {cfg.pe:g}, theta {cfg.theta_bottom_deg:g} deg, "
+            f"dt {cfg.dt:g}")
+
+
+def step_bandwidth(cfg, kernels, steps, ms_per_step, es, ceiling):
+    """Whole-step bandwidth by two byte models: the sum of the kernels' algorithmic bytes
+    (spectral intermediates included) and the compulsory bytes per fine cell of the hot-path
+    model, each against the HBM peak and the measured copy ceiling."""
+    F, _ = grid_sizes(cfg)
+    kb = sum(alg_bytes(k, cfg, es) * v["launches"] / steps for k, v in kernels.items())
+    sb = survey_bytes_per_cell(cfg, es) * F["cells"]
+    out = {}
+    for name, b in (("kernel_bytes", kb), ("compulsory_bytes", sb)):
+        gbs = b / (ms_per_step / 1e3) / 1e9
+        out[name] = {"bytes_per_step": int(b), "achieved": round(gbs, 1),
+                     "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "frac_of_copy": round(gbs / ceiling, 4)}
+    out["copy_ceiling"] = round(ceiling, 1)
+    return out
+
+
+def time_plain(drpf, W, cfg, precision, steps, warmup):
+    """Step time without the per-kernel pass (the workload's own protocol)."""
+    import torch
+    g = drpf.Grid(cfg, precision)
+    st = g.state(W.droplet_state(cfg))
+    g.step(st, warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    g.step(st, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del g, st
+    torch.cuda.empty_cache()
+    return ms / steps
 
 
 def main():
@@ -453,10 +577,11 @@ def main():
         for _ in range(3):
             y.copy_(x)
         torch.cuda.synchronize()
+        del x, y
     head = 32 if 32 in res else 64
     out = {
-        # the value is the FP32 form's rate; the FP64 form, the FP32 form's per-field error and
-        # the adjoint's adj/fwd ratio are reported beside it (fp64, fp32_error_vs_fp64, adjoint)
+        # the value is the FP32 form's rate; the FP64 form, the per-field errors of both forms
+        # against the oracle and the adjoint's adj/fwd ratio are reported beside it
         "metric": "fine-grid cell-updates/s per dual-res step, FP32 vs FP64 at stated error; adj/fwd",
         "value": round(res[head]["value"], 1),
         "unit": "cell-updates/s",
@@ -469,68 +594,54 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if head == 32 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{cfg.name}: 3D Newtonian drop on a wall, coarse {cfg.nx}x{cfg.ny}x{cfg.nz}, "
-                               f"fine {F['nx']}x{F['ny']}x{F['nz']} ({F['cells']} cells), rho ratio "
-                               f"{cfg.rho_ratio:g}, mu ratio {cfg.mu_ratio:g}, Re {cfg.re:g}, Cn {cfg.cn:g}, "
-                               f"Pe {cfg.pe:g}, dt {cfg.dt:g}",
+        "config": {"workload": describe(cfg),
                    "fine_cells": F["cells"], "coarse_cells": C["cells"],
                    "precision_islands": "FP64 Poisson wall-normal solve, zero mode, mass sums"
                    if head == 32 else "all FP64"},
         "roofline": res[head]["roofline"],
         "kernels": res[head]["kernels"],
     }
-    # whole-step algorithmic bytes (sum over the kernels of one step) per step time, against
-    # the HBM peak and a device-copy ceiling measured here
     ceiling = copy_ceiling(torch)
     for prec in res:
         es = 4 if prec == 32 else 8
-        step_bytes = sum(alg_bytes(k, cfg, es) * v["launches"] / a.steps for k, v in res[prec]["kernels"].items())
-        gbs = step_bytes / (res[prec]["ms_per_step"] / 1e3) / 1e9
-        res[prec]["step_bw"] = {"alg_bytes_per_step": int(step_bytes), "achieved": round(gbs, 1),
-                                "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
-                                "copy_ceiling": round(ceiling, 1), "frac_of_copy": round(gbs / ceiling, 4)}
+        res[prec]["step_bw"] = step_bandwidth(cfg, res[prec]["kernels"], a.steps, res[prec]["ms_per_step"], es, ceiling)
     out["step_bandwidth"] = res[head]["step_bw"]
     if 64 in res and head != 64:
         out["fp64"] = {"value": round(res[64]["value"], 1), "ms_per_step": round(res[64]["ms_per_step"], 4),
                        "roofline": res[64]["roofline"], "step_bandwidth": res[64]["step_bw"],
                        "kernels": res[64]["kernels"]}
         out["fp32_vs_fp64_speedup"] = round(res[32]["value"] / res[64]["value"], 3)
-        if not a.no_error:
-            print("[bench] FP32 vs FP64 error: C2 500 steps, C3, C3L and C3P 1000 steps", file=sys.stderr,
-                  flush=True)
-            out["fp32_error_vs_fp64"] = {"C2": precision_error(drpf, W, "C2", 500),
-                                         "C3": precision_error(drpf, W, "C3", 1000),
-                                         "C3L": precision_error(drpf, W, "C3L", 1000),
-                                         "C3P": precision_error(drpf, W, "C3P", 1000)}
+    # the workload's own protocol (10 warm-up, 200 timed steps), when K and W differ from it
+    if (a.steps, a.warmup) != (200, 10):
+        proto = {"warmup": 10, "steps": 200}
+        for prec in forms:
+            print(f"[bench] protocol fp{prec} {cfg.name}: 10 warm-up + 200 steps", file=sys.stderr, flush=True)
+            msps = time_plain(drpf, W, cfg, prec, 200, 10)
+            proto[f"fp{prec}"] = {"value": round(F["cells"] / (msps / 1e3), 1), "ms_per_step": round(msps, 4)}
+        out["protocol_200_steps"] = proto
+    if 64 in res and head != 64 and not a.no_error:
+        print("[bench] FP32 vs FP64 error: C2 500 steps, C3, C3L and C3P 1000 steps", file=sys.stderr,
+              flush=True)
+        out["fp32_error_vs_fp64"] = {"C2": precision_error(drpf, W, "C2", 500),
+                                     "C3": precision_error(drpf, W, "C3", 1000),
+                                     "C3L": precision_error(drpf, W, "C3L", 1000),
+                                     "C3P": precision_error(drpf, W, "C3P", 1000)}
     others = [x for x in a.others.split(",") if x and x != cfg.name]
     if others:
         out["other_workloads"] = {}
     for name in others:
         ocfg = W.config(name)
         OF, OC = grid_sizes(ocfg)
-        law = "Newtonian"
-        if ocfg.viscoelastic:
-            law = f"Giesekus alpha {ocfg.giesekus_alpha:g}" if ocfg.giesekus_alpha else "Oldroyd-B"
-            law += ", log-conformation" if ocfg.constitutive == 1 else ", stress form"
-        law += ", WENO-Z advection" if ocfg.advection == 1 else ", central advection"
-        if ocfg.d_w > 0:
-            law += f", relaxed walls D_w {ocfg.d_w:g}"
-        ent = {"workload": f"{name}: coarse {ocfg.nx}x{ocfg.ny}x{ocfg.nz}, fine {OF['nx']}x{OF['ny']}x{OF['nz']} "
-                           f"({OF['cells']} cells), {law}, "
-                           f"rho ratio {ocfg.rho_ratio:g}, mu ratio {ocfg.mu_ratio:g}",
-               "steps": a.other_steps}
+        ent = {"workload": describe(ocfg), "steps": a.other_steps}
         for prec in (32, 64):
             print(f"[bench] timing fp{prec} {name}: 5 warm-up + {a.other_steps} steps", file=sys.stderr, flush=True)
             g, st, ms, wall, prof, obs = time_form(drpf, W, ocfg, prec, a.other_steps, 5)
             roof, kern = roofline_for(prof, ocfg, prec, a.other_steps)
             es = 4 if prec == 32 else 8
-            step_bytes = sum(alg_bytes(k, ocfg, es) * v["launches"] / a.other_steps for k, v in kern.items())
             msps = ms / a.other_steps
-            gbs = step_bytes / (msps / 1e3) / 1e9
             ent[f"fp{prec}"] = {"value": round(OF["cells"] * a.other_steps / (ms / 1e3), 1),
                                 "ms_per_step": round(msps, 4),
-                                "step_bandwidth": {"achieved": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
-                                                   "frac_of_copy": round(gbs / ceiling, 4)},
+                                "step_bandwidth": step_bandwidth(ocfg, kern, a.other_steps, msps, es, ceiling),
                                 "roofline": roof}
             del g, st
             torch.cuda.empty_cache()
@@ -539,17 +650,13 @@ def main():
     # dual- vs single-resolution step time at the same phase-field grid (256x256x128):
     # C2 / C2S (Newtonian) and C3 / C3S (Oldroyd-B)
     ow = out.get("other_workloads", {})
-    pairs = {"newtonian": (res, "C2S"), "viscoelastic": (ow.get("C3"), "C3S")}
     dvs = {}
-    for kind, (dual, sname) in pairs.items():
-        if dual is None or sname not in ow:
+    for kind, dname, sname in (("newtonian", "C2", "C2S"), ("viscoelastic", "C3", "C3S")):
+        if dname not in ow or sname not in ow:
             continue
         dvs[kind] = {}
         for prec in (32, 64):
-            d = dual.get(prec) if kind == "newtonian" else dual.get(f"fp{prec}")
-            if d is None:
-                continue
-            t_dual = d["ms_per_step"]
+            t_dual = ow[dname][f"fp{prec}"]["ms_per_step"]
             t_single = ow[sname][f"fp{prec}"]["ms_per_step"]
             dvs[kind][f"fp{prec}"] = {"dual_ms": round(t_dual, 4), "single_ms": round(t_single, 4),
                                       "speedup": round(t_single / t_dual, 3)}
@@ -562,8 +669,12 @@ def main():
     else:
         out["adj_fwd"] = None
     if not a.no_cpu_baseline:
-        print(f"[bench] cpu baseline: oracle, {a.cpu_steps} steps", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(W, cfg, a.cpu_steps)
+        print(f"[bench] cpu baseline: oracle, {a.cpu_steps} steps of {cfg.name}, all cores then one",
+              file=sys.stderr, flush=True)
+        out["cpu_baseline"], ostate = cpu_baseline(W, cfg, a.cpu_steps)
+        print(f"[bench] both forms against the oracle after {a.cpu_steps} steps", file=sys.stderr, flush=True)
+        out["error_vs_oracle"] = accuracy_vs_oracle(drpf, W, cfg, a.cpu_steps, ostate)
+        del ostate
     print(json.dumps(out), flush=True)
 
 

@@ -21,7 +21,7 @@ import workloads as W  # noqa: E402
 KERNELS = ["ch_rhs", "weno_adv_fine", "fft_x_fwd_fine", "fft_y_fwd_fine", "zpass_ch", "fft_y_inv_fine",
            "fft_x_inv_fine", "restrict_g", "momentum_rhs", "fft_x_fwd_coarse", "fft_y_fwd_coarse",
            "zpass_ns", "fft_y_inv_coarse", "fft_x_inv_coarse", "fft_xy_fwd_coarse",
-           "fft_xy_inv_coarse", "polymer_stage1", "polymer_stage2"]
+           "fft_xy_inv_coarse", "polymer_stage1", "polymer_stage2", "polymer_rk2"]
 
 
 def test_more_than_one_gpu_is_refused():
@@ -53,7 +53,7 @@ def test_byte_model_properties(name):
         b32, b64 = bench.alg_bytes(k, cfg, 4), bench.alg_bytes(k, cfg, 8)
         assert b64 == 2 * b32 >= 0, k
     # the polymer stages move bytes only when there is a polymer
-    for k in ("polymer_stage1", "polymer_stage2"):
+    for k in ("polymer_stage1", "polymer_stage2", "polymer_rk2"):
         assert (bench.alg_bytes(k, cfg, 8) > 0) == bool(cfg.viscoelastic), k
     # y transforms only where there is a y direction
     for k in ("fft_y_fwd_fine", "fft_y_inv_fine", "fft_y_fwd_coarse", "fft_y_inv_coarse"):
@@ -70,17 +70,41 @@ def test_weno_moves_the_velocity_reads_out_of_ch_rhs():
     assert diff == 8 * (F["cells"] - 6 * C["cells"])
 
 
-def test_traffic_is_reported_only_for_the_measured_source(tmp_path, monkeypatch):
+def test_traffic_is_reported_only_for_the_measured_source_and_workload(tmp_path, monkeypatch):
     root = tmp_path / "repo"
     shutil.copytree(os.path.join(ROOT, "paper_2111_04577_amd", "csrc"), root / "paper_2111_04577_amd" / "csrc")
     (root / "profiles").mkdir()
     monkeypatch.setattr(bench, "ROOT", str(root))
-    assert bench.traffic_entry("restrict_g", 32) is None  # no counter summary at all
+    assert bench.traffic_entry("restrict_g", 32, "C5") is None  # no counter summary at all
     entry = {"source_sha": bench.source_sha("restrict_g"), "bytes_per_launch": 12345}
-    (root / "profiles" / "traffic.json").write_text(json.dumps({"restrict_g/fp32": entry}))
-    assert bench.traffic_entry("restrict_g", 32) == 12345
-    assert bench.traffic_entry("restrict_g", 64) is None
+    (root / "profiles" / "traffic.json").write_text(json.dumps({"restrict_g/fp32/C5": entry}))
+    assert bench.traffic_entry("restrict_g", 32, "C5") == 12345
+    assert bench.traffic_entry("restrict_g", 64, "C5") is None
+    # taken on another workload: not reported for this one
+    assert bench.traffic_entry("restrict_g", 32, "C2") is None
     # a change to a shared header makes the stored figure stale
     hdr = root / "paper_2111_04577_amd" / "csrc" / "common.hpp"
     hdr.write_text(hdr.read_text() + "\n// edited\n")
-    assert bench.traffic_entry("restrict_g", 32) is None
+    assert bench.traffic_entry("restrict_g", 32, "C5") is None
+
+
+def test_compulsory_byte_model():
+    """18.5 / 24.75 words per fine cell in 3D (Newtonian / viscoelastic), 21.5 / 28.25 in 2D."""
+    assert bench.survey_bytes_per_cell(W.config("C2"), 4) == 74
+    assert bench.survey_bytes_per_cell(W.config("C5"), 4) == 99
+    assert bench.survey_bytes_per_cell(W.config("C5"), 8) == 198
+    assert bench.survey_bytes_per_cell(W.config("C1"), 8) == 172
+    assert bench.survey_bytes_per_cell(W.config("C4"), 8) == 226
+
+
+def test_headline_defaults():
+    """The headline workload is the largest single-GPU one, timed 10 + 200 by default."""
+    import sys
+    old = sys.argv
+    sys.argv = ["bench.py"]
+    try:
+        a = bench.parse()
+    finally:
+        sys.argv = old
+    assert a.config == "C5" and a.steps == 200 and a.warmup == 10
+    assert "C5" not in a.others.split(",")
