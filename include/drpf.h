@@ -258,6 +258,19 @@ int drpf_restrict(drpf_grid* g, const void* fine, void* coarse, int location, vo
 int drpf_helmholtz_solve(drpf_grid* g, int which_grid, int bc, double coeff, double shift,
                          const void* rhs, const void* wall_data, void* x, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): drpf_helmholtz_solve with the same arguments,
+ * kernels and results, whose scratch (the spectral buffer, and with wall_data the right-hand
+ * side with the wall terms) is a static 32 MiB device array of the library instead of the
+ * grid's workspace, so that the grid's workspace is left untouched. It calls no hipMalloc,
+ * hipFree or allocating routine. DRPF_EWORKSPACE if the solve needs more than 32 MiB of
+ * scratch: ((nx/2 + 1) * ny * nz complex elements of the chosen grid, plus nx * ny * nz
+ * elements with wall data, the first rounded up to 256 bytes). Every call on one GPU uses that
+ * GPU's one array: calls that overlap on a GPU (on different streams, or from several threads)
+ * race and must be serialised by the caller. */
+int drpf_helmholtz_solve_static(drpf_grid* g, int which_grid, int bc, double coeff, double shift,
+                                const void* rhs, const void* wall_data, void* x, void* stream);
+
 /* Computes the first min(n, DRPF_OBS_COUNT) observables of level n of `s` in FP64 into
  * the host array out. Synchronises `stream`. DRPF_ENONFINITE if the phase field holds a
  * NaN or Inf (the values are still written). */

@@ -104,6 +104,7 @@ def lib():
             "drpf_prolong": [vp, vp, vp, vp, vp, vp, vp, vp],
             "drpf_restrict": [vp, vp, vp, i, vp],
             "drpf_helmholtz_solve": [vp, i, i, d, d, vp, vp, vp, vp],
+            "drpf_helmholtz_solve_static": [vp, i, i, d, d, vp, vp, vp, vp],
             "drpf_state_layout": [vp, P(Layout)],
             "drpf_observables": [vp, P(State), P(d), i, vp],
             "drpf_debug_field": [vp, i, P(vp), P(sz)],
@@ -480,6 +481,17 @@ class Grid:
         _check(lib().drpf_helmholtz_solve(self.handle, 0 if which == "fine" else 1, BCS[bc],
                                           float(coeff), float(shift), ctypes.c_void_p(rhs.data_ptr()),
                                           wp, ctypes.c_void_p(x.data_ptr()), _stream_ptr(stream)))
+        return x
+
+    def helmholtz_solve_static(self, rhs, which="fine", bc="neumann", coeff=1.0, shift=0.0, out=None,
+                               wall=None, stream=None):
+        """drpf_helmholtz_solve_static: the same solve with the library's static scratch."""
+        import torch
+        x = torch.empty_like(rhs) if out is None else out
+        wp = ctypes.c_void_p(wall.data_ptr()) if wall is not None else None
+        _check(lib().drpf_helmholtz_solve_static(self.handle, 0 if which == "fine" else 1, BCS[bc],
+                                                 float(coeff), float(shift), ctypes.c_void_p(rhs.data_ptr()),
+                                                 wp, ctypes.c_void_p(x.data_ptr()), _stream_ptr(stream)))
         return x
 
     def prolong(self, u, v, w, stream=None):

@@ -5,6 +5,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -167,6 +168,37 @@ Offsets layout(const drpf_params& p, const Dims& F, const Dims& C) {
   o.obs = cv.take(8 * 8);
   o.total = cv.off;
   return o;
+}
+
+}  // namespace
+
+// Scratch of the allocation-free solve (drpf_helmholtz_solve_static): the spectral buffer
+// and the right-hand side with the wall terms of one solve, for grids up to this size. Each
+// GPU holds its own copy until the process ends; in host code its name is only a stand-in for
+// the device address, which scratch_ptr() looks up once per device.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up on the first call per
+// device, with that device current).
+int scratch_ptr(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(DRPF_EUNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DRPF_OK;
 }
 
 }  // namespace
@@ -531,17 +563,22 @@ int step_impl(drpf_grid* g, drpf_state* s, int nsteps, hipStream_t st) {
   return DRPF_OK;
 }
 
+// The solve's scratch: the spectral buffer S and the buffer R of the right-hand side with the
+// wall terms (used only with wall data); by default the grid's workspace buffers.
 template <typename T>
 int helmholtz_impl(drpf_grid* g, int which, int bc, double coeff, double shift, const void* rhs,
-                   const void* wall, void* x, hipStream_t st) {
+                   const void* wall, void* x, hipStream_t st, void* s_scr = nullptr,
+                   void* r_scr = nullptr) {
   const Dims& d = which == DRPF_GRID_FINE ? g->F : g->C;
   const Tables<T> tb = tables<T>(g, which == DRPF_GRID_FINE ? g->o.tf : g->o.tc);
-  cx<T>* S = reinterpret_cast<cx<T>*>(g->ws + (which == DRPF_GRID_FINE ? g->o.sf : g->o.sc));
+  cx<T>* S = s_scr ? reinterpret_cast<cx<T>*>(s_scr)
+                   : reinterpret_cast<cx<T>*>(g->ws + (which == DRPF_GRID_FINE ? g->o.sf : g->o.sc));
   const T* in[4] = {(const T*)rhs, nullptr, nullptr, nullptr};
   if (wall) {
-    // the known wall terms move to the right-hand side: rhs - coeff b into the grid's
-    // right-hand-side buffer, which the transforms then read
-    T* R = reinterpret_cast<T*>(g->ws + (which == DRPF_GRID_FINE ? g->o.rf : g->o.rc));
+    // the known wall terms move to the right-hand side: rhs - coeff b into the right-hand-side
+    // buffer, which the transforms then read
+    T* R = r_scr ? reinterpret_cast<T*>(r_scr)
+                 : reinterpret_cast<T*>(g->ws + (which == DRPF_GRID_FINE ? g->o.rf : g->o.rc));
     HIPCHK(launch_wall_rhs<T>(d, bc, coeff, (const T*)rhs, (const T*)wall, R, st), "wall data");
     in[0] = R;
   }
@@ -921,6 +958,11 @@ int drpf_init_grid(const drpf_params* p, void* d_workspace, size_t bytes, void* 
     const hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) rc = hip_fail(e, "init synchronise");
   }
+  if (!rc) {
+    // set-up of the allocation-free solve on this device
+    void* scr = nullptr;
+    rc = scratch_ptr(&scr);
+  }
   if (rc) {
     delete g;
     return rc;
@@ -1021,14 +1063,43 @@ int drpf_restrict(drpf_grid* g, const void* fine, void* coarse, int location, vo
   return DRPF_OK;
 }
 
-int drpf_helmholtz_solve(drpf_grid* g, int which_grid, int bc, double coeff, double shift,
-                         const void* rhs, const void* wall_data, void* x, void* stream) {
+static int helmholtz_args(drpf_grid* g, int which_grid, int bc, double coeff, double shift, const void* rhs,
+                          void* x) {
   if (!g || !rhs || !x) return fail(DRPF_EINVAL, "null argument");
   if (which_grid != DRPF_GRID_FINE && which_grid != DRPF_GRID_COARSE) return fail(DRPF_EINVAL, "bad grid");
   if (bc < DRPF_BC_NEUMANN || bc > DRPF_BC_FACE_DIRICHLET) return fail(DRPF_EINVAL, "bad boundary kind");
   if (!(coeff > 0) || !(shift >= 0) || !isfinite(coeff) || !isfinite(shift))
     return fail(DRPF_EINVAL, "need coeff > 0 and shift >= 0");
   if (shift == 0 && bc != DRPF_BC_NEUMANN) return fail(DRPF_EINVAL, "shift 0 only with Neumann walls");
+  return DRPF_OK;
+}
+
+int drpf_helmholtz_solve_static(drpf_grid* g, int which_grid, int bc, double coeff, double shift,
+                                const void* rhs, const void* wall_data, void* x, void* stream) {
+  const int rc = helmholtz_args(g, which_grid, bc, coeff, shift, rhs, x);
+  if (rc) return rc;
+  const Dims& d = which_grid == DRPF_GRID_FINE ? g->F : g->C;
+  const size_t es = g->p.precision == 32 ? 4 : 8;
+  const size_t sbytes = (d.spec() * 2 * es + 255) & ~(size_t)255;
+  const size_t need = sbytes + (wall_data ? d.cells() * es : 0);
+  if (need > kStaticScratchBytes)
+    return fail(DRPF_EWORKSPACE, "drpf_helmholtz_solve_static: the solve needs " + std::to_string(need) +
+                                     " bytes of scratch, above the static limit of " +
+                                     std::to_string(kStaticScratchBytes));
+  void* scr = nullptr;
+  const int pc = scratch_ptr(&scr);
+  if (pc) return pc;
+  char* base = (char*)scr;
+  hipStream_t st = (hipStream_t)stream;
+  return g->p.precision == 64
+             ? helmholtz_impl<double>(g, which_grid, bc, coeff, shift, rhs, wall_data, x, st, base, base + sbytes)
+             : helmholtz_impl<float>(g, which_grid, bc, coeff, shift, rhs, wall_data, x, st, base, base + sbytes);
+}
+
+int drpf_helmholtz_solve(drpf_grid* g, int which_grid, int bc, double coeff, double shift,
+                         const void* rhs, const void* wall_data, void* x, void* stream) {
+  const int rc = helmholtz_args(g, which_grid, bc, coeff, shift, rhs, x);
+  if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   return g->p.precision == 64 ? helmholtz_impl<double>(g, which_grid, bc, coeff, shift, rhs, wall_data, x, st)
                               : helmholtz_impl<float>(g, which_grid, bc, coeff, shift, rhs, wall_data, x, st);
