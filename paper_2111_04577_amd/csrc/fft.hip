@@ -122,8 +122,11 @@ __global__ void k_fft_y(cx<T>* __restrict__ data, int Ny, int logNy, int P, int 
   extern __shared__ unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int M = P - 1;
-  const int tile = blockIdx.x % ntiles;
-  const int batch = blockIdx.x / ntiles;
+  // XCD-ordered: consecutive tiles, which share cache lines when a tile row is narrower than a
+  // line (FP32 tiles of 8 modes, 64 bytes, on 512-point lines), run on one XCD and its L2
+  const int lb = xcd_block();
+  const int tile = lb % ntiles;
+  const int batch = lb / ntiles;
   cx<T>* base = data + (size_t)batch * Ny * P;
   // tiles 0 .. ntiles-2: tkx consecutive kx < M of every row; the last tile: the Nyquist
   // column (contiguous in ky), in lane 0 of the tile

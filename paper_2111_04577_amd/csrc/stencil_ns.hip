@@ -756,9 +756,10 @@ hipError_t launch_polymer_rk2(const Dims& c, const StepConsts& k, const T* u, co
     hipLaunchKernelGGL(kernel, grid, dim3(TX, TY), shm, st, u, v, w, tn, to, c.nx, c.ny, c.nz, KB, (T)c.ihx,
                        (T)c.ihy, (T)c.ihz, (T)k.dt, (T)k.inv_wi, (T)(1.0 - k.beta), gk, wl);
   };
-  // registers: 2 waves per SIMD (the LDS of a 32 x 8 tile in FP64 allows two blocks per CU
-  // anyway)
-  constexpr int WPE = 2;
+  // registers: FP32 2 waves per SIMD (222 VGPRs, no spills); FP64 1 (its 289 live registers
+  // spill to scratch at 2 waves, 2.5x the algorithmic bytes on the C5 grid and slower: 864 against
+  // 731 us)
+  constexpr int WPE = sizeof(T) == 4 ? 2 : 1;
   constexpr bool PF = sizeof(T) == 4;
   if (need <= 2)
     go(k_polymer_rk2_zm<T, 2, WPE, PF>);
