@@ -31,7 +31,12 @@
  *
  * Streams: every call that takes a stream queues its work asynchronously on it (a
  * hipStream_t passed as void*; NULL is the default stream), except drpf_observables, which
- * synchronises that stream before returning. Calls on one grid must not overlap.
+ * synchronises that stream before returning. Calls on one grid must not overlap. On a
+ * viscoelastic grid drpf_step runs each step's polymer update on a stream the library creates
+ * (default priority, created by drpf_init_grid, released by drpf_destroy), forked from the
+ * caller's stream by an event after the velocity correction and joined back by an event before
+ * the next step's momentum right-hand side and before drpf_step returns: the caller's stream
+ * orders all of the call's work as if it had run on it alone.
  *
  * Errors: every call returns one of the DRPF_* codes below; drpf_last_error() gives a
  * thread-local message for the last failure on the calling thread.

@@ -211,6 +211,12 @@ struct drpf_grid {
   Offsets o;
   // adjoint workspace (FP64 grids), attached by drpf_adjoint_attach
   char* aws = nullptr;
+  // viscoelastic grids: the polymer update of a step runs on a stream of the library's own,
+  // forked from the caller's stream after the velocity correction and joined before the next
+  // step's momentum right-hand side (the next step's Cahn-Hilliard pass overlaps it)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool pending = false;
   // per-kernel timing: one event after each launch, one at the start of profiling
   bool prof = false;
   std::vector<hipEvent_t> ev;
@@ -354,7 +360,7 @@ struct StepIO {
 // One coupled step (Sec. 3.2): Cahn-Hilliard, restriction, Navier-Stokes, polymer stress.
 // Leaves the restricted coarse set and the first polymer stage in the workspace.
 template <typename T>
-int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t st) {
+int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t st, bool overlap = false) {
   const Dims& F = g->F;
   const Dims& C = g->C;
   const Tables<T> tf = tables<T>(g, g->o.tf), tc = tables<T>(g, g->o.tc);
@@ -416,6 +422,11 @@ int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t
   ni.viscoelastic = ve ? 1 : 0;
   // the first three stage-1 polymer arrays are free until the polymer update
   for (int a = 0; a < 3; ++a) ni.pol[a] = ve ? reinterpret_cast<T*>(g->ws + g->o.tau1[a]) : nullptr;
+  // the previous step's polymer update (tau^n here, and the stage arrays) must be complete
+  if (g->pending) {
+    HIPCHK(hipStreamWaitEvent(st, g->ev_join, 0), "join polymer stream");
+    g->pending = false;
+  }
   HIPCHK(launch_momentum_rhs<T>(C, K, ni, R, Rc, Rc + nc, Rc + 2 * nc, st), "momentum_rhs");
   mark(g, 7, st);
   const T* inc[4] = {Rc, Rc + nc, Rc + 2 * nc, nullptr};
@@ -449,7 +460,15 @@ int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t
     HIPCHK(launch_fft_x_inv<T>(C, tc, Sc, oc, st), "ifft_x coarse");
     mark(g, 12, st);
   }
-  // ---- polymer stress, RK2-TVD with u^{n+1}
+  // ---- polymer stress, RK2-TVD with u^{n+1}: on the library's stream when overlapping (it reads
+  // u^{n+1} and tau^n and writes tau^{n+1} and the stage arrays, none of which the next step's
+  // Cahn-Hilliard pass and restriction touch)
+  hipStream_t pst = st;
+  if (ve && overlap) {
+    HIPCHK(hipEventRecord(g->ev_fork, st), "fork polymer stream");
+    HIPCHK(hipStreamWaitEvent(g->side, g->ev_fork, 0), "fork polymer stream");
+    pst = g->side;
+  }
   if (ve) {
     T* t1[6];
     const T* t1c[6];
@@ -462,24 +481,28 @@ int step_one(drpf_grid* g, const StepIO<T>& io, const StepConsts& K, hipStream_t
       // then tau^{n+1} from it
       const T* thn[6];
       for (int m = 0; m < 6; ++m) thn[m] = io.theta[m];
-      HIPCHK(launch_lcr_stage<T>(C, K, io.uo, io.vo, io.wo, thn, thn, t1, nullptr, 0.0, 1.0, st),
+      HIPCHK(launch_lcr_stage<T>(C, K, io.uo, io.vo, io.wo, thn, thn, t1, nullptr, 0.0, 1.0, pst),
              "log-conformation stage 1");
-      mark(g, 13, st);
-      HIPCHK(launch_lcr_stage<T>(C, K, io.uo, io.vo, io.wo, thn, t1c, io.theta, io.tauo, 0.5, 0.5, st),
+      mark(g, 13, pst);
+      HIPCHK(launch_lcr_stage<T>(C, K, io.uo, io.vo, io.wo, thn, t1c, io.theta, io.tauo, 0.5, 0.5, pst),
              "log-conformation stage 2");
-      mark(g, 14, st);
+      mark(g, 14, pst);
     } else if (polymer_rk2_fused<T>(C, K)) {
       // both stages in one pass; tau^(1) is not stored
-      HIPCHK(launch_polymer_rk2<T>(C, K, io.uo, io.vo, io.wo, io.taun, io.tauo, st), "polymer RK2");
-      mark(g, 18, st);
+      HIPCHK(launch_polymer_rk2<T>(C, K, io.uo, io.vo, io.wo, io.taun, io.tauo, pst), "polymer RK2");
+      mark(g, 18, pst);
     } else {
-      HIPCHK(launch_polymer_stage<T>(C, K, io.uo, io.vo, io.wo, io.taun, io.taun, t1, 0.0, 1.0, st),
+      HIPCHK(launch_polymer_stage<T>(C, K, io.uo, io.vo, io.wo, io.taun, io.taun, t1, 0.0, 1.0, pst),
              "polymer stage 1");
-      mark(g, 13, st);
-      HIPCHK(launch_polymer_stage<T>(C, K, io.uo, io.vo, io.wo, io.taun, t1c, io.tauo, 0.5, 0.5, st),
+      mark(g, 13, pst);
+      HIPCHK(launch_polymer_stage<T>(C, K, io.uo, io.vo, io.wo, io.taun, t1c, io.tauo, 0.5, 0.5, pst),
              "polymer stage 2");
-      mark(g, 14, st);
+      mark(g, 14, pst);
     }
+  }
+  if (ve && overlap) {
+    HIPCHK(hipEventRecord(g->ev_join, g->side), "join polymer stream");
+    g->pending = true;
   }
   return DRPF_OK;
 }
@@ -533,9 +556,23 @@ template <typename T>
 int step_impl(drpf_grid* g, drpf_state* s, int nsteps, hipStream_t st) {
   const bool ve = g->p.viscoelastic != 0;
   const int every = g->p.check_finite_every;
+  // the polymer update overlaps the next step on the library's stream, except while per-kernel
+  // events are being recorded (they time one stream)
+  const bool overlap = g->side != nullptr && !g->prof;
+  // whatever happens, the caller's stream ends up after the last polymer update
+  struct Join {
+    drpf_grid* g;
+    hipStream_t st;
+    ~Join() {
+      if (g->pending) {
+        (void)hipStreamWaitEvent(st, g->ev_join, 0);
+        g->pending = false;
+      }
+    }
+  } join{g, st};
   for (int n = 0; n < nsteps; ++n) {
     const StepConsts& K = s->step == 0 ? g->k1 : g->k2;
-    const int rc = step_one<T>(g, state_io<T>(s), K, st);
+    const int rc = step_one<T>(g, state_io<T>(s), K, st, overlap);
     if (rc) return rc;
     // ---- rotate time levels (pointer swaps only)
     void* ph0 = s->phi[0];
@@ -963,8 +1000,15 @@ int drpf_init_grid(const drpf_params* p, void* d_workspace, size_t bytes, void* 
     void* scr = nullptr;
     rc = scratch_ptr(&scr);
   }
+  if (!rc && p->viscoelastic) {
+    // the stream the polymer update overlaps on (default priority) and its fork/join events
+    hipError_t e = hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) rc = hip_fail(e, "polymer stream");
+  }
   if (rc) {
-    delete g;
+    drpf_destroy(g);
     return rc;
   }
   *out = g;
@@ -972,8 +1016,15 @@ int drpf_init_grid(const drpf_params* p, void* d_workspace, size_t bytes, void* 
 }
 
 int drpf_destroy(drpf_grid* g) {
-  if (g)
+  if (g) {
     for (auto e : g->ev) (void)hipEventDestroy(e);
+    if (g->side) {
+      (void)hipStreamSynchronize(g->side);
+      (void)hipStreamDestroy(g->side);
+    }
+    if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
+    if (g->ev_join) (void)hipEventDestroy(g->ev_join);
+  }
   delete g;
   return DRPF_OK;
 }
