@@ -1,4 +1,7 @@
-// In-LDS batched complex FFT shared by the transform passes (x, y and the wall-normal DCT).
+// In-LDS batched complex FFT with the length and the stage strides at run time: the FP64 x
+// and y passes and wall-normal DCT (at 16 bytes per point this form, with consecutive lanes on
+// consecutive LDS words in every stage, measured faster than the compile-time form of
+// lds_fft16.hpp), and the fused x-y passes of a whole layer in both precisions.
 #pragma once
 
 #include "common.hpp"

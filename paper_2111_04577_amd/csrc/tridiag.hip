@@ -21,10 +21,13 @@
 //   zpass_helmholtz -- one generic solve (the drpf_helmholtz_solve entry point).
 #include "kernels.hpp"
 #include "lds_fft.hpp"
+#include "lds_fft16.hpp"
 
 namespace drpf {
 
 namespace {
+
+constexpr int kZBlock = 1024;  // most threads per block of the Cahn-Hilliard wall-normal pass
 
 // Reciprocal of a diagonal entry: the hardware estimate refined by Newton-Raphson steps
 // (r <- r + r (1 - b r)), one for FP32 and two for FP64, each squaring the relative error of
@@ -241,10 +244,172 @@ __global__ void __launch_bounds__(256)
 // away from zero, since lam <= 0, alpha < 0 < c_psi), inverse DCT. Each DCT is one length-nz complex
 // FFT in LDS (Makhoul's even/odd reordering with a quarter-wave twiddle); the data are
 // complex (x/y spectral coefficients), so the real and imaginary sequences are separated
-// from the pair (V_m, V_{nz-m}). A block holds TL consecutive modes, columns in LDS.
+// from the pair (V_m, V_{nz-m}). A block holds TL consecutive modes, each a line of the
+// compile-time FFT form (lds_fft16.hpp), which serves FP32; k_zpass_ch_rt below is the same
+// pass with the run-time form (lds_fft.hpp, columns in LDS), which serves FP64.
+template <typename T, bool ROBIN, int LOGNZ>
+__global__ void __launch_bounds__(kZBlock)
+    k_zpass_ch(cx<T>* __restrict__ S, int P, int Ny, int TL,
+               const double* __restrict__ lamx, const double* __restrict__ lamy,
+               const double* __restrict__ lamz, const cx<T>* __restrict__ twz,
+               const cx<T>* __restrict__ twq, double c_psi, double alpha, double scale, double dwall) {
+  using F = FftPlan<LOGNZ, fft_lp<T>()>;
+  constexpr int Nz = F::M;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem);  // mode t at t LS, position n at pad(n)
+  cx<T>* stw = buf + TL * F::LS;                 // twiddles of the length-Nz transform
+  for (int e = threadIdx.x; e < Nz; e += blockDim.x) stw[e] = twz[e];
+  const int lines = P * Ny;
+  const int l0 = xcd_block() * TL;
+  const size_t stride = (size_t)lines;
+  const int ltl = __ffs(TL) - 1;  // TL is a power of two
+  auto at = [&](int n, int t) -> cx<T>& { return buf[t * F::LS + F::pad(n)]; };
+  for (int e = threadIdx.x; e < Nz * TL; e += blockDim.x) {
+    const int row = e >> ltl, t = e & (TL - 1);
+    const int l = l0 + t;
+    const int pos = (row & 1) ? (Nz - 1 - (row >> 1)) : (row >> 1);
+    at(pos, t) = l < lines ? S[row * stride + l] : mk<T>(0, 0);
+  }
+  __syncthreads();
+  const int fb = threadIdx.x >> F::LT, fq = threadIdx.x & (F::T - 1);
+  fft16<T, false, LOGNZ, fft_lp<T>()>(buf + fb * F::LS, fq, fb < TL, stw);
+  const int half = Nz >> 1;
+  const T hf = (T)0.5;
+  const T cp = (T)c_psi, al = (T)alpha, sc = (T)scale;
+  // forward DCT-II coefficient from (V_m, V_{N-m}): X = Re(w A) + i Re(w B),
+  // A = (V_m + conj V_{N-m}) / 2, B = (V_m - conj V_{N-m}) / (2i)
+  auto dct_out = [&](cx<T> V, cx<T> Vp, cx<T> w) -> cx<T> {
+    const cx<T> A = hf * (V + conj(Vp));
+    const cx<T> B = hf * mul_mi(V - conj(Vp));
+    return mk<T>((w * A).re, (w * B).re);
+  };
+  // inverse: Y_m = conj(w_m) [(P_m + Q_{N-m}) + i (Q_m - P_{N-m})], X_N = 0
+  auto inverse_in = [&](int m, int mr, int t, cx<T> Fm, cx<T> Fr) {
+    if (mr != m) {
+      at(m, t) = conj(twq[m]) * mk<T>(Fm.re + Fr.im, Fm.im - Fr.re);
+      at(mr, t) = conj(twq[mr]) * mk<T>(Fr.re + Fm.im, Fr.im - Fm.re);
+    } else if (m == 0) {
+      at(0, t) = Fm;
+    } else {
+      at(m, t) = conj(twq[m]) * mk<T>(Fm.re + Fm.im, Fm.im - Fm.re);
+    }
+  };
+  if (!ROBIN) {
+    for (int e = threadIdx.x; e < (half + 1) * TL; e += blockDim.x) {
+      const int m = e >> ltl, t = e & (TL - 1);
+      const int l = min(l0 + t, lines - 1);
+      int ky, kx;
+      spec_mode(l, P, Ny, ky, kx);
+      // the eigenvalue factors in the storage type: lambda <= 0, alpha < 0 < c_psi, so neither
+      // factor cancels
+      const T lxy = (T)(lamx[kx] + lamy[ky]);
+      const int mr = (Nz - m) & (Nz - 1);  // partner N - m (0 and N/2 pair with themselves)
+      const cx<T> Vm = at(m, t), Vr = at(mr, t);
+      const T lm = lxy + (T)lamz[m];
+      const cx<T> Fm = (sc * recip((lm - cp) * (lm + al))) * dct_out(Vm, Vr, twq[m]);
+      cx<T> Fr = Fm;
+      if (mr != m) {
+        const T lr = lxy + (T)lamz[mr];
+        Fr = (sc * recip((lr - cp) * (lr + al))) * dct_out(Vr, Vm, twq[mr]);
+      }
+      inverse_in(m, mr, t, Fm, Fr);
+    }
+  } else {
+    // Relaxed walls (eq. NS34 with D_w > 0): the operator is (L - c_psi)(L + alpha) + L dW,
+    // d = dwall on the two wall-adjacent rows, a rank-two change of the Neumann product that
+    // the DCT diagonalises. With F0 = X / A (A = (lambda - c_psi)(lambda + alpha), X the DCT
+    // of the right-hand side, both scaled) the solution is F_m = F0_m - G_m s_m, G_m = d
+    // lambda_m c_m / (N A_m), c_m = cos(pi m / 2N) = (row 0 of the DCT basis), s_m the sum
+    // (m even) or difference (m odd) of the two wall values; since the inverse transform is
+    // x_k = sum_m W_m F_m cos(pi m (k + 1/2) / N), W = (1, 2, 2, ...), the sum and difference
+    // solve sigma = P_e / (1 + H_e), delta = P_o / (1 + H_o) with P = 2 sum W c F0 and
+    // H = 2 sum W c G over even or odd m. H >= 0 (d < 0, lambda <= 0, A > 0).
+    // after the twiddles, rounded up to 16 bytes: the wall sums [TL][2], the partials
+    // [NC][TL][6], then G [Nz][TL] in the storage type
+    const int NC = min((int)(blockDim.x >> ltl), 16);
+    const size_t so = ((size_t)(TL * F::LS + Nz) * sizeof(cx<T>) + 15) & ~(size_t)15;
+    cx<double>* sd = reinterpret_cast<cx<double>*>(smem + so);
+    double* part = reinterpret_cast<double*>(sd + 2 * TL);
+    T* sG = reinterpret_cast<T*>(part + 6 * NC * TL);
+    for (int e = threadIdx.x; e < (half + 1) * TL; e += blockDim.x) {
+      const int m = e >> ltl, t = e & (TL - 1);
+      const int l = min(l0 + t, lines - 1);
+      int ky, kx;
+      spec_mode(l, P, Ny, ky, kx);
+      const T lxy = (T)(lamx[kx] + lamy[ky]);
+      const int mr = (Nz - m) & (Nz - 1);
+      const cx<T> Vm = at(m, t), Vr = at(mr, t);
+      // 1/A once per entry: F0 = scale X / A and G = d lambda c / (N A)
+      const T lm = lxy + (T)lamz[m];
+      const T im = recip((lm - cp) * (lm + al));
+      at(m, t) = (sc * im) * dct_out(Vm, Vr, twq[m]);
+      sG[m * TL + t] = (T)dwall * lm * twq[m].re * im / (T)Nz;
+      if (mr != m) {
+        const T lr = lxy + (T)lamz[mr];
+        const T ir = recip((lr - cp) * (lr + al));
+        at(mr, t) = (sc * ir) * dct_out(Vr, Vm, twq[mr]);
+        sG[mr * TL + t] = (T)dwall * lr * twq[mr].re * ir / (T)Nz;
+      }
+    }
+    __syncthreads();
+    // partial sums over m = ch, ch + NC, ... per mode, then their totals
+    for (int e = threadIdx.x; e < NC * TL; e += blockDim.x) {
+      const int t = e & (TL - 1), ch = e >> ltl;
+      double acc[6] = {0, 0, 0, 0, 0, 0};  // P_e (re, im), P_o (re, im), H_e, H_o
+      for (int m = ch; m < Nz; m += NC) {
+        const double wc = (m == 0 ? 2.0 : 4.0) * (double)twq[m].re;
+        const cx<T> Fv = at(m, t);
+        const int o = (m & 1) * 2;
+        acc[o] += wc * (double)Fv.re;
+        acc[o + 1] += wc * (double)Fv.im;
+        acc[4 + (m & 1)] += wc * (double)sG[m * TL + t];
+      }
+#pragma unroll
+      for (int q = 0; q < 6; ++q) part[(ch * TL + t) * 6 + q] = acc[q];
+    }
+    __syncthreads();
+    // totals: one thread per (quantity, mode), into the first chunk's slots
+    for (int e = threadIdx.x; e < 6 * TL; e += blockDim.x) {
+      const int t = e % TL, q = e / TL;
+      double a = 0;
+      for (int ch = 0; ch < NC; ++ch) a += part[(ch * TL + t) * 6 + q];
+      part[t * 6 + q] = a;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < TL; t += blockDim.x) {
+      const double* a = part + t * 6;
+      sd[2 * t] = mk<double>(a[0] / (1.0 + a[4]), a[1] / (1.0 + a[4]));      // sigma
+      sd[2 * t + 1] = mk<double>(a[2] / (1.0 + a[5]), a[3] / (1.0 + a[5]));  // delta
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < (half + 1) * TL; e += blockDim.x) {
+      const int m = e >> ltl, t = e & (TL - 1);
+      const int mr = (Nz - m) & (Nz - 1);
+      auto corrected = [&](int mm) -> cx<T> {
+        const cx<T> Fv = at(mm, t);
+        const cx<double> s = sd[2 * t + (mm & 1)];
+        const double g = (double)sG[mm * TL + t];
+        return mk<T>((T)((double)Fv.re - g * s.re), (T)((double)Fv.im - g * s.im));
+      };
+      const cx<T> Fm = corrected(m);
+      const cx<T> Fr = mr != m ? corrected(mr) : Fm;
+      inverse_in(m, mr, t, Fm, Fr);
+    }
+  }
+  __syncthreads();
+  fft16<T, true, LOGNZ, fft_lp<T>()>(buf + fb * F::LS, fq, fb < TL, stw);
+  for (int e = threadIdx.x; e < Nz * TL; e += blockDim.x) {
+    const int row = e >> ltl, t = e & (TL - 1);
+    const int l = l0 + t;
+    const int pos = (row & 1) ? (Nz - 1 - (row >> 1)) : (row >> 1);
+    if (l < lines) S[row * stride + l] = at(pos, t);
+  }
+}
+
+// The same pass with the transform length at run time (lds_fft): the FP64 form.
 template <typename T, bool ROBIN>
 __global__ void __launch_bounds__(1024)
-    k_zpass_ch(cx<T>* __restrict__ S, int P, int Ny, int Nz, int logNz, int TL,
+    k_zpass_ch_rt(cx<T>* __restrict__ S, int P, int Ny, int Nz, int logNz, int TL,
                const double* __restrict__ lamx, const double* __restrict__ lamy,
                const double* __restrict__ lamz, const cx<T>* __restrict__ twz,
                const cx<T>* __restrict__ twq, double c_psi, double alpha, double scale, double dwall) {
@@ -653,32 +818,64 @@ hipError_t launch_top_layer(const Dims& d, const T* top, T* x, hipStream_t st) {
 template <typename T>
 hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, double c_psi,
                            double alpha, double scale, double dwall, hipStream_t st) {
-  // tiles of 128 bytes per row (16 complex FP32 or 8 complex FP64 modes): one cache line
-  int TL = (int)(128 / sizeof(cx<T>));
-  while (TL > 1 && TL * d.nz > 4096) TL >>= 1;
-  TL = spread_lines(TL, d.lines(), 2048);
-  int threads = TL * (d.nz >= 4 ? d.nz / 4 : 1);
-  threads = ((threads + 63) / 64) * 64;
-  if (threads > 1024) threads = 1024;
-  const int lines = d.lines();
-  int lognz = 0;
-  while ((1 << lognz) < d.nz) ++lognz;
-  size_t shm = (size_t)d.nz * (TL + 1) * sizeof(cx<T>);
-  // the inverse transforms are unnormalised: fold 1/nz into the spectral scale
-  if (dwall == 0.0) {
-    hipLaunchKernelGGL((k_zpass_ch<T, false>), dim3((lines + TL - 1) / TL), dim3(threads), shm, st, spec,
-                       d.pitch, d.ny, d.nz, lognz, TL, tb.lam_x, tb.lam_y, tb.lam_z, tb.tw_z, tb.tw_zq, c_psi,
-                       alpha, scale / d.nz, 0.0);
+  if constexpr (sizeof(T) == 8) {
+    // tiles of 128 bytes per row (8 complex FP64 modes): one cache line
+    int TL = (int)(128 / sizeof(cx<T>));
+    while (TL > 1 && TL * d.nz > 4096) TL >>= 1;
+    TL = spread_lines(TL, d.lines(), 2048);
+    int threads = TL * (d.nz >= 4 ? d.nz / 4 : 1);
+    threads = ((threads + 63) / 64) * 64;
+    if (threads > 1024) threads = 1024;
+    const int lines = d.lines();
+    int lognz = 0;
+    while ((1 << lognz) < d.nz) ++lognz;
+    size_t shm = (size_t)d.nz * (TL + 1) * sizeof(cx<T>);
+    // the inverse transforms are unnormalised: fold 1/nz into the spectral scale
+    if (dwall == 0.0) {
+      hipLaunchKernelGGL((k_zpass_ch_rt<T, false>), dim3((lines + TL - 1) / TL), dim3(threads), shm, st, spec,
+                         d.pitch, d.ny, d.nz, lognz, TL, tb.lam_x, tb.lam_y, tb.lam_z, tb.tw_z, tb.tw_zq, c_psi,
+                         alpha, scale / d.nz, 0.0);
+    } else {
+      // relaxed walls: partial sums (at most 16 per mode, 6 doubles each) and the wall sums
+      const int nc = (threads / TL) < 16 ? threads / TL : 16;
+      shm = ((shm + 15) & ~(size_t)15) + (size_t)2 * TL * sizeof(cx<double>) + (size_t)6 * nc * TL * sizeof(double) +
+            (size_t)d.nz * TL * sizeof(T);
+      hipLaunchKernelGGL((k_zpass_ch_rt<T, true>), dim3((lines + TL - 1) / TL), dim3(threads), shm, st, spec,
+                         d.pitch, d.ny, d.nz, lognz, TL, tb.lam_x, tb.lam_y, tb.lam_z, tb.tw_z, tb.tw_zq, c_psi,
+                         alpha, scale / d.nz, dwall);
+    }
+    return hipGetLastError();
   } else {
-    // relaxed walls: partial sums (at most 16 per mode, 6 doubles each) and the wall sums
-    const int nc = (threads / TL) < 16 ? threads / TL : 16;
-    shm = ((shm + 15) & ~(size_t)15) + (size_t)2 * TL * sizeof(cx<double>) + (size_t)6 * nc * TL * sizeof(double) +
-          (size_t)d.nz * TL * sizeof(T);
-    hipLaunchKernelGGL((k_zpass_ch<T, true>), dim3((lines + TL - 1) / TL), dim3(threads), shm, st, spec,
-                       d.pitch, d.ny, d.nz, lognz, TL, tb.lam_x, tb.lam_y, tb.lam_z, tb.tw_z, tb.tw_zq, c_psi,
-                       alpha, scale / d.nz, dwall);
+    int lognz = 0;
+    while ((1 << lognz) < d.nz) ++lognz;
+    // tiles of 128 bytes per row (16 complex FP32 modes): one cache line; at most 4096 points
+    // and kZBlock threads of P points per block
+    int TL = 16;
+    const int per_line = d.nz > (1 << fft_lp<T>()) ? d.nz >> fft_lp<T>() : 1;
+    while (TL > 1 && (TL * d.nz > 4096 || TL * per_line > kZBlock)) TL >>= 1;
+    TL = spread_lines(TL, d.lines(), 2048);
+    const int lines = d.lines();
+    const int threads = TL * per_line;
+    // the inverse transforms are unnormalised: fold 1/nz into the spectral scale
+    return with_logm(lognz, [&](auto L) {
+      constexpr int LOGNZ = decltype(L)::value;
+      using F = FftPlan<LOGNZ, fft_lp<T>()>;
+      size_t shm = ((size_t)TL * F::LS + F::M) * sizeof(cx<T>);
+      if (dwall == 0.0) {
+        hipLaunchKernelGGL((k_zpass_ch<T, false, LOGNZ>), dim3((lines + TL - 1) / TL), dim3(threads), shm, st,
+                           spec, d.pitch, d.ny, TL, tb.lam_x, tb.lam_y, tb.lam_z, tb.tw_z, tb.tw_zq, c_psi, alpha,
+                           scale / d.nz, 0.0);
+      } else {
+        // relaxed walls: partial sums (at most 16 per mode, 6 doubles each) and the wall sums
+        const int nc = (threads / TL) < 16 ? threads / TL : 16;
+        shm = ((shm + 15) & ~(size_t)15) + (size_t)2 * TL * sizeof(cx<double>) + (size_t)6 * nc * TL * sizeof(double) +
+              (size_t)d.nz * TL * sizeof(T);
+        hipLaunchKernelGGL((k_zpass_ch<T, true, LOGNZ>), dim3((lines + TL - 1) / TL), dim3(threads), shm, st,
+                           spec, d.pitch, d.ny, TL, tb.lam_x, tb.lam_y, tb.lam_z, tb.tw_z, tb.tw_zq, c_psi, alpha,
+                           scale / d.nz, dwall);
+      }
+    });
   }
-  return hipGetLastError();
 }
 
 template <typename T>
