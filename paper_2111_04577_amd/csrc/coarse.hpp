@@ -124,15 +124,19 @@ struct PolPre {
 // Inputs of the momentum right-hand side. VA reads the extrapolated velocities (methods s, sd,
 // sw as in Field), GA the restricted chemical potential at centres (at, atn as in Coarse) and
 // TA the weighted polymer stress (at as in TauW, from global memory or LDS rings; or PolPre,
-// whose pre flag says that the face divergences are given).
-template <typename T, typename VA, typename GA, typename TA = TauW<T>>
+// whose pre flag says that the face divergences are given); PA the pressure (s, n as in
+// Field), CA phi_c and mu_c (at as in Coarse), EA the z-edge viscosities (at as in ZEdge),
+// from memory or through a register cache of the caller's own column.
+template <typename T, typename VA, typename GA, typename TA = TauW<T>, typename PA = Field<T>,
+          typename CA = Coarse<T>, typename EA = ZEdge<T>>
 struct MomCtxG {
   using value_type = T;
   VA U, V, W;
-  Field<T> P, Pn;
+  PA P, Pn;  // P: s (extrapolated pressure), Pn: n (pressure at level n)
   GA Gc;
-  Coarse<T> phic, muc, muxy;
-  ZEdge<T> muxz, muyz;
+  CA phic, muc;
+  Coarse<T> muxy;
+  EA muxz, muyz;
   TA Tw;
   Restricted<T> R;
   const T *un, *unm1, *vn, *vnm1, *wn, *wnm1;  // levels n, n-1 (for the hat of eq. NS31)

@@ -117,6 +117,44 @@ struct RingG {
   __device__ __forceinline__ T atn(int kk, int jj, int ii) const { return at(kk, jj, ii); }
 };
 
+// Register cache of a z-marching thread's own column (j0, i0): the values on layers k0 and
+// k0 + 1 (the latter loaded one step ahead and carried to the next layer as its k0 value);
+// every other point is read from memory. The comparisons fold away once inlined, since the
+// caller passes its own indices.
+template <typename T>
+struct PCol {  // pressure: extrapolated (s) and level-n (n) values
+  Field<T> g;
+  int k0, j0, i0;
+  T s0, s1, n0, n1;
+  __device__ __forceinline__ T s(int k, int j, int i) const {
+    if (j == j0 && i == i0) {
+      if (k == k0) return s0;
+      if (k == k0 + 1) return s1;
+    }
+    return g.s(k, j, i);
+  }
+  __device__ __forceinline__ T n(int k, int j, int i) const {
+    if (j == j0 && i == i0) {
+      if (k == k0) return n0;
+      if (k == k0 + 1) return n1;
+    }
+    return g.n(k, j, i);
+  }
+};
+template <typename T, typename A>
+struct ACol {  // a Coarse or ZEdge array
+  A g;
+  int k0, j0, i0;
+  T c0, c1;
+  __device__ __forceinline__ T at(int k, int j, int i) const {
+    if (j == j0 && i == i0) {
+      if (k == k0) return c0;
+      if (k == k0 + 1) return c1;
+    }
+    return g.at(k, j, i);
+  }
+};
+
 // Halo tile of a z-marching block: TX x TY coarse columns with one point of halo below and two
 // above in x and y. Each thread owns at most RP tile points; their in-layer byte offsets (a
 // uniform layer base plus a 32-bit lane offset) are computed once.
@@ -267,9 +305,20 @@ __global__ void __launch_bounds__(kBlock)
   load_g(K0);
   load_g(K0 + 1);
   const int K1 = min(K0 + KB, nz);  // the last block of a column may march fewer layers
+  // the own column's pressure, phi_c, mu_c and z-edge viscosities on layers k and k + 1 stay
+  // in registers: each is read from memory once per layer
+  const Field<T> Pg{in.pn, in.pnm1, nx, ny, nz, f};
+  const Coarse<T> Phg{R.phi_c, nx, ny, nz}, Mug{R.mu_c, nx, ny, nz};
+  const ZEdge<T> Exg{R.mu_xz, nx, ny}, Eyg{R.mu_yz, nx, ny};
+  T ps0 = Pg.s(K0, j, i), pn0 = Pg.n(K0, j, i), ph0 = Phg.at(K0, j, i), mu0 = Mug.at(K0, j, i);
+  T ex0 = Exg.at(K0, j, i), ey0 = Eyg.at(K0, j, i);
   for (int k = K0; k < K1; ++k) {
     load_vel(k + 1);
     load_g(k + 2);
+    // layer k + 1 (clamped on the top layer, where no term reads it); the edges have nz + 1
+    const int ku = min(k + 1, nz - 1);
+    const T ps1 = Pg.s(ku, j, i), pn1 = Pg.n(ku, j, i), ph1 = Phg.at(ku, j, i), mu1 = Mug.at(ku, j, i);
+    const T ex1 = Exg.at(k + 1, j, i), ey1 = Eyg.at(k + 1, j, i);
     __syncthreads();
     const int v0 = (k - K0) % 3, v1 = (k - K0 + 1) % 3, v2 = (k - K0 + 2) % 3;
     const RingV<T> Ur{{sU + v0 * HP, sU + v1 * HP, sU + v2 * HP}, k, X0, Y0, ys};
@@ -279,16 +328,18 @@ __global__ void __launch_bounds__(kBlock)
                        sG + ((k - K0 + 3) & 3) * HP},
                       k, X0, Y0, ys};
     const PolPre<T> Pp{{in.pol[0], in.pol[1], in.pol[2]}};
-    MomCtxG<T, RingV<T>, RingG<T>, PolPre<T>> m{Ur, Vr, Wr,
-                                     {in.pn, in.pnm1, nx, ny, nz, f},
-                                     {in.pn, nullptr, nx, ny, nz, 1},
-                                     Gr,
-                                     {R.phi_c, nx, ny, nz},
-                                     {R.mu_c, nx, ny, nz},
-                                     {R.mu_xy, nx, ny, nz},
-                                     {R.mu_xz, nx, ny},
-                                     {R.mu_yz, nx, ny},
-                                     Pp,
+    const PCol<T> Pc{Pg, k, j, i, ps0, ps1, pn0, pn1};
+    MomCtxG<T, RingV<T>, RingG<T>, PolPre<T>, PCol<T>, ACol<T, Coarse<T>>, ACol<T, ZEdge<T>>> m{
+        Ur, Vr, Wr,
+        Pc,
+        Pc,
+        Gr,
+        {Phg, k, j, i, ph0, ph1},
+        {Mug, k, j, i, mu0, mu1},
+        {R.mu_xy, nx, ny, nz},
+        {Exg, k, j, i, ex0, ex1},
+        {Eyg, k, j, i, ey0, ey1},
+        Pp,
                                      R,
                                      in.un, in.unm1, in.vn, in.vnm1, in.wn, in.wnm1,
                                      nx, ny, nz, f, VE ? 1 : 0,
@@ -302,6 +353,12 @@ __global__ void __launch_bounds__(kBlock)
     ru[id] = rhs(mom_u(m, k, j, i, id), (T)c.ax);
     rv[id] = rhs(mom_v(m, k, j, i, id), (T)c.ay);
     rw[id] = k == nz - 1 ? (T)0 : rhs(mom_w(m, k, j, i, id), (T)c.az);
+    ps0 = ps1;
+    pn0 = pn1;
+    ph0 = ph1;
+    mu0 = mu1;
+    ex0 = ex1;
+    ey0 = ey1;
     __syncthreads();
   }
 }
