@@ -432,8 +432,11 @@ def ingest_pmc(fetch_csv, write_csv, out_json, workload):
                 m = re.search(r"(k_\w+)<(float|double)((?:, \w+)*)>", name)
                 if not m:
                     continue
-                flag = re.search(r"\b(true|false)\b", m.group(3)) if m.group(1) == "k_fft_y" else None
-                per[(m.group(1), m.group(2), flag.group(1) if flag else None,
+                # the run-time length forms of the transform passes (suffix _rt) are the same
+                # operations
+                kname = m.group(1)[:-3] if m.group(1).endswith("_rt") else m.group(1)
+                flag = re.search(r"\b(true|false)\b", m.group(3)) if kname == "k_fft_y" else None
+                per[(kname, m.group(2), flag.group(1) if flag else None,
                      int(row["Grid_Size"]))].append(val)
         scale = copy_bytes / (max(copies) * 1024) if copies else None
         return per, scale

@@ -139,13 +139,14 @@ struct MomCtxG {
   EA muxz, muyz;
   TA Tw;
   Restricted<T> R;
-  const T *un, *unm1, *vn, *vnm1, *wn, *wnm1;  // levels n, n-1 (for the hat of eq. NS31)
+  const T *un, *unm1, *vn, *vnm1, *wn, *wnm1;  // levels n, n-1 (n-1 for the hat of eq. NS31)
   int nx, ny, nz, first, ve;
   T ihx, ihy, ihz;
   T inv_dt, inv_re, ir0, nu_m, k_sigma, c_j;
-  // hat of eq. NS31 at an in-range index
-  __device__ __forceinline__ T hat(const T* a, const T* b, int id) const {
-    return first ? a[id] : (T)2 * a[id] - (T)0.5 * b[id];
+  // hat of eq. NS31 at an in-range face from the extrapolated value there: 2 u^n - u^{n-1}/2 =
+  // u* + u^{n-1}/2 with u* = 2 u^n - u^{n-1}; u^n (= u*) on the first step
+  __device__ __forceinline__ T hat(T star, const T* b, int id) const {
+    return first ? star : star + (T)0.5 * b[id];
   }
   // J = -c_j grad G at a centre: 2h central differences, Neumann in z
   __device__ __forceinline__ void Jc(int k, int j, int i, T* J) const {
@@ -206,7 +207,7 @@ __device__ __forceinline__ MomTerms<typename C::value_type> mom_u(const C& m, in
   const T gps = (m.P.s(k, j, i + 1) - m.P.s(k, j, i)) * ihx;
   const T cap = m.R.G_x[id] * (m.phic.at(k, j, i + 1) - m.phic.at(k, j, i)) * ihx;
   const T lap = (uxp - 2 * u0 + uxm) * ihx * ihx + (uyp - 2 * u0 + uym) * ihy * ihy + (uzp - 2 * u0 + uzm) * ihz * ihz;
-  return MomTerms<T>{m.hat(m.un, m.unm1, id), adv, jgu, gpn, gps, lap, pol, vis, cap, ri};
+  return MomTerms<T>{m.hat(u0, m.unm1, id), adv, jgu, gpn, gps, lap, pol, vis, cap, ri};
 }
 
 template <typename C>
@@ -250,7 +251,7 @@ __device__ __forceinline__ MomTerms<typename C::value_type> mom_v(const C& m, in
   const T gps = (m.P.s(k, j + 1, i) - m.P.s(k, j, i)) * ihy;
   const T cap = m.R.G_y[id] * (m.phic.at(k, j + 1, i) - m.phic.at(k, j, i)) * ihy;
   const T lap = (vxp - 2 * v0 + vxm) * ihx * ihx + (vyp - 2 * v0 + vym) * ihy * ihy + (vzp - 2 * v0 + vzm) * ihz * ihz;
-  return MomTerms<T>{m.hat(m.vn, m.vnm1, id), adv, jgv, gpn, gps, lap, pol, vis, cap, ri};
+  return MomTerms<T>{m.hat(v0, m.vnm1, id), adv, jgv, gpn, gps, lap, pol, vis, cap, ri};
 }
 
 template <typename C>
@@ -294,7 +295,7 @@ __device__ __forceinline__ MomTerms<typename C::value_type> mom_w(const C& m, in
   const T gps = (m.P.s(k + 1, j, i) - m.P.s(k, j, i)) * ihz;
   const T cap = m.R.G_z[id] * (m.phic.at(k + 1, j, i) - m.phic.at(k, j, i)) * ihz;
   const T lap = (wxp - 2 * w0 + wxm) * ihx * ihx + (wyp - 2 * w0 + wym) * ihy * ihy + (wzp - 2 * w0 + wzm) * ihz * ihz;
-  return MomTerms<T>{m.hat(m.wn, m.wnm1, id), adv, jgw, gpn, gps, lap, pol, vis, cap, ri};
+  return MomTerms<T>{m.hat(w0, m.wnm1, id), adv, jgw, gpn, gps, lap, pol, vis, cap, ri};
 }
 
 

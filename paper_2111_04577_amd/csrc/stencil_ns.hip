@@ -251,11 +251,10 @@ __global__ void __launch_bounds__(kBlock)
 // live in LDS, every thread forms all three components of its cell from them. The other
 // inputs are read once or twice per cell from global memory; VE (Oldroyd-B) adds the face
 // divergences of the weighted polymer stress, given by k_polymer_div_zm. Each thread loads at
-// most RP points of a halo tile. The FP32 form with two points per thread is held to five
-// wavefronts per SIMD (96 registers, a few spilled; measured 2% faster than four).
+// most RP points of a halo tile. (Five wavefronts per SIMD instead of four spill eight FP32
+// registers: no faster, and the reloads add 0.3 GB of HBM reads per launch at 256 x 256 x 128.)
 template <typename T, bool VE, int RP>
 __global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && RP == 2 ? 5 : 1)))
     k_momentum_rhs_zm(NsIn<T> in, Restricted<T> R, T* __restrict__ ru, T* __restrict__ rv,
                       T* __restrict__ rw, StepConsts c, int nx, int ny, int nz, int KB, T ihx, T ihy,
                       T ihz) {
