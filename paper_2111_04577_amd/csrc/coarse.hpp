@@ -126,9 +126,19 @@ struct PolPre {
 // TA the weighted polymer stress (at as in TauW, from global memory or LDS rings; or PolPre,
 // whose pre flag says that the face divergences are given); PA the pressure (s, n as in
 // Field), CA phi_c and mu_c (at as in Coarse), EA the z-edge viscosities (at as in ZEdge),
-// from memory or through a register cache of the caller's own column.
+// from memory or through a register cache of the caller's own column; HA the level n-1
+// velocities at the face (PrevMem, or values the caller holds).
+// The level n-1 velocities at the face being formed (the hat of eq. NS31), read from memory
+template <typename T>
+struct PrevMem {
+  template <typename C>
+  __device__ __forceinline__ T at(const C& m, int comp, int id) const {
+    return (comp == 0 ? m.unm1 : comp == 1 ? m.vnm1 : m.wnm1)[id];
+  }
+};
+
 template <typename T, typename VA, typename GA, typename TA = TauW<T>, typename PA = Field<T>,
-          typename CA = Coarse<T>, typename EA = ZEdge<T>>
+          typename CA = Coarse<T>, typename EA = ZEdge<T>, typename HA = PrevMem<T>>
 struct MomCtxG {
   using value_type = T;
   VA U, V, W;
@@ -143,10 +153,11 @@ struct MomCtxG {
   int nx, ny, nz, first, ve;
   T ihx, ihy, ihz;
   T inv_dt, inv_re, ir0, nu_m, k_sigma, c_j;
+  HA prev = {};  // level n-1 velocity at the face (memory, or the caller's registers)
   // hat of eq. NS31 at an in-range face from the extrapolated value there: 2 u^n - u^{n-1}/2 =
   // u* + u^{n-1}/2 with u* = 2 u^n - u^{n-1}; u^n (= u*) on the first step
-  __device__ __forceinline__ T hat(T star, const T* b, int id) const {
-    return first ? star : star + (T)0.5 * b[id];
+  __device__ __forceinline__ T hat(T star, int comp, int id) const {
+    return first ? star : star + (T)0.5 * prev.at(*this, comp, id);
   }
   // J = -c_j grad G at a centre: 2h central differences, Neumann in z
   __device__ __forceinline__ void Jc(int k, int j, int i, T* J) const {
@@ -207,7 +218,7 @@ __device__ __forceinline__ MomTerms<typename C::value_type> mom_u(const C& m, in
   const T gps = (m.P.s(k, j, i + 1) - m.P.s(k, j, i)) * ihx;
   const T cap = m.R.G_x[id] * (m.phic.at(k, j, i + 1) - m.phic.at(k, j, i)) * ihx;
   const T lap = (uxp - 2 * u0 + uxm) * ihx * ihx + (uyp - 2 * u0 + uym) * ihy * ihy + (uzp - 2 * u0 + uzm) * ihz * ihz;
-  return MomTerms<T>{m.hat(u0, m.unm1, id), adv, jgu, gpn, gps, lap, pol, vis, cap, ri};
+  return MomTerms<T>{m.hat(u0, 0, id), adv, jgu, gpn, gps, lap, pol, vis, cap, ri};
 }
 
 template <typename C>
@@ -251,7 +262,7 @@ __device__ __forceinline__ MomTerms<typename C::value_type> mom_v(const C& m, in
   const T gps = (m.P.s(k, j + 1, i) - m.P.s(k, j, i)) * ihy;
   const T cap = m.R.G_y[id] * (m.phic.at(k, j + 1, i) - m.phic.at(k, j, i)) * ihy;
   const T lap = (vxp - 2 * v0 + vxm) * ihx * ihx + (vyp - 2 * v0 + vym) * ihy * ihy + (vzp - 2 * v0 + vzm) * ihz * ihz;
-  return MomTerms<T>{m.hat(v0, m.vnm1, id), adv, jgv, gpn, gps, lap, pol, vis, cap, ri};
+  return MomTerms<T>{m.hat(v0, 1, id), adv, jgv, gpn, gps, lap, pol, vis, cap, ri};
 }
 
 template <typename C>
@@ -295,7 +306,7 @@ __device__ __forceinline__ MomTerms<typename C::value_type> mom_w(const C& m, in
   const T gps = (m.P.s(k + 1, j, i) - m.P.s(k, j, i)) * ihz;
   const T cap = m.R.G_z[id] * (m.phic.at(k + 1, j, i) - m.phic.at(k, j, i)) * ihz;
   const T lap = (wxp - 2 * w0 + wxm) * ihx * ihx + (wyp - 2 * w0 + wym) * ihy * ihy + (wzp - 2 * w0 + wzm) * ihz * ihz;
-  return MomTerms<T>{m.hat(w0, m.wnm1, id), adv, jgw, gpn, gps, lap, pol, vis, cap, ri};
+  return MomTerms<T>{m.hat(w0, 2, id), adv, jgw, gpn, gps, lap, pol, vis, cap, ri};
 }
 
 

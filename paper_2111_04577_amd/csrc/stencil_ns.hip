@@ -157,10 +157,14 @@ struct ACol {  // a Coarse or ZEdge array
 
 // Halo tile of a z-marching block: TX x TY coarse columns with one point of halo below and two
 // above in x and y. Each thread owns at most RP tile points; their in-layer byte offsets (a
-// uniform layer base plus a 32-bit lane offset) are computed once.
-template <typename T, int RP>
+// uniform layer base plus a 32-bit lane offset) are computed once. OWN: a thread's first point
+// is its own column (so that it holds its own cell's loaded values), the ring of halo points
+// is spread over the threads' later points; otherwise point q of thread t is tile index
+// t + q TX TY.
+template <typename T, int RP, bool OWN = false>
 struct HaloTile {
   int HX, HP, tid, nth;
+  int e[RP];
   unsigned off[RP];
   __device__ __forceinline__ HaloTile(int TX, int TY, int X0, int Y0, int nx, int ny) {
     HX = TX + 3;
@@ -169,17 +173,57 @@ struct HaloTile {
     nth = TX * TY;
 #pragma unroll
     for (int q = 0; q < RP; ++q) {
-      const int e = tid + q * nth;
-      const int hy = e / HX, hx = e - hy * HX;
-      off[q] = e < HP ? (unsigned)(wrap(Y0 - 1 + hy, ny) * nx + wrap(X0 - 1 + hx, nx)) * (unsigned)sizeof(T) : 0u;
+      int hy, hx;
+      if (!OWN) {
+        const int eq = tid + q * nth;
+        hy = eq / HX;
+        hx = eq - hy * HX;
+      } else if (q == 0) {
+        hy = (int)threadIdx.y + 1;
+        hx = (int)threadIdx.x + 1;
+      } else {
+        // ring: the row below and the two rows above (full width), then the column before
+        // and the two after on the TY inner rows
+        const int r = tid + (q - 1) * nth;
+        if (r < 3 * HX) {
+          hy = r < HX ? 0 : (r < 2 * HX ? TY + 1 : TY + 2);
+          hx = r - (r < HX ? 0 : (r < 2 * HX ? HX : 2 * HX));
+        } else {
+          const int s = r - 3 * HX, c = s % 3;
+          hy = 1 + s / 3;
+          hx = c == 0 ? 0 : TX + c;
+        }
+        e[q] = r < HP - nth ? hy * HX + hx : HP;  // HP: no point
+      }
+      if (OWN && q == 0) e[q] = hy * HX + hx;
+      off[q] = pt(q) < HP ? (unsigned)(wrap(Y0 - 1 + hy, ny) * nx + wrap(X0 - 1 + hx, nx)) * (unsigned)sizeof(T) : 0u;
     }
   }
+  // tile index of point q (HP or more: no point)
+  __device__ __forceinline__ int pt(int q) const { return OWN ? e[q] : tid + q * nth; }
   // fn(tile index, byte offset) for every point of this thread
   template <typename F>
   __device__ __forceinline__ void each(F&& fn) const {
 #pragma unroll
     for (int q = 0; q < RP; ++q)
-      if (tid + q * nth < HP) fn(tid + q * nth, off[q]);
+      if (pt(q) < HP) fn(pt(q), off[q]);
+  }
+  // fn(q, tile index, byte offset): point q = 0 is the thread's own column when OWN
+  template <typename F>
+  __device__ __forceinline__ void each_q(F&& fn) const {
+#pragma unroll
+    for (int q = 0; q < RP; ++q)
+      if (pt(q) < HP) fn(q, pt(q), off[q]);
+  }
+};
+
+// Level n-1 velocities of the caller's own face, held in registers
+template <typename T>
+struct PrevOwn {
+  T v[3];
+  template <typename C>
+  __device__ __forceinline__ T at(const C&, int comp, int) const {
+    return v[comp];
   }
 };
 
@@ -263,7 +307,7 @@ __global__ void __launch_bounds__(kBlock)
   int bx, by, bz;
   xcd_tile(bx, by, bz);
   const int X0 = bx * TX, Y0 = by * TY, K0 = bz * KB;
-  const HaloTile<T, RP> H(TX, TY, X0, Y0, nx, ny);
+  const HaloTile<T, RP, true> H(TX, TY, X0, Y0, nx, ny);
   const int HP = H.HP, ys = H.HX;
   T* sU = reinterpret_cast<T*>(smem);
   T* sV = sU + 3 * HP;
@@ -272,11 +316,11 @@ __global__ void __launch_bounds__(kBlock)
   const int i = X0 + threadIdx.x, j = Y0 + threadIdx.y;
   const int f = c.first;
   const size_t layer = (size_t)ny * nx;
-  auto star_at = [&](const T* a, const T* b, unsigned o) {
-    return f ? ld_at(a, o) : (T)2 * ld_at(a, o) - ld_at(b, o);
-  };
   // extrapolated velocities on layer kk: no-slip ghosts (twice the wall velocity minus the
-  // adjacent layer) for u, v beyond the walls; w is zero on and beyond the walls
+  // adjacent layer) for u, v beyond the walls; w is zero on and beyond the walls. The thread's
+  // own point (the tile's first) also leaves its level n-1 values in prev_next, for the hat of
+  // that layer.
+  T prev_next[3] = {(T)0, (T)0, (T)0};
   auto load_vel = [&](int kk) {
     const int sl = (kk - K0 + 1) % 3;
     const int kc = min(max(kk, 0), nz - 1);
@@ -287,10 +331,19 @@ __global__ void __launch_bounds__(kBlock)
     const size_t o = kc * layer;
     const T *ua = in.un + o, *ub = in.unm1 + o, *va = in.vn + o, *vb = in.vnm1 + o;
     const T *wa = in.wn + o, *wb = in.wnm1 + o;
-    H.each([&](int e, unsigned off) {
-      sU[sl * HP + e] = bu + sg * star_at(ua, ub, off);
-      sV[sl * HP + e] = bv + sg * star_at(va, vb, off);
-      sW[sl * HP + e] = wz ? (T)0 : star_at(wa, wb, off);
+    H.each_q([&](int q, int e, unsigned off) {
+      // each value read once: u* = 2 u^n - u^{n-1} (u^n on the first step)
+      const T un = ld_at(ua, off), vn = ld_at(va, off), wn = wz ? (T)0 : ld_at(wa, off);
+      const T um = f ? (T)0 : ld_at(ub, off), vm = f ? (T)0 : ld_at(vb, off);
+      const T wm = (f || wz) ? (T)0 : ld_at(wb, off);
+      sU[sl * HP + e] = bu + sg * (f ? un : (T)2 * un - um);
+      sV[sl * HP + e] = bv + sg * (f ? vn : (T)2 * vn - vm);
+      sW[sl * HP + e] = wz ? (T)0 : (f ? wn : (T)2 * wn - wm);
+      if (q == 0) {
+        prev_next[0] = um;
+        prev_next[1] = vm;
+        prev_next[2] = wm;
+      }
     });
   };
   auto load_g = [&](int kk) {
@@ -300,6 +353,7 @@ __global__ void __launch_bounds__(kBlock)
   };
   load_vel(K0 - 1);
   load_vel(K0);
+  T prev[3] = {prev_next[0], prev_next[1], prev_next[2]};  // own level n-1 u, v, w on layer k
   load_g(K0 - 1);
   load_g(K0);
   load_g(K0 + 1);
@@ -328,7 +382,7 @@ __global__ void __launch_bounds__(kBlock)
                       k, X0, Y0, ys};
     const PolPre<T> Pp{{in.pol[0], in.pol[1], in.pol[2]}};
     const PCol<T> Pc{Pg, k, j, i, ps0, ps1, pn0, pn1};
-    MomCtxG<T, RingV<T>, RingG<T>, PolPre<T>, PCol<T>, ACol<T, Coarse<T>>, ACol<T, ZEdge<T>>> m{
+    MomCtxG<T, RingV<T>, RingG<T>, PolPre<T>, PCol<T>, ACol<T, Coarse<T>>, ACol<T, ZEdge<T>>, PrevOwn<T>> m{
         Ur, Vr, Wr,
         Pc,
         Pc,
@@ -343,7 +397,8 @@ __global__ void __launch_bounds__(kBlock)
                                      in.un, in.unm1, in.vn, in.vnm1, in.wn, in.wnm1,
                                      nx, ny, nz, f, VE ? 1 : 0,
                                      ihx, ihy, ihz,
-                                     (T)c.inv_dt, (T)c.inv_re, (T)c.inv_rho0, (T)c.nu_m, (T)c.k_sigma, (T)c.c_j};
+                                     (T)c.inv_dt, (T)c.inv_re, (T)c.inv_rho0, (T)c.nu_m, (T)c.k_sigma, (T)c.c_j,
+                                     PrevOwn<T>{{prev[0], prev[1], prev[2]}}};
     auto rhs = [&](const MomTerms<T>& t, T a) -> T {
       return -t.hat * m.inv_dt + t.adv + t.ri * t.jg + t.gpn * m.ir0 + (t.ri - m.ir0) * t.gps + m.nu_m * t.lap -
              m.inv_re * t.ri * t.pol - m.inv_re * t.ri * t.vis - m.k_sigma * t.ri * t.cap - a;
@@ -352,6 +407,7 @@ __global__ void __launch_bounds__(kBlock)
     ru[id] = rhs(mom_u(m, k, j, i, id), (T)c.ax);
     rv[id] = rhs(mom_v(m, k, j, i, id), (T)c.ay);
     rw[id] = k == nz - 1 ? (T)0 : rhs(mom_w(m, k, j, i, id), (T)c.az);
+    for (int a = 0; a < 3; ++a) prev[a] = prev_next[a];
     ps0 = ps1;
     pn0 = pn1;
     ph0 = ph1;
