@@ -158,6 +158,36 @@ inline int march_layers(K kernel, int threads, size_t shm, int cols, int nz) {
   return (nz + zb - 1) / zb;
 }
 
+// Point q of thread tid in a halo tile of TX x TY interior columns (tid = ty TX + tx) with LO
+// halo points before and HI after in x and y, HX = TX + LO + HI wide: point 0 is the thread's
+// own interior point, so that a wavefront's first loads cover whole interior rows; points
+// 1, 2, ... spread the ring of halo points over the threads (the LO rows below and the HI rows
+// above at full width, then the LO columns before and the HI after on each interior row).
+// Returns false where the thread has no point q.
+template <int LO, int HI>
+__device__ __forceinline__ bool own_first_point(int TX, int TY, int tid, int q, int& hy, int& hx) {
+  const int HX = TX + LO + HI;
+  if (q == 0) {
+    hy = tid / TX + LO;
+    hx = tid - (hy - LO) * TX + LO;
+    return true;
+  }
+  const int r = tid + (q - 1) * TX * TY;
+  const int nrow = (LO + HI) * HX;
+  if (r < nrow) {
+    const int row = r / HX;
+    hx = r - row * HX;
+    hy = row < LO ? row : TY + row;
+    return true;
+  }
+  const int s = r - nrow;
+  if (s >= (LO + HI) * TY) return false;
+  const int c = s % (LO + HI);
+  hy = LO + s / (LO + HI);
+  hx = c < LO ? c : TX + c;
+  return true;
+}
+
 // One-dimensional form of xcd_tile: the logical block index, so that consecutive logical
 // blocks (which share cache lines) run on the same XCD.
 __device__ __forceinline__ int xcd_block() {

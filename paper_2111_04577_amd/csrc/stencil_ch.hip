@@ -57,15 +57,17 @@ __global__ void __launch_bounds__(kBlock)
   const bool first = c.first != 0;
   const T icn2 = (T)c.inv_cn2, sc = (T)c.s_cn2;
   const size_t layer = (size_t)ny * nx;
-  // in-layer byte offsets: the loads take a uniform layer base plus a 32-bit lane offset
+  // tile points of this thread (own_first_point: point 0 is the thread's own column) and
+  // their in-layer byte offsets: the loads take a uniform layer base plus a 32-bit lane offset
   unsigned hOff[R];
+  int hE[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const int e = tid + q * nth;
-    const int hy = e / HX, hx = e - hy * HX;
-    hOff[q] = e < HP ? (unsigned)(wrap(Y0 - 1 + hy, ny) * nx + wrap(X0 - 1 + hx, nx)) * sizeof(T) : 0u;
+    int hy = 0, hx = 0;
+    hE[q] = own_first_point<1, 1>(TX, TY, tid, q, hy, hx) ? hy * HX + hx : HP;
+    hOff[q] = hE[q] < HP ? (unsigned)(wrap(Y0 - 1 + hy, ny) * nx + wrap(X0 - 1 + hx, nx)) * sizeof(T) : 0u;
   }
-  auto has = [&](int q) { return tid + q * nth < HP; };
+  auto has = [&](int q) { return hE[q] < HP; };
   // beyond a wall the zero-flux ghost is the adjacent layer
   auto kcl = [&](int Kl) { return min(max(Kl, 0), nz - 1); };
   auto load_tile = [&](int Kl, T* a, T* b) {
@@ -84,17 +86,14 @@ __global__ void __launch_bounds__(kBlock)
     for (int q = 0; q < R; ++q) {
       if (has(q)) {
         const T p = first ? a[q] : (T)2 * a[q] - b[q];
-        sP[slot * HP + tid + q * nth] = p;
-        sW[slot * HP + tid + q * nth] = (p * p * p - p) * icn2 - sc * p;
+        sP[slot * HP + hE[q]] = p;
+        sW[slot * HP + hE[q]] = (p * p * p - p) * icn2 - sc * p;
       }
     }
   };
   const unsigned cid = (J * nx + I) * sizeof(T);
-  auto load_centre = [&](int Kl) -> T {
-    const T* pa = phin + Kl * layer;
-    const T* pb = phinm1 + Kl * layer;
-    return first ? ld_at(pa, cid) : (T)2 * ld_at(pa, cid) - (T)0.5 * ld_at(pb, cid);
-  };
+  // phi_hat of the layer whose tile a, b hold (point 0: the thread's own column)
+  auto own_hat = [&](const T* a, const T* b) -> T { return first ? a[0] : (T)2 * a[0] - (T)0.5 * b[0]; };
   // coarse column of this fine column (eq. dual1); with a single resolution the column itself
   const int ry = pv.ry;
   constexpr bool sr = MODE == 1;   // single resolution (pv.single)
@@ -138,8 +137,8 @@ __global__ void __launch_bounds__(kBlock)
   store_tile(sm, ta, tb);
   load_tile(K0, ta, tb);
   store_tile(s0, ta, tb);
+  T phat_next = own_hat(ta, tb);
   load_tile(K0 + 1, ta, tb);
-  T phat_next = load_centre(K0);
   T ufp = 0, ufm = 0, vfp = 0, vfm = 0, wk = 0, wkm = 0;
   int kcur = -1;
   for (int K = K0; K < K0 + KB; ++K) {
@@ -175,8 +174,8 @@ __global__ void __launch_bounds__(kBlock)
     // layer K + 1 enters the ring; the layer after it and the next centre values go out
     store_tile(sp, ta, tb);
     if (K + 1 < K0 + KB) {
+      phat_next = own_hat(ta, tb);
       load_tile(K + 2, ta, tb);
-      phat_next = load_centre(K + 1);
     }
     // fine z faces K (above) and K-1 (below); the walls carry zero flux
     const T wfp = K == nz - 1 ? (T)0 : (sr || (K & 1) ? wk : h * (wkm + wk));

@@ -157,10 +157,9 @@ struct ACol {  // a Coarse or ZEdge array
 
 // Halo tile of a z-marching block: TX x TY coarse columns with one point of halo below and two
 // above in x and y. Each thread owns at most RP tile points; their in-layer byte offsets (a
-// uniform layer base plus a 32-bit lane offset) are computed once. OWN: a thread's first point
-// is its own column (so that it holds its own cell's loaded values), the ring of halo points
-// is spread over the threads' later points; otherwise point q of thread t is tile index
-// t + q TX TY.
+// uniform layer base plus a 32-bit lane offset) are computed once. OWN: the points of
+// own_first_point (a thread's first point is its own column, so that it also holds its own
+// cell's loaded values); otherwise point q of thread t is tile index t + q TX TY.
 template <typename T, int RP, bool OWN = false>
 struct HaloTile {
   int HX, HP, tid, nth;
@@ -173,29 +172,14 @@ struct HaloTile {
     nth = TX * TY;
 #pragma unroll
     for (int q = 0; q < RP; ++q) {
-      int hy, hx;
+      int hy = 0, hx = 0;
       if (!OWN) {
         const int eq = tid + q * nth;
         hy = eq / HX;
         hx = eq - hy * HX;
-      } else if (q == 0) {
-        hy = (int)threadIdx.y + 1;
-        hx = (int)threadIdx.x + 1;
       } else {
-        // ring: the row below and the two rows above (full width), then the column before
-        // and the two after on the TY inner rows
-        const int r = tid + (q - 1) * nth;
-        if (r < 3 * HX) {
-          hy = r < HX ? 0 : (r < 2 * HX ? TY + 1 : TY + 2);
-          hx = r - (r < HX ? 0 : (r < 2 * HX ? HX : 2 * HX));
-        } else {
-          const int s = r - 3 * HX, c = s % 3;
-          hy = 1 + s / 3;
-          hx = c == 0 ? 0 : TX + c;
-        }
-        e[q] = r < HP - nth ? hy * HX + hx : HP;  // HP: no point
+        e[q] = own_first_point<1, 2>(TX, TY, tid, q, hy, hx) ? hy * HX + hx : HP;  // HP: no point
       }
-      if (OWN && q == 0) e[q] = hy * HX + hx;
       off[q] = pt(q) < HP ? (unsigned)(wrap(Y0 - 1 + hy, ny) * nx + wrap(X0 - 1 + hx, nx)) * (unsigned)sizeof(T) : 0u;
     }
   }
@@ -241,7 +225,7 @@ __global__ void __launch_bounds__(kBlock)
   int bx, by, bz;
   xcd_tile(bx, by, bz);
   const int X0 = bx * TX, Y0 = by * TY, K0 = bz * KB;
-  const HaloTile<T, RP> H(TX, TY, X0, Y0, nx, ny);
+  const HaloTile<T, RP, true> H(TX, TY, X0, Y0, nx, ny);
   const int HP = H.HP;
   T* sT3 = reinterpret_cast<T*>(smem);  // [xz, yz, zz] x 3 slots
   T* sT1 = sT3 + 9 * HP;                // [xx, yy, xy]
