@@ -547,15 +547,16 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE
   T* sW = sV + 3 * BOX;
   const BoxRing<T> Ur{sU, BOX, K0, X0, Y0, BX}, Vr{sV, BOX, K0, X0, Y0, BX}, Wr{sW, BOX, K0, X0, Y0, BX};
   const size_t layer = (size_t)nx * ny;
-  // this thread's box points and their in-layer byte offsets
+  // this thread's box points (own_first_point: point 0 is the thread's own column) and their
+  // in-layer byte offsets
   int bpos[RP];
   unsigned off[RP];
 #pragma unroll
   for (int q = 0; q < RP; ++q) {
-    const int e = tid + q * nth;
-    bpos[q] = e < BOX ? e : -1;
-    const int hy = e / BX, hx = e - hy * BX;
-    off[q] = e < BOX ? (unsigned)(wrap(Y0 - 2 + hy, ny) * nx + wrap(X0 - 2 + hx, nx)) * (unsigned)sizeof(T) : 0u;
+    int hy = 0, hx = 0;
+    const bool in = own_first_point<2, 2>(TX, TY, tid, q, hy, hx);
+    bpos[q] = in ? hy * BX + hx : -1;
+    off[q] = in ? (unsigned)(wrap(Y0 - 2 + hy, ny) * nx + wrap(X0 - 2 + hx, nx)) * (unsigned)sizeof(T) : 0u;
   }
   // own tile cell and, for the first 2 (TX + TY) threads, one ring cell
   const int i = X0 + threadIdx.x, j = Y0 + threadIdx.y;
@@ -676,11 +677,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE
 #pragma unroll
     for (int c = 0; c < 6; ++c) tC[c] = (T)0;
     if constexpr (PF) {
+      // the own column's tau^n of layer m + 1 is the first point of that layer's box fetch
       if (m < nz) put_tau();
       if (m + 1 < nz) put_vel(m + 1);
-      if (m + 1 < nz) load_col(m + 1, oo, tC);
       __syncthreads();
-      if (m + 1 < nz) fetch_tau(m + 1);
+      if (m + 1 < nz) {
+        fetch_tau(m + 1);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) tC[c] = rt[0][c];
+      }
       if (m + 2 < nz) fetch_vel(m + 2);
     } else {
       if (m < nz) box_tau(m);
