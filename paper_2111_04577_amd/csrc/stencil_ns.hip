@@ -227,43 +227,56 @@ __global__ void __launch_bounds__(kBlock)
   const int X0 = bx * TX, Y0 = by * TY, K0 = bz * KB;
   const HaloTile<T, RP, true> H(TX, TY, X0, Y0, nx, ny);
   const int HP = H.HP;
-  T* sT3 = reinterpret_cast<T*>(smem);  // [xz, yz, zz] x 3 slots
-  T* sT1 = sT3 + 9 * HP;                // [xx, yy, xy]
+  T* sT3 = reinterpret_cast<T*>(smem);  // [xz, yz, zz] x 3 slots (layers k-1 .. k+1)
+  T* sT1 = sT3 + 9 * HP;                // [xx, yy, xy] x 2 slots (layers of either parity)
   const size_t layer = (size_t)ny * nx;
   const int i = X0 + threadIdx.x, j = Y0 + threadIdx.y;
-  auto load_t = [&](int kk, const int* comps, T* const* dst) {
+  // raw values of one layer at this thread's tile points (phi_c, tau^n and tau^(n-1) of the six
+  // components), loaded one layer ahead of their use
+  T rw[RP], ra[RP][6], rb[RP][6];
+  auto fetch = [&](int kk) {
     const size_t o = min(max(kk, 0), nz - 1) * layer;
-    H.each([&](int e, unsigned off) {
-      const T w = (T)0.5 * ((T)1 + ld_at(phic + o, off));
+    H.each_q([&](int q, int, unsigned off) {
+      rw[q] = ld_at(phic + o, off);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const T a = ld_at(in.taun[comps[c]] + o, off);
-        dst[c][e] = w * (first ? a : (T)2 * a - ld_at(in.taunm1[comps[c]] + o, off));
+      for (int c = 0; c < 6; ++c) {
+        ra[q][c] = ld_at(in.taun[c] + o, off);
+        rb[q][c] = first ? (T)0 : ld_at(in.taunm1[c] + o, off);
       }
     });
   };
-  const int c3[3] = {4, 5, 2}, c1[3] = {0, 1, 3};
-  auto load_t3 = [&](int kk) {
-    const int sl = (kk - K0 + 1) % 3;
-    T* const dst[3] = {sT3 + (0 * 3 + sl) * HP, sT3 + (1 * 3 + sl) * HP, sT3 + (2 * 3 + sl) * HP};
-    load_t(kk, c3, dst);
+  // the weighted stress of the fetched layer kk into its slots: xz, yz, zz into the ring, xx,
+  // yy, xy into the slot of kk's parity
+  auto put = [&](int kk) {
+    const int s3 = (kk - K0 + 1) % 3, s1 = (kk - K0 + 1) & 1;
+    H.each_q([&](int q, int e, unsigned) {
+      const T w = (T)0.5 * ((T)1 + rw[q]);
+      T v[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[c] = w * (first ? ra[q][c] : (T)2 * ra[q][c] - rb[q][c]);
+      sT3[(0 * 3 + s3) * HP + e] = v[4];
+      sT3[(1 * 3 + s3) * HP + e] = v[5];
+      sT3[(2 * 3 + s3) * HP + e] = v[2];
+      sT1[(0 * 2 + s1) * HP + e] = v[0];
+      sT1[(1 * 2 + s1) * HP + e] = v[1];
+      sT1[(2 * 2 + s1) * HP + e] = v[3];
+    });
   };
-  auto load_t1 = [&](int kk) {
-    T* const dst[3] = {sT1, sT1 + HP, sT1 + 2 * HP};
-    load_t(kk, c1, dst);
-  };
-  load_t3(K0 - 1);
-  load_t3(K0);
+  fetch(K0 - 1);
+  put(K0 - 1);
+  fetch(K0);
+  put(K0);
+  fetch(K0 + 1);
   const int K1 = min(K0 + KB, nz);  // the last block of a column may march fewer layers
   for (int k = K0; k < K1; ++k) {
-    load_t3(k + 1);
-    load_t1(k);
+    put(k + 1);
     __syncthreads();
-    const int t0 = (k - K0) % 3, t1 = (k - K0 + 1) % 3, t2 = (k - K0 + 2) % 3;
+    if (k + 2 <= K1) fetch(k + 2);  // in flight while layer k is formed
+    const int t0 = (k - K0) % 3, t1 = (k - K0 + 1) % 3, t2 = (k - K0 + 2) % 3, p1 = (k - K0 + 1) & 1;
     const RingT<T> Tr{{{sT3 + t0 * HP, sT3 + t1 * HP, sT3 + t2 * HP},
                        {sT3 + (3 + t0) * HP, sT3 + (3 + t1) * HP, sT3 + (3 + t2) * HP},
                        {sT3 + (6 + t0) * HP, sT3 + (6 + t1) * HP, sT3 + (6 + t2) * HP}},
-                      {sT1, sT1 + HP, sT1 + 2 * HP},
+                      {sT1 + p1 * HP, sT1 + (2 + p1) * HP, sT1 + (4 + p1) * HP},
                       k, X0, Y0, H.HX};
     auto tp = [&](int c, int kk, int jj, int ii) { return Tr.at(c, kk, jj, ii); };
     const int id = (k * ny + j) * nx + i;
@@ -785,8 +798,8 @@ hipError_t launch_momentum_rhs(const Dims& c, const StepConsts& k, NsIn<T> in, R
   };
   if (in.viscoelastic) {
     if (!in.pol[0] || !in.pol[1] || !in.pol[2]) return hipErrorInvalidValue;
-    // the face divergences of the weighted polymer stress first (12 LDS tile slots)
-    const size_t shp = (size_t)12 * HP * sizeof(T);
+    // the face divergences of the weighted polymer stress first (15 LDS tile slots)
+    const size_t shp = (size_t)15 * HP * sizeof(T);
     if (need <= 2)
       go(k_polymer_div_zm<T, 2>, shp, in, (const T*)r.phi_c, k.first, c.nx, c.ny, c.nz);
     else
