@@ -36,7 +36,7 @@ constexpr int kBlock = 256;
 // the column enters a new coarse layer. The 3D FP32 form is held to 64 registers, so that the
 // 8 blocks per CU of a 256 x 256 x 128 grid are resident at once. SR: single resolution (the
 // phase field on the flow grid; the face velocities are taken as they are).
-template <typename T, int R, int MODE, bool RELAX>
+template <typename T, int R, int MODE, bool RELAX, int TXC = 0>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && R == 2 && MODE == 0 && !RELAX ? 8
                                        : (RELAX && sizeof(T) == 8 ? 3 : 4))))
@@ -44,7 +44,8 @@ __global__ void __launch_bounds__(kBlock)
              T* __restrict__ out, const T* __restrict__ advp, int nx, int ny, int nz, int KB, T ihx,
              T ihy, T ihz, StepConsts c) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int TX = blockDim.x, TY = blockDim.y;
+  // TXC > 0: the block shape TXC x 4 known at compile time (LDS neighbours at immediate offsets)
+  const int TX = TXC > 0 ? TXC : (int)blockDim.x, TY = TXC > 0 ? 4 : (int)blockDim.y;
   int bx, by, bz;
   xcd_tile(bx, by, bz);
   const int X0 = bx * TX, Y0 = by * TY, K0 = bz * KB;
@@ -726,14 +727,18 @@ hipError_t launch_ch_rhs(const Dims& f, const Dims& c, const StepConsts& k, ChIn
   if (need > 4) return hipErrorInvalidConfiguration;
   const size_t shm = (size_t)6 * HP * sizeof(T);
   const dim3 grid(f.nx / TX, f.ny / TY, f.nz / KB), block(TX, TY, 1);
-#define DRPF_CH(R, MODE, RELAX)                                                                  \
-  hipLaunchKernelGGL((k_ch_rhs<T, R, MODE, RELAX>), grid, block, shm, st, in.phin, in.phinm1, pv,   \
+#define DRPF_CH(R, MODE, RELAX, TXC)                                                               \
+  hipLaunchKernelGGL((k_ch_rhs<T, R, MODE, RELAX, TXC>), grid, block, shm, st, in.phin, in.phinm1, pv, \
                      rhs, in.adv, f.nx, f.ny, f.nz, KB, (T)f.ihx, (T)f.ihy, (T)f.ihz, k)
+  // the 64 x 4 tile of 3D grids with its shape at compile time
+  const bool t64 = TX == 64 && TY == 4;
 #define DRPF_CH_R(MODE, RELAX)      \
-  if (need <= 2)                    \
-    DRPF_CH(2, MODE, RELAX);        \
+  if (t64)                          \
+    DRPF_CH(2, MODE, RELAX, 64);    \
+  else if (need <= 2)               \
+    DRPF_CH(2, MODE, RELAX, 0);     \
   else                              \
-    DRPF_CH(4, MODE, RELAX)
+    DRPF_CH(4, MODE, RELAX, 0)
   // mode: 0 dual resolution, 1 single resolution, 2 advection given
   const int mode = in.adv ? 2 : (single ? 1 : 0);
   if (k.relax_kappa != 0.0) {

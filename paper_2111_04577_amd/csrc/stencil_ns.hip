@@ -294,13 +294,15 @@ __global__ void __launch_bounds__(kBlock)
 // divergences of the weighted polymer stress, given by k_polymer_div_zm. Each thread loads at
 // most RP points of a halo tile. (Five wavefronts per SIMD instead of four spill eight FP32
 // registers: no faster, and the reloads add 0.3 GB of HBM reads per launch at 256 x 256 x 128.)
-template <typename T, bool VE, int RP>
+template <typename T, bool VE, int RP, int TXC = 0>
 __global__ void __launch_bounds__(kBlock)
     k_momentum_rhs_zm(NsIn<T> in, Restricted<T> R, T* __restrict__ ru, T* __restrict__ rv,
                       T* __restrict__ rw, StepConsts c, int nx, int ny, int nz, int KB, T ihx, T ihy,
                       T ihz) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int TX = blockDim.x, TY = blockDim.y;
+  // TXC > 0: the block shape TXC x (256 / TXC) known at compile time (ring neighbours at
+  // immediate offsets)
+  const int TX = TXC > 0 ? TXC : (int)blockDim.x, TY = TXC > 0 ? kBlock / TXC : (int)blockDim.y;
   int bx, by, bz;
   xcd_tile(bx, by, bz);
   const int X0 = bx * TX, Y0 = by * TY, K0 = bz * KB;
@@ -806,11 +808,13 @@ hipError_t launch_momentum_rhs(const Dims& c, const StepConsts& k, NsIn<T> in, R
       go(k_polymer_div_zm<T, 4>, shp, in, (const T*)r.phi_c, k.first, c.nx, c.ny, c.nz);
   }
   const size_t shm = (size_t)13 * HP * sizeof(T);
-#define DRPF_MOM(VE, RP) go(k_momentum_rhs_zm<T, VE, RP>, shm, in, r, ru, rv, rw, k, c.nx, c.ny, c.nz)
+#define DRPF_MOM(VE, RP, TXC) go(k_momentum_rhs_zm<T, VE, RP, TXC>, shm, in, r, ru, rv, rw, k, c.nx, c.ny, c.nz)
+  // the 32 x 8 tile with its shape at compile time
+  const bool t32 = TX == 32 && TY == 8;
   if (in.viscoelastic) {
-    if (need <= 2) DRPF_MOM(true, 2); else DRPF_MOM(true, 4);
+    if (t32) DRPF_MOM(true, 2, 32); else if (need <= 2) DRPF_MOM(true, 2, 0); else DRPF_MOM(true, 4, 0);
   } else {
-    if (need <= 2) DRPF_MOM(false, 2); else DRPF_MOM(false, 4);
+    if (t32) DRPF_MOM(false, 2, 32); else if (need <= 2) DRPF_MOM(false, 2, 0); else DRPF_MOM(false, 4, 0);
   }
 #undef DRPF_MOM
   return hipGetLastError();
