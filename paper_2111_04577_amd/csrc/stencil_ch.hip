@@ -242,7 +242,7 @@ __global__ void __launch_bounds__(kBlock)
 // wavefronts per SIMD (80 registers, a few spilled): at 256 x 256 x 128 coarse cells that makes
 // one round of six blocks per CU with marches of 43 layers, measured 15% faster than five
 // wavefronts (one round of four blocks, marches of 64).
-template <typename T, int R, bool RELAX>
+template <typename T, int R, bool RELAX, int CXC = 0>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && R == 3 && !RELAX ? 6 : 1)))
     k_restrict_g(const T* __restrict__ phinew, const T* __restrict__ phin,
@@ -250,7 +250,8 @@ __global__ void __launch_bounds__(kBlock)
                  T fihx, T fihy, T fihz, int cnx, int cny, int cnz, int ry, int KB,
                  StepConsts c) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int CX = blockDim.x, CY = blockDim.y / 2;
+  // CXC > 0: the block shape CXC x (256 / 2 CXC) coarse columns known at compile time
+  const int CX = CXC > 0 ? CXC : (int)blockDim.x, CY = CXC > 0 ? kBlock / (2 * CXC) : (int)blockDim.y / 2;
   int bx, by, bz;
   xcd_tile(bx, by, bz);
   const int i0 = bx * CX, j0 = by * CY, k0 = bz * KB;
@@ -782,7 +783,9 @@ hipError_t launch_restrict_g(const Dims& f, const Dims& c, const StepConsts& k, 
   if (k.relax_kappa != 0.0) {
     if (Rk == 3) go(k_restrict_g<T, 3, true>); else go(k_restrict_g<T, 6, true>);
   } else {
-    if (Rk == 3) go(k_restrict_g<T, 3, false>); else go(k_restrict_g<T, 6, false>);
+    if (CX == 32 && CY == 4) go(k_restrict_g<T, 3, false, 32>);
+    else if (Rk == 3) go(k_restrict_g<T, 3, false>);
+    else go(k_restrict_g<T, 6, false>);
   }
   return hipGetLastError();
 }

@@ -216,12 +216,12 @@ struct PrevOwn {
 // k+1) in three-layer LDS rings, the xx, yy and xy components (layer k only) in one slot each,
 // Neumann clamp on load. The results go to three arrays shaped like u, v, w (the top-wall w
 // face gets zero); the momentum kernel reads them at its own faces.
-template <typename T, int RP>
+template <typename T, int RP, int TXC = 0>
 __global__ void __launch_bounds__(kBlock)
     k_polymer_div_zm(NsIn<T> in, const T* __restrict__ phic, int first, int nx, int ny, int nz, int KB,
                      T ihx, T ihy, T ihz) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int TX = blockDim.x, TY = blockDim.y;
+  const int TX = TXC > 0 ? TXC : (int)blockDim.x, TY = TXC > 0 ? kBlock / TXC : (int)blockDim.y;
   int bx, by, bz;
   xcd_tile(bx, by, bz);
   const int X0 = bx * TX, Y0 = by * TY, K0 = bz * KB;
@@ -542,13 +542,13 @@ __device__ __forceinline__ void stress_rhs(const T t0[6], const T* S, int plane,
 // rings of u, v, w over the box, from which the velocity gradient of eq. NS41 is formed (the
 // tile cell keeps its own for stage 2). Each thread loads at
 // most RP box points.
-template <typename T, int RP, int WPE, bool PF>
+template <typename T, int RP, int WPE, bool PF, int TXC = 0>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     k_polymer_rk2_zm(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
                      TauSet<T> tn, TauOut<T> tout, int nx, int ny, int nz, int KB, T ihx, T ihy,
                      T ihz, T dt, T inv_wi, T omb, T gk, Walls<T> wl) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int TX = blockDim.x, TY = blockDim.y;
+  const int TX = TXC > 0 ? TXC : (int)blockDim.x, TY = TXC > 0 ? kBlock / TXC : (int)blockDim.y;
   int bx, by, bz;
   xcd_tile(bx, by, bz);
   const int X0 = bx * TX, Y0 = by * TY, K0 = bz * KB;
@@ -803,7 +803,10 @@ hipError_t launch_momentum_rhs(const Dims& c, const StepConsts& k, NsIn<T> in, R
     // the face divergences of the weighted polymer stress first (15 LDS tile slots)
     const size_t shp = (size_t)15 * HP * sizeof(T);
     if (need <= 2)
-      go(k_polymer_div_zm<T, 2>, shp, in, (const T*)r.phi_c, k.first, c.nx, c.ny, c.nz);
+      if (TX == 32 && TY == 8)
+        go(k_polymer_div_zm<T, 2, 32>, shp, in, (const T*)r.phi_c, k.first, c.nx, c.ny, c.nz);
+      else
+        go(k_polymer_div_zm<T, 2>, shp, in, (const T*)r.phi_c, k.first, c.nx, c.ny, c.nz);
     else
       go(k_polymer_div_zm<T, 4>, shp, in, (const T*)r.phi_c, k.first, c.nx, c.ny, c.nz);
   }
@@ -876,12 +879,16 @@ hipError_t launch_polymer_rk2(const Dims& c, const StepConsts& k, const T* u, co
     hipLaunchKernelGGL(kernel, grid, dim3(TX, TY), shm, st, u, v, w, tn, to, c.nx, c.ny, c.nz, KB, (T)c.ihx,
                        (T)c.ihy, (T)c.ihz, (T)k.dt, (T)k.inv_wi, (T)(1.0 - k.beta), gk, wl);
   };
-  // registers: FP32 2 waves per SIMD (222 VGPRs, no spills); FP64 1 (its 289 live registers
-  // spill to scratch at 2 waves, 2.5x the algorithmic bytes on the C5 grid and slower: 864 against
-  // 731 us)
+  // registers: with the 32 x 8 shape at compile time FP32 fits four waves per SIMD (128 VGPRs)
+  // and FP64 two (202), without spills; with the shape at run time FP32 takes 2 waves per SIMD
+  // (226 VGPRs) and FP64 1 (at 2 waves it spills to scratch: 2.5x the algorithmic bytes on the
+  // C5 grid and slower, 864 against 731 us)
   constexpr int WPE = sizeof(T) == 4 ? 2 : 1;
+  constexpr int WPE32 = sizeof(T) == 4 ? 4 : 2;
   constexpr bool PF = sizeof(T) == 4;
-  if (need <= 2)
+  if (TX == 32 && TY == 8)
+    go(k_polymer_rk2_zm<T, 2, WPE32, PF, 32>);
+  else if (need <= 2)
     go(k_polymer_rk2_zm<T, 2, WPE, PF>);
   else
     go(k_polymer_rk2_zm<T, 4, WPE, PF>);
