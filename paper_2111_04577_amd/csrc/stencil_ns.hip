@@ -280,9 +280,9 @@ __global__ void __launch_bounds__(kBlock)
                       k, X0, Y0, H.HX};
     auto tp = [&](int c, int kk, int jj, int ii) { return Tr.at(c, kk, jj, ii); };
     const int id = (k * ny + j) * nx + i;
-    in.pol[0][id] = polymer_div_u<T>(tp, k, j, i, ihx, ihy, ihz);
-    in.pol[1][id] = polymer_div_v<T>(tp, k, j, i, ihx, ihy, ihz);
-    in.pol[2][id] = k == nz - 1 ? (T)0 : polymer_div_w<T>(tp, k, j, i, ihx, ihy, ihz);
+    st_nt(in.pol[0] + id, polymer_div_u<T>(tp, k, j, i, ihx, ihy, ihz));
+    st_nt(in.pol[1] + id, polymer_div_v<T>(tp, k, j, i, ihx, ihy, ihz));
+    st_nt(in.pol[2] + id, k == nz - 1 ? (T)0 : polymer_div_w<T>(tp, k, j, i, ihx, ihy, ihz));
     __syncthreads();
   }
 }
@@ -403,9 +403,9 @@ __global__ void __launch_bounds__(kBlock)
              m.inv_re * t.ri * t.pol - m.inv_re * t.ri * t.vis - m.k_sigma * t.ri * t.cap - a;
     };
     const int id = (k * ny + j) * nx + i;
-    ru[id] = rhs(mom_u(m, k, j, i, id), (T)c.ax);
-    rv[id] = rhs(mom_v(m, k, j, i, id), (T)c.ay);
-    rw[id] = k == nz - 1 ? (T)0 : rhs(mom_w(m, k, j, i, id), (T)c.az);
+    st_nt(ru + id, rhs(mom_u(m, k, j, i, id), (T)c.ax));
+    st_nt(rv + id, rhs(mom_v(m, k, j, i, id), (T)c.ay));
+    st_nt(rw + id, k == nz - 1 ? (T)0 : rhs(mom_w(m, k, j, i, id), (T)c.az));
     for (int a = 0; a < 3; ++a) prev[a] = prev_next[a];
     ps0 = ps1;
     pn0 = pn1;
@@ -727,7 +727,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE
       stress_rhs<T>(t1c, sT1, BOX, eo, BX, t1p, t1o, k > 0, k < nz - 1, Lk, fk, ihx, ihy, ihz, inv_wi, omb, gk, rh);
       const unsigned o = (unsigned)k * lbytes + oo;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) st_at(tout.p[c], o, (T)0.5 * tA[c] + (T)0.5 * (t1c[c] + dt * rh[c]));
+      for (int c = 0; c < 6; ++c) st_nt_at(tout.p[c], o, (T)0.5 * tA[c] + (T)0.5 * (t1c[c] + dt * rh[c]));
     }
     __builtin_amdgcn_sched_barrier(0);
     // ---- stage 1 at layer m, ring cell (needed only for stage 2 of this block's layers); its
