@@ -115,7 +115,8 @@ typedef struct drpf_params {
                                   D_w (gamma0 phi^{n+1} - phi_hat) / dt at the wall-adjacent
                                   cell (a Robin condition; NS25 is solved with it and with
                                   NS33 exactly). 0 (default): static contact angles. The
-                                  adjoint needs 0                                            */
+                                  adjoint covers both (with d_w > 0 it solves with the
+                                  transposed relaxed operator)                               */
   double u_wall_bottom[2];     /* tangential wall velocity (x, y) at z = 0 and ...            */
   double u_wall_top[2];        /* ... at z = lz: the no-slip condition u = u_w of eq. NS13
                                   (ghost = 2 u_w - adjacent in every stencil and in the

@@ -142,6 +142,42 @@ def helmholtz(rhs, coeff, shift, kind, h):
     return torch.fft.ifft2(Y, dim=(1, 2)).real
 
 
+def relaxed_ch_solve(rhs, s, c, d, h):
+    """Solve [L_N (L_N + d W) - s L_N + c] x = rhs, W the indicator of the two wall-adjacent
+    layers: eq. NS25 with the relaxed wall condition of eq. NS34 (s and c may be tensors).
+    FFT in x and y; for every Fourier mode (x-y eigenvalue mu) the nz x nz matrix
+    (T + mu)(T + mu + d W) - s (T + mu) + c, T the wall-normal second difference with Neumann
+    ghosts, is formed densely and solved directly (real and imaginary parts alike)."""
+    nz, ny, nx = rhs.shape
+    hx, hy, hz = h
+    T = torch.zeros((nz, nz), dtype=TT)
+    for k in range(nz):
+        T[k, k] = -2.0
+        if k > 0:
+            T[k, k - 1] = 1.0
+        else:
+            T[k, k] += 1.0
+        if k < nz - 1:
+            T[k, k + 1] = 1.0
+        else:
+            T[k, k] += 1.0
+    T = T / hz ** 2
+    Wd = torch.zeros((nz, nz), dtype=TT)
+    Wd[0, 0] = 1.0
+    Wd[nz - 1, nz - 1] += 1.0
+    lx = -4.0 / hx ** 2 * torch.sin(math.pi * torch.arange(nx, dtype=TT) / nx) ** 2
+    ly = -4.0 / hy ** 2 * torch.sin(math.pi * torch.arange(ny, dtype=TT) / ny) ** 2
+    I = torch.eye(nz, dtype=TT)
+    mu = (ly[:, None] + lx[None, :])[:, :, None, None]
+    A = T + mu * I                                     # (ny, nx, nz, nz)
+    M = A @ (A + d * Wd) - s * A + c * I
+    X = torch.fft.fft2(rhs.to(torch.complex128), dim=(1, 2)).permute(1, 2, 0)  # (ny, nx, nz)
+    Xr = torch.stack([X.real, X.imag], dim=-1)         # (ny, nx, nz, 2)
+    Y = torch.linalg.solve(M, Xr)
+    Yc = torch.complex(Y[..., 0], Y[..., 1]).permute(2, 0, 1)
+    return torch.fft.ifft2(Yc, dim=(1, 2)).real
+
+
 # ---- transfers ------------------------------------------------------------------------
 
 def prolong(u, v, w, ry):
@@ -224,11 +260,11 @@ def constants(P: Params, first, pe):
 
 def step(P: Params, st, theta, pe, wi):
     """One coupled step on tensors; st holds lists of tensors like the NumPy oracle state."""
-    if (P.d_w != 0.0 or P.advection != 0 or P.constitutive != 0 or P.giesekus_alpha != 0.0
-            or P.refine != 2 or P.moving_walls):
+    if (P.advection != 0 or P.constitutive != 0 or P.giesekus_alpha != 0.0 or P.refine != 2
+            or P.moving_walls):
         raise NotImplementedError("the differentiable step covers the dual-resolution step with "
-                                  "static walls at rest, central advection and the Oldroyd-B "
-                                  "stress form")
+                                  "walls at rest, central advection and the Oldroyd-B stress "
+                                  "form")
     first = st["step"] == 0
     C = constants(P, first, pe)
     hf, h = P.hf, P.h
@@ -251,9 +287,24 @@ def step(P: Params, st, theta, pe, wi):
     top = (kz == nzf - 1).to(TT)[:, None, None]
     g1 = (1.0 - phis * phis) / (math.sqrt(2.0) * P.cn) / hf[2]
     b = g1 * (torch.cos(theta) * bot + math.cos(math.radians(P.theta_top_deg)) * top)
-    Psi = helmholtz(Q - C["c_psi"] * b, 1.0, C["c_psi"], "neumann", hf)
-    phi_new = helmholtz(Psi - b, 1.0, -C["alpha"], "neumann", hf)
-    G = -cn2 * (lap_neumann(phi_new, hf) + b) + C["S"] * (phi_new - phis) + phis ** 3 - phis
+    if P.d_w == 0.0:
+        Psi = helmholtz(Q - C["c_psi"] * b, 1.0, C["c_psi"], "neumann", hf)
+        phi_new = helmholtz(Psi - b, 1.0, -C["alpha"], "neumann", hf)
+        G = -cn2 * (lap_neumann(phi_new, hf) + b) + C["S"] * (phi_new - phis) + phis ** 3 - phis
+    else:
+        # relaxed walls (eqs. NS15, NS33, NS34): with kappa = D_w gamma0 / dt the wall-adjacent
+        # ghost of phi^{n+1} carries -kappa phi^{n+1} + kappa phi_hat / gamma0 besides g, so
+        # L_w = L_N + dL + b_R with dL = -kappa / hz and b_R = b + (kappa / hz) phi_hat / gamma0
+        # on the wall layers; NS25 becomes [L_N (L_N + dL) - (S/Cn^2) L_N + c] phi^{n+1} =
+        # Q - L_N b_R, c = gamma0 Pe / (Cn^2 dt)
+        kap = P.d_w * C["gamma0"] / P.dt
+        wall = bot + top
+        dwall = -kap / hf[2]
+        bR = b + (kap / hf[2]) * phih / C["gamma0"] * wall
+        c = C["gamma0"] * pe / (cn2 * P.dt)
+        phi_new = relaxed_ch_solve(Q - lap_neumann(bR, hf), C["S"] / cn2, c, dwall, hf)
+        lw = lap_neumann(phi_new, hf) + dwall * wall * phi_new + bR
+        G = -cn2 * lw + C["S"] * (phi_new - phis) + phis ** 3 - phis
     # ---- restriction and properties
     ry = P.ry
     R = lambda f, loc: restrict(f, loc, ry)

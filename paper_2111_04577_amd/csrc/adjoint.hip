@@ -645,7 +645,7 @@ struct RestrictAdjIn {
 __global__ void __launch_bounds__(kBlock)
     k_adj_restrict_ch(RestrictAdjIn a, const D* __restrict__ lphi_new_in, D* __restrict__ lG_out,
                       D* __restrict__ lphi_out, int fnx, int fny, int fnz, D fihx, D fihy, D fihz,
-                      int cnx, int cny, int cnz, int ry, D cn2, D S) {
+                      int cnx, int cny, int cnz, int ry, D cn2, D S, D dwall) {
   int K, J, I;
   cell_index(K, J, I);
   const int id = (K * fny + J) * fnx + I;
@@ -679,12 +679,14 @@ __global__ void __launch_bounds__(kBlock)
   lp += 0.5 * wyf * 0.5 * cat(a.lph_xy, kc, jyf, ixf);
   lp += wzf * wyc * 0.5 * cat(a.lph_xz, mz, jc, ixf);
   lp += wzf * wyf * 0.5 * cat(a.lph_yz, mz, jyf, ic);
-  // G = -Cn^2 (L_N phi + b) + S (phi - phi*) + f(phi*): phi enters through -Cn^2 L_N + S
+  // G = -Cn^2 (L_N phi + b) + S (phi - phi*) + f(phi*): phi enters through -Cn^2 L_N + S; with
+  // relaxed walls (eq. NS34) also through -Cn^2 dwall on the wall-adjacent layers
   const D lap = (lGf(K, J, I + 1) - 2 * g0 + lGf(K, J, I - 1)) * fihx * fihx +
                 (lGf(K, J + 1, I) - 2 * g0 + lGf(K, J - 1, I)) * fihy * fihy +
                 (lGf(K + 1, J, I) - 2 * g0 + lGf(K - 1, J, I)) * fihz * fihz;
+  const D wallw = (D)((K == 0) + (K == fnz - 1));
   lG_out[id] = g0;
-  lphi_out[id] = lp - cn2 * lap + S * g0;
+  lphi_out[id] = lp - cn2 * lap + S * g0 - cn2 * dwall * wallw * g0;
 }
 
 // ---- Cahn-Hilliard right-hand side, wetting data and advection transposed -----------------
@@ -717,16 +719,19 @@ __global__ void __launch_bounds__(kBlock)
   const D ph = first ? a.phin[id] : 2.0 * a.phin[id] - 0.5 * a.phinm1[id];
   D lphis = (-c.S + 3 * p0 * p0 - 1) * lg + ((3 * p0 * p0 - 1) * c.inv_cn2 - c.s_cn2) * zeta;
   // wetting data b = g cos(theta) (1 - phi*^2) / hz on the wall layers; it enters G
-  // directly and Q - L_N b through the solve
-  D th = 0;
+  // directly and Q - L_N b through the solve. With relaxed walls (eq. NS34) the wall data are
+  // b_R = b + (kappa / hz) phi_hat / gamma0 there, entering the same two places.
+  D th = 0, lbw = 0;
   if (K == 0) {
     const D lb = -c.cn2 * lg - zeta;
     lphis += lb * c.g_bot * fihz * (-2.0 * p0);
     th = lb * (-sin_bot / (sqrt(2.0) * c.cn)) * fihz * (1.0 - p0 * p0);
+    lbw += lb;
   }
   if (K == fnz - 1) {
     const D lb = -c.cn2 * lg - zeta;
     lphis += lb * c.g_top * fihz * (-2.0 * p0);
+    lbw += lb;
   }
   // advection div(u phi*) transposed: lam_A = -(Pe/Cn^2) lam_Q
   auto lA = [&](int kk, int jj, int ii) -> D { return -c.pe_cn2 * Q(kk, jj, ii); };
@@ -751,7 +756,7 @@ __global__ void __launch_bounds__(kBlock)
   // O(1/dt) parts cancel pointwise.
   const D pe_part = (lq * ((ph - c.gamma0 * pn) * c.inv_dt - A) +
                      (c.S / (2.0 * c.pe)) * (zeta + c.cn2 * lg) * (pn - p0)) * c.inv_cn2;
-  const D lphih = c.pe_cn2 * c.inv_dt * lq;
+  const D lphih = c.pe_cn2 * c.inv_dt * lq + c.relax_kappa * c.inv_gamma0 * fihz * lbw;
   lphi_n[id] += first ? lphis + lphih : 2.0 * (lphis + lphih);
   lphi_nm1[id] = first ? 0.0 : -lphis - 0.5 * lphih;
   block_partial(th, part_theta);
@@ -934,7 +939,8 @@ hipError_t launch_adj_restrict_ch(const Dims& f, const Dims& c, const StepConsts
                   b.lph_xy, b.lph_xz, b.lph_yz};
   const Launch3 L = launch3(f.nx, f.ny, f.nz);
   hipLaunchKernelGGL(k_adj_restrict_ch, L.grid, L.block, 0, st, a, lphi_new_in, lG, lphi, f.nx, f.ny, f.nz,
-                     f.ihx, f.ihy, f.ihz, c.nx, c.ny, c.nz, c.ny == 1 ? 1 : 2, k.cn2, k.S);
+                     f.ihx, f.ihy, f.ihz, c.nx, c.ny, c.nz, c.ny == 1 ? 1 : 2, k.cn2, k.S,
+                     -k.relax_kappa * f.ihz);
   return hipGetLastError();
 }
 

@@ -840,7 +840,10 @@ int adjoint_impl(drpf_grid* g, const drpf_state* x, const drpf_state* xn, drpf_a
   const T* inf[4] = {P(A.lQ), nullptr, nullptr, nullptr};
   HIPCHK(launch_fft_x_fwd<T>(F, tf, inf, 1, Sf, st), "adjoint fft_x fine");
   HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, false, st), "adjoint fft_y fine");
-  HIPCHK(launch_zpass_ch<T>(F, tf, Sf, K.c_psi, K.alpha, 1.0 / ((double)F.nx * F.ny), 0.0, st),
+  // the fused Cahn-Hilliard operator is symmetric with static walls; with relaxed walls its
+  // rank-two wall term is not, and the transposed pass solves with the transpose
+  HIPCHK(launch_zpass_ch<T>(F, tf, Sf, K.c_psi, K.alpha, 1.0 / ((double)F.nx * F.ny), -K.relax_kappa / F.hz, st,
+                            K.relax_kappa != 0.0),
          "adjoint zpass_ch");
   HIPCHK(launch_fft_y<T>(F, tf, Sf, 1, true, st), "adjoint ifft_y fine");
   RealSet<T> of;
@@ -1238,7 +1241,6 @@ int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes) {
     return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
   if (p->refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
   if (p->advection != 0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the central advection only");
-  if (p->d_w != 0.0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers static contact angles only");
   if (moving_walls(*p)) return fail(DRPF_EUNSUPPORTED, "the adjoint covers walls at rest only");
   const Dims F = fine_dims(*p);
   // the transposed fine-grid kernels index a fine field with 32-bit integers
@@ -1256,7 +1258,6 @@ int drpf_adjoint_attach(drpf_grid* g, void* d_workspace, size_t bytes) {
     return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
   if (g->p.refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
   if (g->p.advection != 0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the central advection only");
-  if (g->p.d_w != 0.0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers static contact angles only");
   if (!d_workspace) return fail(DRPF_EWORKSPACE, "null adjoint workspace");
   if (((uintptr_t)d_workspace & 255) != 0) return fail(DRPF_EWORKSPACE, "adjoint workspace must be 256-byte aligned");
   const size_t need = adj_layout(g->F, g->C).total;
@@ -1274,7 +1275,6 @@ int drpf_adjoint_step(drpf_grid* g, const drpf_state* x, const drpf_state* x_nex
     return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
   if (g->p.refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
   if (g->p.advection != 0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the central advection only");
-  if (g->p.d_w != 0.0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers static contact angles only");
   if (!g->aws) return fail(DRPF_EINVAL, "no adjoint workspace attached");
   if (!x->phi[0] || !x->phi[1] || !x->u[0] || !x->u[1] || !x->v[0] || !x->v[1] || !x->w[0] || !x->w[1] ||
       !x->p[0] || !x->p[1])

@@ -55,9 +55,10 @@ template <typename T>
 hipError_t launch_top_layer(const Dims& d, const T* top, T* x, hipStream_t st);
 // Cahn-Hilliard: (L - c_psi) then (L + alpha), both Neumann; with dwall != 0 the fused
 // operator gains L dW (dW: dwall on the two wall-adjacent rows), the relaxed walls of eq. NS34.
+// trans (FP64, dwall != 0): the transposed operator, (L - c_psi)(L + alpha) + dW L.
 template <typename T>
 hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, double c_psi,
-                           double alpha, double scale, double dwall, hipStream_t st);
+                           double alpha, double scale, double dwall, hipStream_t st, bool trans = false);
 // Navier-Stokes: velocity Helmholtz x3, divergence, FP64 Poisson, correction.
 template <typename T>
 hipError_t launch_zpass_ns(const Dims& d, const Tables<T>& tb, cx<T>* spec4, const StepConsts& c,

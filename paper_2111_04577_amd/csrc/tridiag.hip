@@ -406,8 +406,9 @@ __global__ void __launch_bounds__(kZBlock)
   }
 }
 
-// The same pass with the transform length at run time (lds_fft): the FP64 form.
-template <typename T, bool ROBIN>
+// The same pass with the transform length at run time (lds_fft): the FP64 form. TRANS (relaxed
+// walls only) solves with the transposed operator, for the discrete adjoint.
+template <typename T, bool ROBIN, bool TRANS = false>
 __global__ void __launch_bounds__(1024)
     k_zpass_ch_rt(cx<T>* __restrict__ S, int P, int Ny, int Nz, int logNz, int TL,
                const double* __restrict__ lamx, const double* __restrict__ lamy,
@@ -480,6 +481,9 @@ __global__ void __launch_bounds__(1024)
     // x_k = sum_m W_m F_m cos(pi m (k + 1/2) / N), W = (1, 2, 2, ...), the sum and difference
     // solve sigma = P_e / (1 + H_e), delta = P_o / (1 + H_o) with P = 2 sum W c F0 and
     // H = 2 sum W c G over even or odd m. H >= 0 (d < 0, lambda <= 0, A > 0).
+    // Transposed (TRANS): the operator is (L - c_psi)(L + alpha) + dW L, whose rank-two part
+    // takes the wall values of L x instead of x: G_m = d c_m / (N A_m), and P and H weight each
+    // term by lambda_m (P = 2 sum W lambda c F0, H = 2 sum W lambda c G, the same H as above).
     // after the twiddles, rounded up to 16 bytes: the wall sums [TL][2], the partials
     // [NC][TL][6], then G [Nz][TL] in the storage type
     const int NC = min((int)(blockDim.x >> ltl), 16);
@@ -499,21 +503,27 @@ __global__ void __launch_bounds__(1024)
       const T lm = lxy + (T)lamz[m];
       const T im = recip((lm - cp) * (lm + al));
       buf[m * TL + t] = (sc * im) * dct_out(Vm, Vr, twq[m]);
-      sG[m * TL + t] = (T)dwall * lm * twq[m].re * im / (T)Nz;
+      sG[m * TL + t] = (T)dwall * (TRANS ? (T)1 : lm) * twq[m].re * im / (T)Nz;
       if (mr != m) {
         const T lr = lxy + (T)lamz[mr];
         const T ir = recip((lr - cp) * (lr + al));
         buf[mr * TL + t] = (sc * ir) * dct_out(Vr, Vm, twq[mr]);
-        sG[mr * TL + t] = (T)dwall * lr * twq[mr].re * ir / (T)Nz;
+        sG[mr * TL + t] = (T)dwall * (TRANS ? (T)1 : lr) * twq[mr].re * ir / (T)Nz;
       }
     }
     __syncthreads();
     // partial sums over m = ch, ch + NC, ... per mode, then their totals
     for (int e = threadIdx.x; e < NC * TL; e += blockDim.x) {
       const int t = e & (TL - 1), ch = e >> ltl;
+      T lxy = (T)0;
+      if (TRANS) {
+        int ky, kx;
+        spec_mode(min(l0 + t, lines - 1), P, Ny, ky, kx);
+        lxy = (T)(lamx[kx] + lamy[ky]);
+      }
       double acc[6] = {0, 0, 0, 0, 0, 0};  // P_e (re, im), P_o (re, im), H_e, H_o
       for (int m = ch; m < Nz; m += NC) {
-        const double wc = (m == 0 ? 2.0 : 4.0) * (double)twq[m].re;
+        const double wc = (m == 0 ? 2.0 : 4.0) * (double)twq[m].re * (TRANS ? (double)(lxy + (T)lamz[m]) : 1.0);
         const cx<T> F = buf[m * TL + t];
         const int o = (m & 1) * 2;
         acc[o] += wc * (double)F.re;
@@ -817,7 +827,8 @@ hipError_t launch_top_layer(const Dims& d, const T* top, T* x, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, double c_psi,
-                           double alpha, double scale, double dwall, hipStream_t st) {
+                           double alpha, double scale, double dwall, hipStream_t st, bool trans) {
+  if (trans && (sizeof(T) != 8 || dwall == 0.0)) return hipErrorInvalidValue;
   if constexpr (sizeof(T) == 8) {
     // tiles of 128 bytes per row (8 complex FP64 modes): one cache line
     int TL = (int)(128 / sizeof(cx<T>));
@@ -840,9 +851,10 @@ hipError_t launch_zpass_ch(const Dims& d, const Tables<T>& tb, cx<T>* spec, doub
       const int nc = (threads / TL) < 16 ? threads / TL : 16;
       shm = ((shm + 15) & ~(size_t)15) + (size_t)2 * TL * sizeof(cx<double>) + (size_t)6 * nc * TL * sizeof(double) +
             (size_t)d.nz * TL * sizeof(T);
-      hipLaunchKernelGGL((k_zpass_ch_rt<T, true>), dim3((lines + TL - 1) / TL), dim3(threads), shm, st, spec,
-                         d.pitch, d.ny, d.nz, lognz, TL, tb.lam_x, tb.lam_y, tb.lam_z, tb.tw_z, tb.tw_zq, c_psi,
-                         alpha, scale / d.nz, dwall);
+      auto kern = trans ? k_zpass_ch_rt<T, true, true> : k_zpass_ch_rt<T, true, false>;
+      hipLaunchKernelGGL(kern, dim3((lines + TL - 1) / TL), dim3(threads), shm, st, spec, d.pitch, d.ny, d.nz,
+                         lognz, TL, tb.lam_x, tb.lam_y, tb.lam_z, tb.tw_z, tb.tw_zq, c_psi, alpha, scale / d.nz,
+                         dwall);
     }
     return hipGetLastError();
   } else {
@@ -926,7 +938,7 @@ hipError_t launch_zpass_ns_adj(const Dims& d, const Tables<double>& tb, cx<doubl
                                          hipStream_t);                                          \
   template hipError_t launch_top_layer<T>(const Dims&, const T*, T*, hipStream_t);             \
   template hipError_t launch_zpass_ch<T>(const Dims&, const Tables<T>&, cx<T>*, double, \
-                                         double, double, double, hipStream_t);                   \
+                                         double, double, double, hipStream_t, bool);             \
   template hipError_t launch_zpass_ns<T>(const Dims&, const Tables<T>&, cx<T>*,         \
                                          const StepConsts&, double, hipStream_t);
 INST(double)

@@ -112,7 +112,7 @@ def test_validation_advection_scheme():
 
 
 def test_validation_wall_relaxation():
-    """d_w >= 0 and finite; the adjoint covers static contact angles only."""
+    """d_w >= 0 and finite; the adjoint covers relaxed walls too (on FP64 grids)."""
     B = _lib()
     L = B.lib()
     for d, rc in ((-0.1, B.DRPF_EINVAL), (float("inf"), B.DRPF_EINVAL), (float("nan"), B.DRPF_EINVAL),
@@ -121,6 +121,8 @@ def test_validation_wall_relaxation():
         assert L.drpf_validate(ctypes.byref(p)) == rc, d
     nb = ctypes.c_size_t()
     p = _params(d_w=0.1)
+    assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_OK and nb.value > 0
+    p = _params(d_w=0.1, precision=32)
     assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_EUNSUPPORTED
 
 

@@ -82,14 +82,24 @@ STEP_CASES = [
 ]
 
 
-@pytest.mark.parametrize("name,kw", STEP_CASES, ids=[c[0] for c in STEP_CASES])
+# relaxed walls (D_w > 0, eqs. NS15, NS33, NS34): the fused Cahn-Hilliard operator is no longer
+# symmetric, and the reverse step solves with its transpose
+RELAXED_CASES = [
+    ("C4", dict(nx=16, nz=8, noise=1e-2, d_w=0.5)),        # 2D Oldroyd-B
+    ("C3", dict(nx=8, ny=4, nz=8, noise=1e-2, d_w=2.0)),   # 3D Oldroyd-B, strong relaxation
+    ("C2", dict(nx=8, ny=4, nz=8, noise=0.0, d_w=0.1)),    # 3D Newtonian, ratios 1000 / 100
+]
+RELAXED_IDS = ["C4-dw0.5", "C3-dw2", "C2-dw0.1"]
+
+
+@pytest.mark.parametrize("name,kw", STEP_CASES + RELAXED_CASES, ids=[c[0] for c in STEP_CASES] + RELAXED_IDS)
 @pytest.mark.parametrize("before", [0, 3], ids=["first", "bdf2"])
 def test_adjoint_step_matches_oracle(drpf, name, kw, before):
     cfg = W.config(name, **kw)
     P = model.Params.from_config(cfg)
     st = S.run(P, W.droplet_state(cfg), before)
     lam = W.adjoint_seed(cfg, 11 + before)
-    say(f"[gpu] adjoint step {name} {cfg.nx}x{cfg.ny}x{cfg.nz} after {before} steps")
+    say(f"[gpu] adjoint step {name} {cfg.nx}x{cfg.ny}x{cfg.nz} d_w {cfg.d_w} after {before} steps")
     ref, gref = OA.adjoint_step(P, st, lam)
     got, g, xh = gpu_adjoint_step(drpf, cfg, st, lam)
     errs = adjoint_errors(got, ref, cfg.viscoelastic)
@@ -127,7 +137,8 @@ def test_adjoint_step_is_linear_and_deterministic(drpf, name, kw):
     assert np.array_equal(gc, gc2)
 
 
-@pytest.mark.parametrize("name,kw", STEP_CASES[:1] + STEP_CASES[3:4], ids=["C4", "C5"])
+@pytest.mark.parametrize("name,kw", STEP_CASES[:1] + STEP_CASES[3:4] + RELAXED_CASES[1:2],
+                         ids=["C4", "C5", "C3-dw2"])
 def test_adjoint_step_with_next_state(drpf, name, kw):
     """Handing drpf_adjoint_step the state after the step (so that it recomputes only the
     restricted set and the first polymer stage) gives the same adjoint as the full recompute,
@@ -216,6 +227,25 @@ def test_trajectory_gradient_small(drpf, observable):
         assert abs(fd - g[a]) <= 1e-6 * abs(g[a]), (which, fd, g[a])
 
 
+def test_trajectory_gradient_relaxed_walls(drpf):
+    """The same with relaxed walls (D_w = 0.5): 12 steps, checkpoints every 5, gradients of
+    the wetted radius equal the oracle's reverse differentiation and central differences of
+    the GPU forward."""
+    cfg = W.config("C4", nx=32, nz=16, cn=0.04, pe=75.0, dt=5e-3, noise=0.0, d_w=0.5)
+    P = model.Params.from_config(cfg)
+    N = 12
+    say(f"[gpu] trajectory gradient, relaxed walls, {cfg.nx}x{cfg.nz} {N} steps")
+    J, g = _autograd(cfg, N, 5, "wetted_radius")
+    Jr, gr = OA.trajectory_gradient(P, W.droplet_state(cfg), N, OA.wetted_radius)
+    say("  J", J, Jr, "grad", g, gr)
+    assert abs(J - Jr) <= 1e-12 * abs(Jr)
+    check_grad(g, gr, (1e-9, 1e-6, 1e-9))
+    for a, which in enumerate(("theta", "pe", "wi")):
+        fd = _fd(drpf, cfg, N, which, 1e-4)
+        say("  fd", which, fd, g[a])
+        assert abs(fd - g[a]) <= 1e-6 * abs(g[a]), (which, fd, g[a])
+
+
 def test_adjoint_step_full_size_c4(drpf):
     """One reverse step on the full 2D viscoelastic grid (256x128 coarse, 512x256 fine), after
     five forward steps, element by element against the oracle."""
@@ -224,6 +254,23 @@ def test_adjoint_step_full_size_c4(drpf):
     st = S.run(P, W.droplet_state(cfg), 5)
     lam = W.adjoint_seed(cfg, 21)
     say("[gpu] adjoint step C4 full size")
+    ref, gref = OA.adjoint_step(P, st, lam)
+    got, g, _ = gpu_adjoint_step(drpf, cfg, st, lam)
+    errs = adjoint_errors(got, ref, True)
+    say("  errors", {k: f"{v:.1e}" for k, v in errs.items()}, "grad", g, gref)
+    assert max(errs.values()) < 1e-10, errs
+    check_grad(g, gref)
+
+
+def test_adjoint_step_full_size_c4_relaxed(drpf):
+    """The full 2D viscoelastic grid with relaxed walls (D_w = 0.5): the transposed relaxed
+    Cahn-Hilliard pass at 256 wall-normal points (its partial sums over 16 chunks per mode)
+    against the oracle, element by element."""
+    cfg = W.config("C4", noise=1e-3, seed=5, d_w=0.5)
+    P = model.Params.from_config(cfg)
+    st = S.run(P, W.droplet_state(cfg), 5)
+    lam = W.adjoint_seed(cfg, 21)
+    say("[gpu] adjoint step C4 full size, relaxed walls")
     ref, gref = OA.adjoint_step(P, st, lam)
     got, g, _ = gpu_adjoint_step(drpf, cfg, st, lam)
     errs = adjoint_errors(got, ref, True)

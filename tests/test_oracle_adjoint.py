@@ -5,7 +5,9 @@
 * its state adjoint satisfies <lam, J v> = <J^T lam, v> with J v taken by central
   differences of the NumPy oracle step along seeded directions v;
 * its parameter gradients through many steps equal central differences of the NumPy oracle
-  trajectory in the bottom static angle, Pe and Wi.
+  trajectory in the bottom static angle, Pe and Wi;
+* all three also with relaxed walls (D_w > 0), whose NumPy step is pinned separately
+  (test_oracle_wall_relaxation.py).
 """
 from __future__ import annotations
 
@@ -24,6 +26,11 @@ FIELDS = ("phi", "u", "v", "w", "p")
 
 CASES = [("C4", dict(nx=16, nz=8, noise=1e-2)), ("C1", dict(nx=16, nz=8, noise=1e-2)),
          ("C3", dict(nx=8, ny=4, nz=8, noise=1e-2)), ("C2", dict(nx=8, ny=4, nz=8, noise=0.0))]
+# relaxed walls (D_w > 0, eqs. NS15, NS33, NS34): 2D Oldroyd-B, 3D Oldroyd-B with strong
+# relaxation, 3D Newtonian with the C2R value
+RELAXED = [("C4", dict(nx=16, nz=8, noise=1e-2, d_w=0.5)), ("C3", dict(nx=8, ny=4, nz=8, noise=1e-2, d_w=2.0)),
+           ("C2", dict(nx=8, ny=4, nz=8, noise=0.0, d_w=0.1))]
+RELAXED_IDS = ["C4-dw0.5", "C3-dw2", "C2-dw0.1"]
 
 
 def _flat(st, ve):
@@ -33,7 +40,7 @@ def _flat(st, ve):
     return xs
 
 
-@pytest.mark.parametrize("name,kw", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("name,kw", CASES + RELAXED, ids=[c[0] for c in CASES] + RELAXED_IDS)
 def test_differentiable_step_equals_numpy_step(name, kw):
     import torch
     cfg = W.config(name, **kw)
@@ -63,7 +70,7 @@ def _inner(a, b, ve):
     return sum(float(np.sum(x * y)) for x, y in zip(_flat(a, ve), _flat(b, ve)))
 
 
-@pytest.mark.parametrize("name,kw", CASES[:3], ids=[c[0] for c in CASES[:3]])
+@pytest.mark.parametrize("name,kw", CASES[:3] + RELAXED[:2], ids=[c[0] for c in CASES[:3]] + RELAXED_IDS[:2])
 def test_state_adjoint_dot_product(name, kw):
     """<lam, (step(x + e v) - step(x - e v)) / 2e> = <adjoint_step(lam), v> (NumPy step for the
     directional derivative)."""
@@ -91,6 +98,28 @@ def test_parameter_gradients_vs_central_differences():
     P = model.Params.from_config(cfg)
     st0 = W.droplet_state(cfg)
     N = 20
+    _, g = OA.trajectory_gradient(P, st0, N, OA.wetted_radius)
+
+    def J(P2):
+        return S.observables(P2, S.run(P2, st0, N))["wetted_radius"]
+
+    th0 = math.radians(P.theta_bottom_deg)
+    for a, (x0, mk) in enumerate((
+            (th0, lambda x: dataclasses.replace(P, theta_bottom_deg=math.degrees(x))),
+            (P.pe, lambda x: dataclasses.replace(P, pe=x)),
+            (P.wi, lambda x: dataclasses.replace(P, wi=x)))):
+        e = 1e-4 * x0
+        fd = (J(mk(x0 + e)) - J(mk(x0 - e))) / (2 * e)
+        assert abs(fd - g[a]) <= 1e-7 * abs(g[a]), (a, fd, g[a])
+
+
+def test_parameter_gradients_relaxed_walls_vs_central_differences():
+    """The same check with relaxed walls (D_w = 0.5): 10 steps, d(wetted radius)/d(theta, Pe,
+    Wi) by reverse differentiation against central differences of the NumPy oracle."""
+    cfg = W.config("C4", nx=32, nz=16, cn=0.04, pe=75.0, dt=5e-3, noise=0.0, d_w=0.5)
+    P = model.Params.from_config(cfg)
+    st0 = W.droplet_state(cfg)
+    N = 10
     _, g = OA.trajectory_gradient(P, st0, N, OA.wetted_radius)
 
     def J(P2):
