@@ -109,7 +109,8 @@ typedef struct drpf_params {
                                   adjoint entry points need 2.                               */
   int advection;               /* advection of the phase field (eq. NS25) and of the polymer
                                   (eq. NS41): 0 second-order central flux form; 1 fifth-order
-                                  WENO-Z face values (Sec. 3.2.1, 3.2.3). The adjoint needs 0 */
+                                  WENO-Z face values (Sec. 3.2.1, 3.2.3). The adjoint covers
+                                  both                                                       */
   double d_w;                  /* wall relaxation D_w >= 0 of eq. NS15, discretised as eq.
                                   NS34 at both walls: the wall derivative of phi^{n+1} gains
                                   D_w (gamma0 phi^{n+1} - phi_hat) / dt at the wall-adjacent

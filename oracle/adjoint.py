@@ -178,6 +178,54 @@ def relaxed_ch_solve(rhs, s, c, d, h):
     return torch.fft.ifft2(Yc, dim=(1, 2)).real
 
 
+# ---- fifth-order WENO-Z advection (Sec. 3.2.3; oracle.weno in differentiable form) --------
+
+_WENO_EPS = 1e-40
+
+
+def _weno_face(vm2, vm1, v0, vp1, vp2):
+    """WENO-Z value at the face between v0 and vp1 from the side of v0 (oracle.weno.reconstruct
+    with torch operations; |beta_0 - beta_2| differentiates to sign(0) = 0 at a tie)."""
+    q0 = (2.0 * vm2 - 7.0 * vm1 + 11.0 * v0) / 6.0
+    q1 = (-vm1 + 5.0 * v0 + 2.0 * vp1) / 6.0
+    q2 = (2.0 * v0 + 5.0 * vp1 - vp2) / 6.0
+    b0 = 13.0 / 12.0 * (vm2 - 2.0 * vm1 + v0) ** 2 + 0.25 * (vm2 - 4.0 * vm1 + 3.0 * v0) ** 2
+    b1 = 13.0 / 12.0 * (vm1 - 2.0 * v0 + vp1) ** 2 + 0.25 * (vm1 - vp1) ** 2
+    b2 = 13.0 / 12.0 * (v0 - 2.0 * vp1 + vp2) ** 2 + 0.25 * (3.0 * v0 - 4.0 * vp1 + vp2) ** 2
+    t5 = torch.abs(b0 - b2)
+    a0 = 0.1 * (1.0 + t5 / (b0 + _WENO_EPS))
+    a1 = 0.6 * (1.0 + t5 / (b1 + _WENO_EPS))
+    a2 = 0.3 * (1.0 + t5 / (b2 + _WENO_EPS))
+    return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2)
+
+
+def _weno_shift(q, s, axis, wall):
+    """q at index i + s along `axis`: periodic, or mirrored beyond the walls."""
+    if not wall:
+        return torch.roll(q, -s, axis)
+    n = q.shape[axis]
+    idx = np.arange(n) + s
+    idx = np.where(idx < 0, -idx - 1, idx)
+    idx = np.where(idx >= n, 2 * n - 1 - idx, idx)
+    return torch.index_select(q, axis, torch.as_tensor(idx, dtype=torch.long))
+
+
+def _weno_flux(q, u, axis, wall):
+    v = {s: _weno_shift(q, s, axis, wall) for s in range(-2, 4)}
+    pos = _weno_face(v[-2], v[-1], v[0], v[1], v[2])
+    neg = _weno_face(v[3], v[2], v[1], v[0], v[-1])
+    return u * torch.where(u > 0.0, pos, neg)
+
+
+def weno_divergence(q, u, v, w, h):
+    """div(u q) with WENO-Z face values, x and y periodic, no flux through the walls."""
+    hx, hy, hz = h
+    fx = _weno_flux(q, u, 2, False)
+    fy = _weno_flux(q, v, 1, False)
+    fz = zero_top(_weno_flux(q, w, 0, True))
+    return (fx - xm(fx)) / hx + (fy - ym(fy)) / hy + (fz - zm_face(fz)) / hz
+
+
 # ---- transfers ------------------------------------------------------------------------
 
 def prolong(u, v, w, ry):
@@ -260,11 +308,9 @@ def constants(P: Params, first, pe):
 
 def step(P: Params, st, theta, pe, wi):
     """One coupled step on tensors; st holds lists of tensors like the NumPy oracle state."""
-    if (P.advection != 0 or P.constitutive != 0 or P.giesekus_alpha != 0.0 or P.refine != 2
-            or P.moving_walls):
+    if P.constitutive != 0 or P.giesekus_alpha != 0.0 or P.refine != 2 or P.moving_walls:
         raise NotImplementedError("the differentiable step covers the dual-resolution step with "
-                                  "walls at rest, central advection and the Oldroyd-B stress "
-                                  "form")
+                                  "walls at rest and the Oldroyd-B stress form")
     first = st["step"] == 0
     C = constants(P, first, pe)
     hf, h = P.hf, P.h
@@ -275,10 +321,13 @@ def step(P: Params, st, theta, pe, wi):
     vs = _levels(st["v"], first)[0]
     ws = _levels(st["w"], first)[0]
     uf, vf, wf = prolong(us, vs, ws, P.ry)
-    fx = uf * 0.5 * (phis + xp(phis))
-    fy = vf * 0.5 * (phis + yp(phis))
-    fz = zero_top(wf * 0.5 * (phis + zp_neu(phis)))
-    A = (fx - xm(fx)) / hf[0] + (fy - ym(fy)) / hf[1] + (fz - zm_face(fz)) / hf[2]
+    if P.advection == 1:
+        A = weno_divergence(phis, uf, vf, wf, hf)
+    else:
+        fx = uf * 0.5 * (phis + xp(phis))
+        fy = vf * 0.5 * (phis + yp(phis))
+        fz = zero_top(wf * 0.5 * (phis + zp_neu(phis)))
+        A = (fx - xm(fx)) / hf[0] + (fy - ym(fy)) / hf[1] + (fz - zm_face(fz)) / hf[2]
     fstar = (phis ** 3 - phis) / cn2
     Q = (pe / cn2) * (phih / P.dt - A) + lap_neumann(fstar - (C["S"] / cn2) * phis, hf)
     nzf = phis.shape[0]
@@ -457,10 +506,13 @@ def polymer_rhs(P, tau, u, v, w, L, wi):
     out = []
     for a, b in ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)):
         t = tau[_PAIRS[(a, b)]]
-        fx = u * 0.5 * (t + xp(t))
-        fy = v * 0.5 * (t + yp(t))
-        fz = zero_top(w * 0.5 * (t + zp_neu(t)))
-        rh = -((fx - xm(fx)) / hx + (fy - ym(fy)) / hy + (fz - zm_face(fz)) / hz)
+        if P.advection == 1:
+            rh = -weno_divergence(t, u, v, w, P.h)
+        else:
+            fx = u * 0.5 * (t + xp(t))
+            fy = v * 0.5 * (t + yp(t))
+            fz = zero_top(w * 0.5 * (t + zp_neu(t)))
+            rh = -((fx - xm(fx)) / hx + (fy - ym(fy)) / hy + (fz - zm_face(fz)) / hz)
         for c in range(3):
             rh = rh + L[c][a] * tau[_PAIRS[(c, b)]] + tau[_PAIRS[(a, c)]] * L[c][b]
         rh = rh + ((1.0 - P.beta) * (L[a][b] + L[b][a]) - t) / wi

@@ -27,6 +27,7 @@
 // difference with odd ghosts uses even ghosts and the reverse.
 #include "coarse.hpp"
 #include "fine.hpp"
+#include "weno.hpp"
 
 namespace drpf {
 
@@ -68,10 +69,112 @@ __device__ __forceinline__ void cell_index(int& k, int& j, int& i) {
   k = bz;
 }
 
+// ---- WENO-Z advection transposed (advection 1, Sec. 3.2.3) ---------------------------------
+// The face value of weno_face (stencil v[0..4] = the five upwind cells, the face between v[2]
+// and v[3]) and its gradient g = d value / d v. value = sum a_k q_k / sum a_k, so
+// d value = sum (a_k dq_k + (q_k - value) da_k) / sum a_k, da_k = d_k (dt5 / (b_k + eps) -
+// t5 db_k / (b_k + eps)^2), t5 = |b_0 - b_2| with dt5 = sign(b_0 - b_2)(db_0 - db_2), taken as
+// 0 at a tie (the subgradient of |x| at 0 that reverse-mode differentiation takes).
+__device__ D weno_face_grad(const D v[5], D g[5]) {
+  const D eps = 1e-40;
+  const D a = v[0], b = v[1], c = v[2], d = v[3], e = v[4];
+  const D q[3] = {(2 * a - 7 * b + 11 * c) / 6, (-b + 5 * c + 2 * d) / 6, (2 * c + 5 * d - e) / 6};
+  const D dq[3][5] = {{2.0 / 6, -7.0 / 6, 11.0 / 6, 0, 0}, {0, -1.0 / 6, 5.0 / 6, 2.0 / 6, 0}, {0, 0, 2.0 / 6, 5.0 / 6, -1.0 / 6}};
+  const D s0 = a - 2 * b + c, r0 = a - 4 * b + 3 * c;
+  const D s1 = b - 2 * c + d, r1 = b - d;
+  const D s2 = c - 2 * d + e, r2 = 3 * c - 4 * d + e;
+  const D c13 = 13.0 / 12.0;
+  const D bt[3] = {c13 * s0 * s0 + 0.25 * r0 * r0, c13 * s1 * s1 + 0.25 * r1 * r1, c13 * s2 * s2 + 0.25 * r2 * r2};
+  // d beta_k / d v: 13/6 s_k (second-difference row) + 1/2 r_k (one-sided row)
+  const D db[3][5] = {{2 * c13 * s0 + 0.5 * r0, -4 * c13 * s0 - 2.0 * r0, 2 * c13 * s0 + 1.5 * r0, 0, 0},
+                      {0, 2 * c13 * s1 + 0.5 * r1, -4 * c13 * s1, 2 * c13 * s1 - 0.5 * r1, 0},
+                      {0, 0, 2 * c13 * s2 + 1.5 * r2, -4 * c13 * s2 - 2.0 * r2, 2 * c13 * s2 + 0.5 * r2}};
+  const D dk[3] = {0.1, 0.6, 0.3};
+  const D diff = bt[0] - bt[2];
+  const D t5 = fabs(diff), sg = diff > 0 ? 1.0 : (diff < 0 ? -1.0 : 0.0);
+  D w[3], al[3], S = 0, num = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    w[k] = 1.0 / (bt[k] + eps);
+    al[k] = dk[k] * (1.0 + t5 * w[k]);
+    S += al[k];
+    num += al[k] * q[k];
+  }
+  const D val = num / S;
+#pragma unroll
+  for (int p = 0; p < 5; ++p) {
+    const D dt5 = sg * (db[0][p] - db[2][p]);
+    D acc = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const D dal = dk[k] * (dt5 * w[k] - t5 * w[k] * w[k] * db[k][p]);
+      acc += al[k] * dq[k][p] + (q[k] - val) * dal;
+    }
+    g[p] = acc / S;
+  }
+  return val;
+}
+
+// The five stencil cells, in weno_face's order, of the face between cells f and f + 1 along an
+// axis of n cells: from cell f's side for a positive face velocity, from f + 1's otherwise;
+// periodic (PER) or mirrored beyond the walls
+template <bool PER>
+__device__ __forceinline__ void weno_cells(int f, int n, bool pos, int c[5]) {
+#pragma unroll
+  for (int p = 0; p < 5; ++p) {
+    const int cc = pos ? f - 2 + p : f + 3 - p;
+    c[p] = PER ? wrap(cc, n) : mirror_index(cc, n);
+  }
+}
+
+// Transposed WENO-Z flux divergence along one axis, gathered at cell j: the sum over the faces
+// f (between cells f and f + 1) whose upwind stencil holds cell j of lF(f) u(f) d(face
+// value)/d(q_j). Periodic axes (n a power of two) visit each face once also when n < 6; on a
+// walled axis only the faces 0 .. n - 2 carry flux. q(c), u(f), lF(f) take in-range indices.
+template <bool PER, typename Q, typename U, typename LF>
+__device__ D weno_adj_axis(int j, int n, Q&& q, U&& u, LF&& lF) {
+  D s = 0;
+  const int nf = PER && n < 6 ? n : 6;
+  for (int o = 0; o < nf; ++o) {
+    int f = j - 3 + o;
+    if (PER)
+      f = wrap(f, n);
+    else if (f < 0 || f > n - 2)
+      continue;
+    const D uf = u(f);
+    int c[5];
+    weno_cells<PER>(f, n, uf > 0.0, c);
+    bool hit = false;
+#pragma unroll
+    for (int p = 0; p < 5; ++p) hit = hit || c[p] == j;
+    if (!hit) continue;
+    D v[5], g[5];
+#pragma unroll
+    for (int p = 0; p < 5; ++p) v[p] = q(c[p]);
+    weno_face_grad(v, g);
+    D acc = 0;
+#pragma unroll
+    for (int p = 0; p < 5; ++p) acc += c[p] == j ? g[p] : 0.0;
+    s += lF(f) * uf * acc;
+  }
+  return s;
+}
+
+// WENO-Z value at the face between cells f and f + 1 (upwind side by the face velocity uf)
+template <bool PER, typename Q>
+__device__ __forceinline__ D weno_value(int f, int n, D uf, Q&& q) {
+  int c[5];
+  weno_cells<PER>(f, n, uf > 0.0, c);
+  return weno_face<D>(q(c[0]), q(c[1]), q(c[2]), q(c[3]), q(c[4]));
+}
+
 // Transposed stress right-hand side for fixed velocity: out = (d RH / d tau)^T g, per cell.
-// Advection -div(u tau) with face-mean stress and zero wall flux; upper-convected coupling
-// L_ca tau_cb + tau_ac L_cb; relaxation -tau / Wi.
-__device__ __forceinline__ void rh_tau_T(const Six& g, int k, int j, int i, int nx, int ny, int nz,
+// Advection -div(u tau) with face-mean stress (or, WENO, the WENO-Z face value of the stage's
+// input stress tq, which the transpose depends on) and zero wall flux; upper-convected
+// coupling L_ca tau_cb + tau_ac L_cb; relaxation -tau / Wi.
+template <bool WENO>
+__device__ __forceinline__ void rh_tau_T(const Six& g, const Six& tq, int k, int j, int i, int nx, int ny,
+                                         int nz, const Coarse<D>& U, const Coarse<D>& V, const Coarse<D>& W,
                                          D uxp, D uxm, D vyp, D vym, D wzp, D wzm, D ihx, D ihy, D ihz,
                                          D inv_wi, const D L[3][3], const D gc[6], D out[6]) {
   const D h = 0.5;
@@ -79,11 +182,26 @@ __device__ __forceinline__ void rh_tau_T(const Six& g, int k, int j, int i, int 
   for (int m = 0; m < 6; ++m) {
     const Coarse<D> G{g.p[m], nx, ny, nz};
     const D g0 = gc[m];
-    const D gzp = k < nz - 1 ? G.at(k + 1, j, i) : 0.0;
-    const D gzm = k > 0 ? G.at(k - 1, j, i) : 0.0;
-    const D adv = (h * uxp * (G.at(k, j, i + 1) - g0) + h * uxm * (g0 - G.at(k, j, i - 1))) * ihx +
-                  (h * vyp * (G.at(k, j + 1, i) - g0) + h * vym * (g0 - G.at(k, j - 1, i))) * ihy +
-                  (h * wzp * (gzp - g0) + h * wzm * (g0 - gzm)) * ihz;
+    D adv;
+    if (!WENO) {
+      const D gzp = k < nz - 1 ? G.at(k + 1, j, i) : 0.0;
+      const D gzm = k > 0 ? G.at(k - 1, j, i) : 0.0;
+      adv = (h * uxp * (G.at(k, j, i + 1) - g0) + h * uxm * (g0 - G.at(k, j, i - 1))) * ihx +
+            (h * vyp * (G.at(k, j + 1, i) - g0) + h * vym * (g0 - G.at(k, j - 1, i))) * ihy +
+            (h * wzp * (gzp - g0) + h * wzm * (g0 - gzm)) * ihz;
+    } else {
+      // RH = -div(F): the face between cells f and f + 1 carries (g_{f+1} - g_f) / h
+      const Coarse<D> Q{tq.p[m], nx, ny, nz};
+      adv = weno_adj_axis<true>(
+          i, nx, [&](int c) { return Q.at(k, j, c); }, [&](int f) { return U.at(k, j, f); },
+          [&](int f) { return (G.at(k, j, f + 1) - G.at(k, j, f)) * ihx; });
+      adv += weno_adj_axis<true>(
+          j, ny, [&](int c) { return Q.at(k, c, i); }, [&](int f) { return V.at(k, f, i); },
+          [&](int f) { return (G.at(k, f + 1, i) - G.at(k, f, i)) * ihy; });
+      adv += weno_adj_axis<false>(
+          k, nz, [&](int c) { return Q.at(c, j, i); }, [&](int f) { return W.at(f, j, i); },
+          [&](int f) { return (G.at(f + 1, j, i) - G.at(f, j, i)) * ihz; });
+    }
     out[m] = adv - g0 * inv_wi;
   }
   const int pairs[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
@@ -118,6 +236,7 @@ struct PolyArgs {
 };
 
 // ---- polymer, second stage: lt1 = 0.5 lam + 0.5 dt RH_tau^T lam ----------------------------
+template <bool WENO>
 __global__ void __launch_bounds__(kBlock)
     k_adj_polymer_s2(PolyArgs a, Six lam, Six t1, SixOut lt1, D* part) {
   int k, j, i;
@@ -135,7 +254,8 @@ __global__ void __launch_bounds__(kBlock)
     gc[m] = lam.p[m][id];
     tc[m] = t1.p[m][id];
   }
-  rh_tau_T(lam, k, j, i, nx, ny, nz, uxp, uxm, vyp, vym, wzp, wzm, a.ihx, a.ihy, a.ihz, a.inv_wi, L, gc, out);
+  rh_tau_T<WENO>(lam, t1, k, j, i, nx, ny, nz, U, V, W, uxp, uxm, vyp, vym, wzp, wzm, a.ihx, a.ihy, a.ihz,
+                 a.inv_wi, L, gc, out);
 #pragma unroll
   for (int m = 0; m < 6; ++m) lt1.p[m][id] = 0.5 * gc[m] + 0.5 * a.dt * out[m];
   block_partial(0.5 * a.dt * wi_term(gc, tc, L, a.omb) * a.inv_wi * a.inv_wi, part);
@@ -143,6 +263,7 @@ __global__ void __launch_bounds__(kBlock)
 
 // ---- polymer, first stage: lam_tau^n += 0.5 lam + lt1 + dt RH_tau^T lt1; velocity-gradient
 // adjoint of both stages ----------------------------------------------------------------------
+template <bool WENO>
 __global__ void __launch_bounds__(kBlock)
     k_adj_polymer_s1(PolyArgs a, Six lam, Six lt1, Six tn, Six t1, SixOut out_tau0, Nine lL, D* part) {
   int k, j, i;
@@ -162,7 +283,8 @@ __global__ void __launch_bounds__(kBlock)
     tnc[m] = tn.p[m][id];
     t1c[m] = t1.p[m][id];
   }
-  rh_tau_T(lt1, k, j, i, nx, ny, nz, uxp, uxm, vyp, vym, wzp, wzm, a.ihx, a.ihy, a.ihz, a.inv_wi, L, gc, out);
+  rh_tau_T<WENO>(lt1, tn, k, j, i, nx, ny, nz, U, V, W, uxp, uxm, vyp, vym, wzp, wzm, a.ihx, a.ihy, a.ihz,
+                 a.inv_wi, L, gc, out);
 #pragma unroll
   for (int m = 0; m < 6; ++m) out_tau0.p[m][id] += 0.5 * lc[m] + gc[m] + a.dt * out[m];
   // adjoint of L from both stages: weights 0.5 dt (lam with t1) and dt (lt1 with tau^n)
@@ -194,6 +316,7 @@ __global__ void __launch_bounds__(kBlock)
 
 // ---- polymer, velocity adjoint: lam_u^{n+1} plus the transposed velocity gradient and the
 // advecting-velocity part of both stages -----------------------------------------------------
+template <bool WENO>
 __global__ void __launch_bounds__(kBlock)
     k_adj_polymer_vel(PolyArgs a, const D* __restrict__ lu_in, const D* __restrict__ lv_in,
                       const D* __restrict__ lw_in, Six lam, Six lt1, Six tn, Six t1, Nine lL,
@@ -206,14 +329,37 @@ __global__ void __launch_bounds__(kBlock)
   auto LL = [&](int c, int kk, int jj, int ii) -> D {
     return lL.p[c][(min(max(kk, 0), nz - 1) * ny + wrap(jj, ny)) * nx + wrap(ii, nx)];
   };
-  auto adv = [&](int i0, int j0, int k0, int i1, int j1, int k1) -> D {
+  // the advecting-velocity part at the face between cells p0 and p1 (along axis ax: 0 x, 1 y,
+  // 2 z): the face value of each stage's input stress times the jump of that stage's adjoint
+  const Coarse<D> Uc{a.u, nx, ny, nz}, Vc{a.v, nx, ny, nz}, Wc{a.w, nx, ny, nz};
+  auto adv = [&](int i0, int j0, int k0, int i1, int j1, int k1, int ax) -> D {
     const int p0 = (k0 * ny + wrap(j0, ny)) * nx + wrap(i0, nx);
     const int p1 = (k1 * ny + wrap(j1, ny)) * nx + wrap(i1, nx);
     D s = 0;
 #pragma unroll
-    for (int m = 0; m < 6; ++m)
-      s += 0.5 * a.dt * h * (t1.p[m][p0] + t1.p[m][p1]) * (lam.p[m][p1] - lam.p[m][p0]) +
-           a.dt * h * (tn.p[m][p0] + tn.p[m][p1]) * (lt1.p[m][p1] - lt1.p[m][p0]);
+    for (int m = 0; m < 6; ++m) {
+      D f1, fn;
+      if (!WENO) {
+        f1 = h * (t1.p[m][p0] + t1.p[m][p1]);
+        fn = h * (tn.p[m][p0] + tn.p[m][p1]);
+      } else {
+        const Coarse<D> T1{t1.p[m], nx, ny, nz}, TN{tn.p[m], nx, ny, nz};
+        if (ax == 0) {
+          const D uf = Uc.at(k0, j0, i0);
+          f1 = weno_value<true>(wrap(i0, nx), nx, uf, [&](int c) { return T1.at(k0, j0, c); });
+          fn = weno_value<true>(wrap(i0, nx), nx, uf, [&](int c) { return TN.at(k0, j0, c); });
+        } else if (ax == 1) {
+          const D uf = Vc.at(k0, j0, i0);
+          f1 = weno_value<true>(wrap(j0, ny), ny, uf, [&](int c) { return T1.at(k0, c, i0); });
+          fn = weno_value<true>(wrap(j0, ny), ny, uf, [&](int c) { return TN.at(k0, c, i0); });
+        } else {
+          const D uf = Wc.at(k0, j0, i0);
+          f1 = weno_value<false>(k0, nz, uf, [&](int c) { return T1.at(c, j0, i0); });
+          fn = weno_value<false>(k0, nz, uf, [&](int c) { return TN.at(c, j0, i0); });
+        }
+      }
+      s += 0.5 * a.dt * f1 * (lam.p[m][p1] - lam.p[m][p0]) + a.dt * fn * (lt1.p[m][p1] - lt1.p[m][p0]);
+    }
     return s;
   };
   // u face (between cells i and i+1)
@@ -222,7 +368,7 @@ __global__ void __launch_bounds__(kBlock)
       return (LL(3, k, j - 1, c) - LL(3, k, j + 1, c)) * h * a.ihy + (LL(6, k - 1, j, c) - LL(6, k + 1, j, c)) * h * a.ihz;
     };
     lu[id] = lu_in[id] + (LL(0, k, j, i) - LL(0, k, j, i + 1)) * a.ihx + h * (cu(i) + cu(i + 1)) +
-             adv(i, j, k, i + 1, j, k) * a.ihx;
+             adv(i, j, k, i + 1, j, k, 0) * a.ihx;
   }
   // v face (between cells j and j+1)
   {
@@ -230,7 +376,7 @@ __global__ void __launch_bounds__(kBlock)
       return (LL(1, k, c, i - 1) - LL(1, k, c, i + 1)) * h * a.ihx + (LL(7, k - 1, c, i) - LL(7, k + 1, c, i)) * h * a.ihz;
     };
     lv[id] = lv_in[id] + (LL(4, k, j, i) - LL(4, k, j + 1, i)) * a.ihy + h * (cv(j) + cv(j + 1)) +
-             adv(i, j, k, i, j + 1, k) * a.ihy;
+             adv(i, j, k, i, j + 1, k, 1) * a.ihy;
   }
   // w face (between layers k and k+1); the top wall carries no unknown
   if (k < nz - 1) {
@@ -238,7 +384,7 @@ __global__ void __launch_bounds__(kBlock)
       return (LL(2, c, j, i - 1) - LL(2, c, j, i + 1)) * h * a.ihx + (LL(5, c, j - 1, i) - LL(5, c, j + 1, i)) * h * a.ihy;
     };
     lw[id] = lw_in[id] + (LL(8, k, j, i) - LL(8, k + 1, j, i)) * a.ihz + h * (cw(k) + cw(k + 1)) +
-             adv(i, j, k, i, j, k + 1) * a.ihz;
+             adv(i, j, k, i, j, k + 1, 2) * a.ihz;
   } else {
     lw[id] = 0.0;
   }
@@ -695,6 +841,7 @@ struct ChAdjIn {
   Prolonged<D> pv;
 };
 
+template <bool WENO>
 __global__ void __launch_bounds__(kBlock)
     k_adj_ch(ChAdjIn a, D* __restrict__ lphi_n, D* __restrict__ lphi_nm1, int fnx, int fny, int fnz,
              D fihx, D fihy, D fihz, StepConsts c, D sin_bot, D* part_theta, D* part_pe) {
@@ -745,12 +892,33 @@ __global__ void __launch_bounds__(kBlock)
   const D ufp = a.pv.uf(K, J, I), ufm = a.pv.uf(K, J, Im);
   const D vfp = a.pv.vf(K, J, I), vfm = a.pv.vf(K, Jm, I);
   const D wfp = a.pv.wf(K, J, I), wfm = a.pv.wf(K - 1, J, I);
-  lphis += h * (lfx(I) * ufp + lfx(I - 1) * ufm) + h * (lfy(J) * vfp + lfy(J - 1) * vfm) +
-           h * (lfz(K) * wfp + lfz(K - 1) * wfm);
-  // forward advection at this cell, for the Pe-derivative of Q
-  const D A = (ufp * h * (p0 + ps(K, J, I + 1)) - ufm * h * (ps(K, J, I - 1) + p0)) * fihx +
-              (vfp * h * (p0 + ps(K, J + 1, I)) - vfm * h * (ps(K, J - 1, I) + p0)) * fihy +
-              (wfp * h * (p0 + ps(K + 1, J, I)) - wfm * h * (ps(K - 1, J, I) + p0)) * fihz;
+  D A;  // forward advection at this cell, for the Pe-derivative of Q
+  if (!WENO) {
+    lphis += h * (lfx(I) * ufp + lfx(I - 1) * ufm) + h * (lfy(J) * vfp + lfy(J - 1) * vfm) +
+             h * (lfz(K) * wfp + lfz(K - 1) * wfm);
+    A = (ufp * h * (p0 + ps(K, J, I + 1)) - ufm * h * (ps(K, J, I - 1) + p0)) * fihx +
+        (vfp * h * (p0 + ps(K, J + 1, I)) - vfm * h * (ps(K, J - 1, I) + p0)) * fihy +
+        (wfp * h * (p0 + ps(K + 1, J, I)) - wfm * h * (ps(K - 1, J, I) + p0)) * fihz;
+  } else {
+    // WENO-Z face values: every face whose upwind stencil holds this cell
+    lphis += weno_adj_axis<true>(
+        I, fnx, [&](int c) { return ps(K, J, c); }, [&](int f) { return a.pv.uf(K, J, f); },
+        [&](int f) { return lfx(f); });
+    lphis += weno_adj_axis<true>(
+        J, fny, [&](int c) { return ps(K, c, I); }, [&](int f) { return a.pv.vf(K, f, I); },
+        [&](int f) { return lfy(f); });
+    lphis += weno_adj_axis<false>(
+        K, fnz, [&](int c) { return ps(c, J, I); }, [&](int f) { return a.pv.wf(f, J, I); },
+        [&](int f) { return lfz(f); });
+    auto vx = [&](int c) { return ps(K, J, c); };
+    auto vy = [&](int c) { return ps(K, c, I); };
+    auto vz = [&](int c) { return ps(c, J, I); };
+    const D fzp = K < fnz - 1 ? wfp * weno_value<false>(K, fnz, wfp, vz) : 0.0;
+    const D fzm = K > 0 ? wfm * weno_value<false>(K - 1, fnz, wfm, vz) : 0.0;
+    A = (ufp * weno_value<true>(I, fnx, ufp, vx) - ufm * weno_value<true>(Im, fnx, ufm, vx)) * fihx +
+        (vfp * weno_value<true>(J, fny, vfp, vy) - vfm * weno_value<true>(Jm, fny, vfm, vy)) * fihy +
+        (fzp - fzm) * fihz;
+  }
   // dJ/dPe: Q carries Pe explicitly and through S (S ~ sqrt(Pe)); the solve operator
   // D = L^2 - (S/Cn^2) L + gamma0 Pe/(dt Cn^2) and G carry it through S. Grouped so that the
   // O(1/dt) parts cancel pointwise.
@@ -764,6 +932,7 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---- prolongation transposed (eq. dual1): fine face adjoints gathered onto coarse faces -----
+template <bool WENO>
 __global__ void __launch_bounds__(kBlock)
     k_adj_prolong(ChAdjIn a, VelOut o, int cnx, int cny, int cnz, int fnx, int fny, int fnz,
                   D fihx, D fihy, D fihz, int ry, StepConsts c) {
@@ -778,16 +947,25 @@ __global__ void __launch_bounds__(kBlock)
     const int p = fidx(min(max(kk, 0), fnz - 1), jj, ii);
     return first ? a.phin[p] : 2.0 * a.phin[p] - a.phinm1[p];
   };
-  // adjoint of the fine face velocities: flux adjoint times the face mean of phi*
+  // adjoint of the fine face velocities: flux adjoint times the face value of phi* (the face
+  // mean, or the WENO-Z value from the side the face velocity picks)
   auto Lx = [&](int K, int J, int I) {
-    return (lA(K, J, I) - lA(K, J, I + 1)) * fihx * h * (ps(K, J, I) + ps(K, J, I + 1));
+    I = wrap(I, fnx);
+    const D fv = WENO ? weno_value<true>(I, fnx, a.pv.uf(K, J, I), [&](int c) { return ps(K, J, c); })
+                      : h * (ps(K, J, I) + ps(K, J, I + 1));
+    return (lA(K, J, I) - lA(K, J, I + 1)) * fihx * fv;
   };
   auto Ly = [&](int K, int J, int I) {
-    return (lA(K, J, I) - lA(K, J + 1, I)) * fihy * h * (ps(K, J, I) + ps(K, J + 1, I));
+    J = wrap(J, fny);
+    const D fv = WENO ? weno_value<true>(J, fny, a.pv.vf(K, J, I), [&](int c) { return ps(K, c, I); })
+                      : h * (ps(K, J, I) + ps(K, J + 1, I));
+    return (lA(K, J, I) - lA(K, J + 1, I)) * fihy * fv;
   };
   auto Lz = [&](int K, int J, int I) -> D {
     if (K < 0 || K >= fnz - 1) return 0.0;
-    return (lA(K, J, I) - lA(K + 1, J, I)) * fihz * h * (ps(K, J, I) + ps(K + 1, J, I));
+    const D fv = WENO ? weno_value<false>(K, fnz, a.pv.wf(K, J, I), [&](int c) { return ps(c, J, I); })
+                      : h * (ps(K, J, I) + ps(K + 1, J, I));
+    return (lA(K, J, I) - lA(K + 1, J, I)) * fihz * fv;
   };
   D su = 0, sv = 0, sw = 0;
   for (int dz = 0; dz < 2; ++dz) {
@@ -881,10 +1059,13 @@ hipError_t launch_adj_polymer(const Dims& c, const StepConsts& k, const double* 
   for (int m = 0; m < 9; ++m) nl.p[m] = lL[m];
   const Launch3 L = launch3(c.nx, c.ny, c.nz);
   const int nb = adj_blocks(c.nx, c.ny, c.nz);
-  hipLaunchKernelGGL(k_adj_polymer_s2, L.grid, L.block, 0, st, a, lam, t1, lo, part);
-  hipLaunchKernelGGL(k_adj_polymer_s1, L.grid, L.block, 0, st, a, lam, l1, tn, t1, ot, nl, part + nb);
-  hipLaunchKernelGGL(k_adj_polymer_vel, L.grid, L.block, 0, st, a, lu_in, lv_in, lw_in, lam, l1, tn, t1, nl, lu,
-                     lv, lw);
+  const bool weno = k.advection == 1;
+  hipLaunchKernelGGL(weno ? k_adj_polymer_s2<true> : k_adj_polymer_s2<false>, L.grid, L.block, 0, st, a, lam, t1,
+                     lo, part);
+  hipLaunchKernelGGL(weno ? k_adj_polymer_s1<true> : k_adj_polymer_s1<false>, L.grid, L.block, 0, st, a, lam, l1,
+                     tn, t1, ot, nl, part + nb);
+  hipLaunchKernelGGL(weno ? k_adj_polymer_vel<true> : k_adj_polymer_vel<false>, L.grid, L.block, 0, st, a, lu_in,
+                     lv_in, lw_in, lam, l1, tn, t1, nl, lu, lv, lw);
   return hipGetLastError();
 }
 
@@ -954,12 +1135,13 @@ hipError_t launch_adj_ch(const Dims& f, const Dims& c, const StepConsts& k, cons
   const int ry = c.ny == 1 ? 1 : 2;
   ChAdjIn a{lQ, lG, phin, phinm1, phinew, {un, unm1, vn, vnm1, wn, wnm1, c.nx, c.ny, c.nz, ry, k.first}};
   const Launch3 L = launch3(f.nx, f.ny, f.nz);
-  hipLaunchKernelGGL(k_adj_ch, L.grid, L.block, 0, st, a, lphi_n, lphi_nm1, f.nx, f.ny, f.nz, f.ihx, f.ihy,
-                     f.ihz, k, sin_bot, part_theta, part_pe);
+  const bool weno = k.advection == 1;
+  hipLaunchKernelGGL(weno ? k_adj_ch<true> : k_adj_ch<false>, L.grid, L.block, 0, st, a, lphi_n, lphi_nm1, f.nx,
+                     f.ny, f.nz, f.ihx, f.ihy, f.ihz, k, sin_bot, part_theta, part_pe);
   VelOut vo{u0, u1, v0, v1, w0, w1};
   const Launch3 Lc = launch3(c.nx, c.ny, c.nz);
-  hipLaunchKernelGGL(k_adj_prolong, Lc.grid, Lc.block, 0, st, a, vo, c.nx, c.ny, c.nz, f.nx, f.ny, f.nz, f.ihx,
-                     f.ihy, f.ihz, ry, k);
+  hipLaunchKernelGGL(weno ? k_adj_prolong<true> : k_adj_prolong<false>, Lc.grid, Lc.block, 0, st, a, vo, c.nx,
+                     c.ny, c.nz, f.nx, f.ny, f.nz, f.ihx, f.ihy, f.ihz, ry, k);
   return hipGetLastError();
 }
 

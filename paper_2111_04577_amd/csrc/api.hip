@@ -1240,7 +1240,6 @@ int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes) {
   if (p->constitutive != 0 || p->giesekus_alpha != 0)
     return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
   if (p->refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
-  if (p->advection != 0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the central advection only");
   if (moving_walls(*p)) return fail(DRPF_EUNSUPPORTED, "the adjoint covers walls at rest only");
   const Dims F = fine_dims(*p);
   // the transposed fine-grid kernels index a fine field with 32-bit integers
@@ -1257,7 +1256,6 @@ int drpf_adjoint_attach(drpf_grid* g, void* d_workspace, size_t bytes) {
   if (g->p.constitutive != 0 || g->p.giesekus_alpha != 0)
     return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
   if (g->p.refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
-  if (g->p.advection != 0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the central advection only");
   if (!d_workspace) return fail(DRPF_EWORKSPACE, "null adjoint workspace");
   if (((uintptr_t)d_workspace & 255) != 0) return fail(DRPF_EWORKSPACE, "adjoint workspace must be 256-byte aligned");
   const size_t need = adj_layout(g->F, g->C).total;
@@ -1274,7 +1272,6 @@ int drpf_adjoint_step(drpf_grid* g, const drpf_state* x, const drpf_state* x_nex
   if (g->p.constitutive != 0 || g->p.giesekus_alpha != 0)
     return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
   if (g->p.refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
-  if (g->p.advection != 0) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the central advection only");
   if (!g->aws) return fail(DRPF_EINVAL, "no adjoint workspace attached");
   if (!x->phi[0] || !x->phi[1] || !x->u[0] || !x->u[1] || !x->v[0] || !x->v[1] || !x->w[0] || !x->w[1] ||
       !x->p[0] || !x->p[1])

@@ -108,7 +108,7 @@ def test_validation_advection_scheme():
         assert L.drpf_validate(ctypes.byref(p)) == rc, a
     nb = ctypes.c_size_t()
     p = _params(advection=1)
-    assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_EUNSUPPORTED
+    assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_OK and nb.value > 0
 
 
 def test_validation_wall_relaxation():
