@@ -327,7 +327,8 @@ typedef struct drpf_adj {
 
 /* Bytes of the second device workspace the adjoint needs (forward intermediates of the
  * recomputed step and the adjoint stage buffers). DRPF_EUNSUPPORTED unless precision 64 and
- * the polymer update is the Oldroyd-B stress form (constitutive 0, giesekus_alpha 0). */
+ * the polymer update is the stress form (constitutive 0: Oldroyd-B, or Giesekus with
+ * giesekus_alpha > 0). */
 int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes);
 
 /* Hands the grid that workspace (device memory, 256-byte aligned, at least the size above;

@@ -308,9 +308,9 @@ def constants(P: Params, first, pe):
 
 def step(P: Params, st, theta, pe, wi):
     """One coupled step on tensors; st holds lists of tensors like the NumPy oracle state."""
-    if P.constitutive != 0 or P.giesekus_alpha != 0.0 or P.refine != 2 or P.moving_walls:
+    if P.constitutive != 0 or P.refine != 2 or P.moving_walls:
         raise NotImplementedError("the differentiable step covers the dual-resolution step with "
-                                  "walls at rest and the Oldroyd-B stress form")
+                                  "walls at rest and the stress form (Oldroyd-B or Giesekus)")
     first = st["step"] == 0
     C = constants(P, first, pe)
     hf, h = P.hf, P.h
@@ -516,6 +516,10 @@ def polymer_rhs(P, tau, u, v, w, L, wi):
         for c in range(3):
             rh = rh + L[c][a] * tau[_PAIRS[(c, b)]] + tau[_PAIRS[(a, c)]] * L[c][b]
         rh = rh + ((1.0 - P.beta) * (L[a][b] + L[b][a]) - t) / wi
+        if P.giesekus_alpha != 0.0:
+            # Giesekus (eq. NS4 with alpha > 0): -alpha / (1 - beta) tau.tau
+            tt = sum(tau[_PAIRS[(a, c)]] * tau[_PAIRS[(c, b)]] for c in range(3))
+            rh = rh - P.giesekus_alpha / (1.0 - P.beta) * tt
         out.append(rh)
     return out
 

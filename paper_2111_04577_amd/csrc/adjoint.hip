@@ -171,12 +171,14 @@ __device__ __forceinline__ D weno_value(int f, int n, D uf, Q&& q) {
 // Transposed stress right-hand side for fixed velocity: out = (d RH / d tau)^T g, per cell.
 // Advection -div(u tau) with face-mean stress (or, WENO, the WENO-Z face value of the stage's
 // input stress tq, which the transpose depends on) and zero wall flux; upper-convected
-// coupling L_ca tau_cb + tau_ac L_cb; relaxation -tau / Wi.
+// coupling L_ca tau_cb + tau_ac L_cb; relaxation -tau / Wi; the Giesekus term -gk tau.tau
+// (tqc: the cell's input stress).
 template <bool WENO>
 __device__ __forceinline__ void rh_tau_T(const Six& g, const Six& tq, int k, int j, int i, int nx, int ny,
                                          int nz, const Coarse<D>& U, const Coarse<D>& V, const Coarse<D>& W,
                                          D uxp, D uxm, D vyp, D vym, D wzp, D wzm, D ihx, D ihy, D ihz,
-                                         D inv_wi, const D L[3][3], const D gc[6], D out[6]) {
+                                         D inv_wi, const D L[3][3], const D gc[6], const D tqc[6], D gk,
+                                         D out[6]) {
   const D h = 0.5;
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
@@ -212,6 +214,9 @@ __device__ __forceinline__ void rh_tau_T(const Six& g, const Six& tq, int k, int
     for (int c = 0; c < 3; ++c) {
       out[tidx(c, b)] += L[c][a] * gc[m];
       out[tidx(a, c)] += L[c][b] * gc[m];
+      // (tau.tau)_ab = sum_c tau_ac tau_cb
+      out[tidx(a, c)] -= gk * gc[m] * tqc[tidx(c, b)];
+      out[tidx(c, b)] -= gk * gc[m] * tqc[tidx(a, c)];
     }
   }
 }
@@ -233,6 +238,7 @@ struct PolyArgs {
   const D *u, *v, *w;  // u^{n+1}
   int nx, ny, nz;
   D ihx, ihy, ihz, dt, inv_wi, omb;
+  D gk;  // Giesekus: alpha / (1 - beta), 0 for Oldroyd-B
 };
 
 // ---- polymer, second stage: lt1 = 0.5 lam + 0.5 dt RH_tau^T lam ----------------------------
@@ -255,7 +261,7 @@ __global__ void __launch_bounds__(kBlock)
     tc[m] = t1.p[m][id];
   }
   rh_tau_T<WENO>(lam, t1, k, j, i, nx, ny, nz, U, V, W, uxp, uxm, vyp, vym, wzp, wzm, a.ihx, a.ihy, a.ihz,
-                 a.inv_wi, L, gc, out);
+                 a.inv_wi, L, gc, tc, a.gk, out);
 #pragma unroll
   for (int m = 0; m < 6; ++m) lt1.p[m][id] = 0.5 * gc[m] + 0.5 * a.dt * out[m];
   block_partial(0.5 * a.dt * wi_term(gc, tc, L, a.omb) * a.inv_wi * a.inv_wi, part);
@@ -284,7 +290,7 @@ __global__ void __launch_bounds__(kBlock)
     t1c[m] = t1.p[m][id];
   }
   rh_tau_T<WENO>(lt1, tn, k, j, i, nx, ny, nz, U, V, W, uxp, uxm, vyp, vym, wzp, wzm, a.ihx, a.ihy, a.ihz,
-                 a.inv_wi, L, gc, out);
+                 a.inv_wi, L, gc, tnc, a.gk, out);
 #pragma unroll
   for (int m = 0; m < 6; ++m) out_tau0.p[m][id] += 0.5 * lc[m] + gc[m] + a.dt * out[m];
   // adjoint of L from both stages: weights 0.5 dt (lam with t1) and dt (lt1 with tau^n)
@@ -1044,7 +1050,8 @@ hipError_t launch_adj_polymer(const Dims& c, const StepConsts& k, const double* 
                               double* const lt1[6], double* const lL[9], double* const out_tau0[6],
                               const double* lu_in, const double* lv_in, const double* lw_in,
                               double* lu, double* lv, double* lw, double* part, hipStream_t st) {
-  PolyArgs a{u, v, w, c.nx, c.ny, c.nz, c.ihx, c.ihy, c.ihz, k.dt, k.inv_wi, 1.0 - k.beta};
+  PolyArgs a{u, v, w, c.nx, c.ny, c.nz, c.ihx, c.ihy, c.ihz, k.dt, k.inv_wi, 1.0 - k.beta,
+             k.giesekus == 0.0 ? 0.0 : k.giesekus / (1.0 - k.beta)};
   Six lam, tn, t1, l1;
   SixOut lo, ot;
   Nine nl;

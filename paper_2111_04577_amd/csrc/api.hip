@@ -1237,8 +1237,8 @@ int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes) {
   if (rc) return rc;
   if (!bytes) return fail(DRPF_EINVAL, "null output");
   if (p->precision != 64) return fail(DRPF_EUNSUPPORTED, "the adjoint runs on FP64 grids only");
-  if (p->constitutive != 0 || p->giesekus_alpha != 0)
-    return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
+  if (p->constitutive != 0)
+    return fail(DRPF_EUNSUPPORTED, "the adjoint covers the stress form only (Oldroyd-B or Giesekus)");
   if (p->refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
   if (moving_walls(*p)) return fail(DRPF_EUNSUPPORTED, "the adjoint covers walls at rest only");
   const Dims F = fine_dims(*p);
@@ -1253,8 +1253,8 @@ int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes) {
 int drpf_adjoint_attach(drpf_grid* g, void* d_workspace, size_t bytes) {
   if (!g) return fail(DRPF_EINVAL, "null grid");
   if (g->p.precision != 64) return fail(DRPF_EUNSUPPORTED, "the adjoint runs on FP64 grids only");
-  if (g->p.constitutive != 0 || g->p.giesekus_alpha != 0)
-    return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
+  if (g->p.constitutive != 0)
+    return fail(DRPF_EUNSUPPORTED, "the adjoint covers the stress form only (Oldroyd-B or Giesekus)");
   if (g->p.refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
   if (!d_workspace) return fail(DRPF_EWORKSPACE, "null adjoint workspace");
   if (((uintptr_t)d_workspace & 255) != 0) return fail(DRPF_EWORKSPACE, "adjoint workspace must be 256-byte aligned");
@@ -1269,8 +1269,8 @@ int drpf_adjoint_step(drpf_grid* g, const drpf_state* x, const drpf_state* x_nex
                       double* d_grad3, void* stream) {
   if (!g || !x || !lam || !d_grad3) return fail(DRPF_EINVAL, "null argument");
   if (g->p.precision != 64) return fail(DRPF_EUNSUPPORTED, "the adjoint runs on FP64 grids only");
-  if (g->p.constitutive != 0 || g->p.giesekus_alpha != 0)
-    return fail(DRPF_EUNSUPPORTED, "the adjoint covers the Oldroyd-B stress form only");
+  if (g->p.constitutive != 0)
+    return fail(DRPF_EUNSUPPORTED, "the adjoint covers the stress form only (Oldroyd-B or Giesekus)");
   if (g->p.refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
   if (!g->aws) return fail(DRPF_EINVAL, "no adjoint workspace attached");
   if (!x->phi[0] || !x->phi[1] || !x->u[0] || !x->u[1] || !x->v[0] || !x->v[1] || !x->w[0] || !x->w[1] ||

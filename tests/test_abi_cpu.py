@@ -81,13 +81,14 @@ def test_validation_polymer_forms():
                    (dict(ok, giesekus_alpha=0.3), B.DRPF_OK)]:
         p = _params(**kw)
         assert L.drpf_validate(ctypes.byref(p)) == rc, kw
-    # the adjoint covers the Oldroyd-B stress form only
+    # the adjoint covers the stress form (Oldroyd-B and Giesekus), not the log-conformation form
     nb = ctypes.c_size_t()
-    for kw in (dict(ok, constitutive=1), dict(ok, giesekus_alpha=0.2)):
+    for kw in (dict(ok, constitutive=1), dict(ok, constitutive=1, giesekus_alpha=0.2)):
         p = _params(**kw)
         assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_EUNSUPPORTED
-    p = _params(**ok)
-    assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_OK
+    for kw in (ok, dict(ok, giesekus_alpha=0.2)):
+        p = _params(**kw)
+        assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_OK
     # single resolution: refine 1 or 2 (0 reads as 2); no adjoint; the phase field on the flow grid
     for r, rc in ((3, B.DRPF_EINVAL), (-1, B.DRPF_EINVAL), (0, B.DRPF_OK), (1, B.DRPF_OK)):
         p = _params(refine=r)

@@ -6,8 +6,9 @@
   differences of the NumPy oracle step along seeded directions v;
 * its parameter gradients through many steps equal central differences of the NumPy oracle
   trajectory in the bottom static angle, Pe and Wi;
-* all three also with relaxed walls (D_w > 0) and with WENO-Z advection, whose NumPy steps
-  are pinned separately (test_oracle_wall_relaxation.py, test_oracle_weno.py).
+* all three also with relaxed walls (D_w > 0) and with WENO-Z advection, the first two also
+  with the Giesekus term of the stress form, whose NumPy steps are pinned separately
+  (test_oracle_wall_relaxation.py, test_oracle_weno.py, test_oracle_lcr.py).
 """
 from __future__ import annotations
 
@@ -36,6 +37,10 @@ WENO = [("C4", dict(nx=16, nz=8, noise=1e-2, advection=1)), ("C3", dict(nx=8, ny
         ("C2", dict(nx=8, ny=4, nz=8, noise=0.0, advection=1)),
         ("C3", dict(nx=8, ny=4, nz=8, noise=1e-2, advection=1, d_w=0.5))]
 WENO_IDS = ["C4-weno", "C3-weno", "C2-weno", "C3-weno-dw0.5"]
+# Giesekus in the stress form (eq. NS4 with alpha > 0): 2D and 3D, the latter with WENO-Z
+GIESEKUS = [("C4", dict(nx=16, nz=8, noise=1e-2, giesekus_alpha=0.3)),
+            ("C3", dict(nx=8, ny=4, nz=8, noise=1e-2, giesekus_alpha=0.2, advection=1))]
+GIESEKUS_IDS = ["C4-giesekus", "C3-giesekus-weno"]
 
 
 def _flat(st, ve):
@@ -45,7 +50,8 @@ def _flat(st, ve):
     return xs
 
 
-@pytest.mark.parametrize("name,kw", CASES + RELAXED + WENO, ids=[c[0] for c in CASES] + RELAXED_IDS + WENO_IDS)
+@pytest.mark.parametrize("name,kw", CASES + RELAXED + WENO + GIESEKUS,
+                         ids=[c[0] for c in CASES] + RELAXED_IDS + WENO_IDS + GIESEKUS_IDS)
 def test_differentiable_step_equals_numpy_step(name, kw):
     import torch
     cfg = W.config(name, **kw)
@@ -75,8 +81,8 @@ def _inner(a, b, ve):
     return sum(float(np.sum(x * y)) for x, y in zip(_flat(a, ve), _flat(b, ve)))
 
 
-@pytest.mark.parametrize("name,kw", CASES[:3] + RELAXED[:2] + WENO[:2] + WENO[3:],
-                         ids=[c[0] for c in CASES[:3]] + RELAXED_IDS[:2] + WENO_IDS[:2] + WENO_IDS[3:])
+@pytest.mark.parametrize("name,kw", CASES[:3] + RELAXED[:2] + WENO[:2] + WENO[3:] + GIESEKUS,
+                         ids=[c[0] for c in CASES[:3]] + RELAXED_IDS[:2] + WENO_IDS[:2] + WENO_IDS[3:] + GIESEKUS_IDS)
 def test_state_adjoint_dot_product(name, kw):
     """<lam, (step(x + e v) - step(x - e v)) / 2e> = <adjoint_step(lam), v> (NumPy step for the
     directional derivative)."""
