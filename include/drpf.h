@@ -124,7 +124,7 @@ typedef struct drpf_params {
                                   implicit velocity solves). Finite; 0 (default): walls at
                                   rest. Moving walls need d_w == 0 (DRPF_EUNSUPPORTED
                                   otherwise: eq. NS15 would gain the wall advection of phi);
-                                  the adjoint needs walls at rest                            */
+                                  the adjoint covers moving walls                            */
   int check_finite_every;      /* > 0: drpf_step checks the phase field and the velocities for
                                   NaN/Inf after every check_finite_every-th step (counted by the
                                   state's step counter), synchronising the stream there, and

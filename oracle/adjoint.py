@@ -53,6 +53,15 @@ def zm_neu(a):
     return torch.cat([a[:1], a[:-1]], 0)
 
 
+def zp_wall(a, top):
+    """a[k+1] with the no-slip ghost of eq. NS13 beyond the top wall: 2 u_w - adjacent."""
+    return torch.cat([a[1:], 2.0 * top - a[-1:]], 0)
+
+
+def zm_wall(a, bot):
+    return torch.cat([2.0 * bot - a[:1], a[:-1]], 0)
+
+
 def zp_dir(a):
     return torch.cat([a[1:], -a[-1:]], 0)
 
@@ -308,9 +317,9 @@ def constants(P: Params, first, pe):
 
 def step(P: Params, st, theta, pe, wi):
     """One coupled step on tensors; st holds lists of tensors like the NumPy oracle state."""
-    if P.constitutive != 0 or P.refine != 2 or P.moving_walls:
+    if P.constitutive != 0 or P.refine != 2 or (P.d_w > 0.0 and P.moving_walls):
         raise NotImplementedError("the differentiable step covers the dual-resolution step with "
-                                  "walls at rest and the stress form (Oldroyd-B or Giesekus)")
+                                  "the stress form (Oldroyd-B or Giesekus), relaxed walls at rest")
     first = st["step"] == 0
     C = constants(P, first, pe)
     hf, h = P.hf, P.h
@@ -378,7 +387,10 @@ def step(P: Params, st, theta, pe, wi):
         taus = [_levels([st["tau"][0][c], st["tau"][1][c]], first)[0] for c in range(6)]
         T = [0.5 * (1.0 + phic) * t for t in taus]
     zc = lambda a: torch.cat([torch.zeros_like(a[:1]), a], 0)           # w on faces -1..nz-1
-    ued = lambda a: 0.5 * (torch.cat([-a[:1], a], 0) + torch.cat([a, -a[-1:]], 0))  # z edges
+    # tangential wall velocities (eq. NS13): (bottom, top) of u and of v; 0 for walls at rest
+    uw, vw = P.walls(0), P.walls(1)
+    gh = lambda a, wv: torch.cat([2.0 * wv[0] - a[:1], a, 2.0 * wv[1] - a[-1:]], 0)  # k = -1 .. nz
+    ued = lambda a, wv: 0.5 * (gh(a, wv)[:-1] + gh(a, wv)[1:])        # z edges k = -1 .. nz-1
     jx = -C["c_j"] * (xp(Gc) - xm(Gc)) / (2 * hx)
     jy = -C["c_j"] * (yp(Gc) - ym(Gc)) / (2 * hy)
     jz = -C["c_j"] * (zp_neu(Gc) - zm_neu(Gc)) / (2 * hz)
@@ -387,41 +399,41 @@ def step(P: Params, st, theta, pe, wi):
     adv_u = (uc * uc - ucl * ucl) / hx
     f = 0.5 * (vs + xp(vs)) * 0.5 * (us + yp(us))
     adv_u = adv_u + (f - ym(f)) / hy
-    f = 0.5 * (zc(ws) + xp(zc(ws))) * ued(us)
+    f = 0.5 * (zc(ws) + xp(zc(ws))) * ued(us, uw)
     adv_u = adv_u + (f[1:] - f[:-1]) / hz
     vc, vcl = 0.5 * (vs + yp(vs)), 0.5 * (ym(vs) + vs)
     adv_v = (vc * vc - vcl * vcl) / hy
     f = 0.5 * (us + yp(us)) * 0.5 * (vs + xp(vs))
     adv_v = adv_v + (f - xm(f)) / hx
-    f = 0.5 * (zc(ws) + yp(zc(ws))) * ued(vs)
+    f = 0.5 * (zc(ws) + yp(zc(ws))) * ued(vs, vw)
     adv_v = adv_v + (f[1:] - f[:-1]) / hz
     wcu, wcl = 0.5 * (ws + zp_face(ws)), 0.5 * (zm_face(ws) + ws)
     adv_w = (wcu * wcu - wcl * wcl) / hz
-    f = 0.5 * (us + zp_dir(us)) * 0.5 * (ws + xp(ws))
+    f = 0.5 * (us + zp_wall(us, uw[1])) * 0.5 * (ws + xp(ws))
     adv_w = adv_w + (f - xm(f)) / hx
-    f = 0.5 * (vs + zp_dir(vs)) * 0.5 * (ws + yp(ws))
+    f = 0.5 * (vs + zp_wall(vs, vw[1])) * 0.5 * (ws + yp(ws))
     adv_w = adv_w + (f - ym(f)) / hy
     # J . grad u*
     fax = lambda a: 0.5 * (a + xp(a))
     fay = lambda a: 0.5 * (a + yp(a))
     faz = lambda a: 0.5 * (a + zp_neu(a))
     jgu = fax(jx) * (xp(us) - xm(us)) / (2 * hx) + fax(jy) * (yp(us) - ym(us)) / (2 * hy) \
-        + fax(jz) * (zp_dir(us) - zm_dir(us)) / (2 * hz)
+        + fax(jz) * (zp_wall(us, uw[1]) - zm_wall(us, uw[0])) / (2 * hz)
     jgv = fay(jx) * (xp(vs) - xm(vs)) / (2 * hx) + fay(jy) * (yp(vs) - ym(vs)) / (2 * hy) \
-        + fay(jz) * (zp_dir(vs) - zm_dir(vs)) / (2 * hz)
+        + fay(jz) * (zp_wall(vs, vw[1]) - zm_wall(vs, vw[0])) / (2 * hz)
     jgw = faz(jx) * (xp(ws) - xm(ws)) / (2 * hx) + faz(jy) * (yp(ws) - ym(ws)) / (2 * hy) \
         + faz(jz) * (zp_face(ws) - zm_face(ws)) / (2 * hz)
     # viscous
     vis_u = (2 * xp(mu_c) * (xp(us) - us) / hx - 2 * mu_c * (us - xm(us)) / hx) / hx
     sxy = mu_xy * ((yp(us) - us) / hy + (xp(vs) - vs) / hx)
     vis_u = vis_u + (sxy - ym(sxy)) / hy
-    ue = torch.cat([-us[:1], us, -us[-1:]], 0)
+    ue = gh(us, uw)
     we = zc(ws)
     sxz = mu_xz * ((ue[1:] - ue[:-1]) / hz + (xp(we) - we) / hx)
     vis_u = vis_u + (sxz[1:] - sxz[:-1]) / hz
     vis_v = (2 * yp(mu_c) * (yp(vs) - vs) / hy - 2 * mu_c * (vs - ym(vs)) / hy) / hy
     vis_v = vis_v + (sxy - xm(sxy)) / hx
-    ve_ = torch.cat([-vs[:1], vs, -vs[-1:]], 0)
+    ve_ = gh(vs, vw)
     syz = mu_yz * ((ve_[1:] - ve_[:-1]) / hz + (yp(we) - we) / hy)
     vis_v = vis_v + (syz[1:] - syz[:-1]) / hz
     vis_w = (2 * zp_neu(mu_c) * (zp_face(ws) - ws) / hz - 2 * mu_c * (ws - zm_face(ws)) / hz) / hz
@@ -448,7 +460,8 @@ def step(P: Params, st, theta, pe, wi):
     cap = (Gf["x"] * (xp(phic) - phic) / hx, Gf["y"] * (yp(phic) - phic) / hy,
            Gf["z"][1:] * (zp_neu(phic) - phic) / hz)
     ri = (rinv["x"], rinv["y"], rinv["z"][1:])
-    lap = (lap_dirichlet(us, h), lap_dirichlet(vs, h), lap_wface(ws, h))
+    lap_w = lambda a, wv: _lap_xy(a, h) + (zp_wall(a, wv[1]) - 2 * a + zm_wall(a, wv[0])) / hz ** 2
+    lap = (lap_w(us, uw), lap_w(vs, vw), lap_wface(ws, h))
     hats, advs, jgs = (uh, vh, wh), (adv_u, adv_v, adv_w), (jgu, jgv, jgw)
     viss, pols = (vis_u, vis_v, vis_w), (pol_u, pol_v, pol_w)
     r = []
@@ -461,8 +474,13 @@ def step(P: Params, st, theta, pe, wi):
     r[2] = zero_top(r[2])
     # ---- projection
     g = C["gamma0"] / P.dt
-    ut = helmholtz(r[0], C["nu_m"], g, "dirichlet", h)
-    vt = helmholtz(r[1], C["nu_m"], g, "dirichlet", h)
+    # moving walls: the implicit Laplacian's ghosts carry 2 u_w / hz^2 on the wall layers, a
+    # known term moved to the right-hand side
+    nzc = r[0].shape[0]
+    kz = torch.arange(nzc)
+    wb_ = lambda wv: (2.0 / hz ** 2) * (wv[0] * (kz == 0).to(TT) + wv[1] * (kz == nzc - 1).to(TT))[:, None, None]
+    ut = helmholtz(r[0] - C["nu_m"] * wb_(uw), C["nu_m"], g, "dirichlet", h)
+    vt = helmholtz(r[1] - C["nu_m"] * wb_(vw), C["nu_m"], g, "dirichlet", h)
     wt = helmholtz(r[2], C["nu_m"], g, "wface", h)
     dp = helmholtz((C["gamma0"] * C["rho0"] / P.dt) * divergence(ut, vt, wt, h), 1.0, 0.0, "neumann", h)
     gx, gy, gz = gradient(dp, h)
@@ -497,7 +515,8 @@ def velocity_gradient(P, u, v, w):
         if b != 1:
             L[1][b] = (yp(f) - ym(f)) / (2 * hy)
         if b != 2:
-            L[2][b] = (zp_dir(f) - zm_dir(f)) / (2 * hz)
+            wv = P.walls(b)
+            L[2][b] = (zp_wall(f, wv[1]) - zm_wall(f, wv[0])) / (2 * hz)
     return L
 
 

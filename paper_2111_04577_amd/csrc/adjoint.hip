@@ -239,6 +239,7 @@ struct PolyArgs {
   int nx, ny, nz;
   D ihx, ihy, ihz, dt, inv_wi, omb;
   D gk;  // Giesekus: alpha / (1 - beta), 0 for Oldroyd-B
+  Walls<D> wl;  // tangential wall velocities (eq. NS13) for the forward velocity gradient
 };
 
 // ---- polymer, second stage: lt1 = 0.5 lam + 0.5 dt RH_tau^T lam ----------------------------
@@ -251,7 +252,7 @@ __global__ void __launch_bounds__(kBlock)
   const int id = (k * ny + j) * nx + i;
   const Coarse<D> U{a.u, nx, ny, nz}, V{a.v, nx, ny, nz}, W{a.w, nx, ny, nz};
   D L[3][3];
-  velocity_gradient(U, V, W, k, j, i, nz, a.ihx, a.ihy, a.ihz, L);
+  velocity_gradient(U, V, W, k, j, i, nz, a.ihx, a.ihy, a.ihz, L, a.wl);
   const D uxp = U.at(k, j, i), uxm = U.at(k, j, i - 1), vyp = V.at(k, j, i), vym = V.at(k, j - 1, i);
   const D wzp = k < nz - 1 ? W.at(k, j, i) : 0.0, wzm = k > 0 ? W.at(k - 1, j, i) : 0.0;
   D gc[6], tc[6], out[6];
@@ -278,7 +279,7 @@ __global__ void __launch_bounds__(kBlock)
   const int id = (k * ny + j) * nx + i;
   const Coarse<D> U{a.u, nx, ny, nz}, V{a.v, nx, ny, nz}, W{a.w, nx, ny, nz};
   D L[3][3];
-  velocity_gradient(U, V, W, k, j, i, nz, a.ihx, a.ihy, a.ihz, L);
+  velocity_gradient(U, V, W, k, j, i, nz, a.ihx, a.ihy, a.ihz, L, a.wl);
   const D uxp = U.at(k, j, i), uxm = U.at(k, j, i - 1), vyp = V.at(k, j, i), vym = V.at(k, j - 1, i);
   const D wzp = k < nz - 1 ? W.at(k, j, i) : 0.0, wzm = k > 0 ? W.at(k - 1, j, i) : 0.0;
   D lc[6], gc[6], tnc[6], t1c[6], out[6];
@@ -416,8 +417,8 @@ __global__ void __launch_bounds__(kBlock)
   const int k = bz / 3;
   const int comp = bz - 3 * k;
   const int f = c.first;
-  MomCtx<D> m{{in.un, in.unm1, nx, ny, nz, f},
-              {in.vn, in.vnm1, nx, ny, nz, f},
+  MomCtx<D> m{{in.un, in.unm1, nx, ny, nz, f, c.uwb[0], c.uwt[0]},
+              {in.vn, in.vnm1, nx, ny, nz, f, c.uwb[1], c.uwt[1]},
               {in.wn, in.wnm1, nx, ny, nz, f},
               {in.pn, in.pnm1, nx, ny, nz, f},
               {in.pn, nullptr, nx, ny, nz, 1},
@@ -482,8 +483,9 @@ __global__ void __launch_bounds__(kBlock)
   const int id = (k * ny + j) * nx + i;
   const int f = c.first;
   const D h = 0.5;
-  const Field<D> U{in.un, in.unm1, nx, ny, nz, f}, V{in.vn, in.vnm1, nx, ny, nz, f},
-      W{in.wn, in.wnm1, nx, ny, nz, f};
+  // forward velocities with the no-slip ghosts of eq. NS13 (2 u_w - adjacent)
+  const Field<D> U{in.un, in.unm1, nx, ny, nz, f, c.uwb[0], c.uwt[0]},
+      V{in.vn, in.vnm1, nx, ny, nz, f, c.uwb[1], c.uwt[1]}, W{in.wn, in.wnm1, nx, ny, nz, f};
   auto at = [&](const D* a, int kk, int jj, int ii) -> D { return a[(kk * ny + wrap(jj, ny)) * nx + wrap(ii, nx)]; };
   // face values with the wall rules: w faces exist for k in [0, nz-2]
   auto muf = [&](int comp, int kk, int jj, int ii) -> D {
@@ -585,8 +587,9 @@ __global__ void __launch_bounds__(kBlock)
   const int id = (k * ny + j) * nx + i;
   const int f = c.first;
   const D h = 0.5, q = 0.25;
-  const Field<D> U{in.un, in.unm1, nx, ny, nz, f}, V{in.vn, in.vnm1, nx, ny, nz, f},
-      W{in.wn, in.wnm1, nx, ny, nz, f};
+  // forward velocities with the no-slip ghosts of eq. NS13 (2 u_w - adjacent)
+  const Field<D> U{in.un, in.unm1, nx, ny, nz, f, c.uwb[0], c.uwt[0]},
+      V{in.vn, in.vnm1, nx, ny, nz, f, c.uwb[1], c.uwt[1]}, W{in.wn, in.wnm1, nx, ny, nz, f};
   auto at = [&](const D* a, int kk, int jj, int ii) -> D { return a[(kk * ny + wrap(jj, ny)) * nx + wrap(ii, nx)]; };
   const D lX = so.lX[id], lY = so.lY[id], lZ = so.lZ[id];
   const D phic = R.phi_c[id];
@@ -649,8 +652,9 @@ __global__ void __launch_bounds__(kBlock)
   const int id = (k * ny + j) * nx + i;
   const int f = c.first;
   const D h = 0.5;
-  const Field<D> U{in.un, in.unm1, nx, ny, nz, f}, V{in.vn, in.vnm1, nx, ny, nz, f},
-      W{in.wn, in.wnm1, nx, ny, nz, f};
+  // forward velocities with the no-slip ghosts of eq. NS13 (2 u_w - adjacent)
+  const Field<D> U{in.un, in.unm1, nx, ny, nz, f, c.uwb[0], c.uwt[0]},
+      V{in.vn, in.vnm1, nx, ny, nz, f, c.uwb[1], c.uwt[1]}, W{in.wn, in.wnm1, nx, ny, nz, f};
   auto at = [&](const D* a, int kk, int jj, int ii) -> D { return a[(kk * ny + wrap(jj, ny)) * nx + wrap(ii, nx)]; };
   // lam_r with the wall rules: u, v odd ghosts beyond the walls (for the Dirichlet Laplacian);
   // w faces k in [0, nz-2], zero elsewhere
@@ -1051,7 +1055,7 @@ hipError_t launch_adj_polymer(const Dims& c, const StepConsts& k, const double* 
                               const double* lu_in, const double* lv_in, const double* lw_in,
                               double* lu, double* lv, double* lw, double* part, hipStream_t st) {
   PolyArgs a{u, v, w, c.nx, c.ny, c.nz, c.ihx, c.ihy, c.ihz, k.dt, k.inv_wi, 1.0 - k.beta,
-             k.giesekus == 0.0 ? 0.0 : k.giesekus / (1.0 - k.beta)};
+             k.giesekus == 0.0 ? 0.0 : k.giesekus / (1.0 - k.beta), walls_of<double>(k)};
   Six lam, tn, t1, l1;
   SixOut lo, ot;
   Nine nl;

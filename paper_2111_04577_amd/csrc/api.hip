@@ -1240,7 +1240,6 @@ int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes) {
   if (p->constitutive != 0)
     return fail(DRPF_EUNSUPPORTED, "the adjoint covers the stress form only (Oldroyd-B or Giesekus)");
   if (p->refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
-  if (moving_walls(*p)) return fail(DRPF_EUNSUPPORTED, "the adjoint covers walls at rest only");
   const Dims F = fine_dims(*p);
   // the transposed fine-grid kernels index a fine field with 32-bit integers
   if (F.cells() > (size_t)INT_MAX)

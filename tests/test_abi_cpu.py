@@ -145,7 +145,7 @@ def test_adjoint_grid_bound():
 
 
 def test_validation_walls_and_checks():
-    """Wall velocities finite; check_finite_every >= 0; moving walls need d_w == 0 and have no
+    """Wall velocities finite; check_finite_every >= 0; moving walls need d_w == 0 and have an
     adjoint."""
     B = _lib()
     L = B.lib()
@@ -160,7 +160,7 @@ def test_validation_walls_and_checks():
     p = _params()
     p.u_wall_bottom[1] = 0.5
     assert L.drpf_validate(ctypes.byref(p)) == B.DRPF_OK
-    assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_EUNSUPPORTED
+    assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_OK
     p.d_w = 0.1
     assert L.drpf_validate(ctypes.byref(p)) == B.DRPF_EUNSUPPORTED
 

@@ -112,10 +112,21 @@ GIESEKUS_CASES = [
     ("C3", dict(nx=8, ny=4, nz=8, noise=1e-2, giesekus_alpha=0.2, advection=1)),
 ]
 GIESEKUS_IDS = ["C4-giesekus", "C3-giesekus", "C3-giesekus-weno"]
+# moving walls (eq. NS13, u = u_w): the forward velocities that multiply adjoints in the
+# transposed products (advection, J . grad u, stresses, the polymer's velocity gradient) carry
+# the wall velocity through their ghosts
+MOVING_CASES = [
+    ("C4", dict(nx=16, nz=8, noise=1e-2, u_wall_bottom=(0.3, 0.0), u_wall_top=(-0.5, 0.0))),
+    ("C3", dict(nx=8, ny=4, nz=8, noise=1e-2, u_wall_bottom=(0.2, -0.1), u_wall_top=(-0.3, 0.4))),
+    ("C2", dict(nx=8, ny=4, nz=8, noise=1e-4, u_wall_top=(0.5, 0.2))),
+    ("C3", dict(nx=8, ny=4, nz=8, noise=1e-2, advection=1, giesekus_alpha=0.2, u_wall_bottom=(0.2, -0.1),
+                u_wall_top=(-0.3, 0.4))),
+]
+MOVING_IDS = ["C4-moving", "C3-moving", "C2-moving", "C3-moving-weno-giesekus"]
 
 
-@pytest.mark.parametrize("name,kw", STEP_CASES + RELAXED_CASES + WENO_CASES + GIESEKUS_CASES,
-                         ids=[c[0] for c in STEP_CASES] + RELAXED_IDS + WENO_IDS + GIESEKUS_IDS)
+@pytest.mark.parametrize("name,kw", STEP_CASES + RELAXED_CASES + WENO_CASES + GIESEKUS_CASES + MOVING_CASES,
+                         ids=[c[0] for c in STEP_CASES] + RELAXED_IDS + WENO_IDS + GIESEKUS_IDS + MOVING_IDS)
 @pytest.mark.parametrize("before", [0, 3], ids=["first", "bdf2"])
 def test_adjoint_step_matches_oracle(drpf, name, kw, before):
     cfg = W.config(name, **kw)
@@ -123,7 +134,7 @@ def test_adjoint_step_matches_oracle(drpf, name, kw, before):
     st = S.run(P, W.droplet_state(cfg), before)
     lam = W.adjoint_seed(cfg, 11 + before)
     say(f"[gpu] adjoint step {name} {cfg.nx}x{cfg.ny}x{cfg.nz} d_w {cfg.d_w} advection {cfg.advection} "
-        f"giesekus {cfg.giesekus_alpha} after {before} steps")
+        f"giesekus {cfg.giesekus_alpha} walls {cfg.u_wall_bottom} {cfg.u_wall_top} after {before} steps")
     ref, gref = OA.adjoint_step(P, st, lam)
     got, g, xh = gpu_adjoint_step(drpf, cfg, st, lam)
     errs = adjoint_errors(got, ref, cfg.viscoelastic)
@@ -259,6 +270,25 @@ def test_trajectory_gradient_relaxed_walls(drpf):
     P = model.Params.from_config(cfg)
     N = 12
     say(f"[gpu] trajectory gradient, relaxed walls, {cfg.nx}x{cfg.nz} {N} steps")
+    J, g = _autograd(cfg, N, 5, "wetted_radius")
+    Jr, gr = OA.trajectory_gradient(P, W.droplet_state(cfg), N, OA.wetted_radius)
+    say("  J", J, Jr, "grad", g, gr)
+    assert abs(J - Jr) <= 1e-12 * abs(Jr)
+    check_grad(g, gr, (1e-9, 1e-6, 1e-9))
+    for a, which in enumerate(("theta", "pe", "wi")):
+        fd = _fd(drpf, cfg, N, which, 1e-4)
+        say("  fd", which, fd, g[a])
+        assert abs(fd - g[a]) <= 1e-6 * abs(g[a]), (which, fd, g[a])
+
+
+def test_trajectory_gradient_moving_walls(drpf):
+    """The same with moving walls (the top wall sheared at u_w = 0.5): 12 steps, checkpoints
+    every 5, against the oracle's reverse differentiation and central differences of the GPU
+    forward."""
+    cfg = W.config("C4", nx=32, nz=16, cn=0.04, pe=75.0, dt=5e-3, noise=0.0, u_wall_top=(0.5, 0.0))
+    P = model.Params.from_config(cfg)
+    N = 12
+    say(f"[gpu] trajectory gradient, moving walls, {cfg.nx}x{cfg.nz} {N} steps")
     J, g = _autograd(cfg, N, 5, "wetted_radius")
     Jr, gr = OA.trajectory_gradient(P, W.droplet_state(cfg), N, OA.wetted_radius)
     say("  J", J, Jr, "grad", g, gr)

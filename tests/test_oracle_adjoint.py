@@ -7,8 +7,9 @@
 * its parameter gradients through many steps equal central differences of the NumPy oracle
   trajectory in the bottom static angle, Pe and Wi;
 * all three also with relaxed walls (D_w > 0) and with WENO-Z advection, the first two also
-  with the Giesekus term of the stress form, whose NumPy steps are pinned separately
-  (test_oracle_wall_relaxation.py, test_oracle_weno.py, test_oracle_lcr.py).
+  with the Giesekus term of the stress form and with moving walls, whose NumPy steps are
+  pinned separately (test_oracle_wall_relaxation.py, test_oracle_weno.py, test_oracle_lcr.py,
+  test_oracle_moving_walls.py).
 """
 from __future__ import annotations
 
@@ -41,6 +42,11 @@ WENO_IDS = ["C4-weno", "C3-weno", "C2-weno", "C3-weno-dw0.5"]
 GIESEKUS = [("C4", dict(nx=16, nz=8, noise=1e-2, giesekus_alpha=0.3)),
             ("C3", dict(nx=8, ny=4, nz=8, noise=1e-2, giesekus_alpha=0.2, advection=1))]
 GIESEKUS_IDS = ["C4-giesekus", "C3-giesekus-weno"]
+# moving walls (eq. NS13, u = u_w on the walls): 2D, 3D Oldroyd-B, 3D Newtonian with contrast
+MOVING = [("C4", dict(nx=16, nz=8, noise=1e-2, u_wall_bottom=(0.3, 0.0), u_wall_top=(-0.5, 0.0))),
+          ("C3", dict(nx=8, ny=4, nz=8, noise=1e-2, u_wall_bottom=(0.2, -0.1), u_wall_top=(-0.3, 0.4))),
+          ("C2", dict(nx=8, ny=4, nz=8, noise=1e-4, u_wall_top=(0.5, 0.2)))]
+MOVING_IDS = ["C4-moving", "C3-moving", "C2-moving"]
 
 
 def _flat(st, ve):
@@ -50,8 +56,8 @@ def _flat(st, ve):
     return xs
 
 
-@pytest.mark.parametrize("name,kw", CASES + RELAXED + WENO + GIESEKUS,
-                         ids=[c[0] for c in CASES] + RELAXED_IDS + WENO_IDS + GIESEKUS_IDS)
+@pytest.mark.parametrize("name,kw", CASES + RELAXED + WENO + GIESEKUS + MOVING,
+                         ids=[c[0] for c in CASES] + RELAXED_IDS + WENO_IDS + GIESEKUS_IDS + MOVING_IDS)
 def test_differentiable_step_equals_numpy_step(name, kw):
     import torch
     cfg = W.config(name, **kw)
@@ -81,8 +87,9 @@ def _inner(a, b, ve):
     return sum(float(np.sum(x * y)) for x, y in zip(_flat(a, ve), _flat(b, ve)))
 
 
-@pytest.mark.parametrize("name,kw", CASES[:3] + RELAXED[:2] + WENO[:2] + WENO[3:] + GIESEKUS,
-                         ids=[c[0] for c in CASES[:3]] + RELAXED_IDS[:2] + WENO_IDS[:2] + WENO_IDS[3:] + GIESEKUS_IDS)
+@pytest.mark.parametrize("name,kw", CASES[:3] + RELAXED[:2] + WENO[:2] + WENO[3:] + GIESEKUS + MOVING[:2],
+                         ids=[c[0] for c in CASES[:3]] + RELAXED_IDS[:2] + WENO_IDS[:2] + WENO_IDS[3:] + GIESEKUS_IDS
+                         + MOVING_IDS[:2])
 def test_state_adjoint_dot_product(name, kw):
     """<lam, (step(x + e v) - step(x - e v)) / 2e> = <adjoint_step(lam), v> (NumPy step for the
     directional derivative)."""
