@@ -387,6 +387,34 @@ def cpu_baseline(W, cfg, nsteps):
     return rec, state
 
 
+# the oracle's rate on the other workloads: steps timed on every logical CPU (a few suffice)
+ORACLE_RATE_STEPS = (("C1", 20), ("C2", 2), ("C3", 2))
+
+
+def oracle_rates(W):
+    """Fine cell-updates/s of the FP64 oracle on C1, C2 and C3 over their first steps, scipy.fft
+    on every logical CPU (context beside the headline's own oracle timing)."""
+    import scipy.fft as sfft
+    from oracle import model
+    from oracle import step as S
+    ncpu = os.cpu_count() or 1
+    out = {}
+    for name, nsteps in ORACLE_RATE_STEPS:
+        cfg = W.config(name)
+        P = model.Params.from_config(cfg)
+        F, _ = grid_sizes(cfg)
+        st = W.droplet_state(cfg)
+        with sfft.set_workers(ncpu):
+            t0 = time.perf_counter()
+            for _ in range(nsteps):
+                st = S.step(P, st)
+            dt = time.perf_counter() - t0
+        out[name] = {"value": round(F["cells"] * nsteps / dt, 1), "steps": nsteps, "seconds": round(dt, 2),
+                     "cores": ncpu}
+        del st
+    return out
+
+
 def accuracy_vs_oracle(drpf, W, cfg, nsteps, oracle_state):
     """Per-field error of both GPU forms against the oracle after nsteps steps from the same
     initial state (max |x - x_ref| / max |x_ref| and rms / max |x_ref|)."""
@@ -685,6 +713,8 @@ def main():
         print(f"[bench] cpu baseline: oracle, {a.cpu_steps} steps of {cfg.name}, all cores then one",
               file=sys.stderr, flush=True)
         out["cpu_baseline"], ostate = cpu_baseline(W, cfg, a.cpu_steps)
+        print("[bench] oracle rates on C1, C2, C3", file=sys.stderr, flush=True)
+        out["cpu_baseline"]["other_workloads"] = oracle_rates(W)
         print(f"[bench] both forms against the oracle after {a.cpu_steps} steps", file=sys.stderr, flush=True)
         out["error_vs_oracle"] = accuracy_vs_oracle(drpf, W, cfg, a.cpu_steps, ostate)
         del ostate
