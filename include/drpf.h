@@ -312,7 +312,10 @@ const char* drpf_kernel_name(int id);
  * final state by reverse accumulation. Not in the paper: it differentiates the discrete
  * step of Sec. 3.2 (every stencil, transfer (eqs. dual1-dual3) and spectral solve
  * transposed; the fused Dong solve of eqs. NS25-NS27, the velocity Helmholtz solves and the
- * pseudo-inverse Poisson solve of eqs. NS36-NS37 are symmetric and reused as they are).
+ * pseudo-inverse Poisson solve of eqs. NS36-NS37 are symmetric and reused as they are; with
+ * relaxed walls, eq. NS34, the fused solve is not, and its transpose is solved instead). It
+ * covers central and WENO-Z advection, static, relaxed and moving walls, and the stress form
+ * of the polymer update (Oldroyd-B or Giesekus), not the log-conformation form.
  *
  * Adjoint state: the same levels as drpf_state without the spare fine buffer. phi[l] fine,
  * the others coarse; tau only when viscoelastic != 0 (may be null otherwise). */
