@@ -391,7 +391,7 @@ def cpu_baseline(W, cfg, nsteps):
 ORACLE_RATE_STEPS = (("C1", 20), ("C2", 2), ("C3", 2))
 
 
-def oracle_rates(W):
+def oracle_rates(W, plan=ORACLE_RATE_STEPS):
     """Fine cell-updates/s of the FP64 oracle on C1, C2 and C3 over their first steps, scipy.fft
     on every logical CPU (context beside the headline's own oracle timing)."""
     import scipy.fft as sfft
@@ -399,7 +399,7 @@ def oracle_rates(W):
     from oracle import step as S
     ncpu = os.cpu_count() or 1
     out = {}
-    for name, nsteps in ORACLE_RATE_STEPS:
+    for name, nsteps in plan:
         cfg = W.config(name)
         P = model.Params.from_config(cfg)
         F, _ = grid_sizes(cfg)

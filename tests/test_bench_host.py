@@ -108,3 +108,13 @@ def test_headline_defaults():
         sys.argv = old
     assert a.config == "C5" and a.steps == 200 and a.warmup == 10
     assert "C5" not in a.others.split(",")
+
+
+def test_oracle_rates_record():
+    """The oracle-rate leg times the oracle itself (fine cells x steps / seconds) on every CPU;
+    checked on a short C1 run."""
+    out = bench.oracle_rates(W, plan=(("C1", 2),))
+    rec = out["C1"]
+    F, _ = bench.grid_sizes(W.config("C1"))
+    assert rec["steps"] == 2 and rec["cores"] == (os.cpu_count() or 1)
+    assert rec["value"] > 0 and abs(rec["value"] * rec["seconds"] - 2 * F["cells"]) <= 0.02 * 2 * F["cells"]
