@@ -117,4 +117,5 @@ def test_oracle_rates_record():
     rec = out["C1"]
     F, _ = bench.grid_sizes(W.config("C1"))
     assert rec["steps"] == 2 and rec["cores"] == (os.cpu_count() or 1)
-    assert rec["value"] > 0 and abs(rec["value"] * rec["seconds"] - 2 * F["cells"]) <= 0.02 * 2 * F["cells"]
+    # seconds carries two decimals: value x seconds is the cell-update count to within value x 0.005
+    assert rec["value"] > 0 and abs(rec["value"] * rec["seconds"] - 2 * F["cells"]) <= rec["value"] * 0.0051
