@@ -542,13 +542,13 @@ __device__ __forceinline__ void stress_rhs(const T t0[6], const T* S, int plane,
 // rings of u, v, w over the box, from which the velocity gradient of eq. NS41 is formed (the
 // tile cell keeps its own for stage 2). Each thread loads at
 // most RP box points.
-template <typename T, int RP, int WPE, bool PF, int TXC = 0>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+template <typename T, int RP, int WPE, bool PF, int TXC = 0, int NT = kBlock>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     k_polymer_rk2_zm(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
                      TauSet<T> tn, TauOut<T> tout, int nx, int ny, int nz, int KB, T ihx, T ihy,
                      T ihz, T dt, T inv_wi, T omb, T gk, Walls<T> wl) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int TX = TXC > 0 ? TXC : (int)blockDim.x, TY = TXC > 0 ? kBlock / TXC : (int)blockDim.y;
+  const int TX = TXC > 0 ? TXC : (int)blockDim.x, TY = TXC > 0 ? NT / TXC : (int)blockDim.y;
   int bx, by, bz;
   xcd_tile(bx, by, bz);
   const int X0 = bx * TX, Y0 = by * TY, K0 = bz * KB;
@@ -864,8 +864,13 @@ hipError_t launch_polymer_rk2(const Dims& c, const StepConsts& k, const T* u, co
     tn.p[m] = tau_n[m];
     to.p[m] = tau_out[m];
   }
-  const int TX = c.nx < 32 ? c.nx : 32;
-  const int TY = c.ny < kBlock / TX ? c.ny : kBlock / TX;
+  // 64 x 8 columns (512 threads, two blocks per CU) where the grid allows: the two-cell halo box
+  // is 1.59x the tile instead of 1.69x and a box row is four cache lines plus two halo sectors
+  // instead of one plus two, so fewer halo bytes are fetched per cell (at 256 x 256 x 128: RK2
+  // march 223 -> 206 us FP32, 471 -> 415 us FP64)
+  const bool wide = c.nx >= 64 && c.ny >= 8;
+  const int TX = wide ? 64 : (c.nx < 32 ? c.nx : 32);
+  const int TY = wide ? 8 : (c.ny < kBlock / TX ? c.ny : kBlock / TX);
   const int cols = (c.nx / TX) * (c.ny / TY);
   const int BOX = (TX + 4) * (TY + 4);
   const int need = (BOX + TX * TY - 1) / (TX * TY);
@@ -879,14 +884,16 @@ hipError_t launch_polymer_rk2(const Dims& c, const StepConsts& k, const T* u, co
     hipLaunchKernelGGL(kernel, grid, dim3(TX, TY), shm, st, u, v, w, tn, to, c.nx, c.ny, c.nz, KB, (T)c.ihx,
                        (T)c.ihy, (T)c.ihz, (T)k.dt, (T)k.inv_wi, (T)(1.0 - k.beta), gk, wl);
   };
-  // registers: with the 32 x 8 shape at compile time FP32 fits four waves per SIMD (128 VGPRs)
-  // and FP64 two (202), without spills; with the shape at run time FP32 takes 2 waves per SIMD
+  // registers: with the 32 x 8 or 64 x 8 shape at compile time FP32 fits four waves per SIMD
+  // (128 VGPRs) and FP64 two (202 / 240), without spills; with the shape at run time FP32 takes 2 waves per SIMD
   // (226 VGPRs) and FP64 1 (at 2 waves it spills to scratch: 2.5x the algorithmic bytes on the
   // C5 grid and slower, 864 against 731 us)
   constexpr int WPE = sizeof(T) == 4 ? 2 : 1;
   constexpr int WPE32 = sizeof(T) == 4 ? 4 : 2;
   constexpr bool PF = sizeof(T) == 4;
-  if (TX == 32 && TY == 8)
+  if (wide)
+    go(k_polymer_rk2_zm<T, 2, WPE32, PF, 64, 512>);
+  else if (TX == 32 && TY == 8)
     go(k_polymer_rk2_zm<T, 2, WPE32, PF, 32>);
   else if (need <= 2)
     go(k_polymer_rk2_zm<T, 2, WPE, PF>);
