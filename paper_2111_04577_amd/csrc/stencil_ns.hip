@@ -216,12 +216,12 @@ struct PrevOwn {
 // k+1) in three-layer LDS rings, the xx, yy and xy components (layer k only) in one slot each,
 // Neumann clamp on load. The results go to three arrays shaped like u, v, w (the top-wall w
 // face gets zero); the momentum kernel reads them at its own faces.
-template <typename T, int RP, int TXC = 0>
-__global__ void __launch_bounds__(kBlock)
+template <typename T, int RP, int TXC = 0, int NT = kBlock>
+__global__ void __launch_bounds__(NT)
     k_polymer_div_zm(NsIn<T> in, const T* __restrict__ phic, int first, int nx, int ny, int nz, int KB,
                      T ihx, T ihy, T ihz) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int TX = TXC > 0 ? TXC : (int)blockDim.x, TY = TXC > 0 ? kBlock / TXC : (int)blockDim.y;
+  const int TX = TXC > 0 ? TXC : (int)blockDim.x, TY = TXC > 0 ? NT / TXC : (int)blockDim.y;
   int bx, by, bz;
   xcd_tile(bx, by, bz);
   const int X0 = bx * TX, Y0 = by * TY, K0 = bz * KB;
@@ -294,15 +294,15 @@ __global__ void __launch_bounds__(kBlock)
 // divergences of the weighted polymer stress, given by k_polymer_div_zm. Each thread loads at
 // most RP points of a halo tile. (Five wavefronts per SIMD instead of four spill eight FP32
 // registers: no faster, and the reloads add 0.3 GB of HBM reads per launch at 256 x 256 x 128.)
-template <typename T, bool VE, int RP, int TXC = 0>
-__global__ void __launch_bounds__(kBlock)
+template <typename T, bool VE, int RP, int TXC = 0, int NT = kBlock>
+__global__ void __launch_bounds__(NT)
     k_momentum_rhs_zm(NsIn<T> in, Restricted<T> R, T* __restrict__ ru, T* __restrict__ rv,
                       T* __restrict__ rw, StepConsts c, int nx, int ny, int nz, int KB, T ihx, T ihy,
                       T ihz) {
   extern __shared__ __align__(16) unsigned char smem[];
   // TXC > 0: the block shape TXC x (256 / TXC) known at compile time (ring neighbours at
   // immediate offsets)
-  const int TX = TXC > 0 ? TXC : (int)blockDim.x, TY = TXC > 0 ? kBlock / TXC : (int)blockDim.y;
+  const int TX = TXC > 0 ? TXC : (int)blockDim.x, TY = TXC > 0 ? NT / TXC : (int)blockDim.y;
   int bx, by, bz;
   xcd_tile(bx, by, bz);
   const int X0 = bx * TX, Y0 = by * TY, K0 = bz * KB;
@@ -785,8 +785,13 @@ hipError_t launch_momentum_rhs(const Dims& c, const StepConsts& k, NsIn<T> in, R
                        (T)c.ihx, (T)c.ihy, (T)c.ihz, k);
     return hipGetLastError();
   }
-  const int TX = c.nx < 32 ? c.nx : 32;
-  const int TY = c.ny < kBlock / TX ? c.ny : kBlock / TX;
+  // FP32: 64 x 8 columns (512 threads, two blocks per CU) where the grid allows: the halo tile
+  // rows span four full cache lines plus two halo sectors instead of one plus two (at 256 x 256
+  // x 128: momentum with its polymer divergence 434 -> 397 us). FP64 keeps 32 x 8: at three
+  // waves per SIMD a CU holds one 512-thread block, against three of 256.
+  const bool wide = sizeof(T) == 4 && c.nx >= 64 && c.ny >= 8;
+  const int TX = wide ? 64 : (c.nx < 32 ? c.nx : 32);
+  const int TY = wide ? 8 : (c.ny < kBlock / TX ? c.ny : kBlock / TX);
   const int cols = (c.nx / TX) * (c.ny / TY);
   const dim3 block(TX, TY);
   // halo points per thread: 2 for tiles of 32 x 4 and up, 4 for the small tiles of small grids
@@ -803,7 +808,9 @@ hipError_t launch_momentum_rhs(const Dims& c, const StepConsts& k, NsIn<T> in, R
     // the face divergences of the weighted polymer stress first (15 LDS tile slots)
     const size_t shp = (size_t)15 * HP * sizeof(T);
     if (need <= 2)
-      if (TX == 32 && TY == 8)
+      if (wide)
+        go(k_polymer_div_zm<T, 2, 64, 512>, shp, in, (const T*)r.phi_c, k.first, c.nx, c.ny, c.nz);
+      else if (TX == 32 && TY == 8)
         go(k_polymer_div_zm<T, 2, 32>, shp, in, (const T*)r.phi_c, k.first, c.nx, c.ny, c.nz);
       else
         go(k_polymer_div_zm<T, 2>, shp, in, (const T*)r.phi_c, k.first, c.nx, c.ny, c.nz);
@@ -811,13 +818,15 @@ hipError_t launch_momentum_rhs(const Dims& c, const StepConsts& k, NsIn<T> in, R
       go(k_polymer_div_zm<T, 4>, shp, in, (const T*)r.phi_c, k.first, c.nx, c.ny, c.nz);
   }
   const size_t shm = (size_t)13 * HP * sizeof(T);
-#define DRPF_MOM(VE, RP, TXC) go(k_momentum_rhs_zm<T, VE, RP, TXC>, shm, in, r, ru, rv, rw, k, c.nx, c.ny, c.nz)
+#define DRPF_MOM(VE, RP, TXC, NT) go(k_momentum_rhs_zm<T, VE, RP, TXC, NT>, shm, in, r, ru, rv, rw, k, c.nx, c.ny, c.nz)
   // the 32 x 8 tile with its shape at compile time
   const bool t32 = TX == 32 && TY == 8;
   if (in.viscoelastic) {
-    if (t32) DRPF_MOM(true, 2, 32); else if (need <= 2) DRPF_MOM(true, 2, 0); else DRPF_MOM(true, 4, 0);
+    if (wide) DRPF_MOM(true, 2, 64, 512); else if (t32) DRPF_MOM(true, 2, 32, kBlock);
+    else if (need <= 2) DRPF_MOM(true, 2, 0, kBlock); else DRPF_MOM(true, 4, 0, kBlock);
   } else {
-    if (t32) DRPF_MOM(false, 2, 32); else if (need <= 2) DRPF_MOM(false, 2, 0); else DRPF_MOM(false, 4, 0);
+    if (wide) DRPF_MOM(false, 2, 64, 512); else if (t32) DRPF_MOM(false, 2, 32, kBlock);
+    else if (need <= 2) DRPF_MOM(false, 2, 0, kBlock); else DRPF_MOM(false, 4, 0, kBlock);
   }
 #undef DRPF_MOM
   return hipGetLastError();
