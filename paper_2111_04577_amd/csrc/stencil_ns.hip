@@ -320,21 +320,41 @@ __global__ void __launch_bounds__(NT)
   // own point (the tile's first) also leaves its level n-1 values in prev_next, for the hat of
   // that layer.
   T prev_next[3] = {(T)0, (T)0, (T)0};
-  auto load_vel = [&](int kk) {
-    const int sl = (kk - K0 + 1) % 3;
+  // FP32 with two points per thread and the block shape at compile time: the raw values of the next layer (u^n, u^{n-1}, v^n,
+  // v^{n-1}, w^n, w^{n-1} and G) are loaded into registers one layer ahead of their LDS slots,
+  // so that the loads are in flight while the current layer is formed (14 registers; the
+  // kernel stays within the 128 that four wavefronts per SIMD allow). FP64 loads and stores in
+  // one go: its registers are at the three-wavefront limit.
+  constexpr bool PF = sizeof(T) == 4 && RP == 2 && TXC > 0;
+  T ra[RP][6], rg[RP];
+  auto fetch_vel = [&](int kk) {
     const int kc = min(max(kk, 0), nz - 1);
-    const T sg = (kk < 0 || kk >= nz) ? (T)-1 : (T)1;
-    const T bu = kk < 0 ? (T)(2.0 * c.uwb[0]) : kk >= nz ? (T)(2.0 * c.uwt[0]) : (T)0;
-    const T bv = kk < 0 ? (T)(2.0 * c.uwb[1]) : kk >= nz ? (T)(2.0 * c.uwt[1]) : (T)0;
     const bool wz = kk < 0 || kk >= nz - 1;
     const size_t o = kc * layer;
     const T *ua = in.un + o, *ub = in.unm1 + o, *va = in.vn + o, *vb = in.vnm1 + o;
     const T *wa = in.wn + o, *wb = in.wnm1 + o;
-    H.each_q([&](int q, int e, unsigned off) {
+    H.each_q([&](int q, int, unsigned off) {
+      ra[q][0] = ld_at(ua, off);
+      ra[q][2] = ld_at(va, off);
+      ra[q][4] = wz ? (T)0 : ld_at(wa, off);
+      ra[q][1] = f ? (T)0 : ld_at(ub, off);
+      ra[q][3] = f ? (T)0 : ld_at(vb, off);
+      ra[q][5] = (f || wz) ? (T)0 : ld_at(wb, off);
+    });
+  };
+  // extrapolated velocities on layer kk from the fetched values: no-slip ghosts (twice the
+  // wall velocity minus the adjacent layer) for u, v beyond the walls; w is zero on and beyond
+  // the walls. The thread's own point (the tile's first) also leaves its level n-1 values in
+  // prev_next, for the hat of that layer.
+  auto put_vel = [&](int kk) {
+    const int sl = (kk - K0 + 1) % 3;
+    const T sg = (kk < 0 || kk >= nz) ? (T)-1 : (T)1;
+    const T bu = kk < 0 ? (T)(2.0 * c.uwb[0]) : kk >= nz ? (T)(2.0 * c.uwt[0]) : (T)0;
+    const T bv = kk < 0 ? (T)(2.0 * c.uwb[1]) : kk >= nz ? (T)(2.0 * c.uwt[1]) : (T)0;
+    const bool wz = kk < 0 || kk >= nz - 1;
+    H.each_q([&](int q, int e, unsigned) {
       // each value read once: u* = 2 u^n - u^{n-1} (u^n on the first step)
-      const T un = ld_at(ua, off), vn = ld_at(va, off), wn = wz ? (T)0 : ld_at(wa, off);
-      const T um = f ? (T)0 : ld_at(ub, off), vm = f ? (T)0 : ld_at(vb, off);
-      const T wm = (f || wz) ? (T)0 : ld_at(wb, off);
+      const T un = ra[q][0], um = ra[q][1], vn = ra[q][2], vm = ra[q][3], wn = ra[q][4], wm = ra[q][5];
       sU[sl * HP + e] = bu + sg * (f ? un : (T)2 * un - um);
       sV[sl * HP + e] = bv + sg * (f ? vn : (T)2 * vn - vm);
       sW[sl * HP + e] = wz ? (T)0 : (f ? wn : (T)2 * wn - wm);
@@ -345,10 +365,53 @@ __global__ void __launch_bounds__(NT)
       }
     });
   };
-  auto load_g = [&](int kk) {
-    const int sl = (kk - K0 + 1) & 3;
+  // without the prefetch each value is combined as it arrives (fewer live registers)
+  auto load_vel = [&](int kk) {
+    if constexpr (PF) {
+      fetch_vel(kk);
+      put_vel(kk);
+    } else {
+      const int sl = (kk - K0 + 1) % 3;
+      const int kc = min(max(kk, 0), nz - 1);
+      const T sg = (kk < 0 || kk >= nz) ? (T)-1 : (T)1;
+      const T bu = kk < 0 ? (T)(2.0 * c.uwb[0]) : kk >= nz ? (T)(2.0 * c.uwt[0]) : (T)0;
+      const T bv = kk < 0 ? (T)(2.0 * c.uwb[1]) : kk >= nz ? (T)(2.0 * c.uwt[1]) : (T)0;
+      const bool wz = kk < 0 || kk >= nz - 1;
+      const size_t o = kc * layer;
+      const T *ua = in.un + o, *ub = in.unm1 + o, *va = in.vn + o, *vb = in.vnm1 + o;
+      const T *wa = in.wn + o, *wb = in.wnm1 + o;
+      H.each_q([&](int q, int e, unsigned off) {
+        const T un = ld_at(ua, off), vn = ld_at(va, off), wn = wz ? (T)0 : ld_at(wa, off);
+        const T um = f ? (T)0 : ld_at(ub, off), vm = f ? (T)0 : ld_at(vb, off);
+        const T wm = (f || wz) ? (T)0 : ld_at(wb, off);
+        sU[sl * HP + e] = bu + sg * (f ? un : (T)2 * un - um);
+        sV[sl * HP + e] = bv + sg * (f ? vn : (T)2 * vn - vm);
+        sW[sl * HP + e] = wz ? (T)0 : (f ? wn : (T)2 * wn - wm);
+        if (q == 0) {
+          prev_next[0] = um;
+          prev_next[1] = vm;
+          prev_next[2] = wm;
+        }
+      });
+    }
+  };
+  auto fetch_g = [&](int kk) {
     const T* g = R.G_c + min(max(kk, 0), nz - 1) * layer;
-    H.each([&](int e, unsigned off) { sG[sl * HP + e] = ld_at(g, off); });
+    H.each_q([&](int q, int, unsigned off) { rg[q] = ld_at(g, off); });
+  };
+  auto put_g = [&](int kk) {
+    const int sl = (kk - K0 + 1) & 3;
+    H.each_q([&](int q, int e, unsigned) { sG[sl * HP + e] = rg[q]; });
+  };
+  auto load_g = [&](int kk) {
+    if constexpr (PF) {
+      fetch_g(kk);
+      put_g(kk);
+    } else {
+      const int sl = (kk - K0 + 1) & 3;
+      const T* g = R.G_c + min(max(kk, 0), nz - 1) * layer;
+      H.each([&](int e, unsigned off) { sG[sl * HP + e] = ld_at(g, off); });
+    }
   };
   load_vel(K0 - 1);
   load_vel(K0);
@@ -356,6 +419,10 @@ __global__ void __launch_bounds__(NT)
   load_g(K0 - 1);
   load_g(K0);
   load_g(K0 + 1);
+  if constexpr (PF) {
+    fetch_vel(K0 + 1);
+    fetch_g(K0 + 2);
+  }
   const int K1 = min(K0 + KB, nz);  // the last block of a column may march fewer layers
   // the own column's pressure, phi_c, mu_c and z-edge viscosities on layers k and k + 1 stay
   // in registers: each is read from memory once per layer
@@ -365,13 +432,25 @@ __global__ void __launch_bounds__(NT)
   T ps0 = Pg.s(K0, j, i), pn0 = Pg.n(K0, j, i), ph0 = Phg.at(K0, j, i), mu0 = Mug.at(K0, j, i);
   T ex0 = Exg.at(K0, j, i), ey0 = Eyg.at(K0, j, i);
   for (int k = K0; k < K1; ++k) {
-    load_vel(k + 1);
-    load_g(k + 2);
+    if constexpr (PF) {
+      put_vel(k + 1);
+      put_g(k + 2);
+    } else {
+      load_vel(k + 1);
+      load_g(k + 2);
+    }
     // layer k + 1 (clamped on the top layer, where no term reads it); the edges have nz + 1
     const int ku = min(k + 1, nz - 1);
     const T ps1 = Pg.s(ku, j, i), pn1 = Pg.n(ku, j, i), ph1 = Phg.at(ku, j, i), mu1 = Mug.at(ku, j, i);
     const T ex1 = Exg.at(k + 1, j, i), ey1 = Eyg.at(k + 1, j, i);
     __syncthreads();
+    // the next iteration's layers, in flight while this layer is formed
+    if constexpr (PF) {
+      if (k + 2 <= K1) {
+        fetch_vel(k + 2);
+        fetch_g(k + 3);
+      }
+    }
     const int v0 = (k - K0) % 3, v1 = (k - K0 + 1) % 3, v2 = (k - K0 + 2) % 3;
     const RingV<T> Ur{{sU + v0 * HP, sU + v1 * HP, sU + v2 * HP}, k, X0, Y0, ys};
     const RingV<T> Vr{{sV + v0 * HP, sV + v1 * HP, sV + v2 * HP}, k, X0, Y0, ys};
