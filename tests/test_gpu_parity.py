@@ -198,9 +198,9 @@ def test_c1_hundred_steps(drpf):
 # velocity solves in FP32; the pressure Poisson, its zero mode and the mass sums in FP64)
 # against the FP64 oracle: max |x - x_ref| / max |x_ref| after the stated number of steps.
 # Each is about twice the error measured with the current kernels (which are deterministic):
-# C2 20 steps phi 1.0e-5, u 5.5e-5, v 3.4e-5, w 1.7e-4, p 2.8e-5; C3 20 steps phi 1.3e-5,
-# u 3.8e-5, v 3.2e-5, w 7.6e-5, p 7.3e-5, tau 2.9e-5; C5 2 steps phi 1.6e-6, u 7.3e-5,
-# v 7.8e-5, w 1.7e-4, p 7.0e-5, tau 8.9e-5.
+# C2 20 steps phi 1.1e-5, u 5.4e-5, v 4.6e-5, w 1.8e-4, p 3.5e-5; C3 20 steps phi 1.5e-5,
+# u 3.6e-5, v 2.5e-5, w 9.1e-5, p 5.6e-5, tau 3.1e-5; C5 2 steps phi 1.5e-6, u 6.1e-5,
+# v 7.2e-5, w 2.2e-4, p 4.5e-5, tau 8.5e-5.
 FP32_BOUND = {
     "C2": {"phi": 2e-5, "u": 1e-4, "v": 1e-4, "w": 4e-4, "p": 1e-4},
     "C3": {"phi": 3e-5, "u": 1e-4, "v": 1e-4, "w": 2e-4, "p": 2e-4, "tau": 1e-4},
