@@ -326,6 +326,8 @@ __global__ void __launch_bounds__(NT)
   // kernel stays within the 128 that four wavefronts per SIMD allow). FP64 loads and stores in
   // one go: its registers are at the three-wavefront limit.
   constexpr bool PF = sizeof(T) == 4 && RP == 2 && TXC > 0;
+  // FP64 has room for G alone (4 registers; 164 of the 168 that three wavefronts per SIMD allow)
+  constexpr bool PG = RP == 2 && TXC > 0;
   T ra[RP][6], rg[RP];
   auto fetch_vel = [&](int kk) {
     const int kc = min(max(kk, 0), nz - 1);
@@ -404,7 +406,7 @@ __global__ void __launch_bounds__(NT)
     H.each_q([&](int q, int e, unsigned) { sG[sl * HP + e] = rg[q]; });
   };
   auto load_g = [&](int kk) {
-    if constexpr (PF) {
+    if constexpr (PG) {
       fetch_g(kk);
       put_g(kk);
     } else {
@@ -419,10 +421,8 @@ __global__ void __launch_bounds__(NT)
   load_g(K0 - 1);
   load_g(K0);
   load_g(K0 + 1);
-  if constexpr (PF) {
-    fetch_vel(K0 + 1);
-    fetch_g(K0 + 2);
-  }
+  if constexpr (PF) fetch_vel(K0 + 1);
+  if constexpr (PG) fetch_g(K0 + 2);
   const int K1 = min(K0 + KB, nz);  // the last block of a column may march fewer layers
   // the own column's pressure, phi_c, mu_c and z-edge viscosities on layers k and k + 1 stay
   // in registers: each is read from memory once per layer
@@ -432,24 +432,23 @@ __global__ void __launch_bounds__(NT)
   T ps0 = Pg.s(K0, j, i), pn0 = Pg.n(K0, j, i), ph0 = Phg.at(K0, j, i), mu0 = Mug.at(K0, j, i);
   T ex0 = Exg.at(K0, j, i), ey0 = Eyg.at(K0, j, i);
   for (int k = K0; k < K1; ++k) {
-    if constexpr (PF) {
+    if constexpr (PF)
       put_vel(k + 1);
-      put_g(k + 2);
-    } else {
+    else
       load_vel(k + 1);
+    if constexpr (PG)
+      put_g(k + 2);
+    else
       load_g(k + 2);
-    }
     // layer k + 1 (clamped on the top layer, where no term reads it); the edges have nz + 1
     const int ku = min(k + 1, nz - 1);
     const T ps1 = Pg.s(ku, j, i), pn1 = Pg.n(ku, j, i), ph1 = Phg.at(ku, j, i), mu1 = Mug.at(ku, j, i);
     const T ex1 = Exg.at(k + 1, j, i), ey1 = Eyg.at(k + 1, j, i);
     __syncthreads();
     // the next iteration's layers, in flight while this layer is formed
-    if constexpr (PF) {
-      if (k + 2 <= K1) {
-        fetch_vel(k + 2);
-        fetch_g(k + 3);
-      }
+    if (k + 2 <= K1) {
+      if constexpr (PF) fetch_vel(k + 2);
+      if constexpr (PG) fetch_g(k + 3);
     }
     const int v0 = (k - K0) % 3, v1 = (k - K0 + 1) % 3, v2 = (k - K0 + 2) % 3;
     const RingV<T> Ur{{sU + v0 * HP, sU + v1 * HP, sU + v2 * HP}, k, X0, Y0, ys};
