@@ -315,18 +315,15 @@ __global__ void __launch_bounds__(NT)
   const int i = X0 + threadIdx.x, j = Y0 + threadIdx.y;
   const int f = c.first;
   const size_t layer = (size_t)ny * nx;
-  // extrapolated velocities on layer kk: no-slip ghosts (twice the wall velocity minus the
-  // adjacent layer) for u, v beyond the walls; w is zero on and beyond the walls. The thread's
-  // own point (the tile's first) also leaves its level n-1 values in prev_next, for the hat of
-  // that layer.
+  // own level n-1 velocities of the layer last put into the ring (see put_vel)
   T prev_next[3] = {(T)0, (T)0, (T)0};
-  // FP32 with two points per thread and the block shape at compile time: the raw values of the next layer (u^n, u^{n-1}, v^n,
-  // v^{n-1}, w^n, w^{n-1} and G) are loaded into registers one layer ahead of their LDS slots,
-  // so that the loads are in flight while the current layer is formed (14 registers; the
-  // kernel stays within the 128 that four wavefronts per SIMD allow). FP64 loads and stores in
-  // one go: its registers are at the three-wavefront limit.
+  // With two points per thread and the block shape at compile time, the raw values of the next
+  // layer are loaded into registers one layer ahead of their LDS slots, so that the loads are in
+  // flight while the current layer is formed. PF (FP32): u^n, u^{n-1}, v^n, v^{n-1}, w^n,
+  // w^{n-1} and G, 14 registers, within the 128 that four wavefronts per SIMD allow. PG: G,
+  // also in FP64 (4 registers, 164 of the 168 that three wavefronts allow; the velocities would
+  // need 24 more, so FP64 loads and stores them in one go).
   constexpr bool PF = sizeof(T) == 4 && RP == 2 && TXC > 0;
-  // FP64 has room for G alone (4 registers; 164 of the 168 that three wavefronts per SIMD allow)
   constexpr bool PG = RP == 2 && TXC > 0;
   T ra[RP][6], rg[RP];
   auto fetch_vel = [&](int kk) {
