@@ -517,7 +517,7 @@ def ingest_pmc(fetch_csv, write_csv, out_json, workload):
     return out
 
 
-def survey_bytes_per_cell(cfg, es):
+def compulsory_bytes_per_cell(cfg, es):
     """Compulsory bytes per fine cell-update of the hot-path byte model (each stage reads its
     inputs and writes its outputs once, spectral intermediates not counted): 11 fine words plus
     60 coarse words per coarse cell (Newtonian) or 110 (viscoelastic), a coarse cell being 8
@@ -554,7 +554,7 @@ def step_bandwidth(cfg, kernels, steps, ms_per_step, es, ceiling):
     model, each against the HBM peak and the measured copy ceiling."""
     F, _ = grid_sizes(cfg)
     kb = sum(alg_bytes(k, cfg, es) * v["launches"] / steps for k, v in kernels.items())
-    sb = survey_bytes_per_cell(cfg, es) * F["cells"]
+    sb = compulsory_bytes_per_cell(cfg, es) * F["cells"]
     out = {}
     for name, b in (("kernel_bytes", kb), ("compulsory_bytes", sb)):
         gbs = b / (ms_per_step / 1e3) / 1e9

@@ -90,11 +90,11 @@ def test_traffic_is_reported_only_for_the_measured_source_and_workload(tmp_path,
 
 def test_compulsory_byte_model():
     """18.5 / 24.75 words per fine cell in 3D (Newtonian / viscoelastic), 21.5 / 28.25 in 2D."""
-    assert bench.survey_bytes_per_cell(W.config("C2"), 4) == 74
-    assert bench.survey_bytes_per_cell(W.config("C5"), 4) == 99
-    assert bench.survey_bytes_per_cell(W.config("C5"), 8) == 198
-    assert bench.survey_bytes_per_cell(W.config("C1"), 8) == 172
-    assert bench.survey_bytes_per_cell(W.config("C4"), 8) == 226
+    assert bench.compulsory_bytes_per_cell(W.config("C2"), 4) == 74
+    assert bench.compulsory_bytes_per_cell(W.config("C5"), 4) == 99
+    assert bench.compulsory_bytes_per_cell(W.config("C5"), 8) == 198
+    assert bench.compulsory_bytes_per_cell(W.config("C1"), 8) == 172
+    assert bench.compulsory_bytes_per_cell(W.config("C4"), 8) == 226
 
 
 def test_headline_defaults():
