@@ -252,3 +252,12 @@ def test_product_path_does_not_import_oracle():
             if fn.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "oracle" not in text.lower(), fn
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library every entry point raises: there is no CPU or Python fallback."""
+    B = _lib()
+    monkeypatch.setattr(B, "_LIB", None)
+    monkeypatch.setattr(B, "lib_path", str(tmp_path / "libdrpf.so"))
+    with pytest.raises(RuntimeError, match="not found"):
+        B.lib()
