@@ -97,8 +97,10 @@ def _cahn_hilliard_relaxed(P: Params, C, Q, b, phis, phih):
     """Eqs. NS25-NS34 with the wall relaxation D_w > 0 of eq. NS15.
 
     Eq. NS34 adds D_w (gamma0 phi^{n+1} - phi_hat) / dt to the wall derivative of phi^{n+1}
-    (the wall value is the wall-adjacent cell's, as for the static data b; the term
-    D_w u* . grad phi* is zero at the stationary no-slip walls). With kappa = D_w gamma0 / dt
+    and moves D_w u* . grad phi* to its right-hand side (the wall value is the wall-adjacent
+    cell's, as for the static data b). On a wall u* is that wall's velocity (eq. NS13):
+    tangential, so the term is D_w (u_w d/dx + v_w d/dy) phi* with central differences on the
+    wall-adjacent layer, and zero at walls at rest. With kappa = D_w gamma0 / dt
     the ghost of the wall-adjacent cell becomes adjacent + hz (g - kappa phi^{n+1} +
     kappa phi_hat / gamma0): L_w phi = L_R phi + b_R, L_R = L_N + dL with dL = -kappa / hz
     on the wall-adjacent layers, b_R = b + (kappa / hz) phi_hat / gamma0 there.
@@ -118,6 +120,14 @@ def _cahn_hilliard_relaxed(P: Params, C, Q, b, phis, phih):
     bR = b.copy()
     bR[0] += (kap / hz) * phih[0] / C.gamma0
     bR[-1] += (kap / hz) * phih[-1] / C.gamma0
+    if P.moving_walls:
+        # the wall advection of eq. NS34, -D_w u_w . grad phi*, in the ghost: -(D_w / hz) u_w . grad phi*
+        for layer, side in ((0, 0), (-1, 1)):
+            pw = phis[layer]  # (ny, nx) on the wall-adjacent layer, periodic in x and y
+            dx = (np.roll(pw, -1, axis=1) - np.roll(pw, 1, axis=1)) / (2.0 * hf[0])
+            dy = (np.roll(pw, -1, axis=0) - np.roll(pw, 1, axis=0)) / (2.0 * hf[1])
+            adv = P.walls(0)[side] * dx + P.walls(1)[side] * dy
+            bR[layer] -= (P.d_w / hz) * adv
     c = C.gamma0 * P.pe / (cn2 * P.dt)
     phi_new = D.ch_relaxed_solve(Q - D.lap_neumann(bR, hf), C.S / cn2, c, -kap / hz, hf)
     lw = D.lap_neumann(phi_new, hf) + dL * phi_new + bR
@@ -451,9 +461,6 @@ def polymer(P: Params, tau_n, u, v, w):
 def step(P: Params, st, return_parts=False):
     """Advance the state by one coupled step; returns the new state (inputs untouched)."""
     first = st["step"] == 0
-    if P.d_w > 0.0 and P.moving_walls:
-        # eq. NS15 then carries the wall advection D_w u_w . grad(phi), not implemented here
-        raise NotImplementedError("relaxed walls (d_w > 0) with moving walls")
     C = constants(P, first)
     phi_new, G, phis, Psi = cahn_hilliard(P, st, C)
     R = restricted_set(P, phi_new, G, C)

@@ -173,7 +173,44 @@ def test_couette_catches_planted_mistake(old, new):
         test_couette_steady_state(3, 4, 0, -1.0, mod=_mutant(old, new))
 
 
-def test_relaxed_moving_walls_rejected():
+@pytest.mark.parametrize("old,new", [
+    # the wall advection of eq. NS34 left out, or with the wrong sign
+    ("            bR[layer] -= (P.d_w / hz) * adv\n", "            pass\n"),
+    ("            bR[layer] -= (P.d_w / hz) * adv\n", "            bR[layer] += (P.d_w / hz) * adv\n"),
+    # the other wall's velocity
+    ("            adv = P.walls(0)[side] * dx + P.walls(1)[side] * dy\n",
+     "            adv = P.walls(0)[1 - side] * dx + P.walls(1)[1 - side] * dy\n"),
+    # x and y derivatives exchanged
+    ("            adv = P.walls(0)[side] * dx + P.walls(1)[side] * dy\n",
+     "            adv = P.walls(0)[side] * dy + P.walls(1)[side] * dx\n"),
+], ids=["dropped", "sign", "other-wall", "swapped-axes"])
+def test_relaxed_moving_walls_catch_planted_mistake(old, new):
+    """The cell-by-cell NS25/NS34 residual with moving, relaxed walls sees each mistake."""
+    from tests import test_oracle_pins as pins
+    with pytest.raises(AssertionError):
+        pins.test_ch_solves_unsplit_equation(2, False, 0.05, True, mod=_mutant(old, new))
+
+
+def test_relaxed_moving_walls_couette_and_mass():
+    """Relaxed walls with moving walls: a flat phase field has no tangential gradient on the
+    walls, so plane Couette flow stays on its linear profile as with static walls; a drop
+    conserves its mass to round-off. The differentiable step still refuses the combination."""
     P = _couette_params(4, 0, d_w=0.1)
+    st = _couette_state(P, -1.0, 3, False)
+    new = S.step(P, st)
+    scale = max(abs(x) for x in UB + UT)
+    for f in ("u", "v"):
+        assert np.max(np.abs(new[f][0] - st[f][0])) <= 1e-12 * scale, f
+    assert np.max(np.abs(new["phi"][0] - st["phi"][0])) <= 1e-13
+    import workloads as W
+    cfg = W.config("C2", nx=8, ny=4, nz=8, lx=1.0, ly=0.5, lz=0.5, radius=0.25, noise=1e-3, seed=3,
+                   d_w=0.2, u_wall_bottom=(0.5, -0.3), u_wall_top=(-0.4, 0.2))
+    P = model.Params.from_config(cfg)
+    st = W.droplet_state(cfg)
+    m0 = np.sum(st["phi"][0])
+    for _ in range(4):
+        st = S.step(P, st)
+    assert abs(np.sum(st["phi"][0]) - m0) < 1e-11 * np.sum(np.abs(st["phi"][0]))
+    from oracle import adjoint as A
     with pytest.raises(NotImplementedError):
-        S.step(P, _couette_state(P, -1.0, 0, False))
+        A.step(P, st, None, None, None)

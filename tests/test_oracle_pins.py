@@ -218,20 +218,27 @@ def _random_state(P, rng, amp_u=0.3):
             "tau": [[z() for _ in range(6)], [z() for _ in range(6)]], "step": 3}
 
 
-@pytest.mark.parametrize("ny,first,d_w", [(1, False, 0.0), (2, False, 0.0), (2, True, 0.0),
-                                          (1, False, 0.05), (2, False, 0.05), (2, True, 0.05)])
-def test_ch_solves_unsplit_equation(ny, first, d_w):
+MOVING = ((0.7, -0.4), (-0.3, 0.9))  # (u, v) of the bottom and the top wall
+
+
+@pytest.mark.parametrize("ny,first,d_w,moving", [
+    (1, False, 0.0, False), (2, False, 0.0, False), (2, True, 0.0, False),
+    (1, False, 0.05, False), (2, False, 0.05, False), (2, True, 0.05, False),
+    (1, False, 0.05, True), (2, False, 0.05, True), (2, True, 0.05, True), (2, False, 0.0, True)])
+def test_ch_solves_unsplit_equation(ny, first, d_w, moving, mod=S):
     """phi^{n+1} satisfies the unsplit eq. NS25 with the wetting ghost of eq. NS34 and the
     zero-flux outer Laplacian, evaluated cell by cell. With wall relaxation (D_w > 0) the ghost
-    of eq. NS34 holds phi^{n+1} itself."""
+    of eq. NS34 holds phi^{n+1} itself, and with moving walls also the wall advection
+    D_w u_w . grad phi* (central differences on the wall-adjacent layer, by loops here)."""
     rng = np.random.default_rng(21)
+    uw = MOVING if moving else ((0.0, 0.0), (0.0, 0.0))
     P = _params(nx=4, ny=ny, nz=4, ly=0.25 * ny, theta_bottom_deg=60.0, theta_top_deg=110.0,
-                s_factor=1.3, d_w=d_w)
+                s_factor=1.3, d_w=d_w, u_wall_bottom=uw[0], u_wall_top=uw[1])
     st = _random_state(P, rng)
     if first:
         st["step"] = 0
     C = model.constants(P, first)
-    phi, G, phis, _ = S.cahn_hilliard(P, st, C)
+    phi, G, phis, _ = mod.cahn_hilliard(P, st, C)
     hf = P.hf
     nzf, nyf, nxf = phi.shape
     p0, p1 = st["phi"]
@@ -273,9 +280,17 @@ def test_ch_solves_unsplit_equation(ny, first, d_w):
     def at(a, K, J, I):
         return a[K, J % nyf, I % nxf]
 
+    def wall_advection(K, J, I):
+        # u* . grad phi* on the wall: the wall's own velocity, tangential
+        ux, uy = uw[0] if K == 0 else uw[1]
+        dx = (ps[K, J, (I + 1) % nxf] - ps[K, J, (I - 1) % nxf]) / (2 * hf[0])
+        dy = (ps[K, (J + 1) % nyf, I] - ps[K, (J - 1) % nyf, I]) / (2 * hf[1])
+        return ux * dx + uy * dy
+
     def wall_derivative(K, J, I, c):
         # eq. NS34: n . grad phi^{n+1} = g(phi*) - D_w (gamma0 phi^{n+1} - phi_hat) / dt
-        return gw[K][J, I] - d_w * (C.gamma0 * c - ph[K, J, I]) / P.dt
+        #                                - D_w u* . grad phi*
+        return gw[K][J, I] - d_w * (C.gamma0 * c - ph[K, J, I]) / P.dt - d_w * wall_advection(K, J, I)
 
     def lap_w(a, K, J, I):
         c = a[K, J, I]
