@@ -122,9 +122,10 @@ typedef struct drpf_params {
   double u_wall_top[2];        /* ... at z = lz: the no-slip condition u = u_w of eq. NS13
                                   (ghost = 2 u_w - adjacent in every stencil and in the
                                   implicit velocity solves). Finite; 0 (default): walls at
-                                  rest. Moving walls need d_w == 0 (DRPF_EUNSUPPORTED
-                                  otherwise: eq. NS15 would gain the wall advection of phi);
-                                  the adjoint covers moving walls                            */
+                                  rest. With d_w > 0, eq. NS34 also carries the wall
+                                  advection D_w u_w . grad phi* (central differences on the
+                                  wall-adjacent layer). The adjoint covers moving walls with
+                                  d_w == 0 (DRPF_EUNSUPPORTED for moving relaxed walls)      */
   int check_finite_every;      /* > 0: drpf_step checks the phase field and the velocities for
                                   NaN/Inf after every check_finite_every-th step (counted by the
                                   state's step counter), synchronising the stream there, and
@@ -314,8 +315,9 @@ const char* drpf_kernel_name(int id);
  * transposed; the fused Dong solve of eqs. NS25-NS27, the velocity Helmholtz solves and the
  * pseudo-inverse Poisson solve of eqs. NS36-NS37 are symmetric and reused as they are; with
  * relaxed walls, eq. NS34, the fused solve is not, and its transpose is solved instead). It
- * covers central and WENO-Z advection, static, relaxed and moving walls, and the stress form
- * of the polymer update (Oldroyd-B or Giesekus), not the log-conformation form.
+ * covers central and WENO-Z advection, static, relaxed and moving walls (not relaxed walls
+ * that move), and the stress form of the polymer update (Oldroyd-B or Giesekus), not the
+ * log-conformation form.
  *
  * Adjoint state: the same levels as drpf_state without the spare fine buffer. phi[l] fine,
  * the others coarse; tau only when viscoelastic != 0 (may be null otherwise). */
@@ -329,9 +331,9 @@ typedef struct drpf_adj {
 } drpf_adj;
 
 /* Bytes of the second device workspace the adjoint needs (forward intermediates of the
- * recomputed step and the adjoint stage buffers). DRPF_EUNSUPPORTED unless precision 64 and
- * the polymer update is the stress form (constitutive 0: Oldroyd-B, or Giesekus with
- * giesekus_alpha > 0). */
+ * recomputed step and the adjoint stage buffers). DRPF_EUNSUPPORTED unless precision 64, the
+ * polymer update is the stress form (constitutive 0: Oldroyd-B, or Giesekus with
+ * giesekus_alpha > 0) and relaxed walls (d_w > 0) are at rest. */
 int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes);
 
 /* Hands the grid that workspace (device memory, 256-byte aligned, at least the size above;

@@ -942,8 +942,6 @@ int drpf_validate(const drpf_params* p) {
     if (!isfinite(p->u_wall_bottom[a]) || !isfinite(p->u_wall_top[a]))
       return fail(DRPF_EINVAL, "wall velocities must be finite");
   if (p->check_finite_every < 0) return fail(DRPF_EINVAL, "check_finite_every must be >= 0");
-  if (p->d_w > 0.0 && moving_walls(*p))
-    return fail(DRPF_EUNSUPPORTED, "relaxed walls (d_w > 0) need walls at rest");
   return DRPF_OK;
 }
 
@@ -1239,6 +1237,8 @@ int drpf_adjoint_workspace_bytes(const drpf_params* p, size_t* bytes) {
   if (p->precision != 64) return fail(DRPF_EUNSUPPORTED, "the adjoint runs on FP64 grids only");
   if (p->constitutive != 0)
     return fail(DRPF_EUNSUPPORTED, "the adjoint covers the stress form only (Oldroyd-B or Giesekus)");
+  if (p->d_w > 0.0 && moving_walls(*p))
+    return fail(DRPF_EUNSUPPORTED, "the adjoint covers relaxed walls (d_w > 0) at rest only");
   if (p->refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
   const Dims F = fine_dims(*p);
   // the transposed fine-grid kernels index a fine field with 32-bit integers
@@ -1254,6 +1254,8 @@ int drpf_adjoint_attach(drpf_grid* g, void* d_workspace, size_t bytes) {
   if (g->p.precision != 64) return fail(DRPF_EUNSUPPORTED, "the adjoint runs on FP64 grids only");
   if (g->p.constitutive != 0)
     return fail(DRPF_EUNSUPPORTED, "the adjoint covers the stress form only (Oldroyd-B or Giesekus)");
+  if (g->p.d_w > 0.0 && moving_walls(g->p))
+    return fail(DRPF_EUNSUPPORTED, "the adjoint covers relaxed walls (d_w > 0) at rest only");
   if (g->p.refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
   if (!d_workspace) return fail(DRPF_EWORKSPACE, "null adjoint workspace");
   if (((uintptr_t)d_workspace & 255) != 0) return fail(DRPF_EWORKSPACE, "adjoint workspace must be 256-byte aligned");
@@ -1270,6 +1272,8 @@ int drpf_adjoint_step(drpf_grid* g, const drpf_state* x, const drpf_state* x_nex
   if (g->p.precision != 64) return fail(DRPF_EUNSUPPORTED, "the adjoint runs on FP64 grids only");
   if (g->p.constitutive != 0)
     return fail(DRPF_EUNSUPPORTED, "the adjoint covers the stress form only (Oldroyd-B or Giesekus)");
+  if (g->p.d_w > 0.0 && moving_walls(g->p))
+    return fail(DRPF_EUNSUPPORTED, "the adjoint covers relaxed walls (d_w > 0) at rest only");
   if (g->p.refine == 1) return fail(DRPF_EUNSUPPORTED, "the adjoint covers the dual-resolution step only");
   if (!g->aws) return fail(DRPF_EINVAL, "no adjoint workspace attached");
   if (!x->phi[0] || !x->phi[1] || !x->u[0] || !x->u[1] || !x->v[0] || !x->v[1] || !x->w[0] || !x->w[1] ||

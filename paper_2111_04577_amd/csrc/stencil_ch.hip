@@ -36,7 +36,7 @@ constexpr int kBlock = 256;
 // the column enters a new coarse layer. The 3D FP32 form is held to 64 registers, so that the
 // 8 blocks per CU of a 256 x 256 x 128 grid are resident at once. SR: single resolution (the
 // phase field on the flow grid; the face velocities are taken as they are).
-template <typename T, int R, int MODE, bool RELAX, int TXC = 0>
+template <typename T, int R, int MODE, bool RELAX, int TXC = 0, bool MOVE = false>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && R == 2 && MODE == 0 && !RELAX ? 8
                                        : (RELAX && sizeof(T) == 8 ? 3 : 4))))
@@ -132,6 +132,25 @@ __global__ void __launch_bounds__(kBlock)
     const size_t id = ((size_t)Kl * ny + wrap(Jl, ny)) * nx + wrap(Il, nx);
     return first ? phin[id] : (T)2 * phin[id] - (T)0.5 * phinm1[id];
   };
+  // relaxed moving walls (MOVE, eq. NS34): the wall advection D_w u_w . grad phi* of the
+  // right-hand side enters the ghost as phi_hat - dt u_w . grad phi* in place of phi_hat
+  // (kappa dt / gamma0 = D_w), u_w the wall's own velocity (eq. NS13), the in-plane derivatives
+  // of phi* central on the wall-adjacent layer. An instantiation of its own: the extra loads
+  // would cost the static-wall forms registers.
+  auto pstar_at = [&](int Kl, int Jl, int Il) -> T {
+    const size_t id = ((size_t)Kl * ny + wrap(Jl, ny)) * nx + wrap(Il, nx);
+    return first ? phin[id] : (T)2 * phin[id] - phinm1[id];
+  };
+  auto phat_wall = [&](int Kl, int Jl, int Il) -> T {
+    T ph = phat_at(Kl, Jl, Il);
+    if constexpr (MOVE) {
+      const double* uw = Kl == 0 ? c.uwb : c.uwt;
+      const T adv = (T)uw[0] * (pstar_at(Kl, Jl, Il + 1) - pstar_at(Kl, Jl, Il - 1)) * ((T)0.5 * ihx) +
+                    (T)uw[1] * (pstar_at(Kl, Jl + 1, Il) - pstar_at(Kl, Jl - 1, Il)) * ((T)0.5 * ihy);
+      ph -= (T)c.dt * adv;
+    }
+    return ph;
+  };
   T ta[R], tb[R];
   int sm = 0, s0 = 1, sp = 2;
   load_tile(K0 - 1, ta, tb);
@@ -206,17 +225,17 @@ __global__ void __launch_bounds__(kBlock)
     };
     T lapb = 0;
     if (K == 0 || K == nz - 1) {
-      const T b0 = bval(K, p0, relax ? phat_at(K, J, I) : (T)0);
-      lapb = (bval(K, pxp, relax ? phat_at(K, J, I + 1) : (T)0) - 2 * b0 +
-              bval(K, pxm, relax ? phat_at(K, J, I - 1) : (T)0)) * ihx2 +
-             (bval(K, pyp, relax ? phat_at(K, J + 1, I) : (T)0) - 2 * b0 +
-              bval(K, pym, relax ? phat_at(K, J - 1, I) : (T)0)) * ihy2;
+      const T b0 = bval(K, p0, relax ? phat_wall(K, J, I) : (T)0);
+      lapb = (bval(K, pxp, relax ? phat_wall(K, J, I + 1) : (T)0) - 2 * b0 +
+              bval(K, pxm, relax ? phat_wall(K, J, I - 1) : (T)0)) * ihx2 +
+             (bval(K, pyp, relax ? phat_wall(K, J + 1, I) : (T)0) - 2 * b0 +
+              bval(K, pym, relax ? phat_wall(K, J - 1, I) : (T)0)) * ihy2;
       const T bup = K + 1 < nz ? bval(K + 1, pzp, (T)0) : b0;
       const T bdn = K > 0 ? bval(K - 1, pzm, (T)0) : b0;
       lapb += (bup - 2 * b0 + bdn) * ihz2;
     } else {
-      if (K == 1) lapb += bval(0, pzm, relax ? phat_at(0, J, I) : (T)0) * ihz2;
-      if (K == nz - 2) lapb += bval(nz - 1, pzp, relax ? phat_at(nz - 1, J, I) : (T)0) * ihz2;
+      if (K == 1) lapb += bval(0, pzm, relax ? phat_wall(0, J, I) : (T)0) * ihz2;
+      if (K == nz - 2) lapb += bval(nz - 1, pzp, relax ? phat_wall(nz - 1, J, I) : (T)0) * ihz2;
     }
     const T q = (T)c.pe_cn2 * (phat * (T)c.inv_dt - adv) + lapw;
     st_at(out + K * layer, cid, q - lapb);
@@ -242,7 +261,7 @@ __global__ void __launch_bounds__(kBlock)
 // wavefronts per SIMD (80 registers, a few spilled): at 256 x 256 x 128 coarse cells that makes
 // one round of six blocks per CU with marches of 43 layers, measured 15% faster than five
 // wavefronts (one round of four blocks, marches of 64).
-template <typename T, int R, bool RELAX, int CXC = 0>
+template <typename T, int R, bool RELAX, int CXC = 0, bool MOVE = false>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && R == 3 && !RELAX ? 6 : 1)))
     k_restrict_g(const T* __restrict__ phinew, const T* __restrict__ phin,
@@ -336,7 +355,21 @@ __global__ void __launch_bounds__(kBlock)
         if (relax && (K == 0 || K == fnz - 1)) {
           // relaxed walls: (kappa / hz)(phi_hat / gamma0 - phi^{n+1}) in the wall ghost
           const T an = ld_at(phin + K * layer, gOff[q]);
-          const T ph = first ? an : (T)2 * an - (T)0.5 * ld_at(phinm1 + K * layer, gOff[q]);
+          T ph = first ? an : (T)2 * an - (T)0.5 * ld_at(phinm1 + K * layer, gOff[q]);
+          if constexpr (MOVE) {
+            // moving walls: phi_hat - dt u_w . grad phi* (eq. NS34), as in the right-hand side
+            const int idx = (int)(gOff[q] / sizeof(T)), I = idx % fnx, J = idx / fnx;
+            const T* a = phin + K * layer;
+            const T* b1 = phinm1 + K * layer;
+            auto pst = [&](int jj, int ii) {
+              const int o = wrap(jj, fny) * fnx + wrap(ii, fnx);
+              return first ? a[o] : (T)2 * a[o] - b1[o];
+            };
+            const double* uw = K == 0 ? c.uwb : c.uwt;
+            const T adv = (T)uw[0] * (pst(J, I + 1) - pst(J, I - 1)) * ((T)0.5 * fihx) +
+                          (T)uw[1] * (pst(J + 1, I) - pst(J - 1, I)) * ((T)0.5 * fihy);
+            ph -= (T)c.dt * adv;
+          }
           b += kg * ph - kk * p;
         }
         *(e < GP ? dst + e : sX + (e - GP)) = -cn2 * (lap + b) + S * (p - ps) + ps * ps * ps - ps;
@@ -608,8 +641,19 @@ __global__ void __launch_bounds__(kBlock)
   if (k == 0) b += (T)c.g_bot * ihz * ((T)1 - ps * ps);
   if (k == nz - 1) b += (T)c.g_top * ihz * ((T)1 - ps * ps);
   if (c.relax_kappa != 0.0 && (k == 0 || k == nz - 1)) {
-    // relaxed walls: (kappa / hz)(phi_hat / gamma0 - phi^{n+1}) in the wall ghost
-    const T ph = c.first ? an : (T)2 * an - (T)0.5 * phinm1[id];
+    // relaxed walls: (kappa / hz)(phi_hat / gamma0 - phi^{n+1}) in the wall ghost; moving
+    // walls: phi_hat - dt u_w . grad phi* (eq. NS34)
+    T ph = c.first ? an : (T)2 * an - (T)0.5 * phinm1[id];
+    const double* uw = k == 0 ? c.uwb : c.uwt;
+    if (uw[0] != 0.0 || uw[1] != 0.0) {
+      auto pst = [&](int jj, int ii) {
+        const int o = (k * ny + wrap(jj, ny)) * nx + wrap(ii, nx);
+        return c.first ? phin[o] : (T)2 * phin[o] - phinm1[o];
+      };
+      const T adv = (T)uw[0] * (pst(j, i + 1) - pst(j, i - 1)) * ((T)0.5 * ihx) +
+                    (T)uw[1] * (pst(j + 1, i) - pst(j - 1, i)) * ((T)0.5 * ihy);
+      ph -= (T)c.dt * adv;
+    }
     b += (T)(c.relax_kappa * c.inv_gamma0) * ihz * ph - (T)c.relax_kappa * ihz * p;
   }
   r.G_c[id] = -(T)c.cn2 * (lap + b) + (T)c.S * (p - ps) + ps * ps * ps - ps;
@@ -728,9 +772,9 @@ hipError_t launch_ch_rhs(const Dims& f, const Dims& c, const StepConsts& k, ChIn
   if (need > 4) return hipErrorInvalidConfiguration;
   const size_t shm = (size_t)6 * HP * sizeof(T);
   const dim3 grid(f.nx / TX, f.ny / TY, f.nz / KB), block(TX, TY, 1);
-#define DRPF_CH(R, MODE, RELAX, TXC)                                                               \
-  hipLaunchKernelGGL((k_ch_rhs<T, R, MODE, RELAX, TXC>), grid, block, shm, st, in.phin, in.phinm1, pv, \
-                     rhs, in.adv, f.nx, f.ny, f.nz, KB, (T)f.ihx, (T)f.ihy, (T)f.ihz, k)
+#define DRPF_CH(R, MODE, RELAX, TXC, ...)                                                          \
+  hipLaunchKernelGGL((k_ch_rhs<T, R, MODE, RELAX, TXC, ##__VA_ARGS__>), grid, block, shm, st, in.phin, \
+                     in.phinm1, pv, rhs, in.adv, f.nx, f.ny, f.nz, KB, (T)f.ihx, (T)f.ihy, (T)f.ihz, k)
   // the 64 x 4 tile of 3D grids with its shape at compile time
   const bool t64 = TX == 64 && TY == 4;
 #define DRPF_CH_R(MODE, RELAX)      \
@@ -742,11 +786,20 @@ hipError_t launch_ch_rhs(const Dims& f, const Dims& c, const StepConsts& k, ChIn
     DRPF_CH(4, MODE, RELAX, 0)
   // mode: 0 dual resolution, 1 single resolution, 2 advection given
   const int mode = in.adv ? 2 : (single ? 1 : 0);
-  if (k.relax_kappa != 0.0) {
+  const bool moving = k.uwb[0] != 0.0 || k.uwb[1] != 0.0 || k.uwt[0] != 0.0 || k.uwt[1] != 0.0;
+#define DRPF_CH_M(MODE)                  \
+  if (need <= 2)                         \
+    DRPF_CH(2, MODE, true, 0, true);     \
+  else                                   \
+    DRPF_CH(4, MODE, true, 0, true)
+  if (k.relax_kappa != 0.0 && moving) {
+    if (mode == 2) { DRPF_CH_M(2); } else if (mode == 1) { DRPF_CH_M(1); } else { DRPF_CH_M(0); }
+  } else if (k.relax_kappa != 0.0) {
     if (mode == 2) { DRPF_CH_R(2, true); } else if (mode == 1) { DRPF_CH_R(1, true); } else { DRPF_CH_R(0, true); }
   } else {
     if (mode == 2) { DRPF_CH_R(2, false); } else if (mode == 1) { DRPF_CH_R(1, false); } else { DRPF_CH_R(0, false); }
   }
+#undef DRPF_CH_M
 #undef DRPF_CH_R
 #undef DRPF_CH
   return hipGetLastError();
@@ -780,7 +833,10 @@ hipError_t launch_restrict_g(const Dims& f, const Dims& c, const StepConsts& k, 
     hipLaunchKernelGGL(kernel, grid, block, shm, st, phinew, phin, phinm1, r, f.nx, f.ny, f.nz, (T)f.ihx,
                        (T)f.ihy, (T)f.ihz, c.nx, c.ny, c.nz, ry, KB, k);
   };
-  if (k.relax_kappa != 0.0) {
+  const bool moving = k.uwb[0] != 0.0 || k.uwb[1] != 0.0 || k.uwt[0] != 0.0 || k.uwt[1] != 0.0;
+  if (k.relax_kappa != 0.0 && moving) {
+    if (Rk == 3) go(k_restrict_g<T, 3, true, 0, true>); else go(k_restrict_g<T, 6, true, 0, true>);
+  } else if (k.relax_kappa != 0.0) {
     if (Rk == 3) go(k_restrict_g<T, 3, true>); else go(k_restrict_g<T, 6, true>);
   } else {
     if (CX == 32 && CY == 4) go(k_restrict_g<T, 3, false, 32>);

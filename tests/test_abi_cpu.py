@@ -145,8 +145,8 @@ def test_adjoint_grid_bound():
 
 
 def test_validation_walls_and_checks():
-    """Wall velocities finite; check_finite_every >= 0; moving walls need d_w == 0 and have an
-    adjoint."""
+    """Wall velocities finite; check_finite_every >= 0; moving walls have an adjoint, and with
+    relaxed walls (d_w > 0) a forward step but no adjoint."""
     B = _lib()
     L = B.lib()
     nb = ctypes.c_size_t()
@@ -162,7 +162,8 @@ def test_validation_walls_and_checks():
     assert L.drpf_validate(ctypes.byref(p)) == B.DRPF_OK
     assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_OK
     p.d_w = 0.1
-    assert L.drpf_validate(ctypes.byref(p)) == B.DRPF_EUNSUPPORTED
+    assert L.drpf_validate(ctypes.byref(p)) == B.DRPF_OK
+    assert L.drpf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == B.DRPF_EUNSUPPORTED
 
 
 C_PROBE = r"""

@@ -100,6 +100,43 @@ def test_relaxed_walls_match_oracle(drpf, name, cfg, n):
         assert e < TOL, (name, k, e)
 
 
+# relaxed walls that move (eq. NS34 with the wall advection D_w u_w . grad phi*): the
+# dual-resolution, 2D, single-resolution and WENO-Z right-hand sides and both G passes
+UWB, UWT = (0.4, -0.3), (-0.2, 0.5)
+MOVING_CASES = [
+    ("3d-dual", C2S.replace(d_w=0.5, u_wall_bottom=UWB, u_wall_top=UWT), 5),
+    ("2d-dual", W.config("C1", nx=64, nz=32, ly=2.0 / 64, noise=1e-3, seed=1, d_w=0.5,
+                         theta_top_deg=100.0, u_wall_bottom=(0.6, 0.0), u_wall_top=(-0.3, 0.0)), 8),
+    ("3d-single", C2S.replace(refine=1, d_w=0.5, u_wall_bottom=UWB, u_wall_top=UWT), 5),
+    ("3d-viscoelastic-weno", W.config("C3", nx=16, ny=16, nz=8, lx=1.0, ly=1.0, lz=0.5,
+                                      radius=0.2, noise=1e-3, seed=5, wi=0.5, d_w=0.5,
+                                      advection=1, u_wall_bottom=UWB, u_wall_top=UWT), 5),
+]
+
+
+@pytest.mark.parametrize("name,cfg,n", MOVING_CASES, ids=[c[0] for c in MOVING_CASES])
+def test_relaxed_moving_walls_match_oracle(drpf, name, cfg, n):
+    for k, e in run_both(drpf, cfg, n).items():
+        assert e < TOL, (name, k, e)
+
+
+def test_relaxed_moving_walls_term_is_felt(drpf):
+    """The wall advection changes the oracle's phase field far beyond the parity tolerance in
+    the case above (so the parity test would see it missing), and the FP32 form follows FP64."""
+    from tests.test_oracle_moving_walls import _mutant
+    cfg, n = MOVING_CASES[0][1], MOVING_CASES[0][2]
+    P = model.Params.from_config(cfg)
+    with_term = S.run(P, W.droplet_state(cfg), n)
+    dropped = _mutant("            bR[layer] -= (P.d_w / hz) * adv\n", "            pass\n")
+    without = dropped.run(P, W.droplet_state(cfg), n)
+    assert rel(without["phi"][0], with_term["phi"][0]) > 1e4 * TOL
+    a = gpu_run(drpf, cfg, 10, 64)
+    b = gpu_run(drpf, cfg, 10, 32)
+    assert np.all(np.isfinite(b["phi"][0]))
+    assert rel(b["phi"][0], a["phi"][0]) < 1e-4
+    assert rel(b["u"][0], a["u"][0]) < 1e-3
+
+
 def test_zero_relaxation_is_the_static_step(drpf):
     """d_w = 0 takes the static kernels: bit for bit the default step; d_w > 0 differs."""
     a = gpu_run(drpf, C2S.replace(d_w=0.0), 3)
