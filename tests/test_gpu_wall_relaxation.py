@@ -130,6 +130,7 @@ def test_relaxed_moving_walls_term_is_felt(drpf):
     dropped = _mutant("            bR[layer] -= (P.d_w / hz) * adv\n", "            pass\n")
     without = dropped.run(P, W.droplet_state(cfg), n)
     assert rel(without["phi"][0], with_term["phi"][0]) > 1e4 * TOL
+    say(f"[gpu] relaxed moving walls {cfg.name} coarse {cfg.nx}x{cfg.ny}x{cfg.nz} fp64 and fp32, 10 steps")
     a = gpu_run(drpf, cfg, 10, 64)
     b = gpu_run(drpf, cfg, 10, 32)
     assert np.all(np.isfinite(b["phi"][0]))
